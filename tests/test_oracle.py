@@ -1,0 +1,458 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+None of these tests re-types an oracle formula: each compares the oracle with
+an independent route (quadrature, library special functions, brute-force
+summation of the integral form Eq. 1, closed-form potentials, invariants).
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize, special
+
+import oracle as O
+from paper_1806_04593_amd import workloads as W
+
+RAD = math.pi / 180
+
+
+# ---------------------------------------------------------------------------
+# tables
+# ---------------------------------------------------------------------------
+
+def test_assoc_legendre_matches_scipy():
+    x = np.linspace(-0.99, 0.99, 37)
+    P = O.assoc_legendre(30, x, np.sqrt(1 - x * x))
+    for l in range(31):
+        for m in range(l + 1):
+            ref = special.lpmv(m, l, x)           # Condon-Shortley phase
+            scale = np.max(np.abs(ref)) + 1e-300
+            assert np.max(np.abs(P[l, m] - ref)) / scale < 1e-12, (l, m)
+
+
+@pytest.mark.parametrize("res,lmax", [(5.0, 24), (2.0, 40), (1.0, 64)])
+def test_theta_integrals_match_quadrature(res, lmax):
+    """Eq. (18) by Gauss-Legendre quadrature in theta (SciPy P_l^m) versus the
+    appendix recurrences (A1)-(A7); normwise over j per (l, m)."""
+    n_t, n_p, d_t, d_p = O.patch_dims_from_resolution(res)
+    th, _ = O.patch_edges(n_t, n_p, d_t, d_p)
+    T = O.theta_integrals(th, lmax)
+    xg, wg = np.polynomial.legendre.leggauss(48)
+    a, b = th[:-1], th[1:]
+    t = 0.5 * (a + b)[:, None] + 0.5 * (b - a)[:, None] * xg[None, :]
+    worst = 0.0
+    for l in range(lmax + 1):
+        for m in range(l + 1):
+            f = np.sin(t) * special.lpmv(m, l, np.cos(t))
+            ref = 0.5 * (b - a) * (f @ wg)
+            err = np.max(np.abs(T[:, l, m] - ref)) / np.max(np.abs(ref))
+            worst = max(worst, err)
+    assert worst < 1e-12, worst
+
+
+def test_theta_integrals_closed_forms():
+    """Low orders against antiderivatives worked by hand."""
+    th = np.array([0.7, 0.9, 1.3, 2.0])
+    T = O.theta_integrals(th, 3)
+    a, b = th[:-1], th[1:]
+    np.testing.assert_allclose(T[:, 0, 0], np.cos(a) - np.cos(b), rtol=1e-14)
+    np.testing.assert_allclose(T[:, 1, 0], 0.5 * (np.sin(b) ** 2 - np.sin(a) ** 2), rtol=1e-13)
+    # P_1^1 = -sin t  ->  -(t/2 - sin 2t/4)
+    np.testing.assert_allclose(T[:, 1, 1], -((b - a) / 2 - (np.sin(2 * b) - np.sin(2 * a)) / 4), rtol=1e-13)
+    # P_2^1 = -3 cos t sin t -> -sin^3 t
+    np.testing.assert_allclose(T[:, 2, 1], -(np.sin(b) ** 3 - np.sin(a) ** 3), rtol=1e-13)
+    # P_2^2 = 3 sin^2 t -> 3 (cos^3/3 - cos)
+    np.testing.assert_allclose(T[:, 2, 2], 3 * ((np.cos(b) ** 3 - np.cos(a) ** 3) / 3 - (np.cos(b) - np.cos(a))), rtol=1e-13)
+
+
+def test_phi_integrals_match_quadrature():
+    n_t, n_p, d_t, d_p = O.patch_dims_from_resolution(5.0)
+    _, ph = O.patch_edges(n_t, n_p, d_t, d_p)
+    C, S = O.phi_integrals(ph, 12)
+    for k in (0, 7, 30, n_p - 1):
+        for m in range(13):
+            c_ref = integrate.quad(lambda x: math.cos(m * x), ph[k], ph[k + 1], epsabs=1e-16)[0]
+            s_ref = integrate.quad(lambda x: math.sin(m * x), ph[k], ph[k + 1], epsabs=1e-16)[0]
+            assert abs(C[k, m] - c_ref) < 1e-15
+            assert abs(S[k, m] - s_ref) < 1e-15
+
+
+def test_norm_factor_addition_theorem():
+    """sum_m N^(lm) P_l^m(x) P_l^m(x') cos(m dphi) = P_l(cos gamma), the identity
+    that turns 1/|r - r'| into Eq. (5)."""
+    rng = np.random.default_rng(0)
+    L = 30
+    N = O.norm_factor(L)
+    for _ in range(20):
+        t1, t2 = rng.uniform(0.1, 3.0, 2)
+        dp = rng.uniform(-math.pi, math.pi)
+        cg = math.cos(t1) * math.cos(t2) + math.sin(t1) * math.sin(t2) * math.cos(dp)
+        for l in range(L + 1):
+            s = sum(N[l, m] * special.lpmv(m, l, math.cos(t1)) * special.lpmv(m, l, math.cos(t2)) * math.cos(m * dp)
+                    for m in range(l + 1))
+            assert abs(s - special.eval_legendre(l, cg)) < 1e-12, (l, s)
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 3, 7, 25])
+def test_radial_ratio_forms(l):
+    """Ratio forms equal Eqs. (16)-(17) evaluated directly and by quadrature."""
+    r_lo, r_hi, r_n = 1.3, 1.7, 2.1
+    direct_in = (r_hi ** (l + 3) - r_lo ** (l + 3)) / (l + 3) / r_n ** (l + 1)
+    quad_in = integrate.quad(lambda x: x ** (l + 2), r_lo, r_hi, epsabs=0, epsrel=3e-14)[0] / r_n ** (l + 1)
+    got_in = float(O.radial_in_ratio(l, r_lo, r_hi, r_n))
+    assert abs(got_in - direct_in) / direct_in < 1e-13
+    assert abs(got_in - quad_in) / quad_in < 1e-13
+    r_n2 = 0.9
+    if l == 2:
+        direct_out = math.log(r_hi) - math.log(r_lo)
+    else:
+        direct_out = (r_hi ** (2 - l) - r_lo ** (2 - l)) / (2 - l)
+    direct_out *= r_n2 ** l
+    quad_out = integrate.quad(lambda x: x ** (1 - l), r_lo, r_hi, epsabs=0, epsrel=3e-14)[0] * r_n2 ** l
+    got_out = float(O.radial_out_ratio(l, r_lo, r_hi, r_n2))
+    assert abs(got_out - direct_out) / direct_out < 1e-13
+    assert abs(got_out - quad_out) / quad_out < 1e-13
+    # a cell starting at the origin
+    assert abs(float(O.radial_in_ratio(l, 0.0, r_hi, r_n)) - r_hi ** (l + 3) / (l + 3) / r_n ** (l + 1)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Yin-Yang geometry
+# ---------------------------------------------------------------------------
+
+def test_transform_involution_and_cartesian_map():
+    rng = np.random.default_rng(1)
+    t = rng.uniform(0.05, math.pi - 0.05, 500)
+    p = rng.uniform(-math.pi, math.pi, 500)
+    c2, s2, p2 = O.other_patch_angles(t, p)
+    t2 = np.arctan2(s2, c2)
+    c3, s3, p3 = O.other_patch_angles(t2, p2)
+    assert np.max(np.abs(np.arctan2(s3, c3) - t)) < 1e-13
+    assert np.max(np.abs(np.angle(np.exp(1j * (p3 - p))))) < 1e-13
+    # Cartesian form of Eqs. (23)-(24): (x, y, z) -> (-x, z, y)
+    x, y, z = np.sin(t) * np.cos(p), np.sin(t) * np.sin(p), np.cos(t)
+    x2, y2, z2 = s2 * np.cos(p2), s2 * np.sin(p2), c2
+    np.testing.assert_allclose(np.stack([x2, y2, z2]), np.stack([-x, z, y]), atol=1e-14)
+    # Eq. (23) literally
+    np.testing.assert_allclose(np.arccos(np.sin(t) * np.sin(p)), t2, atol=1e-7)
+
+
+def test_patches_cover_the_sphere():
+    n_t, n_p, d_t, d_p = O.patch_dims_from_resolution(2.0)
+    rng = np.random.default_rng(2)
+    v = rng.normal(size=(20000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    t = np.arccos(v[:, 2])
+    p = np.arctan2(v[:, 1], v[:, 0])
+
+    def inside(tt, pp):
+        return ((tt >= math.pi / 4 - d_t) & (tt <= 3 * math.pi / 4 + d_t)
+                & (pp >= -3 * math.pi / 4 - d_p) & (pp <= 3 * math.pi / 4 + d_p))
+    c2, s2, p2 = O.other_patch_angles(t, p)
+    assert np.all(inside(t, p) | inside(np.arctan2(s2, c2), p2))
+
+
+@pytest.mark.parametrize("res", [15.0, 5.0, 2.0, 1.0])
+def test_weights_sum_to_two_pi(res):
+    """Eq. (25): sum over one patch of solid angle times weight is 2 pi."""
+    n_t, n_p, d_t, d_p = O.patch_dims_from_resolution(res)
+    th, ph = O.patch_edges(n_t, n_p, d_t, d_p)
+    w = O.overlap_weights(th, ph, d_t, d_p)
+    total = np.sum(O.solid_angles(th, ph) * w)
+    assert abs(total - 2 * math.pi) < 1e-13, total - 2 * math.pi
+    assert w.min() >= 0.5 - 1e-15 and w.max() <= 1.0 + 1e-15
+    # the patch is symmetric under theta -> pi - theta and phi -> -phi
+    np.testing.assert_allclose(w, w[::-1, :], atol=1e-13)
+    np.testing.assert_allclose(w, w[:, ::-1], atol=1e-13)
+
+
+def test_weights_against_point_sampling():
+    """Cut-cell weights against brute point sampling of the other patch's
+    region (64 x 64 midpoints per cell, area weighted): agreement to the
+    sampling error."""
+    n_t, n_p, d_t, d_p = O.patch_dims_from_resolution(5.0)
+    th, ph = O.patch_edges(n_t, n_p, d_t, d_p)
+    w = O.overlap_weights(th, ph, d_t, d_p)
+    s = 64
+    u = (np.arange(s) + 0.5) / s
+    worst = 0.0
+    for j in range(n_t):
+        for k in range(n_p):
+            tt = th[j] + (th[j + 1] - th[j]) * u
+            pp = ph[k] + (ph[k + 1] - ph[k]) * u
+            T, P = np.meshgrid(tt, pp, indexing="ij")
+            c2, s2, p2 = O.other_patch_angles(T, P)
+            t2 = np.arctan2(s2, c2)
+            cov = ((t2 >= math.pi / 4 - d_t) & (t2 <= 3 * math.pi / 4 + d_t)
+                   & (p2 >= -3 * math.pi / 4 - d_p) & (p2 <= 3 * math.pi / 4 + d_p))
+            wt = np.sin(T)
+            f = np.sum(cov * wt) / np.sum(wt)
+            worst = max(worst, abs((1 - f / 2) - w[j, k]))
+    assert worst < 5e-3, worst
+
+
+# ---------------------------------------------------------------------------
+# the whole method
+# ---------------------------------------------------------------------------
+
+def _solve(desc, rho, lmax=None):
+    return O.solve(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
+                   desc["delta_phi"], desc["lmax"] if lmax is None else lmax, desc["G"], rho)
+
+
+def test_shell_theorem_monopole():
+    """Spherically symmetric rho at lmax = 0 reproduces the shell theorem
+    exactly (Sect. 5, first test)."""
+    desc = W.make_desc("t", np.geomspace(1.0, 50.0, 25), 5.0, 0, 2.5, 0)
+    r = desc["r_edges"]
+    nR = len(r) - 1
+    rr = 1.0 + np.cos(np.arange(nR)) ** 2
+    rho = np.broadcast_to(rr[None, :, None, None], (2, nR, desc["n_theta"], desc["n_phi"])).copy()
+    phi = _solve(desc, rho)
+    ex = np.array([-(4 * math.pi / (3 * r[n])) * np.sum(rr[:n] * (r[1:n + 1] ** 3 - r[:n] ** 3))
+                   - 2 * math.pi * np.sum(rr[n:] * (r[n + 1:] ** 2 - r[n:-1] ** 2)) for n in range(1, nR + 1)])
+    ex *= desc["G"]
+    err = np.max(np.abs(phi - ex[None, :, None, None]) / np.abs(ex)[None, :, None, None])
+    assert err < 2e-14, err
+
+
+def _cell_nodes(r_lo, r_hi, t_lo, t_hi, p_lo, p_hi, n):
+    x, wq = np.polynomial.legendre.leggauss(n)
+    r = 0.5 * (r_lo + r_hi) + 0.5 * (r_hi - r_lo) * x
+    t = 0.5 * (t_lo + t_hi) + 0.5 * (t_hi - t_lo) * x
+    p = 0.5 * (p_lo + p_hi) + 0.5 * (p_hi - p_lo) * x
+    wr = 0.5 * (r_hi - r_lo) * wq * r * r
+    wt = 0.5 * (t_hi - t_lo) * wq * np.sin(t)
+    wp = 0.5 * (p_hi - p_lo) * wq
+    R, Tt, Pp = np.meshgrid(r, t, p, indexing="ij")
+    Wt = wr[:, None, None] * wt[None, :, None] * wp[None, None, :]
+    return R.ravel(), Tt.ravel(), Pp.ravel(), Wt.ravel()
+
+
+def _global_xyz(patch, r, t, p):
+    x, y, z = r * np.sin(t) * np.cos(p), r * np.sin(t) * np.sin(p), r * np.cos(t)
+    return np.stack([x, y, z], -1) if patch == 0 else np.stack([-x, z, y], -1)
+
+
+@pytest.mark.parametrize("case", ["inner_sources", "outer_sources"])
+def test_brute_force_integral(case):
+    """Eq. (1) by direct 3-D Gauss-Legendre summation over every weighted
+    source cell of both patches (each in its own frame), against the oracle.
+    Sources and targets are separated by a radius ratio <= 1/4 so that the
+    multipole series truncated at lmax = 24 is exact to ~1e-15: the oracle
+    must then equal the integral to rounding."""
+    r_edges = np.array([0.0, 0.05, 0.1, 0.4, 0.45, 0.5])
+    desc = W.make_desc("bf", r_edges, 15.0, 24, 1.3, 0)
+    nR, n_t, n_p = 5, desc["n_theta"], desc["n_phi"]
+    th, ph = O.patch_edges(n_t, n_p, desc["delta_theta"], desc["delta_phi"])
+    w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
+    rng = np.random.default_rng(7)
+    rho = np.zeros((2, nR, n_t, n_p))
+    src_shells, tgt_n = ((0, 1), (3, 4)) if case == "inner_sources" else ((3, 4), (0, 1))
+    for i in src_shells:
+        rho[:, i] = rng.uniform(0.5, 1.5, (2, n_t, n_p))
+    phi = _solve(desc, rho)
+    # source quadrature nodes
+    pts, wts = [], []
+    for patch in range(2):
+        for i in src_shells:
+            for j in range(n_t):
+                for k in range(n_p):
+                    R, Tt, Pp, Wq = _cell_nodes(r_edges[i], r_edges[i + 1], th[j], th[j + 1], ph[k], ph[k + 1], 8)
+                    pts.append(_global_xyz(patch, R, Tt, Pp))
+                    wts.append(Wq * rho[patch, i, j, k] * w[j, k])
+    pts = np.concatenate(pts)
+    wts = np.concatenate(wts)
+    tc, pc = 0.5 * (th[:-1] + th[1:]), 0.5 * (ph[:-1] + ph[1:])
+    rng2 = np.random.default_rng(8)
+    worst = 0.0
+    for _ in range(24):
+        patch = int(rng2.integers(2))
+        n = int(rng2.choice(tgt_n))
+        j, k = int(rng2.integers(n_t)), int(rng2.integers(n_p))
+        x = _global_xyz(patch, np.array(r_edges[n + 1]), np.array(tc[j]), np.array(pc[k]))
+        bf = -desc["G"] * np.sum(wts / np.linalg.norm(pts - x[None, :], axis=1))
+        worst = max(worst, abs(phi[patch, n, j, k] - bf) / abs(bf))
+    assert worst < 1e-12, worst
+
+
+def _ellipsoid_potential(x, y, z, a, b, c, G, rho0):
+    """Chandrasekhar's homogeneous-ellipsoid potential (Sect. 5), with the
+    integrals A..D written as Carlson symmetric integrals."""
+    inside = (x / a) ** 2 + (y / b) ** 2 + (z / c) ** 2 <= 1.0
+    if inside:
+        u0 = 0.0
+    else:
+        f = lambda u: x * x / (a * a + u) + y * y / (b * b + u) + z * z / (c * c + u) - 1.0
+        hi = 1.0
+        while f(hi) > 0:
+            hi *= 2
+        u0 = optimize.brentq(f, 0.0, hi, xtol=1e-16, rtol=1e-15)
+    A2, B2, C2 = a * a + u0, b * b + u0, c * c + u0
+    D = 2.0 * special.elliprf(A2, B2, C2)
+    Ai = 2.0 / 3.0 * special.elliprd(B2, C2, A2)
+    Bi = 2.0 / 3.0 * special.elliprd(A2, C2, B2)
+    Ci = 2.0 / 3.0 * special.elliprd(A2, B2, C2)
+    return math.pi * G * rho0 * a * b * c * (Ai * x * x + Bi * y * y + Ci * z * z - D)
+
+
+def _volume_fraction(desc, inside_fn, sub):
+    """Volume fraction of a region per cell by sub^3 midpoint sub-cells."""
+    r = desc["r_edges"]
+    th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+    u = (np.arange(sub) + 0.5) / sub
+    nR, n_t, n_p = len(r) - 1, desc["n_theta"], desc["n_phi"]
+    out = np.zeros((2, nR, n_t, n_p))
+    for patch in range(2):
+        for i in range(nR):
+            rs = r[i] + (r[i + 1] - r[i]) * u
+            wr = rs ** 2
+            for j in range(n_t):
+                ts = th[j] + (th[j + 1] - th[j]) * u
+                wt = np.sin(ts)
+                R, Tt, Pp = np.meshgrid(rs, ts, ph[:-1, None] + (ph[1:] - ph[:-1])[:, None] * u[None, :], indexing="ij")
+                # R, Tt: [sub, sub, n_p, sub]
+                Rb = np.broadcast_to(rs[:, None, None, None], (sub, sub, n_p, sub))
+                Tb = np.broadcast_to(ts[None, :, None, None], (sub, sub, n_p, sub))
+                Pb = np.broadcast_to((ph[:-1, None] + (ph[1:] - ph[:-1])[:, None] * u[None, :])[None, None], (sub, sub, n_p, sub))
+                xyz = _global_xyz(patch, Rb, Tb, Pb)
+                ins = inside_fn(xyz[..., 0], xyz[..., 1], xyz[..., 2]).astype(np.float64)
+                wgt = wr[:, None, None, None] * wt[None, :, None, None]
+                out[patch, i, j] = np.sum(ins * wgt, axis=(0, 1, 3)) / (np.sum(wr) * np.sum(wt) * sub)
+    return out
+
+
+def test_offset_uniform_sphere_exterior():
+    """An offset homogeneous ball: outside it the potential is -G M/|x - x0|;
+    the error is set by the discretised surface and falls with lmax."""
+    x0 = np.array([0.1, 0.05, 0.0])
+    R0 = 0.45
+    desc = W.make_desc("ball", np.linspace(0.0, 1.0, 21), 5.0, 12, 1.0, 0)
+    frac = _volume_fraction(desc, lambda x, y, z: (x - x0[0]) ** 2 + (y - x0[1]) ** 2 + (z - x0[2]) ** 2 <= R0 * R0, 6)
+    th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+    w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
+    r = desc["r_edges"]
+    vol = ((r[1:] ** 3 - r[:-1] ** 3) / 3)[None, :, None, None] * O.solid_angles(th, ph)[None, None] * w[None, None]
+    M = np.sum(frac * vol)
+    tc, pc = 0.5 * (th[:-1] + th[1:]), 0.5 * (ph[:-1] + ph[1:])
+    errs = []
+    for L in (2, 6, 12):
+        phi = _solve(desc, frac, lmax=L)
+        worst = 0.0
+        for patch in range(2):
+            for n in range(15, 20):           # r_n >= 0.8 > |x0| + R0
+                T, P = np.meshgrid(tc, pc, indexing="ij")
+                xyz = _global_xyz(patch, np.full(T.shape, r[n + 1]), T, P)
+                ex = -M / np.linalg.norm(xyz - x0, axis=-1)
+                worst = max(worst, np.max(np.abs(phi[patch, n] - ex) / np.abs(ex)))
+        errs.append(worst)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 2e-3, errs
+
+
+@pytest.mark.slow
+def test_homogeneous_ellipsoid_converges():
+    """The paper's ellipsoid test (Sect. 5): b = 1.5a, c = 2a, rotated by
+    pi/8 in phi, r_max = c, equidistant shells; the maximum relative error
+    against the semi-analytic potential falls with lmax."""
+    a, b, c = 0.5, 0.75, 1.0
+    dphi = math.pi / 8
+    desc = W.make_desc("ell", np.linspace(0.0, c, 21), 6.0, 16, 1.0, 0)
+
+    def inside(x, y, z):
+        # rotate the Yin frame by dphi about z into the ellipsoid frame
+        xe = x * math.cos(dphi) - y * math.sin(dphi)
+        ye = x * math.sin(dphi) + y * math.cos(dphi)
+        return (xe / a) ** 2 + (ye / b) ** 2 + (z / c) ** 2 <= 1.0
+    frac = _volume_fraction(desc, inside, 4)
+    th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+    tc, pc = 0.5 * (th[:-1] + th[1:]), 0.5 * (ph[:-1] + ph[1:])
+    r = desc["r_edges"]
+    rng = np.random.default_rng(3)
+    samp = [(int(rng.integers(2)), int(rng.integers(20)), int(rng.integers(desc["n_theta"])),
+             int(rng.integers(desc["n_phi"]))) for _ in range(150)]
+    exact = []
+    for patch, n, j, k in samp:
+        xyz = _global_xyz(patch, np.array(r[n + 1]), np.array(tc[j]), np.array(pc[k]))
+        xe = xyz[0] * math.cos(dphi) - xyz[1] * math.sin(dphi)
+        ye = xyz[0] * math.sin(dphi) + xyz[1] * math.cos(dphi)
+        exact.append(_ellipsoid_potential(xe, ye, xyz[2], a, b, c, 1.0, 1.0))
+    exact = np.array(exact)
+    errs = []
+    for L in (0, 4, 8, 16):
+        phi = _solve(desc, frac, lmax=L)
+        got = np.array([phi[s] for s in samp])
+        errs.append(np.max(np.abs(got - exact) / np.abs(exact)))
+    assert all(errs[i] > errs[i + 1] for i in range(len(errs) - 1)), errs
+    assert errs[-1] < 2e-2, errs
+
+
+# ---------------------------------------------------------------------------
+# invariants
+# ---------------------------------------------------------------------------
+
+def _small():
+    desc = W.describe("small")
+    return desc, W.density(desc)
+
+
+def test_linearity_and_patch_swap():
+    desc, rho = _small()
+    rng = np.random.default_rng(11)
+    rho2 = rng.random(rho.shape)
+    p1, p2 = _solve(desc, rho), _solve(desc, rho2)
+    p12 = _solve(desc, 2.0 * rho - 0.5 * rho2)
+    assert np.max(np.abs(p12 - (2.0 * p1 - 0.5 * p2))) / np.max(np.abs(p12)) < 1e-13
+    # the method treats both patches alike (Sect. 4): swapping the patches'
+    # densities swaps their potentials
+    ps = _solve(desc, rho[::-1].copy())
+    assert np.max(np.abs(ps - p1[::-1])) / np.max(np.abs(p1)) < 1e-14
+
+
+def test_angular_split_moments_sum():
+    """The parallel scheme of Sect. 3: moments of disjoint angular blocks add
+    up to the moments of the whole patch (the global sum)."""
+    desc, rho = _small()
+    th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+    w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
+    T = O.theta_integrals(th, desc["lmax"])
+    C, S = O.phi_integrals(ph, desc["lmax"])
+    AC, AS = O.moments(rho, w, T, C, S)
+    acc_c, acc_s = np.zeros_like(AC), np.zeros_like(AS)
+    for js in np.array_split(np.arange(desc["n_theta"]), 3):
+        for ks in np.array_split(np.arange(desc["n_phi"]), 4):
+            c, s = O.moments(rho[:, :, js][:, :, :, ks], w[js][:, ks], T[js], C[ks], S[ks])
+            acc_c += c
+            acc_s += s
+    scale = np.max(np.abs(AC))
+    assert np.max(np.abs(acc_c - AC)) / scale < 1e-13
+    assert np.max(np.abs(acc_s - AS)) / scale < 1e-13
+
+
+def test_sampled_solve_matches_full():
+    desc, rho = _small()
+    full = _solve(desc, rho)
+    rng = np.random.default_rng(5)
+    samples = np.stack([rng.integers(0, 2, 40), rng.integers(0, 32, 40),
+                        rng.integers(0, desc["n_theta"], 40), rng.integers(0, desc["n_phi"], 40)], 1)
+    vals = O.solve_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
+                           desc["delta_phi"], desc["lmax"], desc["G"], rho, samples)
+    ref = full[samples[:, 0], samples[:, 1], samples[:, 2], samples[:, 3]]
+    np.testing.assert_allclose(vals, ref, rtol=1e-14)
+
+
+def test_golden_small_potential():
+    """Committed oracle values for the small workload (written by
+    tests/golden/make_golden.py) still reproduce: guards the oracle against
+    unintended arithmetic changes."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "small_phi_samples.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    desc, rho = _small()
+    samples = np.array(gold["samples"])
+    vals = O.solve_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
+                           desc["delta_phi"], desc["lmax"], desc["G"], rho, samples)
+    np.testing.assert_allclose(vals, np.array(gold["phi"]), rtol=1e-13)
