@@ -1,0 +1,181 @@
+/*
+ * yyg — Yin-Yang multipole gravity on MI355X (gfx950).
+ *
+ * Solves for the Newtonian potential Phi of a cell-averaged density rho on
+ * the two patches of a Yin-Yang grid with the multipole method of
+ * Almanstoetter, Melson, Janka & Mueller (2018), "Parallelized solution
+ * method of the three-dimensional gravitational potential on the Yin-Yang
+ * grid":
+ *
+ *   1. angular analysis into per-shell moments A_C, A_S     (Eqs. 21-22, 26-27)
+ *   2. radial inner/outer cumulative sums at the interfaces (Eqs. 11-12, 16-17, 19-20)
+ *   3. synthesis on every cell of both patches, both patches' moments
+ *      contributing to each (Eqs. 5, 28-29).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: YYG_OK (0) or a negative yyg_status.  Errors never abort
+ *   the process; yyg_status_string() names them.
+ * - Density and potential arrays are FP64, C order [2][n_r][n_theta][n_phi]:
+ *   patch 0 (Yin) first, then patch 1 (Yang), each in its own local
+ *   coordinates (identical local axes, Sect. 4).  rho[p][i][j][k] is the
+ *   average over radial cell i (between r_edges[i] and r_edges[i+1]) and
+ *   angular cell (j, k).  phi[p][n][j][k] is the potential at the outer
+ *   interface r_edges[n+1] and at the midpoint of angular cell (j, k).
+ * - Each patch covers theta in [pi/4 - delta_theta, 3pi/4 + delta_theta] and
+ *   phi in [-3pi/4 - delta_phi, 3pi/4 + delta_phi] with n_theta x n_phi
+ *   equal cells (Sect. 4).
+ * - Spherical-harmonic columns are ordered q(l,0) = l*l,
+ *   q(l,m,cos) = l*l + 2m - 1, q(l,m,sin) = l*l + 2m (m >= 1), so
+ *   Q = (lmax+1)^2 columns.
+ * - Device pointers are HIP device addresses valid on the stream passed in;
+ *   `stream` is a hipStream_t (NULL = legacy default stream).  The library
+ *   never frees caller memory.
+ * - A grid handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef YYG_H
+#define YYG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  YYG_OK = 0,
+  YYG_ERR_INVALID_ARG = -1,   /* a size, pointer or descriptor field is invalid  */
+  YYG_ERR_OUT_OF_MEMORY = -2, /* device or host allocation failed                */
+  YYG_ERR_DEVICE = -3,        /* a HIP runtime call or kernel launch failed       */
+  YYG_ERR_NOT_READY = -4,     /* solve before upload, or precision not prepared  */
+  YYG_ERR_UNSUPPORTED = -5,   /* valid request this build does not implement     */
+  YYG_ERR_NONFINITE = -6      /* reserved for input checks                       */
+} yyg_status;
+
+/* Arithmetic of the two angular contractions (analysis and synthesis).  The
+ * radial sums always run in FP64.  FP64 is the reference path; the others
+ * trade accuracy for throughput and must be prepared first. */
+typedef enum {
+  YYG_FP64 = 0,   /* FP64 MFMA                                                   */
+  YYG_FP32 = 1,   /* FP32 MFMA operands and accumulation                         */
+  YYG_BF16X3 = 2, /* three-term BF16 operand split, FP32 MFMA accumulation       */
+  YYG_FP16X2 = 3  /* two-term FP16 operand split with power-of-two scaling       */
+} yyg_precision;
+
+#define YYG_LMAX_CAP 128
+
+typedef struct {
+  int n_r;                  /* radial cells, >= 1                                  */
+  const double *r_edges;    /* host, n_r + 1 strictly increasing radii, r_edges[0] >= 0 */
+  int n_theta, n_phi;       /* angular cells per patch, >= 1 each                  */
+  double delta_theta;       /* patch buffer widths [rad], 0 <= delta < pi/4        */
+  double delta_phi;
+  int lmax;                 /* 0 <= lmax <= YYG_LMAX_CAP                           */
+  double G;                 /* gravitational constant (units of the caller)        */
+} yyg_grid_desc;
+
+typedef struct yyg_grid yyg_grid;
+typedef struct yyg_batch yyg_batch;
+
+/* Build a grid plan on HIP device `device`: every density-independent table
+ * of the method, computed once (Sect. 3, last paragraph): overlap weights
+ * w_jk (Sect. 4, Eq. 25), polar integrals T_j^(lm) (Eq. 18), azimuthal
+ * integrals C_k^(m), S_k^(m) (Eqs. 14-15), radial recurrence coefficients
+ * from Eqs. (16)-(17), and the synthesis bases P_l^m cos/sin(m phi) at the
+ * own and at the other patch's cell midpoints (Eqs. 5, 23-24).  Host tables
+ * are FP64.  Allocates device memory (about 8 n_theta n_phi (3Q) + 40 n_r Q
+ * bytes); `*out` receives the handle, to be released by yyg_grid_destroy. */
+int yyg_grid_create(const yyg_grid_desc *desc, int device, yyg_grid **out);
+
+/* Same, with the patch cells derived from an angular resolution in degrees:
+ * n = ceil(span/res) + 2 cells of exactly `res_deg` (span 90 deg in theta,
+ * 270 deg in phi), the surplus split evenly into the two buffer widths. */
+int yyg_grid_create_res(int n_r, const double *r_edges, double res_deg, int lmax,
+                        double G, int device, yyg_grid **out);
+
+/* Sizes of a plan.  Any output pointer may be NULL. */
+int yyg_grid_dims(const yyg_grid *g, int *n_r, int *n_theta, int *n_phi, int *Q);
+
+/* Build the extra tables a reduced-precision path needs (no-op for FP64).
+ * Allocates; call before capturing a solve in a graph. */
+int yyg_prepare(yyg_grid *g, int precision);
+
+/* Hand the density to the plan.  rho_is_device != 0: `rho` is a device
+ * array that the plan borrows (no copy) and that must stay valid until the
+ * next yyg_solve on `stream` completes.  rho_is_device == 0: host array,
+ * copied into plan-owned device memory on `stream`. */
+int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stream);
+
+/* Solve Phi for the last uploaded density.  Asynchronous on `stream` when
+ * phi_is_device != 0 (no host synchronisation, no allocation); with a host
+ * `phi` the call copies back and synchronises the stream.  `precision` is a
+ * yyg_precision that yyg_prepare has enabled (FP64 always is).  Returns
+ * YYG_ERR_NOT_READY before any upload. */
+int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *stream);
+
+/* Debug/test export after a synchronised solve: the angular moments
+ * A[p][i][q] of Eqs. (26)-(27) (A_C in cos columns, A_S in sin columns) for
+ * patch p and radial cell i, unnormalised as the paper defines them.  Host
+ * array of 2*n_r*Q doubles. */
+int yyg_get_moments(yyg_grid *g, double *A_host);
+
+/* Overlap weights w[j][k] of the plan (Sect. 4); host array n_theta*n_phi. */
+int yyg_get_weights(const yyg_grid *g, double *w_host);
+
+/* Release a plan and its device memory (not the caller's arrays). */
+int yyg_grid_destroy(yyg_grid *g);
+
+/* Host-only table builders, callable without a GPU (used by the CPU tests of
+ * the plan logic).  `which` selects the table; `out` is a host array of
+ * exactly `n` doubles:
+ *   YYG_TABLE_WEIGHTS   w[j][k]                         n = n_theta*n_phi
+ *   YYG_TABLE_THETA     T_j^(lm) (unnormalised, Eq. 18) at [j][q], the
+ *                       same value in the cos and sin columns     n = n_theta*Q
+ *   YYG_TABLE_PHI       C_k^(m) / S_k^(m) at [k][q] (Eqs. 14-15) n = n_phi*Q
+ *   YYG_TABLE_RADIAL    per radial index n (0-based) and degree l, the
+ *                       four coefficients alpha, beta, gamma, kappa of the
+ *                       recurrences U_n = I_n + O_n,
+ *                         I_n = alpha I_(n-1) + beta A_n,
+ *                         O_n = gamma O_(n+1) + kappa A_(n+1),
+ *                       which reproduce r^-(l+1) sum_(i<=n) R_in,i A_i and
+ *                       r^l sum_(i>n) R_out,i A_i of Eqs. (19)-(20) at
+ *                       r = r_edges[n+1]; layout [n][l][4]   n = 4*n_r*(lmax+1)
+ *   YYG_TABLE_CROSS     for every angular cell a = j*n_phi + k: cos theta',
+ *                       sin theta', phi' of its midpoint in the other patch's
+ *                       frame (Eqs. 23-24); layout [a][3]      n = 3*n_theta*n_phi
+ */
+enum {
+  YYG_TABLE_WEIGHTS = 0,
+  YYG_TABLE_THETA = 1,
+  YYG_TABLE_PHI = 2,
+  YYG_TABLE_RADIAL = 3,
+  YYG_TABLE_CROSS = 4
+};
+int yyg_host_table(const yyg_grid_desc *desc, int which, double *out, size_t n);
+
+/* Per-kernel timing with HIP events recorded on the solve stream around
+ * every launch of yyg_solve / yyg_batch_solve while enabled.  Kernel slots:
+ * 0 analysis contraction, 1 radial scan, 2 synthesis contraction,
+ * 3 operand conversion (reduced precisions).  yyg_get_timing synchronises
+ * the recorded events and returns the summed milliseconds and launch
+ * counts per slot (arrays of `n_slots` entries, n_slots <= 4); enabling
+ * again clears the sums. */
+int yyg_set_timing(yyg_grid *g, int enable);
+int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots);
+
+/* Batched solves of several plans (uneven sizes and lmax allowed) in one
+ * persistent launch per phase; see the design notes.  `grids` are borrowed
+ * and must outlive the batch; all must be on one device.  d_rho[f], d_phi[f]
+ * are device arrays of field f in the layout above. */
+int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out);
+int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_phi, void *stream);
+int yyg_batch_destroy(yyg_batch *b);
+
+/* Static string naming a status code. */
+const char *yyg_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* YYG_H */

@@ -1,0 +1,498 @@
+// C ABI of the Yin-Yang multipole solver: plan creation (tables), density
+// upload, solve, exports.  See include/yyg.h for the contract.
+#include "yyg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "yyg_internal.h"
+#include "yyg_tables.h"
+
+namespace {
+
+constexpr int kSlots = 4;
+
+struct TimedLaunch {
+  int slot;
+  hipEvent_t start, stop;
+};
+
+long round_up(long v, long m) { return (v + m - 1) / m * m; }
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct yyg_grid {
+  int device = 0;
+  int n_r = 0, n_t = 0, n_p = 0, L = 0, Q = 0;
+  double G = 1.0;
+  long nang = 0, ldb = 0, ldy = 0;
+  int nsplit = 1;
+  std::vector<double> r_edges, w_host, nrm_q;
+  yyg::PatchGeom geom;
+
+  double *d_Bt = nullptr;    // analysis basis [Q][ldb]
+  double *d_Y = nullptr;     // synthesis basis [nang][ldy], self | cross
+  double *d_coef = nullptr;  // radial coefficients [n_r][L+1][4]
+  int *d_qdeg = nullptr;     // degree l of each column
+  double *d_part = nullptr;  // split-K partial moments [nsplit][2 n_r][Q]
+  double *d_Ahat = nullptr;  // reduced moments (sqrt(N) scaled) [2 n_r][Q]
+  double *d_U = nullptr;     // synthesis operand [2 n_r][ldy]
+  double *d_rho_owned = nullptr;
+  const double *rho = nullptr;
+
+  bool timing = false;
+  std::vector<TimedLaunch> launches;
+};
+
+namespace {
+
+int validate(const yyg_grid_desc *d) {
+  if (!d || !d->r_edges) return YYG_ERR_INVALID_ARG;
+  if (d->n_r < 1 || d->n_theta < 1 || d->n_phi < 1) return YYG_ERR_INVALID_ARG;
+  if (d->lmax < 0 || d->lmax > YYG_LMAX_CAP) return YYG_ERR_INVALID_ARG;
+  const double q = 0.78539816339744830962;
+  if (!(d->delta_theta >= 0.0 && d->delta_theta < q) || !(d->delta_phi >= 0.0 && d->delta_phi < q))
+    return YYG_ERR_INVALID_ARG;
+  if (!std::isfinite(d->G)) return YYG_ERR_INVALID_ARG;
+  if (!(d->r_edges[0] >= 0.0) || !std::isfinite(d->r_edges[0])) return YYG_ERR_INVALID_ARG;
+  for (int i = 0; i < d->n_r; ++i)
+    if (!(d->r_edges[i + 1] > d->r_edges[i]) || !std::isfinite(d->r_edges[i + 1])) return YYG_ERR_INVALID_ARG;
+  if ((long)d->n_theta * d->n_phi > (1L << 26)) return YYG_ERR_INVALID_ARG;
+  return YYG_OK;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void free_grid(yyg_grid *g) {
+  if (!g) return;
+  double *bufs[] = {g->d_Bt, g->d_Y, g->d_coef, g->d_part, g->d_Ahat, g->d_U, g->d_rho_owned};
+  for (double *b : bufs)
+    if (b) (void)hipFree(b);
+  if (g->d_qdeg) (void)hipFree(g->d_qdeg);
+  for (auto &t : g->launches) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  delete g;
+}
+
+template <class T>
+int dmalloc(T **p, size_t count) {
+  if (hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return YYG_ERR_OUT_OF_MEMORY;
+  }
+  return YYG_OK;
+}
+
+// Record a start event if timing is on; returns the index of the record.
+int timing_begin(yyg_grid *g, int slot, hipStream_t s) {
+  if (!g->timing) return -1;
+  TimedLaunch t{slot, nullptr, nullptr};
+  if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return -1;
+  (void)hipEventRecord(t.start, s);
+  g->launches.push_back(t);
+  return (int)g->launches.size() - 1;
+}
+void timing_end(yyg_grid *g, int idx, hipStream_t s) {
+  if (idx >= 0) (void)hipEventRecord(g->launches[idx].stop, s);
+}
+
+}  // namespace
+
+namespace yyg {
+int choose_split(long tiles, long K) {
+  // Blocks resident at once: 256 CUs x 2 blocks.  Pick the smallest split
+  // whose wave-quantised cost is within 10% of the best, keeping at least
+  // four 16-wide k stages per split.
+  const long slots = 512;
+  long smax = std::max(1L, std::min(32L, K / 64));
+  double best = 1e30;
+  std::vector<double> cost(smax + 1);
+  for (long s = 1; s <= smax; ++s) {
+    long waves = (tiles * s + slots - 1) / slots;
+    cost[s] = (double)waves / s;
+    best = std::min(best, cost[s]);
+  }
+  for (long s = 1; s <= smax; ++s)
+    if (cost[s] <= 1.1 * best) return (int)s;
+  return 1;
+}
+}  // namespace yyg
+
+extern "C" {
+
+const char *yyg_status_string(int status) {
+  switch (status) {
+    case YYG_OK: return "ok";
+    case YYG_ERR_INVALID_ARG: return "invalid argument";
+    case YYG_ERR_OUT_OF_MEMORY: return "out of memory";
+    case YYG_ERR_DEVICE: return "HIP device error";
+    case YYG_ERR_NOT_READY: return "not ready (no density uploaded or precision not prepared)";
+    case YYG_ERR_UNSUPPORTED: return "unsupported";
+    case YYG_ERR_NONFINITE: return "non-finite input";
+    default: return "unknown status";
+  }
+}
+
+int yyg_host_table(const yyg_grid_desc *d, int which, double *out, size_t n) {
+  int st = validate(d);
+  if (st != YYG_OK) return st;
+  if (!out) return YYG_ERR_INVALID_ARG;
+  const int L = d->lmax, Q = (L + 1) * (L + 1);
+  const size_t nang = (size_t)d->n_theta * d->n_phi;
+  yyg::PatchGeom g = yyg::make_patch(d->n_theta, d->n_phi, d->delta_theta, d->delta_phi);
+  try {
+    switch (which) {
+      case YYG_TABLE_WEIGHTS:
+        if (n != nang) return YYG_ERR_INVALID_ARG;
+        yyg::overlap_weights(g, out);
+        return YYG_OK;
+      case YYG_TABLE_THETA: {
+        if (n != (size_t)d->n_theta * Q) return YYG_ERR_INVALID_ARG;
+        yyg::theta_table_normalised(g, L, out);
+        auto s = yyg::norm_sqrt(L);
+        auto cols = yyg::column_table(L);
+        for (int j = 0; j < d->n_theta; ++j)
+          for (int q = 0; q < Q; ++q) out[(size_t)j * Q + q] /= s[cols[q].l * (L + 1) + cols[q].m];
+        return YYG_OK;
+      }
+      case YYG_TABLE_PHI:
+        if (n != (size_t)d->n_phi * Q) return YYG_ERR_INVALID_ARG;
+        yyg::phi_table(g, L, out);
+        return YYG_OK;
+      case YYG_TABLE_RADIAL:
+        if (n != (size_t)4 * d->n_r * (L + 1)) return YYG_ERR_INVALID_ARG;
+        yyg::radial_coefficients(d->n_r, d->r_edges, L, out);
+        return YYG_OK;
+      case YYG_TABLE_CROSS:
+        if (n != 3 * nang) return YYG_ERR_INVALID_ARG;
+        yyg::cross_points(g, out);
+        return YYG_OK;
+      default:
+        return YYG_ERR_INVALID_ARG;
+    }
+  } catch (const std::bad_alloc &) {
+    return YYG_ERR_OUT_OF_MEMORY;
+  }
+}
+
+int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
+  if (!out) return YYG_ERR_INVALID_ARG;
+  *out = nullptr;
+  int st = validate(d);
+  if (st != YYG_OK) return st;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  if (device < 0 || device >= ndev) return YYG_ERR_INVALID_ARG;
+
+  yyg_grid *g = new (std::nothrow) yyg_grid;
+  if (!g) return YYG_ERR_OUT_OF_MEMORY;
+  g->device = device;
+  g->n_r = d->n_r;
+  g->n_t = d->n_theta;
+  g->n_p = d->n_phi;
+  g->L = d->lmax;
+  g->Q = (d->lmax + 1) * (d->lmax + 1);
+  g->G = d->G;
+  g->nang = (long)g->n_t * g->n_p;
+  g->ldb = round_up(g->nang, 16);
+  g->ldy = round_up(2L * g->Q, 16);
+  g->r_edges.assign(d->r_edges, d->r_edges + d->n_r + 1);
+  g->geom = yyg::make_patch(g->n_t, g->n_p, d->delta_theta, d->delta_phi);
+  const int L = g->L, Q = g->Q, n_r = g->n_r;
+  const long M = 2L * n_r;
+  g->nsplit = yyg::choose_split(((M + 127) / 128) * ((Q + 127) / 128), g->nang);
+
+  std::vector<double> Tt, CS, coef, P, Tr, Yx;
+  std::vector<int> qdeg(Q);
+  try {
+    g->w_host.resize(g->nang);
+    yyg::overlap_weights(g->geom, g->w_host.data());
+    Tt.resize((size_t)g->n_t * Q);
+    yyg::theta_table_normalised(g->geom, L, Tt.data());
+    CS.resize((size_t)g->n_p * Q);
+    yyg::phi_table(g->geom, L, CS.data());
+    coef.resize((size_t)4 * n_r * (L + 1));
+    yyg::radial_coefficients(n_r, g->r_edges.data(), L, coef.data());
+    P.resize((size_t)g->n_t * Q);
+    yyg::self_legendre_table(g->geom, L, P.data());
+    Tr.resize((size_t)g->n_p * Q);
+    yyg::self_trig_table(g->geom, L, Tr.data());
+    Yx.resize((size_t)g->nang * Q);
+    yyg::cross_basis(g->geom, L, Yx.data());
+    auto cols = yyg::column_table(L);
+    auto s = yyg::norm_sqrt(L);
+    g->nrm_q.resize(Q);
+    for (int q = 0; q < Q; ++q) {
+      qdeg[q] = cols[q].l;
+      g->nrm_q[q] = s[cols[q].l * (L + 1) + cols[q].m];
+    }
+  } catch (const std::bad_alloc &) {
+    free_grid(g);
+    return YYG_ERR_OUT_OF_MEMORY;
+  }
+
+  DeviceGuard dg(device);
+  if (!dg.ok) {
+    free_grid(g);
+    return YYG_ERR_DEVICE;
+  }
+  double *d_w = nullptr, *d_Tt = nullptr, *d_CS = nullptr, *d_P = nullptr, *d_Tr = nullptr;
+  auto cleanup_tmp = [&] {
+    double *t[] = {d_w, d_Tt, d_CS, d_P, d_Tr};
+    for (double *b : t)
+      if (b) (void)hipFree(b);
+  };
+  st = YYG_OK;
+  if (st == YYG_OK) st = dmalloc(&g->d_Bt, (size_t)Q * g->ldb);
+  if (st == YYG_OK) st = dmalloc(&g->d_Y, (size_t)g->nang * g->ldy);
+  if (st == YYG_OK) st = dmalloc(&g->d_coef, coef.size());
+  if (st == YYG_OK) st = dmalloc(&g->d_qdeg, (size_t)Q);
+  if (st == YYG_OK) st = dmalloc(&g->d_part, (size_t)g->nsplit * M * Q);
+  if (st == YYG_OK) st = dmalloc(&g->d_Ahat, (size_t)M * Q);
+  if (st == YYG_OK) st = dmalloc(&g->d_U, (size_t)M * g->ldy);
+  if (st == YYG_OK) st = dmalloc(&d_w, (size_t)g->nang);
+  if (st == YYG_OK) st = dmalloc(&d_Tt, Tt.size());
+  if (st == YYG_OK) st = dmalloc(&d_CS, CS.size());
+  if (st == YYG_OK) st = dmalloc(&d_P, P.size());
+  if (st == YYG_OK) st = dmalloc(&d_Tr, Tr.size());
+  if (st != YYG_OK) {
+    cleanup_tmp();
+    free_grid(g);
+    return st;
+  }
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+  };
+  chk(hipMemcpy(g->d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(g->d_qdeg, qdeg.data(), qdeg.size() * sizeof(int), hipMemcpyHostToDevice));
+  chk(hipMemcpy(d_w, g->w_host.data(), g->nang * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(d_Tt, Tt.data(), Tt.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(d_CS, CS.data(), CS.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(d_P, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(d_Tr, Tr.data(), Tr.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemset(g->d_U, 0, (size_t)M * g->ldy * sizeof(double)));
+  chk(hipMemset(g->d_Ahat, 0, (size_t)M * Q * sizeof(double)));
+  if (e == hipSuccess) chk(yyg::launch_expand_analysis_basis(d_w, d_Tt, d_CS, g->n_t, g->n_p, Q, g->d_Bt, g->ldb, 0));
+  if (e == hipSuccess) chk(yyg::launch_expand_self_basis(d_P, d_Tr, g->n_t, g->n_p, Q, g->d_Y, g->ldy, 0));
+  // cross part: columns [Q, 2Q) of every row
+  if (e == hipSuccess)
+    chk(hipMemcpy2D(g->d_Y + Q, g->ldy * sizeof(double), Yx.data(), (size_t)Q * sizeof(double),
+                    (size_t)Q * sizeof(double), g->nang, hipMemcpyHostToDevice));
+  chk(hipDeviceSynchronize());
+  cleanup_tmp();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    free_grid(g);
+    return YYG_ERR_DEVICE;
+  }
+  *out = g;
+  return YYG_OK;
+}
+
+int yyg_grid_create_res(int n_r, const double *r_edges, double res_deg, int lmax, double G, int device,
+                        yyg_grid **out) {
+  if (!(res_deg > 0.0) || !std::isfinite(res_deg) || res_deg > 90.0) return YYG_ERR_INVALID_ARG;
+  yyg_grid_desc d;
+  d.n_r = n_r;
+  d.r_edges = r_edges;
+  yyg::dims_from_resolution(res_deg, &d.n_theta, &d.n_phi, &d.delta_theta, &d.delta_phi);
+  d.lmax = lmax;
+  d.G = G;
+  return yyg_grid_create(&d, device, out);
+}
+
+int yyg_grid_dims(const yyg_grid *g, int *n_r, int *n_theta, int *n_phi, int *Q) {
+  if (!g) return YYG_ERR_INVALID_ARG;
+  if (n_r) *n_r = g->n_r;
+  if (n_theta) *n_theta = g->n_t;
+  if (n_phi) *n_phi = g->n_p;
+  if (Q) *Q = g->Q;
+  return YYG_OK;
+}
+
+int yyg_prepare(yyg_grid *g, int precision) {
+  if (!g) return YYG_ERR_INVALID_ARG;
+  if (precision == YYG_FP64) return YYG_OK;
+  if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
+  return YYG_ERR_UNSUPPORTED;
+}
+
+int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stream) {
+  if (!g || !rho) return YYG_ERR_INVALID_ARG;
+  if (rho_is_device) {
+    g->rho = rho;
+    return YYG_OK;
+  }
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  const size_t bytes = (size_t)2 * g->n_r * g->nang * sizeof(double);
+  if (!g->d_rho_owned) {
+    int st = dmalloc(&g->d_rho_owned, bytes / sizeof(double));
+    if (st != YYG_OK) return st;
+  }
+  if (hipMemcpyAsync(g->d_rho_owned, rho, bytes, hipMemcpyHostToDevice, as_stream(stream)) != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  g->rho = g->d_rho_owned;
+  return YYG_OK;
+}
+
+int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *stream) {
+  if (!g || !phi) return YYG_ERR_INVALID_ARG;
+  if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
+  if (precision != YYG_FP64) return YYG_ERR_NOT_READY;
+  if (!g->rho) return YYG_ERR_NOT_READY;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  hipStream_t s = as_stream(stream);
+  const int Q = g->Q, n_r = g->n_r;
+  const long M = 2L * n_r;
+  double *out = phi;
+  double *tmp = nullptr;
+  if (!phi_is_device) {
+    if (dmalloc(&tmp, (size_t)M * g->nang) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
+    out = tmp;
+  }
+  hipError_t e;
+  int t = timing_begin(g, 0, s);
+  e = yyg::launch_gemm_nt_f64((int)M, Q, (int)g->nang, g->rho, g->nang, g->d_Bt, g->ldb, g->d_part, Q, g->nsplit,
+                              M * Q, s);
+  timing_end(g, t, s);
+  if (e == hipSuccess) {
+    t = timing_begin(g, 1, s);
+    e = yyg::launch_radial_scan(g->d_part, g->nsplit, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, n_r, Q, g->L, -g->G,
+                                g->d_U, g->ldy, s);
+    timing_end(g, t, s);
+  }
+  if (e == hipSuccess) {
+    t = timing_begin(g, 2, s);
+    e = yyg::launch_gemm_nt_f64((int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, out, g->nang, 1, 0, s);
+    timing_end(g, t, s);
+  }
+  if (!phi_is_device) {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(phi, out, (size_t)M * g->nang * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  return YYG_OK;
+}
+
+int yyg_get_moments(yyg_grid *g, double *A_host) {
+  if (!g || !A_host) return YYG_ERR_INVALID_ARG;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  const long M = 2L * g->n_r;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(A_host, g->d_Ahat, (size_t)M * g->Q * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  for (long r = 0; r < M; ++r)
+    for (int q = 0; q < g->Q; ++q) A_host[r * g->Q + q] /= g->nrm_q[q];
+  return YYG_OK;
+}
+
+int yyg_get_weights(const yyg_grid *g, double *w_host) {
+  if (!g || !w_host) return YYG_ERR_INVALID_ARG;
+  std::memcpy(w_host, g->w_host.data(), g->w_host.size() * sizeof(double));
+  return YYG_OK;
+}
+
+int yyg_grid_destroy(yyg_grid *g) {
+  if (!g) return YYG_ERR_INVALID_ARG;
+  DeviceGuard dg(g->device);
+  (void)hipDeviceSynchronize();
+  free_grid(g);
+  return YYG_OK;
+}
+
+int yyg_set_timing(yyg_grid *g, int enable) {
+  if (!g) return YYG_ERR_INVALID_ARG;
+  DeviceGuard dg(g->device);
+  (void)hipDeviceSynchronize();
+  for (auto &t : g->launches) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  g->launches.clear();
+  g->timing = enable != 0;
+  return YYG_OK;
+}
+
+int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots) {
+  if (!g || !ms || !counts || n_slots < 1 || n_slots > kSlots) return YYG_ERR_INVALID_ARG;
+  DeviceGuard dg(g->device);
+  for (int i = 0; i < n_slots; ++i) {
+    ms[i] = 0.0;
+    counts[i] = 0;
+  }
+  for (auto &t : g->launches) {
+    if (hipEventSynchronize(t.stop) != hipSuccess) {
+      (void)hipGetLastError();
+      return YYG_ERR_DEVICE;
+    }
+    float v = 0.f;
+    if (hipEventElapsedTime(&v, t.start, t.stop) != hipSuccess) {
+      (void)hipGetLastError();
+      return YYG_ERR_DEVICE;
+    }
+    if (t.slot < n_slots) {
+      ms[t.slot] += v;
+      counts[t.slot] += 1;
+    }
+  }
+  return YYG_OK;
+}
+
+int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out) {
+  (void)grids;
+  (void)n;
+  (void)precision;
+  if (out) *out = nullptr;
+  return YYG_ERR_UNSUPPORTED;
+}
+
+int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_phi, void *stream) {
+  (void)b;
+  (void)d_rho;
+  (void)d_phi;
+  (void)stream;
+  return YYG_ERR_UNSUPPORTED;
+}
+
+int yyg_batch_destroy(yyg_batch *b) {
+  (void)b;
+  return YYG_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

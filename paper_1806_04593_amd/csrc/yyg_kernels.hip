@@ -1,0 +1,289 @@
+// HIP kernels of the Yin-Yang multipole solve on gfx950 (CDNA4).
+//
+//  * gemm_nt_f64: C[M x N] (+)= A[M x K] . B[N x K]^T, FP64 MFMA 16x16x4,
+//    128 x 128 block tile, four waves of 64 x 64, LDS double buffering and
+//    optional split-K (partials written side by side, reduced in a fixed
+//    order by the consumer).  Serves the angular analysis (Eqs. 26-27: rows
+//    are (patch, shell), K the angular cells, N the (l, m, cos/sin) columns)
+//    and the synthesis (Eqs. 5, 28-29: K the 2Q self + cross columns, N the
+//    angular cells).
+//  * radial_scan: the inner/outer radial sums of Eqs. (19)-(20) as two
+//    first-order recurrences per (patch, column), chunked over radius across
+//    the waves of a workgroup, FP64 throughout.
+//  * table expansion kernels that build the separable analysis and
+//    self-synthesis bases from their FP64 factors.
+#include <hip/hip_runtime.h>
+
+#include "yyg_internal.h"
+
+namespace yyg {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kBM = 128, kBN = 128, kBK = 16, kPad = 2, kLDK = kBK + kPad;
+
+// Logical tile of a block so that the blocks one XCD receives (the hardware
+// hands blocks to the 8 XCDs round-robin) form a contiguous run of tiles in
+// M-fastest order: the M tiles that share a B tile then share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+  const int per = total / 8, rem = total % 8;
+  const int x = b % 8, i = b / 8;
+  return x * per + min(x, rem) + i;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256, 2) void gemm_nt_f64_kernel(
+    int M, int N, int K, const double *__restrict__ A, long lda, const double *__restrict__ B, long ldb,
+    double *__restrict__ C, long ldc, long c_split_stride, int k_per_split, int tiles_m, int tiles_total) {
+  __shared__ double As[2][kBM * kLDK];
+  __shared__ double Bs[2][kBN * kLDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tile = xcd_tile(blockIdx.x, tiles_total);
+  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int z = blockIdx.y;
+  const int kbeg = z * k_per_split;
+  const int kend = min(K, kbeg + k_per_split);
+  C += (long)z * c_split_stride;
+
+  const int wm = wave & 1, wn = wave >> 1;
+  const int lrow = tid >> 1, lcol = (tid & 1) * 8;
+
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[8], rb[8];
+  const int ga = m0 + lrow, gb = n0 + lrow;
+  const double *pa = A + (long)min(ga, M - 1) * lda;
+  const double *pb = B + (long)min(gb, N - 1) * ldb;
+  const bool va = ga < M, vb = gb < N;
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int kk = k0 + lcol + i;
+      const bool kin = kk < kend;
+      ra[i] = (va && kin) ? pa[kk] : 0.0;
+      rb[i] = (vb && kin) ? pb[kk] : 0.0;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      As[buf][lrow * kLDK + lcol + i] = ra[i];
+      Bs[buf][lrow * kLDK + lcol + i] = rb[i];
+    }
+  };
+
+  const int nk = (kend - kbeg + kBK - 1) / kBK;
+  if (nk > 0) {
+    load(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+
+  const int frow = lane & 15, fk = 4 * (lane >> 4);
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    const bool more = it + 1 < nk;
+    if (more) load(kbeg + (it + 1) * kBK);
+    // Each lane holds four consecutive k of its row; MFMA step s uses the
+    // s-th of them, so the four steps cover the 16 k of the stage once.
+    double af[4][4], bf[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double *s = &As[buf][(wm * 64 + i * 16 + frow) * kLDK + fk];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) af[i][s4] = s[s4];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double *s = &Bs[buf][(wn * 64 + j * 16 + frow) * kLDK + fk];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) bf[j][s4] = s[s4];
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // D layout of the 16x16 f64 MFMA: lane l, element r -> row 4*(l/16)+r, col l%16.
+  const int orow = 4 * (lane >> 4), ocol = lane & 15;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wn * 64 + j * 16 + ocol;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + i * 16 + orow + r;
+        if (row < M && col < N) C[(long)row * ldc + col] = acc[i][j][r];
+      }
+    }
+  }
+}
+
+// Radial sums of Eqs. (19)-(20) for every (patch, column), with the split-K
+// partial moments reduced first (fixed order over the splits).
+//   I_n = alpha_n I_(n-1) + beta_n A_n            (I_(-1) = 0)
+//   O_n = gamma_n O_(n+1) + kappa_n A_(n+1)       (O_(nR-1) = 0)
+// Block: 64 columns x nw waves; wave w owns a contiguous chunk of radii.
+// Chunk summaries (product of multipliers, local value) combine in LDS.
+// Output Ucat[(p, n)][q] = -G U[p, n, q] and Ucat[(pbar, n)][Q + q] = the same
+// value, i.e. the synthesis operand [self | other] of Eqs. (28)-(29).
+__global__ __launch_bounds__(1024) void radial_scan_kernel(
+    const double *__restrict__ part, int nsplit, long split_stride, double *__restrict__ Ahat,
+    const double *__restrict__ coef, const int *__restrict__ qdeg, int nR, int Q, int L, double negG,
+    double *__restrict__ U, long ldu) {
+  __shared__ double sI[16][64], sPa[16][64], sO[16][64], sPg[16][64];
+  const int lane = threadIdx.x, w = threadIdx.y, nw = blockDim.y;
+  const int q = blockIdx.x * 64 + lane;
+  const int p = blockIdx.y;
+  const bool ok = q < Q;
+  const int qq = ok ? q : 0;
+  const int l = ok ? qdeg[q] : 0;
+  const int chunk = (nR + nw - 1) / nw;
+  const int n0 = min(nR, w * chunk), n1 = min(nR, n0 + chunk);
+  const long rbase = (long)p * nR;
+  const long rbar = (long)(1 - p) * nR;
+  const double *cf = coef + (long)l * 4;
+  const long cstride = (long)(L + 1) * 4;
+
+  double I = 0.0, Pa = 1.0;
+  if (ok) {
+#pragma unroll 4
+    for (int n = n0; n < n1; ++n) {
+      const long row = rbase + n;
+      double a = 0.0;
+      for (int z = 0; z < nsplit; ++z) a += part[z * split_stride + row * Q + qq];
+      Ahat[row * Q + qq] = a;
+      const double *c = cf + n * cstride;
+      I = c[0] * I + c[1] * a;
+      Pa *= c[0];
+    }
+  }
+  __syncthreads();
+  double O = 0.0, Pg = 1.0;
+  if (ok) {
+#pragma unroll 4
+    for (int n = n1 - 1; n >= n0; --n) {
+      const double *c = cf + n * cstride;
+      const double an = (n + 1 < nR) ? Ahat[(rbase + n + 1) * Q + qq] : 0.0;
+      O = c[2] * O + c[3] * an;
+      Pg *= c[2];
+    }
+  }
+  sI[w][lane] = I;
+  sPa[w][lane] = Pa;
+  sO[w][lane] = O;
+  sPg[w][lane] = Pg;
+  __syncthreads();
+  if (!ok) return;
+  double Iin = 0.0, Oin = 0.0;
+  for (int c = 0; c < w; ++c) Iin = sPa[c][lane] * Iin + sI[c][lane];
+  for (int c = nw - 1; c > w; --c) Oin = sPg[c][lane] * Oin + sO[c][lane];
+
+  I = Iin;
+#pragma unroll 4
+  for (int n = n0; n < n1; ++n) {
+    const double *c = cf + n * cstride;
+    I = c[0] * I + c[1] * Ahat[(rbase + n) * Q + q];
+    U[(rbase + n) * ldu + q] = I;
+  }
+  O = Oin;
+#pragma unroll 4
+  for (int n = n1 - 1; n >= n0; --n) {
+    const double *c = cf + n * cstride;
+    const double an = (n + 1 < nR) ? Ahat[(rbase + n + 1) * Q + q] : 0.0;
+    O = c[2] * O + c[3] * an;
+    const double v = negG * (U[(rbase + n) * ldu + q] + O);
+    U[(rbase + n) * ldu + q] = v;
+    U[(rbar + n) * ldu + Q + q] = v;
+  }
+}
+
+// Bt[q][a] = w[a] Tbar[j][q] CS[k][q], a = j*n_p + k (analysis basis,
+// Eqs. 26-27 with sqrt(N^(lm)) folded in); zero in the padding columns.
+__global__ void expand_analysis_basis_kernel(const double *__restrict__ w, const double *__restrict__ Tt,
+                                             const double *__restrict__ CS, int n_t, int n_p, int Q,
+                                             double *__restrict__ Bt, long ldb) {
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (a >= ldb) return;
+  const long nang = (long)n_t * n_p;
+  double v = 0.0;
+  if (a < nang) {
+    const int j = (int)(a / n_p), k = (int)(a % n_p);
+    v = w[a] * Tt[(long)j * Q + q] * CS[(long)k * Q + q];
+  }
+  Bt[(long)q * ldb + a] = v;
+}
+
+// Ycat[a][q] = Pbar[j][q] trig[k][q] for q < Q (self-synthesis basis at the
+// patch's own cell midpoints, Eq. 5); columns >= 2Q (padding) are zeroed.
+__global__ void expand_self_basis_kernel(const double *__restrict__ P, const double *__restrict__ Tr, int n_t,
+                                         int n_p, int Q, double *__restrict__ Y, long ldy) {
+  const int a = blockIdx.x;
+  const int j = a / n_p, k = a % n_p;
+  for (int q = threadIdx.x; q < ldy; q += blockDim.x) {
+    if (q < Q)
+      Y[(long)a * ldy + q] = P[(long)j * Q + q] * Tr[(long)k * Q + q];
+    else if (q >= 2 * Q)
+      Y[(long)a * ldy + q] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_gemm_nt_f64(int M, int N, int K, const double *A, long lda, const double *B, long ldb, double *C,
+                              long ldc, int nsplit, long c_split_stride, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int tiles_m = (M + kBM - 1) / kBM, tiles_n = (N + kBN - 1) / kBN;
+  int kps = (K + nsplit - 1) / nsplit;
+  kps = ((kps + kBK - 1) / kBK) * kBK;
+  dim3 grid(tiles_m * tiles_n, nsplit);
+  hipLaunchKernelGGL(gemm_nt_f64_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, c_split_stride,
+                     kps, tiles_m, tiles_m * tiles_n);
+  return hipGetLastError();
+}
+
+hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
+                              const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu,
+                              hipStream_t s) {
+  int nw = 16;
+  while (nw > 1 && nR / nw < 8) nw >>= 1;
+  dim3 block(64, nw), grid((Q + 63) / 64, 2);
+  hipLaunchKernelGGL(radial_scan_kernel, grid, block, 0, s, part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L,
+                     negG, U, ldu);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_analysis_basis(const double *w, const double *Tt, const double *CS, int n_t, int n_p,
+                                        int Q, double *Bt, long ldb, hipStream_t s) {
+  dim3 grid((unsigned)((ldb + 255) / 256), Q);
+  hipLaunchKernelGGL(expand_analysis_basis_kernel, grid, dim3(256), 0, s, w, Tt, CS, n_t, n_p, Q, Bt, ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, int n_p, int Q, double *Y, long ldy,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(expand_self_basis_kernel, dim3(n_t * n_p), dim3(256), 0, s, P, Tr, n_t, n_p, Q, Y, ldy);
+  return hipGetLastError();
+}
+
+}  // namespace yyg

@@ -1,0 +1,58 @@
+// Host FP64 builders of the density-independent tables of a Yin-Yang plan.
+#pragma once
+
+#include <cstddef>
+#include <vector>
+
+namespace yyg {
+
+// Column index of (l, m, cos/sin) in the Q = (L+1)^2 spherical-harmonic
+// columns: q(l,0) = l^2, q(l,m,cos) = l^2 + 2m - 1, q(l,m,sin) = l^2 + 2m.
+inline int qcol(int l, int m, int is_sin) { return m == 0 ? l * l : l * l + 2 * m - 1 + is_sin; }
+
+struct ColInfo {
+  int l, m, is_sin;
+};
+std::vector<ColInfo> column_table(int L);
+
+struct PatchGeom {
+  int n_t = 0, n_p = 0;
+  double d_t = 0, d_p = 0;
+  std::vector<double> th, ph;  // edges, n+1 each
+};
+PatchGeom make_patch(int n_t, int n_p, double d_t, double d_p);
+
+// resolution rule n = ceil(span/res) + 2, buffers split the surplus
+void dims_from_resolution(double res_deg, int *n_t, int *n_p, double *d_t, double *d_p);
+
+// exact overlap weights w[j*n_p + k] (Sect. 4, Eq. 25), closed-form areas
+void overlap_weights(const PatchGeom &g, double *w);
+
+// Schmidt-type normalised Legendre values pbar[q-independent index lm]
+// pbar_l^m(x) = sqrt((2 - delta_m0) (l-m)!/(l+m)!) P_l^m(x), Condon-Shortley
+// phase; out indexed [l*(L+1) + m].
+void legendre_normalised(int L, double x, double s, double *out);
+
+// sqrt((2 - delta_m0) (l-m)!/(l+m)!) for l, m <= L, indexed [l*(L+1)+m]
+std::vector<double> norm_sqrt(int L);
+
+// T-bar_j^(q) = sqrt(N^(lm)) T_j^(lm) at [j*Q + q] (same in cos/sin cols),
+// Gauss-Legendre quadrature in theta of sin(t) pbar_l^m(cos t).
+void theta_table_normalised(const PatchGeom &g, int L, double *out);
+
+// C_k^(m) / S_k^(m) (Eqs. 14-15) at [k*Q + q]
+void phi_table(const PatchGeom &g, int L, double *out);
+
+// radial coefficients [n][l][4] = alpha, beta, gamma, kappa (see yyg.h)
+void radial_coefficients(int n_r, const double *r, int L, double *out);
+
+// (cos t', sin t', phi') of every cell midpoint in the other frame, [a][3]
+void cross_points(const PatchGeom &g, double *out);
+
+// Synthesis bases: self part pbar(cos t_j) at [j*Q+q], trig(m phi_k) at [k*Q+q];
+// cross part pbar(cos t') trig(m phi') at [a*Q+q].
+void self_legendre_table(const PatchGeom &g, int L, double *out);
+void self_trig_table(const PatchGeom &g, int L, double *out);
+void cross_basis(const PatchGeom &g, int L, double *out);
+
+}  // namespace yyg

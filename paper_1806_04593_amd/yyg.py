@@ -1,0 +1,211 @@
+"""Thin ctypes binding of libyyg.so (include/yyg.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Device arrays are passed as torch CUDA tensors (their data pointer
+and the current stream); host arrays as numpy arrays.  Raises when the
+library has not been built — there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libyyg.so")
+
+FP64, FP32, BF16X3, FP16X2 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x2": FP16X2}
+
+TABLE_WEIGHTS, TABLE_THETA, TABLE_PHI, TABLE_RADIAL, TABLE_CROSS = 0, 1, 2, 3, 4
+
+EXPORTS = [
+    "yyg_grid_create", "yyg_grid_create_res", "yyg_grid_dims", "yyg_prepare",
+    "yyg_upload_rho", "yyg_solve", "yyg_get_moments", "yyg_get_weights",
+    "yyg_grid_destroy", "yyg_host_table", "yyg_set_timing", "yyg_get_timing",
+    "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
+]
+
+
+class YygError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {lib().yyg_status_string(status).decode()} ({status})")
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_r", ctypes.c_int),
+        ("r_edges", ctypes.POINTER(ctypes.c_double)),
+        ("n_theta", ctypes.c_int),
+        ("n_phi", ctypes.c_int),
+        ("delta_theta", ctypes.c_double),
+        ("delta_phi", ctypes.c_double),
+        ("lmax", ctypes.c_int),
+        ("G", ctypes.c_double),
+    ]
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1806_04593_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)
+        L.yyg_grid_create.argtypes = [ctypes.POINTER(GridDesc), i, ctypes.POINTER(vp)]
+        L.yyg_grid_create_res.argtypes = [i, dp, d, i, d, i, ctypes.POINTER(vp)]
+        L.yyg_grid_dims.argtypes = [vp] + [ctypes.POINTER(i)] * 4
+        L.yyg_prepare.argtypes = [vp, i]
+        L.yyg_upload_rho.argtypes = [vp, vp, i, vp]
+        L.yyg_solve.argtypes = [vp, vp, i, i, vp]
+        L.yyg_get_moments.argtypes = [vp, dp]
+        L.yyg_get_weights.argtypes = [vp, dp]
+        L.yyg_grid_destroy.argtypes = [vp]
+        L.yyg_host_table.argtypes = [ctypes.POINTER(GridDesc), i, dp, ctypes.c_size_t]
+        L.yyg_set_timing.argtypes = [vp, i]
+        L.yyg_get_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_long), i]
+        L.yyg_batch_create.argtypes = [ctypes.POINTER(vp), i, i, ctypes.POINTER(vp)]
+        L.yyg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        L.yyg_batch_destroy.argtypes = [vp]
+        L.yyg_status_string.argtypes = [i]
+        L.yyg_status_string.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "yyg_status_string":
+                getattr(L, name).restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(status, where):
+    if status != 0:
+        raise YygError(status, where)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_desc(r_edges, n_theta, n_phi, delta_theta, delta_phi, lmax, G):
+    r = np.ascontiguousarray(r_edges, dtype=np.float64)
+    d = GridDesc(len(r) - 1, _dptr(r), int(n_theta), int(n_phi), float(delta_theta),
+                 float(delta_phi), int(lmax), float(G))
+    d._keep = r  # keep the radii alive with the descriptor
+    return d
+
+
+def host_table(desc, which):
+    """Host-only table builder (no GPU needed); returns a numpy array."""
+    d = make_desc(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
+                  desc["delta_phi"], desc["lmax"], desc.get("G", 1.0))
+    Q = (desc["lmax"] + 1) ** 2
+    nang = desc["n_theta"] * desc["n_phi"]
+    n_r = len(desc["r_edges"]) - 1
+    shape = {TABLE_WEIGHTS: (desc["n_theta"], desc["n_phi"]),
+             TABLE_THETA: (desc["n_theta"], Q),
+             TABLE_PHI: (desc["n_phi"], Q),
+             TABLE_RADIAL: (n_r, desc["lmax"] + 1, 4),
+             TABLE_CROSS: (nang, 3)}[which]
+    shape = tuple(max(0, v) for v in shape)
+    out = np.zeros(shape)
+    buf = out if out.size else np.zeros(1)   # the library validates the sizes itself
+    _check(lib().yyg_host_table(ctypes.byref(d), which, _dptr(buf), out.size), "yyg_host_table")
+    return out
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Grid:
+    """A plan on one device: yyg_grid_create + the calls taking it."""
+
+    def __init__(self, desc, device=0):
+        d = make_desc(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
+                      desc["delta_phi"], desc["lmax"], desc["G"])
+        h = ctypes.c_void_p()
+        _check(lib().yyg_grid_create(ctypes.byref(d), int(device), ctypes.byref(h)), "yyg_grid_create")
+        self._h = h
+        self.device = device
+        n_r, n_t, n_p, Q = (ctypes.c_int() for _ in range(4))
+        _check(lib().yyg_grid_dims(h, ctypes.byref(n_r), ctypes.byref(n_t), ctypes.byref(n_p), ctypes.byref(Q)),
+               "yyg_grid_dims")
+        self.n_r, self.n_theta, self.n_phi, self.Q = n_r.value, n_t.value, n_p.value, Q.value
+        self.shape = (2, self.n_r, self.n_theta, self.n_phi)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def prepare(self, precision):
+        _check(lib().yyg_prepare(self._h, PRECISIONS.get(precision, precision)), "yyg_prepare")
+
+    def upload_rho(self, rho, stream=None):
+        """rho: torch CUDA tensor (borrowed) or numpy array (copied)."""
+        if isinstance(rho, np.ndarray):
+            r = np.ascontiguousarray(rho, dtype=np.float64)
+            assert r.shape == self.shape
+            self._host_rho = r
+            _check(lib().yyg_upload_rho(self._h, ctypes.c_void_p(r.ctypes.data), 0, _stream_handle(stream)),
+                   "yyg_upload_rho")
+        else:
+            import torch
+            assert rho.dtype == torch.float64 and rho.is_cuda and rho.is_contiguous()
+            assert tuple(rho.shape) == self.shape
+            self._dev_rho = rho
+            _check(lib().yyg_upload_rho(self._h, ctypes.c_void_p(rho.data_ptr()), 1, _stream_handle(stream)),
+                   "yyg_upload_rho")
+
+    def solve(self, phi, precision="fp64", stream=None):
+        """phi: preallocated torch CUDA float64 tensor (async) or numpy (sync)."""
+        p = PRECISIONS.get(precision, precision)
+        if isinstance(phi, np.ndarray):
+            assert phi.dtype == np.float64 and phi.flags.c_contiguous and phi.shape == self.shape
+            _check(lib().yyg_solve(self._h, ctypes.c_void_p(phi.ctypes.data), 0, p, _stream_handle(stream)),
+                   "yyg_solve")
+        else:
+            import torch
+            assert phi.dtype == torch.float64 and phi.is_cuda and phi.is_contiguous()
+            assert tuple(phi.shape) == self.shape
+            _check(lib().yyg_solve(self._h, ctypes.c_void_p(phi.data_ptr()), 1, p, _stream_handle(stream)),
+                   "yyg_solve")
+        return phi
+
+    def moments(self):
+        out = np.zeros((2, self.n_r, self.Q))
+        _check(lib().yyg_get_moments(self._h, _dptr(out)), "yyg_get_moments")
+        return out
+
+    def weights(self):
+        out = np.zeros((self.n_theta, self.n_phi))
+        _check(lib().yyg_get_weights(self._h, _dptr(out)), "yyg_get_weights")
+        return out
+
+    def set_timing(self, enable):
+        _check(lib().yyg_set_timing(self._h, int(bool(enable))), "yyg_set_timing")
+
+    def timing(self, n_slots=4):
+        ms = np.zeros(n_slots)
+        cnt = (ctypes.c_long * n_slots)()
+        _check(lib().yyg_get_timing(self._h, _dptr(ms), cnt, n_slots), "yyg_get_timing")
+        return ms, np.array(list(cnt))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yyg_grid_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def grid_from_workload(desc, device=0):
+    return Grid(desc, device)

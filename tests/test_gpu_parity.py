@@ -1,0 +1,170 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+FP64 gate: maximum pointwise relative error of Phi <= 1e-12 (the maximum
+relative error measure of Sect. 5; Phi < 0 everywhere for rho >= 0).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1806_04593_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _yyg():
+    from paper_1806_04593_amd import yyg
+    return yyg
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_solve(desc, rho, precision="fp64", grid=None):
+    torch = _torch()
+    yyg = _yyg()
+    g = grid or yyg.Grid(desc, 0)
+    if precision != "fp64":
+        g.prepare(precision)
+    d_rho = torch.from_numpy(rho).to("cuda")
+    d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda")
+    g.upload_rho(d_rho)
+    g.solve(d_phi, precision)
+    torch.cuda.synchronize()
+    return g, d_phi.cpu().numpy()
+
+
+def _oracle_args(desc):
+    return (desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"],
+            desc["lmax"], desc["G"])
+
+
+def _moments_to_q(AC, AS):
+    L = AC.shape[2] - 1
+    out = np.zeros(AC.shape[:2] + ((L + 1) ** 2,))
+    for l in range(L + 1):
+        out[:, :, l * l] = AC[:, :, l, 0]
+        for m in range(1, l + 1):
+            out[:, :, l * l + 2 * m - 1] = AC[:, :, l, m]
+            out[:, :, l * l + 2 * m] = AS[:, :, l, m]
+    return out
+
+
+def _max_rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def test_small_full_grid_fp64():
+    desc = W.describe("small")
+    _say(f"small: n_r=32 {desc['n_theta']}x{desc['n_phi']} lmax=8")
+    rho = W.density(desc)
+    g, phi = _gpu_solve(desc, rho)
+    ref = O.solve(*_oracle_args(desc), rho)
+    err = _max_rel(phi, ref)
+    _say(f"small max rel err {err:.3e}")
+    assert err <= TOL_FP64
+    # moments of Eqs. (26)-(27)
+    th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+    w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
+    AC, AS = O.moments(rho, w, O.theta_integrals(th, desc["lmax"]), *O.phi_integrals(ph, desc["lmax"]))
+    A_ref = _moments_to_q(AC, AS)
+    A = g.moments()
+    scale = np.max(np.abs(A_ref), axis=(0, 1), keepdims=True)
+    assert float(np.max(np.abs(A - A_ref) / scale)) < 1e-12
+    np.testing.assert_allclose(g.weights(), w, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", [
+    dict(r=np.array([0.0, 1.0]), res=7.0, lmax=0),                    # one shell, monopole only
+    dict(r=np.array([0.5, 0.7, 1.3]), res=11.0, lmax=3),              # tiny, r0 > 0
+    dict(r=np.linspace(0.0, 2.0, 131), res=9.0, lmax=11),             # M = 260: ragged M tiles
+    dict(r=np.geomspace(1.0, 1e3, 70), res=3.0, lmax=17),             # Q = 324, K = 2852: ragged all round
+])
+def test_ragged_and_degenerate_shapes(case):
+    desc = W.make_desc("edge", case["r"], case["res"], case["lmax"], 0.7, 0)
+    _say(f"edge case n_r={len(case['r']) - 1} res={case['res']} lmax={case['lmax']}")
+    rng = np.random.default_rng(9)
+    rho = rng.uniform(0.1, 1.0, (2, len(case["r"]) - 1, desc["n_theta"], desc["n_phi"]))
+    _, phi = _gpu_solve(desc, rho)
+    ref = O.solve(*_oracle_args(desc), rho)
+    assert _max_rel(phi, ref) <= TOL_FP64
+
+
+def _sampled_parity(name, n_samples, seed=0):
+    desc = W.describe(name)
+    _say(f"{name}: n_r={len(desc['r_edges']) - 1} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']}")
+    rho = W.density(desc)
+    g, phi = _gpu_solve(desc, rho)
+    rng = np.random.default_rng(seed)
+    nR = len(desc["r_edges"]) - 1
+    s = np.stack([rng.integers(0, 2, n_samples), rng.integers(0, nR, n_samples),
+                  rng.integers(0, desc["n_theta"], n_samples), rng.integers(0, desc["n_phi"], n_samples)], 1)
+    # always include the first and last shells and the patch corners
+    extra = np.array([[p, n, j, k] for p in (0, 1) for n in (0, nR - 1)
+                      for j in (0, desc["n_theta"] - 1) for k in (0, desc["n_phi"] - 1)])
+    s = np.concatenate([s, extra])
+    ref, (AC, AS) = O.solve_sampled(*_oracle_args(desc), rho, s, return_moments=True)
+    got = phi[s[:, 0], s[:, 1], s[:, 2], s[:, 3]]
+    err = _max_rel(got, ref)
+    _say(f"{name} sampled max rel err {err:.3e} over {len(s)} cells")
+    A_ref = _moments_to_q(AC, AS)
+    A = g.moments()
+    scale = np.max(np.abs(A_ref), axis=1, keepdims=True)
+    aerr = float(np.max(np.abs(A - A_ref) / scale))
+    _say(f"{name} moments max err (per-column scaled) {aerr:.3e}")
+    return err, aerr, g, rho, phi
+
+
+def test_sn_core_fp64():
+    err, aerr, *_ = _sampled_parity("sn_core", 3000)
+    assert err <= TOL_FP64
+    assert aerr < 1e-11
+
+
+def test_spheroid_fp64():
+    err, aerr, *_ = _sampled_parity("spheroid", 2000)
+    assert err <= TOL_FP64
+    assert aerr < 1e-11
+
+
+def test_determinism_and_patch_swap():
+    torch = _torch()
+    desc = W.describe("sn_core")
+    rho = W.density(desc)
+    g, phi1 = _gpu_solve(desc, rho)
+    _, phi2 = _gpu_solve(desc, rho, grid=g)
+    assert np.array_equal(phi1, phi2), "FP64 solve is not bitwise repeatable"
+    _, phis = _gpu_solve(desc, rho[::-1].copy(), grid=g)
+    assert _max_rel(phis, phi1[::-1]) < 1e-14
+    del torch
+
+
+def test_host_buffers_and_not_ready():
+    yyg = _yyg()
+    _torch()
+    desc = W.describe("small")
+    rho = W.density(desc)
+    g = yyg.Grid(desc, 0)
+    phi = np.zeros(g.shape)
+    with pytest.raises(yyg.YygError) as ei:
+        g.solve(phi)
+    assert ei.value.status == -4
+    g.upload_rho(rho)
+    g.solve(phi)
+    ref = O.solve(*_oracle_args(desc), rho)
+    assert _max_rel(phi, ref) <= TOL_FP64

@@ -1,0 +1,171 @@
+"""CPU tests of the C library's host logic: exported symbols, argument
+validation and the FP64 plan tables against the oracle.  No GPU calls."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1806_04593_amd import workloads as W
+from paper_1806_04593_amd import yyg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "yyg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(yyg_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = yyg.lib()
+    names = _header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(yyg.EXPORTS) == names
+
+
+def test_status_strings():
+    lib = yyg.lib()
+    for s in (0, -1, -2, -3, -4, -5, -6, 7):
+        assert isinstance(lib.yyg_status_string(s), bytes)
+
+
+def _desc(res, lmax, r_edges=None):
+    d = W.make_desc("t", np.linspace(0.0, 1.0, 9) if r_edges is None else r_edges, res, lmax, 1.0, 0)
+    return d
+
+
+def test_invalid_descriptors_rejected():
+    bad = [
+        dict(n_theta=0), dict(n_phi=-1), dict(lmax=-1), dict(lmax=yyg_cap() + 1),
+        dict(delta_theta=-0.1), dict(delta_phi=math.pi / 4), dict(r_edges=np.array([0.0, 1.0, 1.0])),
+        dict(r_edges=np.array([-1.0, 1.0])), dict(G=float("nan")),
+    ]
+    for change in bad:
+        d = dict(_desc(5.0, 4))
+        d.update(change)
+        with pytest.raises(yyg.YygError) as ei:
+            yyg.host_table(d, yyg.TABLE_WEIGHTS)
+        assert ei.value.status == -1, change
+        # plan creation validates before touching any device
+        gd = yyg.make_desc(d["r_edges"], d["n_theta"], d["n_phi"], d["delta_theta"], d["delta_phi"], d["lmax"], d["G"])
+        h = ctypes.c_void_p()
+        assert yyg.lib().yyg_grid_create(ctypes.byref(gd), 0, ctypes.byref(h)) == -1
+        assert not h.value
+
+
+def test_wrong_table_size_and_null_handles():
+    d = _desc(5.0, 4)
+    gd = yyg.make_desc(d["r_edges"], d["n_theta"], d["n_phi"], d["delta_theta"], d["delta_phi"], d["lmax"], 1.0)
+    out = np.zeros(10)
+    assert yyg.lib().yyg_host_table(ctypes.byref(gd), yyg.TABLE_WEIGHTS, yyg._dptr(out), 10) == -1
+    assert yyg.lib().yyg_host_table(ctypes.byref(gd), 99, yyg._dptr(out), 10) == -1
+    lib = yyg.lib()
+    assert lib.yyg_solve(None, None, 1, 0, None) == -1
+    assert lib.yyg_upload_rho(None, None, 1, None) == -1
+    assert lib.yyg_grid_destroy(None) == -1
+    assert lib.yyg_grid_dims(None, None, None, None, None) == -1
+
+
+def yyg_cap():
+    return 128
+
+
+@pytest.mark.parametrize("res", [15.0, 5.0, 2.0, 1.0])
+def test_weights_match_oracle(res):
+    d = _desc(res, 2)
+    w = yyg.host_table(d, yyg.TABLE_WEIGHTS)
+    th, ph = O.patch_edges(d["n_theta"], d["n_phi"], d["delta_theta"], d["delta_phi"])
+    wo = O.overlap_weights(th, ph, d["delta_theta"], d["delta_phi"])
+    # both sides sit within ~1e-13 of a 30-digit reference; small cells lose
+    # a few digits to the cancellation between whole-cell and covered areas
+    assert np.max(np.abs(w - wo)) < 1e-12
+    assert abs(np.sum(O.solid_angles(th, ph) * w) - 2 * math.pi) < 1e-13
+
+
+def test_weights_non_integer_span_and_zero_buffer():
+    # 4 deg: 90/4 = 22.5 -> 25 cells with 5 deg buffers; and a grid without buffers
+    for d in (_desc(4.0, 2), dict(_desc(5.0, 2), n_theta=18, n_phi=54, delta_theta=0.0, delta_phi=0.0)):
+        w = yyg.host_table(d, yyg.TABLE_WEIGHTS)
+        th, ph = O.patch_edges(d["n_theta"], d["n_phi"], d["delta_theta"], d["delta_phi"])
+        wo = O.overlap_weights(th, ph, d["delta_theta"], d["delta_phi"])
+        assert np.max(np.abs(w - wo)) < 1e-12
+
+
+def _col_lm(L):
+    cols = []
+    for l in range(L + 1):
+        cols.append((l, 0, 0))
+        for m in range(1, l + 1):
+            cols += [(l, m, 0), (l, m, 1)]
+    return cols
+
+
+@pytest.mark.parametrize("res,lmax", [(5.0, 24), (1.0, 64)])
+def test_theta_table_matches_oracle(res, lmax):
+    d = _desc(res, lmax)
+    T = yyg.host_table(d, yyg.TABLE_THETA)
+    th, _ = O.patch_edges(d["n_theta"], d["n_phi"], d["delta_theta"], d["delta_phi"])
+    To = O.theta_integrals(th, lmax)
+    for q, (l, m, s) in enumerate(_col_lm(lmax)):
+        ref = To[:, l, m]
+        assert np.max(np.abs(T[:, q] - ref)) <= 1e-12 * np.max(np.abs(ref)), (l, m)
+
+
+def test_phi_table_matches_oracle():
+    d = _desc(2.0, 25)
+    CSt = yyg.host_table(d, yyg.TABLE_PHI)
+    _, ph = O.patch_edges(d["n_theta"], d["n_phi"], d["delta_theta"], d["delta_phi"])
+    C, S = O.phi_integrals(ph, 25)
+    for q, (l, m, s) in enumerate(_col_lm(25)):
+        ref = S[:, m] if s else C[:, m]
+        assert np.max(np.abs(CSt[:, q] - ref)) < 1e-15
+
+
+def test_cross_points_match_oracle():
+    d = _desc(2.0, 1)
+    X = yyg.host_table(d, yyg.TABLE_CROSS)
+    th, ph = O.patch_edges(d["n_theta"], d["n_phi"], d["delta_theta"], d["delta_phi"])
+    T, P = np.meshgrid(0.5 * (th[:-1] + th[1:]), 0.5 * (ph[:-1] + ph[1:]), indexing="ij")
+    c, s, p = O.other_patch_angles(T.ravel(), P.ravel())
+    np.testing.assert_allclose(X[:, 0], c, atol=1e-15)
+    np.testing.assert_allclose(X[:, 1], s, atol=1e-15)
+    np.testing.assert_allclose(X[:, 2], p, atol=1e-14)
+
+
+@pytest.mark.parametrize("r_edges", [np.linspace(0.0, 1.0, 33), np.geomspace(1e5, 1e9, 61)])
+def test_radial_recurrence_reproduces_direct_sums(r_edges):
+    """Running the library's recurrence coefficients over random moments gives
+    the oracle's direct double sums of Eqs. (19)-(20)."""
+    L = 12
+    d = _desc(5.0, L, r_edges)
+    cf = yyg.host_table(d, yyg.TABLE_RADIAL)
+    nR = len(r_edges) - 1
+    rng = np.random.default_rng(3)
+    AC = rng.normal(size=(2, nR, L + 1, L + 1))
+    AS = rng.normal(size=(2, nR, L + 1, L + 1))
+    UC, US = O.radial_sums(AC, AS, r_edges)
+    for l in range(L + 1):
+        a = AC[:, :, l, :]
+        I = np.zeros_like(a[:, 0])
+        Iv = np.zeros_like(a)
+        for n in range(nR):
+            I = cf[n, l, 0] * I + cf[n, l, 1] * a[:, n]
+            Iv[:, n] = I
+        Ov = np.zeros_like(a)
+        Oc = np.zeros_like(a[:, 0])
+        for n in range(nR - 1, -1, -1):
+            an = a[:, n + 1] if n + 1 < nR else 0.0
+            Oc = cf[n, l, 2] * Oc + cf[n, l, 3] * an
+            Ov[:, n] = Oc
+        U = Iv + Ov
+        ref = UC[:, :, l, :]
+        scale = np.max(np.abs(ref[:, :, : l + 1]), axis=1, keepdims=True) + 1e-300
+        assert np.max(np.abs(U[:, :, : l + 1] - ref[:, :, : l + 1]) / scale) < 1e-12, l
