@@ -120,8 +120,9 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f64_kernel(
     __syncthreads();
   }
 
-  // D layout of the 16x16 f64 MFMA: lane l, element r -> row 4*(l/16)+r, col l%16.
-  const int orow = 4 * (lane >> 4), ocol = lane & 15;
+  // D layout of the 16x16x4 f64 MFMA: lane l, element r -> row l/16 + 4r,
+  // col l%16 (one row per group, unlike the f32 variant's four).
+  const int orow = lane >> 4, ocol = lane & 15;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f64_kernel(
       const int col = n0 + wn * 64 + j * 16 + ocol;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + orow + r;
+        const int row = m0 + wm * 64 + i * 16 + orow + 4 * r;
         if (row < M && col < N) C[(long)row * ldc + col] = acc[i][j][r];
       }
     }
