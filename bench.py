@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {a.gpus} requested); the solver holds the whole grid "
@@ -129,6 +130,13 @@ def main():
         g.prepare(a.precision)
     plan_s = time.perf_counter() - t0
     log(f"[bench] plan built in {plan_s:.2f} s")
+    tune_s = 0.0
+    if not a.no_autotune:
+        t0 = time.perf_counter()
+        g.autotune(a.precision)
+        tune_s = time.perf_counter() - t0
+    info = g.plan_info()
+    log(f"[bench] launch configuration {info} (autotune {tune_s:.2f} s)")
     d_rho = torch.from_numpy(rho).to("cuda:0")
     d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
     g.upload_rho(d_rho)
@@ -194,7 +202,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "n_r": nR, "n_theta": desc["n_theta"], "n_phi": desc["n_phi"],
                    "lmax": desc["lmax"], "cells": cells, "precision": a.precision,
-                   "max_rel_err_vs_oracle": err, "plan_build_s": round(plan_s, 3)},
+                   "max_rel_err_vs_oracle": err, "plan_build_s": round(plan_s, 3),
+                   "autotune_s": round(tune_s, 3), "launch": info},
         "roofline": {"bound": "mfma", "kernel": "synthesis gemm_nt (FP64 MFMA)" if a.precision == "fp64"
                      else f"synthesis ({a.precision})",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,

@@ -163,6 +163,26 @@ int yyg_host_table(const yyg_grid_desc *desc, int which, double *out, size_t n);
 int yyg_set_timing(yyg_grid *g, int enable);
 int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots);
 
+/* Choose the tile shape and split-K factor of both angular contractions
+ * for this plan by timing every candidate on the plan's own shapes (HIP
+ * events on `stream`; blocks until done).  Allocates scratch memory for the
+ * duration of the call and may grow the plan's partial-moment buffer.  With
+ * the environment variable YYG_TUNE_CACHE naming a file, earlier choices
+ * for the same (precision, shape) are read from it and new ones appended.
+ * Without autotuning a plan uses a fixed heuristic.  Results do not depend
+ * on the choice beyond FP64 summation order. */
+int yyg_autotune(yyg_grid *g, int precision, void *stream);
+
+/* Set the launch configuration by hand (tile variants as numbered by
+ * yyg_plan_info, split-K factor 1..64 of the analysis).  May allocate a
+ * larger partial-moment buffer; for tests and expert tuning. */
+int yyg_plan_config(yyg_grid *g, int var_ana, int split_ana, int var_syn);
+
+/* Current launch configuration: info[0..6] = analysis tile variant, its
+ * split-K factor, synthesis tile variant, analysis tile rows/cols,
+ * synthesis tile rows/cols (first n entries are written). */
+int yyg_plan_info(const yyg_grid *g, int *info, int n);
+
 /* Batched solves of several plans (uneven sizes and lmax allowed) in one
  * persistent launch per phase; see the design notes.  `grids` are borrowed
  * and must outlive the batch; all must be on one device.  d_rho[f], d_phi[f]

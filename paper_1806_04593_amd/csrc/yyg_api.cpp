@@ -6,7 +6,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -43,7 +47,10 @@ struct yyg_grid {
   int n_r = 0, n_t = 0, n_p = 0, L = 0, Q = 0;
   double G = 1.0;
   long nang = 0, ldb = 0, ldy = 0;
-  int nsplit = 1;
+  int nsplit = 1;        // split-K factor of the analysis contraction
+  int var_ana = 0;       // tile variant of the analysis contraction
+  int var_syn = 0;       // tile variant of the synthesis contraction
+  int part_cap = 1;      // splits the partial-moment buffer can hold
   std::vector<double> r_edges, w_host, nrm_q;
   yyg::PatchGeom geom;
 
@@ -138,6 +145,63 @@ int choose_split(long tiles, long K) {
 }
 }  // namespace yyg
 
+namespace {
+
+// Timing of one launch configuration: one warm-up, then the
+// minimum over `reps` event-timed launches (timings are data-independent).
+template <class F>
+double time_launch(F launch, hipStream_t s, int reps) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return 1e30;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return 1e30;
+  }
+  double best = 1e30;
+  if (launch() == hipSuccess && hipStreamSynchronize(s) == hipSuccess) {
+    for (int r = 0; r < reps; ++r) {
+      (void)hipEventRecord(a, s);
+      hipError_t e = launch();
+      (void)hipEventRecord(b, s);
+      if (e != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+        best = 1e30;
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      best = std::min(best, (double)ms);
+    }
+  }
+  (void)hipGetLastError();
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+std::string tune_key(int prec, int role, long M, long N, long K) {
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "p%d r%d %ld %ld %ld", prec, role, M, N, K);
+  return buf;
+}
+
+std::map<std::string, std::pair<int, int>> read_tune_cache(const char *path) {
+  std::map<std::string, std::pair<int, int>> m;
+  if (!path) return m;
+  std::FILE *f = std::fopen(path, "r");
+  if (!f) return m;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    int p, r, v, sp;
+    long M, N, K;
+    if (std::sscanf(line, "p%d r%d %ld %ld %ld -> %d %d", &p, &r, &M, &N, &K, &v, &sp) == 7)
+      m[tune_key(p, r, M, N, K)] = {v, sp};
+  }
+  std::fclose(f);
+  return m;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *yyg_status_string(int status) {
@@ -223,7 +287,12 @@ int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
   g->geom = yyg::make_patch(g->n_t, g->n_p, d->delta_theta, d->delta_phi);
   const int L = g->L, Q = g->Q, n_r = g->n_r;
   const long M = 2L * n_r;
-  g->nsplit = yyg::choose_split(((M + 127) / 128) * ((Q + 127) / 128), g->nang);
+  {
+    int bm, bn;
+    yyg::gemm_f64_variant_tile(g->var_ana, &bm, &bn);
+    g->nsplit = yyg::choose_split(((M + bm - 1) / bm) * ((Q + bn - 1) / bn), g->nang);
+    g->part_cap = g->nsplit;
+  }
 
   std::vector<double> Tt, CS, coef, P, Tr, Yx;
   std::vector<int> qdeg(Q);
@@ -380,8 +449,8 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
   }
   hipError_t e;
   int t = timing_begin(g, 0, s);
-  e = yyg::launch_gemm_nt_f64((int)M, Q, (int)g->nang, g->rho, g->nang, g->d_Bt, g->ldb, g->d_part, Q, g->nsplit,
-                              M * Q, s);
+  e = yyg::launch_gemm_nt_f64(g->var_ana, 0, (int)M, Q, (int)g->nang, g->rho, g->nang, g->d_Bt, g->ldb, g->d_part,
+                              Q, g->nsplit, M * Q, s);
   timing_end(g, t, s);
   if (e == hipSuccess) {
     t = timing_begin(g, 1, s);
@@ -391,7 +460,8 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
   }
   if (e == hipSuccess) {
     t = timing_begin(g, 2, s);
-    e = yyg::launch_gemm_nt_f64((int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, out, g->nang, 1, 0, s);
+    e = yyg::launch_gemm_nt_f64(g->var_syn, 1, (int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, out,
+                                g->nang, 1, 0, s);
     timing_end(g, t, s);
   }
   if (!phi_is_device) {
@@ -471,6 +541,139 @@ int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots) {
       counts[t.slot] += 1;
     }
   }
+  return YYG_OK;
+}
+
+int yyg_autotune(yyg_grid *g, int precision, void *stream) {
+  if (!g) return YYG_ERR_INVALID_ARG;
+  if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
+  if (precision != YYG_FP64) return YYG_ERR_NOT_READY;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  hipStream_t s = as_stream(stream);
+  const int Q = g->Q;
+  const long M = 2L * g->n_r;
+  const char *cache_path = std::getenv("YYG_TUNE_CACHE");
+  auto cache = read_tune_cache(cache_path);
+  const std::string ka = tune_key(precision, 0, M, Q, g->nang), ks = tune_key(precision, 1, M, g->nang, 2L * Q);
+  int best_va = g->var_ana, best_sp = g->nsplit, best_vs = g->var_syn;
+  bool have_a = false, have_s = false;
+  if (cache.count(ka)) {
+    best_va = cache[ka].first;
+    best_sp = cache[ka].second;
+    have_a = best_va >= 0 && best_va < yyg::gemm_f64_variant_count() && best_sp >= 1 && best_sp <= 32;
+  }
+  if (cache.count(ks)) {
+    best_vs = cache[ks].first;
+    have_s = best_vs >= 0 && best_vs < yyg::gemm_f64_variant_count();
+  }
+  double *tmp_in = nullptr, *tmp_out = nullptr, *tmp_part = nullptr;
+  const int smax = 32;
+  int st = YYG_OK;
+  if (!have_a || !have_s) {
+    if (!g->rho) st = dmalloc(&tmp_in, (size_t)M * g->nang);
+    if (st == YYG_OK) st = dmalloc(&tmp_out, (size_t)M * g->nang);
+    if (st == YYG_OK) st = dmalloc(&tmp_part, (size_t)smax * M * Q);
+    if (st == YYG_OK && tmp_in) (void)hipMemsetAsync(tmp_in, 0, (size_t)M * g->nang * sizeof(double), s);
+    if (st != YYG_OK) {
+      if (tmp_in) (void)hipFree(tmp_in);
+      if (tmp_out) (void)hipFree(tmp_out);
+      if (tmp_part) (void)hipFree(tmp_part);
+      return st;
+    }
+  }
+  const double *rho = g->rho ? g->rho : tmp_in;
+  const int nv = yyg::gemm_f64_variant_count();
+  if (!have_a) {
+    double best = 1e30;
+    for (int v = 0; v < nv; ++v) {
+      int bm, bn;
+      yyg::gemm_f64_variant_tile(v, &bm, &bn);
+      long tiles = ((M + bm - 1) / bm) * ((Q + bn - 1) / bn);
+      int base = yyg::choose_split(tiles, g->nang);
+      int cands[] = {1, 2, 4, 8, 16, 32, base};
+      for (int sp : cands) {
+        if (sp > smax || (long)sp * 64 > g->nang + 64) continue;
+        double t = time_launch([&] {
+          return yyg::launch_gemm_nt_f64(v, 0, (int)M, Q, (int)g->nang, rho, g->nang, g->d_Bt, g->ldb, tmp_part, Q,
+                                         sp, M * Q, s);
+        }, s, 3);
+        // the scan reads every partial once more: charge it at HBM speed
+        t += (double)sp * M * Q * 8.0 / 5.0e9;
+        if (t < best) {
+          best = t;
+          best_va = v;
+          best_sp = sp;
+        }
+      }
+    }
+  }
+  if (!have_s) {
+    double best = 1e30;
+    for (int v = 0; v < nv; ++v) {
+      double t = time_launch([&] {
+        return yyg::launch_gemm_nt_f64(v, 1, (int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, tmp_out,
+                                       g->nang, 1, 0, s);
+      }, s, 3);
+      if (t < best) {
+        best = t;
+        best_vs = v;
+      }
+    }
+  }
+  if (tmp_in) (void)hipFree(tmp_in);
+  if (tmp_out) (void)hipFree(tmp_out);
+  if (tmp_part) (void)hipFree(tmp_part);
+  if (best_sp > g->part_cap) {
+    double *np = nullptr;
+    if (dmalloc(&np, (size_t)best_sp * M * Q) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->d_part);
+    g->d_part = np;
+    g->part_cap = best_sp;
+  }
+  g->var_ana = best_va;
+  g->nsplit = best_sp;
+  g->var_syn = best_vs;
+  if (cache_path && (!have_a || !have_s)) {
+    if (std::FILE *f = std::fopen(cache_path, "a")) {
+      if (!have_a) std::fprintf(f, "%s -> %d %d\n", ka.c_str(), best_va, best_sp);
+      if (!have_s) std::fprintf(f, "%s -> %d %d\n", ks.c_str(), best_vs, 1);
+      std::fclose(f);
+    }
+  }
+  return YYG_OK;
+}
+
+int yyg_plan_config(yyg_grid *g, int var_ana, int split_ana, int var_syn) {
+  if (!g) return YYG_ERR_INVALID_ARG;
+  const int nv = yyg::gemm_f64_variant_count();
+  if (var_ana < 0 || var_ana >= nv || var_syn < 0 || var_syn >= nv || split_ana < 1 || split_ana > 64)
+    return YYG_ERR_INVALID_ARG;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  if (split_ana > g->part_cap) {
+    const long M = 2L * g->n_r;
+    double *np = nullptr;
+    if (dmalloc(&np, (size_t)split_ana * M * g->Q) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->d_part);
+    g->d_part = np;
+    g->part_cap = split_ana;
+  }
+  g->var_ana = var_ana;
+  g->nsplit = split_ana;
+  g->var_syn = var_syn;
+  return YYG_OK;
+}
+
+int yyg_plan_info(const yyg_grid *g, int *info, int n) {
+  if (!g || !info || n < 1) return YYG_ERR_INVALID_ARG;
+  int ba, bn_a, bs, bn_s;
+  yyg::gemm_f64_variant_tile(g->var_ana, &ba, &bn_a);
+  yyg::gemm_f64_variant_tile(g->var_syn, &bs, &bn_s);
+  const int vals[7] = {g->var_ana, g->nsplit, g->var_syn, ba, bn_a, bs, bn_s};
+  for (int i = 0; i < n && i < 7; ++i) info[i] = vals[i];
   return YYG_OK;
 }
 

@@ -22,7 +22,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kBM = 128, kBN = 128, kBK = 16, kPad = 2, kLDK = kBK + kPad;
+constexpr int kBK = 16, kPad = 2, kLDK = kBK + kPad;
 
 // Logical tile of a block so that the blocks one XCD receives (the hardware
 // hands blocks to the 8 XCDs round-robin) form a contiguous run of tiles in
@@ -35,51 +35,62 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 
 }  // namespace
 
-__global__ __launch_bounds__(256, 2) void gemm_nt_f64_kernel(
+// ROLE only separates the analysis (0) and synthesis (1) instantiations so
+// that profilers list them apart.  Block tile BM x BN, WGM x WGN waves, each
+// wave a (BM/WGM) x (BN/WGN) grid of 16 x 16 MFMA tiles.
+template <int ROLE, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(
     int M, int N, int K, const double *__restrict__ A, long lda, const double *__restrict__ B, long ldb,
     double *__restrict__ C, long ldc, long c_split_stride, int k_per_split, int tiles_m, int tiles_total) {
-  __shared__ double As[2][kBM * kLDK];
-  __shared__ double Bs[2][kBN * kLDK];
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int TI = BM / WGM / 16, TJ = BN / WGN / 16;
+  constexpr int EA = BM * kBK / NT, EB = BN * kBK / NT;  // doubles per thread per stage
+  static_assert(EA >= 1 && EB >= 1 && kBK % EA == 0 && kBK % EB == 0, "tile/thread mismatch");
+  __shared__ double As[2][BM * kLDK];
+  __shared__ double Bs[2][BN * kLDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tile = xcd_tile(blockIdx.x, tiles_total);
   const int tm = tile % tiles_m, tn = tile / tiles_m;
-  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int m0 = tm * BM, n0 = tn * BN;
   const int z = blockIdx.y;
   const int kbeg = z * k_per_split;
   const int kend = min(K, kbeg + k_per_split);
   C += (long)z * c_split_stride;
 
-  const int wm = wave & 1, wn = wave >> 1;
-  const int lrow = tid >> 1, lcol = (tid & 1) * 8;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int arow = tid / (kBK / EA), acol = (tid % (kBK / EA)) * EA;
+  const int brow = tid / (kBK / EB), bcol = (tid % (kBK / EB)) * EB;
 
-  dbl4 acc[4][4];
+  dbl4 acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  double ra[8], rb[8];
-  const int ga = m0 + lrow, gb = n0 + lrow;
+  double ra[EA], rb[EB];
+  const int ga = m0 + arow, gb = n0 + brow;
   const double *pa = A + (long)min(ga, M - 1) * lda;
   const double *pb = B + (long)min(gb, N - 1) * ldb;
   const bool va = ga < M, vb = gb < N;
 
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int kk = k0 + lcol + i;
-      const bool kin = kk < kend;
-      ra[i] = (va && kin) ? pa[kk] : 0.0;
-      rb[i] = (vb && kin) ? pb[kk] : 0.0;
+    for (int i = 0; i < EA; ++i) {
+      const int kk = k0 + acol + i;
+      ra[i] = (va && kk < kend) ? pa[kk] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int kk = k0 + bcol + i;
+      rb[i] = (vb && kk < kend) ? pb[kk] : 0.0;
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      As[buf][lrow * kLDK + lcol + i] = ra[i];
-      Bs[buf][lrow * kLDK + lcol + i] = rb[i];
-    }
+    for (int i = 0; i < EA; ++i) As[buf][arow * kLDK + acol + i] = ra[i];
+#pragma unroll
+    for (int i = 0; i < EB; ++i) Bs[buf][brow * kLDK + bcol + i] = rb[i];
   };
 
   const int nk = (kend - kbeg + kBK - 1) / kBK;
@@ -96,41 +107,41 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f64_kernel(
     if (more) load(kbeg + (it + 1) * kBK);
     // Each lane holds four consecutive k of its row; MFMA step s uses the
     // s-th of them, so the four steps cover the 16 k of the stage once.
-    double af[4][4], bf[4][4];
+    double af[TI][4], bf[TJ][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double *s = &As[buf][(wm * 64 + i * 16 + frow) * kLDK + fk];
+    for (int i = 0; i < TI; ++i) {
+      const double *s = &As[buf][(wm * (BM / WGM) + i * 16 + frow) * kLDK + fk];
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) af[i][s4] = s[s4];
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double *s = &Bs[buf][(wn * 64 + j * 16 + frow) * kLDK + fk];
+    for (int j = 0; j < TJ; ++j) {
+      const double *s = &Bs[buf][(wn * (BN / WGN) + j * 16 + frow) * kLDK + fk];
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) bf[j][s4] = s[s4];
     }
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
     if (more) stash(buf ^ 1);
     __syncthreads();
   }
 
   // D layout of the 16x16x4 f64 MFMA: lane l, element r -> row l/16 + 4r,
-  // col l%16 (one row per group, unlike the f32 variant's four).
+  // col l%16 (one row per output group, unlike the f32 variant's four).
   const int orow = lane >> 4, ocol = lane & 15;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < TI; ++i) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = n0 + wn * 64 + j * 16 + ocol;
+    for (int j = 0; j < TJ; ++j) {
+      const int col = n0 + wn * (BN / WGN) + j * 16 + ocol;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + orow + 4 * r;
+        const int row = m0 + wm * (BM / WGM) + i * 16 + orow + 4 * r;
         if (row < M && col < N) C[(long)row * ldc + col] = acc[i][j][r];
       }
     }
@@ -142,10 +153,12 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f64_kernel(
 //   I_n = alpha_n I_(n-1) + beta_n A_n            (I_(-1) = 0)
 //   O_n = gamma_n O_(n+1) + kappa_n A_(n+1)       (O_(nR-1) = 0)
 // Block: 64 columns x nw waves; wave w owns a contiguous chunk of radii.
+// General form for any number of shells (the register form below covers
+// n_r <= 1024).
 // Chunk summaries (product of multipliers, local value) combine in LDS.
 // Output Ucat[(p, n)][q] = -G U[p, n, q] and Ucat[(pbar, n)][Q + q] = the same
 // value, i.e. the synthesis operand [self | other] of Eqs. (28)-(29).
-__global__ __launch_bounds__(1024) void radial_scan_kernel(
+__global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
     const double *__restrict__ part, int nsplit, long split_stride, double *__restrict__ Ahat,
     const double *__restrict__ coef, const int *__restrict__ qdeg, int nR, int Q, int L, double negG,
     double *__restrict__ U, long ldu) {
@@ -216,6 +229,99 @@ __global__ __launch_bounds__(1024) void radial_scan_kernel(
   }
 }
 
+
+// Register form of the radial scan for n_r <= 64 * CMAX.  Block = 16 columns
+// x 64 radial chunks (one thread per (column, chunk)); each thread keeps its
+// chunk's moments in registers, so every pass after the first load is
+// register/LDS work.  Same recurrences, outputs and reduction order as the
+// loop form.
+template <int CMAX>
+__global__ __launch_bounds__(1024) void radial_scan_kernel(
+    const double *__restrict__ part, int nsplit, long split_stride, double *__restrict__ Ahat,
+    const double *__restrict__ coef, const int *__restrict__ qdeg, int nR, int Q, int L, double negG,
+    double *__restrict__ U, long ldu) {
+  __shared__ double sI[64][16], sPa[64][16], sO[64][16], sPg[64][16];
+  const int x = threadIdx.x, y = threadIdx.y;
+  const int q = blockIdx.x * 16 + x;
+  const int p = blockIdx.y;
+  const bool ok = q < Q;
+  const int qq = ok ? q : 0;
+  const int l = qdeg[qq];
+  const int chunk = (nR + 63) / 64;
+  const int n0 = min(nR, y * chunk), n1 = min(nR, n0 + chunk);
+  const int len = n1 - n0;
+  const long rbase = (long)p * nR;
+  const double *cf = coef + (long)l * 4;
+  const long cstride = (long)(L + 1) * 4;
+
+  // a[i] = A at radius n0 + i, i <= len (the element past the chunk feeds
+  // the outer recurrence); zero beyond the grid.
+  double a[CMAX + 1];
+#pragma unroll
+  for (int i = 0; i <= CMAX; ++i) {
+    double v = 0.0;
+    if (ok && i <= len && n0 + i < nR) {
+      const long off = (rbase + n0 + i) * Q + qq;
+      for (int zz = 0; zz < nsplit; ++zz) v += part[zz * split_stride + off];
+    }
+    a[i] = v;
+  }
+  if (ok) {
+#pragma unroll
+    for (int i = 0; i < CMAX; ++i)
+      if (i < len) Ahat[(rbase + n0 + i) * Q + qq] = a[i];
+  }
+  double I = 0.0, Pa = 1.0, O = 0.0, Pg = 1.0;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) {
+    if (i < len) {
+      const double *c = cf + (n0 + i) * cstride;
+      I = c[0] * I + c[1] * a[i];
+      Pa *= c[0];
+    }
+  }
+#pragma unroll
+  for (int i = CMAX - 1; i >= 0; --i) {
+    if (i < len) {
+      const double *c = cf + (n0 + i) * cstride;
+      O = c[2] * O + c[3] * a[i + 1];
+      Pg *= c[2];
+    }
+  }
+  sI[y][x] = I;
+  sPa[y][x] = Pa;
+  sO[y][x] = O;
+  sPg[y][x] = Pg;
+  __syncthreads();
+  if (!ok) return;
+  double Iin = 0.0, Oin = 0.0;
+  for (int c = 0; c < y; ++c) Iin = sPa[c][x] * Iin + sI[c][x];
+  for (int c = 63; c > y; --c) Oin = sPg[c][x] * Oin + sO[c][x];
+
+  double Iv[CMAX];
+  I = Iin;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) {
+    if (i < len) {
+      const double *c = cf + (n0 + i) * cstride;
+      I = c[0] * I + c[1] * a[i];
+    }
+    Iv[i] = I;
+  }
+  const long rbar = (long)(1 - p) * nR;
+  O = Oin;
+#pragma unroll
+  for (int i = CMAX - 1; i >= 0; --i) {
+    if (i < len) {
+      const double *c = cf + (n0 + i) * cstride;
+      O = c[2] * O + c[3] * a[i + 1];
+      const double v = negG * (Iv[i] + O);
+      U[(rbase + n0 + i) * ldu + q] = v;
+      U[(rbar + n0 + i) * ldu + Q + q] = v;
+    }
+  }
+}
+
 // Bt[q][a] = w[a] Tbar[j][q] CS[k][q], a = j*n_p + k (analysis basis,
 // Eqs. 26-27 with sqrt(N^(lm)) folded in); zero in the padding columns.
 __global__ void expand_analysis_basis_kernel(const double *__restrict__ w, const double *__restrict__ Tt,
@@ -251,26 +357,73 @@ __global__ void expand_self_basis_kernel(const double *__restrict__ P, const dou
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_gemm_nt_f64(int M, int N, int K, const double *A, long lda, const double *B, long ldb, double *C,
-                              long ldc, int nsplit, long c_split_stride, hipStream_t s) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  const int tiles_m = (M + kBM - 1) / kBM, tiles_n = (N + kBN - 1) / kBN;
+namespace {
+
+template <int BM, int BN, int WGM, int WGN>
+hipError_t launch_gemm_variant(int role, int M, int N, int K, const double *A, long lda, const double *B, long ldb,
+                               double *C, long ldc, int nsplit, long c_split_stride, hipStream_t s) {
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   int kps = (K + nsplit - 1) / nsplit;
   kps = ((kps + kBK - 1) / kBK) * kBK;
-  dim3 grid(tiles_m * tiles_n, nsplit);
-  hipLaunchKernelGGL(gemm_nt_f64_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, c_split_stride,
-                     kps, tiles_m, tiles_m * tiles_n);
+  dim3 grid(tiles_m * tiles_n, nsplit), block(64 * WGM * WGN);
+  if (role == 0)
+    hipLaunchKernelGGL((gemm_nt_f64_kernel<0, BM, BN, WGM, WGN>), grid, block, 0, s, M, N, K, A, lda, B, ldb, C, ldc,
+                       c_split_stride, kps, tiles_m, tiles_m * tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_nt_f64_kernel<1, BM, BN, WGM, WGN>), grid, block, 0, s, M, N, K, A, lda, B, ldb, C, ldc,
+                       c_split_stride, kps, tiles_m, tiles_m * tiles_n);
   return hipGetLastError();
+}
+
+typedef hipError_t (*gemm_f64_fn)(int, int, int, int, const double *, long, const double *, long, double *, long, int,
+                                  long, hipStream_t);
+
+struct F64Variant {
+  int bm, bn;
+  gemm_f64_fn fn;
+};
+
+const F64Variant kF64Variants[] = {
+    {128, 128, launch_gemm_variant<128, 128, 2, 2>},
+    {64, 128, launch_gemm_variant<64, 128, 2, 2>},
+    {128, 64, launch_gemm_variant<128, 64, 2, 2>},
+    {64, 64, launch_gemm_variant<64, 64, 2, 2>},
+    {256, 128, launch_gemm_variant<256, 128, 4, 2>},
+    {128, 256, launch_gemm_variant<128, 256, 2, 4>},
+};
+
+}  // namespace
+
+int gemm_f64_variant_count() { return (int)(sizeof(kF64Variants) / sizeof(kF64Variants[0])); }
+
+void gemm_f64_variant_tile(int v, int *bm, int *bn) {
+  *bm = kF64Variants[v].bm;
+  *bn = kF64Variants[v].bn;
+}
+
+hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const double *A, long lda, const double *B,
+                              long ldb, double *C, long ldc, int nsplit, long c_split_stride, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (variant < 0 || variant >= gemm_f64_variant_count()) return hipErrorInvalidValue;
+  return kF64Variants[variant].fn(role, M, N, K, A, lda, B, ldb, C, ldc, nsplit, c_split_stride, s);
 }
 
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
                               const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu,
                               hipStream_t s) {
-  int nw = 16;
-  while (nw > 1 && nR / nw < 8) nw >>= 1;
-  dim3 block(64, nw), grid((Q + 63) / 64, 2);
-  hipLaunchKernelGGL(radial_scan_kernel, grid, block, 0, s, part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L,
-                     negG, U, ldu);
+  if (nR <= 64 * 4) {
+    hipLaunchKernelGGL(radial_scan_kernel<4>, dim3((Q + 15) / 16, 2), dim3(16, 64), 0, s, part, nsplit, split_stride,
+                       Ahat, coef, qdeg, nR, Q, L, negG, U, ldu);
+  } else if (nR <= 64 * 16) {
+    hipLaunchKernelGGL(radial_scan_kernel<16>, dim3((Q + 15) / 16, 2), dim3(16, 64), 0, s, part, nsplit,
+                       split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu);
+  } else {
+    int nw = 16;
+    while (nw > 1 && nR / nw < 8) nw >>= 1;
+    dim3 block(64, nw), grid((Q + 63) / 64, 2);
+    hipLaunchKernelGGL(radial_scan_loop_kernel, grid, block, 0, s, part, nsplit, split_stride, Ahat, coef, qdeg, nR,
+                       Q, L, negG, U, ldu);
+  }
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ EXPORTS = [
     "yyg_upload_rho", "yyg_solve", "yyg_get_moments", "yyg_get_weights",
     "yyg_grid_destroy", "yyg_host_table", "yyg_set_timing", "yyg_get_timing",
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
+    "yyg_autotune", "yyg_plan_info", "yyg_plan_config",
 ]
 
 
@@ -71,6 +72,9 @@ def lib():
         L.yyg_batch_create.argtypes = [ctypes.POINTER(vp), i, i, ctypes.POINTER(vp)]
         L.yyg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.yyg_batch_destroy.argtypes = [vp]
+        L.yyg_autotune.argtypes = [vp, i, vp]
+        L.yyg_plan_info.argtypes = [vp, ctypes.POINTER(i), i]
+        L.yyg_plan_config.argtypes = [vp, i, i, i]
         L.yyg_status_string.argtypes = [i]
         L.yyg_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -175,6 +179,19 @@ class Grid:
             _check(lib().yyg_solve(self._h, ctypes.c_void_p(phi.data_ptr()), 1, p, _stream_handle(stream)),
                    "yyg_solve")
         return phi
+
+    def autotune(self, precision="fp64", stream=None):
+        _check(lib().yyg_autotune(self._h, PRECISIONS.get(precision, precision), _stream_handle(stream)),
+               "yyg_autotune")
+
+    def plan_info(self):
+        info = (ctypes.c_int * 7)()
+        _check(lib().yyg_plan_info(self._h, info, 7), "yyg_plan_info")
+        keys = ("var_ana", "split_ana", "var_syn", "bm_ana", "bn_ana", "bm_syn", "bn_syn")
+        return dict(zip(keys, list(info)))
+
+    def set_config(self, var_ana, split_ana, var_syn):
+        _check(lib().yyg_plan_config(self._h, int(var_ana), int(split_ana), int(var_syn)), "yyg_plan_config")
 
     def moments(self):
         out = np.zeros((2, self.n_r, self.Q))

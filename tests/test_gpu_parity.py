@@ -116,6 +116,44 @@ def test_ragged_and_degenerate_shapes(case):
     assert _max_rel(phi, ref) <= TOL_FP64
 
 
+N_F64_VARIANTS = 6
+
+
+@pytest.mark.parametrize("case", [
+    dict(r=np.linspace(0.0, 2.0, 131), res=9.0, lmax=11),
+    dict(r=np.geomspace(1.0, 1e3, 70), res=3.0, lmax=17),
+])
+def test_every_tile_variant_and_split(case):
+    """Each FP64 tile shape, and split-K factors 1..7 of the analysis, give the
+    oracle's potential."""
+    desc = W.make_desc("var", case["r"], case["res"], case["lmax"], 1.0, 0)
+    rng = np.random.default_rng(4)
+    rho = rng.uniform(0.1, 1.0, (2, len(case["r"]) - 1, desc["n_theta"], desc["n_phi"]))
+    ref = O.solve(*_oracle_args(desc), rho)
+    g = _yyg().Grid(desc, 0)
+    for v in range(N_F64_VARIANTS):
+        for split in (1, 3, 7):
+            _say(f"variant {v} split {split}")
+            g.set_config(v, split, (v + split) % N_F64_VARIANTS)
+            _, phi = _gpu_solve(desc, rho, grid=g)
+            assert _max_rel(phi, ref) <= TOL_FP64, (v, split)
+
+
+def test_autotune_keeps_parity():
+    desc = W.describe("sn_core")
+    rho = W.density(desc)
+    g = _yyg().Grid(desc, 0)
+    g.autotune("fp64")
+    _say(f"autotuned: {g.plan_info()}")
+    _, phi = _gpu_solve(desc, rho, grid=g)
+    rng = np.random.default_rng(1)
+    nR = len(desc["r_edges"]) - 1
+    s = np.stack([rng.integers(0, 2, 500), rng.integers(0, nR, 500),
+                  rng.integers(0, desc["n_theta"], 500), rng.integers(0, desc["n_phi"], 500)], 1)
+    ref = O.solve_sampled(*_oracle_args(desc), rho, s)
+    assert _max_rel(phi[s[:, 0], s[:, 1], s[:, 2], s[:, 3]], ref) <= TOL_FP64
+
+
 def _sampled_parity(name, n_samples, seed=0):
     desc = W.describe(name)
     _say(f"{name}: n_r={len(desc['r_edges']) - 1} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']}")
