@@ -19,6 +19,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp16x2": 2500.0}   # dense MFMA TFLOP/s
+# MFMA products executed per algorithmic multiply-add (operand-split terms)
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "fp16x2": 3}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "fp16x2": "f16x2"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1806_04593_amd", "csrc", "yyg_kernels.hip")
 
@@ -135,7 +137,7 @@ def main():
         t0 = time.perf_counter()
         g.autotune(a.precision)
         tune_s = time.perf_counter() - t0
-    info = g.plan_info()
+    info = g.plan_info(a.precision)
     log(f"[bench] launch configuration {info} (autotune {tune_s:.2f} s)")
     d_rho = torch.from_numpy(rho).to("cuda:0")
     d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
@@ -204,10 +206,12 @@ def main():
                    "lmax": desc["lmax"], "cells": cells, "precision": a.precision,
                    "max_rel_err_vs_oracle": err, "plan_build_s": round(plan_s, 3),
                    "autotune_s": round(tune_s, 3), "launch": info},
-        "roofline": {"bound": "mfma", "kernel": "synthesis gemm_nt (FP64 MFMA)" if a.precision == "fp64"
-                     else f"synthesis ({a.precision})",
+        "roofline": {"bound": "mfma", "kernel": ("gemm_nt_f64_kernel<1,...> (synthesis)" if a.precision == "fp64"
+                                                 else f"gemm_nt_lp_kernel<1,...> (synthesis, {a.precision})"),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "executed_products_per_mac": PRODUCTS[a.precision],
+                     "executed_frac": achieved * PRODUCTS[a.precision] / peak},
         "kernels_ms": {"analysis": avg[0], "radial_scan": avg[1], "synthesis": avg[2], "convert": avg[3]},
         "cpu_baseline": cpu,
     }

@@ -96,8 +96,10 @@ int yyg_grid_create_res(int n_r, const double *r_edges, double res_deg, int lmax
 /* Sizes of a plan.  Any output pointer may be NULL. */
 int yyg_grid_dims(const yyg_grid *g, int *n_r, int *n_theta, int *n_phi, int *Q);
 
-/* Build the extra tables a reduced-precision path needs (no-op for FP64).
- * Allocates; call before capturing a solve in a graph. */
+/* Build the extra tables a reduced-precision path needs (no-op for FP64):
+ * the analysis and synthesis bases split into 1 (FP32), 3 (BF16) or 2
+ * (FP16) planes of the operand type, each basis row scaled by a power of
+ * two.  Allocates; call before timing or capturing solves. */
 int yyg_prepare(yyg_grid *g, int precision);
 
 /* Hand the density to the plan.  rho_is_device != 0: `rho` is a device
@@ -173,15 +175,16 @@ int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots);
  * on the choice beyond FP64 summation order. */
 int yyg_autotune(yyg_grid *g, int precision, void *stream);
 
-/* Set the launch configuration by hand (tile variants as numbered by
- * yyg_plan_info, split-K factor 1..64 of the analysis).  May allocate a
- * larger partial-moment buffer; for tests and expert tuning. */
-int yyg_plan_config(yyg_grid *g, int var_ana, int split_ana, int var_syn);
+/* Set the launch configuration of one precision by hand (tile variants as
+ * numbered by yyg_plan_info, split-K factor 1..64 of the analysis).  May
+ * allocate a larger partial-moment buffer; for tests and expert tuning.
+ * YYG_ERR_NOT_READY for a reduced precision that is not prepared. */
+int yyg_plan_config(yyg_grid *g, int precision, int var_ana, int split_ana, int var_syn);
 
-/* Current launch configuration: info[0..6] = analysis tile variant, its
- * split-K factor, synthesis tile variant, analysis tile rows/cols,
- * synthesis tile rows/cols (first n entries are written). */
-int yyg_plan_info(const yyg_grid *g, int *info, int n);
+/* Current launch configuration of one precision: info[0..6] = analysis
+ * tile variant, its split-K factor, synthesis tile variant, analysis tile
+ * rows/cols, synthesis tile rows/cols (first n entries are written). */
+int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
 
 /* Batched solves of several plans (uneven sizes and lmax allowed) in one
  * persistent launch per phase; see the design notes.  `grids` are borrowed

@@ -64,6 +64,24 @@ struct yyg_grid {
   double *d_rho_owned = nullptr;
   const double *rho = nullptr;
 
+  // reduced-precision tables, index prec - 1 (FP32, BF16x3, FP16x2)
+  struct Lp {
+    bool ready = false;
+    void *Bt = nullptr;  // analysis basis planes [parts][Q][ldb]
+    int *eBt = nullptr;  // row exponents of the analysis basis
+    long ldb = 0;
+    void *Y = nullptr;   // synthesis basis planes [parts][nang][ldy]
+    int *eY = nullptr;
+    long ldy = 0;
+    void *Ar = nullptr;  // density planes [parts][2 n_r][lda], split per solve
+    long lda = 0;
+    void *Ur = nullptr;  // synthesis-operand planes [parts][2 n_r][ldu]
+    long ldu = 0;
+    int var_ana = 0, nsplit = 1, var_syn = 0;
+  } lp[3];
+  int *d_eA = nullptr;  // row exponents of the density (FP16x2)
+  int *d_eU = nullptr;  // row exponents of the synthesis operand (FP16x2)
+
   bool timing = false;
   std::vector<TimedLaunch> launches;
 };
@@ -93,6 +111,13 @@ void free_grid(yyg_grid *g) {
   for (double *b : bufs)
     if (b) (void)hipFree(b);
   if (g->d_qdeg) (void)hipFree(g->d_qdeg);
+  for (auto &l : g->lp) {
+    void *b[] = {l.Bt, l.eBt, l.Y, l.eY, l.Ar, l.Ur};
+    for (void *x : b)
+      if (x) (void)hipFree(x);
+  }
+  if (g->d_eA) (void)hipFree(g->d_eA);
+  if (g->d_eU) (void)hipFree(g->d_eU);
   for (auto &t : g->launches) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -407,7 +432,63 @@ int yyg_prepare(yyg_grid *g, int precision) {
   if (!g) return YYG_ERR_INVALID_ARG;
   if (precision == YYG_FP64) return YYG_OK;
   if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
-  return YYG_ERR_UNSUPPORTED;
+  auto &L = g->lp[precision - 1];
+  if (L.ready) return YYG_OK;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  const int Q = g->Q;
+  const long M = 2L * g->n_r;
+  const int parts = yyg::lp_parts(precision), eb = yyg::lp_elem_bytes(precision), bk = yyg::lp_stage_k(precision);
+  L.ldb = round_up(g->nang, std::max(bk, 16));
+  L.ldy = round_up(2L * Q, std::max(bk, 16));
+  L.lda = L.ldb;
+  L.ldu = L.ldy;
+  const size_t bt_plane = (size_t)Q * L.ldb, y_plane = (size_t)g->nang * L.ldy;
+  int st = YYG_OK;
+  auto bmalloc = [&](void **ptr, size_t bytes) {
+    if (st != YYG_OK) return;
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+      *ptr = nullptr;
+      (void)hipGetLastError();
+      st = YYG_ERR_OUT_OF_MEMORY;
+    }
+  };
+  bmalloc(&L.Bt, bt_plane * parts * eb);
+  bmalloc(reinterpret_cast<void **>(&L.eBt), (size_t)Q * sizeof(int));
+  bmalloc(&L.Y, y_plane * parts * eb);
+  bmalloc(reinterpret_cast<void **>(&L.eY), (size_t)g->nang * sizeof(int));
+  bmalloc(&L.Ar, (size_t)M * L.lda * parts * eb);
+  bmalloc(&L.Ur, (size_t)M * L.ldu * parts * eb);
+  if (!g->d_eA) bmalloc(reinterpret_cast<void **>(&g->d_eA), (size_t)M * sizeof(int));
+  if (!g->d_eU) bmalloc(reinterpret_cast<void **>(&g->d_eU), (size_t)M * sizeof(int));
+  if (st != YYG_OK) return st;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+  };
+  chk(yyg::launch_row_exponent(g->d_Bt, g->ldb, Q, (int)g->nang, L.eBt, 0));
+  chk(yyg::launch_split_rows(precision, g->d_Bt, g->ldb, Q, (int)g->nang, L.eBt, L.Bt, L.ldb, (long)bt_plane, 0));
+  chk(yyg::launch_row_exponent(g->d_Y, g->ldy, (int)g->nang, 2 * Q, L.eY, 0));
+  chk(yyg::launch_split_rows(precision, g->d_Y, g->ldy, (int)g->nang, 2 * Q, L.eY, L.Y, L.ldy, (long)y_plane, 0));
+  chk(hipDeviceSynchronize());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  int bm, bn;
+  yyg::gemm_lp_variant_tile(0, &bm, &bn);
+  L.var_ana = 0;
+  L.var_syn = 0;
+  L.nsplit = yyg::choose_split(((M + bm - 1) / bm) * ((Q + bn - 1) / bn), g->nang);
+  if (L.nsplit > g->part_cap) {
+    double *np = nullptr;
+    if (dmalloc(&np, (size_t)L.nsplit * M * Q) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
+    (void)hipFree(g->d_part);
+    g->d_part = np;
+    g->part_cap = L.nsplit;
+  }
+  L.ready = true;
+  return YYG_OK;
 }
 
 int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stream) {
@@ -434,7 +515,7 @@ int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stre
 int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *stream) {
   if (!g || !phi) return YYG_ERR_INVALID_ARG;
   if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
-  if (precision != YYG_FP64) return YYG_ERR_NOT_READY;
+  if (precision != YYG_FP64 && !g->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
   if (!g->rho) return YYG_ERR_NOT_READY;
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
@@ -447,21 +528,60 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
     if (dmalloc(&tmp, (size_t)M * g->nang) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
     out = tmp;
   }
-  hipError_t e;
-  int t = timing_begin(g, 0, s);
-  e = yyg::launch_gemm_nt_f64(g->var_ana, 0, (int)M, Q, (int)g->nang, g->rho, g->nang, g->d_Bt, g->ldb, g->d_part,
-                              Q, g->nsplit, M * Q, s);
-  timing_end(g, t, s);
+  hipError_t e = hipSuccess;
+  int t;
+  const bool lp = precision != YYG_FP64;
+  const bool scaled = precision == YYG_FP16X2;
+  const int nsplit = lp ? g->lp[precision - 1].nsplit : g->nsplit;
+  if (lp) {
+    // split the density into operand planes (rows scaled for FP16)
+    const auto &L = g->lp[precision - 1];
+    t = timing_begin(g, 3, s);
+    if (scaled) e = yyg::launch_row_exponent(g->rho, g->nang, (int)M, (int)g->nang, g->d_eA, s);
+    if (e == hipSuccess)
+      e = yyg::launch_split_rows(precision, g->rho, g->nang, (int)M, (int)g->nang, scaled ? g->d_eA : nullptr, L.Ar,
+                                 L.lda, M * L.lda, s);
+    timing_end(g, t, s);
+  }
+  if (e == hipSuccess) {
+    t = timing_begin(g, 0, s);
+    if (!lp) {
+      e = yyg::launch_gemm_nt_f64(g->var_ana, 0, (int)M, Q, (int)g->nang, g->rho, g->nang, g->d_Bt, g->ldb,
+                                  g->d_part, Q, nsplit, M * Q, s);
+    } else {
+      const auto &L = g->lp[precision - 1];
+      e = yyg::launch_gemm_nt_lp(precision, L.var_ana, 0, (int)M, Q, (int)g->nang, L.Ar, L.lda, M * L.lda,
+                                 scaled ? g->d_eA : nullptr, L.Bt, L.ldb, (long)Q * L.ldb, L.eBt, g->d_part, Q,
+                                 nsplit, M * Q, s);
+    }
+    timing_end(g, t, s);
+  }
   if (e == hipSuccess) {
     t = timing_begin(g, 1, s);
-    e = yyg::launch_radial_scan(g->d_part, g->nsplit, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, n_r, Q, g->L, -g->G,
+    e = yyg::launch_radial_scan(g->d_part, nsplit, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, n_r, Q, g->L, -g->G,
                                 g->d_U, g->ldy, s);
+    timing_end(g, t, s);
+  }
+  if (e == hipSuccess && lp) {
+    const auto &L = g->lp[precision - 1];
+    t = timing_begin(g, 3, s);
+    if (scaled) e = yyg::launch_row_exponent(g->d_U, g->ldy, (int)M, 2 * Q, g->d_eU, s);
+    if (e == hipSuccess)
+      e = yyg::launch_split_rows(precision, g->d_U, g->ldy, (int)M, 2 * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu,
+                                 M * L.ldu, s);
     timing_end(g, t, s);
   }
   if (e == hipSuccess) {
     t = timing_begin(g, 2, s);
-    e = yyg::launch_gemm_nt_f64(g->var_syn, 1, (int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, out,
-                                g->nang, 1, 0, s);
+    if (!lp) {
+      e = yyg::launch_gemm_nt_f64(g->var_syn, 1, (int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, out,
+                                  g->nang, 1, 0, s);
+    } else {
+      const auto &L = g->lp[precision - 1];
+      e = yyg::launch_gemm_nt_lp(precision, L.var_syn, 1, (int)M, (int)g->nang, 2 * Q, L.Ur, L.ldu, M * L.ldu,
+                                 scaled ? g->d_eU : nullptr, L.Y, L.ldy, (long)g->nang * L.ldy, L.eY, out, g->nang,
+                                 1, 0, s);
+    }
     timing_end(g, t, s);
   }
   if (!phi_is_device) {
@@ -547,25 +667,36 @@ int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots) {
 int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   if (!g) return YYG_ERR_INVALID_ARG;
   if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
-  if (precision != YYG_FP64) return YYG_ERR_NOT_READY;
+  const bool lp = precision != YYG_FP64;
+  if (lp && !g->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   hipStream_t s = as_stream(stream);
   const int Q = g->Q;
   const long M = 2L * g->n_r;
+  int *cur_va = lp ? &g->lp[precision - 1].var_ana : &g->var_ana;
+  int *cur_sp = lp ? &g->lp[precision - 1].nsplit : &g->nsplit;
+  int *cur_vs = lp ? &g->lp[precision - 1].var_syn : &g->var_syn;
+  const int nv = lp ? yyg::gemm_lp_variant_count() : yyg::gemm_f64_variant_count();
+  auto tile = [&](int v, int *bm, int *bn) {
+    if (lp)
+      yyg::gemm_lp_variant_tile(v, bm, bn);
+    else
+      yyg::gemm_f64_variant_tile(v, bm, bn);
+  };
   const char *cache_path = std::getenv("YYG_TUNE_CACHE");
   auto cache = read_tune_cache(cache_path);
   const std::string ka = tune_key(precision, 0, M, Q, g->nang), ks = tune_key(precision, 1, M, g->nang, 2L * Q);
-  int best_va = g->var_ana, best_sp = g->nsplit, best_vs = g->var_syn;
+  int best_va = *cur_va, best_sp = *cur_sp, best_vs = *cur_vs;
   bool have_a = false, have_s = false;
   if (cache.count(ka)) {
     best_va = cache[ka].first;
     best_sp = cache[ka].second;
-    have_a = best_va >= 0 && best_va < yyg::gemm_f64_variant_count() && best_sp >= 1 && best_sp <= 32;
+    have_a = best_va >= 0 && best_va < nv && best_sp >= 1 && best_sp <= 32;
   }
   if (cache.count(ks)) {
     best_vs = cache[ks].first;
-    have_s = best_vs >= 0 && best_vs < yyg::gemm_f64_variant_count();
+    have_s = best_vs >= 0 && best_vs < nv;
   }
   double *tmp_in = nullptr, *tmp_out = nullptr, *tmp_part = nullptr;
   const int smax = 32;
@@ -583,21 +714,47 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     }
   }
   const double *rho = g->rho ? g->rho : tmp_in;
-  const int nv = yyg::gemm_f64_variant_count();
+  const bool scaled = precision == YYG_FP16X2;
+  if (lp && (!have_a || !have_s)) {
+    const auto &L = g->lp[precision - 1];
+    if (scaled) {
+      (void)yyg::launch_row_exponent(rho, g->nang, (int)M, (int)g->nang, g->d_eA, s);
+      (void)yyg::launch_row_exponent(g->d_U, g->ldy, (int)M, 2 * Q, g->d_eU, s);
+    }
+    (void)yyg::launch_split_rows(precision, rho, g->nang, (int)M, (int)g->nang, scaled ? g->d_eA : nullptr, L.Ar,
+                                 L.lda, M * L.lda, s);
+    (void)yyg::launch_split_rows(precision, g->d_U, g->ldy, (int)M, 2 * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu,
+                                 M * L.ldu, s);
+  }
+  auto ana = [&](int v, int sp) -> hipError_t {
+    if (!lp)
+      return yyg::launch_gemm_nt_f64(v, 0, (int)M, Q, (int)g->nang, rho, g->nang, g->d_Bt, g->ldb, tmp_part, Q, sp,
+                                     M * Q, s);
+    const auto &L = g->lp[precision - 1];
+    return yyg::launch_gemm_nt_lp(precision, v, 0, (int)M, Q, (int)g->nang, L.Ar, L.lda, M * L.lda,
+                                  scaled ? g->d_eA : nullptr, L.Bt, L.ldb, (long)Q * L.ldb, L.eBt, tmp_part, Q, sp,
+                                  M * Q, s);
+  };
+  auto syn = [&](int v) -> hipError_t {
+    if (!lp)
+      return yyg::launch_gemm_nt_f64(v, 1, (int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, tmp_out,
+                                     g->nang, 1, 0, s);
+    const auto &L = g->lp[precision - 1];
+    return yyg::launch_gemm_nt_lp(precision, v, 1, (int)M, (int)g->nang, 2 * Q, L.Ur, L.ldu, M * L.ldu,
+                                  scaled ? g->d_eU : nullptr, L.Y, L.ldy, (long)g->nang * L.ldy, L.eY, tmp_out,
+                                  g->nang, 1, 0, s);
+  };
   if (!have_a) {
     double best = 1e30;
     for (int v = 0; v < nv; ++v) {
       int bm, bn;
-      yyg::gemm_f64_variant_tile(v, &bm, &bn);
+      tile(v, &bm, &bn);
       long tiles = ((M + bm - 1) / bm) * ((Q + bn - 1) / bn);
       int base = yyg::choose_split(tiles, g->nang);
       int cands[] = {1, 2, 4, 8, 16, 32, base};
       for (int sp : cands) {
         if (sp > smax || (long)sp * 64 > g->nang + 64) continue;
-        double t = time_launch([&] {
-          return yyg::launch_gemm_nt_f64(v, 0, (int)M, Q, (int)g->nang, rho, g->nang, g->d_Bt, g->ldb, tmp_part, Q,
-                                         sp, M * Q, s);
-        }, s, 3);
+        double t = time_launch([&] { return ana(v, sp); }, s, 3);
         // the scan reads every partial once more: charge it at HBM speed
         t += (double)sp * M * Q * 8.0 / 5.0e9;
         if (t < best) {
@@ -611,10 +768,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   if (!have_s) {
     double best = 1e30;
     for (int v = 0; v < nv; ++v) {
-      double t = time_launch([&] {
-        return yyg::launch_gemm_nt_f64(v, 1, (int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, tmp_out,
-                                       g->nang, 1, 0, s);
-      }, s, 3);
+      double t = time_launch([&] { return syn(v); }, s, 3);
       if (t < best) {
         best = t;
         best_vs = v;
@@ -632,9 +786,9 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     g->d_part = np;
     g->part_cap = best_sp;
   }
-  g->var_ana = best_va;
-  g->nsplit = best_sp;
-  g->var_syn = best_vs;
+  *cur_va = best_va;
+  *cur_sp = best_sp;
+  *cur_vs = best_vs;
   if (cache_path && (!have_a || !have_s)) {
     if (std::FILE *f = std::fopen(cache_path, "a")) {
       if (!have_a) std::fprintf(f, "%s -> %d %d\n", ka.c_str(), best_va, best_sp);
@@ -645,9 +799,11 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   return YYG_OK;
 }
 
-int yyg_plan_config(yyg_grid *g, int var_ana, int split_ana, int var_syn) {
-  if (!g) return YYG_ERR_INVALID_ARG;
-  const int nv = yyg::gemm_f64_variant_count();
+int yyg_plan_config(yyg_grid *g, int precision, int var_ana, int split_ana, int var_syn) {
+  if (!g || precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
+  const bool lp = precision != YYG_FP64;
+  if (lp && !g->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
+  const int nv = lp ? yyg::gemm_lp_variant_count() : yyg::gemm_f64_variant_count();
   if (var_ana < 0 || var_ana >= nv || var_syn < 0 || var_syn >= nv || split_ana < 1 || split_ana > 64)
     return YYG_ERR_INVALID_ARG;
   DeviceGuard dg(g->device);
@@ -661,18 +817,37 @@ int yyg_plan_config(yyg_grid *g, int var_ana, int split_ana, int var_syn) {
     g->d_part = np;
     g->part_cap = split_ana;
   }
-  g->var_ana = var_ana;
-  g->nsplit = split_ana;
-  g->var_syn = var_syn;
+  if (lp) {
+    auto &L = g->lp[precision - 1];
+    L.var_ana = var_ana;
+    L.nsplit = split_ana;
+    L.var_syn = var_syn;
+  } else {
+    g->var_ana = var_ana;
+    g->nsplit = split_ana;
+    g->var_syn = var_syn;
+  }
   return YYG_OK;
 }
 
-int yyg_plan_info(const yyg_grid *g, int *info, int n) {
-  if (!g || !info || n < 1) return YYG_ERR_INVALID_ARG;
+int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n) {
+  if (!g || !info || n < 1 || precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
+  const bool lp = precision != YYG_FP64;
+  int va = g->var_ana, sp = g->nsplit, vs = g->var_syn;
+  if (lp) {
+    va = g->lp[precision - 1].var_ana;
+    sp = g->lp[precision - 1].nsplit;
+    vs = g->lp[precision - 1].var_syn;
+  }
   int ba, bn_a, bs, bn_s;
-  yyg::gemm_f64_variant_tile(g->var_ana, &ba, &bn_a);
-  yyg::gemm_f64_variant_tile(g->var_syn, &bs, &bn_s);
-  const int vals[7] = {g->var_ana, g->nsplit, g->var_syn, ba, bn_a, bs, bn_s};
+  if (lp) {
+    yyg::gemm_lp_variant_tile(va, &ba, &bn_a);
+    yyg::gemm_lp_variant_tile(vs, &bs, &bn_s);
+  } else {
+    yyg::gemm_f64_variant_tile(va, &ba, &bn_a);
+    yyg::gemm_f64_variant_tile(vs, &bs, &bn_s);
+  }
+  const int vals[7] = {va, sp, vs, ba, bn_a, bs, bn_s};
   for (int i = 0; i < n && i < 7; ++i) info[i] = vals[i];
   return YYG_OK;
 }

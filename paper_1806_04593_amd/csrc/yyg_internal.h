@@ -22,6 +22,22 @@ hipError_t launch_expand_analysis_basis(const double *w, const double *Tt, const
 hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, int n_p, int Q, double *Y, long ldy,
                                     hipStream_t s);
 
+// Reduced-precision contractions (prec 1 = FP32, 2 = BF16 x 3, 3 = FP16 x 2):
+// A and B as pre-split planes of the operand type ([rows][ld] each, plane
+// strides apart, k zero-padded to the stage width, rows scaled by 2^-e),
+// FP32 MFMA accumulation flushed to FP64.
+int gemm_lp_variant_count();
+void gemm_lp_variant_tile(int variant, int *bm, int *bn);
+int lp_parts(int prec);
+int lp_elem_bytes(int prec);
+int lp_stage_k(int prec);
+hipError_t launch_gemm_nt_lp(int prec, int variant, int role, int M, int N, int K, const void *A, long lda,
+                             long a_plane, const int *eA, const void *B, long ldb, long b_plane, const int *eB,
+                             double *C, long ldc, int nsplit, long c_split_stride, hipStream_t s);
+hipError_t launch_row_exponent(const double *X, long ldx, int rows, int ncols, int *e, hipStream_t s);
+hipError_t launch_split_rows(int prec, const double *X, long ldx, int rows, int ncols, const int *e, void *P,
+                             long ldp, long plane_stride, hipStream_t s);
+
 // Split-K factor for an output of `tiles` block tiles and K columns.
 int choose_split(long tiles, long K);
 

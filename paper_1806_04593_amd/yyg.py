@@ -55,6 +55,10 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1806_04593_amd.build`")
+        # PyTorch ships its own HIP runtime under the same soname; loading it
+        # first makes libyyg bind to that copy, so the process has a single
+        # HIP runtime (two copies cannot share the device, streams or memory).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i, d, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)
         L.yyg_grid_create.argtypes = [ctypes.POINTER(GridDesc), i, ctypes.POINTER(vp)]
@@ -73,8 +77,8 @@ def lib():
         L.yyg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.yyg_batch_destroy.argtypes = [vp]
         L.yyg_autotune.argtypes = [vp, i, vp]
-        L.yyg_plan_info.argtypes = [vp, ctypes.POINTER(i), i]
-        L.yyg_plan_config.argtypes = [vp, i, i, i]
+        L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
+        L.yyg_plan_config.argtypes = [vp, i, i, i, i]
         L.yyg_status_string.argtypes = [i]
         L.yyg_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -184,14 +188,15 @@ class Grid:
         _check(lib().yyg_autotune(self._h, PRECISIONS.get(precision, precision), _stream_handle(stream)),
                "yyg_autotune")
 
-    def plan_info(self):
+    def plan_info(self, precision="fp64"):
         info = (ctypes.c_int * 7)()
-        _check(lib().yyg_plan_info(self._h, info, 7), "yyg_plan_info")
+        _check(lib().yyg_plan_info(self._h, PRECISIONS.get(precision, precision), info, 7), "yyg_plan_info")
         keys = ("var_ana", "split_ana", "var_syn", "bm_ana", "bn_ana", "bm_syn", "bn_syn")
         return dict(zip(keys, list(info)))
 
-    def set_config(self, var_ana, split_ana, var_syn):
-        _check(lib().yyg_plan_config(self._h, int(var_ana), int(split_ana), int(var_syn)), "yyg_plan_config")
+    def set_config(self, var_ana, split_ana, var_syn, precision="fp64"):
+        _check(lib().yyg_plan_config(self._h, PRECISIONS.get(precision, precision), int(var_ana), int(split_ana),
+                                     int(var_syn)), "yyg_plan_config")
 
     def moments(self):
         out = np.zeros((2, self.n_r, self.Q))

@@ -31,6 +31,19 @@ def test_library_exports_every_declared_symbol():
     assert sorted(yyg.EXPORTS) == names
 
 
+def test_single_hip_runtime_in_process():
+    """Loading the library through the binding leaves exactly one HIP runtime
+    mapped (the one PyTorch uses)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1806_04593_amd import yyg; yyg.lib()\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len(set(l.split()[-1] for l in maps if 'libamdhip64' in l)))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True)
+    assert out.stdout.strip().splitlines()[-1] == "1"
+
+
 def test_status_strings():
     lib = yyg.lib()
     for s in (0, -1, -2, -3, -4, -5, -6, 7):
