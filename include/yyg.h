@@ -186,11 +186,36 @@ int yyg_plan_config(yyg_grid *g, int precision, int var_ana, int split_ana, int 
  * rows/cols, synthesis tile rows/cols (first n entries are written). */
 int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
 
-/* Batched solves of several plans (uneven sizes and lmax allowed) in one
- * persistent launch per phase; see the design notes.  `grids` are borrowed
- * and must outlive the batch; all must be on one device.  d_rho[f], d_phi[f]
- * are device arrays of field f in the layout above. */
+/* Batched solves of several plans (uneven n_r <= 1024, angular sizes and
+ * lmax allowed) for fields that each have their own density and potential
+ * arrays.  One batched solve is three persistent grouped launches (five
+ * with the reduced-precision operand splits): all fields' analysis tiles,
+ * then all radial scans, then all synthesis tiles, each launch's blocks
+ * walking a device work list.  The launches, together with the copy of the
+ * per-field arguments, are recorded once into a HIP graph and replayed.
+ * `grids` are borrowed and must outlive the batch; all on one device; for
+ * a reduced precision every plan must be prepared for it.  The batch uses
+ * the plans' work buffers, so a plan must not be solved on its own while a
+ * batched solve that includes it is in flight. */
 int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out);
+
+/* Choose the tile variant of each grouped contraction by timing them on the
+ * batch (blocks until done).  Needs one earlier yyg_batch_solve (the timed
+ * launches reuse its densities and rewrite its potentials with the same
+ * values); YYG_ERR_NOT_READY otherwise.  The next solve records a new graph. */
+int yyg_batch_autotune(yyg_batch *b, void *stream);
+
+/* info[0..5] = fields, precision, analysis variant, synthesis variant,
+ * analysis work items, synthesis work items. */
+int yyg_batch_info(const yyg_batch *b, int *info, int n);
+
+/* Solve every field: d_rho[f] / d_phi[f] are device arrays of field f in
+ * the layout above (host arrays of n pointers).  Asynchronous on `stream`;
+ * with the default (NULL) stream the graph runs on a blocking stream of the
+ * batch, which the default stream orders against.
+ * The first call on a stream records the graph; later calls replay it.
+ * Passing pointers different from the previous call waits for that call
+ * to finish before the argument arrays are rewritten. */
 int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_phi, void *stream);
 int yyg_batch_destroy(yyg_batch *b);
 

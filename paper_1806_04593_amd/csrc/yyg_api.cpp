@@ -227,6 +227,263 @@ std::map<std::string, std::pair<int, int>> read_tune_cache(const char *path) {
 
 }  // namespace
 
+
+struct yyg_batch {
+  int device = 0;
+  int precision = 0;
+  std::vector<yyg_grid *> grids;
+  std::vector<const double *> rho;
+  std::vector<double *> phi;
+  // per-field argument arrays: pinned host copies (pointer-patched per
+  // solve) and their device mirrors, refreshed by a copy at the head of
+  // the recorded graph
+  yyg::GemmF64Args *h_f64[2] = {nullptr, nullptr}, *d_f64[2] = {nullptr, nullptr};
+  yyg::GemmLpArgs *h_lp[2] = {nullptr, nullptr}, *d_lp[2] = {nullptr, nullptr};
+  yyg::ScanArgs *d_scan = nullptr;
+  yyg::SplitArgs *h_split[2] = {nullptr, nullptr}, *d_split[2] = {nullptr, nullptr};
+  int4 *d_items[2] = {nullptr, nullptr};  // analysis / synthesis work items
+  int n_items[2] = {0, 0};
+  int var[2] = {0, 0};                    // tile variants
+  int blocks[2] = {0, 0};                 // resident persistent blocks
+  int4 *d_scan_items = nullptr;
+  int n_scan_items = 0;
+  int2 *d_split_items[2] = {nullptr, nullptr};
+  int n_split_items[2] = {0, 0};
+  int cus = 256;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t exec_stream = nullptr;
+  hipEvent_t done = nullptr;
+  hipStream_t stream = nullptr;  // used when the caller passes the default stream
+  bool launched = false;
+};
+
+namespace {
+
+void batch_drop_graph(yyg_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->exec_stream = nullptr;
+}
+
+void batch_free(yyg_batch *b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  for (int r = 0; r < 2; ++r) {
+    if (b->h_f64[r]) (void)hipHostFree(b->h_f64[r]);
+    if (b->h_lp[r]) (void)hipHostFree(b->h_lp[r]);
+    if (b->h_split[r]) (void)hipHostFree(b->h_split[r]);
+    void *d[] = {b->d_f64[r], b->d_lp[r], b->d_split[r], b->d_items[r], b->d_split_items[r]};
+    for (void *x : d)
+      if (x) (void)hipFree(x);
+  }
+  if (b->d_scan) (void)hipFree(b->d_scan);
+  if (b->d_scan_items) (void)hipFree(b->d_scan_items);
+  if (b->done) (void)hipEventDestroy(b->done);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+template <class T>
+int upload(T **dst, const std::vector<T> &src) {
+  if (*dst) (void)hipFree(*dst);
+  *dst = nullptr;
+  if (src.empty()) return YYG_OK;
+  if (hipMalloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T)) != hipSuccess) {
+    *dst = nullptr;
+    (void)hipGetLastError();
+    return YYG_ERR_OUT_OF_MEMORY;
+  }
+  if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  return YYG_OK;
+}
+
+// Work items of one contraction phase for tile variant v, largest K first
+// so the persistent blocks finish together.
+int batch_set_items(yyg_batch *b, int role, int v) {
+  const bool lp = b->precision != YYG_FP64;
+  int bm, bn;
+  if (lp)
+    yyg::gemm_lp_variant_tile(v, &bm, &bn);
+  else
+    yyg::gemm_f64_variant_tile(v, &bm, &bn);
+  std::vector<std::pair<long, int4>> work;
+  const int n = (int)b->grids.size();
+  for (int f = 0; f < n; ++f) {
+    const yyg_grid *g = b->grids[f];
+    const long M = 2L * g->n_r, N = role == 0 ? g->Q : g->nang, K = role == 0 ? g->nang : 2L * g->Q;
+    const int tm = (int)((M + bm - 1) / bm), tn = (int)((N + bn - 1) / bn);
+    if (lp) {
+      b->h_lp[role][f].tiles_m = tm;
+    } else {
+      b->h_f64[role][f].tiles_m = tm;
+    }
+    for (int j = 0; j < tn; ++j)
+      for (int i = 0; i < tm; ++i) work.push_back({K, int4{f, i, j, 0}});
+  }
+  std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+  std::vector<int4> items(work.size());
+  for (size_t i = 0; i < work.size(); ++i) items[i] = work[i].second;
+  int st = upload(&b->d_items[role], items);
+  if (st != YYG_OK) return st;
+  b->n_items[role] = (int)items.size();
+  b->var[role] = v;
+  // resident blocks: LDS-limited occupancy of the variant, four at most
+  const int eb = lp ? yyg::lp_elem_bytes(b->precision) : 8;
+  const int parts = lp ? yyg::lp_parts(b->precision) : 1;
+  const int bk = lp ? yyg::lp_stage_k(b->precision) : 16;
+  const long lds = 2L * parts * (bm + bn) * (bk + 16 / eb) * eb;
+  int per_cu = (int)std::max(1L, std::min(4L, 160L * 1024 / std::max(1L, lds)));
+  b->blocks[role] = std::max(1, std::min(b->n_items[role], b->cus * per_cu));
+  // the per-problem tiles_m lives in the argument arrays
+  if (lp) {
+    std::vector<yyg::GemmLpArgs> h(b->h_lp[role], b->h_lp[role] + n);
+    if (hipMemcpy(b->d_lp[role], h.data(), n * sizeof(yyg::GemmLpArgs), hipMemcpyHostToDevice) != hipSuccess)
+      return YYG_ERR_DEVICE;
+  } else {
+    std::vector<yyg::GemmF64Args> h(b->h_f64[role], b->h_f64[role] + n);
+    if (hipMemcpy(b->d_f64[role], h.data(), n * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice) != hipSuccess)
+      return YYG_ERR_DEVICE;
+  }
+  return YYG_OK;
+}
+
+hipError_t batch_launch_gemm(yyg_batch *b, int role, hipStream_t s) {
+  if (b->precision == YYG_FP64)
+    return yyg::launch_gemm_f64_grouped(b->var[role], role, b->d_f64[role], b->d_items[role], b->n_items[role],
+                                        b->blocks[role], s);
+  return yyg::launch_gemm_lp_grouped(b->precision, b->var[role], role, b->d_lp[role], b->d_items[role],
+                                     b->n_items[role], b->blocks[role], s);
+}
+
+// Write the current density / potential pointers into the pinned argument
+// arrays (their device mirrors are refreshed by the graph's first nodes).
+void batch_patch_pointers(yyg_batch *b) {
+  const int n = (int)b->grids.size();
+  for (int f = 0; f < n; ++f) {
+    if (b->precision == YYG_FP64) {
+      b->h_f64[0][f].A = b->rho[f];
+      b->h_f64[1][f].C = b->phi[f];
+    } else {
+      b->h_split[0][f].X = b->rho[f];
+      b->h_lp[1][f].C = b->phi[f];
+    }
+  }
+}
+
+// Enqueue the whole batched solve on s (recorded into the graph).
+hipError_t batch_enqueue(yyg_batch *b, hipStream_t s) {
+  const int n = (int)b->grids.size();
+  hipError_t e = hipSuccess;
+  const bool lp = b->precision != YYG_FP64;
+  if (!lp) {
+    e = hipMemcpyAsync(b->d_f64[0], b->h_f64[0], n * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->d_f64[1], b->h_f64[1], n * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice, s);
+  } else {
+    e = hipMemcpyAsync(b->d_split[0], b->h_split[0], n * sizeof(yyg::SplitArgs), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->d_lp[1], b->h_lp[1], n * sizeof(yyg::GemmLpArgs), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = yyg::launch_split_rows_grouped(b->precision, b->d_split[0], b->d_split_items[0], b->n_split_items[0],
+                                         std::min(b->n_split_items[0], b->cus * 8), s);
+  }
+  if (e == hipSuccess) e = batch_launch_gemm(b, 0, s);
+  if (e == hipSuccess)
+    e = yyg::launch_radial_scan_grouped(b->d_scan, b->d_scan_items, b->n_scan_items,
+                                        std::min(b->n_scan_items, b->cus * 2), s);
+  if (e == hipSuccess && lp)
+    e = yyg::launch_split_rows_grouped(b->precision, b->d_split[1], b->d_split_items[1], b->n_split_items[1],
+                                       std::min(b->n_split_items[1], b->cus * 8), s);
+  if (e == hipSuccess) e = batch_launch_gemm(b, 1, s);
+  return e;
+}
+
+int batch_build(yyg_batch *b) {
+  const int n = (int)b->grids.size();
+  const bool lp = b->precision != YYG_FP64;
+  const bool scaled = b->precision == YYG_FP16X2;
+  b->rho.assign(n, nullptr);
+  b->phi.assign(n, nullptr);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
+    b->cus = cus;
+  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) return YYG_ERR_DEVICE;
+  if (hipStreamCreate(&b->stream) != hipSuccess) return YYG_ERR_DEVICE;
+  for (int r = 0; r < 2; ++r) {
+    if (lp) {
+      if (hipHostMalloc(reinterpret_cast<void **>(&b->h_lp[r]), n * sizeof(yyg::GemmLpArgs), 0) != hipSuccess ||
+          hipHostMalloc(reinterpret_cast<void **>(&b->h_split[r]), n * sizeof(yyg::SplitArgs), 0) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void **>(&b->d_lp[r]), n * sizeof(yyg::GemmLpArgs)) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void **>(&b->d_split[r]), n * sizeof(yyg::SplitArgs)) != hipSuccess) {
+        (void)hipGetLastError();
+        return YYG_ERR_OUT_OF_MEMORY;
+      }
+    } else {
+      if (hipHostMalloc(reinterpret_cast<void **>(&b->h_f64[r]), n * sizeof(yyg::GemmF64Args), 0) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void **>(&b->d_f64[r]), n * sizeof(yyg::GemmF64Args)) != hipSuccess) {
+        (void)hipGetLastError();
+        return YYG_ERR_OUT_OF_MEMORY;
+      }
+    }
+  }
+  std::vector<yyg::ScanArgs> scan(n);
+  std::vector<int4> scan_items;
+  std::vector<int2> split_items[2];
+  for (int f = 0; f < n; ++f) {
+    yyg_grid *g = b->grids[f];
+    const int Q = g->Q;
+    const long M = 2L * g->n_r;
+    if (!lp) {
+      yyg::GemmF64Args &a = b->h_f64[0][f];
+      a = yyg::GemmF64Args{(int)M, Q, (int)g->nang, nullptr, g->nang, g->d_Bt, g->ldb, g->d_part, Q, 0,
+                           (int)(((g->nang + 15) / 16) * 16), 1};
+      yyg::GemmF64Args &c = b->h_f64[1][f];
+      c = yyg::GemmF64Args{(int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, nullptr, g->nang, 0,
+                           (int)(((2 * Q + 15) / 16) * 16), 1};
+    } else {
+      auto &L = g->lp[b->precision - 1];
+      const int bk = yyg::lp_stage_k(b->precision);
+      b->h_split[0][f] = yyg::SplitArgs{nullptr, g->nang, (int)g->nang, scaled ? g->d_eA : nullptr, L.Ar, L.lda,
+                                        M * L.lda};
+      b->h_split[1][f] = yyg::SplitArgs{g->d_U, g->ldy, 2 * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu, M * L.ldu};
+      b->h_lp[0][f] = yyg::GemmLpArgs{(int)M, Q, (int)g->nang, L.Ar, L.lda, M * L.lda, scaled ? g->d_eA : nullptr,
+                                      L.Bt, L.ldb, (long)Q * L.ldb, L.eBt, g->d_part, Q, 0,
+                                      (int)((g->nang + bk - 1) / bk * bk), 1};
+      b->h_lp[1][f] = yyg::GemmLpArgs{(int)M, (int)g->nang, 2 * Q, L.Ur, L.ldu, M * L.ldu,
+                                      scaled ? g->d_eU : nullptr, L.Y, L.ldy, (long)g->nang * L.ldy, L.eY, nullptr,
+                                      g->nang, 0, (int)((2 * Q + bk - 1) / bk * bk), 1};
+      for (long r = 0; r < M; ++r) {
+        split_items[0].push_back(int2{f, (int)r});
+        split_items[1].push_back(int2{f, (int)r});
+      }
+    }
+    scan[f] = yyg::ScanArgs{g->d_part, 1, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, g->n_r, Q, g->L, -g->G, g->d_U,
+                            g->ldy};
+    for (int p = 0; p < 2; ++p)
+      for (int cb = 0; cb < (Q + 15) / 16; ++cb) scan_items.push_back(int4{f, cb, p, 0});
+  }
+  int st = upload(&b->d_scan, scan);
+  if (st == YYG_OK) st = upload(&b->d_scan_items, scan_items);
+  b->n_scan_items = (int)scan_items.size();
+  if (lp) {
+    for (int r = 0; r < 2 && st == YYG_OK; ++r) {
+      st = upload(&b->d_split_items[r], split_items[r]);
+      b->n_split_items[r] = (int)split_items[r].size();
+      if (st == YYG_OK &&
+          hipMemcpy(b->d_split[r], b->h_split[r], n * sizeof(yyg::SplitArgs), hipMemcpyHostToDevice) != hipSuccess)
+        st = YYG_ERR_DEVICE;
+    }
+  }
+  // default tile variant 64 x 64 (index 3 of the FP64 list, 0 of the others)
+  for (int role = 0; role < 2 && st == YYG_OK; ++role) st = batch_set_items(b, role, lp ? 0 : 3);
+  return st;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *yyg_status_string(int status) {
@@ -853,24 +1110,139 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n) {
 }
 
 int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out) {
-  (void)grids;
-  (void)n;
-  (void)precision;
-  if (out) *out = nullptr;
-  return YYG_ERR_UNSUPPORTED;
+  if (!out) return YYG_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!grids || n < 1 || precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
+  for (int f = 0; f < n; ++f) {
+    if (!grids[f] || grids[f]->device != grids[0]->device) return YYG_ERR_INVALID_ARG;
+    if (grids[f]->n_r > 1024) return YYG_ERR_UNSUPPORTED;
+    if (precision != YYG_FP64 && !grids[f]->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
+  }
+  yyg_batch *b = new (std::nothrow) yyg_batch;
+  if (!b) return YYG_ERR_OUT_OF_MEMORY;
+  b->device = grids[0]->device;
+  b->precision = precision;
+  b->grids.assign(grids, grids + n);
+  DeviceGuard dg(b->device);
+  if (!dg.ok) {
+    delete b;
+    return YYG_ERR_DEVICE;
+  }
+  int st = batch_build(b);
+  if (st != YYG_OK) {
+    batch_free(b);
+    return st;
+  }
+  *out = b;
+  return YYG_OK;
+}
+
+int yyg_batch_autotune(yyg_batch *b, void *stream) {
+  if (!b) return YYG_ERR_INVALID_ARG;
+  // the timed launches read the densities and write the potentials of the
+  // last batched solve
+  if (!b->launched) return YYG_ERR_NOT_READY;
+  DeviceGuard dg(b->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  hipStream_t s = as_stream(stream);
+  if (hipStreamSynchronize(b->stream) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  const bool lp = b->precision != YYG_FP64;
+  const int nv = lp ? yyg::gemm_lp_variant_count() : yyg::gemm_f64_variant_count();
+  // time each phase's contraction per tile variant on the batch's own
+  // problems (density pointers of the last solve, or whatever the plans
+  // hold: timings do not depend on the values)
+  int best[2] = {b->var[0], b->var[1]};
+  for (int role = 0; role < 2; ++role) {
+    double bt = 1e30;
+    for (int v = 0; v < nv; ++v) {
+      int st = batch_set_items(b, role, v);
+      if (st != YYG_OK) return st;
+      double t = time_launch([&] { return batch_launch_gemm(b, role, s); }, s, 3);
+      if (t < bt) {
+        bt = t;
+        best[role] = v;
+      }
+    }
+  }
+  for (int role = 0; role < 2; ++role) {
+    int st = batch_set_items(b, role, best[role]);
+    if (st != YYG_OK) return st;
+  }
+  batch_drop_graph(b);
+  return YYG_OK;
+}
+
+int yyg_batch_info(const yyg_batch *b, int *info, int n) {
+  if (!b || !info || n < 1) return YYG_ERR_INVALID_ARG;
+  const int vals[6] = {(int)b->grids.size(), b->precision, b->var[0], b->var[1], b->n_items[0], b->n_items[1]};
+  for (int i = 0; i < n && i < 6; ++i) info[i] = vals[i];
+  return YYG_OK;
 }
 
 int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_phi, void *stream) {
-  (void)b;
-  (void)d_rho;
-  (void)d_phi;
-  (void)stream;
-  return YYG_ERR_UNSUPPORTED;
+  if (!b || !d_rho || !d_phi) return YYG_ERR_INVALID_ARG;
+  const int n = (int)b->grids.size();
+  for (int f = 0; f < n; ++f)
+    if (!d_rho[f] || !d_phi[f]) return YYG_ERR_INVALID_ARG;
+  DeviceGuard dg(b->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  // a graph cannot be recorded on the legacy default stream: use the
+  // batch's own blocking stream, which that stream orders against
+  hipStream_t s = stream ? as_stream(stream) : b->stream;
+  bool changed = false;
+  for (int f = 0; f < n; ++f)
+    if (b->rho[f] != d_rho[f] || b->phi[f] != d_phi[f]) changed = true;
+  if (changed) {
+    // the previous launch may still read the staged arguments
+    if (b->launched && hipEventSynchronize(b->done) != hipSuccess) {
+      (void)hipGetLastError();
+      return YYG_ERR_DEVICE;
+    }
+    for (int f = 0; f < n; ++f) {
+      b->rho[f] = d_rho[f];
+      b->phi[f] = d_phi[f];
+    }
+    batch_patch_pointers(b);
+  }
+  hipError_t e = hipSuccess;
+  if (!b->exec || b->exec_stream != s) {
+    batch_drop_graph(b);
+    // record the whole batched solve once, replay it afterwards
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e2 = batch_enqueue(b, s);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(s, &graph);
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e == hipSuccess) b->exec_stream = s;
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      batch_drop_graph(b);
+      return YYG_ERR_DEVICE;
+    }
+  }
+  e = hipGraphLaunch(b->exec, s);
+  if (e == hipSuccess) e = hipEventRecord(b->done, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  b->launched = true;
+  return YYG_OK;
 }
 
 int yyg_batch_destroy(yyg_batch *b) {
-  (void)b;
-  return YYG_ERR_UNSUPPORTED;
+  if (!b) return YYG_ERR_INVALID_ARG;
+  DeviceGuard dg(b->device);
+  (void)hipDeviceSynchronize();
+  batch_free(b);
+  return YYG_OK;
 }
 
 }  // extern "C"

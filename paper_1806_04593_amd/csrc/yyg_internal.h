@@ -5,12 +5,50 @@
 
 namespace yyg {
 
+// Arguments of one FP64 NT GEMM problem (grouped launches read an array).
+struct GemmF64Args {
+  int M, N, K;
+  const double *A;
+  long lda;
+  const double *B;
+  long ldb;
+  double *C;
+  long ldc;
+  long c_split_stride;
+  int k_per_split;  // multiple of the stage width (16)
+  int tiles_m;
+};
+
 // FP64 NT GEMM C = A . B^T in one of several tile shapes ("variants");
 // role 0 = analysis, 1 = synthesis (separate kernel symbols).
 int gemm_f64_variant_count();
 void gemm_f64_variant_tile(int variant, int *bm, int *bn);
 hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const double *A, long lda, const double *B,
                               long ldb, double *C, long ldc, int nsplit, long c_split_stride, hipStream_t s);
+
+// Persistent grouped FP64 GEMM: n_blocks blocks walk `items` = (problem,
+// tm, tn, split) over the problems' tiles of the variant's shape.
+hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *probs, const int4 *items, int n_items,
+                                  int n_blocks, hipStream_t s);
+
+// Arguments of one radial scan (see launch_radial_scan).
+struct ScanArgs {
+  const double *part;
+  int nsplit;
+  long split_stride;
+  double *Ahat;
+  const double *coef;
+  const int *qdeg;
+  int nR, Q, L;
+  double negG;
+  double *U;
+  long ldu;
+};
+
+// Grouped scan over several plans (each n_r <= 1024): items = (problem,
+// 16-column block, patch); blocks of 16 x 64 threads.
+hipError_t launch_radial_scan_grouped(const ScanArgs *probs, const int4 *items, int n_items, int n_blocks,
+                                      hipStream_t s);
 
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
                               const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu,
@@ -26,6 +64,20 @@ hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, 
 // A and B as pre-split planes of the operand type ([rows][ld] each, plane
 // strides apart, k zero-padded to the stage width, rows scaled by 2^-e),
 // FP32 MFMA accumulation flushed to FP64.
+struct GemmLpArgs {
+  int M, N, K;
+  const void *A;  // planes [parts][M][lda], a_plane elements apart
+  long lda, a_plane;
+  const int *eA;  // row exponents of A (nullable)
+  const void *B;  // planes [parts][N][ldb]
+  long ldb, b_plane;
+  const int *eB;
+  double *C;
+  long ldc, c_split_stride;
+  int k_per_split;  // multiple of the stage width
+  int tiles_m;
+};
+
 int gemm_lp_variant_count();
 void gemm_lp_variant_tile(int variant, int *bm, int *bn);
 int lp_parts(int prec);
@@ -34,7 +86,23 @@ int lp_stage_k(int prec);
 hipError_t launch_gemm_nt_lp(int prec, int variant, int role, int M, int N, int K, const void *A, long lda,
                              long a_plane, const int *eA, const void *B, long ldb, long b_plane, const int *eB,
                              double *C, long ldc, int nsplit, long c_split_stride, hipStream_t s);
+hipError_t launch_gemm_lp_grouped(int prec, int variant, int role, const GemmLpArgs *probs, const int4 *items,
+                                 int n_items, int n_blocks, hipStream_t s);
 hipError_t launch_row_exponent(const double *X, long ldx, int rows, int ncols, int *e, hipStream_t s);
+
+// Grouped row split over several matrices: items = (problem, row).  With
+// `e` non-null the row's power-of-two exponent is computed first (and
+// stored), otherwise rows are not scaled.
+struct SplitArgs {
+  const double *X;
+  long ldx;
+  int ncols;
+  int *e;
+  void *P;
+  long ldp, plane;
+};
+hipError_t launch_split_rows_grouped(int prec, const SplitArgs *probs, const int2 *items, int n_items, int n_blocks,
+                                     hipStream_t s);
 hipError_t launch_split_rows(int prec, const double *X, long ldx, int rows, int ncols, const int *e, void *P,
                              long ldp, long plane_stride, hipStream_t s);
 

@@ -35,13 +35,15 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 
 }  // namespace
 
-// ROLE only separates the analysis (0) and synthesis (1) instantiations so
-// that profilers list them apart.  Block tile BM x BN, WGM x WGN waves, each
-// wave a (BM/WGM) x (BN/WGN) grid of 16 x 16 MFMA tiles.
-template <int ROLE, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(
-    int M, int N, int K, const double *__restrict__ A, long lda, const double *__restrict__ B, long ldb,
-    double *__restrict__ C, long ldc, long c_split_stride, int k_per_split, int tiles_m, int tiles_total) {
+// Block tile BM x BN, WGM x WGN waves, each wave a (BM/WGM) x (BN/WGN) grid
+// of 16 x 16 MFMA tiles; computes output tile (tm, tn) over split z.
+template <int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int tn, int z) {
+  const int M = g.M, N = g.N, K = g.K;
+  const double *__restrict__ A = g.A;
+  const double *__restrict__ B = g.B;
+  double *__restrict__ C = g.C;
+  const long lda = g.lda, ldb = g.ldb, ldc = g.ldc;
   constexpr int NT = 64 * WGM * WGN;
   constexpr int TI = BM / WGM / 16, TJ = BN / WGN / 16;
   constexpr int EA = BM * kBK / NT, EB = BN * kBK / NT;  // doubles per thread per stage
@@ -50,13 +52,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(
   __shared__ double Bs[2][BN * kLDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tile = xcd_tile(blockIdx.x, tiles_total);
-  const int tm = tile % tiles_m, tn = tile / tiles_m;
   const int m0 = tm * BM, n0 = tn * BN;
-  const int z = blockIdx.y;
-  const int kbeg = z * k_per_split;
-  const int kend = min(K, kbeg + k_per_split);
-  C += (long)z * c_split_stride;
+  const int kbeg = z * g.k_per_split;
+  const int kend = min(K, kbeg + g.k_per_split);
+  C += (long)z * g.c_split_stride;
 
   const int wm = wave % WGM, wn = wave / WGM;
   const int arow = tid / (kBK / EA), acol = (tid % (kBK / EA)) * EA;
@@ -148,6 +147,26 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(
   }
 }
 
+// ROLE only separates the analysis (0) and synthesis (1) instantiations so
+// that profilers list them apart.
+template <int ROLE, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(GemmF64Args g, int tiles_total) {
+  const int tile = xcd_tile(blockIdx.x, tiles_total);
+  gemm_f64_tile<BM, BN, WGM, WGN>(g, tile % g.tiles_m, tile / g.tiles_m, blockIdx.y);
+}
+
+// Persistent grouped form: blocks walk a list of (problem, tm, tn, split)
+// work items over several independent contractions of one phase.
+template <int ROLE, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_grouped(const GemmF64Args *__restrict__ probs,
+                                                                      const int4 *__restrict__ items, int n_items) {
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const int4 it = items[w];
+    __syncthreads();  // the previous item's LDS reads are done
+    gemm_f64_tile<BM, BN, WGM, WGN>(probs[it.x], it.y, it.z, it.w);
+  }
+}
+
 // Radial sums of Eqs. (19)-(20) for every (patch, column), with the split-K
 // partial moments reduced first (fixed order over the splits).
 //   I_n = alpha_n I_(n-1) + beta_n A_n            (I_(-1) = 0)
@@ -236,14 +255,20 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
 // register/LDS work.  Same recurrences, outputs and reduction order as the
 // loop form.
 template <int CMAX>
-__global__ __launch_bounds__(1024) void radial_scan_kernel(
-    const double *__restrict__ part, int nsplit, long split_stride, double *__restrict__ Ahat,
-    const double *__restrict__ coef, const int *__restrict__ qdeg, int nR, int Q, int L, double negG,
-    double *__restrict__ U, long ldu) {
+__device__ __forceinline__ void radial_scan_block(const ScanArgs &sa, int colblock, int p) {
+  const double *__restrict__ part = sa.part;
+  const int nsplit = sa.nsplit;
+  const long split_stride = sa.split_stride;
+  double *__restrict__ Ahat = sa.Ahat;
+  const double *__restrict__ coef = sa.coef;
+  const int *__restrict__ qdeg = sa.qdeg;
+  const int nR = sa.nR, Q = sa.Q, L = sa.L;
+  const double negG = sa.negG;
+  double *__restrict__ U = sa.U;
+  const long ldu = sa.ldu;
   __shared__ double sI[64][16], sPa[64][16], sO[64][16], sPg[64][16];
   const int x = threadIdx.x, y = threadIdx.y;
-  const int q = blockIdx.x * 16 + x;
-  const int p = blockIdx.y;
+  const int q = colblock * 16 + x;
   const bool ok = q < Q;
   const int qq = ok ? q : 0;
   const int l = qdeg[qq];
@@ -322,6 +347,21 @@ __global__ __launch_bounds__(1024) void radial_scan_kernel(
   }
 }
 
+template <int CMAX>
+__global__ __launch_bounds__(1024) void radial_scan_kernel(ScanArgs sa) {
+  radial_scan_block<CMAX>(sa, blockIdx.x, blockIdx.y);
+}
+
+// Grouped form over several plans: items = (problem, column block, patch).
+__global__ __launch_bounds__(1024) void radial_scan_grouped(const ScanArgs *__restrict__ probs,
+                                                            const int4 *__restrict__ items, int n_items) {
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const int4 it = items[w];
+    __syncthreads();  // LDS summaries of the previous item are consumed
+    radial_scan_block<16>(probs[it.x], it.y, it.z);
+  }
+}
+
 // Bt[q][a] = w[a] Tbar[j][q] CS[k][q], a = j*n_p + k (analysis basis,
 // Eqs. 26-27 with sqrt(N^(lm)) folded in); zero in the padding columns.
 __global__ void expand_analysis_basis_kernel(const double *__restrict__ w, const double *__restrict__ Tt,
@@ -362,34 +402,57 @@ namespace {
 template <int BM, int BN, int WGM, int WGN>
 hipError_t launch_gemm_variant(int role, int M, int N, int K, const double *A, long lda, const double *B, long ldb,
                                double *C, long ldc, int nsplit, long c_split_stride, hipStream_t s) {
-  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  GemmF64Args g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.C = C;
+  g.ldc = ldc;
+  g.c_split_stride = c_split_stride;
+  g.tiles_m = (M + BM - 1) / BM;
+  const int tiles_n = (N + BN - 1) / BN;
   int kps = (K + nsplit - 1) / nsplit;
-  kps = ((kps + kBK - 1) / kBK) * kBK;
-  dim3 grid(tiles_m * tiles_n, nsplit), block(64 * WGM * WGN);
+  g.k_per_split = ((kps + kBK - 1) / kBK) * kBK;
+  dim3 grid(g.tiles_m * tiles_n, nsplit), block(64 * WGM * WGN);
   if (role == 0)
-    hipLaunchKernelGGL((gemm_nt_f64_kernel<0, BM, BN, WGM, WGN>), grid, block, 0, s, M, N, K, A, lda, B, ldb, C, ldc,
-                       c_split_stride, kps, tiles_m, tiles_m * tiles_n);
+    hipLaunchKernelGGL((gemm_nt_f64_kernel<0, BM, BN, WGM, WGN>), grid, block, 0, s, g, g.tiles_m * tiles_n);
   else
-    hipLaunchKernelGGL((gemm_nt_f64_kernel<1, BM, BN, WGM, WGN>), grid, block, 0, s, M, N, K, A, lda, B, ldb, C, ldc,
-                       c_split_stride, kps, tiles_m, tiles_m * tiles_n);
+    hipLaunchKernelGGL((gemm_nt_f64_kernel<1, BM, BN, WGM, WGN>), grid, block, 0, s, g, g.tiles_m * tiles_n);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int WGM, int WGN>
+hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4 *items, int n_items, int n_blocks,
+                                  hipStream_t s) {
+  dim3 grid(n_blocks), block(64 * WGM * WGN);
+  if (role == 0)
+    hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN>), grid, block, 0, s, probs, items, n_items);
+  else
+    hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN>), grid, block, 0, s, probs, items, n_items);
   return hipGetLastError();
 }
 
 typedef hipError_t (*gemm_f64_fn)(int, int, int, int, const double *, long, const double *, long, double *, long, int,
                                   long, hipStream_t);
 
+typedef hipError_t (*grouped_f64_fn)(int, const GemmF64Args *, const int4 *, int, int, hipStream_t);
+
 struct F64Variant {
-  int bm, bn;
+  int bm, bn, threads;
   gemm_f64_fn fn;
+  grouped_f64_fn grouped;
 };
 
+#define YYG_F64_VARIANT(BM, BN, WM, WN) \
+  { BM, BN, 64 * WM * WN, launch_gemm_variant<BM, BN, WM, WN>, launch_grouped_variant<BM, BN, WM, WN> }
+
 const F64Variant kF64Variants[] = {
-    {128, 128, launch_gemm_variant<128, 128, 2, 2>},
-    {64, 128, launch_gemm_variant<64, 128, 2, 2>},
-    {128, 64, launch_gemm_variant<128, 64, 2, 2>},
-    {64, 64, launch_gemm_variant<64, 64, 2, 2>},
-    {256, 128, launch_gemm_variant<256, 128, 4, 2>},
-    {128, 256, launch_gemm_variant<128, 256, 2, 4>},
+    YYG_F64_VARIANT(128, 128, 2, 2), YYG_F64_VARIANT(64, 128, 2, 2),  YYG_F64_VARIANT(128, 64, 2, 2),
+    YYG_F64_VARIANT(64, 64, 2, 2),   YYG_F64_VARIANT(256, 128, 4, 2), YYG_F64_VARIANT(128, 256, 2, 4),
 };
 
 }  // namespace
@@ -399,6 +462,13 @@ int gemm_f64_variant_count() { return (int)(sizeof(kF64Variants) / sizeof(kF64Va
 void gemm_f64_variant_tile(int v, int *bm, int *bn) {
   *bm = kF64Variants[v].bm;
   *bn = kF64Variants[v].bn;
+}
+
+hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *probs, const int4 *items, int n_items,
+                                  int n_blocks, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (variant < 0 || variant >= gemm_f64_variant_count()) return hipErrorInvalidValue;
+  return kF64Variants[variant].grouped(role, probs, items, n_items, n_blocks, s);
 }
 
 hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const double *A, long lda, const double *B,
@@ -411,12 +481,11 @@ hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const 
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
                               const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu,
                               hipStream_t s) {
+  ScanArgs sa{part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu};
   if (nR <= 64 * 4) {
-    hipLaunchKernelGGL(radial_scan_kernel<4>, dim3((Q + 15) / 16, 2), dim3(16, 64), 0, s, part, nsplit, split_stride,
-                       Ahat, coef, qdeg, nR, Q, L, negG, U, ldu);
+    hipLaunchKernelGGL(radial_scan_kernel<4>, dim3((Q + 15) / 16, 2), dim3(16, 64), 0, s, sa);
   } else if (nR <= 64 * 16) {
-    hipLaunchKernelGGL(radial_scan_kernel<16>, dim3((Q + 15) / 16, 2), dim3(16, 64), 0, s, part, nsplit,
-                       split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu);
+    hipLaunchKernelGGL(radial_scan_kernel<16>, dim3((Q + 15) / 16, 2), dim3(16, 64), 0, s, sa);
   } else {
     int nw = 16;
     while (nw > 1 && nR / nw < 8) nw >>= 1;
@@ -424,6 +493,13 @@ hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride,
     hipLaunchKernelGGL(radial_scan_loop_kernel, grid, block, 0, s, part, nsplit, split_stride, Ahat, coef, qdeg, nR,
                        Q, L, negG, U, ldu);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_radial_scan_grouped(const ScanArgs *probs, const int4 *items, int n_items, int n_blocks,
+                                      hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(radial_scan_grouped, dim3(n_blocks), dim3(16, 64), 0, s, probs, items, n_items);
   return hipGetLastError();
 }
 

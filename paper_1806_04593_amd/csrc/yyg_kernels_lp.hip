@@ -73,12 +73,16 @@ __device__ __forceinline__ f32x4 mfma_lp(const typename LpTraits<PREC>::T *a, co
 // is [M][lda], of B [N][ldb], plane_stride elements apart, zero-padded to a
 // multiple of the stage width in k (so a stage never needs a k bound).  Rows
 // carry power-of-two exponents eA / eB (nullable) undone in the epilogue.
-template <int ROLE, int PREC, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_lp_kernel(
-    int M, int N, int K, const typename LpTraits<PREC>::T *__restrict__ A, long lda, long a_plane,
-    const int *__restrict__ eA, const typename LpTraits<PREC>::T *__restrict__ B, long ldb, long b_plane,
-    const int *__restrict__ eB, double *__restrict__ C, long ldc, long c_split_stride, int k_per_split, int tiles_m,
-    int tiles_total) {
+template <int PREC, int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gemm_lp_tile(const GemmLpArgs &g, int tm, int tn, int z) {
+  typedef typename LpTraits<PREC>::T Te;
+  const int M = g.M, N = g.N, K = g.K;
+  const Te *__restrict__ A = static_cast<const Te *>(g.A);
+  const Te *__restrict__ B = static_cast<const Te *>(g.B);
+  const int *__restrict__ eA = g.eA;
+  const int *__restrict__ eB = g.eB;
+  double *__restrict__ C = g.C;
+  const long lda = g.lda, ldb = g.ldb, ldc = g.ldc, a_plane = g.a_plane, b_plane = g.b_plane;
   typedef typename LpTraits<PREC>::T T;
   typedef uint4 V;                                     // 16-byte chunk
   constexpr int NP = LpTraits<PREC>::NP, BK = LpTraits<PREC>::BK, LDK = BK + LpTraits<PREC>::PAD;
@@ -93,13 +97,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_lp_kernel(
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tile = xcd_tile_lp(blockIdx.x, tiles_total);
-  const int tm = tile % tiles_m, tn = tile / tiles_m;
   const int m0 = tm * BM, n0 = tn * BN;
-  const int z = blockIdx.y;
-  const int kbeg = z * k_per_split;
-  const int kend = min(K, kbeg + k_per_split);
-  C += (long)z * c_split_stride;
+  const int kbeg = z * g.k_per_split;
+  const int kend = min(K, kbeg + g.k_per_split);
+  C += (long)z * g.c_split_stride;
   const int wm = wave % WGM, wn = wave / WGM;
 
   f32x4 facc[TI][TJ];
@@ -218,6 +219,22 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_lp_kernel(
   }
 }
 
+template <int ROLE, int PREC, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_lp_kernel(GemmLpArgs g, int tiles_total) {
+  const int tile = xcd_tile_lp(blockIdx.x, tiles_total);
+  gemm_lp_tile<PREC, BM, BN, WGM, WGN>(g, tile % g.tiles_m, tile / g.tiles_m, blockIdx.y);
+}
+
+template <int ROLE, int PREC, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_lp_grouped(const GemmLpArgs *__restrict__ probs,
+                                                                     const int4 *__restrict__ items, int n_items) {
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const int4 it = items[w];
+    __syncthreads();  // the previous item's LDS reads are done
+    gemm_lp_tile<PREC, BM, BN, WGM, WGN>(probs[it.x], it.y, it.z, it.w);
+  }
+}
+
 namespace {
 
 template <>
@@ -287,43 +304,109 @@ __global__ void split_rows_kernel(const double *__restrict__ X, long ldx, int nc
   for (int p = 0; p < NP; ++p) P[p * plane_stride + row * ldp + c] = parts[p];
 }
 
+// Grouped row split: one block per (problem, row) item; optionally the row's
+// exponent first (max-reduction in LDS), then the planes.
+template <int PREC>
+__global__ __launch_bounds__(256) void split_rows_grouped_kernel(const SplitArgs *__restrict__ probs,
+                                                                 const int2 *__restrict__ items, int n_items) {
+  typedef typename LpTraits<PREC>::T T;
+  constexpr int NP = LpTraits<PREC>::NP;
+  __shared__ double red[256];
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const int2 it = items[w];
+    const SplitArgs a = probs[it.x];
+    const long row = it.y;
+    const double *x = a.X + row * a.ldx;
+    int ex = 0;
+    if (a.e) {
+      double m = 0.0;
+      for (int c = threadIdx.x; c < a.ncols; c += blockDim.x) m = fmax(m, fabs(x[c]));
+      __syncthreads();  // previous item's reads of red[] are done
+      red[threadIdx.x] = m;
+      __syncthreads();
+      for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+      }
+      if (red[0] > 0.0) frexp(red[0], &ex);
+      if (threadIdx.x == 0) a.e[row] = ex;
+    }
+    T *P = static_cast<T *>(a.P);
+    for (long c = threadIdx.x; c < a.ldp; c += blockDim.x) {
+      const double v = (c < a.ncols) ? ldexp(x[c], -ex) : 0.0;
+      T parts[NP];
+      split_parts<T, NP>(v, parts);
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp) P[pp * a.plane + row * a.ldp + c] = parts[pp];
+    }
+  }
+}
+
 namespace {
 
 template <int PREC, int BM, int BN, int WGM, int WGN>
 hipError_t launch_lp_variant(int role, int M, int N, int K, const void *A, long lda, long a_plane, const int *eA,
                              const void *B, long ldb, long b_plane, const int *eB, double *C, long ldc, int nsplit,
                              long c_split_stride, hipStream_t s) {
-  typedef typename LpTraits<PREC>::T T;
   constexpr int BK = LpTraits<PREC>::BK;
-  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  GemmLpArgs g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.lda = lda;
+  g.a_plane = a_plane;
+  g.eA = eA;
+  g.B = B;
+  g.ldb = ldb;
+  g.b_plane = b_plane;
+  g.eB = eB;
+  g.C = C;
+  g.ldc = ldc;
+  g.c_split_stride = c_split_stride;
+  g.tiles_m = (M + BM - 1) / BM;
+  const int tiles_n = (N + BN - 1) / BN;
   int kps = (K + nsplit - 1) / nsplit;
-  kps = ((kps + BK - 1) / BK) * BK;
-  dim3 grid(tiles_m * tiles_n, nsplit), block(64 * WGM * WGN);
-  const T *a = static_cast<const T *>(A);
-  const T *b = static_cast<const T *>(B);
+  g.k_per_split = ((kps + BK - 1) / BK) * BK;
+  dim3 grid(g.tiles_m * tiles_n, nsplit), block(64 * WGM * WGN);
   if (role == 0)
-    hipLaunchKernelGGL((gemm_nt_lp_kernel<0, PREC, BM, BN, WGM, WGN>), grid, block, 0, s, M, N, K, a, lda, a_plane,
-                       eA, b, ldb, b_plane, eB, C, ldc, c_split_stride, kps, tiles_m, tiles_m * tiles_n);
+    hipLaunchKernelGGL((gemm_nt_lp_kernel<0, PREC, BM, BN, WGM, WGN>), grid, block, 0, s, g, g.tiles_m * tiles_n);
   else
-    hipLaunchKernelGGL((gemm_nt_lp_kernel<1, PREC, BM, BN, WGM, WGN>), grid, block, 0, s, M, N, K, a, lda, a_plane,
-                       eA, b, ldb, b_plane, eB, C, ldc, c_split_stride, kps, tiles_m, tiles_m * tiles_n);
+    hipLaunchKernelGGL((gemm_nt_lp_kernel<1, PREC, BM, BN, WGM, WGN>), grid, block, 0, s, g, g.tiles_m * tiles_n);
+  return hipGetLastError();
+}
+
+template <int PREC, int BM, int BN, int WGM, int WGN>
+hipError_t launch_lp_grouped(int role, const GemmLpArgs *probs, const int4 *items, int n_items, int n_blocks,
+                             hipStream_t s) {
+  dim3 grid(n_blocks), block(64 * WGM * WGN);
+  if (role == 0)
+    hipLaunchKernelGGL((gemm_nt_lp_grouped<0, PREC, BM, BN, WGM, WGN>), grid, block, 0, s, probs, items, n_items);
+  else
+    hipLaunchKernelGGL((gemm_nt_lp_grouped<1, PREC, BM, BN, WGM, WGN>), grid, block, 0, s, probs, items, n_items);
   return hipGetLastError();
 }
 
 typedef hipError_t (*gemm_lp_fn)(int, int, int, int, const void *, long, long, const int *, const void *, long,
                                  long, const int *, double *, long, int, long, hipStream_t);
 
+typedef hipError_t (*grouped_lp_fn)(int, const GemmLpArgs *, const int4 *, int, int, hipStream_t);
+
 struct LpVariant {
-  int bm, bn;
+  int bm, bn, threads;
   gemm_lp_fn fn[3];  // FP32, BF16x3, FP16x2
+  grouped_lp_fn grouped[3];
 };
 
-#define YYG_LP_VARIANT(BM, BN, WM, WN)                                                                   \
-  {                                                                                                      \
-    BM, BN, {                                                                                            \
-      launch_lp_variant<1, BM, BN, WM, WN>, launch_lp_variant<2, BM, BN, WM, WN>,                        \
-          launch_lp_variant<3, BM, BN, WM, WN>                                                           \
-    }                                                                                                    \
+#define YYG_LP_VARIANT(BM, BN, WM, WN)                                                                         \
+  {                                                                                                            \
+    BM, BN, 64 * WM * WN,                                                                                      \
+        {launch_lp_variant<1, BM, BN, WM, WN>, launch_lp_variant<2, BM, BN, WM, WN>,                           \
+         launch_lp_variant<3, BM, BN, WM, WN>},                                                                \
+    {                                                                                                          \
+      launch_lp_grouped<1, BM, BN, WM, WN>, launch_lp_grouped<2, BM, BN, WM, WN>,                              \
+          launch_lp_grouped<3, BM, BN, WM, WN>                                                                 \
+    }                                                                                                          \
   }
 
 const LpVariant kLpVariants[] = {
@@ -356,9 +439,35 @@ hipError_t launch_gemm_nt_lp(int prec, int variant, int role, int M, int N, int 
                                            c_split_stride, s);
 }
 
+hipError_t launch_gemm_lp_grouped(int prec, int variant, int role, const GemmLpArgs *probs, const int4 *items,
+                                 int n_items, int n_blocks, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (prec < 1 || prec > 3 || variant < 0 || variant >= gemm_lp_variant_count()) return hipErrorInvalidValue;
+  return kLpVariants[variant].grouped[prec - 1](role, probs, items, n_items, n_blocks, s);
+}
+
 hipError_t launch_row_exponent(const double *X, long ldx, int rows, int ncols, int *e, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(row_exponent_kernel, dim3(rows), dim3(256), 0, s, X, ldx, ncols, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_rows_grouped(int prec, const SplitArgs *probs, const int2 *items, int n_items, int n_blocks,
+                                     hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (prec) {
+    case 1:
+      hipLaunchKernelGGL(split_rows_grouped_kernel<1>, dim3(n_blocks), dim3(256), 0, s, probs, items, n_items);
+      break;
+    case 2:
+      hipLaunchKernelGGL(split_rows_grouped_kernel<2>, dim3(n_blocks), dim3(256), 0, s, probs, items, n_items);
+      break;
+    case 3:
+      hipLaunchKernelGGL(split_rows_grouped_kernel<3>, dim3(n_blocks), dim3(256), 0, s, probs, items, n_items);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ EXPORTS = [
     "yyg_upload_rho", "yyg_solve", "yyg_get_moments", "yyg_get_weights",
     "yyg_grid_destroy", "yyg_host_table", "yyg_set_timing", "yyg_get_timing",
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
-    "yyg_autotune", "yyg_plan_info", "yyg_plan_config",
+    "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
 ]
 
 
@@ -76,6 +76,8 @@ def lib():
         L.yyg_batch_create.argtypes = [ctypes.POINTER(vp), i, i, ctypes.POINTER(vp)]
         L.yyg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.yyg_batch_destroy.argtypes = [vp]
+        L.yyg_batch_autotune.argtypes = [vp, vp]
+        L.yyg_batch_info.argtypes = [vp, ctypes.POINTER(i), i]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -231,3 +233,47 @@ class Grid:
 
 def grid_from_workload(desc, device=0):
     return Grid(desc, device)
+
+
+class Batch:
+    """Batched solves of several plans (yyg_batch_*)."""
+
+    def __init__(self, grids, precision="fp64"):
+        self.grids = list(grids)
+        arr = (ctypes.c_void_p * len(self.grids))(*[g.handle.value for g in self.grids])
+        h = ctypes.c_void_p()
+        _check(lib().yyg_batch_create(arr, len(self.grids), PRECISIONS.get(precision, precision), ctypes.byref(h)),
+               "yyg_batch_create")
+        self._h = h
+        self.precision = precision
+
+    def solve(self, rhos, phis, stream=None):
+        """rhos, phis: lists of torch CUDA float64 tensors, one per field."""
+        n = len(self.grids)
+        assert len(rhos) == n and len(phis) == n
+        for g, r, p in zip(self.grids, rhos, phis):
+            assert tuple(r.shape) == g.shape and tuple(p.shape) == g.shape
+            assert r.is_contiguous() and p.is_contiguous()
+        self._keep = (list(rhos), list(phis))
+        ra = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+        pa = (ctypes.c_void_p * n)(*[p.data_ptr() for p in phis])
+        _check(lib().yyg_batch_solve(self._h, ra, pa, _stream_handle(stream)), "yyg_batch_solve")
+
+    def autotune(self, stream=None):
+        _check(lib().yyg_batch_autotune(self._h, _stream_handle(stream)), "yyg_batch_autotune")
+
+    def info(self):
+        info = (ctypes.c_int * 6)()
+        _check(lib().yyg_batch_info(self._h, info, 6), "yyg_batch_info")
+        return dict(zip(("fields", "precision", "var_ana", "var_syn", "items_ana", "items_syn"), list(info)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yyg_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
