@@ -1,11 +1,14 @@
 """Throughput of the full Yin-Yang potential solve on one MI355X.
 
 One step = one full solve (angular analysis, radial scans, synthesis on both
-patches) of a synthetic, device-resident density; the plan (tables) is built
-before timing.  Prints one JSON line.
+patches, plus the operand splits of the reduced precisions) of a synthetic,
+device-resident density; plans and autotuning happen before timing.  Prints
+one JSON line: the headline precision's cells/s as `value`, every
+precision's rate and error against the FP64 oracle under `precisions`.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sn_core]
-                    [--precision fp64] [--no-cpu-baseline]
+                    [--precision fp64] [--no-cpu-baseline] [--no-check]
+    python bench.py --workload batch64      # 64 uneven fields, batched vs sequential
 """
 
 import argparse
@@ -19,10 +22,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp16x2": 2500.0}   # dense MFMA TFLOP/s
-# MFMA products executed per algorithmic multiply-add (operand-split terms)
-PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "fp16x2": 3}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "fp16x2": 3}   # MFMA products per algorithmic multiply-add
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "fp16x2": "f16x2"}
-KERNEL_SRC = os.path.join(ROOT, "paper_1806_04593_amd", "csrc", "yyg_kernels.hip")
+ALL_PRECISIONS = ("fp64", "fp32", "bf16x3", "fp16x2")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1806_04593_amd", "csrc", f) for f in ("yyg_kernels.hip", "yyg_kernels_lp.hip")]
+METRIC = "grid cells/sec per full Phi solve, FP64 vs split-precision, at stated max rel. error"
 
 
 def log(msg):
@@ -30,14 +34,17 @@ def log(msg):
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, n_launch_units):
+def measured_traffic(workload, precision):
     """HBM bytes per launch of the synthesis kernel from committed rocprofv3
-    --pmc counters (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated), or
-    None when absent or taken on a different kernel source."""
+    --pmc counters (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated), or None
+    when absent or taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -53,9 +60,9 @@ def measured_traffic(workload, precision, n_launch_units):
 
 
 def cpu_baseline(desc, rho, budget_s=20.0):
-    """Oracle (as it stands) on the host: full moments and radial sums, then
-    synthesis of a bounded number of (patch, shell) rows, extrapolated to the
-    full grid.  Returns the cells/s figure and what was sampled."""
+    """The oracle as it stands, on the host: full moments and radial sums,
+    then synthesis of as many (patch, shell) rows as fit in `budget_s`,
+    extrapolated to the full grid."""
     import numpy as np
     import oracle as O
     try:
@@ -63,21 +70,19 @@ def cpu_baseline(desc, rho, budget_s=20.0):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    args = (desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"],
-            desc["lmax"], desc["G"])
-    th, ph = O.patch_edges(*args[1:5])
-    tables = (th, ph, O.overlap_weights(th, ph, args[3], args[4]), O.theta_integrals(th, args[5]),
-              *O.phi_integrals(ph, args[5]))
+    th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+    w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
+    T = O.theta_integrals(th, desc["lmax"])
+    C, S = O.phi_integrals(ph, desc["lmax"])
     nR = len(desc["r_edges"]) - 1
     nang = desc["n_theta"] * desc["n_phi"]
     c0, t0 = time.process_time(), time.perf_counter()
-    AC, AS = O.moments(rho, tables[2], tables[3], tables[4], tables[5])
+    AC, AS = O.moments(rho, w, T, C, S)
     UC, US = O.radial_sums(AC, AS, desc["r_edges"])
     t_front = time.perf_counter() - t0
-    tc = 0.5 * (th[:-1] + th[1:])
-    pc = 0.5 * (ph[:-1] + ph[1:])
-    T, P = np.meshgrid(tc, pc, indexing="ij")
-    tt, pp = T.ravel(), P.ravel()
+    tc, pc = 0.5 * (th[:-1] + th[1:]), 0.5 * (ph[:-1] + ph[1:])
+    TT, PP = np.meshgrid(tc, pc, indexing="ij")
+    tt, pp = TT.ravel(), PP.ravel()
     rows = 0
     t1 = time.perf_counter()
     rng = np.random.default_rng(0)
@@ -91,11 +96,213 @@ def cpu_baseline(desc, rho, budget_s=20.0):
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     est = t_front + t_rows / rows * (2 * nR)
-    cells = 2 * nR * nang
-    return {"value": cells / est, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"full moments + radial sums, synthesis of {rows} of {2 * nR} (patch, shell) rows; "
-                       f"full-solve time extrapolated to {est:.1f} s"),
+    return {"value": 2 * nR * nang / est, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"{desc['name']}: full moments + radial sums, synthesis of {rows} of {2 * nR} "
+                       f"(patch, shell) rows; full-solve time extrapolated to {est:.1f} s"),
             "measured_s": round(wall, 2), "effective_cores": round(cpu / wall, 2)}
+
+
+def sampled_error(desc, rho, phi_host, k=400, seed=123):
+    import numpy as np
+    import oracle as O
+    nR = len(desc["r_edges"]) - 1
+    rng = np.random.default_rng(seed)
+    s = np.stack([rng.integers(0, 2, k), rng.integers(0, nR, k),
+                  rng.integers(0, desc["n_theta"], k), rng.integers(0, desc["n_phi"], k)], 1)
+    ref = O.solve_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
+                          desc["delta_phi"], desc["lmax"], desc["G"], rho, s)
+    got = phi_host[s[:, 0], s[:, 1], s[:, 2], s[:, 3]]
+    return float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+
+def bench_single(a):
+    import torch
+
+    from paper_1806_04593_amd import workloads as W
+    from paper_1806_04593_amd import yyg
+
+    desc = W.describe(a.workload)
+    nR = len(desc["r_edges"]) - 1
+    Q = (desc["lmax"] + 1) ** 2
+    nang = desc["n_theta"] * desc["n_phi"]
+    cells = 2 * nR * nang
+    M = 2 * nR
+    log(f"[bench] workload {a.workload}: n_r={nR} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']}")
+    rho = W.density(desc)
+    t0 = time.perf_counter()
+    g = yyg.Grid(desc, 0)
+    plan_s = time.perf_counter() - t0
+    log(f"[bench] plan built in {plan_s:.2f} s")
+    d_rho = torch.from_numpy(rho).to("cuda:0")
+    d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
+    g.upload_rho(d_rho)
+    precisions = [a.precision] + [p for p in ALL_PRECISIONS if p != a.precision and not a.only]
+    results = {}
+    for prec in precisions:
+        t0 = time.perf_counter()
+        g.prepare(prec)
+        if not a.no_autotune:
+            g.autotune(prec)
+        tune_s = time.perf_counter() - t0
+        info = g.plan_info(prec)
+        for _ in range(a.warmup):
+            g.solve(d_phi, prec)
+        torch.cuda.synchronize()
+        g.set_timing(True)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(a.steps):
+            g.solve(d_phi, prec)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / a.steps
+        kms, kcnt = g.timing()
+        g.set_timing(False)
+        avg = [float(kms[i] / max(1, kcnt[i])) for i in range(4)]
+        err = None if a.no_check else sampled_error(desc, rho, d_phi.cpu().numpy())
+        flops_syn = 2.0 * M * nang * (2 * Q)
+        achieved = flops_syn / (avg[2] * 1e-3) / 1e12
+        results[prec] = {"cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
+                         "kernels_ms": {"analysis": avg[0], "radial_scan": avg[1], "synthesis": avg[2],
+                                        "operand_split": avg[3]},
+                         "synthesis_tflops": achieved, "launch": info, "prepare_tune_s": round(tune_s, 2)}
+        log(f"[bench] {prec}: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, kernels {avg}")
+    for prec, r in results.items():
+        r["speedup_vs_fp64"] = results["fp64"]["ms_per_step"] / r["ms_per_step"] if "fp64" in results else None
+
+    head = results[a.precision]
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(desc, rho)
+        log(f"[bench] oracle {cpu['value']:.3e} cells/s")
+    achieved = head["synthesis_tflops"]
+    peak = PEAK[a.precision]
+    out = {
+        "metric": METRIC,
+        "value": head["cells_per_s"],
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[a.precision],
+        "data": "synthetic",
+        "config": {"workload": a.workload, "n_r": nR, "n_theta": desc["n_theta"], "n_phi": desc["n_phi"],
+                   "lmax": desc["lmax"], "cells": cells, "precision": a.precision,
+                   "max_rel_err_vs_oracle": head["max_rel_err_vs_oracle"], "plan_build_s": round(plan_s, 3),
+                   "launch": head["launch"]},
+        "roofline": {"bound": "mfma",
+                     "kernel": ("gemm_nt_f64_kernel<1,...> (synthesis)" if a.precision == "fp64"
+                                else f"gemm_nt_lp_kernel<1,{a.precision},...> (synthesis)"),
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(a.workload, a.precision),
+                     "executed_products_per_mac": PRODUCTS[a.precision],
+                     "executed_frac": achieved * PRODUCTS[a.precision] / peak},
+        "kernels_ms": head["kernels_ms"],
+        "precisions": results,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(a):
+    import numpy as np
+    import torch
+
+    from paper_1806_04593_amd import workloads as W
+    from paper_1806_04593_amd import yyg
+
+    descs = W.batch_descs(64)
+    cells = sum(2 * (len(d["r_edges"]) - 1) * d["n_theta"] * d["n_phi"] for d in descs)
+    flops_syn = sum(2.0 * 2 * (len(d["r_edges"]) - 1) * d["n_theta"] * d["n_phi"] * 2 * (d["lmax"] + 1) ** 2
+                    for d in descs)
+    log(f"[bench] batch64: {len(descs)} fields, {cells} cells")
+    rhos = [W.density(d) for d in descs]
+    t0 = time.perf_counter()
+    grids = [yyg.Grid(d, 0) for d in descs]
+    plan_s = time.perf_counter() - t0
+    log(f"[bench] 64 plans built in {plan_s:.1f} s")
+    d_rho = [torch.from_numpy(r).to("cuda:0") for r in rhos]
+    d_phi = [torch.empty(g.shape, dtype=torch.float64, device="cuda:0") for g in grids]
+    stream = torch.cuda.Stream()
+
+    # 64 sequential FP64 solves (each plan autotuned on its own shape)
+    for g, r in zip(grids, d_rho):
+        g.upload_rho(r)
+        if not a.no_autotune:
+            g.autotune("fp64")
+    torch.cuda.synchronize()
+
+    def seq():
+        for g, p in zip(grids, d_phi):
+            g.solve(p, "fp64", stream=stream)
+    for _ in range(a.warmup):
+        seq()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(a.steps):
+        seq()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = start.elapsed_time(stop) / a.steps
+    log(f"[bench] sequential FP64: {seq_ms:.3f} ms per 64 solves")
+
+    results = {}
+    precisions = [a.precision] + [p for p in ALL_PRECISIONS if p != a.precision and not a.only]
+    for prec in precisions:
+        for g in grids:
+            g.prepare(prec)
+        b = yyg.Batch(grids, prec)
+        b.solve(d_rho, d_phi, stream=stream)
+        stream.synchronize()
+        if not a.no_autotune:
+            b.autotune(stream=stream)
+        for _ in range(a.warmup):
+            b.solve(d_rho, d_phi, stream=stream)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(a.steps):
+            b.solve(d_rho, d_phi, stream=stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / a.steps
+        prof = np.mean([b.profile(stream=stream) for _ in range(3)], axis=0)
+        errs = []
+        if not a.no_check:
+            for i in (0, 21, 42, 63):
+                errs.append(sampled_error(descs[i], rhos[i], d_phi[i].cpu().numpy(), k=100, seed=i))
+        results[prec] = {"cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms,
+                         "speedup_vs_sequential_fp64": seq_ms / ms,
+                         "max_rel_err_vs_oracle": max(errs) if errs else None,
+                         "kernels_ms": {"analysis": prof[0], "radial_scan": prof[1], "synthesis": prof[2],
+                                        "operand_split": prof[3]},
+                         "synthesis_tflops": flops_syn / (prof[2] * 1e-3) / 1e12, "batch": b.info()}
+        log(f"[bench] batched {prec}: {ms:.3f} ms ({seq_ms / ms:.2f}x sequential FP64), phases {prof}, errs {errs}")
+        b.close()
+    head = results[a.precision]
+    achieved = head["synthesis_tflops"]
+    out = {
+        "metric": METRIC, "value": head["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[a.precision], "data": "synthetic",
+        "config": {"workload": "batch64", "fields": len(descs), "cells": cells, "precision": a.precision,
+                   "sequential_fp64_ms": seq_ms, "sequential_fp64_cells_per_s": cells / (seq_ms * 1e-3),
+                   "max_rel_err_vs_oracle": head["max_rel_err_vs_oracle"], "plan_build_s": round(plan_s, 2)},
+        "roofline": {"bound": "mfma", "kernel": f"gemm grouped synthesis ({a.precision})", "achieved": achieved,
+                     "peak": PEAK[a.precision], "unit": "TFLOP/s", "frac": achieved / PEAK[a.precision],
+                     "traffic": None, "executed_products_per_mac": PRODUCTS[a.precision],
+                     "executed_frac": achieved * PRODUCTS[a.precision] / PEAK[a.precision]},
+        "precisions": results,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -104,118 +311,20 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sn_core")
-    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--precision", default="fp64", choices=ALL_PRECISIONS)
+    ap.add_argument("--only", action="store_true", help="measure the headline precision only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {a.gpus} requested); the solver holds the whole grid "
-              "on one device and has no multi-GPU path.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (--gpus {a.gpus} requested): the solver holds the whole grid on "
+              "one device and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    from paper_1806_04593_amd import workloads as W
-    from paper_1806_04593_amd import yyg
-
-    desc = W.describe(a.workload)
-    nR = len(desc["r_edges"]) - 1
-    log(f"[bench] workload {a.workload}: n_r={nR} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']} "
-        f"precision={a.precision}")
-    rho = W.density(desc)
-    log("[bench] density generated")
-    t0 = time.perf_counter()
-    g = yyg.Grid(desc, 0)
-    if a.precision != "fp64":
-        g.prepare(a.precision)
-    plan_s = time.perf_counter() - t0
-    log(f"[bench] plan built in {plan_s:.2f} s")
-    tune_s = 0.0
-    if not a.no_autotune:
-        t0 = time.perf_counter()
-        g.autotune(a.precision)
-        tune_s = time.perf_counter() - t0
-    info = g.plan_info(a.precision)
-    log(f"[bench] launch configuration {info} (autotune {tune_s:.2f} s)")
-    d_rho = torch.from_numpy(rho).to("cuda:0")
-    d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
-    g.upload_rho(d_rho)
-    for _ in range(a.warmup):
-        g.solve(d_phi, a.precision)
-    torch.cuda.synchronize()
-    log("[bench] warmup done")
-
-    g.set_timing(True)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(a.steps):
-        g.solve(d_phi, a.precision)
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / a.steps
-    kms, kcnt = g.timing()
-    g.set_timing(False)
-    log(f"[bench] timed {a.steps} steps: {ms:.4f} ms/step")
-
-    Q = (desc["lmax"] + 1) ** 2
-    nang = desc["n_theta"] * desc["n_phi"]
-    cells = 2 * nR * nang
-    M = 2 * nR
-    flops_syn = 2.0 * M * nang * (2 * Q)
-    flops_ana = 2.0 * M * nang * Q
-    avg = [kms[i] / max(1, kcnt[i]) for i in range(4)]
-    achieved = flops_syn / (avg[2] * 1e-3) / 1e12
-    peak = PEAK[a.precision]
-    traffic = measured_traffic(a.workload, a.precision, 1)
-
-    err = None
-    if not a.no_check:
-        import oracle as O
-        rng = np.random.default_rng(123)
-        s = np.stack([rng.integers(0, 2, 400), rng.integers(0, nR, 400),
-                      rng.integers(0, desc["n_theta"], 400), rng.integers(0, desc["n_phi"], 400)], 1)
-        ref = O.solve_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
-                              desc["delta_phi"], desc["lmax"], desc["G"], rho, s)
-        got = d_phi.cpu().numpy()[s[:, 0], s[:, 1], s[:, 2], s[:, 3]]
-        err = float(np.max(np.abs(got - ref) / np.abs(ref)))
-        log(f"[bench] max rel err vs oracle over 400 sampled cells: {err:.3e}")
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(desc, rho)
-        log(f"[bench] oracle {cpu['value']:.3e} cells/s")
-
-    out = {
-        "metric": "grid cells/sec per full Phi solve, FP64 vs split-precision, at stated max rel. error",
-        "value": cells / (ms * 1e-3),
-        "unit": "cells/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": DTYPE[a.precision],
-        "data": "synthetic",
-        "config": {"workload": a.workload, "n_r": nR, "n_theta": desc["n_theta"], "n_phi": desc["n_phi"],
-                   "lmax": desc["lmax"], "cells": cells, "precision": a.precision,
-                   "max_rel_err_vs_oracle": err, "plan_build_s": round(plan_s, 3),
-                   "autotune_s": round(tune_s, 3), "launch": info},
-        "roofline": {"bound": "mfma", "kernel": ("gemm_nt_f64_kernel<1,...> (synthesis)" if a.precision == "fp64"
-                                                 else f"gemm_nt_lp_kernel<1,...> (synthesis, {a.precision})"),
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic,
-                     "executed_products_per_mac": PRODUCTS[a.precision],
-                     "executed_frac": achieved * PRODUCTS[a.precision] / peak},
-        "kernels_ms": {"analysis": avg[0], "radial_scan": avg[1], "synthesis": avg[2], "convert": avg[3]},
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    if a.workload == "batch64":
+        bench_batch(a)
+    else:
+        bench_single(a)
 
 
 if __name__ == "__main__":

@@ -217,6 +217,13 @@ int yyg_batch_info(const yyg_batch *b, int *info, int n);
  * Passing pointers different from the previous call waits for that call
  * to finish before the argument arrays are rewritten. */
 int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_phi, void *stream);
+
+/* Run the launches of the last batched solve once more, eagerly (not from
+ * the graph), with HIP events between the phases on `stream`; blocks and
+ * writes the milliseconds of ms[0] analysis, ms[1] radial scans, ms[2]
+ * synthesis, ms[3] operand splits (first n entries).  Needs one earlier
+ * yyg_batch_solve. */
+int yyg_batch_profile(yyg_batch *b, void *stream, double *ms, int n);
 int yyg_batch_destroy(yyg_batch *b);
 
 /* Static string naming a status code. */

@@ -1237,6 +1237,61 @@ int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_p
   return YYG_OK;
 }
 
+int yyg_batch_profile(yyg_batch *b, void *stream, double *ms, int n) {
+  if (!b || !ms || n < 1) return YYG_ERR_INVALID_ARG;
+  if (!b->launched) return YYG_ERR_NOT_READY;
+  DeviceGuard dg(b->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  hipStream_t s = stream ? as_stream(stream) : b->stream;
+  hipEvent_t ev[6];
+  for (auto &x : ev)
+    if (hipEventCreate(&x) != hipSuccess) return YYG_ERR_DEVICE;
+  const int nf = (int)b->grids.size();
+  const bool lp = b->precision != YYG_FP64;
+  hipError_t e = hipStreamSynchronize(s);
+  // the same launches as the recorded graph, eagerly, with events between
+  if (e == hipSuccess) {
+    if (!lp) {
+      e = hipMemcpyAsync(b->d_f64[0], b->h_f64[0], nf * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_f64[1], b->h_f64[1], nf * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice, s);
+    } else {
+      e = hipMemcpyAsync(b->d_split[0], b->h_split[0], nf * sizeof(yyg::SplitArgs), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_lp[1], b->h_lp[1], nf * sizeof(yyg::GemmLpArgs), hipMemcpyHostToDevice, s);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+  if (e == hipSuccess && lp)
+    e = yyg::launch_split_rows_grouped(b->precision, b->d_split[0], b->d_split_items[0], b->n_split_items[0],
+                                       std::min(b->n_split_items[0], b->cus * 8), s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = batch_launch_gemm(b, 0, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+  if (e == hipSuccess)
+    e = yyg::launch_radial_scan_grouped(b->d_scan, b->d_scan_items, b->n_scan_items,
+                                        std::min(b->n_scan_items, b->cus * 2), s);
+  if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+  if (e == hipSuccess && lp)
+    e = yyg::launch_split_rows_grouped(b->precision, b->d_split[1], b->d_split_items[1], b->n_split_items[1],
+                                       std::min(b->n_split_items[1], b->cus * 8), s);
+  if (e == hipSuccess) e = hipEventRecord(ev[4], s);
+  if (e == hipSuccess) e = batch_launch_gemm(b, 1, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[5], s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+  float t[5] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ev[i], ev[i + 1]);
+  for (auto &x : ev) (void)hipEventDestroy(x);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  // slots as for plans: 0 analysis, 1 scan, 2 synthesis, 3 operand splits
+  const double vals[4] = {t[1], t[2], t[4], (double)t[0] + t[3]};
+  for (int i = 0; i < n && i < 4; ++i) ms[i] = vals[i];
+  return YYG_OK;
+}
+
 int yyg_batch_destroy(yyg_batch *b) {
   if (!b) return YYG_ERR_INVALID_ARG;
   DeviceGuard dg(b->device);

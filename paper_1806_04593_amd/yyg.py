@@ -25,6 +25,7 @@ EXPORTS = [
     "yyg_grid_destroy", "yyg_host_table", "yyg_set_timing", "yyg_get_timing",
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
+    "yyg_batch_profile",
 ]
 
 
@@ -78,6 +79,7 @@ def lib():
         L.yyg_batch_destroy.argtypes = [vp]
         L.yyg_batch_autotune.argtypes = [vp, vp]
         L.yyg_batch_info.argtypes = [vp, ctypes.POINTER(i), i]
+        L.yyg_batch_profile.argtypes = [vp, vp, dp, i]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -261,6 +263,12 @@ class Batch:
 
     def autotune(self, stream=None):
         _check(lib().yyg_batch_autotune(self._h, _stream_handle(stream)), "yyg_batch_autotune")
+
+    def profile(self, stream=None):
+        """Per-phase milliseconds of one eager run: analysis, scan, synthesis, splits."""
+        ms = np.zeros(4)
+        _check(lib().yyg_batch_profile(self._h, _stream_handle(stream), _dptr(ms), 4), "yyg_batch_profile")
+        return ms
 
     def info(self):
         info = (ctypes.c_int * 6)()
