@@ -168,6 +168,41 @@ def bench_single(a):
                                         "operand_split": avg[3]},
                          "synthesis_tflops": achieved, "launch": info, "prepare_tune_s": round(tune_s, 2)}
         log(f"[bench] {prec}: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, kernels {avg}")
+    # separable form (FP64): phi/theta transforms and rotated cross-patch moments
+    if not a.only or a.method == "separable":
+        g.set_method("separable")
+        if not a.no_autotune:
+            g.autotune("fp64")
+        for _ in range(a.warmup):
+            g.solve(d_phi, "fp64")
+        torch.cuda.synchronize()
+        g.set_timing(True)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(a.steps):
+            g.solve(d_phi, "fp64")
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / a.steps
+        kms, kcnt = g.timing()
+        g.set_timing(False)
+        avg = [float(kms[i] / max(1, kcnt[i])) for i in range(8)]
+        err = None if a.no_check else sampled_error(desc, rho, d_phi.cpu().numpy())
+        L2 = 2 * desc["lmax"] + 1
+        phi_flops = 2.0 * M * nang * L2           # each phi transform
+        phi_bytes = 8.0 * M * nang                # the density read / the potential written
+        results["fp64_separable"] = {
+            "cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
+            "kernels_ms": {"phi_analysis": avg[4], "theta_analysis": avg[5], "radial_scan": avg[1],
+                           "rotate_theta_synthesis": avg[6], "phi_synthesis": avg[7]},
+            "phi_synthesis_tflops": phi_flops / (avg[7] * 1e-3) / 1e12,
+            "phi_synthesis_gbs": phi_bytes / (avg[7] * 1e-3) / 1e9,
+            "phi_analysis_tflops": phi_flops / (avg[4] * 1e-3) / 1e12,
+        }
+        log(f"[bench] fp64 separable: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, "
+            f"kernels {avg[4:]} scan {avg[1]}")
+        g.set_method("dense")
     for prec, r in results.items():
         r["speedup_vs_fp64"] = results["fp64"]["ms_per_step"] / r["ms_per_step"] if "fp64" in results else None
 
@@ -312,6 +347,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sn_core")
     ap.add_argument("--precision", default="fp64", choices=ALL_PRECISIONS)
+    ap.add_argument("--method", default="dense", choices=("dense", "separable"),
+                    help="headline method (both are measured unless --only)")
     ap.add_argument("--only", action="store_true", help="measure the headline precision only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")

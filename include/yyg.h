@@ -102,6 +102,26 @@ int yyg_grid_dims(const yyg_grid *g, int *n_r, int *n_theta, int *n_phi, int *Q)
  * two.  Allocates; call before timing or capturing solves. */
 int yyg_prepare(yyg_grid *g, int precision);
 
+/* Solution method of yyg_solve (FP64 only for the separable form).
+ *  YYG_METHOD_DENSE      the two angular contractions as dense MFMA
+ *                        contractions over all angular cells (Eqs. 26-27 and
+ *                        5, 28-29 written as matrix products): 2Q + 4Q flops
+ *                        per cell.
+ *  YYG_METHOD_SEPARABLE  the same sums factored along the tensor structure
+ *                        of the tables: the analysis as a transform over phi
+ *                        (w_jk C/S_k^(m), a GEMM per colatitude row) followed
+ *                        by one over theta (T_j^(lm)); the potential of the
+ *                        other patch's moments at this patch's points as the
+ *                        potential of those moments rotated degree by degree
+ *                        into this patch's frame (exact rotation blocks of
+ *                        the real harmonics under the Yin <-> Yang map,
+ *                        computed once), then one synthesis over theta and
+ *                        one over phi.  Equal to the dense result up to
+ *                        rounding; about 4(2L+1) + 4Q/n_phi flops per cell.
+ * Switching to the separable form builds its tables (allocates). */
+enum { YYG_METHOD_DENSE = 0, YYG_METHOD_SEPARABLE = 1 };
+int yyg_set_method(yyg_grid *g, int method);
+
 /* Hand the density to the plan.  rho_is_device != 0: `rho` is a device
  * array that the plan borrows (no copy) and that must stay valid until the
  * next yyg_solve on `stream` completes.  rho_is_device == 0: host array,
@@ -145,23 +165,31 @@ int yyg_grid_destroy(yyg_grid *g);
  *   YYG_TABLE_CROSS     for every angular cell a = j*n_phi + k: cos theta',
  *                       sin theta', phi' of its midpoint in the other patch's
  *                       frame (Eqs. 23-24); layout [a][3]      n = 3*n_theta*n_phi
+ *   YYG_TABLE_ROTATION  the rotation blocks of the separable form: for each
+ *                       l the (2l+1)^2 matrix D_l, row-major, blocks in
+ *                       order of l, with Ybar_q(R x) = sum_q' D_l[q][q']
+ *                       Ybar_q'(x) for the map R: (x,y,z) -> (-x,z,y) and
+ *                       Ybar_q = sqrt(N^(lm)) P_l^m cos/sin(m phi)
+ *                                                  n = sum_l (2l+1)^2
  */
 enum {
   YYG_TABLE_WEIGHTS = 0,
   YYG_TABLE_THETA = 1,
   YYG_TABLE_PHI = 2,
   YYG_TABLE_RADIAL = 3,
-  YYG_TABLE_CROSS = 4
+  YYG_TABLE_CROSS = 4,
+  YYG_TABLE_ROTATION = 5
 };
 int yyg_host_table(const yyg_grid_desc *desc, int which, double *out, size_t n);
 
 /* Per-kernel timing with HIP events recorded on the solve stream around
- * every launch of yyg_solve / yyg_batch_solve while enabled.  Kernel slots:
- * 0 analysis contraction, 1 radial scan, 2 synthesis contraction,
- * 3 operand conversion (reduced precisions).  yyg_get_timing synchronises
- * the recorded events and returns the summed milliseconds and launch
- * counts per slot (arrays of `n_slots` entries, n_slots <= 4); enabling
- * again clears the sums. */
+ * every launch of yyg_solve while enabled.  Kernel slots: 0 analysis
+ * contraction, 1 radial scan, 2 synthesis contraction, 3 operand
+ * conversion (reduced precisions); separable form: 4 phi analysis,
+ * 5 theta analysis, 6 rotation + theta synthesis, 7 phi synthesis.
+ * yyg_get_timing synchronises the recorded events and returns the summed
+ * milliseconds and launch counts per slot (arrays of `n_slots` entries,
+ * n_slots <= 8); enabling again clears the sums. */
 int yyg_set_timing(yyg_grid *g, int enable);
 int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots);
 
@@ -196,7 +224,9 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * `grids` are borrowed and must outlive the batch; all on one device; for
  * a reduced precision every plan must be prepared for it.  The batch uses
  * the plans' work buffers, so a plan must not be solved on its own while a
- * batched solve that includes it is in flight. */
+ * batched solve that includes it is in flight.  yyg_autotune or
+ * yyg_plan_config may move a plan's work buffer; a batch built before that
+ * returns YYG_ERR_NOT_READY from yyg_batch_solve and must be re-created. */
 int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out);
 
 /* Choose the tile variant of each grouped contraction by timing them on the

@@ -19,7 +19,7 @@
 
 namespace {
 
-constexpr int kSlots = 4;
+constexpr int kSlots = 8;
 
 struct TimedLaunch {
   int slot;
@@ -51,6 +51,7 @@ struct yyg_grid {
   int var_ana = 0;       // tile variant of the analysis contraction
   int var_syn = 0;       // tile variant of the synthesis contraction
   int part_cap = 1;      // splits the partial-moment buffer can hold
+  int part_gen = 0;      // bumped whenever the partial-moment buffer moves
   std::vector<double> r_edges, w_host, nrm_q;
   yyg::PatchGeom geom;
 
@@ -81,6 +82,32 @@ struct yyg_grid {
   } lp[3];
   int *d_eA = nullptr;  // row exponents of the density (FP16x2)
   int *d_eU = nullptr;  // row exponents of the synthesis operand (FP16x2)
+
+  // separable form
+  int method = YYG_METHOD_DENSE;
+  struct Sep {
+    bool ready = false;
+    long ldk = 0, ldm = 0, ldj = 0, ldl = 0;
+    double *W = nullptr;     // phi-analysis basis [n_t][2L+1][ldk]
+    double *trig = nullptr;  // phi-synthesis basis [n_p][ldm]
+    double *T2 = nullptr;    // theta-analysis basis [mc][l][ldj]: sqrt(N) T_j^(lm)
+    double *P2 = nullptr;    // theta-synthesis basis [mc][j][ldl]: sqrt(N) P_l^m(cos t_j)
+    double *Dt = nullptr;    // transposed rotation blocks, per degree l: [b][a]
+    double *X2 = nullptr;    // phi-analysis output [mc][M][ldj]
+    double *V = nullptr;     // theta-synthesis output [n_t][M][ldm]
+    double *Ut2 = nullptr;   // own + rotated other moments [mc][M][ldl]
+    // problems: phi-ana [n_t], theta-ana [2L+1], theta-syn [2L+1], phi-syn [n_t], rotation [L+1]
+    yyg::GemmF64Args *probs = nullptr;
+    // phases: 0 phi analysis, 1 theta analysis, 2 rotation, 3 theta synthesis, 4 phi synthesis
+    int4 *items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int n_items[5] = {0, 0, 0, 0, 0};
+    int blocks[5] = {0, 0, 0, 0, 0};
+    int var[5] = {6, 3, 9, 3, 3};
+    int part_gen = -1;
+    std::vector<yyg::GemmF64Args> h_probs;
+    const double *rho_c = nullptr;  // pointers the problem arrays hold
+    double *phi_c = nullptr;
+  } sep;
 
   bool timing = false;
   std::vector<TimedLaunch> launches;
@@ -118,6 +145,13 @@ void free_grid(yyg_grid *g) {
   }
   if (g->d_eA) (void)hipFree(g->d_eA);
   if (g->d_eU) (void)hipFree(g->d_eU);
+  {
+    void *b[] = {g->sep.W,        g->sep.trig,     g->sep.T2,       g->sep.P2,       g->sep.Dt,
+                 g->sep.X2,       g->sep.V,        g->sep.Ut2,      g->sep.probs,    g->sep.items[0],
+                 g->sep.items[1], g->sep.items[2], g->sep.items[3], g->sep.items[4]};
+    for (void *x : b)
+      if (x) (void)hipFree(x);
+  }
   for (auto &t : g->launches) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -228,6 +262,224 @@ std::map<std::string, std::pair<int, int>> read_tune_cache(const char *path) {
 }  // namespace
 
 
+namespace {
+
+// Work items of separable phase r for tile variant v, largest K first.
+int sep_set_items(yyg_grid *g, int r, int v) {
+  auto &S = g->sep;
+  const int nt = g->n_t, nmc = 2 * g->L + 1;
+  const int first[5] = {0, nt, 2 * nt + 2 * nmc, nt + nmc, nt + 2 * nmc};
+  const int count[5] = {nt, nmc, g->L + 1, nmc, nt};
+  int bm, bn;
+  yyg::gemm_f64_variant_tile(v, &bm, &bn);
+  std::vector<std::pair<int, int4>> work;
+  for (int pi = first[r]; pi < first[r] + count[r]; ++pi) {
+    const yyg::GemmF64Args &a = S.h_probs[pi];
+    const int tm = (a.M + bm - 1) / bm, tn = (a.N + bn - 1) / bn;
+    for (int b = 0; b < tn; ++b)
+      for (int i = 0; i < tm; ++i) work.push_back({a.K, int4{pi, i, b, 0}});
+  }
+  std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+  std::vector<int4> items(work.size());
+  for (size_t i = 0; i < work.size(); ++i) items[i] = work[i].second;
+  if (S.items[r]) (void)hipFree(S.items[r]);
+  S.items[r] = nullptr;
+  S.n_items[r] = (int)items.size();
+  if (dmalloc(&S.items[r], items.size()) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
+  if (hipMemcpy(S.items[r], items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
+  const long lds = 2L * (bm + bn) * 18 * 8;
+  const int per_cu = (int)std::max(1L, std::min(4L, 160L * 1024 / lds));
+  S.blocks[r] = std::max(1, std::min(S.n_items[r], cus * per_cu));
+  S.var[r] = v;
+  return YYG_OK;
+}
+
+hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
+  auto &S = g->sep;
+  const int role = r < 2 ? 2 : 3;  // general epilogue
+  return yyg::launch_gemm_f64_grouped(S.var[r], role, S.probs, S.items[r], S.n_items[r], S.blocks[r], s);
+}
+
+// (Re)write the pointer-dependent problems (phi analysis reads the density,
+// phi synthesis writes the potential) and upload the problem array.  Waits
+// for earlier work on s: the device copy may still be in use.
+int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t s) {
+  auto &S = g->sep;
+  if (S.rho_c == rho && S.phi_c == phi && S.part_gen == g->part_gen) return YYG_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  const int nt = g->n_t, nmc = 2 * g->L + 1;
+  for (int j = 0; j < nt; ++j) {
+    S.h_probs[j].A = rho + (long)j * g->n_p;
+    S.h_probs[nt + 2 * nmc + j].C = phi + (long)j * g->n_p;
+  }
+  for (int mc = 0; mc < nmc; ++mc) S.h_probs[nt + mc].C = g->d_part + mc;  // the buffer may have moved
+  if (hipMemcpy(S.probs, S.h_probs.data(), S.h_probs.size() * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  S.rho_c = rho;
+  S.phi_c = phi;
+  S.part_gen = g->part_gen;
+  return YYG_OK;
+}
+
+int sep_build(yyg_grid *g) {
+  auto &S = g->sep;
+  const int L = g->L, Q = g->Q, nmc = 2 * L + 1, nt = g->n_t, np = g->n_p;
+  const long M = 2L * g->n_r;
+  S.ldk = round_up(np, 16);
+  S.ldm = round_up(nmc, 16);
+  S.ldj = round_up(nt, 16);
+  S.ldl = round_up(L + 1, 16);
+  std::vector<double> W, trig, T, P, T2, P2, D;
+  try {
+    W.resize((size_t)nt * nmc * S.ldk);
+    yyg::separable_phi_basis(g->geom, g->w_host.data(), L, S.ldk, W.data());
+    trig.resize((size_t)np * S.ldm);
+    yyg::separable_trig(g->geom, L, S.ldm, trig.data());
+    T.resize((size_t)nt * Q);
+    yyg::theta_table_normalised(g->geom, L, T.data());
+    P.resize((size_t)nt * Q);
+    yyg::self_legendre_table(g->geom, L, P.data());
+    // azimuthal-column-major copies for the theta GEMMs
+    T2.assign((size_t)nmc * (L + 1) * S.ldj, 0.0);
+    P2.assign((size_t)nmc * nt * S.ldl, 0.0);
+    for (int mc = 0; mc < nmc; ++mc) {
+      const int m = (mc + 1) / 2;
+      for (int l = m; l <= L; ++l)
+        for (int j = 0; j < nt; ++j) {
+          T2[((size_t)mc * (L + 1) + l) * S.ldj + j] = T[(size_t)j * Q + l * l + mc];
+          P2[((size_t)mc * nt + j) * S.ldl + l] = P[(size_t)j * Q + l * l + mc];
+        }
+    }
+    std::vector<double> D0(yyg::rotation_blocks_size(L));
+    yyg::rotation_blocks(L, D0.data());
+    D.resize(D0.size());
+    for (int l = 0, off = 0; l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) {
+      const int d = 2 * l + 1;
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) D[off + b * d + a] = D0[off + a * d + b];
+    }
+  } catch (const std::bad_alloc &) {
+    return YYG_ERR_OUT_OF_MEMORY;
+  }
+  int st = YYG_OK;
+  if (st == YYG_OK) st = dmalloc(&S.W, W.size());
+  if (st == YYG_OK) st = dmalloc(&S.trig, trig.size());
+  if (st == YYG_OK) st = dmalloc(&S.T2, T2.size());
+  if (st == YYG_OK) st = dmalloc(&S.P2, P2.size());
+  if (st == YYG_OK) st = dmalloc(&S.Dt, D.size());
+  if (st == YYG_OK) st = dmalloc(&S.X2, (size_t)nmc * M * S.ldj);
+  if (st == YYG_OK) st = dmalloc(&S.V, (size_t)nt * M * S.ldm);
+  if (st == YYG_OK) st = dmalloc(&S.Ut2, (size_t)nmc * M * S.ldl);
+  if (st == YYG_OK) st = dmalloc(&S.probs, 2 * (size_t)nt + 2 * (size_t)nmc + (size_t)(L + 1));
+  if (st != YYG_OK) return st;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+  };
+  chk(hipMemcpy(S.W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.T2, T2.data(), T2.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.P2, P2.data(), P2.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.Dt, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  // problems of the grouped GEMM phases (tile-independent)
+  auto kround = [](long k) { return (int)((k + 15) / 16 * 16); };
+  S.h_probs.assign(2 * (size_t)nt + 2 * (size_t)nmc + (size_t)(L + 1), yyg::GemmF64Args{});
+  for (int j = 0; j < nt; ++j) {
+    // X2[mc][row][j] = sum_k rho[row][j][k] W_j[mc][k]     (rho pointer set per solve)
+    yyg::GemmF64Args &a = S.h_probs[j];
+    a = yyg::GemmF64Args{(int)M, nmc, np, nullptr, g->nang, S.W + (long)j * nmc * S.ldk, S.ldk, S.X2 + j, S.ldj, 0,
+                         kround(np), 1};
+    a.ldc_c = M * S.ldj;
+    // phi[row][j][k] = sum_mc V_j[row][mc] trig[k][mc]    (phi pointer set per solve)
+    S.h_probs[nt + 2 * nmc + j] = yyg::GemmF64Args{(int)M, np, nmc, S.V + (long)j * M * S.ldm, S.ldm, S.trig, S.ldm,
+                                                   nullptr, g->nang, 0, kround(nmc), 1};
+  }
+  for (int mc = 0; mc < nmc; ++mc) {
+    const int m = (mc + 1) / 2, nl = L + 1 - m;
+    // A[row][l^2 + mc] = sum_j X2[mc][row][j] T2[mc][l][j], l >= m
+    yyg::GemmF64Args &a = S.h_probs[nt + mc];
+    a = yyg::GemmF64Args{(int)M, nl, nt, S.X2 + (long)mc * M * S.ldj, S.ldj,
+                         S.T2 + ((long)mc * (L + 1) + m) * S.ldj, S.ldj, g->d_part + mc, Q, 0, kround(nt), 1};
+    a.c_sq = m;
+    // V[j][row][mc] = sum_{l >= m} Ut2[mc][row][l] P2[mc][j][l]
+    yyg::GemmF64Args &b = S.h_probs[nt + nmc + mc];
+    b = yyg::GemmF64Args{(int)M, nt, nl, S.Ut2 + (long)mc * M * S.ldl + m, S.ldl, S.P2 + (long)mc * nt * S.ldl + m,
+                         S.ldl, S.V + mc, S.ldm, 0, kround(nl), 1};
+    b.ldc_c = M * S.ldm;
+  }
+  for (int l = 0, off = 0; l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) {
+    // Ut2[b][row][l] += sum_a U_other[row][l^2 + a] D_l[a][b]   (other patch's moments, rotated)
+    const int d = 2 * l + 1;
+    yyg::GemmF64Args &a = S.h_probs[2 * nt + 2 * nmc + l];
+    a = yyg::GemmF64Args{(int)M, d, d, g->d_U + Q + l * l, g->ldy, S.Dt + off, d, S.Ut2 + l, S.ldl, 0, kround(d), 1};
+    a.ldc_c = M * S.ldl;
+    a.c_add = 1;
+  }
+  for (int r = 0; r < 5; ++r) {
+    int st2 = sep_set_items(g, r, S.var[r]);
+    if (st2 != YYG_OK) return st2;
+  }
+  S.rho_c = nullptr;
+  S.phi_c = nullptr;
+  S.ready = true;
+  return YYG_OK;
+}
+
+// Separable solve: phi analysis, theta analysis (grouped GEMMs), radial
+// scan, rotation of the other patch's moments, theta synthesis, phi
+// synthesis (grouped GEMMs).
+hipError_t sep_solve(yyg_grid *g, hipStream_t s) {
+  auto &S = g->sep;
+  const int Q = g->Q;
+  const long M = 2L * g->n_r;
+  hipError_t e = hipSuccess;
+  int t = timing_begin(g, 4, s);
+  e = sep_launch_phase(g, 0, s);
+  timing_end(g, t, s);
+  if (e == hipSuccess) {
+    t = timing_begin(g, 5, s);
+    e = sep_launch_phase(g, 1, s);
+    timing_end(g, t, s);
+  }
+  if (e == hipSuccess) {
+    t = timing_begin(g, 1, s);
+    e = yyg::launch_radial_scan(g->d_part, 1, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, g->n_r, Q, g->L, -g->G,
+                                g->d_U, g->ldy, s);
+    timing_end(g, t, s);
+  }
+  if (e == hipSuccess) {
+    t = timing_begin(g, 6, s);
+    e = yyg::launch_scatter_moments(g->d_U, g->ldy, g->d_qdeg, (int)M, Q, S.Ut2, S.ldl, s);
+    if (e == hipSuccess) e = sep_launch_phase(g, 2, s);
+    if (e == hipSuccess) e = sep_launch_phase(g, 3, s);
+    timing_end(g, t, s);
+  }
+  if (e == hipSuccess) {
+    t = timing_begin(g, 7, s);
+    e = sep_launch_phase(g, 4, s);
+    timing_end(g, t, s);
+  }
+  return e;
+}
+
+}  // namespace
+
+
 struct yyg_batch {
   int device = 0;
   int precision = 0;
@@ -255,6 +507,7 @@ struct yyg_batch {
   hipEvent_t done = nullptr;
   hipStream_t stream = nullptr;  // used when the caller passes the default stream
   bool launched = false;
+  std::vector<int> part_gen;     // plans' partial-buffer generations the arguments hold
 };
 
 namespace {
@@ -407,6 +660,8 @@ int batch_build(yyg_batch *b) {
   const bool scaled = b->precision == YYG_FP16X2;
   b->rho.assign(n, nullptr);
   b->phi.assign(n, nullptr);
+  b->part_gen.resize(n);
+  for (int f = 0; f < n; ++f) b->part_gen[f] = b->grids[f]->part_gen;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
     b->cus = cus;
@@ -532,6 +787,10 @@ int yyg_host_table(const yyg_grid_desc *d, int which, double *out, size_t n) {
       case YYG_TABLE_CROSS:
         if (n != 3 * nang) return YYG_ERR_INVALID_ARG;
         yyg::cross_points(g, out);
+        return YYG_OK;
+      case YYG_TABLE_ROTATION:
+        if (n != (size_t)yyg::rotation_blocks_size(L)) return YYG_ERR_INVALID_ARG;
+        yyg::rotation_blocks(L, out);
         return YYG_OK;
       default:
         return YYG_ERR_INVALID_ARG;
@@ -742,6 +1001,7 @@ int yyg_prepare(yyg_grid *g, int precision) {
     if (dmalloc(&np, (size_t)L.nsplit * M * Q) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
     (void)hipFree(g->d_part);
     g->d_part = np;
+    g->part_gen += 1;
     g->part_cap = L.nsplit;
   }
   L.ready = true;
@@ -789,6 +1049,30 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
   int t;
   const bool lp = precision != YYG_FP64;
   const bool scaled = precision == YYG_FP16X2;
+  if (g->method == YYG_METHOD_SEPARABLE) {
+    if (lp) {
+      if (tmp) (void)hipFree(tmp);
+      return YYG_ERR_UNSUPPORTED;
+    }
+    int st = sep_set_pointers(g, g->rho, out, s);
+    if (st != YYG_OK) {
+      if (tmp) (void)hipFree(tmp);
+      return st;
+    }
+    e = sep_solve(g, s);
+    if (!phi_is_device) {
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(phi, out, (size_t)M * g->nang * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      (void)hipFree(tmp);
+      g->sep.phi_c = nullptr;  // the temporary is gone
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return YYG_ERR_DEVICE;
+    }
+    return YYG_OK;
+  }
   const int nsplit = lp ? g->lp[precision - 1].nsplit : g->nsplit;
   if (lp) {
     // split the density into operand planes (rows scaled for FP16)
@@ -921,6 +1205,22 @@ int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots) {
   return YYG_OK;
 }
 
+int yyg_set_method(yyg_grid *g, int method) {
+  if (!g || (method != YYG_METHOD_DENSE && method != YYG_METHOD_SEPARABLE)) return YYG_ERR_INVALID_ARG;
+  if (method == YYG_METHOD_SEPARABLE && !g->sep.ready) {
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return YYG_ERR_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) {
+      (void)hipGetLastError();
+      return YYG_ERR_DEVICE;
+    }
+    int st = sep_build(g);
+    if (st != YYG_OK) return st;
+  }
+  g->method = method;
+  return YYG_OK;
+}
+
 int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   if (!g) return YYG_ERR_INVALID_ARG;
   if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
@@ -1041,11 +1341,42 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     (void)hipDeviceSynchronize();
     (void)hipFree(g->d_part);
     g->d_part = np;
+    g->part_gen += 1;
     g->part_cap = best_sp;
   }
   *cur_va = best_va;
   *cur_sp = best_sp;
   *cur_vs = best_vs;
+  // separable form (FP64): tile variant of each grouped phase
+  if (!lp && g->sep.ready) {
+    double *phi_t = nullptr, *rho_t = nullptr;
+    int st3 = dmalloc(&phi_t, (size_t)M * g->nang);
+    if (st3 == YYG_OK && !g->rho) {
+      st3 = dmalloc(&rho_t, (size_t)M * g->nang);
+      if (st3 == YYG_OK) (void)hipMemsetAsync(rho_t, 0, (size_t)M * g->nang * sizeof(double), s);
+    }
+    if (st3 == YYG_OK) st3 = sep_set_pointers(g, g->rho ? g->rho : rho_t, phi_t, s);
+    for (int r = 0; r < 5 && st3 == YYG_OK; ++r) {
+      double best = 1e30;
+      int bv = g->sep.var[r];
+      for (int v = 0; v < yyg::gemm_f64_variant_count() && st3 == YYG_OK; ++v) {
+        st3 = sep_set_items(g, r, v);
+        if (st3 != YYG_OK) break;
+        double t = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 3);
+        if (t < best) {
+          best = t;
+          bv = v;
+        }
+      }
+      if (st3 == YYG_OK) st3 = sep_set_items(g, r, bv);
+    }
+    (void)hipStreamSynchronize(s);
+    if (phi_t) (void)hipFree(phi_t);
+    if (rho_t) (void)hipFree(rho_t);
+    g->sep.rho_c = nullptr;  // the next solve writes its own pointers
+    g->sep.phi_c = nullptr;
+    if (st3 != YYG_OK) return st3;
+  }
   if (cache_path && (!have_a || !have_s)) {
     if (std::FILE *f = std::fopen(cache_path, "a")) {
       if (!have_a) std::fprintf(f, "%s -> %d %d\n", ka.c_str(), best_va, best_sp);
@@ -1072,6 +1403,7 @@ int yyg_plan_config(yyg_grid *g, int precision, int var_ana, int split_ana, int 
     (void)hipDeviceSynchronize();
     (void)hipFree(g->d_part);
     g->d_part = np;
+    g->part_gen += 1;
     g->part_cap = split_ana;
   }
   if (lp) {
@@ -1187,6 +1519,10 @@ int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_p
   const int n = (int)b->grids.size();
   for (int f = 0; f < n; ++f)
     if (!d_rho[f] || !d_phi[f]) return YYG_ERR_INVALID_ARG;
+  // a plan's work buffer moved (autotune / plan_config after the batch was
+  // built): the recorded arguments are stale
+  for (int f = 0; f < n; ++f)
+    if (b->grids[f]->part_gen != b->part_gen[f]) return YYG_ERR_NOT_READY;
   DeviceGuard dg(b->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   // a graph cannot be recorded on the legacy default stream: use the

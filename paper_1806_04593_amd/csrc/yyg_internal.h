@@ -13,10 +13,13 @@ struct GemmF64Args {
   const double *B;
   long ldb;
   double *C;
-  long ldc;
+  long ldc;             // row stride of C
   long c_split_stride;
-  int k_per_split;  // multiple of the stage width (16)
+  int k_per_split;      // multiple of the stage width (16)
   int tiles_m;
+  long ldc_c = 1;       // column stride of C
+  int c_sq = -1;        // >= 0: column n of C lands at (n + c_sq)^2 (degree-major q index)
+  int c_add = 0;        // 1: C += A.B^T instead of C = A.B^T
 };
 
 // FP64 NT GEMM C = A . B^T in one of several tile shapes ("variants");
@@ -27,7 +30,9 @@ hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const 
                               long ldb, double *C, long ldc, int nsplit, long c_split_stride, hipStream_t s);
 
 // Persistent grouped FP64 GEMM: n_blocks blocks walk `items` = (problem,
-// tm, tn, split) over the problems' tiles of the variant's shape.
+// tm, tn, split) over the problems' tiles of the variant's shape.  role 0/1
+// = analysis / synthesis with the plain epilogue, 2/3 with the general one
+// (ldc_c, c_sq, c_add honoured).
 hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *probs, const int4 *items, int n_items,
                                   int n_blocks, hipStream_t s);
 
@@ -105,6 +110,11 @@ hipError_t launch_split_rows_grouped(int prec, const SplitArgs *probs, const int
                                      hipStream_t s);
 hipError_t launch_split_rows(int prec, const double *X, long ldx, int rows, int ncols, const int *e, void *P,
                              long ldp, long plane_stride, hipStream_t s);
+
+// Separable-form kernels (see yyg_kernels.hip).
+hipError_t launch_scatter_moments(const double *U, long ldu, const int *qdeg, int M, int Q, double *Ut, long ldl,
+                                  hipStream_t s);
+int gemm_f64_variant_threads(int v);
 
 // Split-K factor for an output of `tiles` block tiles and K columns.
 int choose_split(long tiles, long K);

@@ -37,7 +37,9 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 
 // Block tile BM x BN, WGM x WGN waves, each wave a (BM/WGM) x (BN/WGN) grid
 // of 16 x 16 MFMA tiles; computes output tile (tm, tn) over split z.
-template <int BM, int BN, int WGM, int WGN>
+// GEN selects the general epilogue (column stride, degree-major column
+// index, accumulate); the plain one writes C[row * ldc + col].
+template <int BM, int BN, int WGM, int WGN, bool GEN>
 __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int tn, int z) {
   const int M = g.M, N = g.N, K = g.K;
   const double *__restrict__ A = g.A;
@@ -46,8 +48,14 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   const long lda = g.lda, ldb = g.ldb, ldc = g.ldc;
   constexpr int NT = 64 * WGM * WGN;
   constexpr int TI = BM / WGM / 16, TJ = BN / WGN / 16;
-  constexpr int EA = BM * kBK / NT, EB = BN * kBK / NT;  // doubles per thread per stage
-  static_assert(EA >= 1 && EB >= 1 && kBK % EA == 0 && kBK % EB == 0, "tile/thread mismatch");
+  static_assert(TI >= 1 && TJ >= 1 && TI * 16 * WGM == BM && TJ * 16 * WGN == BN, "tile/wave mismatch");
+  // Stage loads.  When a thread's share of a tile stage divides the 16-wide
+  // stage, it reads one contiguous run of k in one row (one row pointer);
+  // otherwise element e = tid + i*NT sits at row e / 16, column e % 16.
+  constexpr bool RUN_A = (BM * kBK) % NT == 0 && kBK % ((BM * kBK) / NT) == 0;
+  constexpr bool RUN_B = (BN * kBK) % NT == 0 && kBK % ((BN * kBK) / NT) == 0;
+  constexpr int EA = RUN_A ? (BM * kBK) / NT : (BM * kBK + NT - 1) / NT;
+  constexpr int EB = RUN_B ? (BN * kBK) / NT : (BN * kBK + NT - 1) / NT;
   __shared__ double As[2][BM * kLDK];
   __shared__ double Bs[2][BN * kLDK];
 
@@ -58,8 +66,6 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   C += (long)z * g.c_split_stride;
 
   const int wm = wave % WGM, wn = wave / WGM;
-  const int arow = tid / (kBK / EA), acol = (tid % (kBK / EA)) * EA;
-  const int brow = tid / (kBK / EB), bcol = (tid % (kBK / EB)) * EB;
 
   dbl4 acc[TI][TJ];
 #pragma unroll
@@ -68,28 +74,63 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
     for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   double ra[EA], rb[EB];
-  const int ga = m0 + arow, gb = n0 + brow;
-  const double *pa = A + (long)min(ga, M - 1) * lda;
-  const double *pb = B + (long)min(gb, N - 1) * ldb;
-  const bool va = ga < M, vb = gb < N;
-
+  // run mapping: this thread's row and first column
+  const int arow = RUN_A ? tid / (kBK / EA) : 0, acol = RUN_A ? (tid % (kBK / EA)) * EA : 0;
+  const int brow = RUN_B ? tid / (kBK / EB) : 0, bcol = RUN_B ? (tid % (kBK / EB)) * EB : 0;
+  const double *pa = A + (long)min(m0 + arow, M - 1) * lda;
+  const double *pb = B + (long)min(n0 + brow, N - 1) * ldb;
+  const bool va = m0 + arow < M, vb = n0 + brow < N;
   auto load = [&](int k0) {
+    if constexpr (RUN_A) {
 #pragma unroll
-    for (int i = 0; i < EA; ++i) {
-      const int kk = k0 + acol + i;
-      ra[i] = (va && kk < kend) ? pa[kk] : 0.0;
+      for (int i = 0; i < EA; ++i) {
+        const int kk = k0 + acol + i;
+        ra[i] = (va && kk < kend) ? pa[kk] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < EA; ++i) {
+        const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
+        const int gr = m0 + row;
+        ra[i] = (e < BM * kBK && gr < M && kk < kend) ? A[(long)gr * lda + kk] : 0.0;
+      }
     }
+    if constexpr (RUN_B) {
 #pragma unroll
-    for (int i = 0; i < EB; ++i) {
-      const int kk = k0 + bcol + i;
-      rb[i] = (vb && kk < kend) ? pb[kk] : 0.0;
+      for (int i = 0; i < EB; ++i) {
+        const int kk = k0 + bcol + i;
+        rb[i] = (vb && kk < kend) ? pb[kk] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
+        const int gr = n0 + row;
+        rb[i] = (e < BN * kBK && gr < N && kk < kend) ? B[(long)gr * ldb + kk] : 0.0;
+      }
     }
   };
   auto stash = [&](int buf) {
+    if constexpr (RUN_A) {
 #pragma unroll
-    for (int i = 0; i < EA; ++i) As[buf][arow * kLDK + acol + i] = ra[i];
+      for (int i = 0; i < EA; ++i) As[buf][arow * kLDK + acol + i] = ra[i];
+    } else {
 #pragma unroll
-    for (int i = 0; i < EB; ++i) Bs[buf][brow * kLDK + bcol + i] = rb[i];
+      for (int i = 0; i < EA; ++i) {
+        const int e = tid + i * NT;
+        if (e < BM * kBK) As[buf][(e / kBK) * kLDK + e % kBK] = ra[i];
+      }
+    }
+    if constexpr (RUN_B) {
+#pragma unroll
+      for (int i = 0; i < EB; ++i) Bs[buf][brow * kLDK + bcol + i] = rb[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const int e = tid + i * NT;
+        if (e < BN * kBK) Bs[buf][(e / kBK) * kLDK + e % kBK] = rb[i];
+      }
+    }
   };
 
   const int nk = (kend - kbeg + kBK - 1) / kBK;
@@ -141,7 +182,15 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * (BM / WGM) + i * 16 + orow + 4 * r;
-        if (row < M && col < N) C[(long)row * ldc + col] = acc[i][j][r];
+        if (row < M && col < N) {
+          if constexpr (GEN) {
+            const long cc = g.c_sq < 0 ? (long)col * g.ldc_c : (long)(col + g.c_sq) * (col + g.c_sq);
+            double *c = &C[(long)row * ldc + cc];
+            *c = g.c_add ? *c + acc[i][j][r] : acc[i][j][r];
+          } else {
+            C[(long)row * ldc + col] = acc[i][j][r];
+          }
+        }
       }
     }
   }
@@ -152,18 +201,18 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 template <int ROLE, int BM, int BN, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(GemmF64Args g, int tiles_total) {
   const int tile = xcd_tile(blockIdx.x, tiles_total);
-  gemm_f64_tile<BM, BN, WGM, WGN>(g, tile % g.tiles_m, tile / g.tiles_m, blockIdx.y);
+  gemm_f64_tile<BM, BN, WGM, WGN, false>(g, tile % g.tiles_m, tile / g.tiles_m, blockIdx.y);
 }
 
 // Persistent grouped form: blocks walk a list of (problem, tm, tn, split)
 // work items over several independent contractions of one phase.
-template <int ROLE, int BM, int BN, int WGM, int WGN>
+template <int ROLE, int BM, int BN, int WGM, int WGN, bool GEN>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_grouped(const GemmF64Args *__restrict__ probs,
                                                                       const int4 *__restrict__ items, int n_items) {
   for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
     const int4 it = items[w];
     __syncthreads();  // the previous item's LDS reads are done
-    gemm_f64_tile<BM, BN, WGM, WGN>(probs[it.x], it.y, it.z, it.w);
+    gemm_f64_tile<BM, BN, WGM, WGN, GEN>(probs[it.x], it.y, it.z, it.w);
   }
 }
 
@@ -394,6 +443,27 @@ __global__ void expand_self_basis_kernel(const double *__restrict__ P, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Separable form.  The analysis basis factors as T_j^(lm) x (w_jk C/S_k^(m))
+// and the self-synthesis basis as P_l^m(cos t_j) x cos/sin(m phi_k), so each
+// contraction splits into a transform over phi (a GEMM per colatitude row j)
+// and one over theta (a GEMM per azimuthal column mc), both run as grouped
+// launches of gemm_f64_tile.  The other patch's moments enter the synthesis
+// rotated into this patch's frame, degree by degree (kernel below).
+// Azimuthal column mc: 0 for m = 0, 2m-1 (cos) / 2m (sin); q = l^2 + mc.
+
+// Ut[mc][row][l] = U[row][l^2 + mc]: own moments in azimuthal-column-major
+// order; the rotated moments of the other patch are added by grouped GEMMs
+// (one per degree l, with the transposed rotation block).
+__global__ void scatter_moments_kernel(const double *__restrict__ U, long ldu, const int *__restrict__ qdeg, int Q,
+                                       long M, double *__restrict__ Ut, long ldl) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const long row = blockIdx.y;
+  if (q >= Q) return;
+  const int l = qdeg[q];
+  Ut[((long)(q - l * l) * M + row) * ldl + l] = U[row * ldu + q];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -429,10 +499,22 @@ template <int BM, int BN, int WGM, int WGN>
 hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4 *items, int n_items, int n_blocks,
                                   hipStream_t s) {
   dim3 grid(n_blocks), block(64 * WGM * WGN);
-  if (role == 0)
-    hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN>), grid, block, 0, s, probs, items, n_items);
-  else
-    hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN>), grid, block, 0, s, probs, items, n_items);
+  // roles 0/1: analysis / synthesis with the plain epilogue; 2/3: the same
+  // with the general epilogue
+  switch (role) {
+    case 0:
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, false>), grid, block, 0, s, probs, items, n_items);
+      break;
+    case 1:
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, false>), grid, block, 0, s, probs, items, n_items);
+      break;
+    case 2:
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, true>), grid, block, 0, s, probs, items, n_items);
+      break;
+    default:
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, true>), grid, block, 0, s, probs, items, n_items);
+      break;
+  }
   return hipGetLastError();
 }
 
@@ -453,6 +535,9 @@ struct F64Variant {
 const F64Variant kF64Variants[] = {
     YYG_F64_VARIANT(128, 128, 2, 2), YYG_F64_VARIANT(64, 128, 2, 2),  YYG_F64_VARIANT(128, 64, 2, 2),
     YYG_F64_VARIANT(64, 64, 2, 2),   YYG_F64_VARIANT(256, 128, 4, 2), YYG_F64_VARIANT(128, 256, 2, 4),
+    // narrow-N shapes for the transforms whose N is 2L+1 or a degree block
+    YYG_F64_VARIANT(128, 48, 4, 1),  YYG_F64_VARIANT(128, 96, 4, 1),  YYG_F64_VARIANT(128, 144, 4, 1),
+    YYG_F64_VARIANT(64, 32, 2, 2),
 };
 
 }  // namespace
@@ -515,5 +600,14 @@ hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, 
   hipLaunchKernelGGL(expand_self_basis_kernel, dim3(n_t * n_p), dim3(256), 0, s, P, Tr, n_t, n_p, Q, Y, ldy);
   return hipGetLastError();
 }
+
+hipError_t launch_scatter_moments(const double *U, long ldu, const int *qdeg, int M, int Q, double *Ut, long ldl,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(scatter_moments_kernel, dim3((Q + 127) / 128, M), dim3(128), 0, s, U, ldu, qdeg, Q, (long)M, Ut,
+                     ldl);
+  return hipGetLastError();
+}
+
+int gemm_f64_variant_threads(int v) { return kF64Variants[v].threads; }
 
 }  // namespace yyg

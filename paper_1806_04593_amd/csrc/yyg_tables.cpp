@@ -396,4 +396,90 @@ void cross_basis(const PatchGeom &g, int L, double *out) {
   });
 }
 
+void separable_phi_basis(const PatchGeom &g, const double *w, int L, long ldk, double *out) {
+  const int Q = (L + 1) * (L + 1), nmc = 2 * L + 1;
+  std::vector<double> cs((size_t)g.n_p * Q);
+  phi_table(g, L, cs.data());
+  for (int j = 0; j < g.n_t; ++j)
+    for (int mc = 0; mc < nmc; ++mc) {
+      const int m = (mc + 1) / 2;
+      const int q = m * m + mc;  // column (l = m, m, c)
+      double *o = out + ((size_t)j * nmc + mc) * ldk;
+      for (long k = 0; k < ldk; ++k) o[k] = k < g.n_p ? w[(size_t)j * g.n_p + k] * cs[(size_t)k * Q + q] : 0.0;
+    }
+}
+
+void separable_trig(const PatchGeom &g, int L, long ldm, double *out) {
+  const int nmc = 2 * L + 1;
+  for (int k = 0; k < g.n_p; ++k) {
+    const double pc = 0.5 * (g.ph[k] + g.ph[k + 1]);
+    for (long mc = 0; mc < ldm; ++mc) {
+      double v = 0.0;
+      if (mc < nmc) {
+        const int m = (int)(mc + 1) / 2;
+        v = (mc == 0 || (mc & 1)) ? std::cos(m * pc) : std::sin(m * pc);
+      }
+      out[(size_t)k * ldm + mc] = v;
+    }
+  }
+}
+
+long rotation_blocks_size(int L) {
+  long n = 0;
+  for (int l = 0; l <= L; ++l) n += (long)(2 * l + 1) * (2 * l + 1);
+  return n;
+}
+
+void rotation_blocks(int L, double *out) {
+  const int W = L + 1, Q = W * W;
+  // nodes: Gauss-Legendre in cos(theta) (L+1 nodes integrate degree 2L+1)
+  // times 2L+2 equally spaced longitudes (exact for trig degree <= 2L+1)
+  const int nt = L + 1, np = 2 * L + 2;
+  std::vector<double> xg, wg;
+  gauss_legendre(nt, xg, wg);
+  auto cols = column_table(L);
+  std::vector<long> off(L + 2, 0);
+  for (int l = 0; l <= L; ++l) off[l + 1] = off[l] + (long)(2 * l + 1) * (2 * l + 1);
+  // basis values at every node and at its image under the rotation
+  const long npts = (long)nt * np;
+  std::vector<double> Y((size_t)npts * Q), YR((size_t)npts * Q), wt(npts);
+  parallel_for(npts, [&](long idx) {
+    thread_local std::vector<double> P, PR;
+    P.resize(W * W);
+    PR.resize(W * W);
+    const int it = (int)(idx / np), ip = (int)(idx % np);
+    const double ct = xg[it], st = std::sqrt(std::max(0.0, (1.0 - ct) * (1.0 + ct)));
+    const double ph = 2.0 * kPi * (ip + 0.5) / np;
+    wt[idx] = wg[it] * 2.0 * kPi / np;
+    const double sp = std::sin(ph), cp = std::cos(ph);
+    // image point (x, y, z) -> (-x, z, y)
+    const double ct2 = st * sp, st2 = std::hypot(ct, st * cp), ph2 = std::atan2(ct, -st * cp);
+    legendre_normalised(L, ct, st, P.data());
+    legendre_normalised(L, ct2, st2, PR.data());
+    double *y = &Y[(size_t)idx * Q], *yr = &YR[(size_t)idx * Q];
+    for (int q = 0; q < Q; ++q) {
+      const ColInfo &c = cols[q];
+      const double a1 = c.m * ph, a2 = c.m * ph2;
+      y[q] = P[c.l * W + c.m] * (c.is_sin ? std::sin(a1) : std::cos(a1));
+      yr[q] = PR[c.l * W + c.m] * (c.is_sin ? std::sin(a2) : std::cos(a2));
+    }
+  });
+  // D_l[a][b] = (2l+1)/(4 pi) sum_nodes w YR_a Y_b   (the basis has norm 4 pi/(2l+1))
+  parallel_for(L + 1, [&](long l) {
+    const int d = 2 * (int)l + 1, q0 = (int)(l * l);
+    double *blk = out + off[l];
+    for (int i = 0; i < d * d; ++i) blk[i] = 0.0;
+    for (long idx = 0; idx < npts; ++idx) {
+      const double *y = &Y[(size_t)idx * Q + q0], *yr = &YR[(size_t)idx * Q + q0];
+      const double w0 = wt[idx];
+      for (int a = 0; a < d; ++a) {
+        const double f = w0 * yr[a];
+        for (int b = 0; b < d; ++b) blk[a * d + b] += f * y[b];
+      }
+    }
+    const double s = (2.0 * l + 1.0) / (4.0 * kPi);
+    for (int i = 0; i < d * d; ++i) blk[i] *= s;
+  });
+}
+
 }  // namespace yyg

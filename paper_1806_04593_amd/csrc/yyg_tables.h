@@ -55,4 +55,24 @@ void self_legendre_table(const PatchGeom &g, int L, double *out);
 void self_trig_table(const PatchGeom &g, int L, double *out);
 void cross_basis(const PatchGeom &g, int L, double *out);
 
+// ---- separable form (phi transform, theta transform, patch rotation) -----
+// Azimuthal column index of (m, cos/sin): mc = 0 for m = 0, 2m-1 / 2m for
+// cos / sin, so that q(l, m, c) = l^2 + mc.  2L+1 columns.
+
+// W[j][mc][k] = w_jk * (C_k^(m) or S_k^(m)), rows of length ldk (zero padded)
+void separable_phi_basis(const PatchGeom &g, const double *w, int L, long ldk, double *out);
+
+// trig[k][mc] = cos / sin (m phi_k) at the cell midpoints, rows of length ldm
+void separable_trig(const PatchGeom &g, int L, long ldm, double *out);
+
+// Per degree l, the (2l+1) x (2l+1) block D_l with
+//   Ybar_q(R x) = sum_q' D_l[q - l^2][q' - l^2] Ybar_q'(x),
+// where R is the Yin <-> Yang map (x, y, z) -> (-x, z, y) and Ybar_q are the
+// sqrt(N)-normalised real harmonics of the plan.  Blocks are stored one
+// after the other (offset of block l: sum_{l' < l} (2l'+1)^2), row-major.
+// Computed by Gauss-Legendre x uniform-phi quadrature, exact for the
+// degree-2l products.
+void rotation_blocks(int L, double *out);
+long rotation_blocks_size(int L);
+
 }  // namespace yyg

@@ -1,0 +1,58 @@
+"""Profiling driver: a known-size elementwise kernel (dst = src + 1 over
+--copy-mib MiB: reads and writes exactly that many bytes; the calibration of
+hardware byte counters) followed by a few solves of one workload.
+
+    python -m paper_1806_04593_amd.prof_driver --workload sn_core --precision fp64 --solves 3
+
+Run under `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE) to read the HBM
+bytes of each kernel; the calibration kernel moves exactly --copy-mib MiB each way.
+"""
+
+import argparse
+import os
+import sys
+import time
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="sn_core")
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--solves", type=int, default=3)
+    ap.add_argument("--copy-mib", type=int, default=512)
+    a = ap.parse_args()
+
+    import torch
+
+    from paper_1806_04593_amd import workloads as W
+    from paper_1806_04593_amd import yyg
+
+    n = a.copy_mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.add(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(f"[prof] calibration: read and wrote {a.copy_mib} MiB", flush=True)
+
+    desc = W.describe(a.workload)
+    rho = W.density(desc)
+    g = yyg.Grid(desc, 0)
+    g.prepare(a.precision)
+    g.autotune(a.precision)
+    d_rho = torch.from_numpy(rho).to("cuda:0")
+    d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
+    g.upload_rho(d_rho)
+    t0 = time.perf_counter()
+    for _ in range(a.solves):
+        g.solve(d_phi, a.precision)
+    torch.cuda.synchronize()
+    print(f"[prof] {a.solves} solves of {a.workload} ({a.precision}) in {time.perf_counter() - t0:.3f} s; "
+          f"launch {g.plan_info(a.precision)}", flush=True)
+    sys.stdout.flush()
+
+
+if __name__ == "__main__":
+    main()

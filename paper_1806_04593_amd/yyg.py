@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libyyg.so")
 FP64, FP32, BF16X3, FP16X2 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x2": FP16X2}
 
-TABLE_WEIGHTS, TABLE_THETA, TABLE_PHI, TABLE_RADIAL, TABLE_CROSS = 0, 1, 2, 3, 4
+TABLE_WEIGHTS, TABLE_THETA, TABLE_PHI, TABLE_RADIAL, TABLE_CROSS, TABLE_ROTATION = 0, 1, 2, 3, 4, 5
+METHODS = {"dense": 0, "separable": 1}
 
 EXPORTS = [
     "yyg_grid_create", "yyg_grid_create_res", "yyg_grid_dims", "yyg_prepare",
@@ -25,7 +26,7 @@ EXPORTS = [
     "yyg_grid_destroy", "yyg_host_table", "yyg_set_timing", "yyg_get_timing",
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
-    "yyg_batch_profile",
+    "yyg_batch_profile", "yyg_set_method",
 ]
 
 
@@ -80,6 +81,7 @@ def lib():
         L.yyg_batch_autotune.argtypes = [vp, vp]
         L.yyg_batch_info.argtypes = [vp, ctypes.POINTER(i), i]
         L.yyg_batch_profile.argtypes = [vp, vp, dp, i]
+        L.yyg_set_method.argtypes = [vp, i]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -120,7 +122,8 @@ def host_table(desc, which):
              TABLE_THETA: (desc["n_theta"], Q),
              TABLE_PHI: (desc["n_phi"], Q),
              TABLE_RADIAL: (n_r, desc["lmax"] + 1, 4),
-             TABLE_CROSS: (nang, 3)}[which]
+             TABLE_CROSS: (nang, 3),
+             TABLE_ROTATION: (sum((2 * l + 1) ** 2 for l in range(desc["lmax"] + 1)),)}[which]
     shape = tuple(max(0, v) for v in shape)
     out = np.zeros(shape)
     buf = out if out.size else np.zeros(1)   # the library validates the sizes itself
@@ -153,6 +156,9 @@ class Grid:
     @property
     def handle(self):
         return self._h
+
+    def set_method(self, method):
+        _check(lib().yyg_set_method(self._h, METHODS.get(method, method)), "yyg_set_method")
 
     def prepare(self, precision):
         _check(lib().yyg_prepare(self._h, PRECISIONS.get(precision, precision)), "yyg_prepare")
@@ -215,7 +221,7 @@ class Grid:
     def set_timing(self, enable):
         _check(lib().yyg_set_timing(self._h, int(bool(enable))), "yyg_set_timing")
 
-    def timing(self, n_slots=4):
+    def timing(self, n_slots=8):
         ms = np.zeros(n_slots)
         cnt = (ctypes.c_long * n_slots)()
         _check(lib().yyg_get_timing(self._h, _dptr(ms), cnt, n_slots), "yyg_get_timing")

@@ -182,3 +182,37 @@ def test_radial_recurrence_reproduces_direct_sums(r_edges):
         ref = UC[:, :, l, :]
         scale = np.max(np.abs(ref[:, :, : l + 1]), axis=1, keepdims=True) + 1e-300
         assert np.max(np.abs(U[:, :, : l + 1] - ref[:, :, : l + 1]) / scale) < 1e-12, l
+
+
+@pytest.mark.parametrize("lmax", [4, 25])
+def test_rotation_blocks_rotate_the_harmonics(lmax):
+    """D_l maps the normalised real harmonics (built here from the oracle's
+    P_l^m and N^(lm)) at a point x to their values at R x, R the Yin <-> Yang
+    map of Eqs. (23)-(24); each block is orthogonal."""
+    d = _desc(5.0, lmax)
+    D = yyg.host_table(d, yyg.TABLE_ROTATION)
+    N = O.norm_factor(lmax)
+    rng = np.random.default_rng(6)
+    t = rng.uniform(0.1, 3.0, 30)
+    p = rng.uniform(-3.1, 3.1, 30)
+
+    def ybar(ct, st, ph):
+        P = O.assoc_legendre(lmax, ct, st)
+        out = []
+        for l in range(lmax + 1):
+            out.append(np.sqrt(N[l, 0]) * P[l, 0])
+            for m in range(1, l + 1):
+                out.append(np.sqrt(N[l, m]) * P[l, m] * np.cos(m * ph))
+                out.append(np.sqrt(N[l, m]) * P[l, m] * np.sin(m * ph))
+        return np.array(out)            # [Q, pts]
+    Y = ybar(np.cos(t), np.sin(t), p)
+    c2, s2, p2 = O.other_patch_angles(t, p)
+    YR = ybar(c2, s2, p2)
+    off = 0
+    for l in range(lmax + 1):
+        dd = 2 * l + 1
+        blk = D[off:off + dd * dd].reshape(dd, dd)
+        off += dd * dd
+        q0 = l * l
+        np.testing.assert_allclose(blk @ Y[q0:q0 + dd], YR[q0:q0 + dd], atol=1e-12)
+        np.testing.assert_allclose(blk @ blk.T, np.eye(dd), atol=1e-12)
