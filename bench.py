@@ -3,8 +3,10 @@
 One step = one full solve (angular analysis, radial scans, synthesis on both
 patches, plus the operand splits of the reduced precisions) of a synthetic,
 device-resident density; plans and autotuning happen before timing.  Prints
-one JSON line: the headline precision's cells/s as `value`, every
-precision's rate and error against the FP64 oracle under `precisions`.
+one JSON line: the headline's cells/s as `value` (by default the FP64
+separable solve), and every method / precision's rate and error against the
+FP64 oracle under `precisions` (dense FP64, FP32, BF16x3, FP16x2 and the
+separable FP64 form).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sn_core]
                     [--precision fp64] [--no-cpu-baseline] [--no-check]
@@ -41,21 +43,21 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision):
-    """HBM bytes per launch of the synthesis kernel from committed rocprofv3
-    --pmc counters (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated), or None
-    when absent or taken on different kernel sources."""
+def measured_traffic(workload, key, kernel):
+    """HBM bytes per launch of one kernel from committed rocprofv3 --pmc
+    counters (FETCH_SIZE + WRITE_SIZE, scaled by a calibration kernel of
+    known size), or None when absent or taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as fh:
             data = json.load(fh)
-        rec = data.get(f"{workload}/{precision}")
+        rec = data.get(f"{workload}/{key}")
         if not rec or rec.get("kernel_sha") != kernel_sha():
             return None
-        return float(rec["bytes_per_launch"])
-    except (OSError, ValueError, KeyError):
+        return float(rec["kernels"][kernel]["bytes_per_launch"])
+    except (OSError, ValueError, KeyError, TypeError):
         return None
 
 
@@ -206,14 +208,50 @@ def bench_single(a):
     for prec, r in results.items():
         r["speedup_vs_fp64"] = results["fp64"]["ms_per_step"] / r["ms_per_step"] if "fp64" in results else None
 
-    head = results[a.precision]
+    head_key = "fp64_separable" if (a.method == "separable" and a.precision == "fp64") else a.precision
+    head = results[head_key]
     cpu = None
     if not a.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(desc, rho)
         log(f"[bench] oracle {cpu['value']:.3e} cells/s")
-    achieved = head["synthesis_tflops"]
-    peak = PEAK[a.precision]
+
+    def dense_roofline(prec):
+        r = results[prec]
+        ach = r["synthesis_tflops"]
+        pk = PEAK[prec]
+        return {"bound": "mfma",
+                "kernel": ("gemm_nt_f64_kernel<1,...> (dense synthesis)" if prec == "fp64"
+                           else f"gemm_nt_lp_kernel<1,{prec},...> (dense synthesis)"),
+                "achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk,
+                "traffic": measured_traffic(a.workload, prec, "synthesis"),
+                "executed_products_per_mac": PRODUCTS[prec], "executed_frac": ach * PRODUCTS[prec] / pk}
+
+    if head_key == "fp64_separable":
+        # dominant single-launch kernel of the separable solve: the phi transforms
+        k = head["kernels_ms"]
+        L2 = 2 * desc["lmax"] + 1
+        cand = {
+            "phi_analysis": (k["phi_analysis"], 2.0 * M * nang * L2, 8.0 * M * nang + 8.0 * M * desc["n_theta"] * L2),
+            "phi_synthesis": (k["phi_synthesis"], 2.0 * M * nang * L2, 8.0 * M * nang + 8.0 * M * desc["n_theta"] * L2),
+        }
+        name = max(cand, key=lambda n: cand[n][0])
+        ms_k, flops_k, bytes_k = cand[name]
+        tf = flops_k / (ms_k * 1e-3) / 1e12
+        gbs = bytes_k / (ms_k * 1e-3) / 1e9
+        fm, fh = tf / PEAK["fp64"], gbs / 8000.0
+        kname = "gemm_nt_f64_grouped<" + ("0" if name == "phi_analysis" else "1") + ",...,true> (" + name + ")"
+        if fm >= fh:
+            roof = {"bound": "mfma", "kernel": kname, "achieved": tf, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                    "frac": fm, "hbm_frac": fh}
+        else:
+            roof = {"bound": "hbm", "kernel": kname, "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                    "frac": fh, "mfma_frac": fm}
+        roof["traffic"] = measured_traffic(a.workload, head_key, name)
+        roof["algorithmic_flops"] = flops_k
+        roof["algorithmic_bytes"] = bytes_k
+    else:
+        roof = dense_roofline(head_key)
     out = {
         "metric": METRIC,
         "value": head["cells_per_s"],
@@ -229,15 +267,10 @@ def bench_single(a):
         "data": "synthetic",
         "config": {"workload": a.workload, "n_r": nR, "n_theta": desc["n_theta"], "n_phi": desc["n_phi"],
                    "lmax": desc["lmax"], "cells": cells, "precision": a.precision,
-                   "max_rel_err_vs_oracle": head["max_rel_err_vs_oracle"], "plan_build_s": round(plan_s, 3),
-                   "launch": head["launch"]},
-        "roofline": {"bound": "mfma",
-                     "kernel": ("gemm_nt_f64_kernel<1,...> (synthesis)" if a.precision == "fp64"
-                                else f"gemm_nt_lp_kernel<1,{a.precision},...> (synthesis)"),
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(a.workload, a.precision),
-                     "executed_products_per_mac": PRODUCTS[a.precision],
-                     "executed_frac": achieved * PRODUCTS[a.precision] / peak},
+                   "method": "separable" if head_key == "fp64_separable" else "dense",
+                   "max_rel_err_vs_oracle": head["max_rel_err_vs_oracle"], "plan_build_s": round(plan_s, 3)},
+        "roofline": roof,
+        "roofline_dense_fp64": dense_roofline("fp64") if "fp64" in results else None,
         "kernels_ms": head["kernels_ms"],
         "precisions": results,
         "cpu_baseline": cpu,
@@ -347,8 +380,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sn_core")
     ap.add_argument("--precision", default="fp64", choices=ALL_PRECISIONS)
-    ap.add_argument("--method", default="dense", choices=("dense", "separable"),
-                    help="headline method (both are measured unless --only)")
+    ap.add_argument("--method", default="separable", choices=("dense", "separable"),
+                    help="headline method for FP64 (both are measured unless --only)")
     ap.add_argument("--only", action="store_true", help="measure the headline precision only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")

@@ -2,7 +2,7 @@
 --copy-mib MiB: reads and writes exactly that many bytes; the calibration of
 hardware byte counters) followed by a few solves of one workload.
 
-    python -m paper_1806_04593_amd.prof_driver --workload sn_core --precision fp64 --solves 3
+    python paper_1806_04593_amd/prof_driver.py --workload sn_core --precision fp64 --method separable --solves 3
 
 Run under `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE) to read the HBM
 bytes of each kernel; the calibration kernel moves exactly --copy-mib MiB each way.
@@ -20,6 +20,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="sn_core")
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--method", default="dense", choices=("dense", "separable"))
     ap.add_argument("--solves", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=512)
     a = ap.parse_args()
@@ -41,6 +42,8 @@ def main():
     rho = W.density(desc)
     g = yyg.Grid(desc, 0)
     g.prepare(a.precision)
+    if a.method == "separable":
+        g.set_method("separable")
     g.autotune(a.precision)
     d_rho = torch.from_numpy(rho).to("cuda:0")
     d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
@@ -49,7 +52,7 @@ def main():
     for _ in range(a.solves):
         g.solve(d_phi, a.precision)
     torch.cuda.synchronize()
-    print(f"[prof] {a.solves} solves of {a.workload} ({a.precision}) in {time.perf_counter() - t0:.3f} s; "
+    print(f"[prof] {a.solves} solves of {a.workload} ({a.precision}, {a.method}) in {time.perf_counter() - t0:.3f} s; "
           f"launch {g.plan_info(a.precision)}", flush=True)
     sys.stdout.flush()
 
