@@ -30,7 +30,10 @@ listed in the design notes of the repository):
 
 Array conventions: rho and phi are [2][n_R][n_theta][n_phi] (patch 0 = Yin,
 patch 1 = Yang, each in its own local coordinates); moment and radial arrays
-are indexed [patch, shell or interface, l, m].
+are indexed [patch, shell or interface, l, m].  The full-sphere spherical
+polar grid of Sect. 2 (the method before the Yin-Yang extension) is the
+single-patch case: rho and phi are [1][n_R][n_theta][n_phi] over
+theta in [0, pi], phi in [0, 2 pi], every cell counted once (no weights).
 """
 
 import math
@@ -44,6 +47,7 @@ __all__ = [
     "theta_integrals", "phi_integrals", "norm_factor", "moments",
     "radial_in_ratio", "radial_out_ratio", "radial_sums",
     "potential_at", "solve", "solve_sampled",
+    "polar_edges", "potential_polar_at", "solve_polar", "solve_polar_sampled",
 ]
 
 
@@ -442,6 +446,80 @@ def solve_sampled(r_edges, n_theta, n_phi, delta_theta, delta_phi, lmax, G, rho,
     tc = 0.5 * (th[:-1] + th[1:])
     pc = 0.5 * (ph[:-1] + ph[1:])
     vals = potential_at(UC, US, G, samples[:, 0], samples[:, 1], tc[samples[:, 2]], pc[samples[:, 3]])
+    if return_moments:
+        return vals, (AC, AS)
+    return vals
+
+
+# ---------------------------------------------------------------------------
+# Full-sphere spherical polar grid (Sect. 2): the single-patch method
+# ---------------------------------------------------------------------------
+
+def polar_edges(n_theta, n_phi):
+    """Equidistant cell edges of the spherical polar grid of Sect. 2:
+    theta in [0, pi], phi in [0, 2 pi]."""
+    theta = math.pi * np.arange(n_theta + 1) / n_theta
+    phi = 2.0 * math.pi * np.arange(n_phi + 1) / n_phi
+    return theta, phi
+
+
+def _polar_tables(n_theta, n_phi, lmax):
+    th, ph = polar_edges(n_theta, n_phi)
+    w = np.ones((n_theta, n_phi))        # each cell covers its solid angle once
+    T = theta_integrals(th, lmax)
+    C, S = phi_integrals(ph, lmax)
+    return th, ph, w, T, C, S
+
+
+def potential_polar_at(UC, US, G, n, theta, phi):
+    """Phi of Eq. (5) on the polar grid: the coefficients of Eqs. (19)-(20)
+    (interface index n, 0-based) times N^(lm) P_l^m(cos t)(cos m p, sin m p),
+    summed over l <= lmax, m <= l.  There is a single frame and no patch
+    combination.  UC, US are [1, n_R, l, m]; n, theta, phi are 1-D arrays."""
+    n = np.asarray(n)
+    theta = np.asarray(theta, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    lmax = UC.shape[2] - 1
+    N = norm_factor(lmax)
+    m = np.arange(lmax + 1)
+    P = assoc_legendre(lmax, np.cos(theta), np.sin(theta))      # [l, m, pts]
+    cm = np.cos(m[:, None] * phi[None, :])
+    sm = np.sin(m[:, None] * phi[None, :])
+    uc = np.moveaxis(UC[0, n], 0, -1)
+    us = np.moveaxis(US[0, n], 0, -1)
+    return -G * np.einsum("lm,lmx->x", N, P * (cm[None] * uc + sm[None] * us))
+
+
+def solve_polar(r_edges, n_theta, n_phi, lmax, G, rho, tables=None):
+    """Full solve on the polar grid: rho[1, n_R, n_theta, n_phi] ->
+    Phi[1, n_R, n_theta, n_phi] at the outer interfaces and the angular
+    cell midpoints.  Moments by Eqs. (21)-(22) (those of Eqs. 26-27 with
+    unit weights), radial sums by Eqs. (19)-(20), synthesis by Eq. (5)."""
+    th, ph, w, T, C, S = tables or _polar_tables(n_theta, n_phi, lmax)
+    AC, AS = moments(rho, w, T, C, S)
+    UC, US = radial_sums(AC, AS, r_edges)
+    nR = len(r_edges) - 1
+    tc = 0.5 * (th[:-1] + th[1:])
+    pc = 0.5 * (ph[:-1] + ph[1:])
+    TT, PP = np.meshgrid(tc, pc, indexing="ij")
+    tt, pp = TT.ravel(), PP.ravel()
+    out = np.zeros((1, nR, n_theta * n_phi))
+    for n in range(nR):
+        out[0, n] = potential_polar_at(UC, US, G, np.full(tt.shape, n), tt, pp)
+    return out.reshape(1, nR, n_theta, n_phi)
+
+
+def solve_polar_sampled(r_edges, n_theta, n_phi, lmax, G, rho, samples, tables=None,
+                        return_moments=False):
+    """Phi on the polar grid at selected outputs (p, n, j, k) with p = 0;
+    moments and radial sums in full, synthesis only at the samples."""
+    th, ph, w, T, C, S = tables or _polar_tables(n_theta, n_phi, lmax)
+    AC, AS = moments(rho, w, T, C, S)
+    UC, US = radial_sums(AC, AS, r_edges)
+    samples = np.asarray(samples)
+    tc = 0.5 * (th[:-1] + th[1:])
+    pc = 0.5 * (ph[:-1] + ph[1:])
+    vals = potential_polar_at(UC, US, G, samples[:, 1], tc[samples[:, 2]], pc[samples[:, 3]])
     if return_moments:
         return vals, (AC, AS)
     return vals

@@ -24,9 +24,15 @@ Workloads (all FP64, numpy PCG64 seeded):
              of width 2e6 cm, A = 1e13 g/cm^3, separated by 2e7 cm along a
              seeded direction with the pair's centre of mass at the origin.
 
+  polar_small, polar_sn_core
+             the `small` and `sn_core` recipes on the full-sphere spherical
+             polar grid (theta in [0, pi], phi in [0, 2 pi], one patch) at the
+             same angular resolution: 36 x 72 and 90 x 180 cells.
+
 The Yin patch frame is the global frame; a Yang cell with local angles
 (theta, phi) sits at the global Cartesian point (-x', z', y') where
-(x', y', z') are its local Cartesian coordinates.
+(x', y', z') are its local Cartesian coordinates.  The polar grid's frame is
+the global frame.
 """
 
 import math
@@ -36,7 +42,7 @@ from scipy import special
 
 G_CGS = 6.67430e-8
 
-WORKLOADS = ("small", "sn_core", "spheroid", "binary")
+WORKLOADS = ("small", "sn_core", "spheroid", "binary", "polar_small", "polar_sn_core")
 
 
 def grid_from_resolution(res_deg):
@@ -50,11 +56,22 @@ def grid_from_resolution(res_deg):
     return out[0][0], out[1][0], out[0][1], out[1][1]
 
 
-def make_desc(name, r_edges, res_deg, lmax, G, seed):
+def make_desc(name, r_edges, res_deg, lmax, G, seed, recipe=None):
     n_t, n_p, d_t, d_p = grid_from_resolution(res_deg)
-    return dict(name=name, r_edges=np.asarray(r_edges, dtype=np.float64),
+    return dict(name=name, kind="yinyang", patches=2, r_edges=np.asarray(r_edges, dtype=np.float64),
                 n_theta=n_t, n_phi=n_p, delta_theta=d_t, delta_phi=d_p,
-                lmax=int(lmax), G=float(G), res_deg=float(res_deg), seed=int(seed))
+                lmax=int(lmax), G=float(G), res_deg=float(res_deg), seed=int(seed),
+                recipe=recipe or name)
+
+
+def make_polar_desc(name, r_edges, res_deg, lmax, G, seed, recipe=None):
+    """Full-sphere polar grid: round(180/res) x round(360/res) cells."""
+    n_t = int(round(180.0 / res_deg))
+    n_p = int(round(360.0 / res_deg))
+    return dict(name=name, kind="polar", patches=1, r_edges=np.asarray(r_edges, dtype=np.float64),
+                n_theta=n_t, n_phi=n_p, delta_theta=0.0, delta_phi=0.0,
+                lmax=int(lmax), G=float(G), res_deg=float(res_deg), seed=int(seed),
+                recipe=recipe or name)
 
 
 def describe(name):
@@ -67,6 +84,10 @@ def describe(name):
         return make_desc(name, np.geomspace(1e5, 1e9, 551), 1.0, 40, G_CGS, 3)
     if name == "binary":
         return make_desc(name, np.geomspace(1e5, 1e10, 1001), 0.5, 64, G_CGS, 5)
+    if name == "polar_small":
+        return make_polar_desc(name, np.linspace(0.0, 1.0, 33), 5.0, 8, 1.0, 1, recipe="small")
+    if name == "polar_sn_core":
+        return make_polar_desc(name, np.geomspace(1e5, 1e9, 401), 2.0, 25, G_CGS, 2, recipe="sn_core")
     raise ValueError(f"unknown workload {name!r}")
 
 
@@ -88,6 +109,8 @@ def batch_descs(n_fields=64, seed=4):
 
 def _patch_edges(desc):
     n_t, n_p = desc["n_theta"], desc["n_phi"]
+    if desc.get("kind", "yinyang") == "polar":
+        return math.pi * np.arange(n_t + 1) / n_t, 2 * math.pi * np.arange(n_p + 1) / n_p
     d_t, d_p = desc["delta_theta"], desc["delta_phi"]
     th = (math.pi / 4 - d_t) + (math.pi / 2 + 2 * d_t) * np.arange(n_t + 1) / n_t
     ph = (-3 * math.pi / 4 - d_p) + (3 * math.pi / 2 + 2 * d_p) * np.arange(n_p + 1) / n_p
@@ -104,12 +127,16 @@ def _to_global(patch, theta, phi):
     return np.stack([-x, z, y], axis=-1)
 
 
+def n_patches(desc):
+    return 1 if desc.get("kind", "yinyang") == "polar" else 2
+
+
 def cell_directions(desc):
-    """Global unit vector of every angular cell midpoint: [2, n_theta, n_phi, 3]."""
+    """Global unit vector of every angular cell midpoint: [patches, n_theta, n_phi, 3]."""
     th, ph = _patch_edges(desc)
     tc, pc = 0.5 * (th[:-1] + th[1:]), 0.5 * (ph[:-1] + ph[1:])
     T, P = np.meshgrid(tc, pc, indexing="ij")
-    return np.stack([_to_global(0, T, P), _to_global(1, T, P)])
+    return np.stack([_to_global(p, T, P) for p in range(n_patches(desc))])
 
 
 def _real_sh(lmin, lmax, coeffs, dirs):
@@ -166,8 +193,8 @@ def _ball_fraction(desc, rng, centre=(0.1, 0.05, 0.0), radius=0.6, sub=4):
     vol_t = np.cos(t_e[:, :-1]) - np.cos(t_e[:, 1:])                 # [n_t, sub]
     p_m = ph[:-1, None] + (ph[1:] - ph[:-1])[:, None] * u[None, :]   # [n_p, sub]
     centre = np.asarray(centre)
-    out = np.zeros((2, nR, n_t, n_p))
-    for patch in range(2):
+    out = np.zeros((n_patches(desc), nR, n_t, n_p))
+    for patch in range(n_patches(desc)):
         # global directions of sub-cell angular midpoints [n_t, st, n_p, sp, 3]
         T = t_m[:, :, None, None]
         P = p_m[None, None, :, :]
@@ -190,9 +217,9 @@ def _ball_fraction(desc, rng, centre=(0.1, 0.05, 0.0), radius=0.6, sub=4):
 
 
 def density(desc):
-    """Seeded FP64 density rho[2, n_R, n_theta, n_phi] for a description made
-    by `describe` or `batch_descs`."""
-    name = desc["name"]
+    """Seeded FP64 density rho[patches, n_R, n_theta, n_phi] for a
+    description made by `describe`, `batch_descs` or the desc builders."""
+    name = desc.get("recipe", desc["name"])
     rng = np.random.default_rng(desc["seed"])
     r = desc["r_edges"]
     rc = 0.5 * (r[:-1] + r[1:])
@@ -210,8 +237,8 @@ def density(desc):
         pert = 1.0 + _real_sh(1, 20, a, dirs)
         dl = dirs @ R.T                                              # tilted frame
         stretch = np.sqrt(dl[..., 0] ** 2 + dl[..., 1] ** 2 + (dl[..., 2] / 0.7) ** 2)
-        out = np.empty((2, len(rc)) + pert.shape[1:])
-        for p in range(2):
+        out = np.empty((len(dirs), len(rc)) + pert.shape[1:])
+        for p in range(len(dirs)):
             out[p] = rho0(rc[:, None, None] * stretch[p][None]) * pert[p][None]
         return out
     if name == "binary":
@@ -220,8 +247,8 @@ def density(desc):
         sep, q, A, sig = 2e7, 0.3, 1e13, 2e6
         x1 = v * sep * q / (1.0 + q)
         x2 = -v * sep / (1.0 + q)
-        out = np.empty((2, len(rc)) + dirs.shape[1:3])
-        for p in range(2):
+        out = np.empty((len(dirs), len(rc)) + dirs.shape[1:3])
+        for p in range(len(dirs)):
             d1 = dirs[p] @ x1
             d2 = dirs[p] @ x2
             for i, rr in enumerate(rc):
