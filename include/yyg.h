@@ -12,19 +12,25 @@
  *   3. synthesis on every cell of both patches, both patches' moments
  *      contributing to each (Eqs. 5, 28-29).
  *
+ * The same plan type also runs the single-patch method on the full-sphere
+ * spherical polar grid that the paper starts from (Sect. 2, Eqs. 5, 13-22):
+ * desc.kind = YYG_GRID_POLAR.
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  * - Return value: YYG_OK (0) or a negative yyg_status.  Errors never abort
  *   the process; yyg_status_string() names them.
- * - Density and potential arrays are FP64, C order [2][n_r][n_theta][n_phi]:
- *   patch 0 (Yin) first, then patch 1 (Yang), each in its own local
- *   coordinates (identical local axes, Sect. 4).  rho[p][i][j][k] is the
+ * - Density and potential arrays are FP64, C order [P][n_r][n_theta][n_phi]
+ *   with P = 2 patches on the Yin-Yang grid: patch 0 (Yin) first, then
+ *   patch 1 (Yang), each in its own local coordinates (identical local
+ *   axes, Sect. 4); P = 1 on the polar grid.  rho[p][i][j][k] is the
  *   average over radial cell i (between r_edges[i] and r_edges[i+1]) and
  *   angular cell (j, k).  phi[p][n][j][k] is the potential at the outer
  *   interface r_edges[n+1] and at the midpoint of angular cell (j, k).
- * - Each patch covers theta in [pi/4 - delta_theta, 3pi/4 + delta_theta] and
- *   phi in [-3pi/4 - delta_phi, 3pi/4 + delta_phi] with n_theta x n_phi
- *   equal cells (Sect. 4).
+ * - Yin-Yang: each patch covers theta in [pi/4 - delta_theta, 3pi/4 +
+ *   delta_theta] and phi in [-3pi/4 - delta_phi, 3pi/4 + delta_phi] with
+ *   n_theta x n_phi equal cells (Sect. 4).  Polar: theta in [0, pi] and phi
+ *   in [0, 2pi] with n_theta x n_phi equal cells (Sect. 2).
  * - Spherical-harmonic columns are ordered q(l,0) = l*l,
  *   q(l,m,cos) = l*l + 2m - 1, q(l,m,sin) = l*l + 2m (m >= 1), so
  *   Q = (lmax+1)^2 columns.
@@ -64,14 +70,23 @@ typedef enum {
 
 #define YYG_LMAX_CAP 128
 
+/* Angular grid of a plan. */
+enum {
+  YYG_GRID_YINYANG = 0, /* two patches with overlap weights (Sect. 4)           */
+  YYG_GRID_POLAR = 1    /* one full-sphere spherical polar patch (Sect. 2)      */
+};
+
+/* Zero-initialise and fill; kind 0 is the Yin-Yang grid. */
 typedef struct {
   int n_r;                  /* radial cells, >= 1                                  */
   const double *r_edges;    /* host, n_r + 1 strictly increasing radii, r_edges[0] >= 0 */
   int n_theta, n_phi;       /* angular cells per patch, >= 1 each                  */
-  double delta_theta;       /* patch buffer widths [rad], 0 <= delta < pi/4        */
+  double delta_theta;       /* Yin-Yang patch buffer widths [rad], 0 <= delta < pi/4;
+                               must be 0 on the polar grid                          */
   double delta_phi;
   int lmax;                 /* 0 <= lmax <= YYG_LMAX_CAP                           */
   double G;                 /* gravitational constant (units of the caller)        */
+  int kind;                 /* YYG_GRID_YINYANG or YYG_GRID_POLAR                  */
 } yyg_grid_desc;
 
 typedef struct yyg_grid yyg_grid;
@@ -82,19 +97,26 @@ typedef struct yyg_batch yyg_batch;
  * w_jk (Sect. 4, Eq. 25), polar integrals T_j^(lm) (Eq. 18), azimuthal
  * integrals C_k^(m), S_k^(m) (Eqs. 14-15), radial recurrence coefficients
  * from Eqs. (16)-(17), and the synthesis bases P_l^m cos/sin(m phi) at the
- * own and at the other patch's cell midpoints (Eqs. 5, 23-24).  Host tables
- * are FP64.  Allocates device memory (about 8 n_theta n_phi (3Q) + 40 n_r Q
- * bytes); `*out` receives the handle, to be released by yyg_grid_destroy. */
+ * own and at the other patch's cell midpoints (Eqs. 5, 23-24).  On the
+ * polar grid the weights are 1 and there is no other patch.  Host tables
+ * are FP64.  Allocates device memory (about 8 n_theta n_phi (P+1) Q +
+ * 20 P n_r Q bytes); `*out` receives the handle, to be released by
+ * yyg_grid_destroy. */
 int yyg_grid_create(const yyg_grid_desc *desc, int device, yyg_grid **out);
 
-/* Same, with the patch cells derived from an angular resolution in degrees:
- * n = ceil(span/res) + 2 cells of exactly `res_deg` (span 90 deg in theta,
- * 270 deg in phi), the surplus split evenly into the two buffer widths. */
+/* Same, Yin-Yang grid with the patch cells derived from an angular
+ * resolution in degrees: n = ceil(span/res) + 2 cells of exactly `res_deg`
+ * (span 90 deg in theta, 270 deg in phi), the surplus split evenly into the
+ * two buffer widths. */
 int yyg_grid_create_res(int n_r, const double *r_edges, double res_deg, int lmax,
                         double G, int device, yyg_grid **out);
 
 /* Sizes of a plan.  Any output pointer may be NULL. */
 int yyg_grid_dims(const yyg_grid *g, int *n_r, int *n_theta, int *n_phi, int *Q);
+
+/* Grid kind (YYG_GRID_YINYANG or YYG_GRID_POLAR) and patch count P of a
+ * plan.  Either output pointer may be NULL. */
+int yyg_grid_kind(const yyg_grid *g, int *kind, int *patches);
 
 /* Build the extra tables a reduced-precision path needs (no-op for FP64):
  * the analysis and synthesis bases split into 1 (FP32), 3 (BF16) or 2
@@ -138,10 +160,11 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
 /* Debug/test export after a synchronised solve: the angular moments
  * A[p][i][q] of Eqs. (26)-(27) (A_C in cos columns, A_S in sin columns) for
  * patch p and radial cell i, unnormalised as the paper defines them.  Host
- * array of 2*n_r*Q doubles. */
+ * array of P*n_r*Q doubles. */
 int yyg_get_moments(yyg_grid *g, double *A_host);
 
-/* Overlap weights w[j][k] of the plan (Sect. 4); host array n_theta*n_phi. */
+/* Overlap weights w[j][k] of the plan (Sect. 4; all 1 on the polar grid);
+ * host array n_theta*n_phi. */
 int yyg_get_weights(const yyg_grid *g, double *w_host);
 
 /* Release a plan and its device memory (not the caller's arrays). */
@@ -150,7 +173,7 @@ int yyg_grid_destroy(yyg_grid *g);
 /* Host-only table builders, callable without a GPU (used by the CPU tests of
  * the plan logic).  `which` selects the table; `out` is a host array of
  * exactly `n` doubles:
- *   YYG_TABLE_WEIGHTS   w[j][k]                         n = n_theta*n_phi
+ *   YYG_TABLE_WEIGHTS   w[j][k] (1 on the polar grid)   n = n_theta*n_phi
  *   YYG_TABLE_THETA     T_j^(lm) (unnormalised, Eq. 18) at [j][q], the
  *                       same value in the cos and sin columns     n = n_theta*Q
  *   YYG_TABLE_PHI       C_k^(m) / S_k^(m) at [k][q] (Eqs. 14-15) n = n_phi*Q
@@ -165,6 +188,7 @@ int yyg_grid_destroy(yyg_grid *g);
  *   YYG_TABLE_CROSS     for every angular cell a = j*n_phi + k: cos theta',
  *                       sin theta', phi' of its midpoint in the other patch's
  *                       frame (Eqs. 23-24); layout [a][3]      n = 3*n_theta*n_phi
+ *                       (YYG_ERR_UNSUPPORTED on the polar grid)
  *   YYG_TABLE_ROTATION  the rotation blocks of the separable form: for each
  *                       l the (2l+1)^2 matrix D_l, row-major, blocks in
  *                       order of l, with Ybar_q(R x) = sum_q' D_l[q][q']
@@ -219,7 +243,8 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * arrays.  One batched solve is three persistent grouped launches (five
  * with the reduced-precision operand splits): all fields' analysis tiles,
  * then all radial scans, then all synthesis tiles, each launch's blocks
- * walking a device work list.  The launches, together with the copy of the
+ * walking a device work list.  Yin-Yang and polar plans may be mixed.
+ * The launches, together with the copy of the
  * per-field arguments, are recorded once into a HIP graph and replayed.
  * `grids` are borrowed and must outlive the batch; all on one device; for
  * a reduced precision every plan must be prepared for it.  The batch uses

@@ -44,6 +44,8 @@ struct DeviceGuard {
 
 struct yyg_grid {
   int device = 0;
+  int kind = YYG_GRID_YINYANG;
+  int n_patch = 2;       // patches: 2 (Yin-Yang) or 1 (polar)
   int n_r = 0, n_t = 0, n_p = 0, L = 0, Q = 0;
   double G = 1.0;
   long nang = 0, ldb = 0, ldy = 0;
@@ -56,12 +58,12 @@ struct yyg_grid {
   yyg::PatchGeom geom;
 
   double *d_Bt = nullptr;    // analysis basis [Q][ldb]
-  double *d_Y = nullptr;     // synthesis basis [nang][ldy], self | cross
+  double *d_Y = nullptr;     // synthesis basis [nang][ldy], self | cross (cross on Yin-Yang only)
   double *d_coef = nullptr;  // radial coefficients [n_r][L+1][4]
   int *d_qdeg = nullptr;     // degree l of each column
-  double *d_part = nullptr;  // split-K partial moments [nsplit][2 n_r][Q]
-  double *d_Ahat = nullptr;  // reduced moments (sqrt(N) scaled) [2 n_r][Q]
-  double *d_U = nullptr;     // synthesis operand [2 n_r][ldy]
+  double *d_part = nullptr;  // split-K partial moments [nsplit][P n_r][Q]
+  double *d_Ahat = nullptr;  // reduced moments (sqrt(N) scaled) [P n_r][Q]
+  double *d_U = nullptr;     // synthesis operand [P n_r][ldy]
   double *d_rho_owned = nullptr;
   const double *rho = nullptr;
 
@@ -117,6 +119,8 @@ namespace {
 
 int validate(const yyg_grid_desc *d) {
   if (!d || !d->r_edges) return YYG_ERR_INVALID_ARG;
+  if (d->kind != YYG_GRID_YINYANG && d->kind != YYG_GRID_POLAR) return YYG_ERR_INVALID_ARG;
+  if (d->kind == YYG_GRID_POLAR && (d->delta_theta != 0.0 || d->delta_phi != 0.0)) return YYG_ERR_INVALID_ARG;
   if (d->n_r < 1 || d->n_theta < 1 || d->n_phi < 1) return YYG_ERR_INVALID_ARG;
   if (d->lmax < 0 || d->lmax > YYG_LMAX_CAP) return YYG_ERR_INVALID_ARG;
   const double q = 0.78539816339744830962;
@@ -269,7 +273,16 @@ int sep_set_items(yyg_grid *g, int r, int v) {
   auto &S = g->sep;
   const int nt = g->n_t, nmc = 2 * g->L + 1;
   const int first[5] = {0, nt, 2 * nt + 2 * nmc, nt + nmc, nt + 2 * nmc};
-  const int count[5] = {nt, nmc, g->L + 1, nmc, nt};
+  // no rotation phase on a single-patch grid
+  const int count[5] = {nt, nmc, g->n_patch == 2 ? g->L + 1 : 0, nmc, nt};
+  S.var[r] = v;
+  if (count[r] == 0) {
+    if (S.items[r]) (void)hipFree(S.items[r]);
+    S.items[r] = nullptr;
+    S.n_items[r] = 0;
+    S.blocks[r] = 0;
+    return YYG_OK;
+  }
   int bm, bn;
   yyg::gemm_f64_variant_tile(v, &bm, &bn);
   std::vector<std::pair<int, int4>> work;
@@ -295,12 +308,12 @@ int sep_set_items(yyg_grid *g, int r, int v) {
   const long lds = 2L * (bm + bn) * 18 * 8;
   const int per_cu = (int)std::max(1L, std::min(4L, 160L * 1024 / lds));
   S.blocks[r] = std::max(1, std::min(S.n_items[r], cus * per_cu));
-  S.var[r] = v;
   return YYG_OK;
 }
 
 hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
+  if (S.n_items[r] == 0) return hipSuccess;
   const int role = r < 2 ? 2 : 3;  // general epilogue
   return yyg::launch_gemm_f64_grouped(S.var[r], role, S.probs, S.items[r], S.n_items[r], S.blocks[r], s);
 }
@@ -335,7 +348,7 @@ int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t s)
 int sep_build(yyg_grid *g) {
   auto &S = g->sep;
   const int L = g->L, Q = g->Q, nmc = 2 * L + 1, nt = g->n_t, np = g->n_p;
-  const long M = 2L * g->n_r;
+  const long M = (long)g->n_patch * g->n_r;
   S.ldk = round_up(np, 16);
   S.ldm = round_up(nmc, 16);
   S.ldj = round_up(nt, 16);
@@ -422,7 +435,7 @@ int sep_build(yyg_grid *g) {
                          S.ldl, S.V + mc, S.ldm, 0, kround(nl), 1};
     b.ldc_c = M * S.ldm;
   }
-  for (int l = 0, off = 0; l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) {
+  for (int l = 0, off = 0; g->n_patch == 2 && l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) {
     // Ut2[b][row][l] += sum_a U_other[row][l^2 + a] D_l[a][b]   (other patch's moments, rotated)
     const int d = 2 * l + 1;
     yyg::GemmF64Args &a = S.h_probs[2 * nt + 2 * nmc + l];
@@ -446,7 +459,7 @@ int sep_build(yyg_grid *g) {
 hipError_t sep_solve(yyg_grid *g, hipStream_t s) {
   auto &S = g->sep;
   const int Q = g->Q;
-  const long M = 2L * g->n_r;
+  const long M = (long)g->n_patch * g->n_r;
   hipError_t e = hipSuccess;
   int t = timing_begin(g, 4, s);
   e = sep_launch_phase(g, 0, s);
@@ -459,7 +472,7 @@ hipError_t sep_solve(yyg_grid *g, hipStream_t s) {
   if (e == hipSuccess) {
     t = timing_begin(g, 1, s);
     e = yyg::launch_radial_scan(g->d_part, 1, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, g->n_r, Q, g->L, -g->G,
-                                g->d_U, g->ldy, s);
+                                g->d_U, g->ldy, g->n_patch, s);
     timing_end(g, t, s);
   }
   if (e == hipSuccess) {
@@ -566,7 +579,7 @@ int batch_set_items(yyg_batch *b, int role, int v) {
   const int n = (int)b->grids.size();
   for (int f = 0; f < n; ++f) {
     const yyg_grid *g = b->grids[f];
-    const long M = 2L * g->n_r, N = role == 0 ? g->Q : g->nang, K = role == 0 ? g->nang : 2L * g->Q;
+    const long M = (long)g->n_patch * g->n_r, N = role == 0 ? g->Q : g->nang, K = role == 0 ? g->nang : (long)g->n_patch * g->Q;
     const int tm = (int)((M + bm - 1) / bm), tn = (int)((N + bn - 1) / bn);
     if (lp) {
       b->h_lp[role][f].tiles_m = tm;
@@ -690,34 +703,34 @@ int batch_build(yyg_batch *b) {
   for (int f = 0; f < n; ++f) {
     yyg_grid *g = b->grids[f];
     const int Q = g->Q;
-    const long M = 2L * g->n_r;
+    const long M = (long)g->n_patch * g->n_r;
     if (!lp) {
       yyg::GemmF64Args &a = b->h_f64[0][f];
       a = yyg::GemmF64Args{(int)M, Q, (int)g->nang, nullptr, g->nang, g->d_Bt, g->ldb, g->d_part, Q, 0,
                            (int)(((g->nang + 15) / 16) * 16), 1};
       yyg::GemmF64Args &c = b->h_f64[1][f];
-      c = yyg::GemmF64Args{(int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, nullptr, g->nang, 0,
-                           (int)(((2 * Q + 15) / 16) * 16), 1};
+      c = yyg::GemmF64Args{(int)M, (int)g->nang, g->n_patch * Q, g->d_U, g->ldy, g->d_Y, g->ldy, nullptr, g->nang, 0,
+                           (int)(((g->n_patch * Q + 15) / 16) * 16), 1};
     } else {
       auto &L = g->lp[b->precision - 1];
       const int bk = yyg::lp_stage_k(b->precision);
       b->h_split[0][f] = yyg::SplitArgs{nullptr, g->nang, (int)g->nang, scaled ? g->d_eA : nullptr, L.Ar, L.lda,
                                         M * L.lda};
-      b->h_split[1][f] = yyg::SplitArgs{g->d_U, g->ldy, 2 * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu, M * L.ldu};
+      b->h_split[1][f] = yyg::SplitArgs{g->d_U, g->ldy, g->n_patch * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu, M * L.ldu};
       b->h_lp[0][f] = yyg::GemmLpArgs{(int)M, Q, (int)g->nang, L.Ar, L.lda, M * L.lda, scaled ? g->d_eA : nullptr,
                                       L.Bt, L.ldb, (long)Q * L.ldb, L.eBt, g->d_part, Q, 0,
                                       (int)((g->nang + bk - 1) / bk * bk), 1};
-      b->h_lp[1][f] = yyg::GemmLpArgs{(int)M, (int)g->nang, 2 * Q, L.Ur, L.ldu, M * L.ldu,
+      b->h_lp[1][f] = yyg::GemmLpArgs{(int)M, (int)g->nang, g->n_patch * Q, L.Ur, L.ldu, M * L.ldu,
                                       scaled ? g->d_eU : nullptr, L.Y, L.ldy, (long)g->nang * L.ldy, L.eY, nullptr,
-                                      g->nang, 0, (int)((2 * Q + bk - 1) / bk * bk), 1};
+                                      g->nang, 0, (int)((g->n_patch * Q + bk - 1) / bk * bk), 1};
       for (long r = 0; r < M; ++r) {
         split_items[0].push_back(int2{f, (int)r});
         split_items[1].push_back(int2{f, (int)r});
       }
     }
     scan[f] = yyg::ScanArgs{g->d_part, 1, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, g->n_r, Q, g->L, -g->G, g->d_U,
-                            g->ldy};
-    for (int p = 0; p < 2; ++p)
+                            g->ldy, g->n_patch == 2 ? 1 : 0};
+    for (int p = 0; p < g->n_patch; ++p)
       for (int cb = 0; cb < (Q + 15) / 16; ++cb) scan_items.push_back(int4{f, cb, p, 0});
   }
   int st = upload(&b->d_scan, scan);
@@ -760,7 +773,8 @@ int yyg_host_table(const yyg_grid_desc *d, int which, double *out, size_t n) {
   if (!out) return YYG_ERR_INVALID_ARG;
   const int L = d->lmax, Q = (L + 1) * (L + 1);
   const size_t nang = (size_t)d->n_theta * d->n_phi;
-  yyg::PatchGeom g = yyg::make_patch(d->n_theta, d->n_phi, d->delta_theta, d->delta_phi);
+  yyg::PatchGeom g = d->kind == YYG_GRID_POLAR ? yyg::make_polar_patch(d->n_theta, d->n_phi)
+                                               : yyg::make_patch(d->n_theta, d->n_phi, d->delta_theta, d->delta_phi);
   try {
     switch (which) {
       case YYG_TABLE_WEIGHTS:
@@ -786,6 +800,7 @@ int yyg_host_table(const yyg_grid_desc *d, int which, double *out, size_t n) {
         return YYG_OK;
       case YYG_TABLE_CROSS:
         if (n != 3 * nang) return YYG_ERR_INVALID_ARG;
+        if (g.polar) return YYG_ERR_UNSUPPORTED;
         yyg::cross_points(g, out);
         return YYG_OK;
       case YYG_TABLE_ROTATION:
@@ -815,6 +830,8 @@ int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
   yyg_grid *g = new (std::nothrow) yyg_grid;
   if (!g) return YYG_ERR_OUT_OF_MEMORY;
   g->device = device;
+  g->kind = d->kind;
+  g->n_patch = d->kind == YYG_GRID_POLAR ? 1 : 2;
   g->n_r = d->n_r;
   g->n_t = d->n_theta;
   g->n_p = d->n_phi;
@@ -823,11 +840,12 @@ int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
   g->G = d->G;
   g->nang = (long)g->n_t * g->n_p;
   g->ldb = round_up(g->nang, 16);
-  g->ldy = round_up(2L * g->Q, 16);
+  g->ldy = round_up((long)g->n_patch * g->Q, 16);
   g->r_edges.assign(d->r_edges, d->r_edges + d->n_r + 1);
-  g->geom = yyg::make_patch(g->n_t, g->n_p, d->delta_theta, d->delta_phi);
+  g->geom = d->kind == YYG_GRID_POLAR ? yyg::make_polar_patch(g->n_t, g->n_p)
+                                      : yyg::make_patch(g->n_t, g->n_p, d->delta_theta, d->delta_phi);
   const int L = g->L, Q = g->Q, n_r = g->n_r;
-  const long M = 2L * n_r;
+  const long M = (long)g->n_patch * n_r;
   {
     int bm, bn;
     yyg::gemm_f64_variant_tile(g->var_ana, &bm, &bn);
@@ -850,8 +868,10 @@ int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
     yyg::self_legendre_table(g->geom, L, P.data());
     Tr.resize((size_t)g->n_p * Q);
     yyg::self_trig_table(g->geom, L, Tr.data());
-    Yx.resize((size_t)g->nang * Q);
-    yyg::cross_basis(g->geom, L, Yx.data());
+    if (g->n_patch == 2) {
+      Yx.resize((size_t)g->nang * Q);
+      yyg::cross_basis(g->geom, L, Yx.data());
+    }
     auto cols = yyg::column_table(L);
     auto s = yyg::norm_sqrt(L);
     g->nrm_q.resize(Q);
@@ -907,9 +927,9 @@ int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
   chk(hipMemset(g->d_U, 0, (size_t)M * g->ldy * sizeof(double)));
   chk(hipMemset(g->d_Ahat, 0, (size_t)M * Q * sizeof(double)));
   if (e == hipSuccess) chk(yyg::launch_expand_analysis_basis(d_w, d_Tt, d_CS, g->n_t, g->n_p, Q, g->d_Bt, g->ldb, 0));
-  if (e == hipSuccess) chk(yyg::launch_expand_self_basis(d_P, d_Tr, g->n_t, g->n_p, Q, g->d_Y, g->ldy, 0));
+  if (e == hipSuccess) chk(yyg::launch_expand_self_basis(d_P, d_Tr, g->n_t, g->n_p, Q, g->d_Y, g->ldy, g->n_patch * Q, 0));
   // cross part: columns [Q, 2Q) of every row
-  if (e == hipSuccess)
+  if (e == hipSuccess && g->n_patch == 2)
     chk(hipMemcpy2D(g->d_Y + Q, g->ldy * sizeof(double), Yx.data(), (size_t)Q * sizeof(double),
                     (size_t)Q * sizeof(double), g->nang, hipMemcpyHostToDevice));
   chk(hipDeviceSynchronize());
@@ -927,6 +947,8 @@ int yyg_grid_create_res(int n_r, const double *r_edges, double res_deg, int lmax
                         yyg_grid **out) {
   if (!(res_deg > 0.0) || !std::isfinite(res_deg) || res_deg > 90.0) return YYG_ERR_INVALID_ARG;
   yyg_grid_desc d;
+  std::memset(&d, 0, sizeof(d));
+  d.kind = YYG_GRID_YINYANG;
   d.n_r = n_r;
   d.r_edges = r_edges;
   yyg::dims_from_resolution(res_deg, &d.n_theta, &d.n_phi, &d.delta_theta, &d.delta_phi);
@@ -944,6 +966,13 @@ int yyg_grid_dims(const yyg_grid *g, int *n_r, int *n_theta, int *n_phi, int *Q)
   return YYG_OK;
 }
 
+int yyg_grid_kind(const yyg_grid *g, int *kind, int *patches) {
+  if (!g) return YYG_ERR_INVALID_ARG;
+  if (kind) *kind = g->kind;
+  if (patches) *patches = g->n_patch;
+  return YYG_OK;
+}
+
 int yyg_prepare(yyg_grid *g, int precision) {
   if (!g) return YYG_ERR_INVALID_ARG;
   if (precision == YYG_FP64) return YYG_OK;
@@ -953,10 +982,10 @@ int yyg_prepare(yyg_grid *g, int precision) {
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   const int Q = g->Q;
-  const long M = 2L * g->n_r;
+  const long M = (long)g->n_patch * g->n_r;
   const int parts = yyg::lp_parts(precision), eb = yyg::lp_elem_bytes(precision), bk = yyg::lp_stage_k(precision);
   L.ldb = round_up(g->nang, std::max(bk, 16));
-  L.ldy = round_up(2L * Q, std::max(bk, 16));
+  L.ldy = round_up((long)g->n_patch * Q, std::max(bk, 16));
   L.lda = L.ldb;
   L.ldu = L.ldy;
   const size_t bt_plane = (size_t)Q * L.ldb, y_plane = (size_t)g->nang * L.ldy;
@@ -984,8 +1013,8 @@ int yyg_prepare(yyg_grid *g, int precision) {
   };
   chk(yyg::launch_row_exponent(g->d_Bt, g->ldb, Q, (int)g->nang, L.eBt, 0));
   chk(yyg::launch_split_rows(precision, g->d_Bt, g->ldb, Q, (int)g->nang, L.eBt, L.Bt, L.ldb, (long)bt_plane, 0));
-  chk(yyg::launch_row_exponent(g->d_Y, g->ldy, (int)g->nang, 2 * Q, L.eY, 0));
-  chk(yyg::launch_split_rows(precision, g->d_Y, g->ldy, (int)g->nang, 2 * Q, L.eY, L.Y, L.ldy, (long)y_plane, 0));
+  chk(yyg::launch_row_exponent(g->d_Y, g->ldy, (int)g->nang, g->n_patch * Q, L.eY, 0));
+  chk(yyg::launch_split_rows(precision, g->d_Y, g->ldy, (int)g->nang, g->n_patch * Q, L.eY, L.Y, L.ldy, (long)y_plane, 0));
   chk(hipDeviceSynchronize());
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1016,7 +1045,7 @@ int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stre
   }
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
-  const size_t bytes = (size_t)2 * g->n_r * g->nang * sizeof(double);
+  const size_t bytes = (size_t)g->n_patch * g->n_r * g->nang * sizeof(double);
   if (!g->d_rho_owned) {
     int st = dmalloc(&g->d_rho_owned, bytes / sizeof(double));
     if (st != YYG_OK) return st;
@@ -1038,7 +1067,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
   if (!dg.ok) return YYG_ERR_DEVICE;
   hipStream_t s = as_stream(stream);
   const int Q = g->Q, n_r = g->n_r;
-  const long M = 2L * n_r;
+  const long M = (long)g->n_patch * n_r;
   double *out = phi;
   double *tmp = nullptr;
   if (!phi_is_device) {
@@ -1100,26 +1129,26 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
   if (e == hipSuccess) {
     t = timing_begin(g, 1, s);
     e = yyg::launch_radial_scan(g->d_part, nsplit, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, n_r, Q, g->L, -g->G,
-                                g->d_U, g->ldy, s);
+                                g->d_U, g->ldy, g->n_patch, s);
     timing_end(g, t, s);
   }
   if (e == hipSuccess && lp) {
     const auto &L = g->lp[precision - 1];
     t = timing_begin(g, 3, s);
-    if (scaled) e = yyg::launch_row_exponent(g->d_U, g->ldy, (int)M, 2 * Q, g->d_eU, s);
+    if (scaled) e = yyg::launch_row_exponent(g->d_U, g->ldy, (int)M, g->n_patch * Q, g->d_eU, s);
     if (e == hipSuccess)
-      e = yyg::launch_split_rows(precision, g->d_U, g->ldy, (int)M, 2 * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu,
+      e = yyg::launch_split_rows(precision, g->d_U, g->ldy, (int)M, g->n_patch * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu,
                                  M * L.ldu, s);
     timing_end(g, t, s);
   }
   if (e == hipSuccess) {
     t = timing_begin(g, 2, s);
     if (!lp) {
-      e = yyg::launch_gemm_nt_f64(g->var_syn, 1, (int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, out,
+      e = yyg::launch_gemm_nt_f64(g->var_syn, 1, (int)M, (int)g->nang, g->n_patch * Q, g->d_U, g->ldy, g->d_Y, g->ldy, out,
                                   g->nang, 1, 0, s);
     } else {
       const auto &L = g->lp[precision - 1];
-      e = yyg::launch_gemm_nt_lp(precision, L.var_syn, 1, (int)M, (int)g->nang, 2 * Q, L.Ur, L.ldu, M * L.ldu,
+      e = yyg::launch_gemm_nt_lp(precision, L.var_syn, 1, (int)M, (int)g->nang, g->n_patch * Q, L.Ur, L.ldu, M * L.ldu,
                                  scaled ? g->d_eU : nullptr, L.Y, L.ldy, (long)g->nang * L.ldy, L.eY, out, g->nang,
                                  1, 0, s);
     }
@@ -1142,7 +1171,7 @@ int yyg_get_moments(yyg_grid *g, double *A_host) {
   if (!g || !A_host) return YYG_ERR_INVALID_ARG;
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
-  const long M = 2L * g->n_r;
+  const long M = (long)g->n_patch * g->n_r;
   if (hipDeviceSynchronize() != hipSuccess ||
       hipMemcpy(A_host, g->d_Ahat, (size_t)M * g->Q * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
     (void)hipGetLastError();
@@ -1230,7 +1259,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   if (!dg.ok) return YYG_ERR_DEVICE;
   hipStream_t s = as_stream(stream);
   const int Q = g->Q;
-  const long M = 2L * g->n_r;
+  const long M = (long)g->n_patch * g->n_r;
   int *cur_va = lp ? &g->lp[precision - 1].var_ana : &g->var_ana;
   int *cur_sp = lp ? &g->lp[precision - 1].nsplit : &g->nsplit;
   int *cur_vs = lp ? &g->lp[precision - 1].var_syn : &g->var_syn;
@@ -1243,7 +1272,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   };
   const char *cache_path = std::getenv("YYG_TUNE_CACHE");
   auto cache = read_tune_cache(cache_path);
-  const std::string ka = tune_key(precision, 0, M, Q, g->nang), ks = tune_key(precision, 1, M, g->nang, 2L * Q);
+  const std::string ka = tune_key(precision, 0, M, Q, g->nang), ks = tune_key(precision, 1, M, g->nang, (long)g->n_patch * Q);
   int best_va = *cur_va, best_sp = *cur_sp, best_vs = *cur_vs;
   bool have_a = false, have_s = false;
   if (cache.count(ka)) {
@@ -1276,11 +1305,11 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     const auto &L = g->lp[precision - 1];
     if (scaled) {
       (void)yyg::launch_row_exponent(rho, g->nang, (int)M, (int)g->nang, g->d_eA, s);
-      (void)yyg::launch_row_exponent(g->d_U, g->ldy, (int)M, 2 * Q, g->d_eU, s);
+      (void)yyg::launch_row_exponent(g->d_U, g->ldy, (int)M, g->n_patch * Q, g->d_eU, s);
     }
     (void)yyg::launch_split_rows(precision, rho, g->nang, (int)M, (int)g->nang, scaled ? g->d_eA : nullptr, L.Ar,
                                  L.lda, M * L.lda, s);
-    (void)yyg::launch_split_rows(precision, g->d_U, g->ldy, (int)M, 2 * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu,
+    (void)yyg::launch_split_rows(precision, g->d_U, g->ldy, (int)M, g->n_patch * Q, scaled ? g->d_eU : nullptr, L.Ur, L.ldu,
                                  M * L.ldu, s);
   }
   auto ana = [&](int v, int sp) -> hipError_t {
@@ -1294,10 +1323,10 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   };
   auto syn = [&](int v) -> hipError_t {
     if (!lp)
-      return yyg::launch_gemm_nt_f64(v, 1, (int)M, (int)g->nang, 2 * Q, g->d_U, g->ldy, g->d_Y, g->ldy, tmp_out,
+      return yyg::launch_gemm_nt_f64(v, 1, (int)M, (int)g->nang, g->n_patch * Q, g->d_U, g->ldy, g->d_Y, g->ldy, tmp_out,
                                      g->nang, 1, 0, s);
     const auto &L = g->lp[precision - 1];
-    return yyg::launch_gemm_nt_lp(precision, v, 1, (int)M, (int)g->nang, 2 * Q, L.Ur, L.ldu, M * L.ldu,
+    return yyg::launch_gemm_nt_lp(precision, v, 1, (int)M, (int)g->nang, g->n_patch * Q, L.Ur, L.ldu, M * L.ldu,
                                   scaled ? g->d_eU : nullptr, L.Y, L.ldy, (long)g->nang * L.ldy, L.eY, tmp_out,
                                   g->nang, 1, 0, s);
   };
@@ -1357,6 +1386,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     }
     if (st3 == YYG_OK) st3 = sep_set_pointers(g, g->rho ? g->rho : rho_t, phi_t, s);
     for (int r = 0; r < 5 && st3 == YYG_OK; ++r) {
+      if (r == 2 && g->n_patch == 1) continue;  // no rotation phase
       double best = 1e30;
       int bv = g->sep.var[r];
       for (int v = 0; v < yyg::gemm_f64_variant_count() && st3 == YYG_OK; ++v) {
@@ -1397,7 +1427,7 @@ int yyg_plan_config(yyg_grid *g, int precision, int var_ana, int split_ana, int 
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   if (split_ana > g->part_cap) {
-    const long M = 2L * g->n_r;
+    const long M = (long)g->n_patch * g->n_r;
     double *np = nullptr;
     if (dmalloc(&np, (size_t)split_ana * M * g->Q) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
     (void)hipDeviceSynchronize();

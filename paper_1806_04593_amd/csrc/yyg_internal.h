@@ -48,6 +48,7 @@ struct ScanArgs {
   double negG;
   double *U;
   long ldu;
+  int cross;  // also write each row into the other patch's cross columns [Q, 2Q)
 };
 
 // Grouped scan over several plans (each n_r <= 1024): items = (problem,
@@ -55,15 +56,17 @@ struct ScanArgs {
 hipError_t launch_radial_scan_grouped(const ScanArgs *probs, const int4 *items, int n_items, int n_blocks,
                                       hipStream_t s);
 
+// patches = 2 (Yin-Yang: rows of patch p also land in the cross columns of
+// the other patch's rows) or 1 (polar grid: own columns only)
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
-                              const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu,
+                              const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu, int patches,
                               hipStream_t s);
 
 hipError_t launch_expand_analysis_basis(const double *w, const double *Tt, const double *CS, int n_t, int n_p,
                                         int Q, double *Bt, long ldb, hipStream_t s);
 
 hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, int n_p, int Q, double *Y, long ldy,
-                                    hipStream_t s);
+                                    int kend, hipStream_t s);
 
 // Reduced-precision contractions (prec 1 = FP32, 2 = BF16 x 3, 3 = FP16 x 2):
 // A and B as pre-split planes of the operand type ([rows][ld] each, plane

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_grouped(const Gemm
 __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
     const double *__restrict__ part, int nsplit, long split_stride, double *__restrict__ Ahat,
     const double *__restrict__ coef, const int *__restrict__ qdeg, int nR, int Q, int L, double negG,
-    double *__restrict__ U, long ldu) {
+    double *__restrict__ U, long ldu, int cross) {
   __shared__ double sI[16][64], sPa[16][64], sO[16][64], sPg[16][64];
   const int lane = threadIdx.x, w = threadIdx.y, nw = blockDim.y;
   const int q = blockIdx.x * 64 + lane;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
     O = c[2] * O + c[3] * an;
     const double v = negG * (U[(rbase + n) * ldu + q] + O);
     U[(rbase + n) * ldu + q] = v;
-    U[(rbar + n) * ldu + Q + q] = v;
+    if (cross) U[(rbar + n) * ldu + Q + q] = v;
   }
 }
 
@@ -391,7 +391,7 @@ __device__ __forceinline__ void radial_scan_block(const ScanArgs &sa, int colblo
       O = c[2] * O + c[3] * a[i + 1];
       const double v = negG * (Iv[i] + O);
       U[(rbase + n0 + i) * ldu + q] = v;
-      U[(rbar + n0 + i) * ldu + Q + q] = v;
+      if (sa.cross) U[(rbar + n0 + i) * ldu + Q + q] = v;
     }
   }
 }
@@ -429,15 +429,16 @@ __global__ void expand_analysis_basis_kernel(const double *__restrict__ w, const
 }
 
 // Ycat[a][q] = Pbar[j][q] trig[k][q] for q < Q (self-synthesis basis at the
-// patch's own cell midpoints, Eq. 5); columns >= 2Q (padding) are zeroed.
+// patch's own cell midpoints, Eq. 5); columns >= kend (padding past the
+// cross columns, or past the own columns on a single-patch grid) are zeroed.
 __global__ void expand_self_basis_kernel(const double *__restrict__ P, const double *__restrict__ Tr, int n_t,
-                                         int n_p, int Q, double *__restrict__ Y, long ldy) {
+                                         int n_p, int Q, double *__restrict__ Y, long ldy, int kend) {
   const int a = blockIdx.x;
   const int j = a / n_p, k = a % n_p;
   for (int q = threadIdx.x; q < ldy; q += blockDim.x) {
     if (q < Q)
       Y[(long)a * ldy + q] = P[(long)j * Q + q] * Tr[(long)k * Q + q];
-    else if (q >= 2 * Q)
+    else if (q >= kend)
       Y[(long)a * ldy + q] = 0.0;
   }
 }
@@ -564,19 +565,21 @@ hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const 
 }
 
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
-                              const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu,
+                              const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu, int patches,
                               hipStream_t s) {
-  ScanArgs sa{part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu};
+  if (patches != 1 && patches != 2) return hipErrorInvalidValue;
+  const int cross = patches == 2 ? 1 : 0;
+  ScanArgs sa{part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu, cross};
   if (nR <= 64 * 4) {
-    hipLaunchKernelGGL(radial_scan_kernel<4>, dim3((Q + 15) / 16, 2), dim3(16, 64), 0, s, sa);
+    hipLaunchKernelGGL(radial_scan_kernel<4>, dim3((Q + 15) / 16, patches), dim3(16, 64), 0, s, sa);
   } else if (nR <= 64 * 16) {
-    hipLaunchKernelGGL(radial_scan_kernel<16>, dim3((Q + 15) / 16, 2), dim3(16, 64), 0, s, sa);
+    hipLaunchKernelGGL(radial_scan_kernel<16>, dim3((Q + 15) / 16, patches), dim3(16, 64), 0, s, sa);
   } else {
     int nw = 16;
     while (nw > 1 && nR / nw < 8) nw >>= 1;
-    dim3 block(64, nw), grid((Q + 63) / 64, 2);
+    dim3 block(64, nw), grid((Q + 63) / 64, patches);
     hipLaunchKernelGGL(radial_scan_loop_kernel, grid, block, 0, s, part, nsplit, split_stride, Ahat, coef, qdeg, nR,
-                       Q, L, negG, U, ldu);
+                       Q, L, negG, U, ldu, cross);
   }
   return hipGetLastError();
 }
@@ -596,8 +599,8 @@ hipError_t launch_expand_analysis_basis(const double *w, const double *Tt, const
 }
 
 hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, int n_p, int Q, double *Y, long ldy,
-                                    hipStream_t s) {
-  hipLaunchKernelGGL(expand_self_basis_kernel, dim3(n_t * n_p), dim3(256), 0, s, P, Tr, n_t, n_p, Q, Y, ldy);
+                                    int kend, hipStream_t s) {
+  hipLaunchKernelGGL(expand_self_basis_kernel, dim3(n_t * n_p), dim3(256), 0, s, P, Tr, n_t, n_p, Q, Y, ldy, kend);
   return hipGetLastError();
 }
 

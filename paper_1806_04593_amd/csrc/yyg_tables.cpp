@@ -203,6 +203,18 @@ PatchGeom make_patch(int n_t, int n_p, double d_t, double d_p) {
   return g;
 }
 
+PatchGeom make_polar_patch(int n_t, int n_p) {
+  PatchGeom g;
+  g.n_t = n_t;
+  g.n_p = n_p;
+  g.polar = true;
+  g.th.resize(n_t + 1);
+  g.ph.resize(n_p + 1);
+  for (int j = 0; j <= n_t; ++j) g.th[j] = kPi * j / n_t;
+  for (int k = 0; k <= n_p; ++k) g.ph[k] = 2.0 * kPi * k / n_p;
+  return g;
+}
+
 void dims_from_resolution(double res_deg, int *n_t, int *n_p, double *d_t, double *d_p) {
   const double spans[2] = {90.0, 270.0};
   int n[2];
@@ -218,6 +230,10 @@ void dims_from_resolution(double res_deg, int *n_t, int *n_p, double *d_t, doubl
 }
 
 void overlap_weights(const PatchGeom &g, double *w) {
+  if (g.polar) {
+    std::fill(w, w + (long)g.n_t * g.n_p, 1.0);
+    return;
+  }
   Band b;
   b.c = std::cos(0.25 * kPi - g.d_t);
   b.a = std::sin(0.25 * kPi - g.d_t);

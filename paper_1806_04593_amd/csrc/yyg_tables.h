@@ -18,14 +18,18 @@ std::vector<ColInfo> column_table(int L);
 struct PatchGeom {
   int n_t = 0, n_p = 0;
   double d_t = 0, d_p = 0;
+  bool polar = false;          // full-sphere polar grid (one patch, no overlap)
   std::vector<double> th, ph;  // edges, n+1 each
 };
 PatchGeom make_patch(int n_t, int n_p, double d_t, double d_p);
+// spherical polar grid of Sect. 2: theta in [0, pi], phi in [0, 2 pi]
+PatchGeom make_polar_patch(int n_t, int n_p);
 
 // resolution rule n = ceil(span/res) + 2, buffers split the surplus
 void dims_from_resolution(double res_deg, int *n_t, int *n_p, double *d_t, double *d_p);
 
-// exact overlap weights w[j*n_p + k] (Sect. 4, Eq. 25), closed-form areas
+// exact overlap weights w[j*n_p + k] (Sect. 4, Eq. 25), closed-form areas;
+// 1 everywhere on the polar grid
 void overlap_weights(const PatchGeom &g, double *w);
 
 // Schmidt-type normalised Legendre values pbar[q-independent index lm]

@@ -19,6 +19,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x2": FP16X2}
 
 TABLE_WEIGHTS, TABLE_THETA, TABLE_PHI, TABLE_RADIAL, TABLE_CROSS, TABLE_ROTATION = 0, 1, 2, 3, 4, 5
 METHODS = {"dense": 0, "separable": 1}
+GRID_YINYANG, GRID_POLAR = 0, 1
+KINDS = {"yinyang": GRID_YINYANG, "polar": GRID_POLAR}
 
 EXPORTS = [
     "yyg_grid_create", "yyg_grid_create_res", "yyg_grid_dims", "yyg_prepare",
@@ -26,7 +28,7 @@ EXPORTS = [
     "yyg_grid_destroy", "yyg_host_table", "yyg_set_timing", "yyg_get_timing",
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
-    "yyg_batch_profile", "yyg_set_method",
+    "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind",
 ]
 
 
@@ -46,6 +48,7 @@ class GridDesc(ctypes.Structure):
         ("delta_phi", ctypes.c_double),
         ("lmax", ctypes.c_int),
         ("G", ctypes.c_double),
+        ("kind", ctypes.c_int),
     ]
 
 
@@ -66,6 +69,7 @@ def lib():
         L.yyg_grid_create.argtypes = [ctypes.POINTER(GridDesc), i, ctypes.POINTER(vp)]
         L.yyg_grid_create_res.argtypes = [i, dp, d, i, d, i, ctypes.POINTER(vp)]
         L.yyg_grid_dims.argtypes = [vp] + [ctypes.POINTER(i)] * 4
+        L.yyg_grid_kind.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
         L.yyg_prepare.argtypes = [vp, i]
         L.yyg_upload_rho.argtypes = [vp, vp, i, vp]
         L.yyg_solve.argtypes = [vp, vp, i, i, vp]
@@ -103,18 +107,22 @@ def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_desc(r_edges, n_theta, n_phi, delta_theta, delta_phi, lmax, G):
+def make_desc(r_edges, n_theta, n_phi, delta_theta, delta_phi, lmax, G, kind=GRID_YINYANG):
     r = np.ascontiguousarray(r_edges, dtype=np.float64)
     d = GridDesc(len(r) - 1, _dptr(r), int(n_theta), int(n_phi), float(delta_theta),
-                 float(delta_phi), int(lmax), float(G))
+                 float(delta_phi), int(lmax), float(G), int(KINDS.get(kind, kind)))
     d._keep = r  # keep the radii alive with the descriptor
     return d
 
 
+def _desc_of(desc):
+    return make_desc(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
+                     desc["delta_phi"], desc["lmax"], desc.get("G", 1.0), desc.get("kind", "yinyang"))
+
+
 def host_table(desc, which):
     """Host-only table builder (no GPU needed); returns a numpy array."""
-    d = make_desc(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
-                  desc["delta_phi"], desc["lmax"], desc.get("G", 1.0))
+    d = _desc_of(desc)
     Q = (desc["lmax"] + 1) ** 2
     nang = desc["n_theta"] * desc["n_phi"]
     n_r = len(desc["r_edges"]) - 1
@@ -141,8 +149,7 @@ class Grid:
     """A plan on one device: yyg_grid_create + the calls taking it."""
 
     def __init__(self, desc, device=0):
-        d = make_desc(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
-                      desc["delta_phi"], desc["lmax"], desc["G"])
+        d = _desc_of(desc)
         h = ctypes.c_void_p()
         _check(lib().yyg_grid_create(ctypes.byref(d), int(device), ctypes.byref(h)), "yyg_grid_create")
         self._h = h
@@ -151,7 +158,10 @@ class Grid:
         _check(lib().yyg_grid_dims(h, ctypes.byref(n_r), ctypes.byref(n_t), ctypes.byref(n_p), ctypes.byref(Q)),
                "yyg_grid_dims")
         self.n_r, self.n_theta, self.n_phi, self.Q = n_r.value, n_t.value, n_p.value, Q.value
-        self.shape = (2, self.n_r, self.n_theta, self.n_phi)
+        kind, patches = ctypes.c_int(), ctypes.c_int()
+        _check(lib().yyg_grid_kind(h, ctypes.byref(kind), ctypes.byref(patches)), "yyg_grid_kind")
+        self.kind, self.patches = kind.value, patches.value
+        self.shape = (self.patches, self.n_r, self.n_theta, self.n_phi)
 
     @property
     def handle(self):
@@ -209,7 +219,7 @@ class Grid:
                                      int(var_syn)), "yyg_plan_config")
 
     def moments(self):
-        out = np.zeros((2, self.n_r, self.Q))
+        out = np.zeros((self.patches, self.n_r, self.Q))
         _check(lib().yyg_get_moments(self._h, _dptr(out)), "yyg_get_moments")
         return out
 

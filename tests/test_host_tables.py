@@ -216,3 +216,37 @@ def test_rotation_blocks_rotate_the_harmonics(lmax):
         q0 = l * l
         np.testing.assert_allclose(blk @ Y[q0:q0 + dd], YR[q0:q0 + dd], atol=1e-12)
         np.testing.assert_allclose(blk @ blk.T, np.eye(dd), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# full-sphere polar grid
+# ---------------------------------------------------------------------------
+
+def test_polar_tables_match_oracle():
+    d = W.make_polar_desc("t", np.linspace(0.0, 1.0, 9), 5.0, 24, 1.0, 0)
+    assert (d["n_theta"], d["n_phi"]) == (36, 72)
+    w = yyg.host_table(d, yyg.TABLE_WEIGHTS)
+    assert np.all(w == 1.0)
+    th, ph = O.polar_edges(d["n_theta"], d["n_phi"])
+    T = yyg.host_table(d, yyg.TABLE_THETA)
+    To = O.theta_integrals(th, 24)
+    CSt = yyg.host_table(d, yyg.TABLE_PHI)
+    C, S = O.phi_integrals(ph, 24)
+    for q, (l, m, s) in enumerate(_col_lm(24)):
+        ref = To[:, l, m]
+        assert np.max(np.abs(T[:, q] - ref)) <= 1e-12 * np.max(np.abs(ref)), (l, m)
+        ref = S[:, m] if s else C[:, m]
+        assert np.max(np.abs(CSt[:, q] - ref)) < 1e-14, (l, m, s)
+
+
+def test_polar_descriptor_rules():
+    d = W.make_polar_desc("t", np.linspace(0.0, 1.0, 9), 10.0, 4, 1.0, 0)
+    with pytest.raises(yyg.YygError) as ei:
+        yyg.host_table(d, yyg.TABLE_CROSS)          # there is no other patch
+    assert ei.value.status == -5
+    for change in (dict(delta_theta=0.01), dict(delta_phi=0.02), dict(kind=7)):
+        bad = dict(d)
+        bad.update(change)
+        with pytest.raises(yyg.YygError) as ei:
+            yyg.host_table(bad, yyg.TABLE_WEIGHTS)
+        assert ei.value.status == -1, change
