@@ -72,8 +72,14 @@ def cpu_baseline(desc, rho, budget_s=20.0):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
-    w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
+    polar = desc.get("kind") == "polar"
+    P = 1 if polar else 2
+    if polar:
+        th, ph = O.polar_edges(desc["n_theta"], desc["n_phi"])
+        w = np.ones((desc["n_theta"], desc["n_phi"]))
+    else:
+        th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+        w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
     T = O.theta_integrals(th, desc["lmax"])
     C, S = O.phi_integrals(ph, desc["lmax"])
     nR = len(desc["r_edges"]) - 1
@@ -88,18 +94,21 @@ def cpu_baseline(desc, rho, budget_s=20.0):
     rows = 0
     t1 = time.perf_counter()
     rng = np.random.default_rng(0)
-    while rows < 2 * nR:
-        p, n = int(rng.integers(2)), int(rng.integers(nR))
-        O.potential_at(UC, US, desc["G"], np.full(nang, p), np.full(nang, n), tt, pp)
+    while rows < P * nR:
+        p, n = int(rng.integers(P)), int(rng.integers(nR))
+        if polar:
+            O.potential_polar_at(UC, US, desc["G"], np.full(nang, n), tt, pp)
+        else:
+            O.potential_at(UC, US, desc["G"], np.full(nang, p), np.full(nang, n), tt, pp)
         rows += 1
         if time.perf_counter() - t1 > budget_s:
             break
     t_rows = time.perf_counter() - t1
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
-    est = t_front + t_rows / rows * (2 * nR)
-    return {"value": 2 * nR * nang / est, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"{desc['name']}: full moments + radial sums, synthesis of {rows} of {2 * nR} "
+    est = t_front + t_rows / rows * (P * nR)
+    return {"value": P * nR * nang / est, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"{desc['name']}: full moments + radial sums, synthesis of {rows} of {P * nR} "
                        f"(patch, shell) rows; full-solve time extrapolated to {est:.1f} s"),
             "measured_s": round(wall, 2), "effective_cores": round(cpu / wall, 2)}
 
@@ -108,13 +117,48 @@ def sampled_error(desc, rho, phi_host, k=400, seed=123):
     import numpy as np
     import oracle as O
     nR = len(desc["r_edges"]) - 1
+    polar = desc.get("kind") == "polar"
     rng = np.random.default_rng(seed)
-    s = np.stack([rng.integers(0, 2, k), rng.integers(0, nR, k),
+    s = np.stack([rng.integers(0, 1 if polar else 2, k), rng.integers(0, nR, k),
                   rng.integers(0, desc["n_theta"], k), rng.integers(0, desc["n_phi"], k)], 1)
-    ref = O.solve_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
-                          desc["delta_phi"], desc["lmax"], desc["G"], rho, s)
+    if polar:
+        ref = O.solve_polar_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["lmax"], desc["G"], rho, s)
+    else:
+        ref = O.solve_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
+                              desc["delta_phi"], desc["lmax"], desc["G"], rho, s)
     got = phi_host[s[:, 0], s[:, 1], s[:, 2], s[:, 3]]
     return float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+
+def timed_steps(g, d_phi, prec, a):
+    """Warm-up, then the mean milliseconds of `a.steps` back-to-back solves
+    between two events on the current stream (no per-phase events)."""
+    import torch
+    for _ in range(a.warmup):
+        g.solve(d_phi, prec)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(a.steps):
+        g.solve(d_phi, prec)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / a.steps
+
+
+def phase_pass(g, d_phi, prec, a):
+    """The same solves again with the library's per-phase HIP events
+    (recorded on the solve stream around each phase's launches); returns
+    summed milliseconds and launch counts per timing slot."""
+    import torch
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    for _ in range(a.steps):
+        g.solve(d_phi, prec)
+    torch.cuda.synchronize()
+    kms, kcnt = g.timing()
+    g.set_timing(False)
+    return kms, kcnt
 
 
 def bench_single(a):
@@ -127,8 +171,9 @@ def bench_single(a):
     nR = len(desc["r_edges"]) - 1
     Q = (desc["lmax"] + 1) ** 2
     nang = desc["n_theta"] * desc["n_phi"]
-    cells = 2 * nR * nang
-    M = 2 * nR
+    P = W.n_patches(desc)
+    cells = P * nR * nang
+    M = P * nR
     log(f"[bench] workload {a.workload}: n_r={nR} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']}")
     rho = W.density(desc)
     t0 = time.perf_counter()
@@ -147,23 +192,11 @@ def bench_single(a):
             g.autotune(prec)
         tune_s = time.perf_counter() - t0
         info = g.plan_info(prec)
-        for _ in range(a.warmup):
-            g.solve(d_phi, prec)
-        torch.cuda.synchronize()
-        g.set_timing(True)
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record()
-        for _ in range(a.steps):
-            g.solve(d_phi, prec)
-        stop.record()
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(stop) / a.steps
-        kms, kcnt = g.timing()
-        g.set_timing(False)
+        ms = timed_steps(g, d_phi, prec, a)
+        kms, kcnt = phase_pass(g, d_phi, prec, a)
         avg = [float(kms[i] / max(1, kcnt[i])) for i in range(4)]
         err = None if a.no_check else sampled_error(desc, rho, d_phi.cpu().numpy())
-        flops_syn = 2.0 * M * nang * (2 * Q)
+        flops_syn = 2.0 * M * nang * (P * Q)
         achieved = flops_syn / (avg[2] * 1e-3) / 1e12
         results[prec] = {"cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
                          "kernels_ms": {"analysis": avg[0], "radial_scan": avg[1], "synthesis": avg[2],
@@ -175,20 +208,8 @@ def bench_single(a):
         g.set_method("separable")
         if not a.no_autotune:
             g.autotune("fp64")
-        for _ in range(a.warmup):
-            g.solve(d_phi, "fp64")
-        torch.cuda.synchronize()
-        g.set_timing(True)
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record()
-        for _ in range(a.steps):
-            g.solve(d_phi, "fp64")
-        stop.record()
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(stop) / a.steps
-        kms, kcnt = g.timing()
-        g.set_timing(False)
+        ms = timed_steps(g, d_phi, "fp64", a)
+        kms, kcnt = phase_pass(g, d_phi, "fp64", a)
         avg = [float(kms[i] / max(1, kcnt[i])) for i in range(8)]
         err = None if a.no_check else sampled_error(desc, rho, d_phi.cpu().numpy())
         L2 = 2 * desc["lmax"] + 1
@@ -265,7 +286,8 @@ def bench_single(a):
         "vs_baseline": None,
         "dtype": DTYPE[a.precision],
         "data": "synthetic",
-        "config": {"workload": a.workload, "n_r": nR, "n_theta": desc["n_theta"], "n_phi": desc["n_phi"],
+        "config": {"workload": a.workload, "grid": desc.get("kind", "yinyang"), "patches": P, "n_r": nR,
+                   "n_theta": desc["n_theta"], "n_phi": desc["n_phi"],
                    "lmax": desc["lmax"], "cells": cells, "precision": a.precision,
                    "method": "separable" if head_key == "fp64_separable" else "dense",
                    "max_rel_err_vs_oracle": head["max_rel_err_vs_oracle"], "plan_build_s": round(plan_s, 3)},
