@@ -217,8 +217,8 @@ def bench_single(a):
         phi_bytes = 8.0 * M * nang                # the density read / the potential written
         results["fp64_separable"] = {
             "cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
-            "kernels_ms": {"phi_analysis": avg[4], "theta_analysis": avg[5], "radial_scan": avg[1],
-                           "rotate_theta_synthesis": avg[6], "phi_synthesis": avg[7]},
+            "kernels_ms": {"phi_analysis": avg[4], "theta_analysis_rotation": avg[5], "radial_scan": avg[1],
+                           "theta_synthesis": avg[6], "phi_synthesis": avg[7]},
             "phi_synthesis_tflops": phi_flops / (avg[7] * 1e-3) / 1e12,
             "phi_synthesis_gbs": phi_bytes / (avg[7] * 1e-3) / 1e9,
             "phi_analysis_tflops": phi_flops / (avg[4] * 1e-3) / 1e12,

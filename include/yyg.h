@@ -210,7 +210,8 @@ int yyg_host_table(const yyg_grid_desc *desc, int which, double *out, size_t n);
  * every launch of yyg_solve while enabled.  Kernel slots: 0 analysis
  * contraction, 1 radial scan, 2 synthesis contraction, 3 operand
  * conversion (reduced precisions); separable form: 4 phi analysis,
- * 5 theta analysis, 6 rotation + theta synthesis, 7 phi synthesis.
+ * 5 theta analysis and the rotation of the other patch's moments,
+ * 6 theta synthesis, 7 phi synthesis (and 1 its radial scan).
  * yyg_get_timing synchronises the recorded events and returns the summed
  * milliseconds and launch counts per slot (arrays of `n_slots` entries,
  * n_slots <= 8); enabling again clears the sums. */
@@ -237,6 +238,21 @@ int yyg_plan_config(yyg_grid *g, int precision, int var_ana, int split_ana, int 
  * tile variant, its split-K factor, synthesis tile variant, analysis tile
  * rows/cols, synthesis tile rows/cols (first n entries are written). */
 int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
+
+/* Tile variant (numbered as for yyg_plan_info) of one phase of the
+ * separable form: 0 phi analysis, 1 theta analysis, 3 theta synthesis,
+ * 4 phi synthesis (phase 2, the moment rotation, has no tile).  The phi
+ * phases also take variants V, V+1, V+2 (V = the number of FP64 tile
+ * variants): a kernel that keeps the whole phi basis and a 16-, 32- or
+ * 64-row tile of its operand in LDS, available when they fit
+ * (YYG_ERR_INVALID_ARG otherwise).  Needs the separable form built
+ * (yyg_set_method); synchronises the device.  For tests and expert tuning;
+ * yyg_autotune chooses all four. */
+int yyg_sep_config(yyg_grid *g, int phase, int variant);
+
+/* variants[0..4] = the separable form's tile variant per phase (-1 for
+ * phase 2, and for every phase before the form is built). */
+int yyg_sep_info(const yyg_grid *g, int *variants, int n);
 
 /* Batched solves of several plans (uneven n_r <= 1024, angular sizes and
  * lmax allowed) for fields that each have their own density and potential

@@ -22,6 +22,9 @@ FLAGS = [
     "-shared",
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in arch VGPRs: without it, loops with few
+    # accumulator tiles copy them between VGPRs and AGPRs at every step
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -89,26 +89,33 @@ struct yyg_grid {
   int method = YYG_METHOD_DENSE;
   struct Sep {
     bool ready = false;
-    long ldk = 0, ldm = 0, ldj = 0, ldl = 0;
-    double *W = nullptr;     // phi-analysis basis [n_t][2L+1][ldk]
+    long ldk = 0, ldm = 0, ldl = 0;
+    double *CSt = nullptr;   // phi-analysis basis [2L+1][ldk]: C/S_k^(m)
+    double *w = nullptr;     // overlap weights [n_t][n_p] (scale the density as it is loaded)
     double *trig = nullptr;  // phi-synthesis basis [n_p][ldm]
-    double *T2 = nullptr;    // theta-analysis basis [mc][l][ldj]: sqrt(N) T_j^(lm)
+    double *T2 = nullptr;    // theta-analysis basis [mc][l][n_t]: sqrt(N) T_j^(lm)
     double *P2 = nullptr;    // theta-synthesis basis [mc][j][ldl]: sqrt(N) P_l^m(cos t_j)
     double *Dt = nullptr;    // transposed rotation blocks, per degree l: [b][a]
-    double *X2 = nullptr;    // phi-analysis output [mc][M][ldj]
-    double *V = nullptr;     // theta-synthesis output [n_t][M][ldm]
-    double *Ut2 = nullptr;   // own + rotated other moments [mc][M][ldl]
-    // problems: phi-ana [n_t], theta-ana [2L+1], theta-syn [2L+1], phi-syn [n_t], rotation [L+1]
+    int *dofs = nullptr;     // offset of each degree's block in Dt
+    double *X2 = nullptr;    // phi-analysis output [mc][row][j]
+    double *V = nullptr;     // theta-synthesis output [mc][row][j]
+    double *Ut = nullptr;    // potential coefficients of own + rotated other moments [mc][l][row]
+    // single-problem phases: phi analysis over the (row, j) pairs (C stored
+    // column-major, density scaled by w) and phi synthesis (A stored k-major)
+    yyg::GemmF64Args phi_ana{}, phi_syn{};
+    // grouped problems: theta analysis [2L+1], theta synthesis [2L+1]
     yyg::GemmF64Args *probs = nullptr;
-    // phases: 0 phi analysis, 1 theta analysis, 2 rotation, 3 theta synthesis, 4 phi synthesis
+    // phases: 0 phi analysis, 1 theta analysis, 2 (unused: the rotation is
+    // rotate_moments_kernel), 3 theta synthesis, 4 phi synthesis; items
+    // only for the grouped phases 1 and 3
     int4 *items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int n_items[5] = {0, 0, 0, 0, 0};
     int blocks[5] = {0, 0, 0, 0, 0};
-    int var[5] = {6, 3, 9, 3, 3};
-    int part_gen = -1;
+    // phases 0 and 4 also accept variants nv + {0, 1, 2}: the resident
+    // phi transform with 16-, 32- or 64-row tiles (nv = FP64 tile variants)
+    int var[5] = {3, 3, 0, 3, 3};
+    int cus = 256;
     std::vector<yyg::GemmF64Args> h_probs;
-    const double *rho_c = nullptr;  // pointers the problem arrays hold
-    double *phi_c = nullptr;
   } sep;
 
   bool timing = false;
@@ -150,9 +157,10 @@ void free_grid(yyg_grid *g) {
   if (g->d_eA) (void)hipFree(g->d_eA);
   if (g->d_eU) (void)hipFree(g->d_eU);
   {
-    void *b[] = {g->sep.W,        g->sep.trig,     g->sep.T2,       g->sep.P2,       g->sep.Dt,
-                 g->sep.X2,       g->sep.V,        g->sep.Ut2,      g->sep.probs,    g->sep.items[0],
-                 g->sep.items[1], g->sep.items[2], g->sep.items[3], g->sep.items[4]};
+    void *b[] = {g->sep.CSt,      g->sep.w,        g->sep.trig,     g->sep.T2,       g->sep.P2,
+                 g->sep.Dt,       g->sep.X2,       g->sep.V,        g->sep.Ut,       g->sep.probs,
+                 g->sep.items[0], g->sep.items[1], g->sep.items[2], g->sep.items[3], g->sep.items[4],
+                 g->sep.dofs};
     for (void *x : b)
       if (x) (void)hipFree(x);
   }
@@ -268,25 +276,35 @@ std::map<std::string, std::pair<int, int>> read_tune_cache(const char *path) {
 
 namespace {
 
-// Work items of separable phase r for tile variant v, largest K first.
+// Tile variant v for separable phase r; for the grouped phases (theta
+// analysis 1, theta synthesis 3) also their work items, largest K first.
+const int kPhiBM[3] = {16, 32, 64};
+
+// Whether phase r (0 or 4) can run variant v.
+bool sep_phi_variant_ok(const yyg_grid *g, int r, int v) {
+  const int nv = yyg::gemm_f64_variant_count(), nmc = 2 * g->L + 1;
+  if (v >= 0 && v < nv) return true;
+  if (v < nv || v >= nv + 3) return false;
+  return r == 0 ? yyg::phi_transform_fits(kPhiBM[v - nv], nmc, g->n_p)
+                : yyg::phi_transform_fits(kPhiBM[v - nv], g->n_p, nmc);
+}
+
 int sep_set_items(yyg_grid *g, int r, int v) {
   auto &S = g->sep;
-  const int nt = g->n_t, nmc = 2 * g->L + 1;
-  const int first[5] = {0, nt, 2 * nt + 2 * nmc, nt + nmc, nt + 2 * nmc};
-  // no rotation phase on a single-patch grid
-  const int count[5] = {nt, nmc, g->n_patch == 2 ? g->L + 1 : 0, nmc, nt};
-  S.var[r] = v;
-  if (count[r] == 0) {
-    if (S.items[r]) (void)hipFree(S.items[r]);
-    S.items[r] = nullptr;
-    S.n_items[r] = 0;
-    S.blocks[r] = 0;
+  const int nmc = 2 * g->L + 1;
+  if (r == 0 || r == 4) {
+    if (!sep_phi_variant_ok(g, r, v)) return YYG_ERR_INVALID_ARG;
+    S.var[r] = v;
     return YYG_OK;
   }
+  if (v < 0 || v >= yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
+  S.var[r] = v;
+  if (r != 1 && r != 3) return YYG_OK;
+  const int first = r == 1 ? 0 : nmc;
   int bm, bn;
   yyg::gemm_f64_variant_tile(v, &bm, &bn);
   std::vector<std::pair<int, int4>> work;
-  for (int pi = first[r]; pi < first[r] + count[r]; ++pi) {
+  for (int pi = first; pi < first + nmc; ++pi) {
     const yyg::GemmF64Args &a = S.h_probs[pi];
     const int tm = (a.M + bm - 1) / bm, tn = (a.N + bn - 1) / bn;
     for (int b = 0; b < tn; ++b)
@@ -313,35 +331,29 @@ int sep_set_items(yyg_grid *g, int r, int v) {
 
 hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
+  const int nv = yyg::gemm_f64_variant_count();
+  if (r == 0 && S.var[0] >= nv) {
+    const yyg::GemmF64Args &a = S.phi_ana;
+    yyg::PhiArgs p{a.M, a.N, a.K, a.A, a.lda, a.Aw, a.aw_mod, a.B, a.ldb, a.C, a.ldc, 0, 0};
+    return yyg::launch_phi_transform(0, kPhiBM[S.var[0] - nv], p, S.cus, s);
+  }
+  if (r == 4 && S.var[4] >= nv) {
+    const yyg::GemmF64Args &a = S.phi_syn;
+    yyg::PhiArgs p{a.M, a.N, a.K, a.A, a.lda, nullptr, 1, a.B, a.ldb, a.C, a.ldc, 0, 0};
+    return yyg::launch_phi_transform(1, kPhiBM[S.var[4] - nv], p, S.cus, s);
+  }
+  if (r == 0) return yyg::launch_gemm_f64_mode(S.var[0], yyg::kGemmCTrans | yyg::kGemmAScale, S.phi_ana, s);
+  if (r == 4) return yyg::launch_gemm_f64_mode(S.var[4], yyg::kGemmATrans, S.phi_syn, s);
   if (S.n_items[r] == 0) return hipSuccess;
-  const int role = r < 2 ? 2 : 3;  // general epilogue
-  return yyg::launch_gemm_f64_grouped(S.var[r], role, S.probs, S.items[r], S.n_items[r], S.blocks[r], s);
+  // grouped theta phases, general epilogue (the synthesis reads Ut k-major)
+  return yyg::launch_gemm_f64_grouped(S.var[r], r == 1 ? 2 : 4, S.probs, S.items[r], S.n_items[r], S.blocks[r], s);
 }
 
-// (Re)write the pointer-dependent problems (phi analysis reads the density,
-// phi synthesis writes the potential) and upload the problem array.  Waits
-// for earlier work on s: the device copy may still be in use.
-int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t s) {
-  auto &S = g->sep;
-  if (S.rho_c == rho && S.phi_c == phi && S.part_gen == g->part_gen) return YYG_OK;
-  if (hipStreamSynchronize(s) != hipSuccess) {
-    (void)hipGetLastError();
-    return YYG_ERR_DEVICE;
-  }
-  const int nt = g->n_t, nmc = 2 * g->L + 1;
-  for (int j = 0; j < nt; ++j) {
-    S.h_probs[j].A = rho + (long)j * g->n_p;
-    S.h_probs[nt + 2 * nmc + j].C = phi + (long)j * g->n_p;
-  }
-  for (int mc = 0; mc < nmc; ++mc) S.h_probs[nt + mc].C = g->d_part + mc;  // the buffer may have moved
-  if (hipMemcpy(S.probs, S.h_probs.data(), S.h_probs.size() * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice) !=
-      hipSuccess) {
-    (void)hipGetLastError();
-    return YYG_ERR_DEVICE;
-  }
-  S.rho_c = rho;
-  S.phi_c = phi;
-  S.part_gen = g->part_gen;
+// Point the phi phases at this solve's density and potential (kernel
+// arguments: nothing is copied).
+int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
+  g->sep.phi_ana.A = rho;
+  g->sep.phi_syn.C = phi;
   return YYG_OK;
 }
 
@@ -349,14 +361,16 @@ int sep_build(yyg_grid *g) {
   auto &S = g->sep;
   const int L = g->L, Q = g->Q, nmc = 2 * L + 1, nt = g->n_t, np = g->n_p;
   const long M = (long)g->n_patch * g->n_r;
+  const long MJ = M * nt;  // (row, j) pairs
   S.ldk = round_up(np, 16);
   S.ldm = round_up(nmc, 16);
-  S.ldj = round_up(nt, 16);
   S.ldl = round_up(L + 1, 16);
-  std::vector<double> W, trig, T, P, T2, P2, D;
+  std::vector<double> CSt, trig, T, P, T2, P2, D;
+  std::vector<int> dofs;
   try {
-    W.resize((size_t)nt * nmc * S.ldk);
-    yyg::separable_phi_basis(g->geom, g->w_host.data(), L, S.ldk, W.data());
+    for (int l = 0, off = 0; l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) dofs.push_back(off);
+    CSt.resize((size_t)nmc * S.ldk);
+    yyg::separable_cs(g->geom, L, S.ldk, CSt.data());
     trig.resize((size_t)np * S.ldm);
     yyg::separable_trig(g->geom, L, S.ldm, trig.data());
     T.resize((size_t)nt * Q);
@@ -364,13 +378,13 @@ int sep_build(yyg_grid *g) {
     P.resize((size_t)nt * Q);
     yyg::self_legendre_table(g->geom, L, P.data());
     // azimuthal-column-major copies for the theta GEMMs
-    T2.assign((size_t)nmc * (L + 1) * S.ldj, 0.0);
+    T2.assign((size_t)nmc * (L + 1) * nt, 0.0);
     P2.assign((size_t)nmc * nt * S.ldl, 0.0);
     for (int mc = 0; mc < nmc; ++mc) {
       const int m = (mc + 1) / 2;
       for (int l = m; l <= L; ++l)
         for (int j = 0; j < nt; ++j) {
-          T2[((size_t)mc * (L + 1) + l) * S.ldj + j] = T[(size_t)j * Q + l * l + mc];
+          T2[((size_t)mc * (L + 1) + l) * nt + j] = T[(size_t)j * Q + l * l + mc];
           P2[((size_t)mc * nt + j) * S.ldl + l] = P[(size_t)j * Q + l * l + mc];
         }
     }
@@ -386,76 +400,78 @@ int sep_build(yyg_grid *g) {
     return YYG_ERR_OUT_OF_MEMORY;
   }
   int st = YYG_OK;
-  if (st == YYG_OK) st = dmalloc(&S.W, W.size());
+  if (st == YYG_OK) st = dmalloc(&S.CSt, CSt.size());
+  if (st == YYG_OK) st = dmalloc(&S.w, (size_t)g->nang);
   if (st == YYG_OK) st = dmalloc(&S.trig, trig.size());
   if (st == YYG_OK) st = dmalloc(&S.T2, T2.size());
   if (st == YYG_OK) st = dmalloc(&S.P2, P2.size());
   if (st == YYG_OK) st = dmalloc(&S.Dt, D.size());
-  if (st == YYG_OK) st = dmalloc(&S.X2, (size_t)nmc * M * S.ldj);
-  if (st == YYG_OK) st = dmalloc(&S.V, (size_t)nt * M * S.ldm);
-  if (st == YYG_OK) st = dmalloc(&S.Ut2, (size_t)nmc * M * S.ldl);
-  if (st == YYG_OK) st = dmalloc(&S.probs, 2 * (size_t)nt + 2 * (size_t)nmc + (size_t)(L + 1));
+  if (st == YYG_OK) st = dmalloc(&S.X2, (size_t)nmc * MJ);
+  if (st == YYG_OK) st = dmalloc(&S.V, (size_t)nmc * MJ);
+  if (st == YYG_OK) st = dmalloc(&S.Ut, (size_t)nmc * (L + 1) * M);
+  if (st == YYG_OK) st = dmalloc(&S.probs, 2 * (size_t)nmc);
+  if (st == YYG_OK) st = dmalloc(&S.dofs, dofs.size());
   if (st != YYG_OK) return st;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
-  chk(hipMemcpy(S.W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.CSt, CSt.data(), CSt.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.w, g->w_host.data(), g->w_host.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.T2, T2.data(), T2.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.P2, P2.data(), P2.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.Dt, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.dofs, dofs.data(), dofs.size() * sizeof(int), hipMemcpyHostToDevice));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;
   }
-  // problems of the grouped GEMM phases (tile-independent)
   auto kround = [](long k) { return (int)((k + 15) / 16 * 16); };
-  S.h_probs.assign(2 * (size_t)nt + 2 * (size_t)nmc + (size_t)(L + 1), yyg::GemmF64Args{});
-  for (int j = 0; j < nt; ++j) {
-    // X2[mc][row][j] = sum_k rho[row][j][k] W_j[mc][k]     (rho pointer set per solve)
-    yyg::GemmF64Args &a = S.h_probs[j];
-    a = yyg::GemmF64Args{(int)M, nmc, np, nullptr, g->nang, S.W + (long)j * nmc * S.ldk, S.ldk, S.X2 + j, S.ldj, 0,
-                         kround(np), 1};
-    a.ldc_c = M * S.ldj;
-    // phi[row][j][k] = sum_mc V_j[row][mc] trig[k][mc]    (phi pointer set per solve)
-    S.h_probs[nt + 2 * nmc + j] = yyg::GemmF64Args{(int)M, np, nmc, S.V + (long)j * M * S.ldm, S.ldm, S.trig, S.ldm,
-                                                   nullptr, g->nang, 0, kround(nmc), 1};
-  }
+  // X2[mc][row*nt + j] = sum_k rho[row][j][k] w[j][k] CS_k^(mc)   (rho set per solve)
+  S.phi_ana = yyg::GemmF64Args{(int)MJ, nmc, np, nullptr, np, S.CSt, S.ldk, S.X2, MJ, 0, kround(np), 1};
+  S.phi_ana.Aw = S.w;
+  S.phi_ana.aw_mod = nt;
+  // phi[row][j][k] = sum_mc V[mc][row*nt + j] trig[k][mc]         (phi set per solve)
+  S.phi_syn = yyg::GemmF64Args{(int)MJ, np, nmc, S.V, MJ, S.trig, S.ldm, nullptr, np, 0, kround(nmc), 1};
+  S.h_probs.assign(2 * (size_t)nmc, yyg::GemmF64Args{});
   for (int mc = 0; mc < nmc; ++mc) {
     const int m = (mc + 1) / 2, nl = L + 1 - m;
     // A[row][l^2 + mc] = sum_j X2[mc][row][j] T2[mc][l][j], l >= m
-    yyg::GemmF64Args &a = S.h_probs[nt + mc];
-    a = yyg::GemmF64Args{(int)M, nl, nt, S.X2 + (long)mc * M * S.ldj, S.ldj,
-                         S.T2 + ((long)mc * (L + 1) + m) * S.ldj, S.ldj, g->d_part + mc, Q, 0, kround(nt), 1};
+    yyg::GemmF64Args &a = S.h_probs[mc];
+    a = yyg::GemmF64Args{(int)M, nl, nt, S.X2 + (long)mc * MJ, nt, S.T2 + ((long)mc * (L + 1) + m) * nt, nt,
+                         g->d_Ahat + mc, Q, 0, kround(nt), 1};
     a.c_sq = m;
-    // V[j][row][mc] = sum_{l >= m} Ut2[mc][row][l] P2[mc][j][l]
-    yyg::GemmF64Args &b = S.h_probs[nt + nmc + mc];
-    b = yyg::GemmF64Args{(int)M, nt, nl, S.Ut2 + (long)mc * M * S.ldl + m, S.ldl, S.P2 + (long)mc * nt * S.ldl + m,
-                         S.ldl, S.V + mc, S.ldm, 0, kround(nl), 1};
-    b.ldc_c = M * S.ldm;
+    // V[mc][row][j] = sum_{l >= m} Ut[mc][l][row] P2[mc][j][l]      (A stored k-major)
+    yyg::GemmF64Args &b = S.h_probs[nmc + mc];
+    b = yyg::GemmF64Args{(int)M, nt, nl, S.Ut + ((long)mc * (L + 1) + m) * M, M, S.P2 + (long)mc * nt * S.ldl + m,
+                         S.ldl, S.V + (long)mc * MJ, nt, 0, kround(nl), 1};
   }
-  for (int l = 0, off = 0; g->n_patch == 2 && l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) {
-    // Ut2[b][row][l] += sum_a U_other[row][l^2 + a] D_l[a][b]   (other patch's moments, rotated)
-    const int d = 2 * l + 1;
-    yyg::GemmF64Args &a = S.h_probs[2 * nt + 2 * nmc + l];
-    a = yyg::GemmF64Args{(int)M, d, d, g->d_U + Q + l * l, g->ldy, S.Dt + off, d, S.Ut2 + l, S.ldl, 0, kround(d), 1};
-    a.ldc_c = M * S.ldl;
-    a.c_add = 1;
+  if (hipMemcpy(S.probs, S.h_probs.data(), S.h_probs.size() * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) == hipSuccess && cus > 0)
+    S.cus = cus;
+  // default: the resident phi transforms with 32-row tiles where they fit
+  const int nv = yyg::gemm_f64_variant_count();
+  for (int r : {0, 4})
+    if (sep_phi_variant_ok(g, r, nv + 1)) S.var[r] = nv + 1;
   for (int r = 0; r < 5; ++r) {
     int st2 = sep_set_items(g, r, S.var[r]);
     if (st2 != YYG_OK) return st2;
   }
-  S.rho_c = nullptr;
-  S.phi_c = nullptr;
   S.ready = true;
   return YYG_OK;
 }
 
-// Separable solve: phi analysis, theta analysis (grouped GEMMs), radial
-// scan, rotation of the other patch's moments, theta synthesis, phi
-// synthesis (grouped GEMMs).
+// Separable solve: phi analysis (one GEMM over the (row, colatitude)
+// pairs), theta analysis (grouped GEMM per azimuthal column) into the
+// moments, the other patch's moments rotated in (Yin-Yang), radial scan
+// into the azimuthal-column-major coefficients, theta synthesis (grouped),
+// phi synthesis.
 hipError_t sep_solve(yyg_grid *g, hipStream_t s) {
   auto &S = g->sep;
   const int Q = g->Q;
@@ -464,22 +480,26 @@ hipError_t sep_solve(yyg_grid *g, hipStream_t s) {
   int t = timing_begin(g, 4, s);
   e = sep_launch_phase(g, 0, s);
   timing_end(g, t, s);
+  // the scan's input: the moments, or with two patches their rotated sum
+  const double *scan_in = g->d_Ahat;
   if (e == hipSuccess) {
     t = timing_begin(g, 5, s);
     e = sep_launch_phase(g, 1, s);
+    if (e == hipSuccess && g->n_patch == 2) {
+      e = yyg::launch_rotate_moments(g->d_Ahat, g->n_r, g->L, S.dofs, S.Dt, g->d_part, s);
+      scan_in = g->d_part;
+    }
     timing_end(g, t, s);
   }
   if (e == hipSuccess) {
     t = timing_begin(g, 1, s);
-    e = yyg::launch_radial_scan(g->d_part, 1, M * Q, g->d_Ahat, g->d_coef, g->d_qdeg, g->n_r, Q, g->L, -g->G,
-                                g->d_U, g->ldy, g->n_patch, s);
+    e = yyg::launch_radial_scan(scan_in, 1, M * Q, nullptr, g->d_coef, g->d_qdeg, g->n_r, Q, g->L, -g->G, g->d_U,
+                                g->ldy, g->n_patch, s, S.Ut);
     timing_end(g, t, s);
   }
   if (e == hipSuccess) {
     t = timing_begin(g, 6, s);
-    e = yyg::launch_scatter_moments(g->d_U, g->ldy, g->d_qdeg, (int)M, Q, S.Ut2, S.ldl, s);
-    if (e == hipSuccess) e = sep_launch_phase(g, 2, s);
-    if (e == hipSuccess) e = sep_launch_phase(g, 3, s);
+    e = sep_launch_phase(g, 3, s);
     timing_end(g, t, s);
   }
   if (e == hipSuccess) {
@@ -1094,7 +1114,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
         e = hipMemcpyAsync(phi, out, (size_t)M * g->nang * sizeof(double), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       (void)hipFree(tmp);
-      g->sep.phi_c = nullptr;  // the temporary is gone
+      g->sep.phi_syn.C = nullptr;  // the temporary is gone
     }
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -1386,10 +1406,12 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     }
     if (st3 == YYG_OK) st3 = sep_set_pointers(g, g->rho ? g->rho : rho_t, phi_t, s);
     for (int r = 0; r < 5 && st3 == YYG_OK; ++r) {
-      if (r == 2 && g->n_patch == 1) continue;  // no rotation phase
+      if (r == 2) continue;  // the rotation is not a GEMM phase
       double best = 1e30;
       int bv = g->sep.var[r];
-      for (int v = 0; v < yyg::gemm_f64_variant_count() && st3 == YYG_OK; ++v) {
+      const int nvr = yyg::gemm_f64_variant_count() + ((r == 0 || r == 4) ? 3 : 0);
+      for (int v = 0; v < nvr && st3 == YYG_OK; ++v) {
+        if ((r == 0 || r == 4) && !sep_phi_variant_ok(g, r, v)) continue;
         st3 = sep_set_items(g, r, v);
         if (st3 != YYG_OK) break;
         double t = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 3);
@@ -1403,8 +1425,8 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     (void)hipStreamSynchronize(s);
     if (phi_t) (void)hipFree(phi_t);
     if (rho_t) (void)hipFree(rho_t);
-    g->sep.rho_c = nullptr;  // the next solve writes its own pointers
-    g->sep.phi_c = nullptr;
+    g->sep.phi_ana.A = nullptr;  // the next solve writes its own pointers
+    g->sep.phi_syn.C = nullptr;
     if (st3 != YYG_OK) return st3;
   }
   if (cache_path && (!have_a || !have_s)) {
@@ -1468,6 +1490,27 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n) {
   }
   const int vals[7] = {va, sp, vs, ba, bn_a, bs, bn_s};
   for (int i = 0; i < n && i < 7; ++i) info[i] = vals[i];
+  return YYG_OK;
+}
+
+int yyg_sep_config(yyg_grid *g, int phase, int variant) {
+  if (!g || (phase != 0 && phase != 1 && phase != 3 && phase != 4)) return YYG_ERR_INVALID_ARG;
+  if (!g->sep.ready) return YYG_ERR_NOT_READY;
+  if ((phase == 0 || phase == 4) ? !sep_phi_variant_ok(g, phase, variant)
+                                 : (variant < 0 || variant >= yyg::gemm_f64_variant_count()))
+    return YYG_ERR_INVALID_ARG;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  if (hipDeviceSynchronize() != hipSuccess) {  // the work items may be in use
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  return sep_set_items(g, phase, variant);
+}
+
+int yyg_sep_info(const yyg_grid *g, int *variants, int n) {
+  if (!g || !variants || n < 1) return YYG_ERR_INVALID_ARG;
+  for (int i = 0; i < n && i < 5; ++i) variants[i] = (i == 2 || !g->sep.ready) ? -1 : g->sep.var[i];
   return YYG_OK;
 }
 

@@ -20,7 +20,20 @@ struct GemmF64Args {
   long ldc_c = 1;       // column stride of C
   int c_sq = -1;        // >= 0: column n of C lands at (n + c_sq)^2 (degree-major q index)
   int c_add = 0;        // 1: C += A.B^T instead of C = A.B^T
+  const double *Aw = nullptr;  // kGemmAScale: A(m, k) is scaled by Aw[(m % aw_mod) * lda + k]
+  int aw_mod = 1;
 };
+
+// Operand layouts of the single-problem FP64 GEMM (launch_gemm_f64_mode),
+// bit flags:
+//  kGemmATrans  A is stored k-major: element (m, k) at A[k * lda + m]
+//  kGemmCTrans  C is stored column-major: element (m, n) at C[n * ldc + m]
+//  kGemmAScale  A(m, k) is multiplied by Aw[(m % aw_mod) * lda + k] as it
+//               is loaded (row-major A only)
+enum { kGemmATrans = 2, kGemmCTrans = 4, kGemmAScale = 8 };
+// Supported combinations: kGemmCTrans | kGemmAScale (role 0) and
+// kGemmATrans (role 1).  No split-K.
+hipError_t launch_gemm_f64_mode(int variant, int mode, const GemmF64Args &g, hipStream_t s);
 
 // FP64 NT GEMM C = A . B^T in one of several tile shapes ("variants");
 // role 0 = analysis, 1 = synthesis (separate kernel symbols).
@@ -32,7 +45,8 @@ hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const 
 // Persistent grouped FP64 GEMM: n_blocks blocks walk `items` = (problem,
 // tm, tn, split) over the problems' tiles of the variant's shape.  role 0/1
 // = analysis / synthesis with the plain epilogue, 2/3 with the general one
-// (ldc_c, c_sq, c_add honoured).
+// (ldc_c, c_sq, c_add honoured), 4 = synthesis with the general epilogue
+// and A stored k-major (kGemmATrans).
 hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *probs, const int4 *items, int n_items,
                                   int n_blocks, hipStream_t s);
 
@@ -49,6 +63,8 @@ struct ScanArgs {
   double *U;
   long ldu;
   int cross;  // also write each row into the other patch's cross columns [Q, 2Q)
+  double *Ut = nullptr;  // if set: write U to Ut[mc][l][row] (q = l^2 + mc) instead
+  long ut_rows = 0;      // rows of Ut (patches x nR)
 };
 
 // Grouped scan over several plans (each n_r <= 1024): items = (problem,
@@ -58,9 +74,12 @@ hipError_t launch_radial_scan_grouped(const ScanArgs *probs, const int4 *items, 
 
 // patches = 2 (Yin-Yang: rows of patch p also land in the cross columns of
 // the other patch's rows) or 1 (polar grid: own columns only)
+// Ahat may be null (no copy of the reduced moments).  With Ut set the
+// potential coefficients go to Ut[mc][l][row] (azimuthal-column-major,
+// rows contiguous) instead of U; needs nR <= 1024.
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
                               const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu, int patches,
-                              hipStream_t s);
+                              hipStream_t s, double *Ut = nullptr);
 
 hipError_t launch_expand_analysis_basis(const double *w, const double *Tt, const double *CS, int n_t, int n_p,
                                         int Q, double *Bt, long ldb, hipStream_t s);
@@ -115,9 +134,32 @@ hipError_t launch_split_rows(int prec, const double *X, long ldx, int rows, int 
                              long ldp, long plane_stride, hipStream_t s);
 
 // Separable-form kernels (see yyg_kernels.hip).
-hipError_t launch_scatter_moments(const double *U, long ldu, const int *qdeg, int M, int Q, double *Ut, long ldl,
-                                  hipStream_t s);
+// At[row][q] = A[row][q] + the other patch's moments of the same shell
+// rotated degree by degree (rows: 2 nR, Yin then Yang); dofs[l] = offset of
+// the transposed rotation block of degree l in Dt.
+hipError_t launch_rotate_moments(const double *A, int nR, int L, const int *dofs, const double *Dt, double *At,
+                                 hipStream_t s);
 int gemm_f64_variant_threads(int v);
+
+// Phi transforms with B and a BM-row tile of A resident in LDS (see
+// phi_transform_kernel).  role 0: C[n*ldc + m] = sum_k A[m*K + k]
+// w[(m % w_mod)*K + k] B[n*ldb + k]; role 1: C[m*ldc + n] = sum_k
+// A[k*lda + m] B[n*ldb + k].  BM in {16, 32, 64}; `blocks` persistent blocks
+// (at most one per tile).  phi_transform_fits tells whether the shape fits.
+struct PhiArgs {
+  int M, N, K;
+  const double *A;
+  long lda;
+  const double *w;
+  long w_mod;
+  const double *B;
+  long ldb;
+  double *C;
+  long ldc;
+  int ldk, npad;  // set by the launcher
+};
+bool phi_transform_fits(int BM, int N, int K);
+hipError_t launch_phi_transform(int role, int BM, PhiArgs a, int blocks, hipStream_t s);
 
 // Split-K factor for an output of `tiles` block tiles and K columns.
 int choose_split(long tiles, long K);

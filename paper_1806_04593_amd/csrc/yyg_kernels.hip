@@ -14,6 +14,8 @@
 //    self-synthesis bases from their FP64 factors.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "yyg_internal.h"
 
 namespace yyg {
@@ -22,7 +24,19 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
+// x where keep holds, else 0, as an FP multiply by 1 or 0: the compiler
+// cannot move the load of x under a branch on keep (x * 0 is NaN for a
+// non-finite x), so the loads of a loop stay unconditional and in flight
+// together.  x must be finite: it is read from a clamped, valid address.
+__device__ __forceinline__ double keep_if(bool keep, double x) { return x * (keep ? 1.0 : 0.0); }
+
 constexpr int kBK = 16, kPad = 2, kLDK = kBK + kPad;
+// Stages of A and B held in registers ahead of the LDS stage being
+// multiplied: a stage's global loads are issued kPF stages before its LDS
+// store.  Measured on MI355X, deeper prefetch (3) cost occupancy and made
+// the long-K contractions ~10% slower without speeding up the short-K ones,
+// so one stage it is.
+constexpr int kPF = 1;
 
 // Logical tile of a block so that the blocks one XCD receives (the hardware
 // hands blocks to the 8 XCDs round-robin) form a contiguous run of tiles in
@@ -37,10 +51,17 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 
 // Block tile BM x BN, WGM x WGN waves, each wave a (BM/WGM) x (BN/WGN) grid
 // of 16 x 16 MFMA tiles; computes output tile (tm, tn) over split z.
-// GEN selects the general epilogue (column stride, degree-major column
-// index, accumulate); the plain one writes C[row * ldc + col].
-template <int BM, int BN, int WGM, int WGN, bool GEN>
+// MODE bit 1 selects the general epilogue (column stride, degree-major
+// column index, accumulate); the plain one writes C[row * ldc + col].  The
+// other bits (kGemmATrans, kGemmCTrans, kGemmAScale) change the operand
+// layouts as documented with GemmF64Args.
+template <int BM, int BN, int WGM, int WGN, int MODE>
 __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int tn, int z) {
+  constexpr bool GEN = (MODE & 1) != 0;
+  constexpr bool AT = (MODE & kGemmATrans) != 0;
+  constexpr bool CT = (MODE & kGemmCTrans) != 0;
+  constexpr bool AW = (MODE & kGemmAScale) != 0;
+  static_assert(!(AT && AW), "scaled A is row-major");
   const int M = g.M, N = g.N, K = g.K;
   const double *__restrict__ A = g.A;
   const double *__restrict__ B = g.B;
@@ -52,7 +73,9 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   // Stage loads.  When a thread's share of a tile stage divides the 16-wide
   // stage, it reads one contiguous run of k in one row (one row pointer);
   // otherwise element e = tid + i*NT sits at row e / 16, column e % 16.
-  constexpr bool RUN_A = (BM * kBK) % NT == 0 && kBK % ((BM * kBK) / NT) == 0;
+  // A stored k-major loads along m instead: element e = tid + i*NT at
+  // k = e / BM, m = e % BM.
+  constexpr bool RUN_A = !AT && (BM * kBK) % NT == 0 && kBK % ((BM * kBK) / NT) == 0;
   constexpr bool RUN_B = (BN * kBK) % NT == 0 && kBK % ((BN * kBK) / NT) == 0;
   constexpr int EA = RUN_A ? (BM * kBK) / NT : (BM * kBK + NT - 1) / NT;
   constexpr int EB = RUN_B ? (BN * kBK) / NT : (BN * kBK + NT - 1) / NT;
@@ -73,47 +96,71 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  double ra[EA], rb[EB];
+  constexpr int PF = NT > 256 ? 1 : kPF;
+  double ra[PF][EA], rb[PF][EB];
   // run mapping: this thread's row and first column
   const int arow = RUN_A ? tid / (kBK / EA) : 0, acol = RUN_A ? (tid % (kBK / EA)) * EA : 0;
   const int brow = RUN_B ? tid / (kBK / EB) : 0, bcol = RUN_B ? (tid % (kBK / EB)) * EB : 0;
   const double *pa = A + (long)min(m0 + arow, M - 1) * lda;
+  const double *pw = AW ? g.Aw + (long)(min(m0 + arow, M - 1) % g.aw_mod) * lda : nullptr;
   const double *pb = B + (long)min(n0 + brow, N - 1) * ldb;
   const bool va = m0 + arow < M, vb = n0 + brow < N;
-  auto load = [&](int k0) {
+  auto load = [&](double (&ra)[EA], double (&rb)[EB], int k0) {
+    // Every load reads a clamped, valid address and is masked afterwards:
+    // a load under a condition is waited for before the next one issues,
+    // while unconditional ones are all in flight together.
     if constexpr (RUN_A) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
-        const int kk = k0 + acol + i;
-        ra[i] = (va && kk < kend) ? pa[kk] : 0.0;
+        const int kk = k0 + acol + i, kc = min(kk, K - 1);
+        double v = pa[kc];
+        if constexpr (AW) v *= pw[kc];
+        ra[i] = keep_if(va && kk < kend, v);
+      }
+    } else if constexpr (AT) {
+#pragma unroll
+      for (int i = 0; i < EA; ++i) {
+        const int e = tid + i * NT, kk = k0 + e / BM, gm = m0 + e % BM;
+        const double v = A[(long)min(kk, K - 1) * lda + min(gm, M - 1)];
+        ra[i] = keep_if(e < BM * kBK && gm < M && kk < kend, v);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        const int gr = m0 + row;
-        ra[i] = (e < BM * kBK && gr < M && kk < kend) ? A[(long)gr * lda + kk] : 0.0;
+        const int gr = m0 + row, grc = min(gr, M - 1), kc = min(kk, K - 1);
+        double v = A[(long)grc * lda + kc];
+        if constexpr (AW) v *= g.Aw[(long)(grc % g.aw_mod) * lda + kc];
+        ra[i] = keep_if(e < BM * kBK && gr < M && kk < kend, v);
       }
     }
     if constexpr (RUN_B) {
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
         const int kk = k0 + bcol + i;
-        rb[i] = (vb && kk < kend) ? pb[kk] : 0.0;
+        const double v = pb[min(kk, K - 1)];
+        rb[i] = keep_if(vb && kk < kend, v);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
         const int gr = n0 + row;
-        rb[i] = (e < BN * kBK && gr < N && kk < kend) ? B[(long)gr * ldb + kk] : 0.0;
+        const double v = B[(long)min(gr, N - 1) * ldb + min(kk, K - 1)];
+        rb[i] = keep_if(e < BN * kBK && gr < N && kk < kend, v);
       }
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const double (&ra)[EA], const double (&rb)[EB], int buf) {
     if constexpr (RUN_A) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) As[buf][arow * kLDK + acol + i] = ra[i];
+    } else if constexpr (AT) {
+#pragma unroll
+      for (int i = 0; i < EA; ++i) {
+        const int e = tid + i * NT;
+        if (e < BM * kBK) As[buf][(e % BM) * kLDK + e / BM] = ra[i];
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
@@ -133,32 +180,22 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
     }
   };
 
-  const int nk = (kend - kbeg + kBK - 1) / kBK;
-  if (nk > 0) {
-    load(kbeg);
-    stash(0);
-  }
-  __syncthreads();
-
   const int frow = lane & 15, fk = 4 * (lane >> 4);
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    const bool more = it + 1 < nk;
-    if (more) load(kbeg + (it + 1) * kBK);
+  auto compute = [&](int buf) {
     // Each lane holds four consecutive k of its row; MFMA step s uses the
     // s-th of them, so the four steps cover the 16 k of the stage once.
     double af[TI][4], bf[TJ][4];
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
-      const double *s = &As[buf][(wm * (BM / WGM) + i * 16 + frow) * kLDK + fk];
+      const double *sp = &As[buf][(wm * (BM / WGM) + i * 16 + frow) * kLDK + fk];
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) af[i][s4] = s[s4];
+      for (int s4 = 0; s4 < 4; ++s4) af[i][s4] = sp[s4];
     }
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
-      const double *s = &Bs[buf][(wn * (BN / WGN) + j * 16 + frow) * kLDK + fk];
+      const double *sp = &Bs[buf][(wn * (BN / WGN) + j * 16 + frow) * kLDK + fk];
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) bf[j][s4] = s[s4];
+      for (int s4 = 0; s4 < 4; ++s4) bf[j][s4] = sp[s4];
     }
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4)
@@ -167,8 +204,30 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
         for (int j = 0; j < TJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
-    if (more) stash(buf ^ 1);
-    __syncthreads();
+  };
+
+  const int nk = (kend - kbeg + kBK - 1) / kBK;
+#pragma unroll
+  for (int p = 0; p < PF; ++p)
+    if (p < nk) load(ra[p], rb[p], kbeg + p * kBK);
+  if (nk > 0) stash(ra[0], rb[0], 0);
+  __syncthreads();
+
+  // Stage `it` sits in LDS buffer it & 1 and register slot it % PF; the
+  // loop is unrolled by PF so that every slot index is a constant.  With
+  // PF = 1 the stage loaded this iteration is the one stored after it.
+  for (int base = 0; base < nk; base += PF) {
+#pragma unroll
+    for (int sl = 0; sl < PF; ++sl) {
+      const int it = base + sl;
+      if (it < nk) {  // uniform across the block
+        const int buf = it & 1;
+        if (it + PF < nk) load(ra[sl], rb[sl], kbeg + (it + PF) * kBK);
+        compute(buf);
+        if (it + 1 < nk) stash(ra[(sl + 1) % PF], rb[(sl + 1) % PF], buf ^ 1);
+        __syncthreads();
+      }
+    }
   }
 
   // D layout of the 16x16x4 f64 MFMA: lane l, element r -> row l/16 + 4r,
@@ -187,6 +246,8 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
             const long cc = g.c_sq < 0 ? (long)col * g.ldc_c : (long)(col + g.c_sq) * (col + g.c_sq);
             double *c = &C[(long)row * ldc + cc];
             *c = g.c_add ? *c + acc[i][j][r] : acc[i][j][r];
+          } else if constexpr (CT) {
+            C[(long)col * ldc + row] = acc[i][j][r];
           } else {
             C[(long)row * ldc + col] = acc[i][j][r];
           }
@@ -198,21 +259,21 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 
 // ROLE only separates the analysis (0) and synthesis (1) instantiations so
 // that profilers list them apart.
-template <int ROLE, int BM, int BN, int WGM, int WGN>
+template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE = 0>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(GemmF64Args g, int tiles_total) {
   const int tile = xcd_tile(blockIdx.x, tiles_total);
-  gemm_f64_tile<BM, BN, WGM, WGN, false>(g, tile % g.tiles_m, tile / g.tiles_m, blockIdx.y);
+  gemm_f64_tile<BM, BN, WGM, WGN, MODE>(g, tile % g.tiles_m, tile / g.tiles_m, blockIdx.y);
 }
 
 // Persistent grouped form: blocks walk a list of (problem, tm, tn, split)
 // work items over several independent contractions of one phase.
-template <int ROLE, int BM, int BN, int WGM, int WGN, bool GEN>
+template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_grouped(const GemmF64Args *__restrict__ probs,
                                                                       const int4 *__restrict__ items, int n_items) {
   for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
     const int4 it = items[w];
     __syncthreads();  // the previous item's LDS reads are done
-    gemm_f64_tile<BM, BN, WGM, WGN, GEN>(probs[it.x], it.y, it.z, it.w);
+    gemm_f64_tile<BM, BN, WGM, WGN, MODE>(probs[it.x], it.y, it.z, it.w);
   }
 }
 
@@ -229,7 +290,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_grouped(const Gemm
 __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
     const double *__restrict__ part, int nsplit, long split_stride, double *__restrict__ Ahat,
     const double *__restrict__ coef, const int *__restrict__ qdeg, int nR, int Q, int L, double negG,
-    double *__restrict__ U, long ldu, int cross) {
+    double *__restrict__ U, long ldu, int cross, double *__restrict__ Ut, long ut_rows) {
   __shared__ double sI[16][64], sPa[16][64], sO[16][64], sPg[16][64];
   const int lane = threadIdx.x, w = threadIdx.y, nw = blockDim.y;
   const int q = blockIdx.x * 64 + lane;
@@ -243,6 +304,13 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
   const long rbar = (long)(1 - p) * nR;
   const double *cf = coef + (long)l * 4;
   const long cstride = (long)(L + 1) * 4;
+  // reduced moments for the later passes: the copy in Ahat, or the single
+  // partial buffer itself when no copy is kept (nsplit == 1 then)
+  const double *__restrict__ Ared = Ahat ? Ahat : part;
+  // where I_n, then U_n, of this column are kept
+  auto dst = [&](int n) -> double * {
+    return Ut ? Ut + ((long)(qq - l * l) * (L + 1) + l) * ut_rows + rbase + n : U + (rbase + n) * ldu + qq;
+  };
 
   double I = 0.0, Pa = 1.0;
   if (ok) {
@@ -251,7 +319,7 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
       const long row = rbase + n;
       double a = 0.0;
       for (int z = 0; z < nsplit; ++z) a += part[z * split_stride + row * Q + qq];
-      Ahat[row * Q + qq] = a;
+      if (Ahat) Ahat[row * Q + qq] = a;
       const double *c = cf + n * cstride;
       I = c[0] * I + c[1] * a;
       Pa *= c[0];
@@ -263,7 +331,7 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
 #pragma unroll 4
     for (int n = n1 - 1; n >= n0; --n) {
       const double *c = cf + n * cstride;
-      const double an = (n + 1 < nR) ? Ahat[(rbase + n + 1) * Q + qq] : 0.0;
+      const double an = (n + 1 < nR) ? Ared[(rbase + n + 1) * Q + qq] : 0.0;
       O = c[2] * O + c[3] * an;
       Pg *= c[2];
     }
@@ -282,18 +350,18 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
 #pragma unroll 4
   for (int n = n0; n < n1; ++n) {
     const double *c = cf + n * cstride;
-    I = c[0] * I + c[1] * Ahat[(rbase + n) * Q + q];
-    U[(rbase + n) * ldu + q] = I;
+    I = c[0] * I + c[1] * Ared[(rbase + n) * Q + q];
+    *dst(n) = I;
   }
   O = Oin;
 #pragma unroll 4
   for (int n = n1 - 1; n >= n0; --n) {
     const double *c = cf + n * cstride;
-    const double an = (n + 1 < nR) ? Ahat[(rbase + n + 1) * Q + q] : 0.0;
+    const double an = (n + 1 < nR) ? Ared[(rbase + n + 1) * Q + q] : 0.0;
     O = c[2] * O + c[3] * an;
-    const double v = negG * (U[(rbase + n) * ldu + q] + O);
-    U[(rbase + n) * ldu + q] = v;
-    if (cross) U[(rbar + n) * ldu + Q + q] = v;
+    const double v = negG * (*dst(n) + O);
+    *dst(n) = v;
+    if (cross && !Ut) U[(rbar + n) * ldu + Q + q] = v;
   }
 }
 
@@ -329,37 +397,71 @@ __device__ __forceinline__ void radial_scan_block(const ScanArgs &sa, int colblo
   const long cstride = (long)(L + 1) * 4;
 
   // a[i] = A at radius n0 + i, i <= len (the element past the chunk feeds
-  // the outer recurrence); zero beyond the grid.
+  // the outer recurrence); zero beyond the grid.  Every load goes to a
+  // clamped, valid address and is masked afterwards, so that all of a
+  // thread's loads are in flight together (a conditional load would be
+  // waited for before the next one is issued).
   double a[CMAX + 1];
 #pragma unroll
-  for (int i = 0; i <= CMAX; ++i) {
-    double v = 0.0;
-    if (ok && i <= len && n0 + i < nR) {
-      const long off = (rbase + n0 + i) * Q + qq;
-      for (int zz = 0; zz < nsplit; ++zz) v += part[zz * split_stride + off];
+  for (int i = 0; i <= CMAX; ++i) a[i] = 0.0;
+  for (int zz = 0; zz < nsplit; ++zz) {
+    const double *__restrict__ pz = part + zz * split_stride + rbase * Q + qq;
+    // batches of 8 loads, all in flight before the first use
+#pragma unroll
+    for (int h0 = 0; h0 <= CMAX; h0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (h0 + u <= CMAX) t[u] = pz[(long)min(n0 + h0 + u, nR - 1) * Q];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (h0 + u <= CMAX) a[h0 + u] += keep_if(h0 + u <= len && n0 + h0 + u < nR, t[u]);
     }
-    a[i] = v;
   }
-  if (ok) {
+  // This thread's recurrence coefficients, clamped the same way, fetched
+  // H rows at a time (pair o, o+1 of the four per row) with all loads of a
+  // batch in flight together.
+  constexpr int H = CMAX < 8 ? CMAX : (CMAX > 8 ? 4 : 8);  // fewer in flight at CMAX 16: registers
+  auto coef_pair = [&](int h, int o, double (&x)[H], double (&y)[H]) {
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const double *c = cf + (long)min(n0 + h * H + u, nR - 1) * cstride;
+      x[u] = c[o];
+      y[u] = c[o + 1];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  if (ok && Ahat) {
 #pragma unroll
     for (int i = 0; i < CMAX; ++i)
       if (i < len) Ahat[(rbase + n0 + i) * Q + qq] = a[i];
   }
   double I = 0.0, Pa = 1.0, O = 0.0, Pg = 1.0;
 #pragma unroll
-  for (int i = 0; i < CMAX; ++i) {
-    if (i < len) {
-      const double *c = cf + (n0 + i) * cstride;
-      I = c[0] * I + c[1] * a[i];
-      Pa *= c[0];
+  for (int h = 0; h < CMAX / H; ++h) {
+    double c0[H], c1[H];
+    coef_pair(h, 0, c0, c1);
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const int i = h * H + u;
+      if (i < len) {
+        I = c0[u] * I + c1[u] * a[i];
+        Pa *= c0[u];
+      }
     }
   }
 #pragma unroll
-  for (int i = CMAX - 1; i >= 0; --i) {
-    if (i < len) {
-      const double *c = cf + (n0 + i) * cstride;
-      O = c[2] * O + c[3] * a[i + 1];
-      Pg *= c[2];
+  for (int h = CMAX / H - 1; h >= 0; --h) {
+    double c2[H], c3[H];
+    coef_pair(h, 2, c2, c3);
+#pragma unroll
+    for (int u = H - 1; u >= 0; --u) {
+      const int i = h * H + u;
+      if (i < len) {
+        O = c2[u] * O + c3[u] * a[i + 1];
+        Pg *= c2[u];
+      }
     }
   }
   sI[y][x] = I;
@@ -375,29 +477,43 @@ __device__ __forceinline__ void radial_scan_block(const ScanArgs &sa, int colblo
   double Iv[CMAX];
   I = Iin;
 #pragma unroll
-  for (int i = 0; i < CMAX; ++i) {
-    if (i < len) {
-      const double *c = cf + (n0 + i) * cstride;
-      I = c[0] * I + c[1] * a[i];
+  for (int h = 0; h < CMAX / H; ++h) {
+    double c0[H], c1[H];
+    coef_pair(h, 0, c0, c1);
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const int i = h * H + u;
+      if (i < len) I = c0[u] * I + c1[u] * a[i];
+      Iv[i] = I;
     }
-    Iv[i] = I;
   }
   const long rbar = (long)(1 - p) * nR;
+  // azimuthal-column-major output: Ut[mc][l][row], rows contiguous
+  double *__restrict__ ut = sa.Ut ? sa.Ut + ((long)(q - l * l) * (L + 1) + l) * sa.ut_rows : nullptr;
   O = Oin;
 #pragma unroll
-  for (int i = CMAX - 1; i >= 0; --i) {
-    if (i < len) {
-      const double *c = cf + (n0 + i) * cstride;
-      O = c[2] * O + c[3] * a[i + 1];
-      const double v = negG * (Iv[i] + O);
-      U[(rbase + n0 + i) * ldu + q] = v;
-      if (sa.cross) U[(rbar + n0 + i) * ldu + Q + q] = v;
+  for (int h = CMAX / H - 1; h >= 0; --h) {
+    double c2[H], c3[H];
+    coef_pair(h, 2, c2, c3);
+#pragma unroll
+    for (int u = H - 1; u >= 0; --u) {
+      const int i = h * H + u;
+      if (i < len) {
+        O = c2[u] * O + c3[u] * a[i + 1];
+        const double v = negG * (Iv[i] + O);
+        if (ut) {
+          ut[rbase + n0 + i] = v;
+        } else {
+          U[(rbase + n0 + i) * ldu + q] = v;
+          if (sa.cross) U[(rbar + n0 + i) * ldu + Q + q] = v;
+        }
+      }
     }
   }
 }
 
 template <int CMAX>
-__global__ __launch_bounds__(1024) void radial_scan_kernel(ScanArgs sa) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4))) void radial_scan_kernel(ScanArgs sa) {
   radial_scan_block<CMAX>(sa, blockIdx.x, blockIdx.y);
 }
 
@@ -446,22 +562,259 @@ __global__ void expand_self_basis_kernel(const double *__restrict__ P, const dou
 // ---------------------------------------------------------------------------
 // Separable form.  The analysis basis factors as T_j^(lm) x (w_jk C/S_k^(m))
 // and the self-synthesis basis as P_l^m(cos t_j) x cos/sin(m phi_k), so each
-// contraction splits into a transform over phi (a GEMM per colatitude row j)
-// and one over theta (a GEMM per azimuthal column mc), both run as grouped
-// launches of gemm_f64_tile.  The other patch's moments enter the synthesis
-// rotated into this patch's frame, degree by degree (kernel below).
+// contraction splits into a transform over phi (one GEMM over all (row, j)
+// pairs) and one over theta (a grouped GEMM, one problem per azimuthal
+// column mc).  The other patch's moments enter the synthesis rotated into
+// this patch's frame, degree by degree (kernel below).
 // Azimuthal column mc: 0 for m = 0, 2m-1 (cos) / 2m (sin); q = l^2 + mc.
 
-// Ut[mc][row][l] = U[row][l^2 + mc]: own moments in azimuthal-column-major
-// order; the rotated moments of the other patch are added by grouped GEMMs
-// (one per degree l, with the transposed rotation block).
-__global__ void scatter_moments_kernel(const double *__restrict__ U, long ldu, const int *__restrict__ qdeg, int Q,
-                                       long M, double *__restrict__ Ut, long ldl) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const long row = blockIdx.y;
-  if (q >= Q) return;
-  const int l = qdeg[q];
-  Ut[((long)(q - l * l) * M + row) * ldl + l] = U[row * ldu + q];
+// Own moments plus the other patch's moments rotated into this patch's
+// frame, for every row (patch p, shell n) and degree-l column block:
+//   At[row][l^2 + b] = A[row][l^2 + b] + sum_a A[row'][l^2 + a] Dt_l[b][a],
+// row' = the other patch's row of the same shell, Dt_l the transposed
+// rotation block of degree l (d = 2l + 1 values per row, at dofs[l]).
+// The radial recurrences act on every column of degree l alike, so rotating
+// the moments before the scan equals rotating its output.  Block = one
+// degree, a 64-wide chunk of b and 64 rows; the a-sum runs over 32-wide
+// chunks staged in LDS (the rotation block and the other patch's moments);
+// each thread accumulates 4 rows x 4 columns, so an LDS read feeds 2 FMAs.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void rotate_moments_kernel(const double *__restrict__ A, int nR, int Q,
+                                                            const int *__restrict__ dofs,
+                                                            const double *__restrict__ Dt,
+                                                            double *__restrict__ At) {
+  constexpr int RB = 64, BC = 64, AC = 32;
+  __shared__ double sA[RB][AC + 1];
+  __shared__ double sD[AC][BC + 1];
+  const int l = blockIdx.x, d = 2 * l + 1;
+  const int b0 = blockIdx.y * BC;
+  if (b0 >= d) return;  // uniform: the whole block leaves
+  const long M = 2L * nR;
+  const long r0 = (long)blockIdx.z * RB;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;  // columns tx + 16i, rows ty + 16j
+  const double *__restrict__ dl = Dt + dofs[l];
+  const int q0 = l * l;
+  double acc[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[j][i] = 0.0;
+  for (int a0 = 0; a0 < d; a0 += AC) {
+    // the other patch's moments of this block's rows, a-chunk [a0, a0 + AC),
+    // and the rotation coefficients Dt_l[b0 + bb][a0 + a]: every load from a
+    // clamped valid address (masked afterwards) so that all are in flight
+    // together, then the LDS stores
+    double va[RB * AC / 256], vd[BC * AC / 256];
+#pragma unroll
+    for (int u = 0; u < RB * AC / 256; ++u) {
+      const int e = tid + 256 * u, r = e / AC, a = e % AC;
+      const long row = min(r0 + r, M - 1);
+      const long other = row < nR ? row + nR : row - nR;
+      va[u] = A[other * Q + q0 + min(a0 + a, d - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < BC * AC / 256; ++u) {
+      const int e = tid + 256 * u, bb = e / AC, a = e % AC;
+      vd[u] = dl[(long)min(b0 + bb, d - 1) * d + min(a0 + a, d - 1)];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // issue every load before the first use
+#pragma unroll
+    for (int u = 0; u < RB * AC / 256; ++u) {
+      const int e = tid + 256 * u, r = e / AC, a = e % AC;
+      va[u] = keep_if(r0 + r < M && a0 + a < d, va[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < BC * AC / 256; ++u) {
+      const int e = tid + 256 * u, bb = e / AC, a = e % AC;
+      vd[u] = keep_if(b0 + bb < d && a0 + a < d, vd[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < RB * AC / 256; ++u) {
+      const int e = tid + 256 * u;
+      sA[e / AC][e % AC] = va[u];
+    }
+#pragma unroll
+    for (int u = 0; u < BC * AC / 256; ++u) {
+      const int e = tid + 256 * u;
+      sD[e % AC][e / AC] = vd[u];
+    }
+    __syncthreads();
+    const int na = min(AC, d - a0);
+    for (int a = 0; a < na; ++a) {
+      double dv[4], av[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dv[i] = sD[a][tx + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) av[j] = sA[ty + 16 * j][a];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[j][i] += av[j] * dv[i];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const long row = r0 + ty + 16 * j;
+    if (row >= M) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = b0 + tx + 16 * i;
+      if (b < d) {
+        const long off = row * Q + q0 + b;
+        At[off] = A[off] + acc[j][i];
+      }
+    }
+  }
+}
+
+// Phi transforms with the whole contraction resident in LDS (used when the
+// basis fits):
+//   ROLE 0 (analysis):  C[n][m] = sum_k A[m][k] w[m % w_mod][k] B[n][k]
+//                       (A row-major with lda = K, C stored column-major)
+//   ROLE 1 (synthesis): C[m][n] = sum_k A[k][m] B[n][k]
+//                       (A stored k-major, C row-major)
+// m runs over the (row, colatitude) pairs.  B (npad x K) is loaded into LDS
+// once per block; persistent blocks walk BM-row tiles of A, loading the next
+// tile into registers (coalesced: the tile is one contiguous range for
+// ROLE 0, K runs of BM for ROLE 1) while the current one is multiplied.
+// Wave w owns the 16-wide N tiles w, w+4, ... for all BM/16 M tiles.
+template <int ROLE, int BM, int TN, int EMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void phi_transform_kernel(PhiArgs p) {
+  extern __shared__ double lds[];
+  constexpr int MT = BM / 16;
+  const int K = p.K, ldk = p.ldk, npad = p.npad;
+  double *sB = lds;               // [npad][ldk]
+  double *sA = lds + npad * ldk;  // [BM][ldk]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kq16 = (K + 15) / 16;  // groups of four 4-wide MFMA k-steps
+  for (int e = tid; e < npad * ldk; e += 256) {
+    const int n = e / ldk, k = e % ldk;
+    sB[e] = (n < p.N && k < K) ? p.B[(long)n * p.ldb + k] : 0.0;
+  }
+  // k columns past K are never written by the tile loads: zero them once
+  for (int e = tid; e < BM * (ldk - K); e += 256) {
+    const int m = e / (ldk - K), k = K + e % (ldk - K);
+    sA[m * ldk + k] = 0.0;
+  }
+  const int tiles = (p.M + BM - 1) / BM;
+  const int nel = BM * K;
+  double ra[EMAX];
+  // element e = tid + 256 u of a tile: (m, k) stepped incrementally
+  const int qs = 256 / K, rs = 256 % K;
+  auto load = [&](int t) {
+    const long m0 = (long)t * BM;
+    if constexpr (ROLE == 0) {
+      int m = tid / K, k = tid % K;
+#pragma unroll
+      for (int u = 0; u < EMAX; ++u) {
+        const int e = tid + 256 * u;
+        // clamped valid addresses, masked afterwards (loads stay in flight together)
+        const long mm = min(m0 + m, (long)p.M - 1);
+        const int kc = min(k, K - 1);
+        const double v = p.A[mm * K + kc] * p.w[(mm % p.w_mod) * K + kc];
+        ra[u] = keep_if(e < nel && m0 + m < p.M, v);
+        k += rs;
+        m += qs;
+        if (k >= K) {
+          k -= K;
+          ++m;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < EMAX; ++u) {
+        const int e = tid + 256 * u, k = e / BM, m = e % BM;
+        const double v = p.A[(long)min(k, K - 1) * p.lda + min(m0 + m, (long)p.M - 1)];
+        ra[u] = keep_if(e < nel && m0 + m < p.M, v);
+      }
+    }
+  };
+  auto stash = [&]() {
+    if constexpr (ROLE == 0) {
+      int m = tid / K, k = tid % K;
+#pragma unroll
+      for (int u = 0; u < EMAX; ++u) {
+        if (tid + 256 * u < nel) sA[m * ldk + k] = ra[u];
+        k += rs;
+        m += qs;
+        if (k >= K) {
+          k -= K;
+          ++m;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < EMAX; ++u) {
+        const int e = tid + 256 * u;
+        if (e < nel) sA[(e % BM) * ldk + e / BM] = ra[u];
+      }
+    }
+  };
+  const int frow = lane & 15, fg = lane >> 4;
+  // B rows of this wave's N tiles (a tile past npad reads row 0: its
+  // results are never stored)
+  int brow[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int nt = wave + 4 * j;
+    brow[j] = (16 * nt < npad ? 16 * nt + frow : 0) * ldk;
+  }
+  dbl4 acc[MT][TN];
+  int t = blockIdx.x;
+  if (t < tiles) {
+    load(t);
+    stash();
+  }
+  __syncthreads();
+  for (; t < tiles; t += gridDim.x) {
+    const int tn = t + gridDim.x;
+    if (tn < tiles) load(tn);
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // 16 k per iteration: each lane reads k = 16g + 4s + fg, s < 4
+    for (int g16 = 0; g16 < kq16; ++g16) {
+      double af[4][MT], bf[4][TN];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kk = 16 * g16 + 4 * s4 + fg;
+#pragma unroll
+        for (int i = 0; i < MT; ++i) af[s4][i] = sA[(16 * i + frow) * ldk + kk];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bf[s4][j] = sB[brow[j] + kk];
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s4][i], bf[s4][j], acc[i][j], 0, 0, 0);
+    }
+    // D layout: lane, element r -> row lane/16 + 4r, column lane%16
+    const long m0 = (long)t * BM;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = 16 * (wave + 4 * j) + (lane & 15);
+      if (n >= p.N) continue;
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long m = m0 + 16 * i + (lane >> 4) + 4 * r;
+          if (m < p.M) {
+            if constexpr (ROLE == 0)
+              p.C[(long)n * p.ldc + m] = acc[i][j][r];
+            else
+              p.C[m * p.ldc + n] = acc[i][j][r];
+          }
+        }
+    }
+    __syncthreads();  // every wave is done reading this tile
+    if (tn < tiles) stash();
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -501,26 +854,55 @@ hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4
                                   hipStream_t s) {
   dim3 grid(n_blocks), block(64 * WGM * WGN);
   // roles 0/1: analysis / synthesis with the plain epilogue; 2/3: the same
-  // with the general epilogue
+  // with the general epilogue; 4: synthesis, general epilogue, A stored
+  // k-major
   switch (role) {
     case 0:
-      hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, false>), grid, block, 0, s, probs, items, n_items);
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, 0>), grid, block, 0, s, probs, items, n_items);
       break;
     case 1:
-      hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, false>), grid, block, 0, s, probs, items, n_items);
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, 0>), grid, block, 0, s, probs, items, n_items);
       break;
     case 2:
-      hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, true>), grid, block, 0, s, probs, items, n_items);
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, 1>), grid, block, 0, s, probs, items, n_items);
+      break;
+    case 3:
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, 1>), grid, block, 0, s, probs, items, n_items);
+      break;
+    case 4:
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, 1 | kGemmATrans>), grid, block, 0, s, probs, items,
+                         n_items);
       break;
     default:
-      hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, true>), grid, block, 0, s, probs, items, n_items);
-      break;
+      return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Single problem with transposed / scaled operand layouts (no split-K):
+// role 0 takes kGemmCTrans | kGemmAScale, role 1 kGemmATrans.
+template <int BM, int BN, int WGM, int WGN>
+hipError_t launch_mode_variant(int mode, const GemmF64Args &a, hipStream_t s) {
+  GemmF64Args g = a;
+  g.tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  g.k_per_split = ((g.K + kBK - 1) / kBK) * kBK;
+  g.c_split_stride = 0;
+  dim3 grid(g.tiles_m * tiles_n, 1), block(64 * WGM * WGN);
+  if (mode == (kGemmCTrans | kGemmAScale))
+    hipLaunchKernelGGL((gemm_nt_f64_kernel<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmAScale>), grid, block, 0, s, g,
+                       g.tiles_m * tiles_n);
+  else if (mode == kGemmATrans)
+    hipLaunchKernelGGL((gemm_nt_f64_kernel<1, BM, BN, WGM, WGN, kGemmATrans>), grid, block, 0, s, g,
+                       g.tiles_m * tiles_n);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 typedef hipError_t (*gemm_f64_fn)(int, int, int, int, const double *, long, const double *, long, double *, long, int,
                                   long, hipStream_t);
+typedef hipError_t (*mode_f64_fn)(int, const GemmF64Args &, hipStream_t);
 
 typedef hipError_t (*grouped_f64_fn)(int, const GemmF64Args *, const int4 *, int, int, hipStream_t);
 
@@ -528,10 +910,14 @@ struct F64Variant {
   int bm, bn, threads;
   gemm_f64_fn fn;
   grouped_f64_fn grouped;
+  mode_f64_fn mode;
 };
 
-#define YYG_F64_VARIANT(BM, BN, WM, WN) \
-  { BM, BN, 64 * WM * WN, launch_gemm_variant<BM, BN, WM, WN>, launch_grouped_variant<BM, BN, WM, WN> }
+#define YYG_F64_VARIANT(BM, BN, WM, WN)                                                                   \
+  {                                                                                                        \
+    BM, BN, 64 * WM * WN, launch_gemm_variant<BM, BN, WM, WN>, launch_grouped_variant<BM, BN, WM, WN>, \
+        launch_mode_variant<BM, BN, WM, WN>                                                                \
+  }
 
 const F64Variant kF64Variants[] = {
     YYG_F64_VARIANT(128, 128, 2, 2), YYG_F64_VARIANT(64, 128, 2, 2),  YYG_F64_VARIANT(128, 64, 2, 2),
@@ -557,6 +943,13 @@ hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *pro
   return kF64Variants[variant].grouped(role, probs, items, n_items, n_blocks, s);
 }
 
+hipError_t launch_gemm_f64_mode(int variant, int mode, const GemmF64Args &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (variant < 0 || variant >= gemm_f64_variant_count()) return hipErrorInvalidValue;
+  if ((mode & kGemmAScale) && (!g.Aw || g.aw_mod < 1)) return hipErrorInvalidValue;
+  return kF64Variants[variant].mode(mode, g, s);
+}
+
 hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const double *A, long lda, const double *B,
                               long ldb, double *C, long ldc, int nsplit, long c_split_stride, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
@@ -566,12 +959,15 @@ hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const 
 
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
                               const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu, int patches,
-                              hipStream_t s) {
+                              hipStream_t s, double *Ut) {
   if (patches != 1 && patches != 2) return hipErrorInvalidValue;
   const int cross = patches == 2 ? 1 : 0;
-  ScanArgs sa{part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu, cross};
+  if (!Ahat && nsplit != 1) return hipErrorInvalidValue;
+  ScanArgs sa{part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu, cross, Ut, (long)patches * nR};
   if (nR <= 64 * 4) {
     hipLaunchKernelGGL(radial_scan_kernel<4>, dim3((Q + 15) / 16, patches), dim3(16, 64), 0, s, sa);
+  } else if (nR <= 64 * 8) {
+    hipLaunchKernelGGL(radial_scan_kernel<8>, dim3((Q + 15) / 16, patches), dim3(16, 64), 0, s, sa);
   } else if (nR <= 64 * 16) {
     hipLaunchKernelGGL(radial_scan_kernel<16>, dim3((Q + 15) / 16, patches), dim3(16, 64), 0, s, sa);
   } else {
@@ -579,7 +975,7 @@ hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride,
     while (nw > 1 && nR / nw < 8) nw >>= 1;
     dim3 block(64, nw), grid((Q + 63) / 64, patches);
     hipLaunchKernelGGL(radial_scan_loop_kernel, grid, block, 0, s, part, nsplit, split_stride, Ahat, coef, qdeg, nR,
-                       Q, L, negG, U, ldu, cross);
+                       Q, L, negG, U, ldu, cross, Ut, (long)patches * nR);
   }
   return hipGetLastError();
 }
@@ -604,11 +1000,81 @@ hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, 
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_moments(const double *U, long ldu, const int *qdeg, int M, int Q, double *Ut, long ldl,
-                                  hipStream_t s) {
-  hipLaunchKernelGGL(scatter_moments_kernel, dim3((Q + 127) / 128, M), dim3(128), 0, s, U, ldu, qdeg, Q, (long)M, Ut,
-                     ldl);
+
+hipError_t launch_rotate_moments(const double *A, int nR, int L, const int *dofs, const double *Dt, double *At,
+                                 hipStream_t s) {
+  if (nR <= 0) return hipSuccess;
+  const int Q = (L + 1) * (L + 1);
+  dim3 grid(L + 1, (2 * L + 1 + 63) / 64, (2 * nR + 63) / 64);
+  hipLaunchKernelGGL(rotate_moments_kernel, grid, dim3(256), 0, s, A, nR, Q, dofs, Dt, At);
   return hipGetLastError();
+}
+
+namespace {
+
+// A-tile elements per thread (BM x K <= 256 x this)
+constexpr int phi_emax(int BM) { return BM == 16 ? 16 : BM == 32 ? 20 : 36; }
+constexpr int kPhiLds = 156 * 1024;
+
+// LDS footprint and feasibility of a resident phi transform with tile BM
+int phi_ldk(int K) {
+  // k padded to whole 16-wide groups, odd row stride (no LDS bank
+  // conflicts across rows)
+  return (K + 15) / 16 * 16 + 1;
+}
+
+int phi_lds_bytes(int BM, int N, int K) {
+  const int npad = (N + 15) / 16 * 16;
+  return (npad + BM) * phi_ldk(K) * 8;
+}
+
+template <int ROLE, int BM, int TN>
+hipError_t launch_phi_bm_tn(const PhiArgs &a, int blocks, int lds, hipStream_t s) {
+  auto fn = phi_transform_kernel<ROLE, BM, TN, phi_emax(BM)>;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+      hipSuccess)
+    return hipGetLastError();
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int ROLE, int BM>
+hipError_t launch_phi_bm(const PhiArgs &a, int blocks, int lds, hipStream_t s) {
+  switch ((a.npad / 16 + 3) / 4) {
+    case 1: return launch_phi_bm_tn<ROLE, BM, 1>(a, blocks, lds, s);
+    case 2: return launch_phi_bm_tn<ROLE, BM, 2>(a, blocks, lds, s);
+    case 3: return launch_phi_bm_tn<ROLE, BM, 3>(a, blocks, lds, s);
+    case 4: return launch_phi_bm_tn<ROLE, BM, 4>(a, blocks, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool phi_transform_fits(int BM, int N, int K) {
+  if (BM != 16 && BM != 32 && BM != 64) return false;
+  if (N < 1 || K < 1 || N > 256) return false;
+  if ((long)BM * K > 256L * phi_emax(BM)) return false;
+  return phi_lds_bytes(BM, N, K) <= kPhiLds;
+}
+
+hipError_t launch_phi_transform(int role, int BM, PhiArgs a, int blocks, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+  if (!phi_transform_fits(BM, a.N, a.K) || (role != 0 && role != 1) || blocks < 1) return hipErrorInvalidValue;
+  if (role == 0 && (a.lda != a.K || !a.w || a.w_mod < 1)) return hipErrorInvalidValue;
+  a.npad = (a.N + 15) / 16 * 16;
+  a.ldk = phi_ldk(a.K);
+  const int lds = phi_lds_bytes(BM, a.N, a.K);
+  const int tiles = (a.M + BM - 1) / BM;
+  blocks = std::min(blocks, tiles);
+  if (role == 0) {
+    if (BM == 16) return launch_phi_bm<0, 16>(a, blocks, lds, s);
+    if (BM == 32) return launch_phi_bm<0, 32>(a, blocks, lds, s);
+    return launch_phi_bm<0, 64>(a, blocks, lds, s);
+  }
+  if (BM == 16) return launch_phi_bm<1, 16>(a, blocks, lds, s);
+  if (BM == 32) return launch_phi_bm<1, 32>(a, blocks, lds, s);
+  return launch_phi_bm<1, 64>(a, blocks, lds, s);
 }
 
 int gemm_f64_variant_threads(int v) { return kF64Variants[v].threads; }

@@ -412,17 +412,16 @@ void cross_basis(const PatchGeom &g, int L, double *out) {
   });
 }
 
-void separable_phi_basis(const PatchGeom &g, const double *w, int L, long ldk, double *out) {
+void separable_cs(const PatchGeom &g, int L, long ldk, double *out) {
   const int Q = (L + 1) * (L + 1), nmc = 2 * L + 1;
   std::vector<double> cs((size_t)g.n_p * Q);
   phi_table(g, L, cs.data());
-  for (int j = 0; j < g.n_t; ++j)
-    for (int mc = 0; mc < nmc; ++mc) {
-      const int m = (mc + 1) / 2;
-      const int q = m * m + mc;  // column (l = m, m, c)
-      double *o = out + ((size_t)j * nmc + mc) * ldk;
-      for (long k = 0; k < ldk; ++k) o[k] = k < g.n_p ? w[(size_t)j * g.n_p + k] * cs[(size_t)k * Q + q] : 0.0;
-    }
+  for (int mc = 0; mc < nmc; ++mc) {
+    const int m = (mc + 1) / 2;
+    const int q = m * m + mc;  // column (l = m, m, c)
+    double *o = out + (size_t)mc * ldk;
+    for (long k = 0; k < ldk; ++k) o[k] = k < g.n_p ? cs[(size_t)k * Q + q] : 0.0;
+  }
 }
 
 void separable_trig(const PatchGeom &g, int L, long ldm, double *out) {

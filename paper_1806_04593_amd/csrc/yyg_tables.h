@@ -63,8 +63,9 @@ void cross_basis(const PatchGeom &g, int L, double *out);
 // Azimuthal column index of (m, cos/sin): mc = 0 for m = 0, 2m-1 / 2m for
 // cos / sin, so that q(l, m, c) = l^2 + mc.  2L+1 columns.
 
-// W[j][mc][k] = w_jk * (C_k^(m) or S_k^(m)), rows of length ldk (zero padded)
-void separable_phi_basis(const PatchGeom &g, const double *w, int L, long ldk, double *out);
+
+// CS[mc][k] = C_k^(m) or S_k^(m) (Eqs. 14-15), rows of length ldk (zero padded)
+void separable_cs(const PatchGeom &g, int L, long ldk, double *out);
 
 // trig[k][mc] = cos / sin (m phi_k) at the cell midpoints, rows of length ldm
 void separable_trig(const PatchGeom &g, int L, long ldm, double *out);

@@ -28,7 +28,7 @@ EXPORTS = [
     "yyg_grid_destroy", "yyg_host_table", "yyg_set_timing", "yyg_get_timing",
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
-    "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind",
+    "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind", "yyg_sep_config", "yyg_sep_info",
 ]
 
 
@@ -86,6 +86,8 @@ def lib():
         L.yyg_batch_info.argtypes = [vp, ctypes.POINTER(i), i]
         L.yyg_batch_profile.argtypes = [vp, vp, dp, i]
         L.yyg_set_method.argtypes = [vp, i]
+        L.yyg_sep_config.argtypes = [vp, i, i]
+        L.yyg_sep_info.argtypes = [vp, ctypes.POINTER(i), i]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -213,6 +215,14 @@ class Grid:
         _check(lib().yyg_plan_info(self._h, PRECISIONS.get(precision, precision), info, 7), "yyg_plan_info")
         keys = ("var_ana", "split_ana", "var_syn", "bm_ana", "bn_ana", "bm_syn", "bn_syn")
         return dict(zip(keys, list(info)))
+
+    def sep_config(self, phase, variant):
+        _check(lib().yyg_sep_config(self._h, int(phase), int(variant)), "yyg_sep_config")
+
+    def sep_info(self):
+        v = (ctypes.c_int * 5)()
+        _check(lib().yyg_sep_info(self._h, v, 5), "yyg_sep_info")
+        return list(v)
 
     def set_config(self, var_ana, split_ana, var_syn, precision="fp64"):
         _check(lib().yyg_plan_config(self._h, PRECISIONS.get(precision, precision), int(var_ana), int(split_ana),
