@@ -261,7 +261,7 @@ def bench_single(a):
         tf = flops_k / (ms_k * 1e-3) / 1e12
         gbs = bytes_k / (ms_k * 1e-3) / 1e9
         fm, fh = tf / PEAK["fp64"], gbs / 8000.0
-        kname = "gemm_nt_f64_grouped<" + ("0" if name == "phi_analysis" else "1") + ",...,true> (" + name + ")"
+        kname = "gemm_nt_f64_batched<" + ("0" if name == "phi_analysis" else "1") + ",...> (" + name + ")"
         if fm >= fh:
             roof = {"bound": "mfma", "kernel": kname, "achieved": tf, "peak": PEAK["fp64"], "unit": "TFLOP/s",
                     "frac": fm, "hbm_frac": fh}

@@ -241,11 +241,8 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
 
 /* Tile variant (numbered as for yyg_plan_info) of one phase of the
  * separable form: 0 phi analysis, 1 theta analysis, 3 theta synthesis,
- * 4 phi synthesis (phase 2, the moment rotation, has no tile).  The phi
- * phases also take variants V, V+1, V+2 (V = the number of FP64 tile
- * variants): a kernel that keeps the whole phi basis and a 16-, 32- or
- * 64-row tile of its operand in LDS, available when they fit
- * (YYG_ERR_INVALID_ARG otherwise).  Needs the separable form built
+ * 4 phi synthesis (phase 2, the moment rotation, has no tile).  Needs the
+ * separable form built
  * (yyg_set_method); synchronises the device.  For tests and expert tuning;
  * yyg_autotune chooses all four. */
 int yyg_sep_config(yyg_grid *g, int phase, int variant);

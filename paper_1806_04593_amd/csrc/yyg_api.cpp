@@ -90,18 +90,17 @@ struct yyg_grid {
   struct Sep {
     bool ready = false;
     long ldk = 0, ldm = 0, ldl = 0;
-    double *CSt = nullptr;   // phi-analysis basis [2L+1][ldk]: C/S_k^(m)
-    double *w = nullptr;     // overlap weights [n_t][n_p] (scale the density as it is loaded)
+    double *Wcs = nullptr;   // weighted phi-analysis basis [n_t][2L+1][ldk]: w_jk C/S_k^(m)
     double *trig = nullptr;  // phi-synthesis basis [n_p][ldm]
     double *T2 = nullptr;    // theta-analysis basis [mc][l][n_t]: sqrt(N) T_j^(lm)
     double *P2 = nullptr;    // theta-synthesis basis [mc][j][ldl]: sqrt(N) P_l^m(cos t_j)
     double *Dt = nullptr;    // transposed rotation blocks, per degree l: [b][a]
     int *dofs = nullptr;     // offset of each degree's block in Dt
-    double *X2 = nullptr;    // phi-analysis output [mc][row][j]
-    double *V = nullptr;     // theta-synthesis output [mc][row][j]
+    double *X2 = nullptr;    // phi-analysis output [mc][j][row]
+    double *V = nullptr;     // theta-synthesis output [mc][j][row]
     double *Ut = nullptr;    // potential coefficients of own + rotated other moments [mc][l][row]
-    // single-problem phases: phi analysis over the (row, j) pairs (C stored
-    // column-major, density scaled by w) and phi synthesis (A stored k-major)
+    // phi phases, strided batches over the colatitudes j: analysis (C
+    // stored column-major) and synthesis (A stored k-major)
     yyg::GemmF64Args phi_ana{}, phi_syn{};
     // grouped problems: theta analysis [2L+1], theta synthesis [2L+1]
     yyg::GemmF64Args *probs = nullptr;
@@ -111,10 +110,7 @@ struct yyg_grid {
     int4 *items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int n_items[5] = {0, 0, 0, 0, 0};
     int blocks[5] = {0, 0, 0, 0, 0};
-    // phases 0 and 4 also accept variants nv + {0, 1, 2}: the resident
-    // phi transform with 16-, 32- or 64-row tiles (nv = FP64 tile variants)
     int var[5] = {3, 3, 0, 3, 3};
-    int cus = 256;
     std::vector<yyg::GemmF64Args> h_probs;
   } sep;
 
@@ -157,7 +153,7 @@ void free_grid(yyg_grid *g) {
   if (g->d_eA) (void)hipFree(g->d_eA);
   if (g->d_eU) (void)hipFree(g->d_eU);
   {
-    void *b[] = {g->sep.CSt,      g->sep.w,        g->sep.trig,     g->sep.T2,       g->sep.P2,
+    void *b[] = {g->sep.Wcs,      g->sep.trig,     g->sep.T2,       g->sep.P2,
                  g->sep.Dt,       g->sep.X2,       g->sep.V,        g->sep.Ut,       g->sep.probs,
                  g->sep.items[0], g->sep.items[1], g->sep.items[2], g->sep.items[3], g->sep.items[4],
                  g->sep.dofs};
@@ -278,25 +274,9 @@ namespace {
 
 // Tile variant v for separable phase r; for the grouped phases (theta
 // analysis 1, theta synthesis 3) also their work items, largest K first.
-const int kPhiBM[3] = {16, 32, 64};
-
-// Whether phase r (0 or 4) can run variant v.
-bool sep_phi_variant_ok(const yyg_grid *g, int r, int v) {
-  const int nv = yyg::gemm_f64_variant_count(), nmc = 2 * g->L + 1;
-  if (v >= 0 && v < nv) return true;
-  if (v < nv || v >= nv + 3) return false;
-  return r == 0 ? yyg::phi_transform_fits(kPhiBM[v - nv], nmc, g->n_p)
-                : yyg::phi_transform_fits(kPhiBM[v - nv], g->n_p, nmc);
-}
-
 int sep_set_items(yyg_grid *g, int r, int v) {
   auto &S = g->sep;
   const int nmc = 2 * g->L + 1;
-  if (r == 0 || r == 4) {
-    if (!sep_phi_variant_ok(g, r, v)) return YYG_ERR_INVALID_ARG;
-    S.var[r] = v;
-    return YYG_OK;
-  }
   if (v < 0 || v >= yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
   S.var[r] = v;
   if (r != 1 && r != 3) return YYG_OK;
@@ -331,22 +311,11 @@ int sep_set_items(yyg_grid *g, int r, int v) {
 
 hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
-  const int nv = yyg::gemm_f64_variant_count();
-  if (r == 0 && S.var[0] >= nv) {
-    const yyg::GemmF64Args &a = S.phi_ana;
-    yyg::PhiArgs p{a.M, a.N, a.K, a.A, a.lda, a.Aw, a.aw_mod, a.B, a.ldb, a.C, a.ldc, 0, 0};
-    return yyg::launch_phi_transform(0, kPhiBM[S.var[0] - nv], p, S.cus, s);
-  }
-  if (r == 4 && S.var[4] >= nv) {
-    const yyg::GemmF64Args &a = S.phi_syn;
-    yyg::PhiArgs p{a.M, a.N, a.K, a.A, a.lda, nullptr, 1, a.B, a.ldb, a.C, a.ldc, 0, 0};
-    return yyg::launch_phi_transform(1, kPhiBM[S.var[4] - nv], p, S.cus, s);
-  }
-  if (r == 0) return yyg::launch_gemm_f64_mode(S.var[0], yyg::kGemmCTrans | yyg::kGemmAScale, S.phi_ana, s);
-  if (r == 4) return yyg::launch_gemm_f64_mode(S.var[4], yyg::kGemmATrans, S.phi_syn, s);
+  if (r == 0) return yyg::launch_gemm_f64_batched(S.var[0], 0, S.phi_ana, s);
+  if (r == 4) return yyg::launch_gemm_f64_batched(S.var[4], 1, S.phi_syn, s);
   if (S.n_items[r] == 0) return hipSuccess;
-  // grouped theta phases, general epilogue (the synthesis reads Ut k-major)
-  return yyg::launch_gemm_f64_grouped(S.var[r], r == 1 ? 2 : 4, S.probs, S.items[r], S.n_items[r], S.blocks[r], s);
+  // grouped theta phases: general epilogue, A read k-major (X2, Ut)
+  return yyg::launch_gemm_f64_grouped(S.var[r], r == 1 ? 5 : 4, S.probs, S.items[r], S.n_items[r], S.blocks[r], s);
 }
 
 // Point the phi phases at this solve's density and potential (kernel
@@ -365,12 +334,18 @@ int sep_build(yyg_grid *g) {
   S.ldk = round_up(np, 16);
   S.ldm = round_up(nmc, 16);
   S.ldl = round_up(L + 1, 16);
-  std::vector<double> CSt, trig, T, P, T2, P2, D;
+  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D;
   std::vector<int> dofs;
   try {
     for (int l = 0, off = 0; l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) dofs.push_back(off);
     CSt.resize((size_t)nmc * S.ldk);
     yyg::separable_cs(g->geom, L, S.ldk, CSt.data());
+    // the overlap weights folded into one basis copy per colatitude
+    Wcs.assign((size_t)nt * nmc * S.ldk, 0.0);
+    for (int j = 0; j < nt; ++j)
+      for (int mc = 0; mc < nmc; ++mc)
+        for (int k = 0; k < np; ++k)
+          Wcs[((size_t)j * nmc + mc) * S.ldk + k] = g->w_host[(size_t)j * np + k] * CSt[(size_t)mc * S.ldk + k];
     trig.resize((size_t)np * S.ldm);
     yyg::separable_trig(g->geom, L, S.ldm, trig.data());
     T.resize((size_t)nt * Q);
@@ -400,8 +375,7 @@ int sep_build(yyg_grid *g) {
     return YYG_ERR_OUT_OF_MEMORY;
   }
   int st = YYG_OK;
-  if (st == YYG_OK) st = dmalloc(&S.CSt, CSt.size());
-  if (st == YYG_OK) st = dmalloc(&S.w, (size_t)g->nang);
+  if (st == YYG_OK) st = dmalloc(&S.Wcs, Wcs.size());
   if (st == YYG_OK) st = dmalloc(&S.trig, trig.size());
   if (st == YYG_OK) st = dmalloc(&S.T2, T2.size());
   if (st == YYG_OK) st = dmalloc(&S.P2, P2.size());
@@ -416,8 +390,7 @@ int sep_build(yyg_grid *g) {
   auto chk = [&](hipError_t r) {
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
-  chk(hipMemcpy(S.CSt, CSt.data(), CSt.size() * sizeof(double), hipMemcpyHostToDevice));
-  chk(hipMemcpy(S.w, g->w_host.data(), g->w_host.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.Wcs, Wcs.data(), Wcs.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.T2, T2.data(), T2.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.P2, P2.data(), P2.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -428,37 +401,34 @@ int sep_build(yyg_grid *g) {
     return YYG_ERR_DEVICE;
   }
   auto kround = [](long k) { return (int)((k + 15) / 16 * 16); };
-  // X2[mc][row*nt + j] = sum_k rho[row][j][k] w[j][k] CS_k^(mc)   (rho set per solve)
-  S.phi_ana = yyg::GemmF64Args{(int)MJ, nmc, np, nullptr, np, S.CSt, S.ldk, S.X2, MJ, 0, kround(np), 1};
-  S.phi_ana.Aw = S.w;
-  S.phi_ana.aw_mod = nt;
-  // phi[row][j][k] = sum_mc V[mc][row*nt + j] trig[k][mc]         (phi set per solve)
-  S.phi_syn = yyg::GemmF64Args{(int)MJ, np, nmc, S.V, MJ, S.trig, S.ldm, nullptr, np, 0, kround(nmc), 1};
+  // per colatitude j: X2[mc][j][row] = sum_k rho[row][j][k] w_jk CS_k^(mc)   (rho set per solve)
+  S.phi_ana = yyg::GemmF64Args{(int)M, nmc, np, nullptr, (long)nt * np, S.Wcs, S.ldk, S.X2, MJ, M, kround(np), 1};
+  S.phi_ana.batch = nt;
+  S.phi_ana.a_batch = np;
+  S.phi_ana.b_batch = (long)nmc * S.ldk;
+  // per colatitude j: phi[row][j][k] = sum_mc V[mc][j][row] trig[k][mc]        (phi set per solve)
+  S.phi_syn = yyg::GemmF64Args{(int)M, np, nmc, S.V, MJ, S.trig, S.ldm, nullptr, (long)nt * np, np, kround(nmc), 1};
+  S.phi_syn.batch = nt;
+  S.phi_syn.a_batch = M;
   S.h_probs.assign(2 * (size_t)nmc, yyg::GemmF64Args{});
   for (int mc = 0; mc < nmc; ++mc) {
     const int m = (mc + 1) / 2, nl = L + 1 - m;
-    // A[row][l^2 + mc] = sum_j X2[mc][row][j] T2[mc][l][j], l >= m
+    // A[row][l^2 + mc] = sum_j X2[mc][j][row] T2[mc][l][j], l >= m   (A stored k-major)
     yyg::GemmF64Args &a = S.h_probs[mc];
-    a = yyg::GemmF64Args{(int)M, nl, nt, S.X2 + (long)mc * MJ, nt, S.T2 + ((long)mc * (L + 1) + m) * nt, nt,
+    a = yyg::GemmF64Args{(int)M, nl, nt, S.X2 + (long)mc * MJ, M, S.T2 + ((long)mc * (L + 1) + m) * nt, nt,
                          g->d_Ahat + mc, Q, 0, kround(nt), 1};
     a.c_sq = m;
-    // V[mc][row][j] = sum_{l >= m} Ut[mc][l][row] P2[mc][j][l]      (A stored k-major)
+    // V[mc][j][row] = sum_{l >= m} Ut[mc][l][row] P2[mc][j][l]      (A stored k-major, C column-major)
     yyg::GemmF64Args &b = S.h_probs[nmc + mc];
     b = yyg::GemmF64Args{(int)M, nt, nl, S.Ut + ((long)mc * (L + 1) + m) * M, M, S.P2 + (long)mc * nt * S.ldl + m,
-                         S.ldl, S.V + (long)mc * MJ, nt, 0, kround(nl), 1};
+                         S.ldl, S.V + (long)mc * MJ, 1, 0, kround(nl), 1};
+    b.ldc_c = M;
   }
   if (hipMemcpy(S.probs, S.h_probs.data(), S.h_probs.size() * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice) !=
       hipSuccess) {
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;
   }
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device) == hipSuccess && cus > 0)
-    S.cus = cus;
-  // default: the resident phi transforms with 32-row tiles where they fit
-  const int nv = yyg::gemm_f64_variant_count();
-  for (int r : {0, 4})
-    if (sep_phi_variant_ok(g, r, nv + 1)) S.var[r] = nv + 1;
   for (int r = 0; r < 5; ++r) {
     int st2 = sep_set_items(g, r, S.var[r]);
     if (st2 != YYG_OK) return st2;
@@ -1409,9 +1379,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
       if (r == 2) continue;  // the rotation is not a GEMM phase
       double best = 1e30;
       int bv = g->sep.var[r];
-      const int nvr = yyg::gemm_f64_variant_count() + ((r == 0 || r == 4) ? 3 : 0);
-      for (int v = 0; v < nvr && st3 == YYG_OK; ++v) {
-        if ((r == 0 || r == 4) && !sep_phi_variant_ok(g, r, v)) continue;
+      for (int v = 0; v < yyg::gemm_f64_variant_count() && st3 == YYG_OK; ++v) {
         st3 = sep_set_items(g, r, v);
         if (st3 != YYG_OK) break;
         double t = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 3);
@@ -1496,9 +1464,7 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n) {
 int yyg_sep_config(yyg_grid *g, int phase, int variant) {
   if (!g || (phase != 0 && phase != 1 && phase != 3 && phase != 4)) return YYG_ERR_INVALID_ARG;
   if (!g->sep.ready) return YYG_ERR_NOT_READY;
-  if ((phase == 0 || phase == 4) ? !sep_phi_variant_ok(g, phase, variant)
-                                 : (variant < 0 || variant >= yyg::gemm_f64_variant_count()))
-    return YYG_ERR_INVALID_ARG;
+  if (variant < 0 || variant >= yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   if (hipDeviceSynchronize() != hipSuccess) {  // the work items may be in use

@@ -20,20 +20,21 @@ struct GemmF64Args {
   long ldc_c = 1;       // column stride of C
   int c_sq = -1;        // >= 0: column n of C lands at (n + c_sq)^2 (degree-major q index)
   int c_add = 0;        // 1: C += A.B^T instead of C = A.B^T
-  const double *Aw = nullptr;  // kGemmAScale: A(m, k) is scaled by Aw[(m % aw_mod) * lda + k]
-  int aw_mod = 1;
+  // strided batch (launch_gemm_f64_batched): problem z reads A + z a_batch,
+  // B + z b_batch and writes C + z c_split_stride
+  int batch = 1;
+  long a_batch = 0, b_batch = 0;
 };
 
-// Operand layouts of the single-problem FP64 GEMM (launch_gemm_f64_mode),
-// bit flags:
+// Operand layouts (bit flags of the tile kernel):
 //  kGemmATrans  A is stored k-major: element (m, k) at A[k * lda + m]
 //  kGemmCTrans  C is stored column-major: element (m, n) at C[n * ldc + m]
-//  kGemmAScale  A(m, k) is multiplied by Aw[(m % aw_mod) * lda + k] as it
-//               is loaded (row-major A only)
-enum { kGemmATrans = 2, kGemmCTrans = 4, kGemmAScale = 8 };
-// Supported combinations: kGemmCTrans | kGemmAScale (role 0) and
-// kGemmATrans (role 1).  No split-K.
-hipError_t launch_gemm_f64_mode(int variant, int mode, const GemmF64Args &g, hipStream_t s);
+//  kGemmBatch   the split index selects a problem of a strided batch
+enum { kGemmATrans = 2, kGemmCTrans = 4, kGemmBatch = 8 };
+
+// Strided batch of g.batch equal-shape problems, whole K each: role 0
+// stores C column-major, role 1 reads A k-major (plain epilogue otherwise).
+hipError_t launch_gemm_f64_batched(int variant, int role, const GemmF64Args &g, hipStream_t s);
 
 // FP64 NT GEMM C = A . B^T in one of several tile shapes ("variants");
 // role 0 = analysis, 1 = synthesis (separate kernel symbols).
@@ -46,7 +47,8 @@ hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const 
 // tm, tn, split) over the problems' tiles of the variant's shape.  role 0/1
 // = analysis / synthesis with the plain epilogue, 2/3 with the general one
 // (ldc_c, c_sq, c_add honoured), 4 = synthesis with the general epilogue
-// and A stored k-major (kGemmATrans).
+// and A stored k-major (kGemmATrans), 5 = analysis with the general
+// epilogue and A stored k-major.
 hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *probs, const int4 *items, int n_items,
                                   int n_blocks, hipStream_t s);
 
@@ -141,25 +143,6 @@ hipError_t launch_rotate_moments(const double *A, int nR, int L, const int *dofs
                                  hipStream_t s);
 int gemm_f64_variant_threads(int v);
 
-// Phi transforms with B and a BM-row tile of A resident in LDS (see
-// phi_transform_kernel).  role 0: C[n*ldc + m] = sum_k A[m*K + k]
-// w[(m % w_mod)*K + k] B[n*ldb + k]; role 1: C[m*ldc + n] = sum_k
-// A[k*lda + m] B[n*ldb + k].  BM in {16, 32, 64}; `blocks` persistent blocks
-// (at most one per tile).  phi_transform_fits tells whether the shape fits.
-struct PhiArgs {
-  int M, N, K;
-  const double *A;
-  long lda;
-  const double *w;
-  long w_mod;
-  const double *B;
-  long ldb;
-  double *C;
-  long ldc;
-  int ldk, npad;  // set by the launcher
-};
-bool phi_transform_fits(int BM, int N, int K);
-hipError_t launch_phi_transform(int role, int BM, PhiArgs a, int blocks, hipStream_t s);
 
 // Split-K factor for an output of `tiles` block tiles and K columns.
 int choose_split(long tiles, long K);

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 
 #include "yyg_internal.h"
 
@@ -33,9 +34,8 @@ __device__ __forceinline__ double keep_if(bool keep, double x) { return x * (kee
 constexpr int kBK = 16, kPad = 2, kLDK = kBK + kPad;
 // Stages of A and B held in registers ahead of the LDS stage being
 // multiplied: a stage's global loads are issued kPF stages before its LDS
-// store.  Measured on MI355X, deeper prefetch (3) cost occupancy and made
-// the long-K contractions ~10% slower without speeding up the short-K ones,
-// so one stage it is.
+// store.  Measured on MI355X, three stages were slower than one for every
+// contraction of the solver (the registers cost occupancy).
 constexpr int kPF = 1;
 
 // Logical tile of a block so that the blocks one XCD receives (the hardware
@@ -53,18 +53,18 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 // of 16 x 16 MFMA tiles; computes output tile (tm, tn) over split z.
 // MODE bit 1 selects the general epilogue (column stride, degree-major
 // column index, accumulate); the plain one writes C[row * ldc + col].  The
-// other bits (kGemmATrans, kGemmCTrans, kGemmAScale) change the operand
-// layouts as documented with GemmF64Args.
+// other bits (kGemmATrans, kGemmCTrans) change the operand layouts as
+// documented with GemmF64Args.
 template <int BM, int BN, int WGM, int WGN, int MODE>
 __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int tn, int z) {
   constexpr bool GEN = (MODE & 1) != 0;
   constexpr bool AT = (MODE & kGemmATrans) != 0;
   constexpr bool CT = (MODE & kGemmCTrans) != 0;
-  constexpr bool AW = (MODE & kGemmAScale) != 0;
-  static_assert(!(AT && AW), "scaled A is row-major");
+  constexpr bool BATCH = (MODE & kGemmBatch) != 0;
+
   const int M = g.M, N = g.N, K = g.K;
-  const double *__restrict__ A = g.A;
-  const double *__restrict__ B = g.B;
+  const double *__restrict__ A = g.A + (BATCH ? z * g.a_batch : 0L);
+  const double *__restrict__ B = g.B + (BATCH ? z * g.b_batch : 0L);
   double *__restrict__ C = g.C;
   const long lda = g.lda, ldb = g.ldb, ldc = g.ldc;
   constexpr int NT = 64 * WGM * WGN;
@@ -84,8 +84,9 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = tm * BM, n0 = tn * BN;
-  const int kbeg = z * g.k_per_split;
-  const int kend = min(K, kbeg + g.k_per_split);
+  // z is the split-K slice, or with BATCH the problem of a strided batch
+  const int kbeg = BATCH ? 0 : z * g.k_per_split;
+  const int kend = BATCH ? K : min(K, kbeg + g.k_per_split);
   C += (long)z * g.c_split_stride;
 
   const int wm = wave % WGM, wn = wave / WGM;
@@ -96,86 +97,71 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  constexpr int PF = NT > 256 ? 1 : kPF;
+  constexpr int PF = kPF;
   double ra[PF][EA], rb[PF][EB];
   // run mapping: this thread's row and first column
   const int arow = RUN_A ? tid / (kBK / EA) : 0, acol = RUN_A ? (tid % (kBK / EA)) * EA : 0;
   const int brow = RUN_B ? tid / (kBK / EB) : 0, bcol = RUN_B ? (tid % (kBK / EB)) * EB : 0;
   const double *pa = A + (long)min(m0 + arow, M - 1) * lda;
-  const double *pw = AW ? g.Aw + (long)(min(m0 + arow, M - 1) % g.aw_mod) * lda : nullptr;
   const double *pb = B + (long)min(n0 + brow, N - 1) * ldb;
   const bool va = m0 + arow < M, vb = n0 + brow < N;
+  // load: every global load reads a clamped, valid address (a load under a
+  // condition would be waited for before the next one issues); stash: the
+  // entries outside the matrix or the stage's k range are zeroed on the way
+  // into LDS, after the stage's MFMA work, so the loads overlap it.
   auto load = [&](double (&ra)[EA], double (&rb)[EB], int k0) {
-    // Every load reads a clamped, valid address and is masked afterwards:
-    // a load under a condition is waited for before the next one issues,
-    // while unconditional ones are all in flight together.
     if constexpr (RUN_A) {
 #pragma unroll
-      for (int i = 0; i < EA; ++i) {
-        const int kk = k0 + acol + i, kc = min(kk, K - 1);
-        double v = pa[kc];
-        if constexpr (AW) v *= pw[kc];
-        ra[i] = keep_if(va && kk < kend, v);
-      }
+      for (int i = 0; i < EA; ++i) ra[i] = pa[min(k0 + acol + i, K - 1)];
     } else if constexpr (AT) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, kk = k0 + e / BM, gm = m0 + e % BM;
-        const double v = A[(long)min(kk, K - 1) * lda + min(gm, M - 1)];
-        ra[i] = keep_if(e < BM * kBK && gm < M && kk < kend, v);
+        ra[i] = A[(long)min(kk, K - 1) * lda + min(gm, M - 1)];
       }
     } else {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        const int gr = m0 + row, grc = min(gr, M - 1), kc = min(kk, K - 1);
-        double v = A[(long)grc * lda + kc];
-        if constexpr (AW) v *= g.Aw[(long)(grc % g.aw_mod) * lda + kc];
-        ra[i] = keep_if(e < BM * kBK && gr < M && kk < kend, v);
+        ra[i] = A[(long)min(m0 + row, M - 1) * lda + min(kk, K - 1)];
       }
     }
     if constexpr (RUN_B) {
 #pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const int kk = k0 + bcol + i;
-        const double v = pb[min(kk, K - 1)];
-        rb[i] = keep_if(vb && kk < kend, v);
-      }
+      for (int i = 0; i < EB; ++i) rb[i] = pb[min(k0 + bcol + i, K - 1)];
     } else {
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        const int gr = n0 + row;
-        const double v = B[(long)min(gr, N - 1) * ldb + min(kk, K - 1)];
-        rb[i] = keep_if(e < BN * kBK && gr < N && kk < kend, v);
+        rb[i] = B[(long)min(n0 + row, N - 1) * ldb + min(kk, K - 1)];
       }
     }
   };
-  auto stash = [&](const double (&ra)[EA], const double (&rb)[EB], int buf) {
+  auto stash = [&](const double (&ra)[EA], const double (&rb)[EB], int buf, int k0) {
     if constexpr (RUN_A) {
 #pragma unroll
-      for (int i = 0; i < EA; ++i) As[buf][arow * kLDK + acol + i] = ra[i];
+      for (int i = 0; i < EA; ++i) As[buf][arow * kLDK + acol + i] = (va && k0 + acol + i < kend) ? ra[i] : 0.0;
     } else if constexpr (AT) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
-        const int e = tid + i * NT;
-        if (e < BM * kBK) As[buf][(e % BM) * kLDK + e / BM] = ra[i];
+        const int e = tid + i * NT, kk = k0 + e / BM, gm = m0 + e % BM;
+        if (e < BM * kBK) As[buf][(e % BM) * kLDK + e / BM] = (gm < M && kk < kend) ? ra[i] : 0.0;
       }
     } else {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
-        const int e = tid + i * NT;
-        if (e < BM * kBK) As[buf][(e / kBK) * kLDK + e % kBK] = ra[i];
+        const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
+        if (e < BM * kBK) As[buf][row * kLDK + e % kBK] = (m0 + row < M && kk < kend) ? ra[i] : 0.0;
       }
     }
     if constexpr (RUN_B) {
 #pragma unroll
-      for (int i = 0; i < EB; ++i) Bs[buf][brow * kLDK + bcol + i] = rb[i];
+      for (int i = 0; i < EB; ++i) Bs[buf][brow * kLDK + bcol + i] = (vb && k0 + bcol + i < kend) ? rb[i] : 0.0;
     } else {
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
-        const int e = tid + i * NT;
-        if (e < BN * kBK) Bs[buf][(e / kBK) * kLDK + e % kBK] = rb[i];
+        const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
+        if (e < BN * kBK) Bs[buf][row * kLDK + e % kBK] = (n0 + row < N && kk < kend) ? rb[i] : 0.0;
       }
     }
   };
@@ -210,7 +196,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
   for (int p = 0; p < PF; ++p)
     if (p < nk) load(ra[p], rb[p], kbeg + p * kBK);
-  if (nk > 0) stash(ra[0], rb[0], 0);
+  if (nk > 0) stash(ra[0], rb[0], 0, kbeg);
   __syncthreads();
 
   // Stage `it` sits in LDS buffer it & 1 and register slot it % PF; the
@@ -224,7 +210,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
         const int buf = it & 1;
         if (it + PF < nk) load(ra[sl], rb[sl], kbeg + (it + PF) * kBK);
         compute(buf);
-        if (it + 1 < nk) stash(ra[(sl + 1) % PF], rb[(sl + 1) % PF], buf ^ 1);
+        if (it + 1 < nk) stash(ra[(sl + 1) % PF], rb[(sl + 1) % PF], buf ^ 1, kbeg + (it + 1) * kBK);
         __syncthreads();
       }
     }
@@ -263,6 +249,16 @@ template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE = 0>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(GemmF64Args g, int tiles_total) {
   const int tile = xcd_tile(blockIdx.x, tiles_total);
   gemm_f64_tile<BM, BN, WGM, WGN, MODE>(g, tile % g.tiles_m, tile / g.tiles_m, blockIdx.y);
+}
+
+// Strided batch of equal-shape problems, one block per (problem, tile),
+// problem-major after the XCD remapping.
+template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_batched(GemmF64Args g, int per_problem,
+                                                                      int tiles_total) {
+  const int t = xcd_tile(blockIdx.x, tiles_total);
+  const int z = t / per_problem, tile = t - z * per_problem;
+  gemm_f64_tile<BM, BN, WGM, WGN, MODE | kGemmBatch>(g, tile % g.tiles_m, tile / g.tiles_m, z);
 }
 
 // Persistent grouped form: blocks walk a list of (problem, tm, tn, split)
@@ -652,168 +648,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     }
     __syncthreads();
   }
+  // own moments: all 16 loads from clamped addresses first, then the
+  // stores of the valid entries
+  double own[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      own[j][i] = A[min(r0 + ty + 16 * j, M - 1) * Q + q0 + min(b0 + tx + 16 * i, d - 1)];
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const long row = r0 + ty + 16 * j;
-    if (row >= M) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int b = b0 + tx + 16 * i;
-      if (b < d) {
-        const long off = row * Q + q0 + b;
-        At[off] = A[off] + acc[j][i];
-      }
+      if (row < M && b < d) At[row * Q + q0 + b] = own[j][i] + acc[j][i];
     }
-  }
-}
-
-// Phi transforms with the whole contraction resident in LDS (used when the
-// basis fits):
-//   ROLE 0 (analysis):  C[n][m] = sum_k A[m][k] w[m % w_mod][k] B[n][k]
-//                       (A row-major with lda = K, C stored column-major)
-//   ROLE 1 (synthesis): C[m][n] = sum_k A[k][m] B[n][k]
-//                       (A stored k-major, C row-major)
-// m runs over the (row, colatitude) pairs.  B (npad x K) is loaded into LDS
-// once per block; persistent blocks walk BM-row tiles of A, loading the next
-// tile into registers (coalesced: the tile is one contiguous range for
-// ROLE 0, K runs of BM for ROLE 1) while the current one is multiplied.
-// Wave w owns the 16-wide N tiles w, w+4, ... for all BM/16 M tiles.
-template <int ROLE, int BM, int TN, int EMAX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void phi_transform_kernel(PhiArgs p) {
-  extern __shared__ double lds[];
-  constexpr int MT = BM / 16;
-  const int K = p.K, ldk = p.ldk, npad = p.npad;
-  double *sB = lds;               // [npad][ldk]
-  double *sA = lds + npad * ldk;  // [BM][ldk]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int kq16 = (K + 15) / 16;  // groups of four 4-wide MFMA k-steps
-  for (int e = tid; e < npad * ldk; e += 256) {
-    const int n = e / ldk, k = e % ldk;
-    sB[e] = (n < p.N && k < K) ? p.B[(long)n * p.ldb + k] : 0.0;
-  }
-  // k columns past K are never written by the tile loads: zero them once
-  for (int e = tid; e < BM * (ldk - K); e += 256) {
-    const int m = e / (ldk - K), k = K + e % (ldk - K);
-    sA[m * ldk + k] = 0.0;
-  }
-  const int tiles = (p.M + BM - 1) / BM;
-  const int nel = BM * K;
-  double ra[EMAX];
-  // element e = tid + 256 u of a tile: (m, k) stepped incrementally
-  const int qs = 256 / K, rs = 256 % K;
-  auto load = [&](int t) {
-    const long m0 = (long)t * BM;
-    if constexpr (ROLE == 0) {
-      int m = tid / K, k = tid % K;
-#pragma unroll
-      for (int u = 0; u < EMAX; ++u) {
-        const int e = tid + 256 * u;
-        // clamped valid addresses, masked afterwards (loads stay in flight together)
-        const long mm = min(m0 + m, (long)p.M - 1);
-        const int kc = min(k, K - 1);
-        const double v = p.A[mm * K + kc] * p.w[(mm % p.w_mod) * K + kc];
-        ra[u] = keep_if(e < nel && m0 + m < p.M, v);
-        k += rs;
-        m += qs;
-        if (k >= K) {
-          k -= K;
-          ++m;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < EMAX; ++u) {
-        const int e = tid + 256 * u, k = e / BM, m = e % BM;
-        const double v = p.A[(long)min(k, K - 1) * p.lda + min(m0 + m, (long)p.M - 1)];
-        ra[u] = keep_if(e < nel && m0 + m < p.M, v);
-      }
-    }
-  };
-  auto stash = [&]() {
-    if constexpr (ROLE == 0) {
-      int m = tid / K, k = tid % K;
-#pragma unroll
-      for (int u = 0; u < EMAX; ++u) {
-        if (tid + 256 * u < nel) sA[m * ldk + k] = ra[u];
-        k += rs;
-        m += qs;
-        if (k >= K) {
-          k -= K;
-          ++m;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < EMAX; ++u) {
-        const int e = tid + 256 * u;
-        if (e < nel) sA[(e % BM) * ldk + e / BM] = ra[u];
-      }
-    }
-  };
-  const int frow = lane & 15, fg = lane >> 4;
-  // B rows of this wave's N tiles (a tile past npad reads row 0: its
-  // results are never stored)
-  int brow[TN];
-#pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int nt = wave + 4 * j;
-    brow[j] = (16 * nt < npad ? 16 * nt + frow : 0) * ldk;
-  }
-  dbl4 acc[MT][TN];
-  int t = blockIdx.x;
-  if (t < tiles) {
-    load(t);
-    stash();
-  }
-  __syncthreads();
-  for (; t < tiles; t += gridDim.x) {
-    const int tn = t + gridDim.x;
-    if (tn < tiles) load(tn);
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // 16 k per iteration: each lane reads k = 16g + 4s + fg, s < 4
-    for (int g16 = 0; g16 < kq16; ++g16) {
-      double af[4][MT], bf[4][TN];
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int kk = 16 * g16 + 4 * s4 + fg;
-#pragma unroll
-        for (int i = 0; i < MT; ++i) af[s4][i] = sA[(16 * i + frow) * ldk + kk];
-#pragma unroll
-        for (int j = 0; j < TN; ++j) bf[s4][j] = sB[brow[j] + kk];
-      }
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-        for (int i = 0; i < MT; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s4][i], bf[s4][j], acc[i][j], 0, 0, 0);
-    }
-    // D layout: lane, element r -> row lane/16 + 4r, column lane%16
-    const long m0 = (long)t * BM;
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int n = 16 * (wave + 4 * j) + (lane & 15);
-      if (n >= p.N) continue;
-#pragma unroll
-      for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const long m = m0 + 16 * i + (lane >> 4) + 4 * r;
-          if (m < p.M) {
-            if constexpr (ROLE == 0)
-              p.C[(long)n * p.ldc + m] = acc[i][j][r];
-            else
-              p.C[m * p.ldc + n] = acc[i][j][r];
-          }
-        }
-    }
-    __syncthreads();  // every wave is done reading this tile
-    if (tn < tiles) stash();
-    __syncthreads();
   }
 }
 
@@ -855,7 +706,7 @@ hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4
   dim3 grid(n_blocks), block(64 * WGM * WGN);
   // roles 0/1: analysis / synthesis with the plain epilogue; 2/3: the same
   // with the general epilogue; 4: synthesis, general epilogue, A stored
-  // k-major
+  // k-major; 5: analysis with the general epilogue and A k-major
   switch (role) {
     case 0:
       hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, 0>), grid, block, 0, s, probs, items, n_items);
@@ -873,28 +724,32 @@ hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4
       hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, 1 | kGemmATrans>), grid, block, 0, s, probs, items,
                          n_items);
       break;
+    case 5:
+      hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, 1 | kGemmATrans>), grid, block, 0, s, probs, items,
+                         n_items);
+      break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-// Single problem with transposed / scaled operand layouts (no split-K):
-// role 0 takes kGemmCTrans | kGemmAScale, role 1 kGemmATrans.
+// Strided batch (see gemm_nt_f64_batched): role 0 stores C column-major
+// (kGemmCTrans), role 1 reads A k-major (kGemmATrans).
 template <int BM, int BN, int WGM, int WGN>
-hipError_t launch_mode_variant(int mode, const GemmF64Args &a, hipStream_t s) {
+hipError_t launch_batch_variant(int role, const GemmF64Args &a, hipStream_t s) {
   GemmF64Args g = a;
   g.tiles_m = (g.M + BM - 1) / BM;
-  const int tiles_n = (g.N + BN - 1) / BN;
-  g.k_per_split = ((g.K + kBK - 1) / kBK) * kBK;
-  g.c_split_stride = 0;
-  dim3 grid(g.tiles_m * tiles_n, 1), block(64 * WGM * WGN);
-  if (mode == (kGemmCTrans | kGemmAScale))
-    hipLaunchKernelGGL((gemm_nt_f64_kernel<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmAScale>), grid, block, 0, s, g,
-                       g.tiles_m * tiles_n);
-  else if (mode == kGemmATrans)
-    hipLaunchKernelGGL((gemm_nt_f64_kernel<1, BM, BN, WGM, WGN, kGemmATrans>), grid, block, 0, s, g,
-                       g.tiles_m * tiles_n);
+  const int per = g.tiles_m * ((g.N + BN - 1) / BN);
+  const long total = (long)per * g.batch;
+  if (total > INT_MAX) return hipErrorInvalidValue;
+  dim3 grid((unsigned)total), block(64 * WGM * WGN);
+  if (role == 0)
+    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans>), grid, block, 0, s, g, per,
+                       (int)total);
+  else if (role == 1)
+    hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans>), grid, block, 0, s, g, per,
+                       (int)total);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -902,7 +757,7 @@ hipError_t launch_mode_variant(int mode, const GemmF64Args &a, hipStream_t s) {
 
 typedef hipError_t (*gemm_f64_fn)(int, int, int, int, const double *, long, const double *, long, double *, long, int,
                                   long, hipStream_t);
-typedef hipError_t (*mode_f64_fn)(int, const GemmF64Args &, hipStream_t);
+typedef hipError_t (*batch_f64_fn)(int, const GemmF64Args &, hipStream_t);
 
 typedef hipError_t (*grouped_f64_fn)(int, const GemmF64Args *, const int4 *, int, int, hipStream_t);
 
@@ -910,13 +765,13 @@ struct F64Variant {
   int bm, bn, threads;
   gemm_f64_fn fn;
   grouped_f64_fn grouped;
-  mode_f64_fn mode;
+  batch_f64_fn batch;
 };
 
 #define YYG_F64_VARIANT(BM, BN, WM, WN)                                                                   \
   {                                                                                                        \
     BM, BN, 64 * WM * WN, launch_gemm_variant<BM, BN, WM, WN>, launch_grouped_variant<BM, BN, WM, WN>, \
-        launch_mode_variant<BM, BN, WM, WN>                                                                \
+        launch_batch_variant<BM, BN, WM, WN>                                                               \
   }
 
 const F64Variant kF64Variants[] = {
@@ -943,11 +798,10 @@ hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *pro
   return kF64Variants[variant].grouped(role, probs, items, n_items, n_blocks, s);
 }
 
-hipError_t launch_gemm_f64_mode(int variant, int mode, const GemmF64Args &g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+hipError_t launch_gemm_f64_batched(int variant, int role, const GemmF64Args &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (variant < 0 || variant >= gemm_f64_variant_count()) return hipErrorInvalidValue;
-  if ((mode & kGemmAScale) && (!g.Aw || g.aw_mod < 1)) return hipErrorInvalidValue;
-  return kF64Variants[variant].mode(mode, g, s);
+  return kF64Variants[variant].batch(role, g, s);
 }
 
 hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const double *A, long lda, const double *B,
@@ -1008,73 +862,6 @@ hipError_t launch_rotate_moments(const double *A, int nR, int L, const int *dofs
   dim3 grid(L + 1, (2 * L + 1 + 63) / 64, (2 * nR + 63) / 64);
   hipLaunchKernelGGL(rotate_moments_kernel, grid, dim3(256), 0, s, A, nR, Q, dofs, Dt, At);
   return hipGetLastError();
-}
-
-namespace {
-
-// A-tile elements per thread (BM x K <= 256 x this)
-constexpr int phi_emax(int BM) { return BM == 16 ? 16 : BM == 32 ? 20 : 36; }
-constexpr int kPhiLds = 156 * 1024;
-
-// LDS footprint and feasibility of a resident phi transform with tile BM
-int phi_ldk(int K) {
-  // k padded to whole 16-wide groups, odd row stride (no LDS bank
-  // conflicts across rows)
-  return (K + 15) / 16 * 16 + 1;
-}
-
-int phi_lds_bytes(int BM, int N, int K) {
-  const int npad = (N + 15) / 16 * 16;
-  return (npad + BM) * phi_ldk(K) * 8;
-}
-
-template <int ROLE, int BM, int TN>
-hipError_t launch_phi_bm_tn(const PhiArgs &a, int blocks, int lds, hipStream_t s) {
-  auto fn = phi_transform_kernel<ROLE, BM, TN, phi_emax(BM)>;
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
-      hipSuccess)
-    return hipGetLastError();
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
-  return hipGetLastError();
-}
-
-template <int ROLE, int BM>
-hipError_t launch_phi_bm(const PhiArgs &a, int blocks, int lds, hipStream_t s) {
-  switch ((a.npad / 16 + 3) / 4) {
-    case 1: return launch_phi_bm_tn<ROLE, BM, 1>(a, blocks, lds, s);
-    case 2: return launch_phi_bm_tn<ROLE, BM, 2>(a, blocks, lds, s);
-    case 3: return launch_phi_bm_tn<ROLE, BM, 3>(a, blocks, lds, s);
-    case 4: return launch_phi_bm_tn<ROLE, BM, 4>(a, blocks, lds, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-}  // namespace
-
-bool phi_transform_fits(int BM, int N, int K) {
-  if (BM != 16 && BM != 32 && BM != 64) return false;
-  if (N < 1 || K < 1 || N > 256) return false;
-  if ((long)BM * K > 256L * phi_emax(BM)) return false;
-  return phi_lds_bytes(BM, N, K) <= kPhiLds;
-}
-
-hipError_t launch_phi_transform(int role, int BM, PhiArgs a, int blocks, hipStream_t s) {
-  if (a.M <= 0 || a.N <= 0) return hipSuccess;
-  if (!phi_transform_fits(BM, a.N, a.K) || (role != 0 && role != 1) || blocks < 1) return hipErrorInvalidValue;
-  if (role == 0 && (a.lda != a.K || !a.w || a.w_mod < 1)) return hipErrorInvalidValue;
-  a.npad = (a.N + 15) / 16 * 16;
-  a.ldk = phi_ldk(a.K);
-  const int lds = phi_lds_bytes(BM, a.N, a.K);
-  const int tiles = (a.M + BM - 1) / BM;
-  blocks = std::min(blocks, tiles);
-  if (role == 0) {
-    if (BM == 16) return launch_phi_bm<0, 16>(a, blocks, lds, s);
-    if (BM == 32) return launch_phi_bm<0, 32>(a, blocks, lds, s);
-    return launch_phi_bm<0, 64>(a, blocks, lds, s);
-  }
-  if (BM == 16) return launch_phi_bm<1, 16>(a, blocks, lds, s);
-  if (BM == 32) return launch_phi_bm<1, 32>(a, blocks, lds, s);
-  return launch_phi_bm<1, 64>(a, blocks, lds, s);
 }
 
 int gemm_f64_variant_threads(int v) { return kF64Variants[v].threads; }

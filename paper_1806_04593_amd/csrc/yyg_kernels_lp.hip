@@ -121,8 +121,10 @@ __device__ __forceinline__ void gemm_lp_tile(const GemmLpArgs &g, int tm, int tn
       const int id = tid + c * NT;
       const int p = id / (BM * CPR), rem = id % (BM * CPR), row = rem / CPR, cc = rem % CPR;
       const int gr = m0 + row;
+      // clamped, valid address; rows past M are zeroed by stash (a load
+      // under a condition would be waited for before the next one issues)
       const V *src = reinterpret_cast<const V *>(A + p * a_plane + (long)min(gr, M - 1) * lda + k0 + cc * EPC);
-      ra[c] = gr < M ? *src : V{0u, 0u, 0u, 0u};
+      ra[c] = *src;
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
@@ -130,7 +132,7 @@ __device__ __forceinline__ void gemm_lp_tile(const GemmLpArgs &g, int tm, int tn
       const int p = id / (BN * CPR), rem = id % (BN * CPR), row = rem / CPR, cc = rem % CPR;
       const int gr = n0 + row;
       const V *src = reinterpret_cast<const V *>(B + p * b_plane + (long)min(gr, N - 1) * ldb + k0 + cc * EPC);
-      rb[c] = gr < N ? *src : V{0u, 0u, 0u, 0u};
+      rb[c] = *src;
     }
   };
   auto stash = [&](int buf) {
@@ -138,13 +140,13 @@ __device__ __forceinline__ void gemm_lp_tile(const GemmLpArgs &g, int tm, int tn
     for (int c = 0; c < CA; ++c) {
       const int id = tid + c * NT;
       const int p = id / (BM * CPR), rem = id % (BM * CPR), row = rem / CPR, cc = rem % CPR;
-      *reinterpret_cast<V *>(&As[buf][p][row * LDK + cc * EPC]) = ra[c];
+      *reinterpret_cast<V *>(&As[buf][p][row * LDK + cc * EPC]) = m0 + row < M ? ra[c] : V{0u, 0u, 0u, 0u};
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       const int id = tid + c * NT;
       const int p = id / (BN * CPR), rem = id % (BN * CPR), row = rem / CPR, cc = rem % CPR;
-      *reinterpret_cast<V *>(&Bs[buf][p][row * LDK + cc * EPC]) = rb[c];
+      *reinterpret_cast<V *>(&Bs[buf][p][row * LDK + cc * EPC]) = n0 + row < N ? rb[c] : V{0u, 0u, 0u, 0u};
     }
   };
 

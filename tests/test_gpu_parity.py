@@ -277,10 +277,10 @@ def test_separable_workloads_and_dense_agreement(name):
 
 @pytest.mark.parametrize("phase", [0, 1, 3, 4])
 def test_separable_every_phase_variant(phase):
-    """Every tile variant of each grouped / single-problem phase of the
-    separable form, on a ragged grid (n_r 37, 9 deg, lmax 11; 74 rows, so
-    the last 16-, 32- and 64-row tiles of the (row, colatitude) pairs are
-    partial), against the oracle on the full grid."""
+    """Every tile variant of each phase of the separable form (grouped theta
+    phases, phi phases as strided batches over the colatitudes), on a ragged
+    grid (n_r 37, 9 deg, lmax 11: 74-row problems, so every variant's last
+    row tile is partial), against the oracle on the full grid."""
     yyg = _yyg()
     desc = W.make_desc("edge", np.geomspace(1.0, 50.0, 38), 9.0, 11, 0.9, 0)
     rng = np.random.default_rng(12)
@@ -288,8 +288,7 @@ def test_separable_every_phase_variant(phase):
     ref = O.solve(*_oracle_args(desc), rho)
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
-    # the phi phases also run the LDS-resident transform (16-, 32-, 64-row tiles)
-    for v in range(N_F64_VARIANTS + (3 if phase in (0, 4) else 0)):
+    for v in range(N_F64_VARIANTS):
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
