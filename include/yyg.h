@@ -240,15 +240,17 @@ int yyg_plan_config(yyg_grid *g, int precision, int var_ana, int split_ana, int 
 int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
 
 /* Tile variant (numbered as for yyg_plan_info) of one phase of the
- * separable form: 0 phi analysis, 1 theta analysis, 3 theta synthesis,
- * 4 phi synthesis (phase 2, the moment rotation, has no tile).  Needs the
- * separable form built
+ * separable form: 0 phi analysis, 1 theta analysis, 2 rotation of the other
+ * patch's moments (Yin-Yang grids; no work on a polar grid), 3 theta
+ * synthesis, 4 phi synthesis.  variant in [0, 2V), V = the number of FP64
+ * tile variants: V + v is tile v with three stages of operand loads in
+ * flight instead of one.  Needs the separable form built
  * (yyg_set_method); synchronises the device.  For tests and expert tuning;
- * yyg_autotune chooses all four. */
+ * yyg_autotune chooses all of them. */
 int yyg_sep_config(yyg_grid *g, int phase, int variant);
 
 /* variants[0..4] = the separable form's tile variant per phase (-1 for
- * phase 2, and for every phase before the form is built). */
+ * phase 2 on a polar grid, and for every phase before the form is built). */
 int yyg_sep_info(const yyg_grid *g, int *variants, int n);
 
 /* Batched solves of several plans (uneven n_r <= 1024, angular sizes and

@@ -62,7 +62,8 @@ struct yyg_grid {
   double *d_coef = nullptr;  // radial coefficients [n_r][L+1][4]
   int *d_qdeg = nullptr;     // degree l of each column
   double *d_part = nullptr;  // split-K partial moments [nsplit][P n_r][Q]
-  double *d_Ahat = nullptr;  // reduced moments (sqrt(N) scaled) [P n_r][Q]
+  double *d_Ahat = nullptr;  // reduced moments (sqrt(N) scaled) [P n_r][Q], or [Q][P n_r] after a separable solve
+  bool ahat_cols = false;    // d_Ahat holds the column-major layout
   double *d_U = nullptr;     // synthesis operand [P n_r][ldy]
   double *d_rho_owned = nullptr;
   const double *rho = nullptr;
@@ -94,24 +95,21 @@ struct yyg_grid {
     double *trig = nullptr;  // phi-synthesis basis [n_p][ldm]
     double *T2 = nullptr;    // theta-analysis basis [mc][l][n_t]: sqrt(N) T_j^(lm)
     double *P2 = nullptr;    // theta-synthesis basis [mc][j][ldl]: sqrt(N) P_l^m(cos t_j)
-    double *Dt = nullptr;    // transposed rotation blocks, per degree l: [b][a]
-    int *dofs = nullptr;     // offset of each degree's block in Dt
+    double *DI = nullptr;    // per degree l: [identity; D_l] (2d x d), one after the other
     double *X2 = nullptr;    // phi-analysis output [mc][j][row]
     double *V = nullptr;     // theta-synthesis output [mc][j][row]
+    double *At = nullptr;    // own + rotated other moments, column-major [Q][row] (Yin-Yang)
     double *Ut = nullptr;    // potential coefficients of own + rotated other moments [mc][l][row]
+    double *coefS = nullptr; // radial recurrence coefficients [L+1][4][n_r]
     // phi phases, strided batches over the colatitudes j: analysis (C
     // stored column-major) and synthesis (A stored k-major)
     yyg::GemmF64Args phi_ana{}, phi_syn{};
-    // grouped problems: theta analysis [2L+1], theta synthesis [2L+1]
-    yyg::GemmF64Args *probs = nullptr;
-    // phases: 0 phi analysis, 1 theta analysis, 2 (unused: the rotation is
-    // rotate_moments_kernel), 3 theta synthesis, 4 phi synthesis; items
-    // only for the grouped phases 1 and 3
-    int4 *items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    int n_items[5] = {0, 0, 0, 0, 0};
-    int blocks[5] = {0, 0, 0, 0, 0};
-    int var[5] = {3, 3, 0, 3, 3};
-    std::vector<yyg::GemmF64Args> h_probs;
+    // theta phases and rotation: one launch each over their problems
+    yyg::SepPhaseArgs args{};
+    // tile variant per phase (0 phi analysis, 1 theta analysis, 2 moment
+    // rotation, 3 theta synthesis, 4 phi synthesis); V + v = tile v with
+    // the deep prefetch
+    int var[5] = {3, 3, 9, 3, 3};
   } sep;
 
   bool timing = false;
@@ -153,10 +151,8 @@ void free_grid(yyg_grid *g) {
   if (g->d_eA) (void)hipFree(g->d_eA);
   if (g->d_eU) (void)hipFree(g->d_eU);
   {
-    void *b[] = {g->sep.Wcs,      g->sep.trig,     g->sep.T2,       g->sep.P2,
-                 g->sep.Dt,       g->sep.X2,       g->sep.V,        g->sep.Ut,       g->sep.probs,
-                 g->sep.items[0], g->sep.items[1], g->sep.items[2], g->sep.items[3], g->sep.items[4],
-                 g->sep.dofs};
+    void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2, g->sep.P2, g->sep.DI,
+                 g->sep.X2,  g->sep.V,    g->sep.Ut, g->sep.coefS, g->sep.At};
     for (void *x : b)
       if (x) (void)hipFree(x);
   }
@@ -272,50 +268,23 @@ std::map<std::string, std::pair<int, int>> read_tune_cache(const char *path) {
 
 namespace {
 
-// Tile variant v for separable phase r; for the grouped phases (theta
-// analysis 1, theta synthesis 3) also their work items, largest K first.
-int sep_set_items(yyg_grid *g, int r, int v) {
-  auto &S = g->sep;
-  const int nmc = 2 * g->L + 1;
-  if (v < 0 || v >= yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
-  S.var[r] = v;
-  if (r != 1 && r != 3) return YYG_OK;
-  const int first = r == 1 ? 0 : nmc;
-  int bm, bn;
-  yyg::gemm_f64_variant_tile(v, &bm, &bn);
-  std::vector<std::pair<int, int4>> work;
-  for (int pi = first; pi < first + nmc; ++pi) {
-    const yyg::GemmF64Args &a = S.h_probs[pi];
-    const int tm = (a.M + bm - 1) / bm, tn = (a.N + bn - 1) / bn;
-    for (int b = 0; b < tn; ++b)
-      for (int i = 0; i < tm; ++i) work.push_back({a.K, int4{pi, i, b, 0}});
-  }
-  std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
-  std::vector<int4> items(work.size());
-  for (size_t i = 0; i < work.size(); ++i) items[i] = work[i].second;
-  if (S.items[r]) (void)hipFree(S.items[r]);
-  S.items[r] = nullptr;
-  S.n_items[r] = (int)items.size();
-  if (dmalloc(&S.items[r], items.size()) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
-  if (hipMemcpy(S.items[r], items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipGetLastError();
-    return YYG_ERR_DEVICE;
-  }
-  int cus = 256;
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device);
-  const long lds = 2L * (bm + bn) * 18 * 8;
-  const int per_cu = (int)std::max(1L, std::min(4L, 160L * 1024 / lds));
-  S.blocks[r] = std::max(1, std::min(S.n_items[r], cus * per_cu));
+// Tile variant of separable phase r: v < V the tile v, V + v the same
+// with three stages of loads in flight (V = the FP64 tile variants).
+int sep_set_variant(yyg_grid *g, int r, int v) {
+  if (r < 0 || r > 4 || v < 0 || v >= 2 * yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
+  g->sep.var[r] = v;
   return YYG_OK;
 }
 
 hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
-  if (r == 0) return yyg::launch_gemm_f64_batched(S.var[0], 0, S.phi_ana, s);
-  if (r == 4) return yyg::launch_gemm_f64_batched(S.var[4], 1, S.phi_syn, s);
-  if (S.n_items[r] == 0) return hipSuccess;
-  // grouped theta phases: general epilogue, A read k-major (X2, Ut)
-  return yyg::launch_gemm_f64_grouped(S.var[r], r == 1 ? 5 : 4, S.probs, S.items[r], S.n_items[r], S.blocks[r], s);
+  const int nv = yyg::gemm_f64_variant_count();
+  const int v = S.var[r] % nv;
+  const bool deep = S.var[r] >= nv;
+  if (r == 0) return yyg::launch_gemm_f64_batched(v, deep ? yyg::kRoleDeep : 0, S.phi_ana, s);
+  if (r == 4) return yyg::launch_gemm_f64_batched(v, 1 + (deep ? yyg::kRoleDeep : 0), S.phi_syn, s);
+  if (r == 2 && g->n_patch != 2) return hipSuccess;  // one patch: nothing to rotate
+  return yyg::launch_gemm_f64_sep(v, r, deep, S.args, s);
 }
 
 // Point the phi phases at this solve's density and potential (kernel
@@ -334,9 +303,17 @@ int sep_build(yyg_grid *g) {
   S.ldk = round_up(np, 16);
   S.ldm = round_up(nmc, 16);
   S.ldl = round_up(L + 1, 16);
-  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D;
+  if (yyg::radial_scan_q_lds(g->n_r, g->n_patch) > yyg::kScanQMaxLds) return YYG_ERR_UNSUPPORTED;
+  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS;
   std::vector<int> dofs;
   try {
+    coef.resize((size_t)4 * g->n_r * (L + 1));
+    yyg::radial_coefficients(g->n_r, g->r_edges.data(), L, coef.data());
+    coefS.resize(coef.size());
+    for (int n = 0; n < g->n_r; ++n)
+      for (int l = 0; l <= L; ++l)
+        for (int k = 0; k < 4; ++k)
+          coefS[((size_t)l * 4 + k) * g->n_r + n] = coef[((size_t)n * (L + 1) + l) * 4 + k];
     for (int l = 0, off = 0; l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) dofs.push_back(off);
     CSt.resize((size_t)nmc * S.ldk);
     yyg::separable_cs(g->geom, L, S.ldk, CSt.data());
@@ -363,13 +340,17 @@ int sep_build(yyg_grid *g) {
           P2[((size_t)mc * nt + j) * S.ldl + l] = P[(size_t)j * Q + l * l + mc];
         }
     }
+    // per degree: [identity; D_l], so that the rotation phase adds a patch's
+    // own moments in the same contraction
     std::vector<double> D0(yyg::rotation_blocks_size(L));
     yyg::rotation_blocks(L, D0.data());
-    D.resize(D0.size());
-    for (int l = 0, off = 0; l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) {
+    D.assign(2 * D0.size(), 0.0);
+    for (int l = 0; l <= L; ++l) {
       const int d = 2 * l + 1;
+      double *blk = D.data() + 2 * (size_t)dofs[l];
+      for (int b = 0; b < d; ++b) blk[(size_t)b * d + b] = 1.0;
       for (int a = 0; a < d; ++a)
-        for (int b = 0; b < d; ++b) D[off + b * d + a] = D0[off + a * d + b];
+        for (int b = 0; b < d; ++b) blk[(size_t)(d + a) * d + b] = D0[dofs[l] + (size_t)a * d + b];
     }
   } catch (const std::bad_alloc &) {
     return YYG_ERR_OUT_OF_MEMORY;
@@ -379,12 +360,12 @@ int sep_build(yyg_grid *g) {
   if (st == YYG_OK) st = dmalloc(&S.trig, trig.size());
   if (st == YYG_OK) st = dmalloc(&S.T2, T2.size());
   if (st == YYG_OK) st = dmalloc(&S.P2, P2.size());
-  if (st == YYG_OK) st = dmalloc(&S.Dt, D.size());
+  if (st == YYG_OK) st = dmalloc(&S.DI, D.size());
   if (st == YYG_OK) st = dmalloc(&S.X2, (size_t)nmc * MJ);
   if (st == YYG_OK) st = dmalloc(&S.V, (size_t)nmc * MJ);
   if (st == YYG_OK) st = dmalloc(&S.Ut, (size_t)nmc * (L + 1) * M);
-  if (st == YYG_OK) st = dmalloc(&S.probs, 2 * (size_t)nmc);
-  if (st == YYG_OK) st = dmalloc(&S.dofs, dofs.size());
+  if (st == YYG_OK && g->n_patch == 2) st = dmalloc(&S.At, (size_t)M * Q);
+  if (st == YYG_OK) st = dmalloc(&S.coefS, coefS.size());
   if (st != YYG_OK) return st;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
@@ -394,8 +375,8 @@ int sep_build(yyg_grid *g) {
   chk(hipMemcpy(S.trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.T2, T2.data(), T2.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.P2, P2.data(), P2.size() * sizeof(double), hipMemcpyHostToDevice));
-  chk(hipMemcpy(S.Dt, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
-  chk(hipMemcpy(S.dofs, dofs.data(), dofs.size() * sizeof(int), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.DI, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.coefS, coefS.data(), coefS.size() * sizeof(double), hipMemcpyHostToDevice));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;
@@ -410,61 +391,38 @@ int sep_build(yyg_grid *g) {
   S.phi_syn = yyg::GemmF64Args{(int)M, np, nmc, S.V, MJ, S.trig, S.ldm, nullptr, (long)nt * np, np, kround(nmc), 1};
   S.phi_syn.batch = nt;
   S.phi_syn.a_batch = M;
-  S.h_probs.assign(2 * (size_t)nmc, yyg::GemmF64Args{});
-  for (int mc = 0; mc < nmc; ++mc) {
-    const int m = (mc + 1) / 2, nl = L + 1 - m;
-    // A[row][l^2 + mc] = sum_j X2[mc][j][row] T2[mc][l][j], l >= m   (A stored k-major)
-    yyg::GemmF64Args &a = S.h_probs[mc];
-    a = yyg::GemmF64Args{(int)M, nl, nt, S.X2 + (long)mc * MJ, M, S.T2 + ((long)mc * (L + 1) + m) * nt, nt,
-                         g->d_Ahat + mc, Q, 0, kround(nt), 1};
-    a.c_sq = m;
-    // V[mc][j][row] = sum_{l >= m} Ut[mc][l][row] P2[mc][j][l]      (A stored k-major, C column-major)
-    yyg::GemmF64Args &b = S.h_probs[nmc + mc];
-    b = yyg::GemmF64Args{(int)M, nt, nl, S.Ut + ((long)mc * (L + 1) + m) * M, M, S.P2 + (long)mc * nt * S.ldl + m,
-                         S.ldl, S.V + (long)mc * MJ, 1, 0, kround(nl), 1};
-    b.ldc_c = M;
-  }
-  if (hipMemcpy(S.probs, S.h_probs.data(), S.h_probs.size() * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice) !=
-      hipSuccess) {
-    (void)hipGetLastError();
-    return YYG_ERR_DEVICE;
-  }
-  for (int r = 0; r < 5; ++r) {
-    int st2 = sep_set_items(g, r, S.var[r]);
-    if (st2 != YYG_OK) return st2;
-  }
+  // theta analysis, rotation (Yin-Yang) and theta synthesis: problem
+  // operands derived in the kernels from these
+  S.args = yyg::SepPhaseArgs{L,    g->n_r, g->n_patch, nt,  S.ldl, S.X2, S.T2, S.P2,
+                             S.Ut, S.DI,   g->d_Ahat,  S.At, S.V};
   S.ready = true;
   return YYG_OK;
 }
 
-// Separable solve: phi analysis (one GEMM over the (row, colatitude)
-// pairs), theta analysis (grouped GEMM per azimuthal column) into the
-// moments, the other patch's moments rotated in (Yin-Yang), radial scan
-// into the azimuthal-column-major coefficients, theta synthesis (grouped),
-// phi synthesis.
+// Separable solve: phi analysis (a strided batch over the colatitudes),
+// theta analysis (one problem per azimuthal column) into the column-major
+// moments, own plus rotated other moments (Yin-Yang; one problem per degree
+// and patch), radial scan into the azimuthal-column-major coefficients,
+// theta synthesis (one problem per azimuthal column), phi synthesis (a
+// strided batch over the colatitudes).
 hipError_t sep_solve(yyg_grid *g, hipStream_t s) {
   auto &S = g->sep;
-  const int Q = g->Q;
-  const long M = (long)g->n_patch * g->n_r;
   hipError_t e = hipSuccess;
+  g->ahat_cols = true;
   int t = timing_begin(g, 4, s);
   e = sep_launch_phase(g, 0, s);
   timing_end(g, t, s);
   // the scan's input: the moments, or with two patches their rotated sum
-  const double *scan_in = g->d_Ahat;
+  const double *scan_in = g->n_patch == 2 ? S.At : g->d_Ahat;
   if (e == hipSuccess) {
     t = timing_begin(g, 5, s);
     e = sep_launch_phase(g, 1, s);
-    if (e == hipSuccess && g->n_patch == 2) {
-      e = yyg::launch_rotate_moments(g->d_Ahat, g->n_r, g->L, S.dofs, S.Dt, g->d_part, s);
-      scan_in = g->d_part;
-    }
+    if (e == hipSuccess) e = sep_launch_phase(g, 2, s);
     timing_end(g, t, s);
   }
   if (e == hipSuccess) {
     t = timing_begin(g, 1, s);
-    e = yyg::launch_radial_scan(scan_in, 1, M * Q, nullptr, g->d_coef, g->d_qdeg, g->n_r, Q, g->L, -g->G, g->d_U,
-                                g->ldy, g->n_patch, s, S.Ut);
+    e = yyg::launch_radial_scan_q(scan_in, S.coefS, g->d_qdeg, g->n_r, g->L, -g->G, g->n_patch, S.Ut, s);
     timing_end(g, t, s);
   }
   if (e == hipSuccess) {
@@ -1092,6 +1050,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
     }
     return YYG_OK;
   }
+  g->ahat_cols = false;
   const int nsplit = lp ? g->lp[precision - 1].nsplit : g->nsplit;
   if (lp) {
     // split the density into operand planes (rows scaled for FP16)
@@ -1166,6 +1125,11 @@ int yyg_get_moments(yyg_grid *g, double *A_host) {
       hipMemcpy(A_host, g->d_Ahat, (size_t)M * g->Q * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;
+  }
+  if (g->ahat_cols) {
+    std::vector<double> t(A_host, A_host + M * g->Q);
+    for (long r = 0; r < M; ++r)
+      for (int q = 0; q < g->Q; ++q) A_host[r * g->Q + q] = t[q * M + r];
   }
   for (long r = 0; r < M; ++r)
     for (int q = 0; q < g->Q; ++q) A_host[r * g->Q + q] /= g->nrm_q[q];
@@ -1376,19 +1340,19 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     }
     if (st3 == YYG_OK) st3 = sep_set_pointers(g, g->rho ? g->rho : rho_t, phi_t, s);
     for (int r = 0; r < 5 && st3 == YYG_OK; ++r) {
-      if (r == 2) continue;  // the rotation is not a GEMM phase
+      if (r == 2 && g->n_patch != 2) continue;  // one patch: no rotation
       double best = 1e30;
       int bv = g->sep.var[r];
-      for (int v = 0; v < yyg::gemm_f64_variant_count() && st3 == YYG_OK; ++v) {
-        st3 = sep_set_items(g, r, v);
+      for (int v = 0; v < 2 * yyg::gemm_f64_variant_count() && st3 == YYG_OK; ++v) {
+        st3 = sep_set_variant(g, r, v);
         if (st3 != YYG_OK) break;
-        double t = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 3);
+        double t = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 5);
         if (t < best) {
           best = t;
           bv = v;
         }
       }
-      if (st3 == YYG_OK) st3 = sep_set_items(g, r, bv);
+      if (st3 == YYG_OK) st3 = sep_set_variant(g, r, bv);
     }
     (void)hipStreamSynchronize(s);
     if (phi_t) (void)hipFree(phi_t);
@@ -1462,21 +1426,22 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n) {
 }
 
 int yyg_sep_config(yyg_grid *g, int phase, int variant) {
-  if (!g || (phase != 0 && phase != 1 && phase != 3 && phase != 4)) return YYG_ERR_INVALID_ARG;
+  if (!g || phase < 0 || phase > 4) return YYG_ERR_INVALID_ARG;
   if (!g->sep.ready) return YYG_ERR_NOT_READY;
-  if (variant < 0 || variant >= yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
+  if (variant < 0 || variant >= 2 * yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   if (hipDeviceSynchronize() != hipSuccess) {  // the work items may be in use
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;
   }
-  return sep_set_items(g, phase, variant);
+  return sep_set_variant(g, phase, variant);
 }
 
 int yyg_sep_info(const yyg_grid *g, int *variants, int n) {
   if (!g || !variants || n < 1) return YYG_ERR_INVALID_ARG;
-  for (int i = 0; i < n && i < 5; ++i) variants[i] = (i == 2 || !g->sep.ready) ? -1 : g->sep.var[i];
+  for (int i = 0; i < n && i < 5; ++i)
+    variants[i] = (!g->sep.ready || (i == 2 && g->n_patch != 2)) ? -1 : g->sep.var[i];
   return YYG_OK;
 }
 
@@ -1567,6 +1532,7 @@ int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_p
   // a graph cannot be recorded on the legacy default stream: use the
   // batch's own blocking stream, which that stream orders against
   hipStream_t s = stream ? as_stream(stream) : b->stream;
+  for (int f = 0; f < n; ++f) b->grids[f]->ahat_cols = false;
   bool changed = false;
   for (int f = 0; f < n; ++f)
     if (b->rho[f] != d_rho[f] || b->phi[f] != d_phi[f]) changed = true;

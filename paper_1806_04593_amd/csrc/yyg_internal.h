@@ -18,8 +18,11 @@ struct GemmF64Args {
   int k_per_split;      // multiple of the stage width (16)
   int tiles_m;
   long ldc_c = 1;       // column stride of C
-  int c_sq = -1;        // >= 0: column n of C lands at (n + c_sq)^2 (degree-major q index)
-  int c_add = 0;        // 1: C += A.B^T instead of C = A.B^T
+  int c_sq = -1;        // >= 0: column n of C lands at column (n + c_sq)^2 (degree-major q index)
+  // kGemmSplitA: A(m, k) for k >= k_split is read at column k - k_split,
+  // a_off elements further on
+  int k_split = 0;
+  long a_off = 0;
   // strided batch (launch_gemm_f64_batched): problem z reads A + z a_batch,
   // B + z b_batch and writes C + z c_split_stride
   int batch = 1;
@@ -30,10 +33,35 @@ struct GemmF64Args {
 //  kGemmATrans  A is stored k-major: element (m, k) at A[k * lda + m]
 //  kGemmCTrans  C is stored column-major: element (m, n) at C[n * ldc + m]
 //  kGemmBatch   the split index selects a problem of a strided batch
-enum { kGemmATrans = 2, kGemmCTrans = 4, kGemmBatch = 8 };
+//  kGemmBTrans  B is stored k-major: element (n, k) at B[k * ldb + n]
+//  kGemmDeep    three stages of loads in flight instead of one (short K)
+//  kGemmSplitA  (with kGemmATrans) A's columns from k_split on come from a
+//               second block a_off elements away
+enum { kGemmATrans = 2, kGemmCTrans = 4, kGemmBatch = 8, kGemmBTrans = 16, kGemmDeep = 32, kGemmSplitA = 64 };
+// role offset of the kGemmDeep forms of the batched roles
+constexpr int kRoleDeep = 16;
+
+// The separable form's theta phases and moment rotation (one launch each;
+// problem z of a phase derives its operands from these arguments).
+struct SepPhaseArgs {
+  int L, nR, P, nt;  // degree, shells, patches, colatitudes
+  long ldl;          // row stride of P2
+  const double *X2;  // phi-analysis output [mc][j][row]
+  const double *T2;  // theta-analysis basis [mc][l][n_t]
+  const double *P2;  // theta-synthesis basis [mc][j][ldl]
+  const double *Ut;  // potential coefficients [mc][l][row]
+  const double *DI;  // per degree l: [identity; D_l], (2d) x d, one after the other
+  double *Ahat;      // column-major moments [Q][row] (theta analysis output)
+  double *At;        // own + rotated other moments [Q][row] (Yin-Yang)
+  double *V;         // theta-synthesis output [mc][j][row]
+};
+// phase 1 theta analysis, 2 rotation (two patches), 3 theta synthesis;
+// deep = kGemmDeep.
+hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s);
 
 // Strided batch of g.batch equal-shape problems, whole K each: role 0
-// stores C column-major, role 1 reads A k-major (plain epilogue otherwise).
+// stores C column-major, role 1 reads A k-major (plain epilogue otherwise);
+// roles + kRoleDeep: the same with kGemmDeep.
 hipError_t launch_gemm_f64_batched(int variant, int role, const GemmF64Args &g, hipStream_t s);
 
 // FP64 NT GEMM C = A . B^T in one of several tile shapes ("variants");
@@ -46,9 +74,7 @@ hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const 
 // Persistent grouped FP64 GEMM: n_blocks blocks walk `items` = (problem,
 // tm, tn, split) over the problems' tiles of the variant's shape.  role 0/1
 // = analysis / synthesis with the plain epilogue, 2/3 with the general one
-// (ldc_c, c_sq, c_add honoured), 4 = synthesis with the general epilogue
-// and A stored k-major (kGemmATrans), 5 = analysis with the general
-// epilogue and A stored k-major.
+// (ldc_c and c_sq honoured).
 hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *probs, const int4 *items, int n_items,
                                   int n_blocks, hipStream_t s);
 
@@ -65,8 +91,6 @@ struct ScanArgs {
   double *U;
   long ldu;
   int cross;  // also write each row into the other patch's cross columns [Q, 2Q)
-  double *Ut = nullptr;  // if set: write U to Ut[mc][l][row] (q = l^2 + mc) instead
-  long ut_rows = 0;      // rows of Ut (patches x nR)
 };
 
 // Grouped scan over several plans (each n_r <= 1024): items = (problem,
@@ -76,12 +100,10 @@ hipError_t launch_radial_scan_grouped(const ScanArgs *probs, const int4 *items, 
 
 // patches = 2 (Yin-Yang: rows of patch p also land in the cross columns of
 // the other patch's rows) or 1 (polar grid: own columns only)
-// Ahat may be null (no copy of the reduced moments).  With Ut set the
-// potential coefficients go to Ut[mc][l][row] (azimuthal-column-major,
-// rows contiguous) instead of U; needs nR <= 1024.
+// Ahat may be null (no copy of the reduced moments; nsplit must be 1).
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
                               const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu, int patches,
-                              hipStream_t s, double *Ut = nullptr);
+                              hipStream_t s);
 
 hipError_t launch_expand_analysis_basis(const double *w, const double *Tt, const double *CS, int n_t, int n_p,
                                         int Q, double *Bt, long ldb, hipStream_t s);
@@ -136,11 +158,15 @@ hipError_t launch_split_rows(int prec, const double *X, long ldx, int rows, int 
                              long ldp, long plane_stride, hipStream_t s);
 
 // Separable-form kernels (see yyg_kernels.hip).
-// At[row][q] = A[row][q] + the other patch's moments of the same shell
-// rotated degree by degree (rows: 2 nR, Yin then Yang); dofs[l] = offset of
-// the transposed rotation block of degree l in Dt.
-hipError_t launch_rotate_moments(const double *A, int nR, int L, const int *dofs, const double *Dt, double *At,
-                                 hipStream_t s);
+// Radial scan of column-major moments X[q][patches nR] (one block per
+// column, one wave per patch) into Ut[mc][l][patches nR]; coefS = the
+// recurrence coefficients as [L+1][4][nR].  The column and its coefficients
+// sit in LDS: radial_scan_q_lds bytes, at most kScanQMaxLds
+// (hipErrorInvalidValue beyond).
+constexpr size_t kScanQMaxLds = 160 * 1024;
+size_t radial_scan_q_lds(int nR, int patches);
+hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int *qdeg, int nR, int L, double negG,
+                                int patches, double *Ut, hipStream_t s);
 int gemm_f64_variant_threads(int v);
 
 

@@ -34,9 +34,12 @@ __device__ __forceinline__ double keep_if(bool keep, double x) { return x * (kee
 constexpr int kBK = 16, kPad = 2, kLDK = kBK + kPad;
 // Stages of A and B held in registers ahead of the LDS stage being
 // multiplied: a stage's global loads are issued kPF stages before its LDS
-// store.  Measured on MI355X, three stages were slower than one for every
-// contraction of the solver (the registers cost occupancy).
-constexpr int kPF = 1;
+// store.  Measured on MI355X, three stages were slower than one for the
+// long dense contractions (the registers cost occupancy); the short
+// contractions of the separable form (K of a few stages) can ask for
+// kDeepPF with the kGemmDeep mode bit, so that their loads are in flight
+// together.
+constexpr int kPF = 1, kDeepPF = 3;
 
 // Logical tile of a block so that the blocks one XCD receives (the hardware
 // hands blocks to the 8 XCDs round-robin) form a contiguous run of tiles in
@@ -52,15 +55,18 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 // Block tile BM x BN, WGM x WGN waves, each wave a (BM/WGM) x (BN/WGN) grid
 // of 16 x 16 MFMA tiles; computes output tile (tm, tn) over split z.
 // MODE bit 1 selects the general epilogue (column stride, degree-major
-// column index, accumulate); the plain one writes C[row * ldc + col].  The
-// other bits (kGemmATrans, kGemmCTrans) change the operand layouts as
-// documented with GemmF64Args.
+// column index); the plain one writes C[row * ldc + col].  The other bits
+// change the operand layouts and the prefetch depth as documented with
+// GemmF64Args.
 template <int BM, int BN, int WGM, int WGN, int MODE>
 __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int tn, int z) {
   constexpr bool GEN = (MODE & 1) != 0;
   constexpr bool AT = (MODE & kGemmATrans) != 0;
   constexpr bool CT = (MODE & kGemmCTrans) != 0;
   constexpr bool BATCH = (MODE & kGemmBatch) != 0;
+  constexpr bool BT = (MODE & kGemmBTrans) != 0;
+  constexpr bool SPLIT = (MODE & kGemmSplitA) != 0;
+  static_assert(!SPLIT || AT, "the split A operand is stored k-major");
 
   const int M = g.M, N = g.N, K = g.K;
   const double *__restrict__ A = g.A + (BATCH ? z * g.a_batch : 0L);
@@ -73,10 +79,10 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   // Stage loads.  When a thread's share of a tile stage divides the 16-wide
   // stage, it reads one contiguous run of k in one row (one row pointer);
   // otherwise element e = tid + i*NT sits at row e / 16, column e % 16.
-  // A stored k-major loads along m instead: element e = tid + i*NT at
-  // k = e / BM, m = e % BM.
+  // An operand stored k-major loads along m (n) instead: element
+  // e = tid + i*NT at k = e / BM, m = e % BM.
   constexpr bool RUN_A = !AT && (BM * kBK) % NT == 0 && kBK % ((BM * kBK) / NT) == 0;
-  constexpr bool RUN_B = (BN * kBK) % NT == 0 && kBK % ((BN * kBK) / NT) == 0;
+  constexpr bool RUN_B = !BT && (BN * kBK) % NT == 0 && kBK % ((BN * kBK) / NT) == 0;
   constexpr int EA = RUN_A ? (BM * kBK) / NT : (BM * kBK + NT - 1) / NT;
   constexpr int EB = RUN_B ? (BN * kBK) / NT : (BN * kBK + NT - 1) / NT;
   __shared__ double As[2][BM * kLDK];
@@ -97,7 +103,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  constexpr int PF = kPF;
+  constexpr int PF = (MODE & kGemmDeep) ? kDeepPF : kPF;
   double ra[PF][EA], rb[PF][EB];
   // run mapping: this thread's row and first column
   const int arow = RUN_A ? tid / (kBK / EA) : 0, acol = RUN_A ? (tid % (kBK / EA)) * EA : 0;
@@ -116,8 +122,16 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
     } else if constexpr (AT) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
-        const int e = tid + i * NT, kk = k0 + e / BM, gm = m0 + e % BM;
-        ra[i] = A[(long)min(kk, K - 1) * lda + min(gm, M - 1)];
+        const int e = tid + i * NT, gm = m0 + e % BM;
+        int kc = min(k0 + e / BM, K - 1);
+        long off = 0;
+        if constexpr (SPLIT) {
+          if (kc >= g.k_split) {
+            kc -= g.k_split;
+            off = g.a_off;
+          }
+        }
+        ra[i] = A[(long)kc * lda + off + min(gm, M - 1)];
       }
     } else {
 #pragma unroll
@@ -129,6 +143,12 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
     if constexpr (RUN_B) {
 #pragma unroll
       for (int i = 0; i < EB; ++i) rb[i] = pb[min(k0 + bcol + i, K - 1)];
+    } else if constexpr (BT) {
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const int e = tid + i * NT, kk = k0 + e / BN, gn = n0 + e % BN;
+        rb[i] = B[(long)min(kk, K - 1) * ldb + min(gn, N - 1)];
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
@@ -157,6 +177,12 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
     if constexpr (RUN_B) {
 #pragma unroll
       for (int i = 0; i < EB; ++i) Bs[buf][brow * kLDK + bcol + i] = (vb && k0 + bcol + i < kend) ? rb[i] : 0.0;
+    } else if constexpr (BT) {
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const int e = tid + i * NT, kk = k0 + e / BN, gn = n0 + e % BN;
+        if (e < BN * kBK) Bs[buf][(e % BN) * kLDK + e / BN] = (gn < N && kk < kend) ? rb[i] : 0.0;
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
@@ -229,9 +255,8 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
         const int row = m0 + wm * (BM / WGM) + i * 16 + orow + 4 * r;
         if (row < M && col < N) {
           if constexpr (GEN) {
-            const long cc = g.c_sq < 0 ? (long)col * g.ldc_c : (long)(col + g.c_sq) * (col + g.c_sq);
-            double *c = &C[(long)row * ldc + cc];
-            *c = g.c_add ? *c + acc[i][j][r] : acc[i][j][r];
+            const long cc = g.c_sq < 0 ? (long)col : (long)(col + g.c_sq) * (col + g.c_sq);
+            C[(long)row * ldc + cc * g.ldc_c] = acc[i][j][r];
           } else if constexpr (CT) {
             C[(long)col * ldc + row] = acc[i][j][r];
           } else {
@@ -261,6 +286,66 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_batched(GemmF64Arg
   gemm_f64_tile<BM, BN, WGM, WGN, MODE | kGemmBatch>(g, tile % g.tiles_m, tile / g.tiles_m, z);
 }
 
+// The theta phases and the moment rotation of the separable form: one
+// problem per blockIdx.z, its shapes and operands derived from the phase
+// arguments (no descriptor loads ahead of the operand loads).
+//  PHASE 1, theta analysis, z = mc (m = (mc + 1) / 2): the column-major
+//    moments A[(l^2 + mc)][row] = sum_j X2[mc][j][row] T2[mc][l][j], l >= m.
+//  PHASE 2, rotation, z = 2 (L - l) + p: At[l^2 + b][p nR + n] =
+//    sum_{k < 2d} [A_own | A_other](n, k) DI_l[k][b], d = 2l + 1, where
+//    DI_l = [identity; D_l] and A_other is the other patch's rows.
+//  PHASE 3, theta synthesis, z = mc: V[mc][j][row] =
+//    sum_{l >= m} P2[mc][j][l] Ut[mc][l][row].
+template <int PHASE, int BM, int BN, int WGM, int WGN, int MODE>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_sep_phase(SepPhaseArgs a) {
+  const long Mr = (long)a.P * a.nR, MJ = Mr * a.nt;
+  const int z = blockIdx.z;
+  GemmF64Args g{};
+  if constexpr (PHASE == 1) {
+    const int mc = z, m = (mc + 1) >> 1;
+    g.M = (int)Mr;
+    g.N = a.L + 1 - m;
+    g.K = a.nt;
+    g.A = a.X2 + mc * MJ;
+    g.lda = Mr;
+    g.B = a.T2 + ((long)mc * (a.L + 1) + m) * a.nt;
+    g.ldb = a.nt;
+    g.C = a.Ahat + mc * Mr;
+    g.ldc = 1;
+    g.ldc_c = Mr;
+    g.c_sq = m;
+  } else if constexpr (PHASE == 2) {
+    const int l = a.L - (z >> 1), p = z & 1, d = 2 * l + 1;
+    g.M = a.nR;
+    g.N = d;
+    g.K = 2 * d;
+    g.A = a.Ahat + (long)l * l * Mr + (long)p * a.nR;
+    g.lda = Mr;
+    g.k_split = d;
+    g.a_off = (long)(1 - 2 * p) * a.nR;
+    g.B = a.DI + 2 * (long)l * (4 * (long)l * l - 1) / 3;
+    g.ldb = d;
+    g.C = a.At + (long)l * l * Mr + (long)p * a.nR;
+    g.ldc = 1;
+    g.ldc_c = Mr;
+  } else {
+    const int mc = z, m = (mc + 1) >> 1;
+    g.M = a.nt;
+    g.N = (int)Mr;
+    g.K = a.L + 1 - m;
+    g.A = a.P2 + (long)mc * a.nt * a.ldl + m;
+    g.lda = a.ldl;
+    g.B = a.Ut + ((long)mc * (a.L + 1) + m) * Mr;
+    g.ldb = Mr;
+    g.C = a.V + mc * MJ;
+    g.ldc = Mr;
+  }
+  g.k_per_split = (g.K + kBK - 1) / kBK * kBK;
+  g.tiles_m = 1;
+  if ((int)blockIdx.x * BM >= g.M || (int)blockIdx.y * BN >= g.N) return;  // uniform: past this problem's tiles
+  gemm_f64_tile<BM, BN, WGM, WGN, MODE>(g, blockIdx.x, blockIdx.y, 0);
+}
+
 // Persistent grouped form: blocks walk a list of (problem, tm, tn, split)
 // work items over several independent contractions of one phase.
 template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE>
@@ -286,7 +371,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_grouped(const Gemm
 __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
     const double *__restrict__ part, int nsplit, long split_stride, double *__restrict__ Ahat,
     const double *__restrict__ coef, const int *__restrict__ qdeg, int nR, int Q, int L, double negG,
-    double *__restrict__ U, long ldu, int cross, double *__restrict__ Ut, long ut_rows) {
+    double *__restrict__ U, long ldu, int cross) {
   __shared__ double sI[16][64], sPa[16][64], sO[16][64], sPg[16][64];
   const int lane = threadIdx.x, w = threadIdx.y, nw = blockDim.y;
   const int q = blockIdx.x * 64 + lane;
@@ -303,10 +388,6 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
   // reduced moments for the later passes: the copy in Ahat, or the single
   // partial buffer itself when no copy is kept (nsplit == 1 then)
   const double *__restrict__ Ared = Ahat ? Ahat : part;
-  // where I_n, then U_n, of this column are kept
-  auto dst = [&](int n) -> double * {
-    return Ut ? Ut + ((long)(qq - l * l) * (L + 1) + l) * ut_rows + rbase + n : U + (rbase + n) * ldu + qq;
-  };
 
   double I = 0.0, Pa = 1.0;
   if (ok) {
@@ -347,7 +428,7 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
   for (int n = n0; n < n1; ++n) {
     const double *c = cf + n * cstride;
     I = c[0] * I + c[1] * Ared[(rbase + n) * Q + q];
-    *dst(n) = I;
+    U[(rbase + n) * ldu + q] = I;
   }
   O = Oin;
 #pragma unroll 4
@@ -355,9 +436,9 @@ __global__ __launch_bounds__(1024) void radial_scan_loop_kernel(
     const double *c = cf + n * cstride;
     const double an = (n + 1 < nR) ? Ared[(rbase + n + 1) * Q + q] : 0.0;
     O = c[2] * O + c[3] * an;
-    const double v = negG * (*dst(n) + O);
-    *dst(n) = v;
-    if (cross && !Ut) U[(rbar + n) * ldu + Q + q] = v;
+    const double v = negG * (U[(rbase + n) * ldu + q] + O);
+    U[(rbase + n) * ldu + q] = v;
+    if (cross) U[(rbar + n) * ldu + Q + q] = v;
   }
 }
 
@@ -484,8 +565,6 @@ __device__ __forceinline__ void radial_scan_block(const ScanArgs &sa, int colblo
     }
   }
   const long rbar = (long)(1 - p) * nR;
-  // azimuthal-column-major output: Ut[mc][l][row], rows contiguous
-  double *__restrict__ ut = sa.Ut ? sa.Ut + ((long)(q - l * l) * (L + 1) + l) * sa.ut_rows : nullptr;
   O = Oin;
 #pragma unroll
   for (int h = CMAX / H - 1; h >= 0; --h) {
@@ -497,12 +576,8 @@ __device__ __forceinline__ void radial_scan_block(const ScanArgs &sa, int colblo
       if (i < len) {
         O = c2[u] * O + c3[u] * a[i + 1];
         const double v = negG * (Iv[i] + O);
-        if (ut) {
-          ut[rbase + n0 + i] = v;
-        } else {
-          U[(rbase + n0 + i) * ldu + q] = v;
-          if (sa.cross) U[(rbar + n0 + i) * ldu + Q + q] = v;
-        }
+        U[(rbase + n0 + i) * ldu + q] = v;
+        if (sa.cross) U[(rbar + n0 + i) * ldu + Q + q] = v;
       }
     }
   }
@@ -558,114 +633,124 @@ __global__ void expand_self_basis_kernel(const double *__restrict__ P, const dou
 // ---------------------------------------------------------------------------
 // Separable form.  The analysis basis factors as T_j^(lm) x (w_jk C/S_k^(m))
 // and the self-synthesis basis as P_l^m(cos t_j) x cos/sin(m phi_k), so each
-// contraction splits into a transform over phi (one GEMM over all (row, j)
-// pairs) and one over theta (a grouped GEMM, one problem per azimuthal
-// column mc).  The other patch's moments enter the synthesis rotated into
-// this patch's frame, degree by degree (kernel below).
+// contraction splits into a transform over phi (a strided batch over the
+// colatitudes j) and one over theta (a grouped GEMM, one problem per
+// azimuthal column mc).  The other patch's moments enter the synthesis
+// rotated into this patch's frame, degree by degree (a grouped GEMM, one
+// problem per degree and patch), before the radial scan below.
 // Azimuthal column mc: 0 for m = 0, 2m-1 (cos) / 2m (sin); q = l^2 + mc.
 
-// Own moments plus the other patch's moments rotated into this patch's
-// frame, for every row (patch p, shell n) and degree-l column block:
-//   At[row][l^2 + b] = A[row][l^2 + b] + sum_a A[row'][l^2 + a] Dt_l[b][a],
-// row' = the other patch's row of the same shell, Dt_l the transposed
-// rotation block of degree l (d = 2l + 1 values per row, at dofs[l]).
-// The radial recurrences act on every column of degree l alike, so rotating
-// the moments before the scan equals rotating its output.  Block = one
-// degree, a 64-wide chunk of b and 64 rows; the a-sum runs over 32-wide
-// chunks staged in LDS (the rotation block and the other patch's moments);
-// each thread accumulates 4 rows x 4 columns, so an LDS read feeds 2 FMAs.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void rotate_moments_kernel(const double *__restrict__ A, int nR, int Q,
-                                                            const int *__restrict__ dofs,
-                                                            const double *__restrict__ Dt,
-                                                            double *__restrict__ At) {
-  constexpr int RB = 64, BC = 64, AC = 32;
-  __shared__ double sA[RB][AC + 1];
-  __shared__ double sD[AC][BC + 1];
-  const int l = blockIdx.x, d = 2 * l + 1;
-  const int b0 = blockIdx.y * BC;
-  if (b0 >= d) return;  // uniform: the whole block leaves
-  const long M = 2L * nR;
-  const long r0 = (long)blockIdx.z * RB;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;  // columns tx + 16i, rows ty + 16j
-  const double *__restrict__ dl = Dt + dofs[l];
-  const int q0 = l * l;
-  double acc[4][4];
+// Radial scan of Eqs. (31)-(34) on column-major moments X[q][p nR + n]: one
+// block per column q, one wave per patch.  The column (and its degree's
+// recurrence coefficients, coefS[l][4][nR], shared by the waves) is staged
+// in LDS; lane i owns the radial chunk [i c, i c + c) (c odd, so that the
+// chunk-strided LDS reads spread over the banks); the chunk summaries
+// (product of multipliers, local value) combine across the wave with
+// shuffles, and the potential coefficients -G U_n^(q) go back through LDS to
+// Ut[mc][l][p nR + n] (q = l^2 + mc), rows contiguous.
+// CMAX bounds the chunk length: the chunk loops unroll with every LDS read
+// at a clamped index, so that the reads issue ahead of the recurrences.
+template <int CMAX>
+__global__ __launch_bounds__(128) void radial_scan_q_kernel(const double *__restrict__ X, const double *__restrict__ coefS,
+                                                            const int *__restrict__ qdeg, int nR, int L, int chunk,
+                                                            double negG, double *__restrict__ Ut) {
+  extern __shared__ double smem[];
+  const int q = blockIdx.x, l = qdeg[q];
+  const int P = blockDim.x / 64;
+  const int tid = threadIdx.x, lane = tid & 63, p = tid >> 6;
+  const long M = (long)P * nR;
+  double *sc = smem;                                 // [4][nR]: c0, c1, c2, c3 over n
+  double *sx = smem + 4L * nR + (long)p * (2 * nR + 1);  // [nR + 1]: the moments, zero at nR
+  double *so = sx + nR + 1;                          // [nR]: output staging
+  {
+    // staging: batches of CB coefficient and XB moment loads from clamped
+    // addresses, all in flight before the first LDS store (one batch covers
+    // n_r <= 512 with two patches)
+    constexpr int CB = 16, XB = 8;
+    const double *__restrict__ cl = coefS + (long)l * 4 * nR;
+    const double *__restrict__ xp = X + (long)q * M + (long)p * nR;
+    const int nt = blockDim.x;
+    for (int c0 = 0, x0 = 0; c0 < 4 * nR || x0 <= nR; c0 += CB * nt, x0 += XB * 64) {
+      double tc[CB], tx[XB];
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+      for (int u = 0; u < CB; ++u) tc[u] = cl[min(c0 + u * nt + tid, 4 * nR - 1)];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[j][i] = 0.0;
-  for (int a0 = 0; a0 < d; a0 += AC) {
-    // the other patch's moments of this block's rows, a-chunk [a0, a0 + AC),
-    // and the rotation coefficients Dt_l[b0 + bb][a0 + a]: every load from a
-    // clamped valid address (masked afterwards) so that all are in flight
-    // together, then the LDS stores
-    double va[RB * AC / 256], vd[BC * AC / 256];
+      for (int u = 0; u < XB; ++u) tx[u] = xp[min(x0 + u * 64 + lane, nR - 1)];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < RB * AC / 256; ++u) {
-      const int e = tid + 256 * u, r = e / AC, a = e % AC;
-      const long row = min(r0 + r, M - 1);
-      const long other = row < nR ? row + nR : row - nR;
-      va[u] = A[other * Q + q0 + min(a0 + a, d - 1)];
-    }
+      for (int u = 0; u < CB; ++u)
+        if (c0 + u * nt + tid < 4 * nR) sc[c0 + u * nt + tid] = tc[u];
 #pragma unroll
-    for (int u = 0; u < BC * AC / 256; ++u) {
-      const int e = tid + 256 * u, bb = e / AC, a = e % AC;
-      vd[u] = dl[(long)min(b0 + bb, d - 1) * d + min(a0 + a, d - 1)];
-    }
-    __builtin_amdgcn_sched_barrier(0);  // issue every load before the first use
-#pragma unroll
-    for (int u = 0; u < RB * AC / 256; ++u) {
-      const int e = tid + 256 * u, r = e / AC, a = e % AC;
-      va[u] = keep_if(r0 + r < M && a0 + a < d, va[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < BC * AC / 256; ++u) {
-      const int e = tid + 256 * u, bb = e / AC, a = e % AC;
-      vd[u] = keep_if(b0 + bb < d && a0 + a < d, vd[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < RB * AC / 256; ++u) {
-      const int e = tid + 256 * u;
-      sA[e / AC][e % AC] = va[u];
-    }
-#pragma unroll
-    for (int u = 0; u < BC * AC / 256; ++u) {
-      const int e = tid + 256 * u;
-      sD[e % AC][e / AC] = vd[u];
-    }
-    __syncthreads();
-    const int na = min(AC, d - a0);
-    for (int a = 0; a < na; ++a) {
-      double dv[4], av[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) dv[i] = sD[a][tx + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) av[j] = sA[ty + 16 * j][a];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[j][i] += av[j] * dv[i];
-    }
-    __syncthreads();
-  }
-  // own moments: all 16 loads from clamped addresses first, then the
-  // stores of the valid entries
-  double own[4][4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      own[j][i] = A[min(r0 + ty + 16 * j, M - 1) * Q + q0 + min(b0 + tx + 16 * i, d - 1)];
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const long row = r0 + ty + 16 * j;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int b = b0 + tx + 16 * i;
-      if (row < M && b < d) At[row * Q + q0 + b] = own[j][i] + acc[j][i];
+      for (int u = 0; u < XB; ++u) {
+        const int e = x0 + u * 64 + lane;
+        if (e <= nR) sx[e] = keep_if(e < nR, tx[u]);
+      }
     }
   }
+  __syncthreads();
+  const double *c0 = sc, *c1 = sc + nR, *c2 = sc + 2L * nR, *c3 = sc + 3L * nR;
+  const int n0 = min(nR, lane * chunk), len = min(nR, n0 + chunk) - n0;
+  // chunk summaries: I_out = Pa I_in + I, O_out = Pg O_in + O
+  double I = 0.0, Pa = 1.0, O = 0.0, Pg = 1.0;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) {
+    const int n = min(n0 + i, nR - 1);
+    const double a = c0[n], b = c1[n] * sx[n];
+    if (i < len) {
+      I = a * I + b;
+      Pa *= a;
+    }
+  }
+#pragma unroll
+  for (int i = CMAX - 1; i >= 0; --i) {
+    const int n = min(n0 + i, nR - 1);
+    const double a = c2[n], b = c3[n] * sx[n + 1];
+    if (i < len) {
+      O = a * O + b;
+      Pg *= a;
+    }
+  }
+  // inclusive scans across the wave: inner sums from the left, outer sums
+  // from the right
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double Pp = __shfl_up(Pa, off), Ip = __shfl_up(I, off);
+    const double Pn = __shfl_down(Pg, off), On = __shfl_down(O, off);
+    if (lane >= off) {
+      I = Pa * Ip + I;
+      Pa *= Pp;
+    }
+    if (lane + off < 64) {
+      O = Pg * On + O;
+      Pg *= Pn;
+    }
+  }
+  double Iin = __shfl_up(I, 1), Oin = __shfl_down(O, 1);
+  if (lane == 0) Iin = 0.0;
+  if (lane == 63) Oin = 0.0;
+  double Iv[CMAX];
+  I = Iin;
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) {
+    const int n = min(n0 + i, nR - 1);
+    const double a = c0[n], b = c1[n] * sx[n];
+    if (i < len) I = a * I + b;
+    Iv[i] = I;
+  }
+  O = Oin;
+#pragma unroll
+  for (int i = CMAX - 1; i >= 0; --i) {
+    const int n = min(n0 + i, nR - 1);
+    const double a = c2[n], b = c3[n] * sx[n + 1];
+    if (i < len) {
+      O = a * O + b;
+      so[n] = negG * (Iv[i] + O);
+    }
+  }
+  __syncthreads();
+  const int mc = q - l * l;
+  double *__restrict__ ut = Ut + ((long)mc * (L + 1) + l) * M + (long)p * nR;
+  for (int e = lane; e < nR; e += 64) ut[e] = so[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -705,8 +790,7 @@ hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4
                                   hipStream_t s) {
   dim3 grid(n_blocks), block(64 * WGM * WGN);
   // roles 0/1: analysis / synthesis with the plain epilogue; 2/3: the same
-  // with the general epilogue; 4: synthesis, general epilogue, A stored
-  // k-major; 5: analysis with the general epilogue and A k-major
+  // with the general epilogue
   switch (role) {
     case 0:
       hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, 0>), grid, block, 0, s, probs, items, n_items);
@@ -720,14 +804,7 @@ hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4
     case 3:
       hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, 1>), grid, block, 0, s, probs, items, n_items);
       break;
-    case 4:
-      hipLaunchKernelGGL((gemm_nt_f64_grouped<1, BM, BN, WGM, WGN, 1 | kGemmATrans>), grid, block, 0, s, probs, items,
-                         n_items);
-      break;
-    case 5:
-      hipLaunchKernelGGL((gemm_nt_f64_grouped<0, BM, BN, WGM, WGN, 1 | kGemmATrans>), grid, block, 0, s, probs, items,
-                         n_items);
-      break;
+
     default:
       return hipErrorInvalidValue;
   }
@@ -735,7 +812,8 @@ hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4
 }
 
 // Strided batch (see gemm_nt_f64_batched): role 0 stores C column-major
-// (kGemmCTrans), role 1 reads A k-major (kGemmATrans).
+// (kGemmCTrans), role 1 reads A k-major (kGemmATrans); + kRoleDeep: the
+// same with kGemmDeep.
 template <int BM, int BN, int WGM, int WGN>
 hipError_t launch_batch_variant(int role, const GemmF64Args &a, hipStream_t s) {
   GemmF64Args g = a;
@@ -750,14 +828,54 @@ hipError_t launch_batch_variant(int role, const GemmF64Args &a, hipStream_t s) {
   else if (role == 1)
     hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans>), grid, block, 0, s, g, per,
                        (int)total);
+  else if (role == kRoleDeep)
+    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmDeep>), grid, block, 0, s, g, per,
+                       (int)total);
+  else if (role == 1 + kRoleDeep)
+    hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans | kGemmDeep>), grid, block, 0, s, g, per,
+                       (int)total);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// Separable theta phases and rotation (see gemm_f64_sep_phase).
+template <int BM, int BN, int WGM, int WGN>
+hipError_t launch_sep_variant(int phase, bool deep, const SepPhaseArgs &a, hipStream_t s) {
+  const long Mr = (long)a.P * a.nR;
+  long mmax, nmax;
+  int nz;
+  if (phase == 1) {
+    mmax = Mr, nmax = a.L + 1, nz = 2 * a.L + 1;
+  } else if (phase == 2) {
+    mmax = a.nR, nmax = 2 * a.L + 1, nz = 2 * (a.L + 1);
+  } else if (phase == 3) {
+    mmax = a.nt, nmax = Mr, nz = 2 * a.L + 1;
+  } else {
+    return hipErrorInvalidValue;
+  }
+  if ((mmax + BM - 1) / BM > INT_MAX || (nmax + BN - 1) / BN > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((mmax + BM - 1) / BM), (unsigned)((nmax + BN - 1) / BN), nz), block(64 * WGM * WGN);
+  constexpr int A1 = 1 | kGemmATrans, A2 = 1 | kGemmATrans | kGemmBTrans | kGemmSplitA, A3 = kGemmBTrans;
+#define YYG_SEP_GO(P, M)                                                                                     \
+  hipLaunchKernelGGL((gemm_f64_sep_phase<P, BM, BN, WGM, WGN, M>), grid, block, 0, s, a);                  \
+  break
+  switch (phase * 2 + (deep ? 1 : 0)) {
+    case 2: YYG_SEP_GO(1, A1);
+    case 3: YYG_SEP_GO(1, A1 | kGemmDeep);
+    case 4: YYG_SEP_GO(2, A2);
+    case 5: YYG_SEP_GO(2, A2 | kGemmDeep);
+    case 6: YYG_SEP_GO(3, A3);
+    default: YYG_SEP_GO(3, A3 | kGemmDeep);
+  }
+#undef YYG_SEP_GO
   return hipGetLastError();
 }
 
 typedef hipError_t (*gemm_f64_fn)(int, int, int, int, const double *, long, const double *, long, double *, long, int,
                                   long, hipStream_t);
 typedef hipError_t (*batch_f64_fn)(int, const GemmF64Args &, hipStream_t);
+typedef hipError_t (*sep_f64_fn)(int, bool, const SepPhaseArgs &, hipStream_t);
 
 typedef hipError_t (*grouped_f64_fn)(int, const GemmF64Args *, const int4 *, int, int, hipStream_t);
 
@@ -766,12 +884,13 @@ struct F64Variant {
   gemm_f64_fn fn;
   grouped_f64_fn grouped;
   batch_f64_fn batch;
+  sep_f64_fn sep;
 };
 
 #define YYG_F64_VARIANT(BM, BN, WM, WN)                                                                   \
   {                                                                                                        \
     BM, BN, 64 * WM * WN, launch_gemm_variant<BM, BN, WM, WN>, launch_grouped_variant<BM, BN, WM, WN>, \
-        launch_batch_variant<BM, BN, WM, WN>                                                               \
+        launch_batch_variant<BM, BN, WM, WN>, launch_sep_variant<BM, BN, WM, WN>                          \
   }
 
 const F64Variant kF64Variants[] = {
@@ -798,6 +917,12 @@ hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *pro
   return kF64Variants[variant].grouped(role, probs, items, n_items, n_blocks, s);
 }
 
+hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s) {
+  if (a.nR <= 0) return hipSuccess;
+  if (variant < 0 || variant >= gemm_f64_variant_count()) return hipErrorInvalidValue;
+  return kF64Variants[variant].sep(phase, deep, a, s);
+}
+
 hipError_t launch_gemm_f64_batched(int variant, int role, const GemmF64Args &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (variant < 0 || variant >= gemm_f64_variant_count()) return hipErrorInvalidValue;
@@ -813,11 +938,11 @@ hipError_t launch_gemm_nt_f64(int variant, int role, int M, int N, int K, const 
 
 hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride, double *Ahat, const double *coef,
                               const int *qdeg, int nR, int Q, int L, double negG, double *U, long ldu, int patches,
-                              hipStream_t s, double *Ut) {
+                              hipStream_t s) {
   if (patches != 1 && patches != 2) return hipErrorInvalidValue;
   const int cross = patches == 2 ? 1 : 0;
   if (!Ahat && nsplit != 1) return hipErrorInvalidValue;
-  ScanArgs sa{part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu, cross, Ut, (long)patches * nR};
+  ScanArgs sa{part, nsplit, split_stride, Ahat, coef, qdeg, nR, Q, L, negG, U, ldu, cross};
   if (nR <= 64 * 4) {
     hipLaunchKernelGGL(radial_scan_kernel<4>, dim3((Q + 15) / 16, patches), dim3(16, 64), 0, s, sa);
   } else if (nR <= 64 * 8) {
@@ -829,7 +954,7 @@ hipError_t launch_radial_scan(const double *part, int nsplit, long split_stride,
     while (nw > 1 && nR / nw < 8) nw >>= 1;
     dim3 block(64, nw), grid((Q + 63) / 64, patches);
     hipLaunchKernelGGL(radial_scan_loop_kernel, grid, block, 0, s, part, nsplit, split_stride, Ahat, coef, qdeg, nR,
-                       Q, L, negG, U, ldu, cross, Ut, (long)patches * nR);
+                       Q, L, negG, U, ldu, cross);
   }
   return hipGetLastError();
 }
@@ -855,13 +980,29 @@ hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, 
 }
 
 
-hipError_t launch_rotate_moments(const double *A, int nR, int L, const int *dofs, const double *Dt, double *At,
-                                 hipStream_t s) {
+size_t radial_scan_q_lds(int nR, int patches) { return (4UL * nR + (size_t)patches * (2UL * nR + 1)) * sizeof(double); }
+
+hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int *qdeg, int nR, int L, double negG,
+                                int patches, double *Ut, hipStream_t s) {
   if (nR <= 0) return hipSuccess;
+  if (patches < 1 || patches > 2) return hipErrorInvalidValue;
+  const size_t lds = radial_scan_q_lds(nR, patches);
+  if (lds > kScanQMaxLds) return hipErrorInvalidValue;
+  const int chunk = ((nR + 63) / 64) | 1;
   const int Q = (L + 1) * (L + 1);
-  dim3 grid(L + 1, (2 * L + 1 + 63) / 64, (2 * nR + 63) / 64);
-  hipLaunchKernelGGL(rotate_moments_kernel, grid, dim3(256), 0, s, A, nR, Q, dofs, Dt, At);
-  return hipGetLastError();
+  auto go = [&](auto kern) {
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3(Q), dim3(64 * patches), lds, s, X, coefS, qdeg, nR, L, chunk, negG, Ut);
+    return hipGetLastError();
+  };
+  if (chunk <= 7) return go(radial_scan_q_kernel<7>);
+  if (chunk <= 15) return go(radial_scan_q_kernel<15>);
+  if (chunk <= 31) return go(radial_scan_q_kernel<31>);
+  if (chunk <= 63) return go(radial_scan_q_kernel<63>);
+  return hipErrorInvalidValue;
 }
 
 int gemm_f64_variant_threads(int v) { return kF64Variants[v].threads; }

@@ -249,6 +249,12 @@ def test_separable_ragged_shapes(case):
     _, phi = _gpu_solve(desc, rho, grid=g)
     ref = O.solve(*_oracle_args(desc), rho)
     assert _max_rel(phi, ref) <= TOL_FP64
+    # the separable form keeps its moments column-major; the export is the
+    # same [patch][shell][q] array as after a dense solve
+    th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+    w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
+    AC, AS = O.moments(rho, w, O.theta_integrals(th, desc["lmax"]), *O.phi_integrals(ph, desc["lmax"]))
+    assert np.all(np.abs(g.moments() - _moments_to_q(AC, AS)) <= _moment_bound(desc, rho))
 
 
 @pytest.mark.parametrize("name", ["sn_core", "spheroid"])
@@ -275,12 +281,13 @@ def test_separable_workloads_and_dense_agreement(name):
     assert agree <= TOL_FP64
 
 
-@pytest.mark.parametrize("phase", [0, 1, 3, 4])
+@pytest.mark.parametrize("phase", [0, 1, 2, 3, 4])
 def test_separable_every_phase_variant(phase):
     """Every tile variant of each phase of the separable form (grouped theta
-    phases, phi phases as strided batches over the colatitudes), on a ragged
-    grid (n_r 37, 9 deg, lmax 11: 74-row problems, so every variant's last
-    row tile is partial), against the oracle on the full grid."""
+    phases and moment rotation, phi phases as strided batches over the
+    colatitudes), on a ragged grid (n_r 37, 9 deg, lmax 11: 74-row problems,
+    37-row rotation problems, so every variant's last row tile is partial),
+    against the oracle on the full grid."""
     yyg = _yyg()
     desc = W.make_desc("edge", np.geomspace(1.0, 50.0, 38), 9.0, 11, 0.9, 0)
     rng = np.random.default_rng(12)
@@ -288,7 +295,7 @@ def test_separable_every_phase_variant(phase):
     ref = O.solve(*_oracle_args(desc), rho)
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
-    for v in range(N_F64_VARIANTS):
+    for v in range(2 * N_F64_VARIANTS):     # every tile, one and three stages of loads in flight
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
