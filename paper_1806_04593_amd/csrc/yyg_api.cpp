@@ -104,12 +104,15 @@ struct yyg_grid {
     // phi phases, strided batches over the colatitudes j: analysis (C
     // stored column-major) and synthesis (A stored k-major)
     yyg::GemmF64Args phi_ana{}, phi_syn{};
+    // the same two as LDS-basis kernels
+    yyg::PhiDirectArgs phi_ana_d{}, phi_syn_d{};
     // theta phases and rotation: one launch each over their problems
     yyg::SepPhaseArgs args{};
     // tile variant per phase (0 phi analysis, 1 theta analysis, 2 moment
     // rotation, 3 theta synthesis, 4 phi synthesis); V + v = tile v with
     // the deep prefetch
-    int var[5] = {3, 3, 9, 3, 3};
+    static constexpr int kDefaultVariant = 9;  // 64 x 32 tiles
+    int var[5] = {kDefaultVariant, kDefaultVariant, kDefaultVariant, kDefaultVariant, kDefaultVariant};
   } sep;
 
   bool timing = false;
@@ -268,10 +271,16 @@ std::map<std::string, std::pair<int, int>> read_tune_cache(const char *path) {
 
 namespace {
 
-// Tile variant of separable phase r: v < V the tile v, V + v the same
-// with three stages of loads in flight (V = the FP64 tile variants).
+// Variants of separable phase r: v < V the tile v, V + v the same with
+// three stages of loads in flight (V = the FP64 tile variants); the phi
+// phases (0, 4) also 2V + d, the LDS-basis kernel variant d.
+int sep_variant_count(int r) {
+  const int v = 2 * yyg::gemm_f64_variant_count();
+  return (r == 0 || r == 4) ? v + yyg::phi_direct_variant_count() : v;
+}
+
 int sep_set_variant(yyg_grid *g, int r, int v) {
-  if (r < 0 || r > 4 || v < 0 || v >= 2 * yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
+  if (r < 0 || r > 4 || v < 0 || v >= sep_variant_count(r)) return YYG_ERR_INVALID_ARG;
   g->sep.var[r] = v;
   return YYG_OK;
 }
@@ -279,6 +288,10 @@ int sep_set_variant(yyg_grid *g, int r, int v) {
 hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
   const int nv = yyg::gemm_f64_variant_count();
+  if ((r == 0 || r == 4) && S.var[r] >= 2 * nv) {
+    yyg::PhiDirectArgs d = r == 0 ? S.phi_ana_d : S.phi_syn_d;
+    return yyg::launch_phi_direct(S.var[r] - 2 * nv, r == 0, d, s);
+  }
   const int v = S.var[r] % nv;
   const bool deep = S.var[r] >= nv;
   if (r == 0) return yyg::launch_gemm_f64_batched(v, deep ? yyg::kRoleDeep : 0, S.phi_ana, s);
@@ -292,6 +305,8 @@ hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
 int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
   g->sep.phi_ana.A = rho;
   g->sep.phi_syn.C = phi;
+  g->sep.phi_ana_d.X = rho;
+  g->sep.phi_syn_d.C = phi;
   return YYG_OK;
 }
 
@@ -391,6 +406,8 @@ int sep_build(yyg_grid *g) {
   S.phi_syn = yyg::GemmF64Args{(int)M, np, nmc, S.V, MJ, S.trig, S.ldm, nullptr, (long)nt * np, np, kround(nmc), 1};
   S.phi_syn.batch = nt;
   S.phi_syn.a_batch = M;
+  S.phi_ana_d = yyg::PhiDirectArgs{nullptr, S.Wcs, S.X2, (int)M, nt, nmc, np, S.ldk, (long)nmc * S.ldk};
+  S.phi_syn_d = yyg::PhiDirectArgs{S.V, S.trig, nullptr, (int)M, nt, np, nmc, S.ldm, 0};
   // theta analysis, rotation (Yin-Yang) and theta synthesis: problem
   // operands derived in the kernels from these
   S.args = yyg::SepPhaseArgs{L,    g->n_r, g->n_patch, nt,  S.ldl, S.X2, S.T2, S.P2,
@@ -1043,6 +1060,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       (void)hipFree(tmp);
       g->sep.phi_syn.C = nullptr;  // the temporary is gone
+      g->sep.phi_syn_d.C = nullptr;
     }
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -1339,11 +1357,18 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
       if (st3 == YYG_OK) (void)hipMemsetAsync(rho_t, 0, (size_t)M * g->nang * sizeof(double), s);
     }
     if (st3 == YYG_OK) st3 = sep_set_pointers(g, g->rho ? g->rho : rho_t, phi_t, s);
+    // a variant replaces the default tile only when it is 3% faster, so
+    // that near-ties do not flip between runs
     for (int r = 0; r < 5 && st3 == YYG_OK; ++r) {
       if (r == 2 && g->n_patch != 2) continue;  // one patch: no rotation
-      double best = 1e30;
-      int bv = g->sep.var[r];
-      for (int v = 0; v < 2 * yyg::gemm_f64_variant_count() && st3 == YYG_OK; ++v) {
+      const int v0 = yyg_grid::Sep::kDefaultVariant;
+      st3 = sep_set_variant(g, r, v0);
+      if (st3 != YYG_OK) break;
+      const double t0 = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 5);
+      double best = 0.97 * t0;
+      int bv = v0;
+      for (int v = 0; v < sep_variant_count(r) && st3 == YYG_OK; ++v) {
+        if (v == v0) continue;
         st3 = sep_set_variant(g, r, v);
         if (st3 != YYG_OK) break;
         double t = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 5);
@@ -1359,6 +1384,8 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     if (rho_t) (void)hipFree(rho_t);
     g->sep.phi_ana.A = nullptr;  // the next solve writes its own pointers
     g->sep.phi_syn.C = nullptr;
+    g->sep.phi_ana_d.X = nullptr;
+    g->sep.phi_syn_d.C = nullptr;
     if (st3 != YYG_OK) return st3;
   }
   if (cache_path && (!have_a || !have_s)) {
@@ -1428,7 +1455,7 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n) {
 int yyg_sep_config(yyg_grid *g, int phase, int variant) {
   if (!g || phase < 0 || phase > 4) return YYG_ERR_INVALID_ARG;
   if (!g->sep.ready) return YYG_ERR_NOT_READY;
-  if (variant < 0 || variant >= 2 * yyg::gemm_f64_variant_count()) return YYG_ERR_INVALID_ARG;
+  if (variant < 0 || variant >= sep_variant_count(phase)) return YYG_ERR_INVALID_ARG;
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   if (hipDeviceSynchronize() != hipSuccess) {  // the work items may be in use

@@ -55,6 +55,22 @@ struct SepPhaseArgs {
   double *At;        // own + rotated other moments [Q][row] (Yin-Yang)
   double *V;         // theta-synthesis output [mc][j][row]
 };
+// Phi transforms of the separable form with the basis staged in LDS and
+// the data streamed into MFMA fragments (one launch over all colatitudes).
+//  analysis:  C = X2[mc][j][row] (N = 2L+1 columns mc) from X = rho
+//             [row][j][k] (K = n_p) and bas = W [j][mc][ldb] (bas_batch =
+//             N ldb);
+//  synthesis: C = phi[row][j][k] (N = n_p) from X = V [mc][j][row] (K = 2L+1)
+//             and bas = trig [k][ldb] (bas_batch = 0).
+struct PhiDirectArgs {
+  const double *X, *bas;
+  double *C;
+  int M, nt, N, K;  // rows, colatitudes, basis rows, contraction length
+  long ldb, bas_batch;
+};
+int phi_direct_variant_count();
+hipError_t launch_phi_direct(int variant, bool analysis, const PhiDirectArgs &a, hipStream_t s);
+
 // phase 1 theta analysis, 2 rotation (two patches), 3 theta synthesis;
 // deep = kGemmDeep.
 hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s);

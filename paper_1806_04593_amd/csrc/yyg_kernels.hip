@@ -640,6 +640,105 @@ __global__ void expand_self_basis_kernel(const double *__restrict__ P, const dou
 // problem per degree and patch), before the radial scan below.
 // Azimuthal column mc: 0 for m = 0, 2m-1 (cos) / 2m (sin); q = l^2 + mc.
 
+// Phi transforms with the basis in LDS and the data streamed straight into
+// MFMA fragments.  Block = WAVES waves of 16 data rows each, one colatitude
+// j (blockIdx.y) and a group of G = 16 NT basis rows (blockIdx.z); the
+// basis passes through LDS in chunks of 64 along the contraction, double
+// buffered, so the main loop has one barrier per chunk; each wave keeps the
+// next PF stages (16 contraction values each) of its data fragments in
+// registers.  Every basis entry outside the matrix is zeroed on its way into
+// LDS, so the data loads only clamp their addresses.
+//  analysis  (ANA): X2[mc][j][row] = sum_k W_j[mc][k] rho[row][j][k]; the
+//            MFMA's A side is the basis (rows mc), the B side the data.
+//  synthesis:       phi[row][j][k] = sum_mc V[mc][j][row] trig[k][mc]; the
+//            A side is the data (rows), the B side the basis (rows k).
+template <bool ANA, int WAVES, int NT>
+__global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a) {
+  constexpr int G = 16 * NT, KC = 64, NTH = 64 * WAVES, PF = 4;
+  constexpr int EL = (G * KC + NTH - 1) / NTH;  // basis chunk elements per thread
+  __shared__ __align__(16) double sB[2][G][KC + 2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int j = blockIdx.y, g0 = blockIdx.z * G;
+  const int r0 = blockIdx.x * (16 * WAVES) + 16 * wave;
+  const int M = a.M, N = a.N, K = a.K, nt = a.nt;
+  const double *__restrict__ bas = a.bas + (long)j * a.bas_batch;
+  // this lane's data row (clamped) and its view of the contraction index
+  const int row = min(r0 + lr, M - 1);
+  const double *__restrict__ xr =
+      ANA ? a.X + (long)row * ((long)nt * K) + (long)j * K : a.X + (long)j * M + row;
+  const long xk = ANA ? 1 : (long)nt * M;  // stride of the contraction index
+  auto xload = [&](int st, double (&v)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = xr[(long)min(st * 16 + 4 * lg + s, K - 1) * xk];
+  };
+  double stg[EL];
+  auto bload = [&](int c) {
+#pragma unroll
+    for (int u = 0; u < EL; ++u) {
+      const int e = min(tid + NTH * u, G * KC - 1), br = e / KC, kk = e % KC;
+      stg[u] = bas[(long)min(g0 + br, N - 1) * a.ldb + min(c * KC + kk, K - 1)];
+    }
+  };
+  auto bstore = [&](int c, int buf) {
+#pragma unroll
+    for (int u = 0; u < EL; ++u) {
+      const int e = tid + NTH * u, br = e / KC, kk = e % KC;
+      if (e < G * KC) sB[buf][br][kk] = keep_if(g0 + br < N && c * KC + kk < K, stg[u]);
+    }
+  };
+
+  dbl4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int nst = (K + 15) / 16, nch = (K + KC - 1) / KC;
+  double xs[PF][4];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) xload(min(p, nst - 1), xs[p]);
+  bload(0);
+  __builtin_amdgcn_sched_barrier(0);
+  bstore(0, 0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) bload(c + 1);
+    // the chunk's four stages; stage st = 4c + q sits in register slot q
+#pragma unroll
+    for (int q = 0; q < KC / 16; ++q) {
+      const int st = c * (KC / 16) + q;
+      if (st < nst) {  // uniform
+        double bf[NT][4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) bf[t][s] = sB[buf][16 * t + lr][16 * q + 4 * lg + s];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[t] = ANA ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[t][s], xs[q][s], acc[t], 0, 0, 0)
+                         : __builtin_amdgcn_mfma_f64_16x16x4f64(xs[q][s], bf[t][s], acc[t], 0, 0, 0);
+        if (st + PF < nst) xload(st + PF, xs[q]);
+      }
+    }
+    if (c + 1 < nch) bstore(c + 1, buf ^ 1);
+    __syncthreads();
+  }
+  // D layout: lane l, element e -> MFMA row l/16 + 4e, column l%16
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (ANA) {
+        const int mc = g0 + 16 * t + lg + 4 * e, r = r0 + lr;
+        if (mc < N && r < M) a.C[(long)mc * ((long)nt * M) + (long)j * M + r] = acc[t][e];
+      } else {
+        const int r = r0 + lg + 4 * e, k = g0 + 16 * t + lr;
+        if (r < M && k < N) a.C[(long)r * ((long)nt * N) + (long)j * N + k] = acc[t][e];
+      }
+    }
+}
+
 // Radial scan of Eqs. (31)-(34) on column-major moments X[q][p nR + n]: one
 // block per column q, one wave per patch.  The column (and its degree's
 // recurrence coefficients, coefS[l][4][nR], shared by the waves) is staged
@@ -899,6 +998,8 @@ const F64Variant kF64Variants[] = {
     // narrow-N shapes for the transforms whose N is 2L+1 or a degree block
     YYG_F64_VARIANT(128, 48, 4, 1),  YYG_F64_VARIANT(128, 96, 4, 1),  YYG_F64_VARIANT(128, 144, 4, 1),
     YYG_F64_VARIANT(64, 32, 2, 2),
+    // more waves per tile for the short contractions of the separable form
+    YYG_F64_VARIANT(32, 32, 2, 2),   YYG_F64_VARIANT(64, 64, 4, 2),
 };
 
 }  // namespace
@@ -915,6 +1016,46 @@ hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *pro
   if (n_items <= 0) return hipSuccess;
   if (variant < 0 || variant >= gemm_f64_variant_count()) return hipErrorInvalidValue;
   return kF64Variants[variant].grouped(role, probs, items, n_items, n_blocks, s);
+}
+
+namespace {
+
+template <bool ANA, int WAVES, int NT>
+hipError_t launch_phi_direct_t(const PhiDirectArgs &a, hipStream_t s) {
+  dim3 grid((a.M + 16 * WAVES - 1) / (16 * WAVES), a.nt, (a.N + 16 * NT - 1) / (16 * NT));
+  hipLaunchKernelGGL((phi_direct_kernel<ANA, WAVES, NT>), grid, dim3(64 * WAVES), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int phi_direct_variant_count() { return 6; }
+
+hipError_t launch_phi_direct(int variant, bool analysis, const PhiDirectArgs &a, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || a.nt <= 0) return hipSuccess;
+  if (a.K <= 0 || a.nt > 65535 || (a.N + 31) / 32 > 65535) return hipErrorInvalidValue;
+  // variants: (waves per block, basis tiles per block) =
+  // (8, 4), (8, 3), (8, 2), (4, 4), (4, 3), (4, 2)
+  if (analysis) {
+    switch (variant) {
+      case 0: return launch_phi_direct_t<true, 8, 4>(a, s);
+      case 1: return launch_phi_direct_t<true, 8, 3>(a, s);
+      case 2: return launch_phi_direct_t<true, 8, 2>(a, s);
+      case 3: return launch_phi_direct_t<true, 4, 4>(a, s);
+      case 4: return launch_phi_direct_t<true, 4, 3>(a, s);
+      case 5: return launch_phi_direct_t<true, 4, 2>(a, s);
+    }
+  } else {
+    switch (variant) {
+      case 0: return launch_phi_direct_t<false, 8, 4>(a, s);
+      case 1: return launch_phi_direct_t<false, 8, 3>(a, s);
+      case 2: return launch_phi_direct_t<false, 8, 2>(a, s);
+      case 3: return launch_phi_direct_t<false, 4, 4>(a, s);
+      case 4: return launch_phi_direct_t<false, 4, 3>(a, s);
+      case 5: return launch_phi_direct_t<false, 4, 2>(a, s);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s) {

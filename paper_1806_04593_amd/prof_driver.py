@@ -52,8 +52,9 @@ def main():
     for _ in range(a.solves):
         g.solve(d_phi, a.precision)
     torch.cuda.synchronize()
+    launch = g.sep_info() if a.method == "separable" else g.plan_info(a.precision)
     print(f"[prof] {a.solves} solves of {a.workload} ({a.precision}, {a.method}) in {time.perf_counter() - t0:.3f} s; "
-          f"launch {g.plan_info(a.precision)}", flush=True)
+          f"launch {launch}", flush=True)
     sys.stdout.flush()
 
 

@@ -4,6 +4,7 @@ FP64 gate: maximum pointwise relative error of Phi <= 1e-12 (the maximum
 relative error measure of Sect. 5; Phi < 0 everywhere for rho >= 0).
 """
 
+import functools
 import math
 import sys
 
@@ -116,7 +117,8 @@ def test_ragged_and_degenerate_shapes(case):
     assert _max_rel(phi, ref) <= TOL_FP64
 
 
-N_F64_VARIANTS = 10
+N_F64_VARIANTS = 12
+N_PHI_DIRECT = 6
 
 
 @pytest.mark.parametrize("case", [
@@ -281,6 +283,39 @@ def test_separable_workloads_and_dense_agreement(name):
     assert agree <= TOL_FP64
 
 
+PHI_DIRECT_CASES = [
+    dict(r=np.geomspace(1.0, 50.0, 22), res=3.0, lmax=40),   # 2L+1 = 81: two basis groups; n_phi > 64
+    dict(r=np.linspace(0.0, 1.0, 40), res=1.5, lmax=20),     # n_phi > 128: three basis chunks
+]
+
+
+@functools.lru_cache(maxsize=None)
+def _phi_direct_case(i):
+    case = PHI_DIRECT_CASES[i]
+    desc = W.make_desc("edge", case["r"], case["res"], case["lmax"], 0.8, 0)
+    rng = np.random.default_rng(14)
+    rho = rng.uniform(0.1, 1.0, (2, len(case["r"]) - 1, desc["n_theta"], desc["n_phi"]))
+    return desc, rho, O.solve(*_oracle_args(desc), rho)
+
+
+@pytest.mark.parametrize("ci", range(len(PHI_DIRECT_CASES)))
+@pytest.mark.parametrize("phase", [0, 4])
+def test_separable_phi_direct_shapes(ci, phase):
+    """The LDS-basis phi kernels where the basis spans several 64-row groups
+    and the contraction several 64-wide chunks, against the oracle."""
+    yyg = _yyg()
+    desc, rho, ref = _phi_direct_case(ci)
+    nR = rho.shape[1]
+    g = yyg.Grid(desc, 0)
+    g.set_method("separable")
+    for d in range(N_PHI_DIRECT):
+        g.sep_config(phase, 2 * N_F64_VARIANTS + d)
+        _say(f"phi direct phase {phase} variant {d}: n_r={nR} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']}")
+        _, phi = _gpu_solve(desc, rho, grid=g)
+        err = _max_rel(phi, ref)
+        assert err <= TOL_FP64, (phase, d, err)
+
+
 @pytest.mark.parametrize("phase", [0, 1, 2, 3, 4])
 def test_separable_every_phase_variant(phase):
     """Every tile variant of each phase of the separable form (grouped theta
@@ -295,7 +330,9 @@ def test_separable_every_phase_variant(phase):
     ref = O.solve(*_oracle_args(desc), rho)
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
-    for v in range(2 * N_F64_VARIANTS):     # every tile, one and three stages of loads in flight
+    # every tile with one and with three stages of loads in flight; the phi
+    # phases also every LDS-basis variant
+    for v in range(2 * N_F64_VARIANTS + (N_PHI_DIRECT if phase in (0, 4) else 0)):
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
