@@ -43,10 +43,11 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, key, kernel):
+def measured_traffic(workload, key, kernel, name=None):
     """HBM bytes per launch of one kernel from committed rocprofv3 --pmc
     counters (FETCH_SIZE + WRITE_SIZE, scaled by a calibration kernel of
-    known size), or None when absent or taken on different kernel sources."""
+    known size), or None when absent, taken on different kernel sources or
+    (given `name`) on another kernel variant than the one timed."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -56,7 +57,10 @@ def measured_traffic(workload, key, kernel):
         rec = data.get(f"{workload}/{key}")
         if not rec or rec.get("kernel_sha") != kernel_sha():
             return None
-        return float(rec["kernels"][kernel]["bytes_per_launch"])
+        k = rec["kernels"][kernel]
+        if name is not None and k.get("name") != name:
+            return None
+        return float(k["bytes_per_launch"])
     except (OSError, ValueError, KeyError, TypeError):
         return None
 
@@ -222,6 +226,9 @@ def bench_single(a):
             "phi_synthesis_tflops": phi_flops / (avg[7] * 1e-3) / 1e12,
             "phi_synthesis_gbs": phi_bytes / (avg[7] * 1e-3) / 1e9,
             "phi_analysis_tflops": phi_flops / (avg[4] * 1e-3) / 1e12,
+            "variants": g.sep_info(),
+            "kernel_names": {n: g.sep_kernel(p) for p, n in enumerate(
+                ("phi_analysis", "theta_analysis", "rotation", "theta_synthesis", "phi_synthesis"))},
         }
         log(f"[bench] fp64 separable: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, "
             f"kernels {avg[4:]} scan {avg[1]}")
@@ -261,14 +268,15 @@ def bench_single(a):
         tf = flops_k / (ms_k * 1e-3) / 1e12
         gbs = bytes_k / (ms_k * 1e-3) / 1e9
         fm, fh = tf / PEAK["fp64"], gbs / 8000.0
-        kname = "gemm_nt_f64_batched<" + ("0" if name == "phi_analysis" else "1") + ",...> (" + name + ")"
+        kname = head["kernel_names"][name]
         if fm >= fh:
             roof = {"bound": "mfma", "kernel": kname, "achieved": tf, "peak": PEAK["fp64"], "unit": "TFLOP/s",
                     "frac": fm, "hbm_frac": fh}
         else:
             roof = {"bound": "hbm", "kernel": kname, "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
                     "frac": fh, "mfma_frac": fm}
-        roof["traffic"] = measured_traffic(a.workload, head_key, name)
+        roof["traffic"] = measured_traffic(a.workload, head_key, name, kname)
+        roof["phase"] = name
         roof["algorithmic_flops"] = flops_k
         roof["algorithmic_bytes"] = bytes_k
     else:

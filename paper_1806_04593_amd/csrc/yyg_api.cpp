@@ -1472,6 +1472,16 @@ int yyg_sep_info(const yyg_grid *g, int *variants, int n) {
   return YYG_OK;
 }
 
+int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
+  if (!g || !name || n < 1 || phase < 0 || phase > 4) return YYG_ERR_INVALID_ARG;
+  if (!g->sep.ready) return YYG_ERR_NOT_READY;
+  if (phase == 2 && g->n_patch != 2) {
+    name[0] = 0;
+    return YYG_OK;
+  }
+  return yyg::sep_kernel_name(phase, g->sep.var[phase], name, n) == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
+}
+
 int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out) {
   if (!out) return YYG_ERR_INVALID_ARG;
   *out = nullptr;

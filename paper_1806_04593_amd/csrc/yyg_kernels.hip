@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 
 #include "yyg_internal.h"
 
@@ -643,8 +644,10 @@ __global__ void expand_self_basis_kernel(const double *__restrict__ P, const dou
 // Phi transforms with the basis in LDS and the data streamed straight into
 // MFMA fragments.  Block = WAVES waves of 16 data rows each, one colatitude
 // j (blockIdx.y) and a group of G = 16 NT basis rows (blockIdx.z); the
-// basis passes through LDS in chunks of 64 along the contraction, double
-// buffered, so the main loop has one barrier per chunk; each wave keeps the
+// basis passes through LDS in chunks of 64 along the contraction (NBUF = 2:
+// double buffered, one barrier per chunk; NBUF = 1: one buffer and two
+// barriers per chunk, for wide groups whose contraction is mostly one
+// chunk); each wave keeps the
 // next PF stages (16 contraction values each) of its data fragments in
 // registers.  Every basis entry outside the matrix is zeroed on its way into
 // LDS, so the data loads only clamp their addresses.
@@ -652,11 +655,11 @@ __global__ void expand_self_basis_kernel(const double *__restrict__ P, const dou
 //            MFMA's A side is the basis (rows mc), the B side the data.
 //  synthesis:       phi[row][j][k] = sum_mc V[mc][j][row] trig[k][mc]; the
 //            A side is the data (rows), the B side the basis (rows k).
-template <bool ANA, int WAVES, int NT>
+template <bool ANA, int WAVES, int NT, int NBUF>
 __global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a) {
   constexpr int G = 16 * NT, KC = 64, NTH = 64 * WAVES, PF = 4;
   constexpr int EL = (G * KC + NTH - 1) / NTH;  // basis chunk elements per thread
-  __shared__ __align__(16) double sB[2][G][KC + 2];
+  __shared__ __align__(16) double sB[NBUF][G][KC + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int j = blockIdx.y, g0 = blockIdx.z * G;
@@ -700,7 +703,7 @@ __global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a)
   bstore(0, 0);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
+    const int buf = NBUF == 2 ? (c & 1) : 0;
     if (c + 1 < nch) bload(c + 1);
     // the chunk's four stages; stage st = 4c + q sits in register slot q
 #pragma unroll
@@ -721,7 +724,10 @@ __global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a)
         if (st + PF < nst) xload(st + PF, xs[q]);
       }
     }
-    if (c + 1 < nch) bstore(c + 1, buf ^ 1);
+    if (c + 1 < nch) {
+      if (NBUF == 1) __syncthreads();  // every wave is done with the one buffer
+      bstore(c + 1, NBUF == 2 ? buf ^ 1 : 0);
+    }
     __syncthreads();
   }
   // D layout: lane l, element e -> MFMA row l/16 + 4e, column l%16
@@ -979,7 +985,7 @@ typedef hipError_t (*sep_f64_fn)(int, bool, const SepPhaseArgs &, hipStream_t);
 typedef hipError_t (*grouped_f64_fn)(int, const GemmF64Args *, const int4 *, int, int, hipStream_t);
 
 struct F64Variant {
-  int bm, bn, threads;
+  int bm, bn, threads, wm, wn;
   gemm_f64_fn fn;
   grouped_f64_fn grouped;
   batch_f64_fn batch;
@@ -988,7 +994,7 @@ struct F64Variant {
 
 #define YYG_F64_VARIANT(BM, BN, WM, WN)                                                                   \
   {                                                                                                        \
-    BM, BN, 64 * WM * WN, launch_gemm_variant<BM, BN, WM, WN>, launch_grouped_variant<BM, BN, WM, WN>, \
+    BM, BN, 64 * WM * WN, WM, WN, launch_gemm_variant<BM, BN, WM, WN>, launch_grouped_variant<BM, BN, WM, WN>, \
         launch_batch_variant<BM, BN, WM, WN>, launch_sep_variant<BM, BN, WM, WN>                          \
   }
 
@@ -1020,42 +1026,39 @@ hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *pro
 
 namespace {
 
-template <bool ANA, int WAVES, int NT>
+template <bool ANA, int WAVES, int NT, int NBUF>
 hipError_t launch_phi_direct_t(const PhiDirectArgs &a, hipStream_t s) {
   dim3 grid((a.M + 16 * WAVES - 1) / (16 * WAVES), a.nt, (a.N + 16 * NT - 1) / (16 * NT));
-  hipLaunchKernelGGL((phi_direct_kernel<ANA, WAVES, NT>), grid, dim3(64 * WAVES), 0, s, a);
+  hipLaunchKernelGGL((phi_direct_kernel<ANA, WAVES, NT, NBUF>), grid, dim3(64 * WAVES), 0, s, a);
   return hipGetLastError();
+}
+
+template <bool ANA>
+hipError_t launch_phi_direct_v(int variant, const PhiDirectArgs &a, hipStream_t s) {
+  switch (variant) {
+    case 0: return launch_phi_direct_t<ANA, 8, 4, 2>(a, s);
+    case 1: return launch_phi_direct_t<ANA, 8, 3, 2>(a, s);
+    case 2: return launch_phi_direct_t<ANA, 8, 2, 2>(a, s);
+    case 3: return launch_phi_direct_t<ANA, 4, 4, 2>(a, s);
+    case 4: return launch_phi_direct_t<ANA, 4, 3, 2>(a, s);
+    case 5: return launch_phi_direct_t<ANA, 4, 2, 2>(a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int phi_direct_variant_count() { return 6; }
+// (waves per block, basis tiles per block, LDS buffers) of each variant
+// (measured on MI355X: single-buffered groups of 96-144 basis rows were
+// slower than these at 2L+1 = 51 and n_p = 137)
+const int kPhiDirect[][3] = {{8, 4, 2}, {8, 3, 2}, {8, 2, 2}, {4, 4, 2}, {4, 3, 2}, {4, 2, 2}};
+
+int phi_direct_variant_count() { return (int)(sizeof(kPhiDirect) / sizeof(kPhiDirect[0])); }
 
 hipError_t launch_phi_direct(int variant, bool analysis, const PhiDirectArgs &a, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || a.nt <= 0) return hipSuccess;
   if (a.K <= 0 || a.nt > 65535 || (a.N + 31) / 32 > 65535) return hipErrorInvalidValue;
-  // variants: (waves per block, basis tiles per block) =
-  // (8, 4), (8, 3), (8, 2), (4, 4), (4, 3), (4, 2)
-  if (analysis) {
-    switch (variant) {
-      case 0: return launch_phi_direct_t<true, 8, 4>(a, s);
-      case 1: return launch_phi_direct_t<true, 8, 3>(a, s);
-      case 2: return launch_phi_direct_t<true, 8, 2>(a, s);
-      case 3: return launch_phi_direct_t<true, 4, 4>(a, s);
-      case 4: return launch_phi_direct_t<true, 4, 3>(a, s);
-      case 5: return launch_phi_direct_t<true, 4, 2>(a, s);
-    }
-  } else {
-    switch (variant) {
-      case 0: return launch_phi_direct_t<false, 8, 4>(a, s);
-      case 1: return launch_phi_direct_t<false, 8, 3>(a, s);
-      case 2: return launch_phi_direct_t<false, 8, 2>(a, s);
-      case 3: return launch_phi_direct_t<false, 4, 4>(a, s);
-      case 4: return launch_phi_direct_t<false, 4, 3>(a, s);
-      case 5: return launch_phi_direct_t<false, 4, 2>(a, s);
-    }
-  }
-  return hipErrorInvalidValue;
+  return analysis ? launch_phi_direct_v<true>(variant, a, s) : launch_phi_direct_v<false>(variant, a, s);
 }
 
 hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s) {
@@ -1147,5 +1150,23 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
 }
 
 int gemm_f64_variant_threads(int v) { return kF64Variants[v].threads; }
+
+int sep_kernel_name(int phase, int v, char *buf, size_t n) {
+  const int nv = gemm_f64_variant_count(), nd = phi_direct_variant_count();
+  if (phase < 0 || phase > 4 || v < 0 || v >= 2 * nv + ((phase == 0 || phase == 4) ? nd : 0)) return -1;
+  if (v >= 2 * nv) {
+    const int *d = kPhiDirect[v - 2 * nv];
+    return snprintf(buf, n, "yyg::phi_direct_kernel<%s, %d, %d, %d>", phase == 0 ? "true" : "false", d[0], d[1],
+                    d[2]) < 0 ? -1 : 0;
+  }
+  const F64Variant &f = kF64Variants[v % nv];
+  const int deep = v >= nv ? kGemmDeep : 0;
+  if (phase == 0 || phase == 4)
+    return snprintf(buf, n, "yyg::gemm_nt_f64_batched<%d, %d, %d, %d, %d, %d>", phase == 0 ? 0 : 1, f.bm, f.bn, f.wm,
+                    f.wn, (phase == 0 ? kGemmCTrans : kGemmATrans) | deep) < 0 ? -1 : 0;
+  const int mode = phase == 1 ? 1 | kGemmATrans : phase == 2 ? 1 | kGemmATrans | kGemmBTrans | kGemmSplitA : kGemmBTrans;
+  return snprintf(buf, n, "yyg::gemm_f64_sep_phase<%d, %d, %d, %d, %d, %d>", phase, f.bm, f.bn, f.wm, f.wn,
+                  mode | deep) < 0 ? -1 : 0;
+}
 
 }  // namespace yyg

@@ -23,6 +23,9 @@ def main():
     ap.add_argument("--method", default="dense", choices=("dense", "separable"))
     ap.add_argument("--solves", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--sep-variants", default=None,
+                    help="comma-separated variants of the five separable phases (as yyg_sep_config), "
+                         "instead of the autotuner's choice, to profile the kernels a bench run chose")
     a = ap.parse_args()
 
     import torch
@@ -44,7 +47,12 @@ def main():
     g.prepare(a.precision)
     if a.method == "separable":
         g.set_method("separable")
-    g.autotune(a.precision)
+    if a.sep_variants and a.method == "separable":
+        for phase, v in enumerate(int(x) for x in a.sep_variants.split(",")):
+            if v >= 0:
+                g.sep_config(phase, v)
+    else:
+        g.autotune(a.precision)
     d_rho = torch.from_numpy(rho).to("cuda:0")
     d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
     g.upload_rho(d_rho)
@@ -52,7 +60,7 @@ def main():
     for _ in range(a.solves):
         g.solve(d_phi, a.precision)
     torch.cuda.synchronize()
-    launch = g.sep_info() if a.method == "separable" else g.plan_info(a.precision)
+    launch = ([g.sep_kernel(p) for p in range(5)] if a.method == "separable" else g.plan_info(a.precision))
     print(f"[prof] {a.solves} solves of {a.workload} ({a.precision}, {a.method}) in {time.perf_counter() - t0:.3f} s; "
           f"launch {launch}", flush=True)
     sys.stdout.flush()

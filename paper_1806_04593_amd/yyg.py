@@ -29,6 +29,7 @@ EXPORTS = [
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
     "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind", "yyg_sep_config", "yyg_sep_info",
+    "yyg_sep_kernel",
 ]
 
 
@@ -88,6 +89,7 @@ def lib():
         L.yyg_set_method.argtypes = [vp, i]
         L.yyg_sep_config.argtypes = [vp, i, i]
         L.yyg_sep_info.argtypes = [vp, ctypes.POINTER(i), i]
+        L.yyg_sep_kernel.argtypes = [vp, i, ctypes.c_char_p, ctypes.c_size_t]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -223,6 +225,11 @@ class Grid:
         v = (ctypes.c_int * 5)()
         _check(lib().yyg_sep_info(self._h, v, 5), "yyg_sep_info")
         return list(v)
+
+    def sep_kernel(self, phase):
+        buf = ctypes.create_string_buffer(256)
+        _check(lib().yyg_sep_kernel(self._h, int(phase), buf, 256), "yyg_sep_kernel")
+        return buf.value.decode()
 
     def set_config(self, var_ana, split_ana, var_syn, precision="fp64"):
         _check(lib().yyg_plan_config(self._h, PRECISIONS.get(precision, precision), int(var_ana), int(split_ana),
