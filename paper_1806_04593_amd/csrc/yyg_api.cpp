@@ -106,6 +106,13 @@ struct yyg_grid {
     yyg::GemmF64Args phi_ana{}, phi_syn{};
     // the same two as LDS-basis kernels
     yyg::PhiDirectArgs phi_ana_d{}, phi_syn_d{};
+    // the same two folded about the patch's central meridian (the tile
+    // variants use these when the grid is mirror-symmetric: fold = true)
+    bool fold = false;
+    long h = 0, ldkh = 0, ks = 0, ldtf = 0;  // folded length, its row stride; synthesis split and row stride
+    double *WF = nullptr;    // folded analysis basis [2][n_t][L+1][ldkh]: even (cos) / odd (sin) halves
+    double *TF = nullptr;    // folded synthesis basis [h][ldtf]: cos m at m, sin m at ks + m - 1
+    yyg::GemmF64Args phi_ana_f{}, phi_syn_f{};
     // theta phases and rotation: one launch each over their problems
     yyg::SepPhaseArgs args{};
     // tile variant per phase (0 phi analysis, 1 theta analysis, 2 moment
@@ -154,8 +161,8 @@ void free_grid(yyg_grid *g) {
   if (g->d_eA) (void)hipFree(g->d_eA);
   if (g->d_eU) (void)hipFree(g->d_eU);
   {
-    void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2, g->sep.P2, g->sep.DI,
-                 g->sep.X2,  g->sep.V,    g->sep.Ut, g->sep.coefS, g->sep.At};
+    void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2,    g->sep.P2, g->sep.DI, g->sep.X2,
+                 g->sep.V,   g->sep.Ut,   g->sep.coefS, g->sep.At, g->sep.WF, g->sep.TF};
     for (void *x : b)
       if (x) (void)hipFree(x);
   }
@@ -294,8 +301,9 @@ hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   }
   const int v = S.var[r] % nv;
   const bool deep = S.var[r] >= nv;
-  if (r == 0) return yyg::launch_gemm_f64_batched(v, deep ? yyg::kRoleDeep : 0, S.phi_ana, s);
-  if (r == 4) return yyg::launch_gemm_f64_batched(v, 1 + (deep ? yyg::kRoleDeep : 0), S.phi_syn, s);
+  const int dr = deep ? yyg::kRoleDeep : 0;
+  if (r == 0) return yyg::launch_gemm_f64_batched(v, (S.fold ? 2 : 0) + dr, S.fold ? S.phi_ana_f : S.phi_ana, s);
+  if (r == 4) return yyg::launch_gemm_f64_batched(v, (S.fold ? 3 : 1) + dr, S.fold ? S.phi_syn_f : S.phi_syn, s);
   if (r == 2 && g->n_patch != 2) return hipSuccess;  // one patch: nothing to rotate
   return yyg::launch_gemm_f64_sep(v, r, deep, S.args, s);
 }
@@ -307,6 +315,8 @@ int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
   g->sep.phi_syn.C = phi;
   g->sep.phi_ana_d.X = rho;
   g->sep.phi_syn_d.C = phi;
+  g->sep.phi_ana_f.A = rho;
+  g->sep.phi_syn_f.C = phi;
   return YYG_OK;
 }
 
@@ -319,7 +329,7 @@ int sep_build(yyg_grid *g) {
   S.ldm = round_up(nmc, 16);
   S.ldl = round_up(L + 1, 16);
   if (yyg::radial_scan_q_lds(g->n_r, g->n_patch) > yyg::kScanQMaxLds) return YYG_ERR_UNSUPPORTED;
-  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS;
+  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF;
   std::vector<int> dofs;
   try {
     coef.resize((size_t)4 * g->n_r * (L + 1));
@@ -340,6 +350,55 @@ int sep_build(yyg_grid *g) {
           Wcs[((size_t)j * nmc + mc) * S.ldk + k] = g->w_host[(size_t)j * np + k] * CSt[(size_t)mc * S.ldk + k];
     trig.resize((size_t)np * S.ldm);
     yyg::separable_trig(g->geom, L, S.ldm, trig.data());
+    // Mirror symmetry about the central meridian: the cell centres, overlap
+    // weights and cos / sin bases are even / odd under k -> n_p - 1 - k (up
+    // to rounding), so each phi transform folds into an even and an odd
+    // half of ceil(n_p / 2) points.
+    {
+      double cmax = 0.0, tmax = 0.0, wbad = 0.0, cbad = 0.0, tbad = 0.0;
+      for (int mc = 0; mc < nmc; ++mc)
+        for (int k = 0; k < np; ++k) {
+          cmax = std::max(cmax, std::fabs(CSt[(size_t)mc * S.ldk + k]));
+          tmax = std::max(tmax, std::fabs(trig[(size_t)k * S.ldm + mc]));
+        }
+      for (int k = 0; k < np; ++k) {
+        const int km = np - 1 - k;
+        for (int j = 0; j < nt; ++j)
+          wbad = std::max(wbad, std::fabs(g->w_host[(size_t)j * np + k] - g->w_host[(size_t)j * np + km]));
+        for (int mc = 0; mc < nmc; ++mc) {
+          const double sg = (mc > 0 && mc % 2 == 0) ? -1.0 : 1.0;  // sin columns are odd
+          cbad = std::max(cbad, std::fabs(CSt[(size_t)mc * S.ldk + k] - sg * CSt[(size_t)mc * S.ldk + km]));
+          tbad = std::max(tbad, std::fabs(trig[(size_t)k * S.ldm + mc] - sg * trig[(size_t)km * S.ldm + mc]));
+        }
+      }
+      S.fold = wbad <= 1e-12 && cbad <= 1e-12 * cmax && tbad <= 1e-12 * tmax;
+    }
+    S.h = (np + 1) / 2;
+    S.ldkh = round_up(S.h, 16);
+    S.ks = round_up(L + 1, 16);
+    S.ldtf = S.ks + round_up(L, 16);
+    if (S.fold) {
+      const int h = S.h, mid = np % 2 ? h - 1 : -1;
+      WF.assign((size_t)2 * nt * (L + 1) * S.ldkh, 0.0);
+      TF.assign((size_t)h * S.ldtf, 0.0);
+      for (int j = 0; j < nt; ++j)
+        for (int k = 0; k < h; ++k) {
+          // one weight per mirror pair (equal up to rounding); the middle
+          // cell enters the even half twice
+          const double wb = 0.5 * (g->w_host[(size_t)j * np + k] + g->w_host[(size_t)j * np + np - 1 - k]);
+          const double f = (k == mid ? 0.5 : 1.0) * wb;
+          for (int m = 0; m <= L; ++m) {
+            WF[(((size_t)0 * nt + j) * (L + 1) + m) * S.ldkh + k] = f * CSt[(size_t)(m ? 2 * m - 1 : 0) * S.ldk + k];
+            if (m > 0)
+              WF[(((size_t)1 * nt + j) * (L + 1) + m - 1) * S.ldkh + k] = f * CSt[(size_t)(2 * m) * S.ldk + k];
+          }
+        }
+      for (int k = 0; k < h; ++k)
+        for (int m = 0; m <= L; ++m) {
+          TF[(size_t)k * S.ldtf + m] = trig[(size_t)k * S.ldm + (m ? 2 * m - 1 : 0)];
+          if (m > 0) TF[(size_t)k * S.ldtf + S.ks + m - 1] = trig[(size_t)k * S.ldm + 2 * m];
+        }
+    }
     T.resize((size_t)nt * Q);
     yyg::theta_table_normalised(g->geom, L, T.data());
     P.resize((size_t)nt * Q);
@@ -381,6 +440,8 @@ int sep_build(yyg_grid *g) {
   if (st == YYG_OK) st = dmalloc(&S.Ut, (size_t)nmc * (L + 1) * M);
   if (st == YYG_OK && g->n_patch == 2) st = dmalloc(&S.At, (size_t)M * Q);
   if (st == YYG_OK) st = dmalloc(&S.coefS, coefS.size());
+  if (st == YYG_OK && S.fold) st = dmalloc(&S.WF, WF.size());
+  if (st == YYG_OK && S.fold) st = dmalloc(&S.TF, TF.size());
   if (st != YYG_OK) return st;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
@@ -392,6 +453,10 @@ int sep_build(yyg_grid *g) {
   chk(hipMemcpy(S.P2, P2.data(), P2.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.DI, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.coefS, coefS.data(), coefS.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (S.fold) {
+    chk(hipMemcpy(S.WF, WF.data(), WF.size() * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(S.TF, TF.data(), TF.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;
@@ -406,6 +471,21 @@ int sep_build(yyg_grid *g) {
   S.phi_syn = yyg::GemmF64Args{(int)M, np, nmc, S.V, MJ, S.trig, S.ldm, nullptr, (long)nt * np, np, kround(nmc), 1};
   S.phi_syn.batch = nt;
   S.phi_syn.a_batch = M;
+  // folded: even (cos) and odd (sin) halves of every row, h = ceil(n_p / 2)
+  S.phi_ana_f = yyg::GemmF64Args{(int)M, L + 1, (int)S.h, nullptr, (long)nt * np, S.WF, S.ldkh, S.X2, MJ, M, kround(S.h), 1};
+  S.phi_ana_f.batch = 2 * nt;
+  S.phi_ana_f.a_batch = np;
+  S.phi_ana_f.b_batch = (long)(L + 1) * S.ldkh;
+  S.phi_ana_f.fold_n = nt;
+  S.phi_ana_f.fold_k = np;
+  S.phi_ana_f.fold_mc = nmc;
+  S.phi_syn_f = yyg::GemmF64Args{(int)M, (int)S.h, (int)S.ldtf, S.V, MJ, S.TF, S.ldtf, nullptr, (long)nt * np, np,
+                                 kround(S.ldtf), 1};
+  S.phi_syn_f.batch = nt;
+  S.phi_syn_f.a_batch = M;
+  S.phi_syn_f.k_split = (int)S.ks;
+  S.phi_syn_f.fold_k = np;
+  S.phi_syn_f.fold_mc = nmc;
   S.phi_ana_d = yyg::PhiDirectArgs{nullptr, S.Wcs, S.X2, (int)M, nt, nmc, np, S.ldk, (long)nmc * S.ldk};
   S.phi_syn_d = yyg::PhiDirectArgs{S.V, S.trig, nullptr, (int)M, nt, np, nmc, S.ldm, 0};
   // theta analysis, rotation (Yin-Yang) and theta synthesis: problem
@@ -1061,6 +1141,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
       (void)hipFree(tmp);
       g->sep.phi_syn.C = nullptr;  // the temporary is gone
       g->sep.phi_syn_d.C = nullptr;
+      g->sep.phi_syn_f.C = nullptr;
     }
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -1386,6 +1467,8 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     g->sep.phi_syn.C = nullptr;
     g->sep.phi_ana_d.X = nullptr;
     g->sep.phi_syn_d.C = nullptr;
+    g->sep.phi_ana_f.A = nullptr;
+    g->sep.phi_syn_f.C = nullptr;
     if (st3 != YYG_OK) return st3;
   }
   if (cache_path && (!have_a || !have_s)) {
@@ -1479,7 +1562,7 @@ int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
     name[0] = 0;
     return YYG_OK;
   }
-  return yyg::sep_kernel_name(phase, g->sep.var[phase], name, n) == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
+  return yyg::sep_kernel_name(phase, g->sep.var[phase], g->sep.fold, name, n) == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
 }
 
 int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out) {

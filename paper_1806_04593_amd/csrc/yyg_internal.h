@@ -27,6 +27,9 @@ struct GemmF64Args {
   // B + z b_batch and writes C + z c_split_stride
   int batch = 1;
   long a_batch = 0, b_batch = 0;
+  // folded phi transforms (kGemmFoldA / kGemmFoldC): problems per fold
+  // group (analysis), the unfolded row length, the azimuthal columns
+  int fold_n = 1, fold_k = 0, fold_mc = 0;
 };
 
 // Operand layouts (bit flags of the tile kernel):
@@ -37,7 +40,28 @@ struct GemmF64Args {
 //  kGemmDeep    three stages of loads in flight instead of one (short K)
 //  kGemmSplitA  (with kGemmATrans) A's columns from k_split on come from a
 //               second block a_off elements away
-enum { kGemmATrans = 2, kGemmCTrans = 4, kGemmBatch = 8, kGemmBTrans = 16, kGemmDeep = 32, kGemmSplitA = 64 };
+//  kGemmFoldA   phi analysis folded about the middle of each row: batched
+//               problem z = g fold_n + j reads A(m, k) = X(m, k) +/- X(m,
+//               fold_k - 1 - k) (+ for g = 0, - for g = 1) at A + j a_batch,
+//               B at B + z b_batch, and stores output column c of group g
+//               at azimuthal column mc = max(2c - 1, 0) (g = 0) or 2c + 2
+//               (g = 1), if mc < fold_mc, of the column-major C + j
+//               c_split_stride
+//  kGemmFoldC   phi synthesis folded: A (k-major) row k is the azimuthal
+//               column max(2k - 1, 0) for k < k_split, 2 (k - k_split) + 2
+//               beyond (clamped below fold_mc); stages below k_split sum the
+//               even part e, the rest the odd part o; output column c gets
+//               e + o, column fold_k - 1 - c gets e - o
+enum {
+  kGemmATrans = 2,
+  kGemmCTrans = 4,
+  kGemmBatch = 8,
+  kGemmBTrans = 16,
+  kGemmDeep = 32,
+  kGemmSplitA = 64,
+  kGemmFoldA = 128,
+  kGemmFoldC = 256
+};
 // role offset of the kGemmDeep forms of the batched roles
 constexpr int kRoleDeep = 16;
 
@@ -76,8 +100,9 @@ hipError_t launch_phi_direct(int variant, bool analysis, const PhiDirectArgs &a,
 hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s);
 
 // Strided batch of g.batch equal-shape problems, whole K each: role 0
-// stores C column-major, role 1 reads A k-major (plain epilogue otherwise);
-// roles + kRoleDeep: the same with kGemmDeep.
+// stores C column-major, role 1 reads A k-major (plain epilogue otherwise),
+// role 2 = role 0 with kGemmFoldA, role 3 = role 1 with kGemmFoldC; roles
+// + kRoleDeep: the same with kGemmDeep.
 hipError_t launch_gemm_f64_batched(int variant, int role, const GemmF64Args &g, hipStream_t s);
 
 // FP64 NT GEMM C = A . B^T in one of several tile shapes ("variants");
@@ -186,7 +211,7 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
 int gemm_f64_variant_threads(int v);
 // Kernel symbol (as profilers print it) of variant v of separable phase
 // `phase`; 0, or -1 for an invalid phase / variant.
-int sep_kernel_name(int phase, int v, char *buf, size_t n);
+int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n);
 
 
 // Split-K factor for an output of `tiles` block tiles and K columns.

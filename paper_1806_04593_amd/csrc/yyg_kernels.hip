@@ -67,10 +67,18 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr bool BATCH = (MODE & kGemmBatch) != 0;
   constexpr bool BT = (MODE & kGemmBTrans) != 0;
   constexpr bool SPLIT = (MODE & kGemmSplitA) != 0;
+  constexpr bool FOLDA = (MODE & kGemmFoldA) != 0;
+  constexpr bool FOLDC = (MODE & kGemmFoldC) != 0;
   static_assert(!SPLIT || AT, "the split A operand is stored k-major");
+  static_assert(!FOLDA || (BATCH && CT && !AT && !GEN), "folded analysis: batched, row-major A, C column-major");
+  static_assert(!FOLDC || (BATCH && AT && !CT && !GEN && !SPLIT), "folded synthesis: batched, A k-major");
 
   const int M = g.M, N = g.N, K = g.K;
-  const double *__restrict__ A = g.A + (BATCH ? z * g.a_batch : 0L);
+  // FOLDA: problem z = group * fold_n + zj (group 0 the even, 1 the odd half)
+  const int fgrp = FOLDA ? z / g.fold_n : 0;
+  const int zj = FOLDA ? z - fgrp * g.fold_n : z;
+  const double fsign = fgrp ? -1.0 : 1.0;
+  const double *__restrict__ A = g.A + (BATCH ? zj * g.a_batch : 0L);
   const double *__restrict__ B = g.B + (BATCH ? z * g.b_batch : 0L);
   double *__restrict__ C = g.C;
   const long lda = g.lda, ldb = g.ldb, ldc = g.ldc;
@@ -94,15 +102,22 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   // z is the split-K slice, or with BATCH the problem of a strided batch
   const int kbeg = BATCH ? 0 : z * g.k_per_split;
   const int kend = BATCH ? K : min(K, kbeg + g.k_per_split);
-  C += (long)z * g.c_split_stride;
+  C += (long)zj * g.c_split_stride;
 
   const int wm = wave % WGM, wn = wave / WGM;
 
-  dbl4 acc[TI][TJ];
+  // FOLDC: acc sums the stages below k_split (the even part), acc2 the rest
+  dbl4 acc[TI][TJ], acc2[FOLDC ? TI : 1][FOLDC ? TJ : 1];
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  if constexpr (FOLDC) {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) acc2[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
 
   constexpr int PF = (MODE & kGemmDeep) ? kDeepPF : kPF;
   double ra[PF][EA], rb[PF][EB];
@@ -116,10 +131,15 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   // condition would be waited for before the next one issues); stash: the
   // entries outside the matrix or the stage's k range are zeroed on the way
   // into LDS, after the stage's MFMA work, so the loads overlap it.
+  // FOLDA: A(m, k) = X(m, k) + sign X(m, fold_k - 1 - k), the even (odd)
+  // half of a row about its middle
+  auto aval = [&](const double *row, int kc) {
+    return FOLDA ? row[kc] + fsign * row[g.fold_k - 1 - kc] : row[kc];
+  };
   auto load = [&](double (&ra)[EA], double (&rb)[EB], int k0) {
     if constexpr (RUN_A) {
 #pragma unroll
-      for (int i = 0; i < EA; ++i) ra[i] = pa[min(k0 + acol + i, K - 1)];
+      for (int i = 0; i < EA; ++i) ra[i] = aval(pa, min(k0 + acol + i, K - 1));
     } else if constexpr (AT) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
@@ -132,13 +152,18 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
             off = g.a_off;
           }
         }
+        if constexpr (FOLDC) {
+          // contraction index -> azimuthal column: cos m at k = m, sin m at
+          // k_split + m - 1 (padding clamps; its basis entries are zero)
+          kc = min(kc < g.k_split ? max(2 * kc - 1, 0) : 2 * (kc - g.k_split) + 2, g.fold_mc - 1);
+        }
         ra[i] = A[(long)kc * lda + off + min(gm, M - 1)];
       }
     } else {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        ra[i] = A[(long)min(m0 + row, M - 1) * lda + min(kk, K - 1)];
+        ra[i] = aval(A + (long)min(m0 + row, M - 1) * lda, min(kk, K - 1));
       }
     }
     if constexpr (RUN_B) {
@@ -194,7 +219,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   };
 
   const int frow = lane & 15, fk = 4 * (lane >> 4);
-  auto compute = [&](int buf) {
+  auto compute = [&](int buf, bool second) {
     // Each lane holds four consecutive k of its row; MFMA step s uses the
     // s-th of them, so the four steps cover the 16 k of the stage once.
     double af[TI][4], bf[TJ][4];
@@ -210,13 +235,24 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) bf[j][s4] = sp[s4];
     }
+    if (FOLDC && second) {  // uniform: the whole stage is past k_split
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4)
+      for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < TJ; ++j)
+            acc2[FOLDC ? i : 0][FOLDC ? j : 0] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                af[i][s4], bf[j][s4], acc2[FOLDC ? i : 0][FOLDC ? j : 0], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
+    }
   };
 
   const int nk = (kend - kbeg + kBK - 1) / kBK;
@@ -236,7 +272,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
       if (it < nk) {  // uniform across the block
         const int buf = it & 1;
         if (it + PF < nk) load(ra[sl], rb[sl], kbeg + (it + PF) * kBK);
-        compute(buf);
+        compute(buf, FOLDC && kbeg + it * kBK >= g.k_split);
         if (it + 1 < nk) stash(ra[(sl + 1) % PF], rb[(sl + 1) % PF], buf ^ 1, kbeg + (it + 1) * kBK);
         __syncthreads();
       }
@@ -258,8 +294,19 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
           if constexpr (GEN) {
             const long cc = g.c_sq < 0 ? (long)col : (long)(col + g.c_sq) * (col + g.c_sq);
             C[(long)row * ldc + cc * g.ldc_c] = acc[i][j][r];
+          } else if constexpr (FOLDA) {
+            // output column -> azimuthal column: cos m (group 0, col m), sin m
+            // (group 1, col m - 1)
+            const int mc = max(2 * col + (fgrp ? 2 : -1), 0);
+            if (mc < g.fold_mc) C[(long)mc * ldc + row] = acc[i][j][r];
           } else if constexpr (CT) {
             C[(long)col * ldc + row] = acc[i][j][r];
+          } else if constexpr (FOLDC) {
+            // the even part plus / minus the odd part, at col and its mirror
+            const double e = acc[i][j][r], o = acc2[FOLDC ? i : 0][FOLDC ? j : 0][r];
+            const int cm = g.fold_k - 1 - col;
+            C[(long)row * ldc + col] = e + o;
+            if (cm != col) C[(long)row * ldc + cm] = e - o;
           } else {
             C[(long)row * ldc + col] = acc[i][j][r];
           }
@@ -917,8 +964,8 @@ hipError_t launch_grouped_variant(int role, const GemmF64Args *probs, const int4
 }
 
 // Strided batch (see gemm_nt_f64_batched): role 0 stores C column-major
-// (kGemmCTrans), role 1 reads A k-major (kGemmATrans); + kRoleDeep: the
-// same with kGemmDeep.
+// (kGemmCTrans), role 1 reads A k-major (kGemmATrans), roles 2 and 3 the
+// same with kGemmFoldA / kGemmFoldC; + kRoleDeep: with kGemmDeep.
 template <int BM, int BN, int WGM, int WGN>
 hipError_t launch_batch_variant(int role, const GemmF64Args &a, hipStream_t s) {
   GemmF64Args g = a;
@@ -939,6 +986,18 @@ hipError_t launch_batch_variant(int role, const GemmF64Args &a, hipStream_t s) {
   else if (role == 1 + kRoleDeep)
     hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans | kGemmDeep>), grid, block, 0, s, g, per,
                        (int)total);
+  else if (role == 2)
+    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmFoldA>), grid, block, 0, s, g,
+                       per, (int)total);
+  else if (role == 3)
+    hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans | kGemmFoldC>), grid, block, 0, s, g,
+                       per, (int)total);
+  else if (role == 2 + kRoleDeep)
+    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmFoldA | kGemmDeep>), grid, block,
+                       0, s, g, per, (int)total);
+  else if (role == 3 + kRoleDeep)
+    hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans | kGemmFoldC | kGemmDeep>), grid, block,
+                       0, s, g, per, (int)total);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1151,7 +1210,7 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
 
 int gemm_f64_variant_threads(int v) { return kF64Variants[v].threads; }
 
-int sep_kernel_name(int phase, int v, char *buf, size_t n) {
+int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n) {
   const int nv = gemm_f64_variant_count(), nd = phi_direct_variant_count();
   if (phase < 0 || phase > 4 || v < 0 || v >= 2 * nv + ((phase == 0 || phase == 4) ? nd : 0)) return -1;
   if (v >= 2 * nv) {
@@ -1161,9 +1220,11 @@ int sep_kernel_name(int phase, int v, char *buf, size_t n) {
   }
   const F64Variant &f = kF64Variants[v % nv];
   const int deep = v >= nv ? kGemmDeep : 0;
-  if (phase == 0 || phase == 4)
+  if (phase == 0 || phase == 4) {
+    const int mode = phase == 0 ? kGemmCTrans | (fold ? kGemmFoldA : 0) : kGemmATrans | (fold ? kGemmFoldC : 0);
     return snprintf(buf, n, "yyg::gemm_nt_f64_batched<%d, %d, %d, %d, %d, %d>", phase == 0 ? 0 : 1, f.bm, f.bn, f.wm,
-                    f.wn, (phase == 0 ? kGemmCTrans : kGemmATrans) | deep) < 0 ? -1 : 0;
+                    f.wn, mode | deep) < 0 ? -1 : 0;
+  }
   const int mode = phase == 1 ? 1 | kGemmATrans : phase == 2 ? 1 | kGemmATrans | kGemmBTrans | kGemmSplitA : kGemmBTrans;
   return snprintf(buf, n, "yyg::gemm_f64_sep_phase<%d, %d, %d, %d, %d, %d>", phase, f.bm, f.bn, f.wm, f.wn,
                   mode | deep) < 0 ? -1 : 0;
