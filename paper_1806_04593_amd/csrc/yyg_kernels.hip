@@ -792,9 +792,10 @@ __global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a)
     }
 }
 
-// Radial scan of Eqs. (31)-(34) on column-major moments X[q][p nR + n]: one
-// block per column q, one wave per patch.  The column (and its degree's
-// recurrence coefficients, coefS[l][4][nR], shared by the waves) is staged
+// Radial sums of Eqs. (19)-(20) (the recurrences above) on column-major
+// moments X[q][p nR + n]: one block per column q, one wave per patch.  The
+// column (and its degree's recurrence coefficients, coefS[l][4][nR], shared
+// by the waves) is staged
 // in LDS; lane i owns the radial chunk [i c, i c + c) (c odd, so that the
 // chunk-strided LDS reads spread over the banks); the chunk summaries
 // (product of multipliers, local value) combine across the wave with

@@ -250,3 +250,44 @@ def test_polar_descriptor_rules():
         with pytest.raises(yyg.YygError) as ei:
             yyg.host_table(bad, yyg.TABLE_WEIGHTS)
         assert ei.value.status == -1, change
+
+
+@pytest.mark.parametrize("kind,res", [("yinyang", 2.0), ("yinyang", 7.0), ("yinyang", 9.0), ("polar", 5.0),
+                                      ("polar", 7.5)])
+def test_mirror_symmetry_and_folded_phi_transform(kind, res):
+    """The separable form folds each phi transform about the patch's central
+    meridian (k -> n_phi - 1 - k): that needs the overlap weights even and
+    the cos / sin cell integrals even / odd under the mirror, and then the
+    contraction over n_phi cells equals the even / odd halves over
+    ceil(n_phi / 2) (the middle cell, for odd n_phi, counted once)."""
+    L = 12
+    d = _desc(res, L) if kind == "yinyang" else W.make_polar_desc("p", np.linspace(0.0, 1.0, 3), res, L, 1.0, 0)
+    nt, npp = d["n_theta"], d["n_phi"]
+    w = yyg.host_table(d, yyg.TABLE_WEIGHTS).reshape(nt, npp)
+    CS = yyg.host_table(d, yyg.TABLE_PHI).reshape(npp, -1)
+    assert np.max(np.abs(w - w[:, ::-1])) <= 1e-12
+    cols = _col_lm(L)
+    for q, (l, m, s) in enumerate(cols):
+        sg = -1.0 if s else 1.0
+        assert np.max(np.abs(CS[:, q] - sg * CS[::-1, q])) <= 1e-12 * max(1e-300, np.max(np.abs(CS[:, q])))
+    # folded analysis of random rows against the plain contraction
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(-1.0, 1.0, (7, nt, npp))
+    h = (npp + 1) // 2
+    half = np.ones(h)
+    if npp % 2:
+        half[-1] = 0.5
+    wb = 0.5 * (w + w[:, ::-1])[:, :h] * half
+    E = rho[..., :h] + rho[..., ::-1][..., :h]
+    Od = rho[..., :h] - rho[..., ::-1][..., :h]
+    for q, (l, m, s) in enumerate(cols):
+        plain = np.einsum("rjk,jk,k->rj", rho, w, CS[:, q])
+        folded = np.einsum("rjk,jk,k->rj", Od if s else E, wb, CS[:h, q])
+        assert np.max(np.abs(folded - plain)) <= 1e-13 * np.max(np.abs(rho)) * npp, (l, m, s)
+    # folded synthesis: even part plus / minus odd part at k and its mirror
+    coef = rng.normal(size=(7, nt, len(cols)))
+    plain = np.einsum("rjq,kq->rjk", coef, CS)
+    ev = sum(np.einsum("rj,k->rjk", coef[..., q], CS[:h, q]) for q, c in enumerate(cols) if not c[2])
+    od = sum(np.einsum("rj,k->rjk", coef[..., q], CS[:h, q]) for q, c in enumerate(cols) if c[2])
+    back = np.concatenate([ev + od, (ev - od)[..., ::-1][..., npp % 2:]], axis=-1)
+    assert np.max(np.abs(back - plain)) <= 1e-13 * np.max(np.abs(plain))
