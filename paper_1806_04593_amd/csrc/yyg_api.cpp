@@ -110,7 +110,7 @@ struct yyg_grid {
     // variants use these when the grid is mirror-symmetric: fold = true)
     bool fold = false;
     long h = 0, ldkh = 0, ks = 0, ldtf = 0;  // folded length, its row stride; synthesis split and row stride
-    double *WF = nullptr;    // folded analysis basis [2][n_t][L+1][ldkh]: even (cos) / odd (sin) halves
+    double *WF = nullptr;    // folded analysis basis [n_t][2][L+1][ldkh]: even (cos) / odd (sin) halves
     double *TF = nullptr;    // folded synthesis basis [h][ldtf]: cos m at m, sin m at ks + m - 1
     yyg::GemmF64Args phi_ana_f{}, phi_syn_f{};
     // theta phases and rotation: one launch each over their problems
@@ -388,9 +388,9 @@ int sep_build(yyg_grid *g) {
           const double wb = 0.5 * (g->w_host[(size_t)j * np + k] + g->w_host[(size_t)j * np + np - 1 - k]);
           const double f = (k == mid ? 0.5 : 1.0) * wb;
           for (int m = 0; m <= L; ++m) {
-            WF[(((size_t)0 * nt + j) * (L + 1) + m) * S.ldkh + k] = f * CSt[(size_t)(m ? 2 * m - 1 : 0) * S.ldk + k];
+            WF[(((size_t)j * 2 + 0) * (L + 1) + m) * S.ldkh + k] = f * CSt[(size_t)(m ? 2 * m - 1 : 0) * S.ldk + k];
             if (m > 0)
-              WF[(((size_t)1 * nt + j) * (L + 1) + m - 1) * S.ldkh + k] = f * CSt[(size_t)(2 * m) * S.ldk + k];
+              WF[(((size_t)j * 2 + 1) * (L + 1) + m - 1) * S.ldkh + k] = f * CSt[(size_t)(2 * m) * S.ldk + k];
           }
         }
       for (int k = 0; k < h; ++k)
@@ -476,7 +476,6 @@ int sep_build(yyg_grid *g) {
   S.phi_ana_f.batch = 2 * nt;
   S.phi_ana_f.a_batch = np;
   S.phi_ana_f.b_batch = (long)(L + 1) * S.ldkh;
-  S.phi_ana_f.fold_n = nt;
   S.phi_ana_f.fold_k = np;
   S.phi_ana_f.fold_mc = nmc;
   S.phi_syn_f = yyg::GemmF64Args{(int)M, (int)S.h, (int)S.ldtf, S.V, MJ, S.TF, S.ldtf, nullptr, (long)nt * np, np,

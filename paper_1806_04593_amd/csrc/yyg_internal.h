@@ -27,9 +27,9 @@ struct GemmF64Args {
   // B + z b_batch and writes C + z c_split_stride
   int batch = 1;
   long a_batch = 0, b_batch = 0;
-  // folded phi transforms (kGemmFoldA / kGemmFoldC): problems per fold
-  // group (analysis), the unfolded row length, the azimuthal columns
-  int fold_n = 1, fold_k = 0, fold_mc = 0;
+  // folded phi transforms (kGemmFoldA / kGemmFoldC): the unfolded row
+  // length and the number of azimuthal columns
+  int fold_k = 0, fold_mc = 0;
 };
 
 // Operand layouts (bit flags of the tile kernel):
@@ -41,7 +41,7 @@ struct GemmF64Args {
 //  kGemmSplitA  (with kGemmATrans) A's columns from k_split on come from a
 //               second block a_off elements away
 //  kGemmFoldA   phi analysis folded about the middle of each row: batched
-//               problem z = g fold_n + j reads A(m, k) = X(m, k) +/- X(m,
+//               problem z = 2 j + g reads A(m, k) = X(m, k) +/- X(m,
 //               fold_k - 1 - k) (+ for g = 0, - for g = 1) at A + j a_batch,
 //               B at B + z b_batch, and stores output column c of group g
 //               at azimuthal column mc = max(2c - 1, 0) (g = 0) or 2c + 2

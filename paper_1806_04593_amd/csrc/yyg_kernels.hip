@@ -74,9 +74,10 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   static_assert(!FOLDC || (BATCH && AT && !CT && !GEN && !SPLIT), "folded synthesis: batched, A k-major");
 
   const int M = g.M, N = g.N, K = g.K;
-  // FOLDA: problem z = group * fold_n + zj (group 0 the even, 1 the odd half)
-  const int fgrp = FOLDA ? z / g.fold_n : 0;
-  const int zj = FOLDA ? z - fgrp * g.fold_n : z;
+  // FOLDA: problem z = 2 zj + group (group 0 the even, 1 the odd half), so
+  // that the two halves of a row tile run close together and share L2
+  const int fgrp = FOLDA ? (z & 1) : 0;
+  const int zj = FOLDA ? (z >> 1) : z;
   const double fsign = fgrp ? -1.0 : 1.0;
   const double *__restrict__ A = g.A + (BATCH ? zj * g.a_batch : 0L);
   const double *__restrict__ B = g.B + (BATCH ? z * g.b_batch : 0L);
@@ -120,7 +121,10 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   }
 
   constexpr int PF = (MODE & kGemmDeep) ? kDeepPF : kPF;
-  double ra[PF][EA], rb[PF][EB];
+  // FOLDA keeps the raw front and mirror values (ra[i], ra[EA + i]) until
+  // the stash: folding them at load time would wait for the loads there
+  constexpr int EAR = FOLDA ? 2 * EA : EA;
+  double ra[PF][EAR], rb[PF][EB];
   // run mapping: this thread's row and first column
   const int arow = RUN_A ? tid / (kBK / EA) : 0, acol = RUN_A ? (tid % (kBK / EA)) * EA : 0;
   const int brow = RUN_B ? tid / (kBK / EB) : 0, bcol = RUN_B ? (tid % (kBK / EB)) * EB : 0;
@@ -133,13 +137,15 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   // into LDS, after the stage's MFMA work, so the loads overlap it.
   // FOLDA: A(m, k) = X(m, k) + sign X(m, fold_k - 1 - k), the even (odd)
   // half of a row about its middle
-  auto aval = [&](const double *row, int kc) {
-    return FOLDA ? row[kc] + fsign * row[g.fold_k - 1 - kc] : row[kc];
+  auto aload = [&](double (&ra)[EAR], int i, const double *row, int kc) {
+    ra[i] = row[kc];
+    if constexpr (FOLDA) ra[EA + i] = row[g.fold_k - 1 - kc];
   };
-  auto load = [&](double (&ra)[EA], double (&rb)[EB], int k0) {
+  auto aval = [&](const double (&ra)[EAR], int i) { return FOLDA ? ra[i] + fsign * ra[(FOLDA ? EA : 0) + i] : ra[i]; };
+  auto load = [&](double (&ra)[EAR], double (&rb)[EB], int k0) {
     if constexpr (RUN_A) {
 #pragma unroll
-      for (int i = 0; i < EA; ++i) ra[i] = aval(pa, min(k0 + acol + i, K - 1));
+      for (int i = 0; i < EA; ++i) aload(ra, i, pa, min(k0 + acol + i, K - 1));
     } else if constexpr (AT) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
@@ -163,7 +169,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        ra[i] = aval(A + (long)min(m0 + row, M - 1) * lda, min(kk, K - 1));
+        aload(ra, i, A + (long)min(m0 + row, M - 1) * lda, min(kk, K - 1));
       }
     }
     if constexpr (RUN_B) {
@@ -183,10 +189,11 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
       }
     }
   };
-  auto stash = [&](const double (&ra)[EA], const double (&rb)[EB], int buf, int k0) {
+  auto stash = [&](const double (&ra)[EAR], const double (&rb)[EB], int buf, int k0) {
     if constexpr (RUN_A) {
 #pragma unroll
-      for (int i = 0; i < EA; ++i) As[buf][arow * kLDK + acol + i] = (va && k0 + acol + i < kend) ? ra[i] : 0.0;
+      for (int i = 0; i < EA; ++i)
+        As[buf][arow * kLDK + acol + i] = (va && k0 + acol + i < kend) ? aval(ra, i) : 0.0;
     } else if constexpr (AT) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
@@ -197,7 +204,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        if (e < BM * kBK) As[buf][row * kLDK + e % kBK] = (m0 + row < M && kk < kend) ? ra[i] : 0.0;
+        if (e < BM * kBK) As[buf][row * kLDK + e % kBK] = (m0 + row < M && kk < kend) ? aval(ra, i) : 0.0;
       }
     }
     if constexpr (RUN_B) {
