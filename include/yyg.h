@@ -138,8 +138,15 @@ int yyg_prepare(yyg_grid *g, int precision);
  *                        into this patch's frame (exact rotation blocks of
  *                        the real harmonics under the Yin <-> Yang map,
  *                        computed once), then one synthesis over theta and
- *                        one over phi.  Equal to the dense result up to
- *                        rounding; about 4(2L+1) + 4Q/n_phi flops per cell.
+ *                        one over phi.  On a grid that is mirror-symmetric
+ *                        about the patch's central meridian (every Yin-Yang
+ *                        and polar grid this library builds) each phi
+ *                        transform folds into even and odd halves of
+ *                        ceil(n_phi/2) points.  Equal to the dense result up
+ *                        to rounding; about 2(2L+1) + 4Q/n_phi flops per
+ *                        cell.  Needs 8(4 n_r + P(2 n_r + 1)) bytes of LDS
+ *                        for its radial scan (P patches): YYG_ERR_UNSUPPORTED
+ *                        beyond 160 KiB (n_r > 2559 on a Yin-Yang grid).
  * Switching to the separable form builds its tables (allocates). */
 enum { YYG_METHOD_DENSE = 0, YYG_METHOD_SEPARABLE = 1 };
 int yyg_set_method(yyg_grid *g, int method);

@@ -204,6 +204,22 @@ def test_determinism_and_patch_swap():
     del torch
 
 
+def test_separable_shell_limit():
+    """The separable form's radial scan keeps a column in LDS: more shells
+    than fit are refused with YYG_ERR_UNSUPPORTED, and the dense form of
+    the same plan still solves."""
+    yyg = _yyg()
+    _torch()
+    desc = W.make_desc("deep", np.linspace(0.0, 1.0, 2601), 30.0, 2, 1.0, 0)
+    g = yyg.Grid(desc, 0)
+    with pytest.raises(yyg.YygError) as ei:
+        g.set_method("separable")
+    assert ei.value.status == -5
+    rho = np.ones(g.shape)
+    _, phi = _gpu_solve(desc, rho, grid=g)
+    assert np.all(np.isfinite(phi)) and np.all(phi < 0)
+
+
 def test_host_buffers_and_not_ready():
     yyg = _yyg()
     _torch()
