@@ -115,9 +115,10 @@ struct yyg_grid {
     yyg::GemmF64Args phi_ana_f{}, phi_syn_f{};
     // theta phases and rotation: one launch each over their problems
     yyg::SepPhaseArgs args{};
-    // tile variant per phase (0 phi analysis, 1 theta analysis, 2 moment
-    // rotation, 3 theta synthesis, 4 phi synthesis); V + v = tile v with
-    // the deep prefetch
+    // variant per phase (0 phi analysis, 1 theta analysis, 2 moment
+    // rotation, 3 theta synthesis, 4 phi synthesis): v < V the tile v,
+    // V + v the same with the deep prefetch, 2V + d (phi phases) the
+    // LDS-basis kernel d
     static constexpr int kDefaultVariant = 9;  // 64 x 32 tiles
     int var[5] = {kDefaultVariant, kDefaultVariant, kDefaultVariant, kDefaultVariant, kDefaultVariant};
   } sep;

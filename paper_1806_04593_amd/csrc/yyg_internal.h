@@ -208,9 +208,10 @@ constexpr size_t kScanQMaxLds = 160 * 1024;
 size_t radial_scan_q_lds(int nR, int patches);
 hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int *qdeg, int nR, int L, double negG,
                                 int patches, double *Ut, hipStream_t s);
-int gemm_f64_variant_threads(int v);
+
 // Kernel symbol (as profilers print it) of variant v of separable phase
-// `phase`; 0, or -1 for an invalid phase / variant.
+// `phase`, with the phi phases folded (fold) or not; 0, or -1 for an
+// invalid phase / variant.
 int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n);
 
 

@@ -1216,8 +1216,6 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
   return hipErrorInvalidValue;
 }
 
-int gemm_f64_variant_threads(int v) { return kF64Variants[v].threads; }
-
 int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n) {
   const int nv = gemm_f64_variant_count(), nd = phi_direct_variant_count();
   if (phase < 0 || phase > 4 || v < 0 || v >= 2 * nv + ((phase == 0 || phase == 4) ? nd : 0)) return -1;
