@@ -251,7 +251,9 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * patch's moments (Yin-Yang grids; no work on a polar grid), 3 theta
  * synthesis, 4 phi synthesis.  variant in [0, 2V), V = the number of FP64
  * tile variants: V + v is tile v with three stages of operand loads in
- * flight instead of one.  Needs the separable form built
+ * flight instead of one; the phi phases also take [2V, 2V + 6), kernels
+ * that keep the phi basis in LDS and stream the data straight into MFMA
+ * fragments (unfolded).  Needs the separable form built
  * (yyg_set_method); synchronises the device.  For tests and expert tuning;
  * yyg_autotune chooses all of them. */
 int yyg_sep_config(yyg_grid *g, int phase, int variant);
