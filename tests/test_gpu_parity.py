@@ -354,3 +354,40 @@ def test_separable_every_phase_variant(phase):
         _, phi = _gpu_solve(desc, rho, grid=g)
         err = _max_rel(phi, ref)
         assert err <= TOL_FP64, (phase, v, err)
+
+
+@pytest.mark.parametrize("method", ["dense", "separable"])
+def test_solve_captures_in_a_graph(method):
+    """A solve on device buffers is asynchronous and allocation-free, so it
+    records into a HIP graph: replays (with eager work and synchronisations
+    between them) reproduce the eager result bit for bit."""
+    torch = _torch()
+    yyg = _yyg()
+    desc = W.describe("small")
+    rho = W.density(desc)
+    g = yyg.Grid(desc, 0)
+    if method == "separable":
+        g.set_method("separable")
+    d_rho = torch.from_numpy(rho).to("cuda")
+    d_phi = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    g.upload_rho(d_rho)
+    g.solve(d_phi)
+    torch.cuda.synchronize()
+    eager = d_phi.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g.solve(d_phi)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.solve(d_phi)
+    for rep in range(3):
+        d_phi.fill_(0.0)
+        _ = (torch.arange(4096, device="cuda", dtype=torch.float64) * rep).sum().item()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(d_phi, eager), (method, rep)
+    assert _max_rel(eager.cpu().numpy(), O.solve(*_oracle_args(desc), rho)) <= TOL_FP64
