@@ -119,8 +119,9 @@ struct yyg_grid {
     // rotation, 3 theta synthesis, 4 phi synthesis): v < V the tile v,
     // V + v the same with the deep prefetch, 2V + d (phi phases) the
     // LDS-basis kernel d
-    static constexpr int kDefaultVariant = 9;  // 64 x 32 tiles
-    int var[5] = {kDefaultVariant, kDefaultVariant, kDefaultVariant, kDefaultVariant, kDefaultVariant};
+    // defaults (before autotuning): 32 x 32 tiles, 64 x 32 for the theta
+    // synthesis
+    int var[5] = {10, 10, 10, 9, 10};
   } sep;
 
   bool timing = false;
@@ -1438,21 +1439,26 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
       if (st3 == YYG_OK) (void)hipMemsetAsync(rho_t, 0, (size_t)M * g->nang * sizeof(double), s);
     }
     if (st3 == YYG_OK) st3 = sep_set_pointers(g, g->rho ? g->rho : rho_t, phi_t, s);
-    // a variant replaces the default tile only when it is 3% faster, so
-    // that near-ties do not flip between runs
+    // Each phase in turn (the others at their current choice): every
+    // variant is timed inside whole back-to-back solves, where the kernels
+    // meet the caches and clocks they run under in use (timed alone, the
+    // short phases rank differently); a variant replaces the current one only
+    // when the solve gets faster by more than 0.5% (at least 0.3 us), so that
+    // near-ties do not flip between runs.
+    auto solve_ms = [&]() { return time_launch([&] { return sep_solve(g, s); }, s, 5); };
+    const bool timing = g->timing;
+    g->timing = false;  // no per-phase events while tuning
     for (int r = 0; r < 5 && st3 == YYG_OK; ++r) {
       if (r == 2 && g->n_patch != 2) continue;  // one patch: no rotation
-      const int v0 = yyg_grid::Sep::kDefaultVariant;
-      st3 = sep_set_variant(g, r, v0);
-      if (st3 != YYG_OK) break;
-      const double t0 = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 5);
-      double best = 0.97 * t0;
+      const int v0 = g->sep.var[r];
+      const double t0 = solve_ms();
+      double best = t0 - std::max(0.0003, 0.005 * t0);
       int bv = v0;
       for (int v = 0; v < sep_variant_count(r) && st3 == YYG_OK; ++v) {
         if (v == v0) continue;
         st3 = sep_set_variant(g, r, v);
         if (st3 != YYG_OK) break;
-        double t = time_launch([&] { return sep_launch_phase(g, r, s); }, s, 5);
+        const double t = solve_ms();
         if (t < best) {
           best = t;
           bv = v;
@@ -1460,6 +1466,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
       }
       if (st3 == YYG_OK) st3 = sep_set_variant(g, r, bv);
     }
+    g->timing = timing;
     (void)hipStreamSynchronize(s);
     if (phi_t) (void)hipFree(phi_t);
     if (rho_t) (void)hipFree(rho_t);
