@@ -212,6 +212,12 @@ def bench_single(a):
         g.set_method("separable")
         if not a.no_autotune:
             g.autotune("fp64")
+        if a.sep_variants:
+            # profiling runs: the variants an unprofiled run chose (the
+            # autotuner's timings shift under a profiler)
+            for phase, v in enumerate(int(x) for x in a.sep_variants.split(",")):
+                if v >= 0:
+                    g.sep_config(phase, v)
         ms = timed_steps(g, d_phi, "fp64", a)
         kms, kcnt = phase_pass(g, d_phi, "fp64", a)
         avg = [float(kms[i] / max(1, kcnt[i])) for i in range(8)]
@@ -418,6 +424,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--sep-variants", default=None,
+                    help="comma-separated variants of the five separable phases (as yyg_sep_config), set after "
+                         "autotuning; for profiling the kernels an unprofiled run chose")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {a.gpus} requested): the solver holds the whole grid on "
