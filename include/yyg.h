@@ -253,9 +253,12 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * tile variants: V + v is tile v with three stages of operand loads in
  * flight instead of one; the phi phases also take [2V, 2V + 6), kernels
  * that keep the phi basis in LDS and stream the data straight into MFMA
- * fragments (unfolded).  Needs the separable form built
- * (yyg_set_method); synchronises the device.  For tests and expert tuning;
- * yyg_autotune chooses all of them. */
+ * fragments (unfolded), and [2V + 6, 2V + 14), the same kernels folded
+ * about the patch's central meridian (h = ceil(n_phi / 2) cells per row;
+ * YYG_ERR_UNSUPPORTED on a grid whose rows are not mirror-symmetric, the
+ * condition under which the tile variants of the phi phases fold too).
+ * Needs the separable form built (yyg_set_method); synchronises the
+ * device.  For tests and expert tuning; yyg_autotune chooses all of them. */
 int yyg_sep_config(yyg_grid *g, int phase, int variant);
 
 /* variants[0..4] = the separable form's tile variant per phase (-1 for

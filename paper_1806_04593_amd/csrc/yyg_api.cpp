@@ -110,15 +110,22 @@ struct yyg_grid {
     // variants use these when the grid is mirror-symmetric: fold = true)
     bool fold = false;
     long h = 0, ldkh = 0, ks = 0, ldtf = 0;  // folded length, its row stride; synthesis split and row stride
+    long kca = 0, nba = 0, kcs = 0, nks = 0;  // folded LDS-basis kernels: cos rows / slots and totals
     double *WF = nullptr;    // folded analysis basis [n_t][2][L+1][ldkh]: even (cos) / odd (sin) halves
     double *TF = nullptr;    // folded synthesis basis [h][ldtf]: cos m at m, sin m at ks + m - 1
     yyg::GemmF64Args phi_ana_f{}, phi_syn_f{};
+    // folded LDS-basis kernels: the cos / sin halves without padding each to
+    // the tile width
+    double *WFD = nullptr;   // analysis basis [n_t][kca + 16 ceil(L/16)][h]: cos m at row m, sin m at kca + m - 1
+    double *TFD = nullptr;   // synthesis basis [h][kcs + 4 ceil(L/4)]: cos m at slot m, sin m at kcs + m - 1
+    yyg::PhiDirectArgs phi_ana_fd{}, phi_syn_fd{};
     // theta phases and rotation: one launch each over their problems
     yyg::SepPhaseArgs args{};
     // variant per phase (0 phi analysis, 1 theta analysis, 2 moment
     // rotation, 3 theta synthesis, 4 phi synthesis): v < V the tile v,
     // V + v the same with the deep prefetch, 2V + d (phi phases) the
-    // LDS-basis kernel d
+    // LDS-basis kernel d, 2V + D + f (phi phases, fold) the folded
+    // LDS-basis kernel f
     // defaults (before autotuning): 32 x 32 tiles, 64 x 32 for the theta
     // synthesis
     int var[5] = {10, 10, 10, 9, 10};
@@ -164,7 +171,8 @@ void free_grid(yyg_grid *g) {
   if (g->d_eU) (void)hipFree(g->d_eU);
   {
     void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2,    g->sep.P2, g->sep.DI, g->sep.X2,
-                 g->sep.V,   g->sep.Ut,   g->sep.coefS, g->sep.At, g->sep.WF, g->sep.TF};
+                 g->sep.V,   g->sep.Ut,   g->sep.coefS, g->sep.At, g->sep.WF, g->sep.TF,
+                 g->sep.WFD, g->sep.TFD};
     for (void *x : b)
       if (x) (void)hipFree(x);
   }
@@ -282,25 +290,31 @@ namespace {
 
 // Variants of separable phase r: v < V the tile v, V + v the same with
 // three stages of loads in flight (V = the FP64 tile variants); the phi
-// phases (0, 4) also 2V + d, the LDS-basis kernel variant d.
+// phases (0, 4) also 2V + d, the LDS-basis kernel variant d (d < D), and
+// 2V + D + f, its folded form f (mirror-symmetric grids only).
 int sep_variant_count(int r) {
   const int v = 2 * yyg::gemm_f64_variant_count();
-  return (r == 0 || r == 4) ? v + yyg::phi_direct_variant_count() : v;
+  return (r == 0 || r == 4) ? v + yyg::phi_direct_variant_count() + yyg::phi_fold_variant_count() : v;
+}
+
+bool sep_fold_variant(int r, int v) {
+  return (r == 0 || r == 4) && v >= 2 * yyg::gemm_f64_variant_count() + yyg::phi_direct_variant_count();
 }
 
 int sep_set_variant(yyg_grid *g, int r, int v) {
   if (r < 0 || r > 4 || v < 0 || v >= sep_variant_count(r)) return YYG_ERR_INVALID_ARG;
+  if (sep_fold_variant(r, v) && !g->sep.fold) return YYG_ERR_UNSUPPORTED;
   g->sep.var[r] = v;
   return YYG_OK;
 }
 
 hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
-  const int nv = yyg::gemm_f64_variant_count();
-  if ((r == 0 || r == 4) && S.var[r] >= 2 * nv) {
-    yyg::PhiDirectArgs d = r == 0 ? S.phi_ana_d : S.phi_syn_d;
-    return yyg::launch_phi_direct(S.var[r] - 2 * nv, r == 0, d, s);
-  }
+  const int nv = yyg::gemm_f64_variant_count(), nd = yyg::phi_direct_variant_count();
+  if (sep_fold_variant(r, S.var[r]))
+    return yyg::launch_phi_fold(S.var[r] - 2 * nv - nd, r == 0, r == 0 ? S.phi_ana_fd : S.phi_syn_fd, s);
+  if ((r == 0 || r == 4) && S.var[r] >= 2 * nv)
+    return yyg::launch_phi_direct(S.var[r] - 2 * nv, r == 0, r == 0 ? S.phi_ana_d : S.phi_syn_d, s);
   const int v = S.var[r] % nv;
   const bool deep = S.var[r] >= nv;
   const int dr = deep ? yyg::kRoleDeep : 0;
@@ -319,6 +333,8 @@ int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
   g->sep.phi_syn_d.C = phi;
   g->sep.phi_ana_f.A = rho;
   g->sep.phi_syn_f.C = phi;
+  g->sep.phi_ana_fd.X = rho;
+  g->sep.phi_syn_fd.C = phi;
   return YYG_OK;
 }
 
@@ -331,7 +347,7 @@ int sep_build(yyg_grid *g) {
   S.ldm = round_up(nmc, 16);
   S.ldl = round_up(L + 1, 16);
   if (yyg::radial_scan_q_lds(g->n_r, g->n_patch) > yyg::kScanQMaxLds) return YYG_ERR_UNSUPPORTED;
-  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF;
+  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD;
   std::vector<int> dofs;
   try {
     coef.resize((size_t)4 * g->n_r * (L + 1));
@@ -355,7 +371,13 @@ int sep_build(yyg_grid *g) {
     // Mirror symmetry about the central meridian: the cell centres, overlap
     // weights and cos / sin bases are even / odd under k -> n_p - 1 - k (up
     // to rounding), so each phi transform folds into an even and an odd
-    // half of ceil(n_p / 2) points.
+    // half of ceil(n_p / 2) points.  The bases are closed forms, symmetric
+    // to a few ulps; a weight is the covered fraction of a cell, the
+    // difference of O(1) terms over the cell's solid angle, so its rounding
+    // grows as the cells shrink (1.5e-12 between mirror cells at 0.5 deg):
+    // the weights are checked to 1e-10 (an asymmetric grid is off by the
+    // partial cells' O(1e-3) and more) and each mirror pair takes their mean,
+    // as close to the exact fraction as either.
     {
       double cmax = 0.0, tmax = 0.0, wbad = 0.0, cbad = 0.0, tbad = 0.0;
       for (int mc = 0; mc < nmc; ++mc)
@@ -373,7 +395,7 @@ int sep_build(yyg_grid *g) {
           tbad = std::max(tbad, std::fabs(trig[(size_t)k * S.ldm + mc] - sg * trig[(size_t)km * S.ldm + mc]));
         }
       }
-      S.fold = wbad <= 1e-12 && cbad <= 1e-12 * cmax && tbad <= 1e-12 * tmax;
+      S.fold = np >= 2 && wbad <= 1e-10 && cbad <= 1e-12 * cmax && tbad <= 1e-12 * tmax;
     }
     S.h = (np + 1) / 2;
     S.ldkh = round_up(S.h, 16);
@@ -399,6 +421,27 @@ int sep_build(yyg_grid *g) {
         for (int m = 0; m <= L; ++m) {
           TF[(size_t)k * S.ldtf + m] = trig[(size_t)k * S.ldm + (m ? 2 * m - 1 : 0)];
           if (m > 0) TF[(size_t)k * S.ldtf + S.ks + m - 1] = trig[(size_t)k * S.ldm + 2 * m];
+        }
+      // the same for the folded LDS-basis kernels: the cos half padded to a
+      // multiple of 16 rows (analysis) / 4 slots (synthesis), the sin half
+      // after it
+      S.kca = round_up(L + 1, 16);
+      S.kcs = round_up(L + 1, 4);
+      S.nba = S.kca + round_up(L, 16);
+      S.nks = S.kcs + round_up(L, 4);
+      WFD.assign((size_t)nt * S.nba * h, 0.0);
+      TFD.assign((size_t)h * S.nks, 0.0);
+      for (int j = 0; j < nt; ++j)
+        for (int m = 0; m <= L; ++m)
+          for (int k = 0; k < h; ++k) {
+            const double *wf = &WF[((size_t)j * 2 * (L + 1)) * S.ldkh + k];
+            WFD[((size_t)j * S.nba + m) * h + k] = wf[(size_t)m * S.ldkh];
+            if (m > 0) WFD[((size_t)j * S.nba + S.kca + m - 1) * h + k] = wf[(size_t)(L + 1 + m - 1) * S.ldkh];
+          }
+      for (int k = 0; k < h; ++k)
+        for (int m = 0; m <= L; ++m) {
+          TFD[(size_t)k * S.nks + m] = TF[(size_t)k * S.ldtf + m];
+          if (m > 0) TFD[(size_t)k * S.nks + S.kcs + m - 1] = TF[(size_t)k * S.ldtf + S.ks + m - 1];
         }
     }
     T.resize((size_t)nt * Q);
@@ -444,6 +487,8 @@ int sep_build(yyg_grid *g) {
   if (st == YYG_OK) st = dmalloc(&S.coefS, coefS.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.WF, WF.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.TF, TF.size());
+  if (st == YYG_OK && S.fold) st = dmalloc(&S.WFD, WFD.size());
+  if (st == YYG_OK && S.fold) st = dmalloc(&S.TFD, TFD.size());
   if (st != YYG_OK) return st;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
@@ -458,6 +503,8 @@ int sep_build(yyg_grid *g) {
   if (S.fold) {
     chk(hipMemcpy(S.WF, WF.data(), WF.size() * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemcpy(S.TF, TF.data(), TF.size() * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(S.WFD, WFD.data(), WFD.size() * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(S.TFD, TFD.data(), TFD.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -489,6 +536,10 @@ int sep_build(yyg_grid *g) {
   S.phi_syn_f.fold_mc = nmc;
   S.phi_ana_d = yyg::PhiDirectArgs{nullptr, S.Wcs, S.X2, (int)M, nt, nmc, np, S.ldk, (long)nmc * S.ldk};
   S.phi_syn_d = yyg::PhiDirectArgs{S.V, S.trig, nullptr, (int)M, nt, np, nmc, S.ldm, 0};
+  S.phi_ana_fd = yyg::PhiDirectArgs{nullptr, S.WFD, S.X2, (int)M, nt, (int)S.nba, (int)S.h, S.h, S.nba * S.h,
+                                    np, (int)S.kca, nmc};
+  S.phi_syn_fd = yyg::PhiDirectArgs{S.V, S.TFD, nullptr, (int)M, nt, (int)S.h, (int)S.nks, S.nks, 0,
+                                    np, (int)S.kcs, nmc};
   // theta analysis, rotation (Yin-Yang) and theta synthesis: problem
   // operands derived in the kernels from these
   S.args = yyg::SepPhaseArgs{L,    g->n_r, g->n_patch, nt,  S.ldl, S.X2, S.T2, S.P2,
@@ -1143,6 +1194,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
       g->sep.phi_syn.C = nullptr;  // the temporary is gone
       g->sep.phi_syn_d.C = nullptr;
       g->sep.phi_syn_f.C = nullptr;
+      g->sep.phi_syn_fd.C = nullptr;
     }
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -1455,7 +1507,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
       double best = t0 - std::max(0.0003, 0.005 * t0);
       int bv = v0;
       for (int v = 0; v < sep_variant_count(r) && st3 == YYG_OK; ++v) {
-        if (v == v0) continue;
+        if (v == v0 || (sep_fold_variant(r, v) && !g->sep.fold)) continue;
         st3 = sep_set_variant(g, r, v);
         if (st3 != YYG_OK) break;
         const double t = solve_ms();
@@ -1476,6 +1528,8 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     g->sep.phi_syn_d.C = nullptr;
     g->sep.phi_ana_f.A = nullptr;
     g->sep.phi_syn_f.C = nullptr;
+    g->sep.phi_ana_fd.X = nullptr;
+    g->sep.phi_syn_fd.C = nullptr;
     if (st3 != YYG_OK) return st3;
   }
   if (cache_path && (!have_a || !have_s)) {

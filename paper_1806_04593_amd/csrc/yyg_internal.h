@@ -52,6 +52,8 @@ struct GemmF64Args {
 //               beyond (clamped below fold_mc); stages below k_split sum the
 //               even part e, the rest the odd part o; output column c gets
 //               e + o, column fold_k - 1 - c gets e - o
+//  kGemmDT      accumulate the transposed tile (B A^T): each store then
+//               covers 16 consecutive rows, for C stored column-major
 enum {
   kGemmATrans = 2,
   kGemmCTrans = 4,
@@ -60,7 +62,8 @@ enum {
   kGemmDeep = 32,
   kGemmSplitA = 64,
   kGemmFoldA = 128,
-  kGemmFoldC = 256
+  kGemmFoldC = 256,
+  kGemmDT = 512
 };
 // role offset of the kGemmDeep forms of the batched roles
 constexpr int kRoleDeep = 16;
@@ -86,14 +89,24 @@ struct SepPhaseArgs {
 //             N ldb);
 //  synthesis: C = phi[row][j][k] (N = n_p) from X = V [mc][j][row] (K = 2L+1)
 //             and bas = trig [k][ldb] (bas_batch = 0).
+// The folded forms (launch_phi_fold) run over h = ceil(n_p / 2) cells:
+//  analysis:  N = the folded basis rows (cos m at row m, sin m at row kc +
+//             m - 1; kc a multiple of 16), K = h, bas = [j][N][ldb];
+//  synthesis: N = h, K = the contraction slots (cos m at slot m, sin m at
+//             slot kc + m - 1; kc a multiple of 4), bas = [h][ldb]
+//             (bas_batch = 0);
+// with np = n_p and nmc = 2L+1 the azimuthal columns.
 struct PhiDirectArgs {
   const double *X, *bas;
   double *C;
   int M, nt, N, K;  // rows, colatitudes, basis rows, contraction length
   long ldb, bas_batch;
+  int np = 0, kc = 0, nmc = 0;  // folded forms only
 };
 int phi_direct_variant_count();
 hipError_t launch_phi_direct(int variant, bool analysis, const PhiDirectArgs &a, hipStream_t s);
+int phi_fold_variant_count();
+hipError_t launch_phi_fold(int variant, bool analysis, const PhiDirectArgs &a, hipStream_t s);
 
 // phase 1 theta analysis, 2 rotation (two patches), 3 theta synthesis;
 // deep = kGemmDeep.

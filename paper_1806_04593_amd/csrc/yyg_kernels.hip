@@ -69,7 +69,9 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr bool SPLIT = (MODE & kGemmSplitA) != 0;
   constexpr bool FOLDA = (MODE & kGemmFoldA) != 0;
   constexpr bool FOLDC = (MODE & kGemmFoldC) != 0;
+  constexpr bool DT = (MODE & kGemmDT) != 0;
   static_assert(!SPLIT || AT, "the split A operand is stored k-major");
+  static_assert(!DT || !FOLDC, "the folded synthesis stores rows");
   static_assert(!FOLDA || (BATCH && CT && !AT && !GEN), "folded analysis: batched, row-major A, C column-major");
   static_assert(!FOLDC || (BATCH && AT && !CT && !GEN && !SPLIT), "folded synthesis: batched, A k-major");
 
@@ -141,9 +143,28 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
     ra[i] = row[kc];
     if constexpr (FOLDA) ra[EA + i] = row[g.fold_k - 1 - kc];
   };
+  // FOLDA, a run of EA (even) values per thread: pairs of neighbours as one
+  // 16-byte load each at the front and at the mirror.  K = h < fold_k, so a
+  // pair starting at a clamped kc <= K - 1 stays inside the row on both sides
+  // (its second value, past K, is zeroed at the stash like every value past K).
+  typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
+  auto apairs = [&](double (&ra)[EAR], const double *row, int k0) {
+#pragma unroll
+    for (int i = 0; i < EA; i += 2) {
+      const int kc = min(k0 + acol + i, K - 1);
+      const dbl2u f = *reinterpret_cast<const dbl2u *>(row + kc);
+      const dbl2u b = *reinterpret_cast<const dbl2u *>(row + (g.fold_k - 2 - kc));
+      ra[i] = f.x;
+      ra[i + 1] = f.y;
+      ra[EA + i] = b.y;
+      ra[EA + i + 1] = b.x;
+    }
+  };
   auto aval = [&](const double (&ra)[EAR], int i) { return FOLDA ? ra[i] + fsign * ra[(FOLDA ? EA : 0) + i] : ra[i]; };
   auto load = [&](double (&ra)[EAR], double (&rb)[EB], int k0) {
-    if constexpr (RUN_A) {
+    if constexpr (RUN_A && FOLDA && EA % 2 == 0) {
+      apairs(ra, pa, k0);
+    } else if constexpr (RUN_A) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) aload(ra, i, pa, min(k0 + acol + i, K - 1));
     } else if constexpr (AT) {
@@ -252,13 +273,15 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
             acc2[FOLDC ? i : 0][FOLDC ? j : 0] = __builtin_amdgcn_mfma_f64_16x16x4f64(
                 af[i][s4], bf[j][s4], acc2[FOLDC ? i : 0][FOLDC ? j : 0], 0, 0, 0);
     } else {
+      // DT: the transposed tile B A^T, so that a store covers 16 rows
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
           for (int j = 0; j < TJ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
+            acc[i][j] = DT ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j][s4], af[i][s4], acc[i][j], 0, 0, 0)
+                           : __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
     }
   };
 
@@ -287,16 +310,17 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   }
 
   // D layout of the 16x16x4 f64 MFMA: lane l, element r -> row l/16 + 4r,
-  // col l%16 (one row per output group, unlike the f32 variant's four).
+  // col l%16 (one row per output group, unlike the f32 variant's four);
+  // with DT the roles of row and column swap.
   const int orow = lane >> 4, ocol = lane & 15;
 #pragma unroll
   for (int i = 0; i < TI; ++i) {
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
-      const int col = n0 + wn * (BN / WGN) + j * 16 + ocol;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * (BM / WGM) + i * 16 + orow + 4 * r;
+        const int row = m0 + wm * (BM / WGM) + i * 16 + (DT ? ocol : orow + 4 * r);
+        const int col = n0 + wn * (BN / WGN) + j * 16 + (DT ? orow + 4 * r : ocol);
         if (row < M && col < N) {
           if constexpr (GEN) {
             const long cc = g.c_sq < 0 ? (long)col : (long)(col + g.c_sq) * (col + g.c_sq);
@@ -709,9 +733,24 @@ __global__ void expand_self_basis_kernel(const double *__restrict__ P, const dou
 //            MFMA's A side is the basis (rows mc), the B side the data.
 //  synthesis:       phi[row][j][k] = sum_mc V[mc][j][row] trig[k][mc]; the
 //            A side is the data (rows), the B side the basis (rows k).
-template <bool ANA, int WAVES, int NT, int NBUF>
+// FOLD: every row of n_p cells is even (cos) / odd (sin) about its middle,
+// so the transforms run over h = ceil(n_p / 2) cells (the kGemmFoldA /
+// kGemmFoldC forms, without their padding of each half to 16):
+//  analysis:  basis rows kc (a multiple of 16) apart: row i < kc is cos m =
+//             i, row i >= kc sin m = i - kc + 1 (W_j folded, K = h); a cos
+//             tile multiplies rho[k] + rho[n_p - 1 - k], a sin tile
+//             rho[k] - rho[n_p - 1 - k]; row i lands at azimuthal column mc
+//             (dropped when mc >= nmc);
+//  synthesis: contraction slots in steps of 4 consecutive slots, slot s < kc
+//             (a multiple of 4) cos m = s, beyond sin m = s - kc + 1; the data
+//             of a slot is V's azimuthal column mc (clamped below nmc; the
+//             basis is zero at padding slots); the cos steps sum the even
+//             part e, the sin steps the odd part o, and cell k < h gets
+//             e + o, its mirror n_p - 1 - k gets e - o.
+template <bool ANA, int WAVES, int NT, int NBUF, bool FOLD>
 __global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a) {
   constexpr int G = 16 * NT, KC = 64, NTH = 64 * WAVES, PF = 4;
+  constexpr bool FA = FOLD && ANA, FS = FOLD && !ANA;
   constexpr int EL = (G * KC + NTH - 1) / NTH;  // basis chunk elements per thread
   __shared__ __align__(16) double sB[NBUF][G][KC + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -719,70 +758,123 @@ __global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a)
   const int j = blockIdx.y, g0 = blockIdx.z * G;
   const int r0 = blockIdx.x * (16 * WAVES) + 16 * wave;
   const int M = a.M, N = a.N, K = a.K, nt = a.nt;
+  const int np = FOLD ? a.np : (ANA ? K : N);  // cells per row
   const double *__restrict__ bas = a.bas + (long)j * a.bas_batch;
   // this lane's data row (clamped) and its view of the contraction index
   const int row = min(r0 + lr, M - 1);
   const double *__restrict__ xr =
-      ANA ? a.X + (long)row * ((long)nt * K) + (long)j * K : a.X + (long)j * M + row;
+      ANA ? a.X + (long)row * ((long)nt * np) + (long)j * np : a.X + (long)j * M + row;
   const long xk = ANA ? 1 : (long)nt * M;  // stride of the contraction index
-  auto xload = [&](int st, double (&v)[4]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = xr[(long)min(st * 16 + 4 * lg + s, K - 1) * xk];
-  };
+  // contraction slot of step s of stage st: each lane four consecutive
+  // slots (one per step) or, FS, each step four consecutive slots
+  auto slot = [&](int st, int s) { return FS ? 16 * st + 4 * s + lg : 16 * st + 4 * lg + s; };
+  double xs[PF][4], xm[FA ? PF : 1][4];
   double stg[EL];
-  auto bload = [&](int c) {
-#pragma unroll
-    for (int u = 0; u < EL; ++u) {
-      const int e = min(tid + NTH * u, G * KC - 1), br = e / KC, kk = e % KC;
-      stg[u] = bas[(long)min(g0 + br, N - 1) * a.ldb + min(c * KC + kk, K - 1)];
-    }
-  };
-  auto bstore = [&](int c, int buf) {
-#pragma unroll
-    for (int u = 0; u < EL; ++u) {
-      const int e = tid + NTH * u, br = e / KC, kk = e % KC;
-      if (e < G * KC) sB[buf][br][kk] = keep_if(g0 + br < N && c * KC + kk < K, stg[u]);
-    }
-  };
-
-  dbl4 acc[NT];
+  // FS: acc sums the cos slots (even part), acc2 the sin slots (odd part)
+  dbl4 acc[NT], acc2[FS ? NT : 1];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const int nst = (K + 15) / 16, nch = (K + KC - 1) / KC;
-  double xs[PF][4];
+  if constexpr (FS) {
 #pragma unroll
-  for (int p = 0; p < PF; ++p) xload(min(p, nst - 1), xs[p]);
-  bload(0);
-  __builtin_amdgcn_sched_barrier(0);
-  bstore(0, 0);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = NBUF == 2 ? (c & 1) : 0;
-    if (c + 1 < nch) bload(c + 1);
-    // the chunk's four stages; stage st = 4c + q sits in register slot q
+    for (int t = 0; t < NT; ++t) acc2[FS ? t : 0] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+
+  // The contraction over slots [kb, kb + kn) into ac: data fragments PF
+  // stages ahead in registers, the basis in chunks of KC slots through LDS.
+  auto run = [&](dbl4 (&ac)[NT], int kb, int kn) {
+    auto xload = [&](int st, int q) {
 #pragma unroll
-    for (int q = 0; q < KC / 16; ++q) {
-      const int st = c * (KC / 16) + q;
-      if (st < nst) {  // uniform
-        double bf[NT][4];
+      for (int s = 0; s < 4; ++s) {
+        const int k = kb + min(slot(st, s), kn - 1);
+        if constexpr (FS) {
+          const int m = k < a.kc ? k : k - a.kc + 1;
+          const int mc = min(k < a.kc ? max(2 * m - 1, 0) : 2 * m, a.nmc - 1);
+          xs[q][s] = xr[(long)mc * xk];
+        } else {
+          xs[q][s] = xr[(long)k * xk];
+          if constexpr (FA) xm[FA ? q : 0][s] = xr[np - 1 - k];
+        }
+      }
+    };
+    auto bload = [&](int c) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+      for (int u = 0; u < EL; ++u) {
+        const int e = min(tid + NTH * u, G * KC - 1), br = e / KC, kk = e % KC;
+        stg[u] = bas[(long)min(g0 + br, N - 1) * a.ldb + kb + min(c * KC + kk, kn - 1)];
+      }
+    };
+    auto bstore = [&](int c, int buf) {
 #pragma unroll
-          for (int s = 0; s < 4; ++s) bf[t][s] = sB[buf][16 * t + lr][16 * q + 4 * lg + s];
+      for (int u = 0; u < EL; ++u) {
+        const int e = tid + NTH * u, br = e / KC, kk = e % KC;
+        if (e < G * KC) sB[buf][br][kk] = keep_if(g0 + br < N && c * KC + kk < kn, stg[u]);
+      }
+    };
+    const int nst = (kn + 15) / 16, nch = (kn + KC - 1) / KC;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+    for (int p = 0; p < PF; ++p) xload(min(p, nst - 1), p);
+    bload(0);
+    __builtin_amdgcn_sched_barrier(0);
+    bstore(0, 0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      const int buf = NBUF == 2 ? (c & 1) : 0;
+      if (c + 1 < nch) bload(c + 1);
+      // the chunk's four stages; stage st = 4c + q sits in register slot q
+#pragma unroll
+      for (int q = 0; q < KC / 16; ++q) {
+        const int st = c * (KC / 16) + q;
+        if (st < nst) {  // uniform
+          double bf[NT][4];
 #pragma unroll
           for (int t = 0; t < NT; ++t)
-            acc[t] = ANA ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[t][s], xs[q][s], acc[t], 0, 0, 0)
-                         : __builtin_amdgcn_mfma_f64_16x16x4f64(xs[q][s], bf[t][s], acc[t], 0, 0, 0);
-        if (st + PF < nst) xload(st + PF, xs[q]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) bf[t][s] = sB[buf][16 * t + lr][slot(q, s)];
+          if constexpr (FA) {
+            // the even and odd parts of the data; a tile is all cos or all sin
+            double de[4], dd[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              de[s] = xs[q][s] + xm[FA ? q : 0][s];
+              dd[s] = xs[q][s] - xm[FA ? q : 0][s];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+              for (int t = 0; t < NT; ++t)
+                ac[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[t][s], g0 + 16 * t < a.kc ? de[s] : dd[s], ac[t], 0,
+                                                             0, 0);
+          } else if constexpr (FS) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              if (16 * st + 4 * s < kn) {  // uniform: steps past the end skipped
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                  ac[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[q][s], bf[t][s], ac[t], 0, 0, 0);
+              }
+          } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+              for (int t = 0; t < NT; ++t)
+                ac[t] = ANA ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[t][s], xs[q][s], ac[t], 0, 0, 0)
+                            : __builtin_amdgcn_mfma_f64_16x16x4f64(xs[q][s], bf[t][s], ac[t], 0, 0, 0);
+          }
+          if (st + PF < nst) xload(st + PF, q);
+        }
       }
+      if (c + 1 < nch) {
+        if (NBUF == 1) __syncthreads();  // every wave is done with the one buffer
+        bstore(c + 1, NBUF == 2 ? buf ^ 1 : 0);
+      }
+      __syncthreads();
     }
-    if (c + 1 < nch) {
-      if (NBUF == 1) __syncthreads();  // every wave is done with the one buffer
-      bstore(c + 1, NBUF == 2 ? buf ^ 1 : 0);
-    }
-    __syncthreads();
+  };
+  if constexpr (FS) {
+    run(acc, 0, a.kc);
+    if (K > a.kc) run(acc2, a.kc, K - a.kc);  // none at L = 0
+  } else {
+    run(acc, 0, K);
   }
   // D layout: lane l, element e -> MFMA row l/16 + 4e, column l%16
 #pragma unroll
@@ -790,11 +882,25 @@ __global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       if (ANA) {
-        const int mc = g0 + 16 * t + lg + 4 * e, r = r0 + lr;
-        if (mc < N && r < M) a.C[(long)mc * ((long)nt * M) + (long)j * M + r] = acc[t][e];
+        const int br = g0 + 16 * t + lg + 4 * e, r = r0 + lr;
+        int mc = br;
+        if constexpr (FA) {
+          const int m = br < a.kc ? br : br - a.kc + 1;
+          mc = br < a.kc ? max(2 * m - 1, 0) : 2 * m;
+        }
+        if (br < N && mc < (FA ? a.nmc : N) && r < M) a.C[(long)mc * ((long)nt * M) + (long)j * M + r] = acc[t][e];
       } else {
         const int r = r0 + lg + 4 * e, k = g0 + 16 * t + lr;
-        if (r < M && k < N) a.C[(long)r * ((long)nt * N) + (long)j * N + k] = acc[t][e];
+        if (r < M && k < N) {
+          double *__restrict__ cr = a.C + (long)r * ((long)nt * np) + (long)j * np;
+          if constexpr (FS) {
+            const double ev = acc[t][e], od = acc2[FS ? t : 0][e];
+            cr[k] = ev + od;
+            if (np - 1 - k != k) cr[np - 1 - k] = ev - od;
+          } else {
+            cr[k] = acc[t][e];
+          }
+        }
       }
     }
 }
@@ -982,27 +1088,28 @@ hipError_t launch_batch_variant(int role, const GemmF64Args &a, hipStream_t s) {
   const long total = (long)per * g.batch;
   if (total > INT_MAX) return hipErrorInvalidValue;
   dim3 grid((unsigned)total), block(64 * WGM * WGN);
+  // column-major C: the transposed accumulation (kGemmDT) stores 16 rows at once
   if (role == 0)
-    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans>), grid, block, 0, s, g, per,
+    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmDT>), grid, block, 0, s, g, per,
                        (int)total);
   else if (role == 1)
     hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans>), grid, block, 0, s, g, per,
                        (int)total);
   else if (role == kRoleDeep)
-    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmDeep>), grid, block, 0, s, g, per,
-                       (int)total);
+    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmDT | kGemmDeep>), grid, block, 0, s,
+                       g, per, (int)total);
   else if (role == 1 + kRoleDeep)
     hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans | kGemmDeep>), grid, block, 0, s, g, per,
                        (int)total);
   else if (role == 2)
-    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmFoldA>), grid, block, 0, s, g,
-                       per, (int)total);
+    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmDT | kGemmFoldA>), grid, block, 0,
+                       s, g, per, (int)total);
   else if (role == 3)
     hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans | kGemmFoldC>), grid, block, 0, s, g,
                        per, (int)total);
   else if (role == 2 + kRoleDeep)
-    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmFoldA | kGemmDeep>), grid, block,
-                       0, s, g, per, (int)total);
+    hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, kGemmCTrans | kGemmDT | kGemmFoldA | kGemmDeep>), grid,
+                       block, 0, s, g, per, (int)total);
   else if (role == 3 + kRoleDeep)
     hipLaunchKernelGGL((gemm_nt_f64_batched<1, BM, BN, WGM, WGN, kGemmATrans | kGemmFoldC | kGemmDeep>), grid, block,
                        0, s, g, per, (int)total);
@@ -1028,7 +1135,9 @@ hipError_t launch_sep_variant(int phase, bool deep, const SepPhaseArgs &a, hipSt
   }
   if ((mmax + BM - 1) / BM > INT_MAX || (nmax + BN - 1) / BN > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)((mmax + BM - 1) / BM), (unsigned)((nmax + BN - 1) / BN), nz), block(64 * WGM * WGN);
-  constexpr int A1 = 1 | kGemmATrans, A2 = 1 | kGemmATrans | kGemmBTrans | kGemmSplitA, A3 = kGemmBTrans;
+  // phases 1 and 2 store column-major (ldc = 1): transposed accumulation
+  constexpr int A1 = 1 | kGemmATrans | kGemmDT, A2 = 1 | kGemmATrans | kGemmBTrans | kGemmSplitA | kGemmDT,
+                A3 = kGemmBTrans;
 #define YYG_SEP_GO(P, M)                                                                                     \
   hipLaunchKernelGGL((gemm_f64_sep_phase<P, BM, BN, WGM, WGN, M>), grid, block, 0, s, a);                  \
   break
@@ -1073,6 +1182,9 @@ const F64Variant kF64Variants[] = {
     YYG_F64_VARIANT(64, 32, 2, 2),
     // more waves per tile for the short contractions of the separable form
     YYG_F64_VARIANT(32, 32, 2, 2),   YYG_F64_VARIANT(64, 64, 4, 2),
+    // five MFMA columns per wave: folded phi transforms whose N is one or a
+    // few past a multiple of 32 or 64 (L + 1 = 65, h = 69)
+    YYG_F64_VARIANT(32, 80, 2, 1),   YYG_F64_VARIANT(64, 80, 4, 1),
 };
 
 }  // namespace
@@ -1093,22 +1205,37 @@ hipError_t launch_gemm_f64_grouped(int variant, int role, const GemmF64Args *pro
 
 namespace {
 
-template <bool ANA, int WAVES, int NT, int NBUF>
+template <bool ANA, int WAVES, int NT, int NBUF, bool FOLD>
 hipError_t launch_phi_direct_t(const PhiDirectArgs &a, hipStream_t s) {
   dim3 grid((a.M + 16 * WAVES - 1) / (16 * WAVES), a.nt, (a.N + 16 * NT - 1) / (16 * NT));
-  hipLaunchKernelGGL((phi_direct_kernel<ANA, WAVES, NT, NBUF>), grid, dim3(64 * WAVES), 0, s, a);
+  hipLaunchKernelGGL((phi_direct_kernel<ANA, WAVES, NT, NBUF, FOLD>), grid, dim3(64 * WAVES), 0, s, a);
   return hipGetLastError();
 }
 
 template <bool ANA>
 hipError_t launch_phi_direct_v(int variant, const PhiDirectArgs &a, hipStream_t s) {
   switch (variant) {
-    case 0: return launch_phi_direct_t<ANA, 8, 4, 2>(a, s);
-    case 1: return launch_phi_direct_t<ANA, 8, 3, 2>(a, s);
-    case 2: return launch_phi_direct_t<ANA, 8, 2, 2>(a, s);
-    case 3: return launch_phi_direct_t<ANA, 4, 4, 2>(a, s);
-    case 4: return launch_phi_direct_t<ANA, 4, 3, 2>(a, s);
-    case 5: return launch_phi_direct_t<ANA, 4, 2, 2>(a, s);
+    case 0: return launch_phi_direct_t<ANA, 8, 4, 2, false>(a, s);
+    case 1: return launch_phi_direct_t<ANA, 8, 3, 2, false>(a, s);
+    case 2: return launch_phi_direct_t<ANA, 8, 2, 2, false>(a, s);
+    case 3: return launch_phi_direct_t<ANA, 4, 4, 2, false>(a, s);
+    case 4: return launch_phi_direct_t<ANA, 4, 3, 2, false>(a, s);
+    case 5: return launch_phi_direct_t<ANA, 4, 2, 2, false>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <bool ANA>
+hipError_t launch_phi_fold_v(int variant, const PhiDirectArgs &a, hipStream_t s) {
+  switch (variant) {
+    case 0: return launch_phi_direct_t<ANA, 2, 4, 1, true>(a, s);
+    case 1: return launch_phi_direct_t<ANA, 4, 4, 1, true>(a, s);
+    case 2: return launch_phi_direct_t<ANA, 8, 4, 1, true>(a, s);
+    case 3: return launch_phi_direct_t<ANA, 2, 5, 1, true>(a, s);
+    case 4: return launch_phi_direct_t<ANA, 4, 5, 1, true>(a, s);
+    case 5: return launch_phi_direct_t<ANA, 8, 5, 1, true>(a, s);
+    case 6: return launch_phi_direct_t<ANA, 4, 4, 2, true>(a, s);
+    case 7: return launch_phi_direct_t<ANA, 4, 5, 2, true>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1119,13 +1246,26 @@ hipError_t launch_phi_direct_v(int variant, const PhiDirectArgs &a, hipStream_t 
 // (measured on MI355X: single-buffered groups of 96-144 basis rows were
 // slower than these at 2L+1 = 51 and n_p = 137)
 const int kPhiDirect[][3] = {{8, 4, 2}, {8, 3, 2}, {8, 2, 2}, {4, 4, 2}, {4, 3, 2}, {4, 2, 2}};
+// the same for the folded form
+const int kPhiFold[][3] = {{2, 4, 1}, {4, 4, 1}, {8, 4, 1}, {2, 5, 1}, {4, 5, 1}, {8, 5, 1}, {4, 4, 2}, {4, 5, 2}};
 
 int phi_direct_variant_count() { return (int)(sizeof(kPhiDirect) / sizeof(kPhiDirect[0])); }
+int phi_fold_variant_count() { return (int)(sizeof(kPhiFold) / sizeof(kPhiFold[0])); }
 
 hipError_t launch_phi_direct(int variant, bool analysis, const PhiDirectArgs &a, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || a.nt <= 0) return hipSuccess;
   if (a.K <= 0 || a.nt > 65535 || (a.N + 31) / 32 > 65535) return hipErrorInvalidValue;
   return analysis ? launch_phi_direct_v<true>(variant, a, s) : launch_phi_direct_v<false>(variant, a, s);
+}
+
+hipError_t launch_phi_fold(int variant, bool analysis, const PhiDirectArgs &a, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || a.nt <= 0) return hipSuccess;
+  if (a.K <= 0 || a.nt > 65535 || (a.N + 31) / 32 > 65535 || a.nmc < 1) return hipErrorInvalidValue;
+  // the cos / sin boundary: whole basis tiles (analysis), whole steps (synthesis)
+  if (a.kc < 0 || a.kc % (analysis ? 16 : 4) != 0) return hipErrorInvalidValue;
+  // analysis: K = h cells of the n_p per row; synthesis: N = h
+  if ((analysis ? a.K : a.N) != (a.np + 1) / 2) return hipErrorInvalidValue;
+  return analysis ? launch_phi_fold_v<true>(variant, a, s) : launch_phi_fold_v<false>(variant, a, s);
 }
 
 hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s) {
@@ -1217,21 +1357,27 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
 }
 
 int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n) {
-  const int nv = gemm_f64_variant_count(), nd = phi_direct_variant_count();
-  if (phase < 0 || phase > 4 || v < 0 || v >= 2 * nv + ((phase == 0 || phase == 4) ? nd : 0)) return -1;
+  const int nv = gemm_f64_variant_count(), nd = phi_direct_variant_count(), nf = phi_fold_variant_count();
+  const bool phi = phase == 0 || phase == 4;
+  if (phase < 0 || phase > 4 || v < 0 || v >= 2 * nv + (phi ? nd + nf : 0)) return -1;
   if (v >= 2 * nv) {
-    const int *d = kPhiDirect[v - 2 * nv];
-    return snprintf(buf, n, "yyg::phi_direct_kernel<%s, %d, %d, %d>", phase == 0 ? "true" : "false", d[0], d[1],
-                    d[2]) < 0 ? -1 : 0;
+    const bool fd = v >= 2 * nv + nd;
+    if (fd && !fold) return -1;
+    const int *d = fd ? kPhiFold[v - 2 * nv - nd] : kPhiDirect[v - 2 * nv];
+    return snprintf(buf, n, "yyg::phi_direct_kernel<%s, %d, %d, %d, %s>", phase == 0 ? "true" : "false", d[0], d[1],
+                    d[2], fd ? "true" : "false") < 0 ? -1 : 0;
   }
   const F64Variant &f = kF64Variants[v % nv];
   const int deep = v >= nv ? kGemmDeep : 0;
   if (phase == 0 || phase == 4) {
-    const int mode = phase == 0 ? kGemmCTrans | (fold ? kGemmFoldA : 0) : kGemmATrans | (fold ? kGemmFoldC : 0);
+    const int mode =
+        phase == 0 ? kGemmCTrans | kGemmDT | (fold ? kGemmFoldA : 0) : kGemmATrans | (fold ? kGemmFoldC : 0);
     return snprintf(buf, n, "yyg::gemm_nt_f64_batched<%d, %d, %d, %d, %d, %d>", phase == 0 ? 0 : 1, f.bm, f.bn, f.wm,
                     f.wn, mode | deep) < 0 ? -1 : 0;
   }
-  const int mode = phase == 1 ? 1 | kGemmATrans : phase == 2 ? 1 | kGemmATrans | kGemmBTrans | kGemmSplitA : kGemmBTrans;
+  const int mode = phase == 1   ? 1 | kGemmATrans | kGemmDT
+                   : phase == 2 ? 1 | kGemmATrans | kGemmBTrans | kGemmSplitA | kGemmDT
+                                : kGemmBTrans;
   return snprintf(buf, n, "yyg::gemm_f64_sep_phase<%d, %d, %d, %d, %d, %d>", phase, f.bm, f.bn, f.wm, f.wn,
                   mode | deep) < 0 ? -1 : 0;
 }

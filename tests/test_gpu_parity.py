@@ -117,8 +117,9 @@ def test_ragged_and_degenerate_shapes(case):
     assert _max_rel(phi, ref) <= TOL_FP64
 
 
-N_F64_VARIANTS = 12
+N_F64_VARIANTS = 14
 N_PHI_DIRECT = 6
+N_PHI_FOLD = 8
 
 
 @pytest.mark.parametrize("case", [
@@ -267,6 +268,14 @@ def test_separable_ragged_shapes(case):
     _, phi = _gpu_solve(desc, rho, grid=g)
     ref = O.solve(*_oracle_args(desc), rho)
     assert _max_rel(phi, ref) <= TOL_FP64
+    # the folded LDS-basis phi kernels on the same shapes (odd and even
+    # n_phi, lmax 0: no sin half)
+    for f in (0, 4, 7):
+        g.sep_config(0, 2 * N_F64_VARIANTS + N_PHI_DIRECT + f)
+        g.sep_config(4, 2 * N_F64_VARIANTS + N_PHI_DIRECT + f)
+        _say(f"separable ragged, folded phi variant {f}: {g.sep_info()}")
+        _, phi_f = _gpu_solve(desc, rho, grid=g)
+        assert _max_rel(phi_f, ref) <= TOL_FP64, f
     # the separable form keeps its moments column-major; the export is the
     # same [patch][shell][q] array as after a dense solve
     th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
@@ -317,14 +326,15 @@ def _phi_direct_case(i):
 @pytest.mark.parametrize("ci", range(len(PHI_DIRECT_CASES)))
 @pytest.mark.parametrize("phase", [0, 4])
 def test_separable_phi_direct_shapes(ci, phase):
-    """The LDS-basis phi kernels where the basis spans several 64-row groups
-    and the contraction several 64-wide chunks, against the oracle."""
+    """The LDS-basis phi kernels (unfolded and folded) where the basis spans
+    several 64-row groups and the contraction several 64-wide chunks,
+    against the oracle."""
     yyg = _yyg()
     desc, rho, ref = _phi_direct_case(ci)
     nR = rho.shape[1]
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
-    for d in range(N_PHI_DIRECT):
+    for d in range(N_PHI_DIRECT + N_PHI_FOLD):
         g.sep_config(phase, 2 * N_F64_VARIANTS + d)
         _say(f"phi direct phase {phase} variant {d}: n_r={nR} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']}")
         _, phi = _gpu_solve(desc, rho, grid=g)
@@ -347,8 +357,8 @@ def test_separable_every_phase_variant(phase):
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
     # every tile with one and with three stages of loads in flight; the phi
-    # phases also every LDS-basis variant
-    for v in range(2 * N_F64_VARIANTS + (N_PHI_DIRECT if phase in (0, 4) else 0)):
+    # phases also every LDS-basis variant, unfolded and folded
+    for v in range(2 * N_F64_VARIANTS + (N_PHI_DIRECT + N_PHI_FOLD if phase in (0, 4) else 0)):
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
