@@ -256,7 +256,10 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * fragments (unfolded), and [2V + 6, 2V + 14), the same kernels folded
  * about the patch's central meridian (h = ceil(n_phi / 2) cells per row;
  * YYG_ERR_UNSUPPORTED on a grid whose rows are not mirror-symmetric, the
- * condition under which the tile variants of the phi phases fold too).
+ * condition under which the tile variants of the phi phases fold too); the
+ * phi synthesis also [2V + 14, 2V + 18), folded kernels in which every wave
+ * loads its matrix-core operands straight from memory (no LDS; the same
+ * mirror-symmetry condition).
  * Needs the separable form built (yyg_set_method); synchronises the
  * device.  For tests and expert tuning; yyg_autotune chooses all of them. */
 int yyg_sep_config(yyg_grid *g, int phase, int variant);

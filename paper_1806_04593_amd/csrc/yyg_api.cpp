@@ -119,13 +119,18 @@ struct yyg_grid {
     double *WFD = nullptr;   // analysis basis [n_t][kca + 16 ceil(L/16)][h]: cos m at row m, sin m at kca + m - 1
     double *TFD = nullptr;   // synthesis basis [h][kcs + 4 ceil(L/4)]: cos m at slot m, sin m at kcs + m - 1
     yyg::PhiDirectArgs phi_ana_fd{}, phi_syn_fd{};
+    // folded phi synthesis with the fragments loaded straight from memory
+    double *BK = nullptr;    // its basis, slot-major [kcs + 4 ceil(L/4)][hp]
+    long hp = 0;             // h padded to a multiple of 32
+    yyg::PhiLeanArgs phi_syn_l{};
     // theta phases and rotation: one launch each over their problems
     yyg::SepPhaseArgs args{};
     // variant per phase (0 phi analysis, 1 theta analysis, 2 moment
     // rotation, 3 theta synthesis, 4 phi synthesis): v < V the tile v,
     // V + v the same with the deep prefetch, 2V + d (phi phases) the
     // LDS-basis kernel d, 2V + D + f (phi phases, fold) the folded
-    // LDS-basis kernel f
+    // LDS-basis kernel f, 2V + D + F + e (phi synthesis, fold) the LDS-free
+    // kernel e
     // defaults (before autotuning): 32 x 32 tiles, 64 x 32 for the theta
     // synthesis
     int var[5] = {10, 10, 10, 9, 10};
@@ -172,7 +177,7 @@ void free_grid(yyg_grid *g) {
   {
     void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2,    g->sep.P2, g->sep.DI, g->sep.X2,
                  g->sep.V,   g->sep.Ut,   g->sep.coefS, g->sep.At, g->sep.WF, g->sep.TF,
-                 g->sep.WFD, g->sep.TFD};
+                 g->sep.WFD, g->sep.TFD, g->sep.BK};
     for (void *x : b)
       if (x) (void)hipFree(x);
   }
@@ -291,10 +296,12 @@ namespace {
 // Variants of separable phase r: v < V the tile v, V + v the same with
 // three stages of loads in flight (V = the FP64 tile variants); the phi
 // phases (0, 4) also 2V + d, the LDS-basis kernel variant d (d < D), and
-// 2V + D + f, its folded form f (mirror-symmetric grids only).
+// 2V + D + f, its folded form f (F of them; mirror-symmetric grids only);
+// the phi synthesis also 2V + D + F + e, the LDS-free folded kernel e.
 int sep_variant_count(int r) {
   const int v = 2 * yyg::gemm_f64_variant_count();
-  return (r == 0 || r == 4) ? v + yyg::phi_direct_variant_count() + yyg::phi_fold_variant_count() : v;
+  const int phi = yyg::phi_direct_variant_count() + yyg::phi_fold_variant_count();
+  return r == 0 ? v + phi : r == 4 ? v + phi + yyg::phi_lean_variant_count() : v;
 }
 
 bool sep_fold_variant(int r, int v) {
@@ -311,6 +318,8 @@ int sep_set_variant(yyg_grid *g, int r, int v) {
 hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
   const int nv = yyg::gemm_f64_variant_count(), nd = yyg::phi_direct_variant_count();
+  const int nf = yyg::phi_fold_variant_count();
+  if (r == 4 && S.var[r] >= 2 * nv + nd + nf) return yyg::launch_phi_syn_lean(S.var[r] - 2 * nv - nd - nf, S.phi_syn_l, s);
   if (sep_fold_variant(r, S.var[r]))
     return yyg::launch_phi_fold(S.var[r] - 2 * nv - nd, r == 0, r == 0 ? S.phi_ana_fd : S.phi_syn_fd, s);
   if ((r == 0 || r == 4) && S.var[r] >= 2 * nv)
@@ -335,6 +344,7 @@ int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
   g->sep.phi_syn_f.C = phi;
   g->sep.phi_ana_fd.X = rho;
   g->sep.phi_syn_fd.C = phi;
+  g->sep.phi_syn_l.C = phi;
   return YYG_OK;
 }
 
@@ -347,7 +357,7 @@ int sep_build(yyg_grid *g) {
   S.ldm = round_up(nmc, 16);
   S.ldl = round_up(L + 1, 16);
   if (yyg::radial_scan_q_lds(g->n_r, g->n_patch) > yyg::kScanQMaxLds) return YYG_ERR_UNSUPPORTED;
-  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD;
+  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD, BK;
   std::vector<int> dofs;
   try {
     coef.resize((size_t)4 * g->n_r * (L + 1));
@@ -443,6 +453,11 @@ int sep_build(yyg_grid *g) {
           TFD[(size_t)k * S.nks + m] = TF[(size_t)k * S.ldtf + m];
           if (m > 0) TFD[(size_t)k * S.nks + S.kcs + m - 1] = TF[(size_t)k * S.ldtf + S.ks + m - 1];
         }
+      // the same synthesis basis slot-major, cells padded to a multiple of 32
+      S.hp = round_up(h, 32);
+      BK.assign((size_t)S.nks * S.hp, 0.0);
+      for (long sl = 0; sl < S.nks; ++sl)
+        for (int k = 0; k < h; ++k) BK[(size_t)sl * S.hp + k] = TFD[(size_t)k * S.nks + sl];
     }
     T.resize((size_t)nt * Q);
     yyg::theta_table_normalised(g->geom, L, T.data());
@@ -489,6 +504,7 @@ int sep_build(yyg_grid *g) {
   if (st == YYG_OK && S.fold) st = dmalloc(&S.TF, TF.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.WFD, WFD.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.TFD, TFD.size());
+  if (st == YYG_OK && S.fold) st = dmalloc(&S.BK, BK.size());
   if (st != YYG_OK) return st;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
@@ -505,6 +521,7 @@ int sep_build(yyg_grid *g) {
     chk(hipMemcpy(S.TF, TF.data(), TF.size() * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemcpy(S.WFD, WFD.data(), WFD.size() * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemcpy(S.TFD, TFD.data(), TFD.size() * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(S.BK, BK.data(), BK.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -540,6 +557,7 @@ int sep_build(yyg_grid *g) {
                                     np, (int)S.kca, nmc};
   S.phi_syn_fd = yyg::PhiDirectArgs{S.V, S.TFD, nullptr, (int)M, nt, (int)S.h, (int)S.nks, S.nks, 0,
                                     np, (int)S.kcs, nmc};
+  S.phi_syn_l = yyg::PhiLeanArgs{S.V, S.BK, nullptr, (int)M, nt, np, (int)S.h, (int)S.hp, (int)S.nks, (int)S.kcs, nmc};
   // theta analysis, rotation (Yin-Yang) and theta synthesis: problem
   // operands derived in the kernels from these
   S.args = yyg::SepPhaseArgs{L,    g->n_r, g->n_patch, nt,  S.ldl, S.X2, S.T2, S.P2,
@@ -1195,6 +1213,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
       g->sep.phi_syn_d.C = nullptr;
       g->sep.phi_syn_f.C = nullptr;
       g->sep.phi_syn_fd.C = nullptr;
+      g->sep.phi_syn_l.C = nullptr;
     }
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -1530,6 +1549,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     g->sep.phi_syn_f.C = nullptr;
     g->sep.phi_ana_fd.X = nullptr;
     g->sep.phi_syn_fd.C = nullptr;
+    g->sep.phi_syn_l.C = nullptr;
     if (st3 != YYG_OK) return st3;
   }
   if (cache_path && (!have_a || !have_s)) {

@@ -108,6 +108,20 @@ hipError_t launch_phi_direct(int variant, bool analysis, const PhiDirectArgs &a,
 int phi_fold_variant_count();
 hipError_t launch_phi_fold(int variant, bool analysis, const PhiDirectArgs &a, hipStream_t s);
 
+// Folded phi synthesis with every wave loading its MFMA fragments straight
+// from memory (no LDS): phi[row][j][k] for k < h = ceil(n_p / 2) and the
+// mirror n_p - 1 - k, from V[mc][j][row] and the slot-major basis Bk[s][hp]
+// (slot s < kc: cos m = s; s >= kc: sin m = s - kc + 1; zero at padding
+// slots and cells k >= h).
+struct PhiLeanArgs {
+  const double *V, *Bk;
+  double *C;
+  int M, nt, np, h, hp;  // rows, colatitudes, cells per row, folded cells, padded row (multiple of 32, >= h)
+  int ns, kc, nmc;       // slots and cos slots (multiples of 4), azimuthal columns (2L+1)
+};
+int phi_lean_variant_count();
+hipError_t launch_phi_syn_lean(int variant, const PhiLeanArgs &a, hipStream_t s);
+
 // phase 1 theta analysis, 2 rotation (two patches), 3 theta synthesis;
 // deep = kGemmDeep.
 hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s);

@@ -905,6 +905,82 @@ __global__ __launch_bounds__(64 * WAVES) void phi_direct_kernel(PhiDirectArgs a)
     }
 }
 
+// Folded phi synthesis with no LDS and no barrier: every wave owns 16 rows
+// and CT column tiles of 16 folded cells of one colatitude, loads its data
+// and basis fragments straight from memory in MFMA layout (S steps of 4
+// contraction slots at a time, the next S in flight behind them) and
+// stores its cells and their mirrors.  The waves are numbered column group
+// fastest, then row tile, then colatitude; a block holds 4 of them.
+//   data:  V[mc][j][row] (slot s: cos m = s for s < kc, sin m = s - kc + 1;
+//          its azimuthal column mc clamped below nmc);
+//   basis: Bk[s][n] (slot-major, n < hp, zero at padding slots and cells);
+//   out:   phi[row][j][k] = e + o (k < h), phi[row][j][n_p - 1 - k] = e - o.
+template <int CT, int S>
+__global__ __launch_bounds__(256) void phi_syn_lean_kernel(PhiLeanArgs a) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int M = a.M, nt = a.nt, ncg = (a.h + 16 * CT - 1) / (16 * CT), nrt = (M + 15) / 16;
+  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int cg = (int)(w % ncg), rt = (int)((w / ncg) % nrt), j = (int)(w / ((long)ncg * nrt));
+  if (j >= nt) return;  // uniform across the wave; no barrier below
+  const int row0 = rt * 16, n0 = cg * 16 * CT;
+  const double *__restrict__ xr = a.V + (long)j * M + min(row0 + lr, M - 1);
+  const long xk = (long)nt * M;
+  dbl4 acc[CT], acc2[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) acc[c] = acc2[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // steps s0 / 4 .. s0 / 4 + S - 1 of the slots [.., se): lane group lg
+  // takes slot 4t + lg of step t
+  auto load = [&](double (&xa)[S], double (&xb)[CT][S], int s0, int se) {
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int sl = min(s0 + 4 * t + lg, se - 1);
+      const int m = sl < a.kc ? sl : sl - a.kc + 1;
+      const int mc = min(sl < a.kc ? max(2 * m - 1, 0) : 2 * m, a.nmc - 1);
+      xa[t] = xr[(long)mc * xk];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) xb[c][t] = a.Bk[(long)sl * a.hp + n0 + 16 * c + lr];
+    }
+  };
+  auto mma = [&](dbl4 (&ac)[CT], const double (&xa)[S], const double (&xb)[CT][S], int s0, int se) {
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      if (s0 + 4 * t < se) {  // uniform
+#pragma unroll
+        for (int c = 0; c < CT; ++c) ac[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[t], xb[c][t], ac[c], 0, 0, 0);
+      }
+  };
+  // the slots [sb, se) into ac, two register sets of S steps in turn
+  auto run = [&](dbl4 (&ac)[CT], int sb, int se) {
+    double xa0[S], xb0[CT][S], xa1[S], xb1[CT][S];
+    load(xa0, xb0, sb, se);
+    for (int s0 = sb; s0 < se; s0 += 8 * S) {
+      if (s0 + 4 * S < se) load(xa1, xb1, s0 + 4 * S, se);
+      mma(ac, xa0, xb0, s0, se);
+      if (s0 + 4 * S >= se) break;
+      if (s0 + 8 * S < se) load(xa0, xb0, s0 + 8 * S, se);
+      mma(ac, xa1, xb1, s0 + 4 * S, se);
+    }
+  };
+  run(acc, 0, a.kc);
+  if (a.ns > a.kc) run(acc2, a.kc, a.ns);  // no sin slots at L = 0
+  // D layout: lane l, element e -> row l/16 + 4e, column l%16
+  const int np = a.np;
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int k = n0 + 16 * c + lr;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = row0 + lg + 4 * e;
+      if (r < M && k < a.h) {
+        double *__restrict__ cr = a.C + ((long)r * nt + j) * np;
+        const double ev = acc[c][e], od = acc2[c][e];
+        cr[k] = ev + od;
+        if (np - 1 - k != k) cr[np - 1 - k] = ev - od;
+      }
+    }
+  }
+}
+
 // Radial sums of Eqs. (19)-(20) (the recurrences above) on column-major
 // moments X[q][p nR + n]: one block per column q, one wave per patch.  The
 // column (and its degree's recurrence coefficients, coefS[l][4][nR], shared
@@ -1268,6 +1344,37 @@ hipError_t launch_phi_fold(int variant, bool analysis, const PhiDirectArgs &a, h
   return analysis ? launch_phi_fold_v<true>(variant, a, s) : launch_phi_fold_v<false>(variant, a, s);
 }
 
+namespace {
+
+template <int CT, int S>
+hipError_t launch_phi_syn_lean_t(const PhiLeanArgs &a, hipStream_t s) {
+  const long waves = (long)a.nt * ((a.M + 15) / 16) * ((a.h + 16 * CT - 1) / (16 * CT));
+  if ((waves + 3) / 4 > INT_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((phi_syn_lean_kernel<CT, S>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// (column tiles per wave, steps per register set) of each variant
+const int kPhiLean[][2] = {{1, 4}, {1, 8}, {2, 4}, {2, 8}};
+
+int phi_lean_variant_count() { return (int)(sizeof(kPhiLean) / sizeof(kPhiLean[0])); }
+
+hipError_t launch_phi_syn_lean(int variant, const PhiLeanArgs &a, hipStream_t s) {
+  if (a.M <= 0 || a.nt <= 0 || a.h <= 0) return hipSuccess;
+  if (a.nmc < 1 || a.ns < 4 || a.ns % 4 || a.kc < 4 || a.kc % 4 || a.kc > a.ns || a.h != (a.np + 1) / 2 ||
+      a.hp % 32 || a.hp < a.h)
+    return hipErrorInvalidValue;
+  switch (variant) {
+    case 0: return launch_phi_syn_lean_t<1, 4>(a, s);
+    case 1: return launch_phi_syn_lean_t<1, 8>(a, s);
+    case 2: return launch_phi_syn_lean_t<2, 4>(a, s);
+    case 3: return launch_phi_syn_lean_t<2, 8>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhaseArgs &a, hipStream_t s) {
   if (a.nR <= 0) return hipSuccess;
   if (variant < 0 || variant >= gemm_f64_variant_count()) return hipErrorInvalidValue;
@@ -1358,8 +1465,14 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
 
 int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n) {
   const int nv = gemm_f64_variant_count(), nd = phi_direct_variant_count(), nf = phi_fold_variant_count();
+  const int nl = phase == 4 ? phi_lean_variant_count() : 0;
   const bool phi = phase == 0 || phase == 4;
-  if (phase < 0 || phase > 4 || v < 0 || v >= 2 * nv + (phi ? nd + nf : 0)) return -1;
+  if (phase < 0 || phase > 4 || v < 0 || v >= 2 * nv + (phi ? nd + nf : 0) + nl) return -1;
+  if (v >= 2 * nv + nd + nf) {
+    if (!fold) return -1;
+    const int *d = kPhiLean[v - 2 * nv - nd - nf];
+    return snprintf(buf, n, "yyg::phi_syn_lean_kernel<%d, %d>", d[0], d[1]) < 0 ? -1 : 0;
+  }
   if (v >= 2 * nv) {
     const bool fd = v >= 2 * nv + nd;
     if (fd && !fold) return -1;

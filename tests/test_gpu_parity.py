@@ -120,6 +120,7 @@ def test_ragged_and_degenerate_shapes(case):
 N_F64_VARIANTS = 14
 N_PHI_DIRECT = 6
 N_PHI_FOLD = 8
+N_PHI_LEAN = 4   # phi synthesis only
 
 
 @pytest.mark.parametrize("case", [
@@ -268,11 +269,11 @@ def test_separable_ragged_shapes(case):
     _, phi = _gpu_solve(desc, rho, grid=g)
     ref = O.solve(*_oracle_args(desc), rho)
     assert _max_rel(phi, ref) <= TOL_FP64
-    # the folded LDS-basis phi kernels on the same shapes (odd and even
-    # n_phi, lmax 0: no sin half)
-    for f in (0, 4, 7):
-        g.sep_config(0, 2 * N_F64_VARIANTS + N_PHI_DIRECT + f)
-        g.sep_config(4, 2 * N_F64_VARIANTS + N_PHI_DIRECT + f)
+    # the folded LDS-basis phi kernels and the LDS-free folded synthesis on
+    # the same shapes (odd and even n_phi, lmax 0: no sin half)
+    for f in (0, 4, 7, 8, 11):
+        g.sep_config(0, 2 * N_F64_VARIANTS + N_PHI_DIRECT + min(f, N_PHI_FOLD - 1))
+        g.sep_config(4, 2 * N_F64_VARIANTS + N_PHI_DIRECT + f)   # f >= 8: the LDS-free synthesis
         _say(f"separable ragged, folded phi variant {f}: {g.sep_info()}")
         _, phi_f = _gpu_solve(desc, rho, grid=g)
         assert _max_rel(phi_f, ref) <= TOL_FP64, f
@@ -334,7 +335,7 @@ def test_separable_phi_direct_shapes(ci, phase):
     nR = rho.shape[1]
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
-    for d in range(N_PHI_DIRECT + N_PHI_FOLD):
+    for d in range(N_PHI_DIRECT + N_PHI_FOLD + (N_PHI_LEAN if phase == 4 else 0)):
         g.sep_config(phase, 2 * N_F64_VARIANTS + d)
         _say(f"phi direct phase {phase} variant {d}: n_r={nR} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']}")
         _, phi = _gpu_solve(desc, rho, grid=g)
@@ -358,7 +359,8 @@ def test_separable_every_phase_variant(phase):
     g.set_method("separable")
     # every tile with one and with three stages of loads in flight; the phi
     # phases also every LDS-basis variant, unfolded and folded
-    for v in range(2 * N_F64_VARIANTS + (N_PHI_DIRECT + N_PHI_FOLD if phase in (0, 4) else 0)):
+    for v in range(2 * N_F64_VARIANTS + (N_PHI_DIRECT + N_PHI_FOLD if phase in (0, 4) else 0)
+                   + (N_PHI_LEAN if phase == 4 else 0)):
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
