@@ -275,7 +275,11 @@ def bench_single(a):
         name = max(cand, key=lambda n: cand[n][0])
         ms_k, flops_k, bytes_k = cand[name]
         kname = head["kernel_names"][name]
-        if kname.startswith("yyg::gemm_nt_f64_batched<") and int(kname.rstrip(">").split(",")[-1]) & (128 | 256):
+        args = kname[kname.find("<") + 1:].rstrip(">").split(", ")
+        folded = (kname.startswith("yyg::phi_syn_lean_kernel<")
+                  or (kname.startswith("yyg::phi_direct_kernel<") and args[-1] == "true")
+                  or (kname.startswith("yyg::gemm_nt_f64_batched<") and int(args[-1]) & (128 | 256)))
+        if folded:
             flops_k /= 2.0   # folded about the central meridian: half the multiply-adds
         tf = flops_k / (ms_k * 1e-3) / 1e12
         gbs = bytes_k / (ms_k * 1e-3) / 1e9
