@@ -95,7 +95,7 @@ struct yyg_grid {
     double *trig = nullptr;  // phi-synthesis basis [n_p][ldm]
     double *T2 = nullptr;    // theta-analysis basis [mc][l][n_t]: sqrt(N) T_j^(lm)
     double *P2 = nullptr;    // theta-synthesis basis [mc][j][ldl]: sqrt(N) P_l^m(cos t_j)
-    double *DI = nullptr;    // per degree l: [identity; D_l] (2d x d), one after the other
+    double *Drot = nullptr;  // per degree l: the rotation block D_l (d x d), one after the other
     double *X2 = nullptr;    // phi-analysis output [mc][j][row]
     double *V = nullptr;     // theta-synthesis output [mc][j][row]
     double *At = nullptr;    // own + rotated other moments, column-major [Q][row] (Yin-Yang)
@@ -175,7 +175,7 @@ void free_grid(yyg_grid *g) {
   if (g->d_eA) (void)hipFree(g->d_eA);
   if (g->d_eU) (void)hipFree(g->d_eU);
   {
-    void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2,    g->sep.P2, g->sep.DI, g->sep.X2,
+    void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2,    g->sep.P2, g->sep.Drot, g->sep.X2,
                  g->sep.V,   g->sep.Ut,   g->sep.coefS, g->sep.At, g->sep.WF, g->sep.TF,
                  g->sep.WFD, g->sep.TFD, g->sep.BK};
     for (void *x : b)
@@ -358,7 +358,6 @@ int sep_build(yyg_grid *g) {
   S.ldl = round_up(L + 1, 16);
   if (yyg::radial_scan_q_lds(g->n_r, g->n_patch) > yyg::kScanQMaxLds) return YYG_ERR_UNSUPPORTED;
   std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD, BK;
-  std::vector<int> dofs;
   try {
     coef.resize((size_t)4 * g->n_r * (L + 1));
     yyg::radial_coefficients(g->n_r, g->r_edges.data(), L, coef.data());
@@ -367,7 +366,6 @@ int sep_build(yyg_grid *g) {
       for (int l = 0; l <= L; ++l)
         for (int k = 0; k < 4; ++k)
           coefS[((size_t)l * 4 + k) * g->n_r + n] = coef[((size_t)n * (L + 1) + l) * 4 + k];
-    for (int l = 0, off = 0; l <= L; off += (2 * l + 1) * (2 * l + 1), ++l) dofs.push_back(off);
     CSt.resize((size_t)nmc * S.ldk);
     yyg::separable_cs(g->geom, L, S.ldk, CSt.data());
     // the overlap weights folded into one basis copy per colatitude
@@ -474,18 +472,10 @@ int sep_build(yyg_grid *g) {
           P2[((size_t)mc * nt + j) * S.ldl + l] = P[(size_t)j * Q + l * l + mc];
         }
     }
-    // per degree: [identity; D_l], so that the rotation phase adds a patch's
-    // own moments in the same contraction
-    std::vector<double> D0(yyg::rotation_blocks_size(L));
-    yyg::rotation_blocks(L, D0.data());
-    D.assign(2 * D0.size(), 0.0);
-    for (int l = 0; l <= L; ++l) {
-      const int d = 2 * l + 1;
-      double *blk = D.data() + 2 * (size_t)dofs[l];
-      for (int b = 0; b < d; ++b) blk[(size_t)b * d + b] = 1.0;
-      for (int a = 0; a < d; ++a)
-        for (int b = 0; b < d; ++b) blk[(size_t)(d + a) * d + b] = D0[dofs[l] + (size_t)a * d + b];
-    }
+    // per degree: D_l (the rotation phase starts its accumulators from a
+    // patch's own moments and adds the other patch's moments times D_l)
+    D.resize(yyg::rotation_blocks_size(L));
+    yyg::rotation_blocks(L, D.data());
   } catch (const std::bad_alloc &) {
     return YYG_ERR_OUT_OF_MEMORY;
   }
@@ -494,7 +484,7 @@ int sep_build(yyg_grid *g) {
   if (st == YYG_OK) st = dmalloc(&S.trig, trig.size());
   if (st == YYG_OK) st = dmalloc(&S.T2, T2.size());
   if (st == YYG_OK) st = dmalloc(&S.P2, P2.size());
-  if (st == YYG_OK) st = dmalloc(&S.DI, D.size());
+  if (st == YYG_OK) st = dmalloc(&S.Drot, D.size());
   if (st == YYG_OK) st = dmalloc(&S.X2, (size_t)nmc * MJ);
   if (st == YYG_OK) st = dmalloc(&S.V, (size_t)nmc * MJ);
   if (st == YYG_OK) st = dmalloc(&S.Ut, (size_t)nmc * (L + 1) * M);
@@ -514,7 +504,7 @@ int sep_build(yyg_grid *g) {
   chk(hipMemcpy(S.trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.T2, T2.data(), T2.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.P2, P2.data(), P2.size() * sizeof(double), hipMemcpyHostToDevice));
-  chk(hipMemcpy(S.DI, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(S.Drot, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(S.coefS, coefS.data(), coefS.size() * sizeof(double), hipMemcpyHostToDevice));
   if (S.fold) {
     chk(hipMemcpy(S.WF, WF.data(), WF.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -561,7 +551,7 @@ int sep_build(yyg_grid *g) {
   // theta analysis, rotation (Yin-Yang) and theta synthesis: problem
   // operands derived in the kernels from these
   S.args = yyg::SepPhaseArgs{L,    g->n_r, g->n_patch, nt,  S.ldl, S.X2, S.T2, S.P2,
-                             S.Ut, S.DI,   g->d_Ahat,  S.At, S.V};
+                             S.Ut, S.Drot,   g->d_Ahat,  S.At, S.V};
   S.ready = true;
   return YYG_OK;
 }

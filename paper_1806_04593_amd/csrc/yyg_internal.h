@@ -19,10 +19,10 @@ struct GemmF64Args {
   int tiles_m;
   long ldc_c = 1;       // column stride of C
   int c_sq = -1;        // >= 0: column n of C lands at column (n + c_sq)^2 (degree-major q index)
-  // kGemmSplitA: A(m, k) for k >= k_split is read at column k - k_split,
-  // a_off elements further on
+  // kGemmFoldC: the first contraction index of the odd part
   int k_split = 0;
-  long a_off = 0;
+  // kGemmAccInit: the accumulators' initial values, addressed like C
+  const double *Cin = nullptr;
   // strided batch (launch_gemm_f64_batched): problem z reads A + z a_batch,
   // B + z b_batch and writes C + z c_split_stride
   int batch = 1;
@@ -38,8 +38,6 @@ struct GemmF64Args {
 //  kGemmBatch   the split index selects a problem of a strided batch
 //  kGemmBTrans  B is stored k-major: element (n, k) at B[k * ldb + n]
 //  kGemmDeep    three stages of loads in flight instead of one (short K)
-//  kGemmSplitA  (with kGemmATrans) A's columns from k_split on come from a
-//               second block a_off elements away
 //  kGemmFoldA   phi analysis folded about the middle of each row: batched
 //               problem z = 2 j + g reads A(m, k) = X(m, k) +/- X(m,
 //               fold_k - 1 - k) (+ for g = 0, - for g = 1) at A + j a_batch,
@@ -54,16 +52,18 @@ struct GemmF64Args {
 //               e + o, column fold_k - 1 - c gets e - o
 //  kGemmDT      accumulate the transposed tile (B A^T): each store then
 //               covers 16 consecutive rows, for C stored column-major
+//  kGemmAccInit (with the general epilogue) the accumulators start from
+//               Cin (same strides as C) instead of zero
 enum {
   kGemmATrans = 2,
   kGemmCTrans = 4,
   kGemmBatch = 8,
   kGemmBTrans = 16,
   kGemmDeep = 32,
-  kGemmSplitA = 64,
   kGemmFoldA = 128,
   kGemmFoldC = 256,
-  kGemmDT = 512
+  kGemmDT = 512,
+  kGemmAccInit = 1024
 };
 // role offset of the kGemmDeep forms of the batched roles
 constexpr int kRoleDeep = 16;
@@ -77,7 +77,7 @@ struct SepPhaseArgs {
   const double *T2;  // theta-analysis basis [mc][l][n_t]
   const double *P2;  // theta-synthesis basis [mc][j][ldl]
   const double *Ut;  // potential coefficients [mc][l][row]
-  const double *DI;  // per degree l: [identity; D_l], (2d) x d, one after the other
+  const double *D;   // per degree l: D_l (d x d, row k the input column), one after the other
   double *Ahat;      // column-major moments [Q][row] (theta analysis output)
   double *At;        // own + rotated other moments [Q][row] (Yin-Yang)
   double *V;         // theta-synthesis output [mc][j][row]

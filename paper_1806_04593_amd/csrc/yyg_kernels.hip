@@ -66,14 +66,14 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr bool CT = (MODE & kGemmCTrans) != 0;
   constexpr bool BATCH = (MODE & kGemmBatch) != 0;
   constexpr bool BT = (MODE & kGemmBTrans) != 0;
-  constexpr bool SPLIT = (MODE & kGemmSplitA) != 0;
+  constexpr bool ACCINIT = (MODE & kGemmAccInit) != 0;
   constexpr bool FOLDA = (MODE & kGemmFoldA) != 0;
   constexpr bool FOLDC = (MODE & kGemmFoldC) != 0;
   constexpr bool DT = (MODE & kGemmDT) != 0;
-  static_assert(!SPLIT || AT, "the split A operand is stored k-major");
+  static_assert(!ACCINIT || GEN, "the initial accumulator is addressed like C");
   static_assert(!DT || !FOLDC, "the folded synthesis stores rows");
   static_assert(!FOLDA || (BATCH && CT && !AT && !GEN), "folded analysis: batched, row-major A, C column-major");
-  static_assert(!FOLDC || (BATCH && AT && !CT && !GEN && !SPLIT), "folded synthesis: batched, A k-major");
+  static_assert(!FOLDC || (BATCH && AT && !CT && !GEN), "folded synthesis: batched, A k-major");
 
   const int M = g.M, N = g.N, K = g.K;
   // FOLDA: problem z = 2 zj + group (group 0 the even, 1 the odd half), so
@@ -120,6 +120,22 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
     for (int i = 0; i < TI; ++i)
 #pragma unroll
       for (int j = 0; j < TJ; ++j) acc2[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+  if constexpr (ACCINIT) {
+    // start from Cin, element by element in the D layout of the epilogue
+    // (clamped addresses; entries outside the matrix start at zero)
+    const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + (wv % WGM) * (BM / WGM) + i * 16 + (DT ? (ln & 15) : (ln >> 4) + 4 * r);
+          const int col = n0 + (wv / WGM) * (BN / WGN) + j * 16 + (DT ? (ln >> 4) + 4 * r : (ln & 15));
+          const double v = g.Cin[(long)min(row, M - 1) * ldc + (long)min(col, N - 1) * g.ldc_c];
+          acc[i][j][r] = (row < M && col < N) ? v : 0.0;
+        }
   }
 
   constexpr int PF = (MODE & kGemmDeep) ? kDeepPF : kPF;
@@ -172,19 +188,12 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, gm = m0 + e % BM;
         int kc = min(k0 + e / BM, K - 1);
-        long off = 0;
-        if constexpr (SPLIT) {
-          if (kc >= g.k_split) {
-            kc -= g.k_split;
-            off = g.a_off;
-          }
-        }
         if constexpr (FOLDC) {
           // contraction index -> azimuthal column: cos m at k = m, sin m at
           // k_split + m - 1 (padding clamps; its basis entries are zero)
           kc = min(kc < g.k_split ? max(2 * kc - 1, 0) : 2 * (kc - g.k_split) + 2, g.fold_mc - 1);
         }
-        ra[i] = A[(long)kc * lda + off + min(gm, M - 1)];
+        ra[i] = A[(long)kc * lda + min(gm, M - 1)];
       }
     } else {
 #pragma unroll
@@ -371,8 +380,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_batched(GemmF64Arg
 //  PHASE 1, theta analysis, z = mc (m = (mc + 1) / 2): the column-major
 //    moments A[(l^2 + mc)][row] = sum_j X2[mc][j][row] T2[mc][l][j], l >= m.
 //  PHASE 2, rotation, z = 2 (L - l) + p: At[l^2 + b][p nR + n] =
-//    sum_{k < 2d} [A_own | A_other](n, k) DI_l[k][b], d = 2l + 1, where
-//    DI_l = [identity; D_l] and A_other is the other patch's rows.
+//    A_own(n, b) + sum_{k < d} A_other(n, k) D_l[k][b], d = 2l + 1, with
+//    A_own / A_other this / the other patch's rows of degree l's columns;
+//    the accumulators start from A_own (kGemmAccInit).
 //  PHASE 3, theta synthesis, z = mc: V[mc][j][row] =
 //    sum_{l >= m} P2[mc][j][l] Ut[mc][l][row].
 template <int PHASE, int BM, int BN, int WGM, int WGN, int MODE>
@@ -397,14 +407,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_sep_phase(SepPhaseArg
     const int l = a.L - (z >> 1), p = z & 1, d = 2 * l + 1;
     g.M = a.nR;
     g.N = d;
-    g.K = 2 * d;
-    g.A = a.Ahat + (long)l * l * Mr + (long)p * a.nR;
+    g.K = d;
+    g.A = a.Ahat + (long)l * l * Mr + (long)(1 - p) * a.nR;  // the other patch's rows
     g.lda = Mr;
-    g.k_split = d;
-    g.a_off = (long)(1 - 2 * p) * a.nR;
-    g.B = a.DI + 2 * (long)l * (4 * (long)l * l - 1) / 3;
+    g.B = a.D + (long)l * (4 * (long)l * l - 1) / 3;  // D_l after the blocks of degrees below l
     g.ldb = d;
     g.C = a.At + (long)l * l * Mr + (long)p * a.nR;
+    g.Cin = a.Ahat + (long)l * l * Mr + (long)p * a.nR;  // this patch's own moments
     g.ldc = 1;
     g.ldc_c = Mr;
   } else {
@@ -1212,7 +1221,7 @@ hipError_t launch_sep_variant(int phase, bool deep, const SepPhaseArgs &a, hipSt
   if ((mmax + BM - 1) / BM > INT_MAX || (nmax + BN - 1) / BN > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)((mmax + BM - 1) / BM), (unsigned)((nmax + BN - 1) / BN), nz), block(64 * WGM * WGN);
   // phases 1 and 2 store column-major (ldc = 1): transposed accumulation
-  constexpr int A1 = 1 | kGemmATrans | kGemmDT, A2 = 1 | kGemmATrans | kGemmBTrans | kGemmSplitA | kGemmDT,
+  constexpr int A1 = 1 | kGemmATrans | kGemmDT, A2 = 1 | kGemmATrans | kGemmBTrans | kGemmDT | kGemmAccInit,
                 A3 = kGemmBTrans;
 #define YYG_SEP_GO(P, M)                                                                                     \
   hipLaunchKernelGGL((gemm_f64_sep_phase<P, BM, BN, WGM, WGN, M>), grid, block, 0, s, a);                  \
@@ -1489,7 +1498,7 @@ int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n) {
                     f.wn, mode | deep) < 0 ? -1 : 0;
   }
   const int mode = phase == 1   ? 1 | kGemmATrans | kGemmDT
-                   : phase == 2 ? 1 | kGemmATrans | kGemmBTrans | kGemmSplitA | kGemmDT
+                   : phase == 2 ? 1 | kGemmATrans | kGemmBTrans | kGemmDT | kGemmAccInit
                                 : kGemmBTrans;
   return snprintf(buf, n, "yyg::gemm_f64_sep_phase<%d, %d, %d, %d, %d, %d>", phase, f.bm, f.bn, f.wm, f.wn,
                   mode | deep) < 0 ? -1 : 0;
