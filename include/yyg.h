@@ -275,6 +275,17 @@ int yyg_sep_info(const yyg_grid *g, int *variants, int n);
  * grid.  For matching profiles to a plan.  Needs the separable form built. */
 int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n);
 
+/* Launch one phase (0-4, as for yyg_sep_config) of the separable solve on
+ * `stream`, asynchronously, reading what the earlier phases of the last
+ * yyg_solve left in the plan's buffers (the density of the last
+ * yyg_upload_rho for phase 0) and writing that phase's output (phi, a device
+ * buffer laid out as for yyg_solve, for phase 4).  Repeated after a solve,
+ * each phase recomputes the same output, so that a phase can be timed or
+ * profiled alone.  YYG_ERR_NOT_READY without the separable form or a
+ * density; before the first solve the intermediate buffers hold no defined
+ * values (no fault, meaningless output). */
+int yyg_sep_phase(yyg_grid *g, int phase, double *phi, void *stream);
+
 /* Batched solves of several plans (uneven n_r <= 1024, angular sizes and
  * lmax allowed) for fields that each have their own density and potential
  * arrays.  One batched solve is three persistent grouped launches (five

@@ -1626,6 +1626,21 @@ int yyg_sep_info(const yyg_grid *g, int *variants, int n) {
   return YYG_OK;
 }
 
+int yyg_sep_phase(yyg_grid *g, int phase, double *phi, void *stream) {
+  if (!g || !phi || phase < 0 || phase > 4) return YYG_ERR_INVALID_ARG;
+  if (g->method != YYG_METHOD_SEPARABLE || !g->sep.ready || !g->rho) return YYG_ERR_NOT_READY;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  hipStream_t s = as_stream(stream);
+  const int st = sep_set_pointers(g, g->rho, phi, s);
+  if (st != YYG_OK) return st;
+  if (sep_launch_phase(g, phase, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  return YYG_OK;
+}
+
 int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
   if (!g || !name || n < 1 || phase < 0 || phase > 4) return YYG_ERR_INVALID_ARG;
   if (!g->sep.ready) return YYG_ERR_NOT_READY;

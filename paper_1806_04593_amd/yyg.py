@@ -29,7 +29,7 @@ EXPORTS = [
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
     "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind", "yyg_sep_config", "yyg_sep_info",
-    "yyg_sep_kernel",
+    "yyg_sep_kernel", "yyg_sep_phase",
 ]
 
 
@@ -90,6 +90,7 @@ def lib():
         L.yyg_sep_config.argtypes = [vp, i, i]
         L.yyg_sep_info.argtypes = [vp, ctypes.POINTER(i), i]
         L.yyg_sep_kernel.argtypes = [vp, i, ctypes.c_char_p, ctypes.c_size_t]
+        L.yyg_sep_phase.argtypes = [vp, i, vp, vp]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -230,6 +231,15 @@ class Grid:
         buf = ctypes.create_string_buffer(256)
         _check(lib().yyg_sep_kernel(self._h, int(phase), buf, 256), "yyg_sep_kernel")
         return buf.value.decode()
+
+    def sep_phase(self, phase, phi, stream=None):
+        """Launch one separable phase alone (after a solve); phi: the torch
+        CUDA float64 tensor phase 4 writes."""
+        import torch
+        assert phi.dtype == torch.float64 and phi.is_cuda and phi.is_contiguous()
+        assert tuple(phi.shape) == self.shape
+        _check(lib().yyg_sep_phase(self._h, int(phase), ctypes.c_void_p(phi.data_ptr()), _stream_handle(stream)),
+               "yyg_sep_phase")
 
     def set_config(self, var_ana, split_ana, var_syn, precision="fp64"):
         _check(lib().yyg_plan_config(self._h, PRECISIONS.get(precision, precision), int(var_ana), int(split_ana),

@@ -368,6 +368,35 @@ def test_separable_every_phase_variant(phase):
         assert err <= TOL_FP64, (phase, v, err)
 
 
+def test_separable_phase_alone():
+    """yyg_sep_phase: one phase launched alone after a solve recomputes that
+    phase's output from what the solve left (the phi synthesis rewrites the
+    potential bit for bit); without the separable form it is not ready."""
+    torch = _torch()
+    yyg = _yyg()
+    desc = W.describe("small")
+    rho = W.density(desc)
+    g = yyg.Grid(desc, 0)
+    d_rho = torch.from_numpy(rho).to("cuda")
+    d_phi = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    g.upload_rho(d_rho)
+    with pytest.raises(yyg.YygError) as ei:
+        g.sep_phase(4, d_phi)
+    assert ei.value.status == -4          # YYG_ERR_NOT_READY: dense method
+    g.set_method("separable")
+    g.solve(d_phi)
+    torch.cuda.synchronize()
+    ref = d_phi.clone()
+    for phase in range(5):
+        d_phi.fill_(0.0)
+        for _ in range(2):
+            g.sep_phase(phase, d_phi)
+        if phase < 4:
+            g.sep_phase(4, d_phi)
+        torch.cuda.synchronize()
+        assert torch.equal(d_phi, ref), phase
+
+
 @pytest.mark.parametrize("method", ["dense", "separable"])
 def test_solve_captures_in_a_graph(method):
     """A solve on device buffers is asynchronous and allocation-free, so it
