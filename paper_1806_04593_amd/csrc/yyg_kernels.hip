@@ -958,10 +958,10 @@ __global__ __launch_bounds__(256) void phi_syn_lean_kernel(PhiLeanArgs a) {
         for (int c = 0; c < CT; ++c) ac[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[t], xb[c][t], ac[c], 0, 0, 0);
       }
   };
-  // the slots [sb, se) into ac, two register sets of S steps in turn
-  auto run = [&](dbl4 (&ac)[CT], int sb, int se) {
-    double xa0[S], xb0[CT][S], xa1[S], xb1[CT][S];
-    load(xa0, xb0, sb, se);
+  // the slots [sb, se) into ac, two register sets of S steps in turn, the
+  // first (xa0, xb0) already loaded
+  auto run = [&](dbl4 (&ac)[CT], double (&xa0)[S], double (&xb0)[CT][S], int sb, int se) {
+    double xa1[S], xb1[CT][S];
     for (int s0 = sb; s0 < se; s0 += 8 * S) {
       if (s0 + 4 * S < se) load(xa1, xb1, s0 + 4 * S, se);
       mma(ac, xa0, xb0, s0, se);
@@ -970,8 +970,14 @@ __global__ __launch_bounds__(256) void phi_syn_lean_kernel(PhiLeanArgs a) {
       mma(ac, xa1, xb1, s0 + 4 * S, se);
     }
   };
-  run(acc, 0, a.kc);
-  if (a.ns > a.kc) run(acc2, a.kc, a.ns);  // no sin slots at L = 0
+  // the first register sets of the cos and of the sin slots load together,
+  // so that the sin pass does not start with a wait of its own
+  const bool odd = a.ns > a.kc;  // no sin slots at L = 0
+  double ca[S], cb[CT][S], sa[S], sb[CT][S];
+  load(ca, cb, 0, a.kc);
+  if (odd) load(sa, sb, a.kc, a.ns);
+  run(acc, ca, cb, 0, a.kc);
+  if (odd) run(acc2, sa, sb, a.kc, a.ns);
   // D layout: lane l, element e -> row l/16 + 4e, column l%16
   const int np = a.np;
 #pragma unroll
