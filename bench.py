@@ -43,11 +43,12 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, key, kernel, name=None):
+def measured_traffic(workload, key, kernel, name=None, tile=None):
     """HBM bytes per launch of one kernel from committed rocprofv3 --pmc
     counters (FETCH_SIZE + WRITE_SIZE, scaled by a calibration kernel of
     known size), or None when absent, taken on different kernel sources or
-    (given `name`) on another kernel variant than the one timed."""
+    on another kernel variant than the one timed (given `name`, the exact
+    symbol; given `tile`, the (rows, columns) of a dense GEMM tile)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -60,6 +61,10 @@ def measured_traffic(workload, key, kernel, name=None):
         k = rec["kernels"][kernel]
         if name is not None and k.get("name") != name:
             return None
+        if tile is not None:
+            args = [int(x) for x in k["name"][k["name"].index("<") + 1:].rstrip(">").split(",")]
+            if (args[1], args[2]) != tuple(tile) or "write_kernel" in k:
+                return None
         return float(k["bytes_per_launch"])
     except (OSError, ValueError, KeyError, TypeError):
         return None
@@ -280,7 +285,8 @@ def bench_single(a):
                 "kernel": ("gemm_nt_f64_kernel<1,...> (dense synthesis)" if prec == "fp64"
                            else f"gemm_nt_lp_kernel<1,{prec},...> (dense synthesis)"),
                 "achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk,
-                "traffic": measured_traffic(a.workload, prec, "synthesis"),
+                "traffic": measured_traffic(a.workload, prec, "synthesis",
+                                            tile=(r["launch"]["bm_syn"], r["launch"]["bn_syn"])),
                 "executed_products_per_mac": PRODUCTS[prec], "executed_frac": ach * PRODUCTS[prec] / pk}
 
     if head_key == "fp64_separable":

@@ -26,6 +26,9 @@ def main():
     ap.add_argument("--sep-variants", default=None,
                     help="comma-separated variants of the five separable phases (as yyg_sep_config), "
                          "instead of the autotuner's choice, to profile the kernels a bench run chose")
+    ap.add_argument("--dense-config", default=None,
+                    help="var_ana,split_ana,var_syn of the dense plan (as yyg_plan_config) instead of the "
+                         "autotuner's choice")
     a = ap.parse_args()
 
     import torch
@@ -51,6 +54,9 @@ def main():
         for phase, v in enumerate(int(x) for x in a.sep_variants.split(",")):
             if v >= 0:
                 g.sep_config(phase, v)
+    elif a.dense_config and a.method == "dense":
+        va, sp, vs = (int(x) for x in a.dense_config.split(","))
+        g.set_config(va, sp, vs, a.precision)
     else:
         g.autotune(a.precision)
     d_rho = torch.from_numpy(rho).to("cuda:0")
