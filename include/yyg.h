@@ -270,7 +270,7 @@ int yyg_sep_info(const yyg_grid *g, int *variants, int n);
 
 /* The kernel that runs separable phase `phase` (0-4, as for yyg_sep_config)
  * with the current variant, named as profilers print it (e.g.
- * "yyg::gemm_nt_f64_batched<0, 64, 32, 2, 2, 4>"), NUL-terminated into
+ * "yyg::gemm_nt_f64_batched<0, 64, 32, 2, 2, 644>"), NUL-terminated into
  * name[0..n) (truncated if longer); the empty string for phase 2 on a polar
  * grid.  For matching profiles to a plan.  Needs the separable form built. */
 int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n);
