@@ -48,7 +48,8 @@ def measured_traffic(workload, key, kernel, name=None, tile=None):
     counters (FETCH_SIZE + WRITE_SIZE, scaled by a calibration kernel of
     known size), or None when absent, taken on different kernel sources or
     on another kernel variant than the one timed (given `name`, the exact
-    symbol; given `tile`, the (rows, columns) of a dense GEMM tile)."""
+    symbol, also looked up among the per-variant figures; given `tile`, the
+    (rows, columns) of a dense GEMM tile)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -58,6 +59,9 @@ def measured_traffic(workload, key, kernel, name=None, tile=None):
         rec = data.get(f"{workload}/{key}")
         if not rec or rec.get("kernel_sha") != kernel_sha():
             return None
+        if name is not None and name in rec.get("by_name", {}):
+            # every variant the autotuner launched in an unpinned counter run
+            return float(rec["by_name"][name]["bytes_per_launch"])
         k = rec["kernels"][kernel]
         if name is not None and k.get("name") != name:
             return None
