@@ -151,13 +151,20 @@ int yyg_prepare(yyg_grid *g, int precision);
 enum { YYG_METHOD_DENSE = 0, YYG_METHOD_SEPARABLE = 1 };
 int yyg_set_method(yyg_grid *g, int method);
 
-/* Hand the density to the plan.  rho_is_device != 0: `rho` is a device
+/* Hand the density to the plan: the cell averages rho_ijk of Eq. (10), one
+ * array per patch stacked as [P][n_r][n_theta][n_phi] (Yin first; Sect. 4:
+ * both patches in their own local coordinates).  rho_is_device != 0: `rho` is a device
  * array that the plan borrows (no copy) and that must stay valid until the
  * next yyg_solve on `stream` completes.  rho_is_device == 0: host array,
  * copied into plan-owned device memory on `stream`. */
 int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stream);
 
-/* Solve Phi for the last uploaded density.  Asynchronous on `stream` when
+/* Solve Phi for the last uploaded density: the per-patch weighted moments
+ * of Eqs. (21)-(22) with the overlap weights of Eqs. (26)-(27), the inner
+ * and outer radial sums of Eqs. (19)-(20) at the interfaces, and the
+ * synthesis of Eq. (5) with its normalisation (Eqs. 8-9), both patches'
+ * moments contributing at every point (Eqs. 28-29).  Output layout as rho.
+ * Asynchronous on `stream` when
  * phi_is_device != 0 (no host synchronisation, no allocation); with a host
  * `phi` the call copies back and synchronises the stream.  `precision` is a
  * yyg_precision that yyg_prepare has enabled (FP64 always is).  Returns
@@ -225,9 +232,11 @@ int yyg_host_table(const yyg_grid_desc *desc, int which, double *out, size_t n);
 int yyg_set_timing(yyg_grid *g, int enable);
 int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots);
 
-/* Choose the tile shape and split-K factor of both angular contractions
- * for this plan by timing every candidate on the plan's own shapes (HIP
- * events on `stream`; blocks until done).  Allocates scratch memory for the
+/* Choose the launch configuration of the plan's current method by timing
+ * every candidate on the plan's own shapes (HIP events on `stream`; blocks
+ * until done).  Dense method: the tile shape and split-K factor of both
+ * angular contractions of `precision`.  Separable method (FP64): the tile
+ * variant of each of its five phases, each timed inside whole solves.  Allocates scratch memory for the
  * duration of the call and may grow the plan's partial-moment buffer.  With
  * the environment variable YYG_TUNE_CACHE naming a file, earlier choices
  * for the same (precision, shape) are read from it and new ones appended.
@@ -259,7 +268,10 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * condition under which the tile variants of the phi phases fold too); the
  * phi synthesis also [2V + 14, 2V + 18), folded kernels in which every wave
  * loads its matrix-core operands straight from memory (no LDS; the same
- * mirror-symmetry condition).
+ * mirror-symmetry condition).  Every phase then takes X further variants
+ * (X = 12 in this build) at the end of its range: tiles on the 4x4x4 FP64
+ * matrix instruction, for the phi phases folded whenever the grid is
+ * mirror-symmetric.
  * Needs the separable form built (yyg_set_method); synchronises the
  * device.  For tests and expert tuning; yyg_autotune chooses all of them. */
 int yyg_sep_config(yyg_grid *g, int phase, int variant);

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libyyg.so")
 
-SOURCES = ["yyg_kernels.hip", "yyg_kernels_lp.hip", "yyg_tables.cpp", "yyg_api.cpp"]
+SOURCES = ["yyg_kernels.hip", "yyg_kernels_x4.hip", "yyg_kernels_lp.hip", "yyg_tables.cpp", "yyg_api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -29,12 +29,34 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
+def build(verbose=False, jobs=None):
+    """Compile every source to an object in parallel (one hipcc process per
+    source), then link the shared library; replaces LIB atomically."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    procs, objs = [], []
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1))
+    pending = list(SOURCES)
+    failed = []
+    while pending or procs:
+        while pending and len(procs) < jobs:
+            src = pending.pop(0)
+            obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+            cmd = [hipcc] + compile_flags + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((src, subprocess.Popen(cmd)))
+            objs.append(obj)
+        src, p = procs.pop(0)
+        if p.wait() != 0:
+            failed.append(src)
+    if failed:
+        raise subprocess.CalledProcessError(1, f"hipcc ({', '.join(failed)})")
     tmp = LIB + ".tmp"
-    cmd += ["-o", tmp, "-lpthread"]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

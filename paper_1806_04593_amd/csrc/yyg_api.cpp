@@ -298,14 +298,19 @@ namespace {
 // phases (0, 4) also 2V + d, the LDS-basis kernel variant d (d < D), and
 // 2V + D + f, its folded form f (F of them; mirror-symmetric grids only);
 // the phi synthesis also 2V + D + F + e, the LDS-free folded kernel e.
-int sep_variant_count(int r) {
+// Every phase then takes X = yyg::x4_variant_count() tiles on the 4x4x4
+// FP64 MFMA at the end of its range (sep_x4_base).
+int sep_x4_base(int r) {
   const int v = 2 * yyg::gemm_f64_variant_count();
   const int phi = yyg::phi_direct_variant_count() + yyg::phi_fold_variant_count();
   return r == 0 ? v + phi : r == 4 ? v + phi + yyg::phi_lean_variant_count() : v;
 }
 
+int sep_variant_count(int r) { return sep_x4_base(r) + yyg::x4_variant_count(); }
+
 bool sep_fold_variant(int r, int v) {
-  return (r == 0 || r == 4) && v >= 2 * yyg::gemm_f64_variant_count() + yyg::phi_direct_variant_count();
+  return (r == 0 || r == 4) && v >= 2 * yyg::gemm_f64_variant_count() + yyg::phi_direct_variant_count() &&
+         v < sep_x4_base(r);
 }
 
 int sep_set_variant(yyg_grid *g, int r, int v) {
@@ -319,6 +324,11 @@ hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
   const int nv = yyg::gemm_f64_variant_count(), nd = yyg::phi_direct_variant_count();
   const int nf = yyg::phi_fold_variant_count();
+  if (S.var[r] >= sep_x4_base(r)) {
+    if (r == 2 && g->n_patch != 2) return hipSuccess;
+    const yyg::GemmF64Args &phi = r == 0 ? (S.fold ? S.phi_ana_f : S.phi_ana) : (S.fold ? S.phi_syn_f : S.phi_syn);
+    return yyg::launch_x4_sep_phase(S.var[r] - sep_x4_base(r), r, S.fold, phi, S.args, s);
+  }
   if (r == 4 && S.var[r] >= 2 * nv + nd + nf) return yyg::launch_phi_syn_lean(S.var[r] - 2 * nv - nd - nf, S.phi_syn_l, s);
   if (sep_fold_variant(r, S.var[r]))
     return yyg::launch_phi_fold(S.var[r] - 2 * nv - nd, r == 0, r == 0 ? S.phi_ana_fd : S.phi_syn_fd, s);
@@ -1389,13 +1399,16 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   auto cache = read_tune_cache(cache_path);
   const std::string ka = tune_key(precision, 0, M, Q, g->nang), ks = tune_key(precision, 1, M, g->nang, (long)g->n_patch * Q);
   int best_va = *cur_va, best_sp = *cur_sp, best_vs = *cur_vs;
-  bool have_a = false, have_s = false;
-  if (cache.count(ka)) {
+  // a plan in the separable form tunes that form's phases only (FP64): the
+  // dense contractions keep their configuration
+  const bool sep_only = !lp && g->method == YYG_METHOD_SEPARABLE;
+  bool have_a = sep_only, have_s = sep_only;
+  if (!sep_only && cache.count(ka)) {
     best_va = cache[ka].first;
     best_sp = cache[ka].second;
     have_a = best_va >= 0 && best_va < nv && best_sp >= 1 && best_sp <= 32;
   }
-  if (cache.count(ks)) {
+  if (!sep_only && cache.count(ks)) {
     best_vs = cache[ks].first;
     have_s = best_vs >= 0 && best_vs < nv;
   }
@@ -1492,7 +1505,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   *cur_sp = best_sp;
   *cur_vs = best_vs;
   // separable form (FP64): tile variant of each grouped phase
-  if (!lp && g->sep.ready) {
+  if (sep_only && g->sep.ready) {
     double *phi_t = nullptr, *rho_t = nullptr;
     int st3 = dmalloc(&phi_t, (size_t)M * g->nang);
     if (st3 == YYG_OK && !g->rho) {
@@ -1542,7 +1555,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     g->sep.phi_syn_l.C = nullptr;
     if (st3 != YYG_OK) return st3;
   }
-  if (cache_path && (!have_a || !have_s)) {
+  if (cache_path && !sep_only && (!have_a || !have_s)) {
     if (std::FILE *f = std::fopen(cache_path, "a")) {
       if (!have_a) std::fprintf(f, "%s -> %d %d\n", ka.c_str(), best_va, best_sp);
       if (!have_s) std::fprintf(f, "%s -> %d %d\n", ks.c_str(), best_vs, 1);
@@ -1648,7 +1661,10 @@ int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
     name[0] = 0;
     return YYG_OK;
   }
-  return yyg::sep_kernel_name(phase, g->sep.var[phase], g->sep.fold, name, n) == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
+  const int v = g->sep.var[phase], x0 = sep_x4_base(phase);
+  const int r = v >= x0 ? yyg::x4_kernel_name(v - x0, phase, g->sep.fold, name, n)
+                        : yyg::sep_kernel_name(phase, v, g->sep.fold, name, n);
+  return r == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
 }
 
 int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out) {

@@ -54,6 +54,11 @@ struct GemmF64Args {
 //               covers 16 consecutive rows, for C stored column-major
 //  kGemmAccInit (with the general epilogue) the accumulators start from
 //               Cin (same strides as C) instead of zero
+//  kGemmX4      v_mfma_f64_4x4x4f64 instead of the 16x16x4 form: measured on
+//               MI355X it runs at ~92% of the FP64 matrix peak where the
+//               16x16x4 form stops at ~62%, for four times the operand
+//               traffic per flop (each 4 x 4 operand is replicated over the
+//               instruction's four blocks)
 enum {
   kGemmATrans = 2,
   kGemmCTrans = 4,
@@ -63,7 +68,8 @@ enum {
   kGemmFoldA = 128,
   kGemmFoldC = 256,
   kGemmDT = 512,
-  kGemmAccInit = 1024
+  kGemmAccInit = 1024,
+  kGemmX4 = 2048
 };
 // role offset of the kGemmDeep forms of the batched roles
 constexpr int kRoleDeep = 16;
@@ -121,6 +127,15 @@ struct PhiLeanArgs {
 };
 int phi_lean_variant_count();
 hipError_t launch_phi_syn_lean(int variant, const PhiLeanArgs &a, hipStream_t s);
+
+// FP64 tiles on v_mfma_f64_4x4x4f64 (kGemmX4) for the separable phases:
+// x4_variant_count() shapes; phase 0 / 4 are the phi transforms (folded
+// when `fold`, as launch_gemm_f64_batched roles 2 / 3, else roles 0 / 1),
+// phases 1-3 as launch_gemm_f64_sep.
+int x4_variant_count();
+hipError_t launch_x4_sep_phase(int variant, int phase, bool fold, const GemmF64Args &phi, const SepPhaseArgs &a,
+                               hipStream_t s);
+int x4_kernel_name(int variant, int phase, bool fold, char *buf, size_t n);
 
 // phase 1 theta analysis, 2 rotation (two patches), 3 theta synthesis;
 // deep = kGemmDeep.

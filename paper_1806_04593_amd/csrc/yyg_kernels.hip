@@ -19,432 +19,9 @@
 #include <cstdio>
 
 #include "yyg_internal.h"
+#include "yyg_tile.h"
 
 namespace yyg {
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-namespace {
-
-// x where keep holds, else 0, as an FP multiply by 1 or 0: the compiler
-// cannot move the load of x under a branch on keep (x * 0 is NaN for a
-// non-finite x), so the loads of a loop stay unconditional and in flight
-// together.  x must be finite: it is read from a clamped, valid address.
-__device__ __forceinline__ double keep_if(bool keep, double x) { return x * (keep ? 1.0 : 0.0); }
-
-constexpr int kBK = 16, kPad = 2, kLDK = kBK + kPad;
-// Stages of A and B held in registers ahead of the LDS stage being
-// multiplied: a stage's global loads are issued kPF stages before its LDS
-// store.  Measured on MI355X, three stages were slower than one for the
-// long dense contractions (the registers cost occupancy); the short
-// contractions of the separable form (K of a few stages) can ask for
-// kDeepPF with the kGemmDeep mode bit, so that their loads are in flight
-// together.
-constexpr int kPF = 1, kDeepPF = 3;
-
-// Logical tile of a block so that the blocks one XCD receives (the hardware
-// hands blocks to the 8 XCDs round-robin) form a contiguous run of tiles in
-// M-fastest order: the M tiles that share a B tile then share that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int total) {
-  const int per = total / 8, rem = total % 8;
-  const int x = b % 8, i = b / 8;
-  return x * per + min(x, rem) + i;
-}
-
-}  // namespace
-
-// Block tile BM x BN, WGM x WGN waves, each wave a (BM/WGM) x (BN/WGN) grid
-// of 16 x 16 MFMA tiles; computes output tile (tm, tn) over split z.
-// MODE bit 1 selects the general epilogue (column stride, degree-major
-// column index); the plain one writes C[row * ldc + col].  The other bits
-// change the operand layouts and the prefetch depth as documented with
-// GemmF64Args.
-template <int BM, int BN, int WGM, int WGN, int MODE>
-__device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int tn, int z) {
-  constexpr bool GEN = (MODE & 1) != 0;
-  constexpr bool AT = (MODE & kGemmATrans) != 0;
-  constexpr bool CT = (MODE & kGemmCTrans) != 0;
-  constexpr bool BATCH = (MODE & kGemmBatch) != 0;
-  constexpr bool BT = (MODE & kGemmBTrans) != 0;
-  constexpr bool ACCINIT = (MODE & kGemmAccInit) != 0;
-  constexpr bool FOLDA = (MODE & kGemmFoldA) != 0;
-  constexpr bool FOLDC = (MODE & kGemmFoldC) != 0;
-  constexpr bool DT = (MODE & kGemmDT) != 0;
-  static_assert(!ACCINIT || GEN, "the initial accumulator is addressed like C");
-  static_assert(!DT || !FOLDC, "the folded synthesis stores rows");
-  static_assert(!FOLDA || (BATCH && CT && !AT && !GEN), "folded analysis: batched, row-major A, C column-major");
-  static_assert(!FOLDC || (BATCH && AT && !CT && !GEN), "folded synthesis: batched, A k-major");
-
-  const int M = g.M, N = g.N, K = g.K;
-  // FOLDA: problem z = 2 zj + group (group 0 the even, 1 the odd half), so
-  // that the two halves of a row tile run close together and share L2
-  const int fgrp = FOLDA ? (z & 1) : 0;
-  const int zj = FOLDA ? (z >> 1) : z;
-  const double fsign = fgrp ? -1.0 : 1.0;
-  const double *__restrict__ A = g.A + (BATCH ? zj * g.a_batch : 0L);
-  const double *__restrict__ B = g.B + (BATCH ? z * g.b_batch : 0L);
-  double *__restrict__ C = g.C;
-  const long lda = g.lda, ldb = g.ldb, ldc = g.ldc;
-  constexpr int NT = 64 * WGM * WGN;
-  constexpr int TI = BM / WGM / 16, TJ = BN / WGN / 16;
-  static_assert(TI >= 1 && TJ >= 1 && TI * 16 * WGM == BM && TJ * 16 * WGN == BN, "tile/wave mismatch");
-  // Stage loads.  When a thread's share of a tile stage divides the 16-wide
-  // stage, it reads one contiguous run of k in one row (one row pointer);
-  // otherwise element e = tid + i*NT sits at row e / 16, column e % 16.
-  // An operand stored k-major loads along m (n) instead: element
-  // e = tid + i*NT at k = e / BM, m = e % BM.
-  constexpr bool RUN_A = !AT && (BM * kBK) % NT == 0 && kBK % ((BM * kBK) / NT) == 0;
-  constexpr bool RUN_B = !BT && (BN * kBK) % NT == 0 && kBK % ((BN * kBK) / NT) == 0;
-  constexpr int EA = RUN_A ? (BM * kBK) / NT : (BM * kBK + NT - 1) / NT;
-  constexpr int EB = RUN_B ? (BN * kBK) / NT : (BN * kBK + NT - 1) / NT;
-  __shared__ double As[2][BM * kLDK];
-  __shared__ double Bs[2][BN * kLDK];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = tm * BM, n0 = tn * BN;
-  // z is the split-K slice, or with BATCH the problem of a strided batch
-  const int kbeg = BATCH ? 0 : z * g.k_per_split;
-  const int kend = BATCH ? K : min(K, kbeg + g.k_per_split);
-  C += (long)zj * g.c_split_stride;
-
-  const int wm = wave % WGM, wn = wave / WGM;
-
-  // FOLDC: acc sums the stages below k_split (the even part), acc2 the rest
-  dbl4 acc[TI][TJ], acc2[FOLDC ? TI : 1][FOLDC ? TJ : 1];
-#pragma unroll
-  for (int i = 0; i < TI; ++i)
-#pragma unroll
-    for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  if constexpr (FOLDC) {
-#pragma unroll
-    for (int i = 0; i < TI; ++i)
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) acc2[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  }
-  if constexpr (ACCINIT) {
-    // start from Cin, element by element in the D layout of the epilogue
-    // (clamped addresses; entries outside the matrix start at zero)
-    const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < TI; ++i)
-#pragma unroll
-      for (int j = 0; j < TJ; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = m0 + (wv % WGM) * (BM / WGM) + i * 16 + (DT ? (ln & 15) : (ln >> 4) + 4 * r);
-          const int col = n0 + (wv / WGM) * (BN / WGN) + j * 16 + (DT ? (ln >> 4) + 4 * r : (ln & 15));
-          const double v = g.Cin[(long)min(row, M - 1) * ldc + (long)min(col, N - 1) * g.ldc_c];
-          acc[i][j][r] = (row < M && col < N) ? v : 0.0;
-        }
-  }
-
-  constexpr int PF = (MODE & kGemmDeep) ? kDeepPF : kPF;
-  // FOLDA keeps the raw front and mirror values (ra[i], ra[EA + i]) until
-  // the stash: folding them at load time would wait for the loads there
-  constexpr int EAR = FOLDA ? 2 * EA : EA;
-  double ra[PF][EAR], rb[PF][EB];
-  // run mapping: this thread's row and first column
-  const int arow = RUN_A ? tid / (kBK / EA) : 0, acol = RUN_A ? (tid % (kBK / EA)) * EA : 0;
-  const int brow = RUN_B ? tid / (kBK / EB) : 0, bcol = RUN_B ? (tid % (kBK / EB)) * EB : 0;
-  const double *pa = A + (long)min(m0 + arow, M - 1) * lda;
-  const double *pb = B + (long)min(n0 + brow, N - 1) * ldb;
-  const bool va = m0 + arow < M, vb = n0 + brow < N;
-  // load: every global load reads a clamped, valid address (a load under a
-  // condition would be waited for before the next one issues); stash: the
-  // entries outside the matrix or the stage's k range are zeroed on the way
-  // into LDS, after the stage's MFMA work, so the loads overlap it.
-  // FOLDA: A(m, k) = X(m, k) + sign X(m, fold_k - 1 - k), the even (odd)
-  // half of a row about its middle
-  auto aload = [&](double (&ra)[EAR], int i, const double *row, int kc) {
-    ra[i] = row[kc];
-    if constexpr (FOLDA) ra[EA + i] = row[g.fold_k - 1 - kc];
-  };
-  // FOLDA, a run of EA (even) values per thread: pairs of neighbours as one
-  // 16-byte load each at the front and at the mirror.  K = h < fold_k, so a
-  // pair starting at a clamped kc <= K - 1 stays inside the row on both sides
-  // (its second value, past K, is zeroed at the stash like every value past K).
-  typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
-  auto apairs = [&](double (&ra)[EAR], const double *row, int k0) {
-#pragma unroll
-    for (int i = 0; i < EA; i += 2) {
-      const int kc = min(k0 + acol + i, K - 1);
-      const dbl2u f = *reinterpret_cast<const dbl2u *>(row + kc);
-      const dbl2u b = *reinterpret_cast<const dbl2u *>(row + (g.fold_k - 2 - kc));
-      ra[i] = f.x;
-      ra[i + 1] = f.y;
-      ra[EA + i] = b.y;
-      ra[EA + i + 1] = b.x;
-    }
-  };
-  auto aval = [&](const double (&ra)[EAR], int i) { return FOLDA ? ra[i] + fsign * ra[(FOLDA ? EA : 0) + i] : ra[i]; };
-  auto load = [&](double (&ra)[EAR], double (&rb)[EB], int k0) {
-    if constexpr (RUN_A && FOLDA && EA % 2 == 0) {
-      apairs(ra, pa, k0);
-    } else if constexpr (RUN_A) {
-#pragma unroll
-      for (int i = 0; i < EA; ++i) aload(ra, i, pa, min(k0 + acol + i, K - 1));
-    } else if constexpr (AT) {
-#pragma unroll
-      for (int i = 0; i < EA; ++i) {
-        const int e = tid + i * NT, gm = m0 + e % BM;
-        int kc = min(k0 + e / BM, K - 1);
-        if constexpr (FOLDC) {
-          // contraction index -> azimuthal column: cos m at k = m, sin m at
-          // k_split + m - 1 (padding clamps; its basis entries are zero)
-          kc = min(kc < g.k_split ? max(2 * kc - 1, 0) : 2 * (kc - g.k_split) + 2, g.fold_mc - 1);
-        }
-        ra[i] = A[(long)kc * lda + min(gm, M - 1)];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < EA; ++i) {
-        const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        aload(ra, i, A + (long)min(m0 + row, M - 1) * lda, min(kk, K - 1));
-      }
-    }
-    if constexpr (RUN_B) {
-#pragma unroll
-      for (int i = 0; i < EB; ++i) rb[i] = pb[min(k0 + bcol + i, K - 1)];
-    } else if constexpr (BT) {
-#pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const int e = tid + i * NT, kk = k0 + e / BN, gn = n0 + e % BN;
-        rb[i] = B[(long)min(kk, K - 1) * ldb + min(gn, N - 1)];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        rb[i] = B[(long)min(n0 + row, N - 1) * ldb + min(kk, K - 1)];
-      }
-    }
-  };
-  auto stash = [&](const double (&ra)[EAR], const double (&rb)[EB], int buf, int k0) {
-    if constexpr (RUN_A) {
-#pragma unroll
-      for (int i = 0; i < EA; ++i)
-        As[buf][arow * kLDK + acol + i] = (va && k0 + acol + i < kend) ? aval(ra, i) : 0.0;
-    } else if constexpr (AT) {
-#pragma unroll
-      for (int i = 0; i < EA; ++i) {
-        const int e = tid + i * NT, kk = k0 + e / BM, gm = m0 + e % BM;
-        if (e < BM * kBK) As[buf][(e % BM) * kLDK + e / BM] = (gm < M && kk < kend) ? ra[i] : 0.0;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < EA; ++i) {
-        const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        if (e < BM * kBK) As[buf][row * kLDK + e % kBK] = (m0 + row < M && kk < kend) ? aval(ra, i) : 0.0;
-      }
-    }
-    if constexpr (RUN_B) {
-#pragma unroll
-      for (int i = 0; i < EB; ++i) Bs[buf][brow * kLDK + bcol + i] = (vb && k0 + bcol + i < kend) ? rb[i] : 0.0;
-    } else if constexpr (BT) {
-#pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const int e = tid + i * NT, kk = k0 + e / BN, gn = n0 + e % BN;
-        if (e < BN * kBK) Bs[buf][(e % BN) * kLDK + e / BN] = (gn < N && kk < kend) ? rb[i] : 0.0;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        if (e < BN * kBK) Bs[buf][row * kLDK + e % kBK] = (n0 + row < N && kk < kend) ? rb[i] : 0.0;
-      }
-    }
-  };
-
-  const int frow = lane & 15, fk = 4 * (lane >> 4);
-  auto compute = [&](int buf, bool second) {
-    // Each lane holds four consecutive k of its row; MFMA step s uses the
-    // s-th of them, so the four steps cover the 16 k of the stage once.
-    double af[TI][4], bf[TJ][4];
-#pragma unroll
-    for (int i = 0; i < TI; ++i) {
-      const double *sp = &As[buf][(wm * (BM / WGM) + i * 16 + frow) * kLDK + fk];
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) af[i][s4] = sp[s4];
-    }
-#pragma unroll
-    for (int j = 0; j < TJ; ++j) {
-      const double *sp = &Bs[buf][(wn * (BN / WGN) + j * 16 + frow) * kLDK + fk];
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) bf[j][s4] = sp[s4];
-    }
-    if (FOLDC && second) {  // uniform: the whole stage is past k_split
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-          for (int j = 0; j < TJ; ++j)
-            acc2[FOLDC ? i : 0][FOLDC ? j : 0] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                af[i][s4], bf[j][s4], acc2[FOLDC ? i : 0][FOLDC ? j : 0], 0, 0, 0);
-    } else {
-      // DT: the transposed tile B A^T, so that a store covers 16 rows
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-          for (int j = 0; j < TJ; ++j)
-            acc[i][j] = DT ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j][s4], af[i][s4], acc[i][j], 0, 0, 0)
-                           : __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
-    }
-  };
-
-  const int nk = (kend - kbeg + kBK - 1) / kBK;
-#pragma unroll
-  for (int p = 0; p < PF; ++p)
-    if (p < nk) load(ra[p], rb[p], kbeg + p * kBK);
-  if (nk > 0) stash(ra[0], rb[0], 0, kbeg);
-  __syncthreads();
-
-  // Stage `it` sits in LDS buffer it & 1 and register slot it % PF; the
-  // loop is unrolled by PF so that every slot index is a constant.  With
-  // PF = 1 the stage loaded this iteration is the one stored after it.
-  for (int base = 0; base < nk; base += PF) {
-#pragma unroll
-    for (int sl = 0; sl < PF; ++sl) {
-      const int it = base + sl;
-      if (it < nk) {  // uniform across the block
-        const int buf = it & 1;
-        if (it + PF < nk) load(ra[sl], rb[sl], kbeg + (it + PF) * kBK);
-        compute(buf, FOLDC && kbeg + it * kBK >= g.k_split);
-        if (it + 1 < nk) stash(ra[(sl + 1) % PF], rb[(sl + 1) % PF], buf ^ 1, kbeg + (it + 1) * kBK);
-        __syncthreads();
-      }
-    }
-  }
-
-  // D layout of the 16x16x4 f64 MFMA: lane l, element r -> row l/16 + 4r,
-  // col l%16 (one row per output group, unlike the f32 variant's four);
-  // with DT the roles of row and column swap.
-  const int orow = lane >> 4, ocol = lane & 15;
-#pragma unroll
-  for (int i = 0; i < TI; ++i) {
-#pragma unroll
-    for (int j = 0; j < TJ; ++j) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * (BM / WGM) + i * 16 + (DT ? ocol : orow + 4 * r);
-        const int col = n0 + wn * (BN / WGN) + j * 16 + (DT ? orow + 4 * r : ocol);
-        if (row < M && col < N) {
-          if constexpr (GEN) {
-            const long cc = g.c_sq < 0 ? (long)col : (long)(col + g.c_sq) * (col + g.c_sq);
-            C[(long)row * ldc + cc * g.ldc_c] = acc[i][j][r];
-          } else if constexpr (FOLDA) {
-            // output column -> azimuthal column: cos m (group 0, col m), sin m
-            // (group 1, col m - 1)
-            const int mc = max(2 * col + (fgrp ? 2 : -1), 0);
-            if (mc < g.fold_mc) C[(long)mc * ldc + row] = acc[i][j][r];
-          } else if constexpr (CT) {
-            C[(long)col * ldc + row] = acc[i][j][r];
-          } else if constexpr (FOLDC) {
-            // the even part plus / minus the odd part, at col and its mirror
-            const double e = acc[i][j][r], o = acc2[FOLDC ? i : 0][FOLDC ? j : 0][r];
-            const int cm = g.fold_k - 1 - col;
-            C[(long)row * ldc + col] = e + o;
-            if (cm != col) C[(long)row * ldc + cm] = e - o;
-          } else {
-            C[(long)row * ldc + col] = acc[i][j][r];
-          }
-        }
-      }
-    }
-  }
-}
-
-// ROLE only separates the analysis (0) and synthesis (1) instantiations so
-// that profilers list them apart.
-template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE = 0>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_kernel(GemmF64Args g, int tiles_total) {
-  const int tile = xcd_tile(blockIdx.x, tiles_total);
-  gemm_f64_tile<BM, BN, WGM, WGN, MODE>(g, tile % g.tiles_m, tile / g.tiles_m, blockIdx.y);
-}
-
-// Strided batch of equal-shape problems, one block per (problem, tile),
-// problem-major after the XCD remapping.
-template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_batched(GemmF64Args g, int per_problem,
-                                                                      int tiles_total) {
-  const int t = xcd_tile(blockIdx.x, tiles_total);
-  const int z = t / per_problem, tile = t - z * per_problem;
-  gemm_f64_tile<BM, BN, WGM, WGN, MODE | kGemmBatch>(g, tile % g.tiles_m, tile / g.tiles_m, z);
-}
-
-// The theta phases and the moment rotation of the separable form: one
-// problem per blockIdx.z, its shapes and operands derived from the phase
-// arguments (no descriptor loads ahead of the operand loads).
-//  PHASE 1, theta analysis, z = mc (m = (mc + 1) / 2): the column-major
-//    moments A[(l^2 + mc)][row] = sum_j X2[mc][j][row] T2[mc][l][j], l >= m.
-//  PHASE 2, rotation, z = 2 (L - l) + p: At[l^2 + b][p nR + n] =
-//    A_own(n, b) + sum_{k < d} A_other(n, k) D_l[k][b], d = 2l + 1, with
-//    A_own / A_other this / the other patch's rows of degree l's columns;
-//    the accumulators start from A_own (kGemmAccInit).
-//  PHASE 3, theta synthesis, z = mc: V[mc][j][row] =
-//    sum_{l >= m} P2[mc][j][l] Ut[mc][l][row].
-template <int PHASE, int BM, int BN, int WGM, int WGN, int MODE>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_sep_phase(SepPhaseArgs a) {
-  const long Mr = (long)a.P * a.nR, MJ = Mr * a.nt;
-  const int z = blockIdx.z;
-  GemmF64Args g{};
-  if constexpr (PHASE == 1) {
-    const int mc = z, m = (mc + 1) >> 1;
-    g.M = (int)Mr;
-    g.N = a.L + 1 - m;
-    g.K = a.nt;
-    g.A = a.X2 + mc * MJ;
-    g.lda = Mr;
-    g.B = a.T2 + ((long)mc * (a.L + 1) + m) * a.nt;
-    g.ldb = a.nt;
-    g.C = a.Ahat + mc * Mr;
-    g.ldc = 1;
-    g.ldc_c = Mr;
-    g.c_sq = m;
-  } else if constexpr (PHASE == 2) {
-    const int l = a.L - (z >> 1), p = z & 1, d = 2 * l + 1;
-    g.M = a.nR;
-    g.N = d;
-    g.K = d;
-    g.A = a.Ahat + (long)l * l * Mr + (long)(1 - p) * a.nR;  // the other patch's rows
-    g.lda = Mr;
-    g.B = a.D + (long)l * (4 * (long)l * l - 1) / 3;  // D_l after the blocks of degrees below l
-    g.ldb = d;
-    g.C = a.At + (long)l * l * Mr + (long)p * a.nR;
-    g.Cin = a.Ahat + (long)l * l * Mr + (long)p * a.nR;  // this patch's own moments
-    g.ldc = 1;
-    g.ldc_c = Mr;
-  } else {
-    const int mc = z, m = (mc + 1) >> 1;
-    g.M = a.nt;
-    g.N = (int)Mr;
-    g.K = a.L + 1 - m;
-    g.A = a.P2 + (long)mc * a.nt * a.ldl + m;
-    g.lda = a.ldl;
-    g.B = a.Ut + ((long)mc * (a.L + 1) + m) * Mr;
-    g.ldb = Mr;
-    g.C = a.V + mc * MJ;
-    g.ldc = Mr;
-  }
-  g.k_per_split = (g.K + kBK - 1) / kBK * kBK;
-  g.tiles_m = 1;
-  if ((int)blockIdx.x * BM >= g.M || (int)blockIdx.y * BN >= g.N) return;  // uniform: past this problem's tiles
-  gemm_f64_tile<BM, BN, WGM, WGN, MODE>(g, blockIdx.x, blockIdx.y, 0);
-}
-
-// Persistent grouped form: blocks walk a list of (problem, tm, tn, split)
-// work items over several independent contractions of one phase.
-template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_grouped(const GemmF64Args *__restrict__ probs,
-                                                                      const int4 *__restrict__ items, int n_items) {
-  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
-    const int4 it = items[w];
-    __syncthreads();  // the previous item's LDS reads are done
-    gemm_f64_tile<BM, BN, WGM, WGN, MODE>(probs[it.x], it.y, it.z, it.w);
-  }
-}
 
 // Radial sums of Eqs. (19)-(20) for every (patch, column), with the split-K
 // partial moments reduced first (fixed order over the splits).

@@ -144,6 +144,36 @@ def host_table(desc, which):
     return out
 
 
+def device_array(t, shape, what, device=None):
+    """Check that `t` is a C-contiguous torch CUDA float64 tensor of `shape`
+    and return its device address.  The library cannot size-check a raw
+    device pointer, so a wrong dtype, size or a host tensor is refused here,
+    before any library call (ValueError, not an assert: -O keeps it)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch CUDA tensor, got {type(t).__name__}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected torch.float64")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: tensor on {t.device}, expected a CUDA (HIP) device tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what}: tensor on {t.device}, the plan is on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor is not contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def host_array(a, shape, what):
+    """Check that `a` is a C-contiguous numpy float64 array of `shape`."""
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise ValueError(f"{what}: expected a C-contiguous numpy float64 array")
+    if a.shape != tuple(shape):
+        raise ValueError(f"{what}: shape {a.shape}, expected {tuple(shape)}")
+    return a.ctypes.data
+
+
 def _stream_handle(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -182,31 +212,25 @@ class Grid:
         """rho: torch CUDA tensor (borrowed) or numpy array (copied)."""
         if isinstance(rho, np.ndarray):
             r = np.ascontiguousarray(rho, dtype=np.float64)
-            assert r.shape == self.shape
+            ptr = host_array(r, self.shape, "upload_rho")
             self._host_rho = r
-            _check(lib().yyg_upload_rho(self._h, ctypes.c_void_p(r.ctypes.data), 0, _stream_handle(stream)),
+            _check(lib().yyg_upload_rho(self._h, ctypes.c_void_p(ptr), 0, _stream_handle(stream)),
                    "yyg_upload_rho")
         else:
-            import torch
-            assert rho.dtype == torch.float64 and rho.is_cuda and rho.is_contiguous()
-            assert tuple(rho.shape) == self.shape
+            ptr = device_array(rho, self.shape, "upload_rho", self.device)
             self._dev_rho = rho
-            _check(lib().yyg_upload_rho(self._h, ctypes.c_void_p(rho.data_ptr()), 1, _stream_handle(stream)),
+            _check(lib().yyg_upload_rho(self._h, ctypes.c_void_p(ptr), 1, _stream_handle(stream)),
                    "yyg_upload_rho")
 
     def solve(self, phi, precision="fp64", stream=None):
         """phi: preallocated torch CUDA float64 tensor (async) or numpy (sync)."""
         p = PRECISIONS.get(precision, precision)
         if isinstance(phi, np.ndarray):
-            assert phi.dtype == np.float64 and phi.flags.c_contiguous and phi.shape == self.shape
-            _check(lib().yyg_solve(self._h, ctypes.c_void_p(phi.ctypes.data), 0, p, _stream_handle(stream)),
-                   "yyg_solve")
+            ptr = host_array(phi, self.shape, "solve")
+            _check(lib().yyg_solve(self._h, ctypes.c_void_p(ptr), 0, p, _stream_handle(stream)), "yyg_solve")
         else:
-            import torch
-            assert phi.dtype == torch.float64 and phi.is_cuda and phi.is_contiguous()
-            assert tuple(phi.shape) == self.shape
-            _check(lib().yyg_solve(self._h, ctypes.c_void_p(phi.data_ptr()), 1, p, _stream_handle(stream)),
-                   "yyg_solve")
+            ptr = device_array(phi, self.shape, "solve", self.device)
+            _check(lib().yyg_solve(self._h, ctypes.c_void_p(ptr), 1, p, _stream_handle(stream)), "yyg_solve")
         return phi
 
     def autotune(self, precision="fp64", stream=None):
@@ -235,10 +259,8 @@ class Grid:
     def sep_phase(self, phase, phi, stream=None):
         """Launch one separable phase alone (after a solve); phi: the torch
         CUDA float64 tensor phase 4 writes."""
-        import torch
-        assert phi.dtype == torch.float64 and phi.is_cuda and phi.is_contiguous()
-        assert tuple(phi.shape) == self.shape
-        _check(lib().yyg_sep_phase(self._h, int(phase), ctypes.c_void_p(phi.data_ptr()), _stream_handle(stream)),
+        ptr = device_array(phi, self.shape, "sep_phase", self.device)
+        _check(lib().yyg_sep_phase(self._h, int(phase), ctypes.c_void_p(ptr), _stream_handle(stream)),
                "yyg_sep_phase")
 
     def set_config(self, var_ana, split_ana, var_syn, precision="fp64"):
@@ -276,10 +298,6 @@ class Grid:
             pass
 
 
-def grid_from_workload(desc, device=0):
-    return Grid(desc, device)
-
-
 class Batch:
     """Batched solves of several plans (yyg_batch_*)."""
 
@@ -295,13 +313,13 @@ class Batch:
     def solve(self, rhos, phis, stream=None):
         """rhos, phis: lists of torch CUDA float64 tensors, one per field."""
         n = len(self.grids)
-        assert len(rhos) == n and len(phis) == n
-        for g, r, p in zip(self.grids, rhos, phis):
-            assert tuple(r.shape) == g.shape and tuple(p.shape) == g.shape
-            assert r.is_contiguous() and p.is_contiguous()
+        if len(rhos) != n or len(phis) != n:
+            raise ValueError(f"batch solve: {len(rhos)} densities and {len(phis)} potentials for {n} fields")
+        rp = [device_array(r, g.shape, f"batch rho[{f}]", g.device) for f, (g, r) in enumerate(zip(self.grids, rhos))]
+        pp = [device_array(p, g.shape, f"batch phi[{f}]", g.device) for f, (g, p) in enumerate(zip(self.grids, phis))]
         self._keep = (list(rhos), list(phis))
-        ra = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
-        pa = (ctypes.c_void_p * n)(*[p.data_ptr() for p in phis])
+        ra = (ctypes.c_void_p * n)(*rp)
+        pa = (ctypes.c_void_p * n)(*pp)
         _check(lib().yyg_batch_solve(self._h, ra, pa, _stream_handle(stream)), "yyg_batch_solve")
 
     def autotune(self, stream=None):

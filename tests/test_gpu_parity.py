@@ -121,6 +121,13 @@ N_F64_VARIANTS = 14
 N_PHI_DIRECT = 6
 N_PHI_FOLD = 8
 N_PHI_LEAN = 4   # phi synthesis only
+N_X4 = 12        # tiles on the 4x4x4 FP64 MFMA, every phase (last in each phase's range)
+
+
+def _x4_base(phase):
+    if phase in (0, 4):
+        return 2 * N_F64_VARIANTS + N_PHI_DIRECT + N_PHI_FOLD + (N_PHI_LEAN if phase == 4 else 0)
+    return 2 * N_F64_VARIANTS
 
 
 @pytest.mark.parametrize("case", [
@@ -358,9 +365,9 @@ def test_separable_every_phase_variant(phase):
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
     # every tile with one and with three stages of loads in flight; the phi
-    # phases also every LDS-basis variant, unfolded and folded
-    for v in range(2 * N_F64_VARIANTS + (N_PHI_DIRECT + N_PHI_FOLD if phase in (0, 4) else 0)
-                   + (N_PHI_LEAN if phase == 4 else 0)):
+    # phases also every LDS-basis variant, unfolded and folded; every phase
+    # the 4x4x4-MFMA tiles
+    for v in range(_x4_base(phase) + N_X4):
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
