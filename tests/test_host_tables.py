@@ -184,7 +184,7 @@ def test_radial_recurrence_reproduces_direct_sums(r_edges):
         assert np.max(np.abs(U[:, :, : l + 1] - ref[:, :, : l + 1]) / scale) < 1e-12, l
 
 
-@pytest.mark.parametrize("lmax", [4, 25])
+@pytest.mark.parametrize("lmax", [4, 25, 64])
 def test_rotation_blocks_rotate_the_harmonics(lmax):
     """D_l maps the normalised real harmonics (built here from the oracle's
     P_l^m and N^(lm)) at a point x to their values at R x, R the Yin <-> Yang

@@ -456,3 +456,21 @@ def test_golden_small_potential():
     vals = O.solve_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
                            desc["delta_phi"], desc["lmax"], desc["G"], rho, samples)
     np.testing.assert_allclose(vals, np.array(gold["phi"]), rtol=1e-13)
+
+
+def test_potential_at_chunking_is_exact():
+    """The synthesis processes points in bounded chunks; chunk boundaries do
+    not change any value (points are independent)."""
+    d = W.describe("small")
+    rho = W.density(d)
+    th, ph = O.patch_edges(d["n_theta"], d["n_phi"], d["delta_theta"], d["delta_phi"])
+    w = O.overlap_weights(th, ph, d["delta_theta"], d["delta_phi"])
+    AC, AS = O.moments(rho, w, O.theta_integrals(th, d["lmax"]), *O.phi_integrals(ph, d["lmax"]))
+    UC, US = O.radial_sums(AC, AS, d["r_edges"])
+    rng = np.random.default_rng(9)
+    k = 5000
+    p, n = rng.integers(0, 2, k), rng.integers(0, len(d["r_edges"]) - 1, k)
+    t, f = rng.uniform(0.8, 2.3, k), rng.uniform(-2.3, 2.3, k)
+    a = O.potential_at(UC, US, 1.0, p, n, t, f, chunk=777)
+    b = O.potential_at(UC, US, 1.0, p, n, t, f, chunk=10 ** 9)
+    assert np.array_equal(a, b)
