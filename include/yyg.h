@@ -171,6 +171,28 @@ int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stre
  * YYG_ERR_NOT_READY before any upload. */
 int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *stream);
 
+/* Allocation-free separable solve, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels as yyg_solve in the separable form
+ * (FP64), with every intermediate (phi and theta transform outputs,
+ * moments, rotated moments, radial sums) in a fixed device scratch array of
+ * 64 MiB that the library holds on each GPU it runs on until the process
+ * ends, instead of the plan's own work buffers.  `rho` and `phi` are device
+ * arrays in the layout of yyg_upload_rho / yyg_solve (the density is read
+ * directly; no upload is needed or used); asynchronous on `stream`; no
+ * allocation, no host synchronisation, no events.  YYG_ERR_NOT_READY when
+ * the plan is not in the separable form (yyg_set_method);
+ * YYG_ERR_UNSUPPORTED when its intermediates (sizes below) exceed the
+ * scratch array; the result equals
+ * yyg_solve's bit for bit.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (concurrent streams or threads)
+ * race and must be serialised by the caller.  yyg_get_moments keeps
+ * reporting the last yyg_solve.  The intermediates take
+ * 8 [2 (2L+1) n_theta M + (2L+1)(L+1) M + P' M Q] bytes (M = P n_r rows,
+ * P' = 2 on a Yin-Yang grid, 1 on the polar grid), each part rounded up to
+ * 256 bytes: e.g. 48 MB at n_r 400, 2 deg, lmax 25. */
+int yyg_solve_noalloc(yyg_grid *g, const double *rho, double *phi, void *stream);
+
 /* Debug/test export after a synchronised solve: the angular moments
  * A[p][i][q] of Eqs. (26)-(27) (A_C in cos columns, A_S in sin columns) for
  * patch p and radial cell i, unnormalised as the paper defines them.  Host

@@ -343,6 +343,43 @@ hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   return yyg::launch_gemm_f64_sep(v, r, deep, S.args, s);
 }
 
+// Work buffers of the separable form: the plan's own, or (allocation-free
+// solve) regions of the device scratch array.
+struct SepWork {
+  double *X2, *V, *Ut, *At, *Ahat;
+};
+
+SepWork sep_work(const yyg_grid *g) { return {g->sep.X2, g->sep.V, g->sep.Ut, g->sep.At, g->d_Ahat}; }
+
+// Point every launch argument of the separable form at the work buffers w.
+void sep_bind_work(yyg_grid *g, const SepWork &w) {
+  auto &S = g->sep;
+  S.X2 = w.X2;
+  S.V = w.V;
+  S.Ut = w.Ut;
+  S.At = w.At;
+  g->d_Ahat = w.Ahat;
+  S.phi_ana.C = S.phi_ana_f.C = w.X2;
+  S.phi_ana_d.C = S.phi_ana_fd.C = w.X2;
+  S.phi_syn.A = S.phi_syn_f.A = w.V;
+  S.phi_syn_d.X = S.phi_syn_fd.X = w.V;
+  S.phi_syn_l.V = w.V;
+  S.args.X2 = w.X2;
+  S.args.Ut = w.Ut;
+  S.args.Ahat = w.Ahat;
+  S.args.At = w.At;
+  S.args.V = w.V;
+}
+
+// Doubles of the separable form's work buffers, each region rounded up to
+// 256 bytes.
+size_t sep_work_doubles(const yyg_grid *g) {
+  const long M = (long)g->n_patch * g->n_r, nmc = 2L * g->L + 1;
+  auto r32 = [](long v) { return (size_t)((v + 31) / 32 * 32); };
+  return 2 * r32(nmc * g->n_t * M) + r32(nmc * (g->L + 1) * M) + (g->n_patch == 2 ? r32(M * g->Q) : 0) +
+         r32(M * g->Q);
+}
+
 // Point the phi phases at this solve's density and potential (kernel
 // arguments: nothing is copied).
 int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
@@ -1280,6 +1317,49 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(tmp);
   }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  return YYG_OK;
+}
+
+int yyg_solve_noalloc(yyg_grid *g, const double *rho, double *phi, void *stream) {
+  if (!g || !rho || !phi) return YYG_ERR_INVALID_ARG;
+  if (g->method != YYG_METHOD_SEPARABLE || !g->sep.ready) return YYG_ERR_NOT_READY;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return YYG_ERR_DEVICE;
+  double *base = nullptr;
+  size_t bytes = 0;
+  if (yyg::scratch_region(g->device, &base, &bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  if (sep_work_doubles(g) * sizeof(double) > bytes) return YYG_ERR_UNSUPPORTED;
+  // carve the work buffers out of the scratch array; every one of them is
+  // written in full by its phase before any later phase reads it, so none
+  // needs clearing
+  const long M = (long)g->n_patch * g->n_r, nmc = 2L * g->L + 1;
+  auto r32 = [](long v) { return (v + 31) / 32 * 32; };
+  SepWork w{};
+  double *p = base;
+  w.X2 = p, p += r32(nmc * g->n_t * M);
+  w.V = p, p += r32(nmc * g->n_t * M);
+  w.Ut = p, p += r32(nmc * (g->L + 1) * M);
+  w.At = g->n_patch == 2 ? p : nullptr, p += g->n_patch == 2 ? r32(M * g->Q) : 0;
+  w.Ahat = p;
+  const SepWork own = sep_work(g);
+  const bool timing = g->timing, cols = g->ahat_cols;
+  g->timing = false;  // no events: nothing is created
+  sep_bind_work(g, w);
+  hipStream_t s = as_stream(stream);
+  hipError_t e = hipSuccess;
+  if (sep_set_pointers(g, rho, phi, s) != YYG_OK) e = hipErrorInvalidValue;
+  if (e == hipSuccess) e = sep_solve(g, s);
+  sep_bind_work(g, own);
+  g->timing = timing;
+  g->ahat_cols = cols;  // the plan's moments buffer still holds the last yyg_solve's
+  sep_set_pointers(g, nullptr, nullptr, s);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;

@@ -260,4 +260,9 @@ int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n);
 // Split-K factor for an output of `tiles` block tiles and K columns.
 int choose_split(long tiles, long K);
 
+// Allocation-free solve: the fixed-size device scratch array of the current
+// device (yyg_noalloc.hip).
+constexpr size_t kScratchBytes = 64UL << 20;
+hipError_t scratch_region(int device, double **ptr, size_t *bytes);
+
 }  // namespace yyg

@@ -29,7 +29,7 @@ EXPORTS = [
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
     "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind", "yyg_sep_config", "yyg_sep_info",
-    "yyg_sep_kernel", "yyg_sep_phase",
+    "yyg_sep_kernel", "yyg_sep_phase", "yyg_solve_noalloc",
 ]
 
 
@@ -91,6 +91,7 @@ def lib():
         L.yyg_sep_info.argtypes = [vp, ctypes.POINTER(i), i]
         L.yyg_sep_kernel.argtypes = [vp, i, ctypes.c_char_p, ctypes.c_size_t]
         L.yyg_sep_phase.argtypes = [vp, i, vp, vp]
+        L.yyg_solve_noalloc.argtypes = [vp, vp, vp, vp]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -231,6 +232,16 @@ class Grid:
         else:
             ptr = device_array(phi, self.shape, "solve", self.device)
             _check(lib().yyg_solve(self._h, ctypes.c_void_p(ptr), 1, p, _stream_handle(stream)), "yyg_solve")
+        return phi
+
+    def solve_noalloc(self, rho, phi, stream=None):
+        """yyg_solve_noalloc: separable FP64 solve of device `rho` into
+        device `phi` with the intermediates in the library's fixed scratch
+        array (no allocation)."""
+        rp = device_array(rho, self.shape, "solve_noalloc rho", self.device)
+        pp = device_array(phi, self.shape, "solve_noalloc phi", self.device)
+        _check(lib().yyg_solve_noalloc(self._h, ctypes.c_void_p(rp), ctypes.c_void_p(pp), _stream_handle(stream)),
+               "yyg_solve_noalloc")
         return phi
 
     def autotune(self, precision="fp64", stream=None):
