@@ -290,10 +290,13 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * condition under which the tile variants of the phi phases fold too); the
  * phi synthesis also [2V + 14, 2V + 18), folded kernels in which every wave
  * loads its matrix-core operands straight from memory (no LDS; the same
- * mirror-symmetry condition).  Every phase then takes X further variants
- * (X = 12 in this build) at the end of its range: tiles on the 4x4x4 FP64
- * matrix instruction, for the phi phases folded whenever the grid is
- * mirror-symmetric.
+ * mirror-symmetry condition).  Every phase then takes 12 further variants
+ * at the end of its range: tiles on the 4x4x4 FP64 matrix instruction, for
+ * the phi phases folded whenever the grid is mirror-symmetric; after them
+ * the phi analysis takes 8 and the phi synthesis 6 folded variants in which
+ * one block covers both halves of its rows (the analysis reading each
+ * density value once, the synthesis its tiles ordered along the cells;
+ * mirror-symmetric grids only, else YYG_ERR_UNSUPPORTED).
  * Needs the separable form built (yyg_set_method); synchronises the
  * device.  For tests and expert tuning; yyg_autotune chooses all of them. */
 int yyg_sep_config(yyg_grid *g, int phase, int variant);

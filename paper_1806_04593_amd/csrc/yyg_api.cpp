@@ -114,6 +114,10 @@ struct yyg_grid {
     double *WF = nullptr;    // folded analysis basis [n_t][2][L+1][ldkh]: even (cos) / odd (sin) halves
     double *TF = nullptr;    // folded synthesis basis [h][ldtf]: cos m at m, sin m at ks + m - 1
     yyg::GemmF64Args phi_ana_f{}, phi_syn_f{};
+    // folded analysis, both halves per block: basis rows cos m at slot m
+    // (m <= L), sin m at slot ks + m - 1, [n_t][ks + L][ldkh], exact weights
+    double *WFAB = nullptr;
+    yyg::GemmF64Args phi_ana_ab{};
     // folded LDS-basis kernels: the cos / sin halves without padding each to
     // the tile width
     double *WFD = nullptr;   // analysis basis [n_t][kca + 16 ceil(L/16)][h]: cos m at row m, sin m at kca + m - 1
@@ -177,7 +181,7 @@ void free_grid(yyg_grid *g) {
   {
     void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2,    g->sep.P2, g->sep.Drot, g->sep.X2,
                  g->sep.V,   g->sep.Ut,   g->sep.coefS, g->sep.At, g->sep.WF, g->sep.TF,
-                 g->sep.WFD, g->sep.TFD, g->sep.BK};
+                 g->sep.WFD, g->sep.TFD, g->sep.BK, g->sep.WFAB};
     for (void *x : b)
       if (x) (void)hipFree(x);
   }
@@ -306,11 +310,11 @@ int sep_x4_base(int r) {
   return r == 0 ? v + phi : r == 4 ? v + phi + yyg::phi_lean_variant_count() : v;
 }
 
-int sep_variant_count(int r) { return sep_x4_base(r) + yyg::x4_variant_count(); }
+int sep_variant_count(int r) { return sep_x4_base(r) + yyg::x4_variant_count(r); }
 
 bool sep_fold_variant(int r, int v) {
-  return (r == 0 || r == 4) && v >= 2 * yyg::gemm_f64_variant_count() + yyg::phi_direct_variant_count() &&
-         v < sep_x4_base(r);
+  if (v >= sep_x4_base(r)) return yyg::x4_fold_only(r, v - sep_x4_base(r)) != 0;
+  return (r == 0 || r == 4) && v >= 2 * yyg::gemm_f64_variant_count() + yyg::phi_direct_variant_count();
 }
 
 int sep_set_variant(yyg_grid *g, int r, int v) {
@@ -327,7 +331,7 @@ hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   if (S.var[r] >= sep_x4_base(r)) {
     if (r == 2 && g->n_patch != 2) return hipSuccess;
     const yyg::GemmF64Args &phi = r == 0 ? (S.fold ? S.phi_ana_f : S.phi_ana) : (S.fold ? S.phi_syn_f : S.phi_syn);
-    return yyg::launch_x4_sep_phase(S.var[r] - sep_x4_base(r), r, S.fold, phi, S.args, s);
+    return yyg::launch_x4_sep_phase(S.var[r] - sep_x4_base(r), r, S.fold, phi, S.phi_ana_ab, S.args, s);
   }
   if (r == 4 && S.var[r] >= 2 * nv + nd + nf) return yyg::launch_phi_syn_lean(S.var[r] - 2 * nv - nd - nf, S.phi_syn_l, s);
   if (sep_fold_variant(r, S.var[r]))
@@ -359,7 +363,7 @@ void sep_bind_work(yyg_grid *g, const SepWork &w) {
   S.Ut = w.Ut;
   S.At = w.At;
   g->d_Ahat = w.Ahat;
-  S.phi_ana.C = S.phi_ana_f.C = w.X2;
+  S.phi_ana.C = S.phi_ana_f.C = S.phi_ana_ab.C = w.X2;
   S.phi_ana_d.C = S.phi_ana_fd.C = w.X2;
   S.phi_syn.A = S.phi_syn_f.A = w.V;
   S.phi_syn_d.X = S.phi_syn_fd.X = w.V;
@@ -388,6 +392,7 @@ int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
   g->sep.phi_ana_d.X = rho;
   g->sep.phi_syn_d.C = phi;
   g->sep.phi_ana_f.A = rho;
+  g->sep.phi_ana_ab.A = rho;
   g->sep.phi_syn_f.C = phi;
   g->sep.phi_ana_fd.X = rho;
   g->sep.phi_syn_fd.C = phi;
@@ -404,7 +409,7 @@ int sep_build(yyg_grid *g) {
   S.ldm = round_up(nmc, 16);
   S.ldl = round_up(L + 1, 16);
   if (yyg::radial_scan_q_lds(g->n_r, g->n_patch) > yyg::kScanQMaxLds) return YYG_ERR_UNSUPPORTED;
-  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD, BK;
+  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD, BK, WFAB;
   try {
     coef.resize((size_t)4 * g->n_r * (L + 1));
     yyg::radial_coefficients(g->n_r, g->r_edges.data(), L, coef.data());
@@ -477,6 +482,16 @@ int sep_build(yyg_grid *g) {
           TF[(size_t)k * S.ldtf + m] = trig[(size_t)k * S.ldm + (m ? 2 * m - 1 : 0)];
           if (m > 0) TF[(size_t)k * S.ldtf + S.ks + m - 1] = trig[(size_t)k * S.ldm + 2 * m];
         }
+      // both halves in one basis for kGemmFoldAB: slot s < ks the cos half,
+      // ks <= s < ks + L the sin half
+      WFAB.assign((size_t)nt * (S.ks + L) * S.ldkh, 0.0);
+      for (int j = 0; j < nt; ++j)
+        for (int m = 0; m <= L; ++m)
+          for (int k = 0; k < h; ++k) {
+            const size_t base = (size_t)j * (S.ks + L);
+            WFAB[(base + m) * S.ldkh + k] = WF[(((size_t)j * 2 + 0) * (L + 1) + m) * S.ldkh + k];
+            if (m > 0) WFAB[(base + S.ks + m - 1) * S.ldkh + k] = WF[(((size_t)j * 2 + 1) * (L + 1) + m - 1) * S.ldkh + k];
+          }
       // the same for the folded LDS-basis kernels: the cos half padded to a
       // multiple of 16 rows (analysis) / 4 slots (synthesis), the sin half
       // after it
@@ -542,6 +557,7 @@ int sep_build(yyg_grid *g) {
   if (st == YYG_OK && S.fold) st = dmalloc(&S.WFD, WFD.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.TFD, TFD.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.BK, BK.size());
+  if (st == YYG_OK && S.fold) st = dmalloc(&S.WFAB, WFAB.size());
   if (st != YYG_OK) return st;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
@@ -559,6 +575,7 @@ int sep_build(yyg_grid *g) {
     chk(hipMemcpy(S.WFD, WFD.data(), WFD.size() * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemcpy(S.TFD, TFD.data(), TFD.size() * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemcpy(S.BK, BK.data(), BK.size() * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(S.WFAB, WFAB.data(), WFAB.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -581,6 +598,15 @@ int sep_build(yyg_grid *g) {
   S.phi_ana_f.b_batch = (long)(L + 1) * S.ldkh;
   S.phi_ana_f.fold_k = np;
   S.phi_ana_f.fold_mc = nmc;
+  // both halves per block: slots ks + L, the same density rows and output
+  S.phi_ana_ab = yyg::GemmF64Args{(int)M, (int)(S.ks + L), (int)S.h, nullptr, (long)nt * np, S.WFAB, S.ldkh, S.X2, MJ,
+                                  M, kround(S.h), 1};
+  S.phi_ana_ab.batch = nt;
+  S.phi_ana_ab.a_batch = np;
+  S.phi_ana_ab.b_batch = (long)(S.ks + L) * S.ldkh;
+  S.phi_ana_ab.k_split = (int)S.ks;
+  S.phi_ana_ab.fold_k = np;
+  S.phi_ana_ab.fold_mc = nmc;
   S.phi_syn_f = yyg::GemmF64Args{(int)M, (int)S.h, (int)S.ldtf, S.V, MJ, S.TF, S.ldtf, nullptr, (long)nt * np, np,
                                  kround(S.ldtf), 1};
   S.phi_syn_f.batch = nt;
@@ -1629,6 +1655,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     g->sep.phi_ana_d.X = nullptr;
     g->sep.phi_syn_d.C = nullptr;
     g->sep.phi_ana_f.A = nullptr;
+    g->sep.phi_ana_ab.A = nullptr;
     g->sep.phi_syn_f.C = nullptr;
     g->sep.phi_ana_fd.X = nullptr;
     g->sep.phi_syn_fd.C = nullptr;

@@ -54,6 +54,15 @@ struct GemmF64Args {
 //               covers 16 consecutive rows, for C stored column-major
 //  kGemmAccInit (with the general epilogue) the accumulators start from
 //               Cin (same strides as C) instead of zero
+//  kGemmFoldAB  phi analysis folded, both halves in one block: batched
+//               problem z = j reads A(m, k) = X(m, k) +/- X(m, fold_k - 1 - k)
+//               (LDS holds both), B rows (slots) below k_split are the cos
+//               half (cos m at slot m) and take the sum, the rest the sin half
+//               (sin m at slot k_split + m - 1) and take the difference; slot
+//               s stores azimuthal column mc (if mc < fold_mc) of the
+//               column-major C + j c_split_stride
+//  kGemmNFast   strided batch: a problem's tiles are numbered N-fastest (the
+//               blocks that share an A tile run together and share L2)
 //  kGemmX4      v_mfma_f64_4x4x4f64 instead of the 16x16x4 form: measured on
 //               MI355X it runs at ~92% of the FP64 matrix peak where the
 //               16x16x4 form stops at ~62%, for four times the operand
@@ -69,7 +78,9 @@ enum {
   kGemmFoldC = 256,
   kGemmDT = 512,
   kGemmAccInit = 1024,
-  kGemmX4 = 2048
+  kGemmX4 = 2048,
+  kGemmFoldAB = 4096,
+  kGemmNFast = 8192
 };
 // role offset of the kGemmDeep forms of the batched roles
 constexpr int kRoleDeep = 16;
@@ -132,9 +143,14 @@ hipError_t launch_phi_syn_lean(int variant, const PhiLeanArgs &a, hipStream_t s)
 // x4_variant_count() shapes; phase 0 / 4 are the phi transforms (folded
 // when `fold`, as launch_gemm_f64_batched roles 2 / 3, else roles 0 / 1),
 // phases 1-3 as launch_gemm_f64_sep.
-int x4_variant_count();
-hipError_t launch_x4_sep_phase(int variant, int phase, bool fold, const GemmF64Args &phi, const SepPhaseArgs &a,
-                               hipStream_t s);
+// x4_variant_count(phase) of them: the generic tiles first, then (phases 0
+// and 4, mirror-symmetric grids only: x4_fold_only) the folded phi
+// transforms with both halves per block, phase 0 reading phi_ab
+// (kGemmFoldAB), phase 4 phi (kGemmFoldC, tiles cell-fastest).
+int x4_variant_count(int phase);
+int x4_fold_only(int phase, int variant);
+hipError_t launch_x4_sep_phase(int variant, int phase, bool fold, const GemmF64Args &phi, const GemmF64Args &phi_ab,
+                               const SepPhaseArgs &a, hipStream_t s);
 int x4_kernel_name(int variant, int phase, bool fold, char *buf, size_t n);
 
 // phase 1 theta analysis, 2 rotation (two patches), 3 theta synthesis;

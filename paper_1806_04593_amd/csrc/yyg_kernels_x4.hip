@@ -107,19 +107,73 @@ const X4Variant kX4Variants[] = {
     YYG_X4_VARIANT(128, 32, 4, 1, 0, 0), YYG_X4_VARIANT(64, 32, 2, 2, 0, 1),  YYG_X4_VARIANT(128, 32, 4, 2, 0, 1),
     YYG_X4_VARIANT(64, 64, 4, 1, 1, 0),  YYG_X4_VARIANT(64, 80, 4, 1, 1, 0),  YYG_X4_VARIANT(64, 32, 2, 2, 1, 1),
 };
+constexpr int kNX4 = (int)(sizeof(kX4Variants) / sizeof(kX4Variants[0]));
+
+// Folded phi transforms with one block over both halves of its rows:
+//  phase 0: kGemmFoldAB, every basis slot (cos half then sin half) in one
+//           tile of BN >= the slots, so the density is read once;
+//  phase 4: kGemmFoldC with the tiles numbered cell-fastest, so the blocks
+//           that read the same coefficient rows run together.
+// X4 = 1: the 4x4x4 MFMA (rows on the four-wide side), else 16x16x4 (for
+// phase 0 with the transposed tile).
+template <int PHASE, int BM, int BN, int WGM, int WGN, int X4, int DEEP>
+hipError_t launch_phi_both_t(const GemmF64Args &phi, hipStream_t s) {
+  if (phi.M <= 0 || phi.N <= 0 || phi.batch <= 0) return hipSuccess;
+  constexpr int D = DEEP ? kGemmDeep : 0;
+  constexpr int XM = X4 ? kGemmX4 : 0;
+  if constexpr (PHASE == 0)
+    return launch_batched_x4<BM, BN, WGM, WGN, XM | kGemmCTrans | kGemmFoldAB | (X4 ? 0 : kGemmDT) | D>(phi, 0, s);
+  else
+    return launch_batched_x4<BM, BN, WGM, WGN, XM | kGemmATrans | kGemmFoldC | kGemmNFast | D>(phi, 1, s);
+}
+
+typedef hipError_t (*both_fn)(const GemmF64Args &, hipStream_t);
+struct BothVariant {
+  int bm, bn, wm, wn, x4, deep;
+  both_fn fn;
+};
+#define YYG_BOTH_VARIANT(PH, BM, BN, WM, WN, X4, DEEP) \
+  { BM, BN, WM, WN, X4, DEEP, launch_phi_both_t<PH, BM, BN, WM, WN, X4, DEEP> }
+
+const BothVariant kPhiAnaBoth[] = {
+    YYG_BOTH_VARIANT(0, 64, 144, 4, 1, 1, 0), YYG_BOTH_VARIANT(0, 32, 144, 2, 1, 1, 0),
+    YYG_BOTH_VARIANT(0, 64, 96, 4, 1, 1, 0),  YYG_BOTH_VARIANT(0, 64, 64, 4, 1, 1, 0),
+    YYG_BOTH_VARIANT(0, 64, 144, 4, 1, 0, 0), YYG_BOTH_VARIANT(0, 64, 96, 4, 1, 0, 0),
+    YYG_BOTH_VARIANT(0, 64, 64, 4, 1, 0, 0),  YYG_BOTH_VARIANT(0, 64, 144, 4, 1, 1, 1),
+};
+const BothVariant kPhiSynBoth[] = {
+    YYG_BOTH_VARIANT(4, 64, 64, 4, 1, 1, 0),  YYG_BOTH_VARIANT(4, 128, 64, 4, 1, 1, 0),
+    YYG_BOTH_VARIANT(4, 64, 128, 4, 1, 1, 0), YYG_BOTH_VARIANT(4, 128, 48, 4, 1, 0, 0),
+    YYG_BOTH_VARIANT(4, 64, 64, 2, 2, 0, 0),  YYG_BOTH_VARIANT(4, 128, 64, 2, 2, 0, 0),
+};
+constexpr int kNAna = (int)(sizeof(kPhiAnaBoth) / sizeof(kPhiAnaBoth[0]));
+constexpr int kNSyn = (int)(sizeof(kPhiSynBoth) / sizeof(kPhiSynBoth[0]));
 
 }  // namespace
 
-int x4_variant_count() { return (int)(sizeof(kX4Variants) / sizeof(kX4Variants[0])); }
+int x4_variant_count(int phase) { return kNX4 + (phase == 0 ? kNAna : phase == 4 ? kNSyn : 0); }
 
-hipError_t launch_x4_sep_phase(int variant, int phase, bool fold, const GemmF64Args &phi, const SepPhaseArgs &a,
-                               hipStream_t s) {
-  if (variant < 0 || variant >= x4_variant_count() || phase < 0 || phase > 4) return hipErrorInvalidValue;
-  return kX4Variants[variant].fn(phase, fold, phi, a, s);
+int x4_fold_only(int phase, int variant) { return variant >= kNX4 && variant < x4_variant_count(phase); }
+
+hipError_t launch_x4_sep_phase(int variant, int phase, bool fold, const GemmF64Args &phi, const GemmF64Args &phi_ab,
+                               const SepPhaseArgs &a, hipStream_t s) {
+  if (variant < 0 || variant >= x4_variant_count(phase) || phase < 0 || phase > 4) return hipErrorInvalidValue;
+  if (variant < kNX4) return kX4Variants[variant].fn(phase, fold, phi, a, s);
+  if (!fold) return hipErrorInvalidValue;
+  return phase == 0 ? kPhiAnaBoth[variant - kNX4].fn(phi_ab, s) : kPhiSynBoth[variant - kNX4].fn(phi, s);
 }
 
 int x4_kernel_name(int variant, int phase, bool fold, char *buf, size_t n) {
-  if (variant < 0 || variant >= x4_variant_count() || phase < 0 || phase > 4) return -1;
+  if (variant < 0 || variant >= x4_variant_count(phase) || phase < 0 || phase > 4) return -1;
+  if (variant >= kNX4) {
+    if (!fold) return -1;
+    const BothVariant &v = phase == 0 ? kPhiAnaBoth[variant - kNX4] : kPhiSynBoth[variant - kNX4];
+    const int xm = v.x4 ? kGemmX4 : 0, d = v.deep ? kGemmDeep : 0;
+    const int mode = phase == 0 ? xm | kGemmCTrans | kGemmFoldAB | (v.x4 ? 0 : kGemmDT) | d
+                                : xm | kGemmATrans | kGemmFoldC | kGemmNFast | d;
+    return snprintf(buf, n, "yyg::gemm_nt_f64_batched<%d, %d, %d, %d, %d, %d>", phase == 0 ? 0 : 1, v.bm, v.bn, v.wm,
+                    v.wn, mode) < 0 ? -1 : 0;
+  }
   const X4Variant &v = kX4Variants[variant];
   const int deep = v.deep ? kGemmDeep : 0;
   int mode;

@@ -59,6 +59,8 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr bool BT = (MODE & kGemmBTrans) != 0;
   constexpr bool ACCINIT = (MODE & kGemmAccInit) != 0;
   constexpr bool FOLDA = (MODE & kGemmFoldA) != 0;
+  constexpr bool FOLDAB = (MODE & kGemmFoldAB) != 0;
+  constexpr bool FLD = FOLDA || FOLDAB;  // the loads keep front and mirror values
   constexpr bool FOLDC = (MODE & kGemmFoldC) != 0;
   constexpr bool DT = (MODE & kGemmDT) != 0;
   constexpr bool X4 = (MODE & kGemmX4) != 0;
@@ -66,6 +68,8 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   static_assert(!DT || !FOLDC, "the folded synthesis stores rows");
   static_assert(!FOLDA || (BATCH && CT && !AT && !GEN), "folded analysis: batched, row-major A, C column-major");
   static_assert(!FOLDC || (BATCH && AT && !CT && !GEN), "folded synthesis: batched, A k-major");
+  static_assert(!FOLDAB || (BATCH && CT && !AT && !GEN && !FOLDA && (X4 ? !DT : DT)),
+                "both folded halves: batched, row-major A, C column-major, rows on the coalesced side");
 
   const int M = g.M, N = g.N, K = g.K;
   // FOLDA: problem z = 2 zj + group (group 0 the even, 1 the odd half), so
@@ -94,6 +98,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr int EA = RUN_A ? (BM * kBK) / NT : (BM * kBK + NT - 1) / NT;
   constexpr int EB = RUN_B ? (BN * kBK) / NT : (BN * kBK + NT - 1) / NT;
   __shared__ double As[2][BM * kLDK];
+  __shared__ double Ao[FOLDAB ? 2 : 1][FOLDAB ? BM * kLDK : 1];  // FOLDAB: the odd half of A
   __shared__ double Bs[2][BN * kLDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -168,7 +173,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr int PF = (MODE & kGemmDeep) ? kDeepPF : kPF;
   // FOLDA keeps the raw front and mirror values (ra[i], ra[EA + i]) until
   // the stash: folding them at load time would wait for the loads there
-  constexpr int EAR = FOLDA ? 2 * EA : EA;
+  constexpr int EAR = FLD ? 2 * EA : EA;
   double ra[PF][EAR], rb[PF][EB];
   // run mapping: this thread's row and first column
   const int arow = RUN_A ? tid / (kBK / EA) : 0, acol = RUN_A ? (tid % (kBK / EA)) * EA : 0;
@@ -184,7 +189,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   // half of a row about its middle
   auto aload = [&](double (&ra)[EAR], int i, const double *row, int kc) {
     ra[i] = row[kc];
-    if constexpr (FOLDA) ra[EA + i] = row[g.fold_k - 1 - kc];
+    if constexpr (FLD) ra[EA + i] = row[g.fold_k - 1 - kc];
   };
   // FOLDA, a run of EA (even) values per thread: pairs of neighbours as one
   // 16-byte load each at the front and at the mirror.  K = h < fold_k, so a
@@ -203,9 +208,11 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
       ra[EA + i + 1] = b.x;
     }
   };
-  auto aval = [&](const double (&ra)[EAR], int i) { return FOLDA ? ra[i] + fsign * ra[(FOLDA ? EA : 0) + i] : ra[i]; };
+  auto aval = [&](const double (&ra)[EAR], int i) { return FLD ? ra[i] + fsign * ra[(FLD ? EA : 0) + i] : ra[i]; };
+  // FOLDAB: the odd half, front minus mirror
+  auto aval_o = [&](const double (&ra)[EAR], int i) { return FLD ? ra[i] - ra[(FLD ? EA : 0) + i] : ra[i]; };
   auto load = [&](double (&ra)[EAR], double (&rb)[EB], int k0) {
-    if constexpr (RUN_A && FOLDA && EA % 2 == 0) {
+    if constexpr (RUN_A && FLD && EA % 2 == 0) {
       apairs(ra, pa, k0);
     } else if constexpr (RUN_A) {
 #pragma unroll
@@ -249,8 +256,11 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   auto stash = [&](const double (&ra)[EAR], const double (&rb)[EB], int buf, int k0) {
     if constexpr (RUN_A) {
 #pragma unroll
-      for (int i = 0; i < EA; ++i)
-        As[buf][arow * kLDK + acol + i] = (va && k0 + acol + i < kend) ? aval(ra, i) : 0.0;
+      for (int i = 0; i < EA; ++i) {
+        const bool ok = va && k0 + acol + i < kend;
+        As[buf][arow * kLDK + acol + i] = ok ? aval(ra, i) : 0.0;
+        if constexpr (FOLDAB) Ao[FOLDAB ? buf : 0][arow * kLDK + acol + i] = ok ? aval_o(ra, i) : 0.0;
+      }
     } else if constexpr (AT) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
@@ -261,7 +271,11 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        if (e < BM * kBK) As[buf][row * kLDK + e % kBK] = (m0 + row < M && kk < kend) ? aval(ra, i) : 0.0;
+        if (e < BM * kBK) {
+          const bool ok = m0 + row < M && kk < kend;
+          As[buf][row * kLDK + e % kBK] = ok ? aval(ra, i) : 0.0;
+          if constexpr (FOLDAB) Ao[FOLDAB ? buf : 0][row * kLDK + e % kBK] = ok ? aval_o(ra, i) : 0.0;
+        }
       }
     }
     if constexpr (RUN_B) {
@@ -290,12 +304,17 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   auto compute4 = [&](int buf, bool second) {
     const double *__restrict__ s4p = DT ? Bs[buf] : As[buf];
     const double *__restrict__ s16p = DT ? As[buf] : Bs[buf];
+    const double *__restrict__ s4o = Ao[FOLDAB ? buf : 0];
     const int b4 = DT ? wn * WN : wm * WM, b16 = DT ? wm * WM : wn * WN;
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
-      double rf[R4], sf[S16];
+      double rf[R4], sf[S16], ro[FOLDAB ? R4 : 1];
 #pragma unroll
       for (int r = 0; r < R4; ++r) rf[r] = s4p[(b4 + 4 * r + xv) * kLDK + 4 * xu + s4];
+      if constexpr (FOLDAB) {
+#pragma unroll
+        for (int r = 0; r < R4; ++r) ro[FOLDAB ? r : 0] = s4o[(b4 + 4 * r + xv) * kLDK + 4 * xu + s4];
+      }
 #pragma unroll
       for (int c = 0; c < S16; ++c) sf[c] = s16p[(b16 + 16 * c + 4 * xb + xv) * kLDK + 4 * xu + s4];
       if (FOLDC && second) {  // uniform: the whole stage is past k_split
@@ -309,19 +328,28 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
         for (int r = 0; r < R4; ++r)
 #pragma unroll
-          for (int c = 0; c < S16; ++c) acc4[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(rf[r], sf[c], acc4[r][c], 0, 0, 0);
+          for (int c = 0; c < S16; ++c) {
+            // FOLDAB: slot tiles at or past k_split are the odd half (uniform)
+            const double a = (FOLDAB && n0 + b16 + 16 * c >= g.k_split) ? ro[FOLDAB ? r : 0] : rf[r];
+            acc4[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, sf[c], acc4[r][c], 0, 0, 0);
+          }
       }
     }
   };
   auto compute16 = [&](int buf, bool second) {
     // Each lane holds four consecutive k of its row; MFMA step s uses the
     // s-th of them, so the four steps cover the 16 k of the stage once.
-    double af[TIa][4], bf[TJa][4];
+    double af[TIa][4], bf[TJa][4], ao[FOLDAB ? TIa : 1][4];
 #pragma unroll
     for (int i = 0; i < TIa; ++i) {
       const double *sp = &As[buf][(wm * (BM / WGM) + i * 16 + frow) * kLDK + fk];
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) af[i][s4] = sp[s4];
+      if constexpr (FOLDAB) {
+        const double *so = &Ao[FOLDAB ? buf : 0][(wm * (BM / WGM) + i * 16 + frow) * kLDK + fk];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) ao[FOLDAB ? i : 0][s4] = so[s4];
+      }
     }
 #pragma unroll
     for (int j = 0; j < TJa; ++j) {
@@ -345,9 +373,13 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
         for (int i = 0; i < TIa; ++i)
 #pragma unroll
-          for (int j = 0; j < TJa; ++j)
-            acc[i][j] = DT ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j][s4], af[i][s4], acc[i][j], 0, 0, 0)
-                           : __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < TJa; ++j) {
+            // FOLDAB: column tiles at or past k_split take the odd half (uniform)
+            const double a = (FOLDAB && n0 + wn * (BN / WGN) + 16 * j >= g.k_split) ? ao[FOLDAB ? i : 0][s4]
+                                                                                    : af[i][s4];
+            acc[i][j] = DT ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j][s4], a, acc[i][j], 0, 0, 0)
+                           : __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[j][s4], acc[i][j], 0, 0, 0);
+          }
     }
   };
   auto compute = [&](int buf, bool second) {
@@ -391,6 +423,10 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
         // output column -> azimuthal column: cos m (group 0, col m), sin m
         // (group 1, col m - 1)
         const int mc = max(2 * col + (fgrp ? 2 : -1), 0);
+        if (mc < g.fold_mc) C[(long)mc * ldc + row] = v;
+      } else if constexpr (FOLDAB) {
+        // slot -> azimuthal column: cos m at slot m, sin m at k_split + m - 1
+        const int mc = col < g.k_split ? max(2 * col - 1, 0) : 2 * (col - g.k_split) + 2;
         if (mc < g.fold_mc) C[(long)mc * ldc + row] = v;
       } else if constexpr (CT) {
         C[(long)col * ldc + row] = v;
@@ -444,7 +480,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_batched(GemmF64Arg
                                                                       int tiles_total) {
   const int t = xcd_tile(blockIdx.x, tiles_total);
   const int z = t / per_problem, tile = t - z * per_problem;
-  gemm_f64_tile<BM, BN, WGM, WGN, MODE | kGemmBatch>(g, tile % g.tiles_m, tile / g.tiles_m, z);
+  if constexpr ((MODE & kGemmNFast) != 0) {
+    const int tiles_n = per_problem / g.tiles_m;
+    gemm_f64_tile<BM, BN, WGM, WGN, MODE | kGemmBatch>(g, tile / tiles_n, tile % tiles_n, z);
+  } else {
+    gemm_f64_tile<BM, BN, WGM, WGN, MODE | kGemmBatch>(g, tile % g.tiles_m, tile / g.tiles_m, z);
+  }
 }
 
 // The theta phases and the moment rotation of the separable form: one

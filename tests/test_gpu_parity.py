@@ -122,6 +122,11 @@ N_PHI_DIRECT = 6
 N_PHI_FOLD = 8
 N_PHI_LEAN = 4   # phi synthesis only
 N_X4 = 12        # tiles on the 4x4x4 FP64 MFMA, every phase (last in each phase's range)
+N_BOTH = {0: 8, 4: 6}   # then the folded phi transforms with both halves per block
+
+
+def _n_x4(phase):
+    return N_X4 + N_BOTH.get(phase, 0)
 
 
 def _x4_base(phase):
@@ -393,7 +398,7 @@ def test_separable_every_phase_variant(phase):
     # every tile with one and with three stages of loads in flight; the phi
     # phases also every LDS-basis variant, unfolded and folded; every phase
     # the 4x4x4-MFMA tiles
-    for v in range(_x4_base(phase) + N_X4):
+    for v in range(_x4_base(phase) + _n_x4(phase)):
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
