@@ -8,7 +8,7 @@ separable solve), and every method / precision's rate and error against the
 FP64 oracle under `precisions` (dense FP64, FP32, BF16x3, FP16x2 and the
 separable FP64 form).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sn_core]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload binary]
                     [--precision fp64] [--no-cpu-baseline] [--no-check]
     python bench.py --workload batch64      # 64 uneven fields, batched vs sequential
 """
@@ -74,74 +74,113 @@ def measured_traffic(workload, key, kernel, name=None, tile=None):
         return None
 
 
-def cpu_baseline(desc, rho, budget_s=20.0):
-    """The oracle as it stands, on the host: full moments and radial sums,
-    then synthesis of as many (patch, shell) rows as fit in `budget_s`,
-    extrapolated to the full grid."""
-    import numpy as np
-    import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    polar = desc.get("kind") == "polar"
-    P = 1 if polar else 2
-    if polar:
-        th, ph = O.polar_edges(desc["n_theta"], desc["n_phi"])
-        w = np.ones((desc["n_theta"], desc["n_phi"]))
-    else:
-        th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
-        w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
-    T = O.theta_integrals(th, desc["lmax"])
-    C, S = O.phi_integrals(ph, desc["lmax"])
-    nR = len(desc["r_edges"]) - 1
-    nang = desc["n_theta"] * desc["n_phi"]
-    c0, t0 = time.process_time(), time.perf_counter()
-    AC, AS = O.moments(rho, w, T, C, S)
-    UC, US = O.radial_sums(AC, AS, desc["r_edges"])
-    t_front = time.perf_counter() - t0
-    tc, pc = 0.5 * (th[:-1] + th[1:]), 0.5 * (ph[:-1] + ph[1:])
-    TT, PP = np.meshgrid(tc, pc, indexing="ij")
-    tt, pp = TT.ravel(), PP.ravel()
-    rows = 0
-    t1 = time.perf_counter()
-    rng = np.random.default_rng(0)
-    while rows < P * nR:
-        p, n = int(rng.integers(P)), int(rng.integers(nR))
-        if polar:
-            O.potential_polar_at(UC, US, desc["G"], np.full(nang, n), tt, pp)
+class OracleFront:
+    """The oracle's density-dependent front of a solve (moments of Eqs. 26-27
+    and radial sums of Eqs. 19-20, in full), kept for sampled synthesis:
+    the error of every measured precision and the CPU baseline use it."""
+
+    def __init__(self, desc, rho):
+        import numpy as np
+        import oracle as O
+        self.desc, self.np = desc, np
+        self.polar = desc.get("kind") == "polar"
+        self.P = 1 if self.polar else 2
+        if self.polar:
+            th, ph = O.polar_edges(desc["n_theta"], desc["n_phi"])
+            w = np.ones((desc["n_theta"], desc["n_phi"]))
         else:
-            O.potential_at(UC, US, desc["G"], np.full(nang, p), np.full(nang, n), tt, pp)
-        rows += 1
-        if time.perf_counter() - t1 > budget_s:
-            break
-    t_rows = time.perf_counter() - t1
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    est = t_front + t_rows / rows * (P * nR)
-    # cores actually used: process CPU time over wall time (numpy's element-wise
-    # work runs on one thread whatever the BLAS pool holds)
-    return {"value": P * nR * nang / est, "unit": "cells/s", "cores": max(1, int(round(cpu / wall))),
-            "kind": "oracle",
-            "sample": (f"{desc['name']}: full moments + radial sums, synthesis of {rows} of {P * nR} "
-                       f"(patch, shell) rows; full-solve time extrapolated to {est:.1f} s"),
-            "measured_s": round(wall, 2), "cpu_over_wall": round(cpu / wall, 2), "threads_available": int(threads)}
+            th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
+            w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
+        T = O.theta_integrals(th, desc["lmax"])
+        C, S = O.phi_integrals(ph, desc["lmax"])
+        c0, t0 = time.process_time(), time.perf_counter()
+        AC, AS = O.moments(rho, w, T, C, S)
+        self.UC, self.US = O.radial_sums(AC, AS, desc["r_edges"])
+        self.front_s = time.perf_counter() - t0
+        self.front_cpu_s = time.process_time() - c0
+        self.tc, self.pc = 0.5 * (th[:-1] + th[1:]), 0.5 * (ph[:-1] + ph[1:])
+
+    def at(self, s):
+        """Phi at samples s[:, (p, n, j, k)]."""
+        import oracle as O
+        t, f = self.tc[s[:, 2]], self.pc[s[:, 3]]
+        if self.polar:
+            return O.potential_polar_at(self.UC, self.US, self.desc["G"], s[:, 1], t, f)
+        return O.potential_at(self.UC, self.US, self.desc["G"], s[:, 0], s[:, 1], t, f)
+
+    def samples(self, k, seed):
+        np = self.np
+        d = self.desc
+        nR = len(d["r_edges"]) - 1
+        rng = np.random.default_rng(seed)
+        return np.stack([rng.integers(0, self.P, k), rng.integers(0, nR, k), rng.integers(0, d["n_theta"], k),
+                         rng.integers(0, d["n_phi"], k)], 1)
 
 
-def sampled_error(desc, rho, phi_host, k=400, seed=123):
+_FRONT = None   # the oracle front shared with forked baseline workers
+
+
+def _synth_chunks(args):
+    """Baseline worker: synthesise `n` chunks of `pts` consecutive angular
+    cells of a random (patch, shell) row each, as the oracle's full solve
+    does row by row; returns the outputs done and the wall seconds."""
     import numpy as np
-    import oracle as O
-    nR = len(desc["r_edges"]) - 1
-    polar = desc.get("kind") == "polar"
+    n, pts, seed = args
+    d = _FRONT.desc
+    nang = d["n_theta"] * d["n_phi"]
     rng = np.random.default_rng(seed)
-    s = np.stack([rng.integers(0, 1 if polar else 2, k), rng.integers(0, nR, k),
-                  rng.integers(0, desc["n_theta"], k), rng.integers(0, desc["n_phi"], k)], 1)
-    if polar:
-        ref = O.solve_polar_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["lmax"], desc["G"], rho, s)
-    else:
-        ref = O.solve_sampled(desc["r_edges"], desc["n_theta"], desc["n_phi"], desc["delta_theta"],
-                              desc["delta_phi"], desc["lmax"], desc["G"], rho, s)
+    t0 = time.perf_counter()
+    for i in range(n):
+        a0 = int(rng.integers(0, max(1, nang - pts + 1)))
+        a = np.arange(a0, min(nang, a0 + pts))
+        s = np.stack([np.full(a.size, rng.integers(0, _FRONT.P)), np.full(a.size, rng.integers(0, len(d["r_edges"]) - 1)),
+                      a // d["n_phi"], a % d["n_phi"]], 1)
+        _FRONT.at(s)
+    return n * pts, time.perf_counter() - t0
+
+
+def cpu_baseline(front, budget_s=10.0, pts=4096):
+    """The oracle as it stands, timed on this host: its front (moments and
+    radial sums, in full) as computed for the error checks, then its
+    synthesis of whole chunks of outputs, on every available core at once
+    (one forked process per core, each synthesising independent chunks)
+    and on one core.  The full solve's time is the front plus the synthesis
+    of every output at the measured rate (extrapolated)."""
+    import multiprocessing as mp
+    global _FRONT
+    _FRONT = front
+    d = front.desc
+    cells = front.P * (len(d["r_edges"]) - 1) * d["n_theta"] * d["n_phi"]
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    # one core: chunks until about a third of the budget
+    done, t1 = 0, time.perf_counter()
+    i = 0
+    while time.perf_counter() - t1 < budget_s / 3 or done == 0:
+        done += _synth_chunks((1, pts, 10_000 + i))[0]
+        i += 1
+    rate1 = done / (time.perf_counter() - t1)
+    per = max(1, int(round(rate1 * (2 * budget_s / 3) / pts)))   # chunks per worker
+    ctx = mp.get_context("fork")
+    t2 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_synth_chunks, [(per, pts, w) for w in range(cores)])
+    wall = time.perf_counter() - t2
+    rate = sum(r[0] for r in res) / wall
+    est = front.front_s + cells / rate
+    est1 = front.front_s + cells / rate1
+    return {"value": cells / est, "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{d['name']}: moments and radial sums in full ({front.front_s:.1f} s, one process), then "
+                       f"{cores} processes x {per} chunks of {pts} outputs of the synthesis ({wall:.1f} s); the full "
+                       f"solve's {cells:.3g} outputs extrapolated to {est:.0f} s"),
+            "single_core": {"value": cells / est1, "cores": 1,
+                            "sample": f"{done} outputs synthesised on one core; full solve extrapolated to {est1:.0f} s"},
+            "front_s": round(front.front_s, 2), "extrapolated": True}
+
+
+def sampled_error(front, phi_host, k=400, seed=123):
+    import numpy as np
+    s = front.samples(k, seed)
+    ref = front.at(s)
     got = phi_host[s[:, 0], s[:, 1], s[:, 2], s[:, 3]]
     return float(np.max(np.abs(got - ref) / np.abs(ref)))
 
@@ -194,6 +233,50 @@ def phase_alone_ms(g, d_phi, phase, a):
     return start.elapsed_time(stop) / a.steps
 
 
+# dense autotuning times every tile and split on the plan's shapes; above
+# this many cells (the binary workload: 1.97e8) its sweep would take minutes,
+# and the dense contractions run their fixed heuristic configuration
+DENSE_TUNE_MAX_CELLS = 5e7
+
+
+def phi_roofline(head, desc, M, nang):
+    """Roofline of the dominant single-launch kernel of the separable solve,
+    the longer phi transform."""
+    k = head["kernels_ms"]
+    L2 = 2 * desc["lmax"] + 1
+    cand = {
+        "phi_analysis": (k["phi_analysis"], 2.0 * M * nang * L2, 8.0 * M * nang + 8.0 * M * desc["n_theta"] * L2),
+        "phi_synthesis": (k["phi_synthesis"], 2.0 * M * nang * L2, 8.0 * M * nang + 8.0 * M * desc["n_theta"] * L2),
+    }
+    name = max(cand, key=lambda n: cand[n][0])
+    ms_solve, flops_k, bytes_k = cand[name]
+    # the kernel's average duration: launched alone, back to back (the
+    # per-phase events inside solves add a launch gap to each)
+    ms_k = head["phase_alone_ms"][name]
+    kname = head["kernel_names"][name]
+    args = kname[kname.find("<") + 1:].rstrip(">").split(", ")
+    folded = (kname.startswith("yyg::phi_syn_lean_kernel<")
+              or (kname.startswith("yyg::phi_direct_kernel<") and args[-1] == "true")
+              or (kname.startswith("yyg::gemm_nt_f64_batched<") and int(args[-1]) & (128 | 256 | 4096)))
+    if folded:
+        flops_k /= 2.0   # folded about the central meridian: half the multiply-adds
+    tf = flops_k / (ms_k * 1e-3) / 1e12
+    gbs = bytes_k / (ms_k * 1e-3) / 1e9
+    fm, fh = tf / PEAK["fp64"], gbs / 8000.0
+    if fm >= fh:
+        roof = {"bound": "mfma", "kernel": kname, "achieved": tf, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                "frac": fm, "hbm_frac": fh}
+    else:
+        roof = {"bound": "hbm", "kernel": kname, "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                "frac": fh, "mfma_frac": fm}
+    roof["phase"] = name
+    roof["ms_per_launch"] = ms_k
+    roof["achieved_in_solve"] = (tf if roof["unit"] == "TFLOP/s" else gbs) * ms_k / ms_solve
+    roof["algorithmic_flops"] = flops_k
+    roof["algorithmic_bytes"] = bytes_k
+    return roof, name, kname
+
+
 def bench_single(a):
     import torch
 
@@ -209,6 +292,17 @@ def bench_single(a):
     M = P * nR
     log(f"[bench] workload {a.workload}: n_r={nR} {desc['n_theta']}x{desc['n_phi']} lmax={desc['lmax']}")
     rho = W.density(desc)
+    # the oracle's front and the CPU baseline run before the GPU is touched
+    # (the baseline forks worker processes)
+    front = None
+    if not (a.no_check and a.no_cpu_baseline):
+        log("[bench] oracle: moments and radial sums")
+        front = OracleFront(desc, rho)
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(front)
+        log(f"[bench] oracle {cpu['value']:.3e} cells/s on {cpu['cores']} cores")
     t0 = time.perf_counter()
     g = yyg.Grid(desc, 0)
     plan_s = time.perf_counter() - t0
@@ -216,31 +310,16 @@ def bench_single(a):
     d_rho = torch.from_numpy(rho).to("cuda:0")
     d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
     g.upload_rho(d_rho)
-    precisions = [a.precision] + [p for p in ALL_PRECISIONS if p != a.precision and not a.only]
     results = {}
-    for prec in precisions:
-        t0 = time.perf_counter()
-        g.prepare(prec)
-        if not a.no_autotune:
-            g.autotune(prec)
-        tune_s = time.perf_counter() - t0
-        info = g.plan_info(prec)
-        ms = timed_steps(g, d_phi, prec, a)
-        kms, kcnt = phase_pass(g, d_phi, prec, a)
-        avg = [float(kms[i] / max(1, kcnt[i])) for i in range(4)]
-        err = None if a.no_check else sampled_error(desc, rho, d_phi.cpu().numpy())
-        flops_syn = 2.0 * M * nang * (P * Q)
-        achieved = flops_syn / (avg[2] * 1e-3) / 1e12
-        results[prec] = {"cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
-                         "kernels_ms": {"analysis": avg[0], "radial_scan": avg[1], "synthesis": avg[2],
-                                        "operand_split": avg[3]},
-                         "synthesis_tflops": achieved, "launch": info, "prepare_tune_s": round(tune_s, 2)}
-        log(f"[bench] {prec}: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, kernels {avg}")
+    sep_head = a.method == "separable" and a.precision == "fp64"
+
     # separable form (FP64): phi/theta transforms and rotated cross-patch moments
-    if not a.only or a.method == "separable":
+    if sep_head or not a.only:
         g.set_method("separable")
+        t0 = time.perf_counter()
         if not a.no_autotune:
             g.autotune("fp64")
+        tune_s = time.perf_counter() - t0
         if a.sep_variants:
             # profiling runs: the variants an unprofiled run chose (the
             # autotuner's timings shift under a profiler)
@@ -250,36 +329,57 @@ def bench_single(a):
         ms = timed_steps(g, d_phi, "fp64", a)
         kms, kcnt = phase_pass(g, d_phi, "fp64", a)
         avg = [float(kms[i] / max(1, kcnt[i])) for i in range(8)]
-        err = None if a.no_check else sampled_error(desc, rho, d_phi.cpu().numpy())
+        err = None if a.no_check else sampled_error(front, d_phi.cpu().numpy())
         alone = {n: phase_alone_ms(g, d_phi, ph, a) for n, ph in (("phi_analysis", 0), ("phi_synthesis", 4))}
         L2 = 2 * desc["lmax"] + 1
-        phi_flops = 2.0 * M * nang * L2           # each phi transform
-        phi_bytes = 8.0 * M * nang                # the density read / the potential written
+        phi_flops = 2.0 * M * nang * L2           # each phi transform (unfolded count)
         results["fp64_separable"] = {
             "cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
             "kernels_ms": {"phi_analysis": avg[4], "theta_analysis_rotation": avg[5], "radial_scan": avg[1],
                            "theta_synthesis": avg[6], "phi_synthesis": avg[7]},
             "phi_synthesis_tflops": phi_flops / (avg[7] * 1e-3) / 1e12,
-            "phi_synthesis_gbs": phi_bytes / (avg[7] * 1e-3) / 1e9,
             "phi_analysis_tflops": phi_flops / (avg[4] * 1e-3) / 1e12,
-            "phase_alone_ms": alone,
-            "variants": g.sep_info(),
+            "phase_alone_ms": alone, "variants": g.sep_info(), "tune_s": round(tune_s, 2),
             "kernel_names": {n: g.sep_kernel(p) for p, n in enumerate(
                 ("phi_analysis", "theta_analysis", "rotation", "theta_synthesis", "phi_synthesis"))},
         }
         log(f"[bench] fp64 separable: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, "
             f"kernels {avg[4:]} scan {avg[1]}")
         g.set_method("dense")
-    for prec, r in results.items():
-        r["speedup_vs_fp64"] = results["fp64"]["ms_per_step"] / r["ms_per_step"] if "fp64" in results else None
 
-    head_key = "fp64_separable" if (a.method == "separable" and a.precision == "fp64") else a.precision
+    # dense form: every precision of the two angular contractions
+    tune_dense = not a.no_autotune and cells <= DENSE_TUNE_MAX_CELLS
+    precisions = [] if (a.only and sep_head) else (
+        [a.precision] if a.only else [a.precision] + [p for p in ALL_PRECISIONS if p != a.precision])
+    for prec in precisions:
+        t0 = time.perf_counter()
+        g.prepare(prec)
+        if tune_dense:
+            g.autotune(prec)
+        tune_s = time.perf_counter() - t0
+        info = g.plan_info(prec)
+        ms = timed_steps(g, d_phi, prec, a)
+        kms, kcnt = phase_pass(g, d_phi, prec, a)
+        avg = [float(kms[i] / max(1, kcnt[i])) for i in range(4)]
+        err = None if a.no_check else sampled_error(front, d_phi.cpu().numpy())
+        flops_syn = 2.0 * M * nang * (P * Q)
+        achieved = flops_syn / (avg[2] * 1e-3) / 1e12
+        results[prec] = {"cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
+                         "method": "dense", "autotuned": tune_dense,
+                         "kernels_ms": {"analysis": avg[0], "radial_scan": avg[1], "synthesis": avg[2],
+                                        "operand_split": avg[3]},
+                         "synthesis_tflops": achieved, "launch": info, "prepare_tune_s": round(tune_s, 2)}
+        log(f"[bench] dense {prec}: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, kernels {avg}")
+
+    # speed-ups against the fastest FP64 form (and against dense FP64)
+    fp64_forms = [results[k]["ms_per_step"] for k in ("fp64_separable", "fp64") if k in results]
+    best64 = min(fp64_forms) if fp64_forms else None
+    for key, r in results.items():
+        r["speedup_vs_fastest_fp64"] = best64 / r["ms_per_step"] if best64 else None
+        r["speedup_vs_dense_fp64"] = results["fp64"]["ms_per_step"] / r["ms_per_step"] if "fp64" in results else None
+
+    head_key = "fp64_separable" if sep_head else a.precision
     head = results[head_key]
-    cpu = None
-    if not a.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(desc, rho)
-        log(f"[bench] oracle {cpu['value']:.3e} cells/s")
 
     def dense_roofline(prec):
         r = results[prec]
@@ -294,40 +394,8 @@ def bench_single(a):
                 "executed_products_per_mac": PRODUCTS[prec], "executed_frac": ach * PRODUCTS[prec] / pk}
 
     if head_key == "fp64_separable":
-        # dominant single-launch kernel of the separable solve: the phi transforms
-        k = head["kernels_ms"]
-        L2 = 2 * desc["lmax"] + 1
-        cand = {
-            "phi_analysis": (k["phi_analysis"], 2.0 * M * nang * L2, 8.0 * M * nang + 8.0 * M * desc["n_theta"] * L2),
-            "phi_synthesis": (k["phi_synthesis"], 2.0 * M * nang * L2, 8.0 * M * nang + 8.0 * M * desc["n_theta"] * L2),
-        }
-        name = max(cand, key=lambda n: cand[n][0])
-        ms_solve, flops_k, bytes_k = cand[name]
-        # the kernel's average duration: launched alone, back to back (the
-        # per-phase events inside solves add a launch gap to each)
-        ms_k = head["phase_alone_ms"][name]
-        kname = head["kernel_names"][name]
-        args = kname[kname.find("<") + 1:].rstrip(">").split(", ")
-        folded = (kname.startswith("yyg::phi_syn_lean_kernel<")
-                  or (kname.startswith("yyg::phi_direct_kernel<") and args[-1] == "true")
-                  or (kname.startswith("yyg::gemm_nt_f64_batched<") and int(args[-1]) & (128 | 256)))
-        if folded:
-            flops_k /= 2.0   # folded about the central meridian: half the multiply-adds
-        tf = flops_k / (ms_k * 1e-3) / 1e12
-        gbs = bytes_k / (ms_k * 1e-3) / 1e9
-        fm, fh = tf / PEAK["fp64"], gbs / 8000.0
-        if fm >= fh:
-            roof = {"bound": "mfma", "kernel": kname, "achieved": tf, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                    "frac": fm, "hbm_frac": fh}
-        else:
-            roof = {"bound": "hbm", "kernel": kname, "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
-                    "frac": fh, "mfma_frac": fm}
+        roof, name, kname = phi_roofline(head, desc, M, nang)
         roof["traffic"] = measured_traffic(a.workload, head_key, name, kname)
-        roof["phase"] = name
-        roof["ms_per_launch"] = ms_k
-        roof["achieved_in_solve"] = (tf if roof["unit"] == "TFLOP/s" else gbs) * ms_k / ms_solve
-        roof["algorithmic_flops"] = flops_k
-        roof["algorithmic_bytes"] = bytes_k
     else:
         roof = dense_roofline(head_key)
     out = {
@@ -370,6 +438,8 @@ def bench_batch(a):
                     for d in descs)
     log(f"[bench] batch64: {len(descs)} fields, {cells} cells")
     rhos = [W.density(d) for d in descs]
+    check = (0, 21, 42, 63)
+    fronts = {} if a.no_check else {i: OracleFront(descs[i], rhos[i]) for i in check}
     t0 = time.perf_counter()
     grids = [yyg.Grid(d, 0) for d in descs]
     plan_s = time.perf_counter() - t0
@@ -377,75 +447,96 @@ def bench_batch(a):
     d_rho = [torch.from_numpy(r).to("cuda:0") for r in rhos]
     d_phi = [torch.empty(g.shape, dtype=torch.float64, device="cuda:0") for g in grids]
     stream = torch.cuda.Stream()
-
-    # 64 sequential FP64 solves (each plan autotuned on its own shape)
     for g, r in zip(grids, d_rho):
         g.upload_rho(r)
-        if not a.no_autotune:
-            g.autotune("fp64")
-    torch.cuda.synchronize()
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(a.steps):
+            fn()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / a.steps
+
+    def errors():
+        if a.no_check:
+            return None
+        return max(sampled_error(fronts[i], d_phi[i].cpu().numpy(), k=100, seed=i) for i in check)
 
     def seq():
         for g, p in zip(grids, d_phi):
             g.solve(p, "fp64", stream=stream)
-    for _ in range(a.warmup):
-        seq()
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(a.steps):
-        seq()
-    stop.record(stream)
-    torch.cuda.synchronize()
-    seq_ms = start.elapsed_time(stop) / a.steps
-    log(f"[bench] sequential FP64: {seq_ms:.3f} ms per 64 solves")
+
+    # 64 sequential FP64 solves in each form, each plan autotuned on its own shape
+    sequential = {}
+    for method in ("dense", "separable"):
+        for g in grids:
+            g.set_method(method)
+            if not a.no_autotune:
+                g.autotune("fp64")
+        sequential[method] = timed(seq)
+        log(f"[bench] 64 sequential {method} FP64 solves: {sequential[method]:.3f} ms")
+    seq_best = min(sequential.values())
 
     results = {}
-    precisions = [a.precision] + [p for p in ALL_PRECISIONS if p != a.precision and not a.only]
-    for prec in precisions:
+    forms = [("fp64_separable", "fp64", "separable")] + [(p, p, "dense") for p in ALL_PRECISIONS]
+    if a.only:
+        forms = [f for f in forms if f[0] == ("fp64_separable" if a.method == "separable" and a.precision == "fp64"
+                                               else a.precision)]
+    for key, prec, method in forms:
         for g in grids:
+            g.set_method(method)
             g.prepare(prec)
         b = yyg.Batch(grids, prec)
         b.solve(d_rho, d_phi, stream=stream)
         stream.synchronize()
         if not a.no_autotune:
             b.autotune(stream=stream)
-        for _ in range(a.warmup):
-            b.solve(d_rho, d_phi, stream=stream)
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        for _ in range(a.steps):
-            b.solve(d_rho, d_phi, stream=stream)
-        stop.record(stream)
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(stop) / a.steps
+        ms = timed(lambda: b.solve(d_rho, d_phi, stream=stream))
         prof = np.mean([b.profile(stream=stream) for _ in range(3)], axis=0)
-        errs = []
-        if not a.no_check:
-            for i in (0, 21, 42, 63):
-                errs.append(sampled_error(descs[i], rhos[i], d_phi[i].cpu().numpy(), k=100, seed=i))
-        results[prec] = {"cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms,
-                         "speedup_vs_sequential_fp64": seq_ms / ms,
-                         "max_rel_err_vs_oracle": max(errs) if errs else None,
-                         "kernels_ms": {"analysis": prof[0], "radial_scan": prof[1], "synthesis": prof[2],
-                                        "operand_split": prof[3]},
-                         "synthesis_tflops": flops_syn / (prof[2] * 1e-3) / 1e12, "batch": b.info()}
-        log(f"[bench] batched {prec}: {ms:.3f} ms ({seq_ms / ms:.2f}x sequential FP64), phases {prof}, errs {errs}")
+        err = errors()
+        results[key] = {"cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "method": method,
+                        "speedup_vs_sequential_fastest_fp64": seq_best / ms,
+                        "speedup_vs_sequential_dense_fp64": sequential["dense"] / ms,
+                        "speedup_vs_sequential_separable_fp64": sequential["separable"] / ms,
+                        "max_rel_err_vs_oracle": err,
+                        "kernels_ms": {"analysis": prof[0], "radial_scan": prof[1], "synthesis": prof[2],
+                                       "operand_split": prof[3]},
+                        "batch": b.info()}
+        if method == "dense":
+            results[key]["synthesis_tflops"] = flops_syn / (prof[2] * 1e-3) / 1e12
+        log(f"[bench] batched {key}: {ms:.3f} ms ({seq_best / ms:.2f}x the fastest sequential FP64), "
+            f"phases {prof}, err {err}")
         b.close()
-    head = results[a.precision]
-    achieved = head["synthesis_tflops"]
+    head_key = "fp64_separable" if (a.method == "separable" and a.precision == "fp64") else a.precision
+    head = results[head_key]
+    if head["method"] == "dense":
+        ach = head["synthesis_tflops"]
+        roof = {"bound": "mfma", "kernel": f"gemm grouped synthesis ({a.precision})", "achieved": ach,
+                "peak": PEAK[a.precision], "unit": "TFLOP/s", "frac": ach / PEAK[a.precision], "traffic": None,
+                "executed_products_per_mac": PRODUCTS[a.precision],
+                "executed_frac": ach * PRODUCTS[a.precision] / PEAK[a.precision]}
+    else:
+        # grouped phi transforms: FP64 flops of the folded transforms over their phases' time
+        fl = sum(2.0 * 2 * (len(d["r_edges"]) - 1) * d["n_theta"] * d["n_phi"] * (2 * d["lmax"] + 1) / 2
+                 for d in descs)
+        t = (head["kernels_ms"]["analysis"] + head["kernels_ms"]["synthesis"]) * 1e-3
+        roof = {"bound": "mfma", "kernel": "grouped separable phases (both phi transforms and theta phases)",
+                "achieved": fl / t / 1e12, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                "frac": fl / t / 1e12 / PEAK["fp64"], "traffic": None}
     out = {
         "metric": METRIC, "value": head["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPE[a.precision], "data": "synthetic",
         "config": {"workload": "batch64", "fields": len(descs), "cells": cells, "precision": a.precision,
-                   "sequential_fp64_ms": seq_ms, "sequential_fp64_cells_per_s": cells / (seq_ms * 1e-3),
-                   "max_rel_err_vs_oracle": head["max_rel_err_vs_oracle"], "plan_build_s": round(plan_s, 2)},
-        "roofline": {"bound": "mfma", "kernel": f"gemm grouped synthesis ({a.precision})", "achieved": achieved,
-                     "peak": PEAK[a.precision], "unit": "TFLOP/s", "frac": achieved / PEAK[a.precision],
-                     "traffic": None, "executed_products_per_mac": PRODUCTS[a.precision],
-                     "executed_frac": achieved * PRODUCTS[a.precision] / PEAK[a.precision]},
+                   "method": head["method"],
+                   "sequential_fp64_ms": sequential, "max_rel_err_vs_oracle": head["max_rel_err_vs_oracle"],
+                   "plan_build_s": round(plan_s, 2)},
+        "roofline": roof,
         "precisions": results,
         "cpu_baseline": None,
     }
@@ -457,7 +548,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sn_core")
+    ap.add_argument("--workload", default="binary")
     ap.add_argument("--precision", default="fp64", choices=ALL_PRECISIONS)
     ap.add_argument("--method", default="separable", choices=("dense", "separable"),
                     help="headline method for FP64 (both are measured unless --only)")

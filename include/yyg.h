@@ -323,12 +323,20 @@ int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n);
  * values (no fault, meaningless output). */
 int yyg_sep_phase(yyg_grid *g, int phase, double *phi, void *stream);
 
-/* Batched solves of several plans (uneven n_r <= 1024, angular sizes and
- * lmax allowed) for fields that each have their own density and potential
- * arrays.  One batched solve is three persistent grouped launches (five
+/* Batched solves of several plans (uneven n_r, angular sizes and lmax
+ * allowed) for fields that each have their own density and potential
+ * arrays: the tables of every plan are built once (Sect. 3, last
+ * paragraph), the density-dependent work of all fields runs together.
+ * When every plan is in the separable form (yyg_set_method) and
+ * `precision` is FP64, one batched solve is six persistent grouped
+ * launches, the separable form's phases over every field's problems: phi
+ * analysis, theta analysis, rotation of the other patch's moments, the
+ * column scans, theta synthesis, phi synthesis (n_r as the plans'
+ * separable form allows).  Otherwise it is the dense form's three (five
  * with the reduced-precision operand splits): all fields' analysis tiles,
- * then all radial scans, then all synthesis tiles, each launch's blocks
- * walking a device work list.  Yin-Yang and polar plans may be mixed.
+ * then all radial scans, then all synthesis tiles (n_r <= 1024).  Each
+ * launch's blocks walk a device work list.  Yin-Yang and polar plans may
+ * be mixed.
  * The launches, together with the copy of the
  * per-field arguments, are recorded once into a HIP graph and replayed.
  * `grids` are borrowed and must outlive the batch; all on one device; for
@@ -346,7 +354,10 @@ int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **o
 int yyg_batch_autotune(yyg_batch *b, void *stream);
 
 /* info[0..5] = fields, precision, analysis variant, synthesis variant,
- * analysis work items, synthesis work items. */
+ * analysis work items, synthesis work items; for a separable batch the
+ * variants and items are those of the phi analysis and phi synthesis, and
+ * info[6..8] the tiles of the theta analysis, rotation and theta synthesis
+ * (-1 for a dense batch).  Writes the first n entries (n <= 9). */
 int yyg_batch_info(const yyg_batch *b, int *info, int n);
 
 /* Solve every field: d_rho[f] / d_phi[f] are device arrays of field f in
@@ -361,8 +372,9 @@ int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_p
 /* Run the launches of the last batched solve once more, eagerly (not from
  * the graph), with HIP events between the phases on `stream`; blocks and
  * writes the milliseconds of ms[0] analysis, ms[1] radial scans, ms[2]
- * synthesis, ms[3] operand splits (first n entries).  Needs one earlier
- * yyg_batch_solve. */
+ * synthesis, ms[3] operand splits (first n entries; a separable batch:
+ * phi + theta analysis and rotation, scans, theta + phi synthesis, 0).
+ * Needs one earlier yyg_batch_solve. */
 int yyg_batch_profile(yyg_batch *b, void *stream, double *ms, int n);
 int yyg_batch_destroy(yyg_batch *b);
 

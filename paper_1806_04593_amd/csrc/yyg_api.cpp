@@ -699,6 +699,18 @@ struct yyg_batch {
   hipStream_t stream = nullptr;  // used when the caller passes the default stream
   bool launched = false;
   std::vector<int> part_gen;     // plans' partial-buffer generations the arguments hold
+  // separable batches (FP64, every plan in the separable form): the five
+  // phases and the column scans as grouped launches over all plans
+  bool sep = false, sep_fold = false;
+  yyg::GemmF64Args *h_phi[2] = {nullptr, nullptr}, *d_phi[2] = {nullptr, nullptr};  // phi analysis / synthesis
+  yyg::SepPhaseArgs *d_sargs = nullptr;
+  yyg::ScanQArgs *d_qscan = nullptr;
+  int2 *d_qitems = nullptr;
+  int n_qitems = 0, max_nr = 0;
+  int4 *d_sitems[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int n_sitems[5] = {0, 0, 0, 0, 0};
+  int svar[5] = {0, 0, 0, 0, 0};    // tile of each phase (yyg::sep_batch_tile)
+  int sblocks[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -722,6 +734,15 @@ void batch_free(yyg_batch *b) {
   }
   if (b->d_scan) (void)hipFree(b->d_scan);
   if (b->d_scan_items) (void)hipFree(b->d_scan_items);
+  for (int r = 0; r < 2; ++r) {
+    if (b->h_phi[r]) (void)hipHostFree(b->h_phi[r]);
+    if (b->d_phi[r]) (void)hipFree(b->d_phi[r]);
+  }
+  for (int r = 0; r < 5; ++r)
+    if (b->d_sitems[r]) (void)hipFree(b->d_sitems[r]);
+  if (b->d_sargs) (void)hipFree(b->d_sargs);
+  if (b->d_qscan) (void)hipFree(b->d_qscan);
+  if (b->d_qitems) (void)hipFree(b->d_qitems);
   if (b->done) (void)hipEventDestroy(b->done);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -807,7 +828,10 @@ hipError_t batch_launch_gemm(yyg_batch *b, int role, hipStream_t s) {
 void batch_patch_pointers(yyg_batch *b) {
   const int n = (int)b->grids.size();
   for (int f = 0; f < n; ++f) {
-    if (b->precision == YYG_FP64) {
+    if (b->sep) {
+      b->h_phi[0][f].A = b->rho[f];
+      b->h_phi[1][f].C = b->phi[f];
+    } else if (b->precision == YYG_FP64) {
       b->h_f64[0][f].A = b->rho[f];
       b->h_f64[1][f].C = b->phi[f];
     } else {
@@ -817,8 +841,11 @@ void batch_patch_pointers(yyg_batch *b) {
   }
 }
 
+hipError_t sep_batch_enqueue(yyg_batch *b, hipStream_t s, hipEvent_t *ev);
+
 // Enqueue the whole batched solve on s (recorded into the graph).
 hipError_t batch_enqueue(yyg_batch *b, hipStream_t s) {
+  if (b->sep) return sep_batch_enqueue(b, s, nullptr);
   const int n = (int)b->grids.size();
   hipError_t e = hipSuccess;
   const bool lp = b->precision != YYG_FP64;
@@ -926,6 +953,130 @@ int batch_build(yyg_batch *b) {
   // default tile variant 64 x 64 (index 3 of the FP64 list, 0 of the others)
   for (int role = 0; role < 2 && st == YYG_OK; ++role) st = batch_set_items(b, role, lp ? 0 : 3);
   return st;
+}
+
+// Work items of separable phase r over every plan for batch tile t, the
+// longest contractions first so that the persistent blocks finish together:
+// (plan, tile row, tile column, z), z the strided-batch index (phi phases)
+// or the problem of the phase (theta phases, rotation).
+int sep_batch_set_items(yyg_batch *b, int r, int t) {
+  int bm, bn, threads;
+  yyg::sep_batch_tile(t, &bm, &bn, &threads);
+  std::vector<std::pair<long, int4>> work;
+  const int n = (int)b->grids.size();
+  auto tiles = [&](long M, long N, long K, int f, int z) {
+    const int tm = (int)((M + bm - 1) / bm), tn = (int)((N + bn - 1) / bn);
+    for (int j = 0; j < tn; ++j)
+      for (int i = 0; i < tm; ++i) work.push_back({K, int4{f, i, j, z}});
+  };
+  for (int f = 0; f < n; ++f) {
+    const yyg_grid *g = b->grids[f];
+    const long Mr = (long)g->n_patch * g->n_r;
+    const int L = g->L, nmc = 2 * L + 1;
+    if (r == 0 || r == 4) {
+      const yyg::GemmF64Args &a = b->h_phi[r == 0 ? 0 : 1][f];
+      for (int z = 0; z < a.batch; ++z) tiles(a.M, a.N, a.K, f, z);
+    } else if (r == 1) {
+      for (int z = 0; z < nmc; ++z) tiles(Mr, L + 1 - (z + 1) / 2, g->n_t, f, z);
+    } else if (r == 2) {
+      if (g->n_patch == 2)
+        for (int z = 0; z < 2 * (L + 1); ++z) tiles(g->n_r, 2 * (L - z / 2) + 1, 2 * (L - z / 2) + 1, f, z);
+    } else {
+      for (int z = 0; z < nmc; ++z) tiles(g->n_t, Mr, L + 1 - (z + 1) / 2, f, z);
+    }
+  }
+  std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+  std::vector<int4> items(work.size());
+  for (size_t i = 0; i < work.size(); ++i) items[i] = work[i].second;
+  int st = upload(&b->d_sitems[r], items);
+  if (st != YYG_OK) return st;
+  b->n_sitems[r] = (int)items.size();
+  b->svar[r] = t;
+  // resident blocks: LDS-limited occupancy of the tile, four at most
+  const long lds = 2L * (bm + bn) * 18 * 8;
+  const int per_cu = (int)std::max(1L, std::min(4L, 160L * 1024 / lds));
+  b->sblocks[r] = std::max(1, std::min(b->n_sitems[r], b->cus * per_cu));
+  return YYG_OK;
+}
+
+int sep_batch_build(yyg_batch *b) {
+  const int n = (int)b->grids.size();
+  b->rho.assign(n, nullptr);
+  b->phi.assign(n, nullptr);
+  b->part_gen.resize(n);
+  for (int f = 0; f < n; ++f) b->part_gen[f] = b->grids[f]->part_gen;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
+    b->cus = cus;
+  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) return YYG_ERR_DEVICE;
+  if (hipStreamCreate(&b->stream) != hipSuccess) return YYG_ERR_DEVICE;
+  // folded phi transforms when every plan is mirror-symmetric (one launch
+  // mode for all plans)
+  b->sep_fold = true;
+  for (int f = 0; f < n; ++f) b->sep_fold = b->sep_fold && b->grids[f]->sep.fold;
+  for (int r = 0; r < 2; ++r)
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->h_phi[r]), n * sizeof(yyg::GemmF64Args), 0) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&b->d_phi[r]), n * sizeof(yyg::GemmF64Args)) != hipSuccess) {
+      (void)hipGetLastError();
+      return YYG_ERR_OUT_OF_MEMORY;
+    }
+  std::vector<yyg::SepPhaseArgs> sargs(n);
+  std::vector<yyg::ScanQArgs> qscan(n);
+  std::vector<int2> qitems;
+  for (int f = 0; f < n; ++f) {
+    yyg_grid *g = b->grids[f];
+    auto &S = g->sep;
+    b->h_phi[0][f] = b->sep_fold ? S.phi_ana_f : S.phi_ana;
+    b->h_phi[1][f] = b->sep_fold ? S.phi_syn_f : S.phi_syn;
+    sargs[f] = S.args;
+    const int chunk = ((g->n_r + 63) / 64) | 1;
+    qscan[f] = yyg::ScanQArgs{g->n_patch == 2 ? S.At : g->d_Ahat, S.coefS, g->d_qdeg, g->n_r, g->L, chunk,
+                              g->n_patch, -g->G, S.Ut};
+    b->max_nr = std::max(b->max_nr, g->n_r);
+    for (int q = 0; q < g->Q; ++q) qitems.push_back(int2{f, q});
+  }
+  int st = upload(&b->d_sargs, sargs);
+  if (st == YYG_OK) st = upload(&b->d_qscan, qscan);
+  if (st == YYG_OK) st = upload(&b->d_qitems, qitems);
+  b->n_qitems = (int)qitems.size();
+  // default tiles: 64 x 80 for the phi analysis, 128 x 48 for the phi
+  // synthesis, 32 x 32 for the theta phases and the rotation
+  const int def[5] = {3, 0, 0, 0, 4};
+  for (int r = 0; r < 5 && st == YYG_OK; ++r) st = sep_batch_set_items(b, r, def[r]);
+  return st;
+}
+
+// The batched separable solve on s; with ev (6 events) recorded before
+// the argument copies and after each of the six launches.
+hipError_t sep_batch_enqueue(yyg_batch *b, hipStream_t s, hipEvent_t *ev) {
+  const int n = (int)b->grids.size();
+  hipError_t e = hipSuccess;
+  auto mark = [&](int i) {
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[i], s);
+  };
+  mark(0);
+  e = hipMemcpyAsync(b->d_phi[0], b->h_phi[0], n * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_phi[1], b->h_phi[1], n * sizeof(yyg::GemmF64Args), hipMemcpyHostToDevice, s);
+  auto phase = [&](int r) {
+    if (e == hipSuccess)
+      e = yyg::launch_sep_batch_phase(b->svar[r], r, b->sep_fold, b->d_phi[r == 0 ? 0 : 1], b->d_sargs, b->d_sitems[r],
+                                      b->n_sitems[r], b->sblocks[r], s);
+  };
+  phase(0);
+  mark(1);
+  phase(1);
+  phase(2);
+  mark(2);
+  if (e == hipSuccess)
+    e = yyg::launch_radial_scan_q_grouped(b->d_qscan, b->d_qitems, b->n_qitems, std::min(b->n_qitems, b->cus * 4),
+                                          b->max_nr, s);
+  mark(3);
+  phase(3);
+  mark(4);
+  phase(4);
+  mark(5);
+  return e;
 }
 
 }  // namespace
@@ -1778,22 +1929,28 @@ int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **o
   if (!out) return YYG_ERR_INVALID_ARG;
   *out = nullptr;
   if (!grids || n < 1 || precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
+  // the separable form when every plan is in it (FP64), the dense form otherwise
+  bool sep = precision == YYG_FP64;
   for (int f = 0; f < n; ++f) {
     if (!grids[f] || grids[f]->device != grids[0]->device) return YYG_ERR_INVALID_ARG;
-    if (grids[f]->n_r > 1024) return YYG_ERR_UNSUPPORTED;
+    sep = sep && grids[f]->method == YYG_METHOD_SEPARABLE && grids[f]->sep.ready;
+  }
+  for (int f = 0; f < n; ++f) {
+    if (!sep && grids[f]->n_r > 1024) return YYG_ERR_UNSUPPORTED;
     if (precision != YYG_FP64 && !grids[f]->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
   }
   yyg_batch *b = new (std::nothrow) yyg_batch;
   if (!b) return YYG_ERR_OUT_OF_MEMORY;
   b->device = grids[0]->device;
   b->precision = precision;
+  b->sep = sep;
   b->grids.assign(grids, grids + n);
   DeviceGuard dg(b->device);
   if (!dg.ok) {
     delete b;
     return YYG_ERR_DEVICE;
   }
-  int st = batch_build(b);
+  int st = sep ? sep_batch_build(b) : batch_build(b);
   if (st != YYG_OK) {
     batch_free(b);
     return st;
@@ -1813,6 +1970,28 @@ int yyg_batch_autotune(yyg_batch *b, void *stream) {
   if (hipStreamSynchronize(b->stream) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;
+  }
+  if (b->sep) {
+    // each phase in turn, the others at their current tile: whole eager
+    // batched solves, the fastest of three per tile
+    for (int r = 0; r < 5; ++r) {
+      if (r == 2 && b->n_sitems[2] == 0) continue;  // no two-patch plan: nothing to rotate
+      int best = b->svar[r];
+      double bt = 1e30;
+      for (int t = 0; t < yyg::sep_batch_tile_count(); ++t) {
+        int st = sep_batch_set_items(b, r, t);
+        if (st != YYG_OK) return st;
+        const double tm = time_launch([&] { return sep_batch_enqueue(b, s, nullptr); }, s, 3);
+        if (tm < bt) {
+          bt = tm;
+          best = t;
+        }
+      }
+      int st = sep_batch_set_items(b, r, best);
+      if (st != YYG_OK) return st;
+    }
+    batch_drop_graph(b);
+    return YYG_OK;
   }
   const bool lp = b->precision != YYG_FP64;
   const int nv = lp ? yyg::gemm_lp_variant_count() : yyg::gemm_f64_variant_count();
@@ -1842,8 +2021,15 @@ int yyg_batch_autotune(yyg_batch *b, void *stream) {
 
 int yyg_batch_info(const yyg_batch *b, int *info, int n) {
   if (!b || !info || n < 1) return YYG_ERR_INVALID_ARG;
-  const int vals[6] = {(int)b->grids.size(), b->precision, b->var[0], b->var[1], b->n_items[0], b->n_items[1]};
-  for (int i = 0; i < n && i < 6; ++i) info[i] = vals[i];
+  if (b->sep) {
+    const int vals[9] = {(int)b->grids.size(), b->precision, b->svar[0], b->svar[4], b->n_sitems[0], b->n_sitems[4],
+                         b->svar[1], b->svar[2], b->svar[3]};
+    for (int i = 0; i < n && i < 9; ++i) info[i] = vals[i];
+    return YYG_OK;
+  }
+  const int vals[9] = {(int)b->grids.size(), b->precision, b->var[0], b->var[1], b->n_items[0], b->n_items[1],
+                       -1, -1, -1};
+  for (int i = 0; i < n && i < 9; ++i) info[i] = vals[i];
   return YYG_OK;
 }
 
@@ -1861,7 +2047,7 @@ int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_p
   // a graph cannot be recorded on the legacy default stream: use the
   // batch's own blocking stream, which that stream orders against
   hipStream_t s = stream ? as_stream(stream) : b->stream;
-  for (int f = 0; f < n; ++f) b->grids[f]->ahat_cols = false;
+  for (int f = 0; f < n; ++f) b->grids[f]->ahat_cols = b->sep;  // the moments' layout the batch leaves
   bool changed = false;
   for (int f = 0; f < n; ++f)
     if (b->rho[f] != d_rho[f] || b->phi[f] != d_phi[f]) changed = true;
@@ -1916,6 +2102,22 @@ int yyg_batch_profile(yyg_batch *b, void *stream, double *ms, int n) {
   hipEvent_t ev[6];
   for (auto &x : ev)
     if (hipEventCreate(&x) != hipSuccess) return YYG_ERR_DEVICE;
+  if (b->sep) {
+    // phases 0-2 (phi and theta analysis, rotation), the scans, phases 3-4
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = sep_batch_enqueue(b, s, ev);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+    float t[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ev[i], ev[i + 1]);
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return YYG_ERR_DEVICE;
+    }
+    const double vals[4] = {(double)t[0] + t[1], t[2], (double)t[3] + t[4], 0.0};
+    for (int i = 0; i < n && i < 4; ++i) ms[i] = vals[i];
+    return YYG_OK;
+  }
   const int nf = (int)b->grids.size();
   const bool lp = b->precision != YYG_FP64;
   hipError_t e = hipStreamSynchronize(s);

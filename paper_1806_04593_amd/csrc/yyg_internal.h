@@ -267,6 +267,30 @@ size_t radial_scan_q_lds(int nR, int patches);
 hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int *qdeg, int nR, int L, double negG,
                                 int patches, double *Ut, hipStream_t s);
 
+// Batched separable solves: one plan's column scan (as launch_radial_scan_q)
+// per entry; chunk = ((nR + 63) / 64) | 1, P patches.
+struct ScanQArgs {
+  const double *X, *coefS;
+  const int *qdeg;
+  int nR, L, chunk, P;
+  double negG;
+  double *Ut;
+};
+// items = (plan, column q); blocks of 128 threads with the LDS of the
+// largest plan (max_nR shells).
+hipError_t launch_radial_scan_q_grouped(const ScanQArgs *args, const int2 *items, int n_items, int n_blocks,
+                                        int max_nR, hipStream_t s);
+// Grouped separable phases over several plans with one of
+// sep_batch_tile_count() tile shapes: phase 0 / 4 the phi transforms
+// (folded or not; items (plan, tile row, tile column, batch index z) over
+// the plans' GemmF64Args), 1-3 the theta phases and rotation (items (plan,
+// tile row, tile column, problem z) over the plans' SepPhaseArgs).
+int sep_batch_tile_count();
+void sep_batch_tile(int t, int *bm, int *bn, int *threads);
+hipError_t launch_sep_batch_phase(int t, int phase, bool fold, const GemmF64Args *phi, const SepPhaseArgs *args,
+                                  const int4 *items, int n_items, int n_blocks, hipStream_t s);
+int sep_batch_kernel_name(int t, int phase, bool fold, char *buf, size_t n);
+
 // Kernel symbol (as profilers print it) of variant v of separable phase
 // `phase`, with the phi phases folded (fold) or not; 0, or -1 for an
 // invalid phase / variant.

@@ -584,17 +584,20 @@ __global__ __launch_bounds__(256) void phi_syn_lean_kernel(PhiLeanArgs a) {
 // Ut[mc][l][p nR + n] (q = l^2 + mc), rows contiguous.
 // CMAX bounds the chunk length: the chunk loops unroll with every LDS read
 // at a clamped index, so that the reads issue ahead of the recurrences.
+// Column q of one plan's scan; waves p >= P (a one-patch plan in a block
+// sized for two) take part in the barriers only.
 template <int CMAX>
-__global__ __launch_bounds__(128) void radial_scan_q_kernel(const double *__restrict__ X, const double *__restrict__ coefS,
-                                                            const int *__restrict__ qdeg, int nR, int L, int chunk,
-                                                            double negG, double *__restrict__ Ut) {
-  extern __shared__ double smem[];
-  const int q = blockIdx.x, l = qdeg[q];
-  const int P = blockDim.x / 64;
+__device__ __forceinline__ void radial_scan_q_body(const double *__restrict__ X, const double *__restrict__ coefS,
+                                                   const int *__restrict__ qdeg, int nR, int L, int chunk,
+                                                   double negG, double *__restrict__ Ut, int q, int P,
+                                                   double *smem) {
+  const int l = qdeg[q];
   const int tid = threadIdx.x, lane = tid & 63, p = tid >> 6;
+  const bool active = p < P;
+  const int pa = active ? p : 0;                     // an inactive wave addresses patch 0 and stores nothing
   const long M = (long)P * nR;
   double *sc = smem;                                 // [4][nR]: c0, c1, c2, c3 over n
-  double *sx = smem + 4L * nR + (long)p * (2 * nR + 1);  // [nR + 1]: the moments, zero at nR
+  double *sx = smem + 4L * nR + (long)pa * (2 * nR + 1);  // [nR + 1]: the moments, zero at nR
   double *so = sx + nR + 1;                          // [nR]: output staging
   {
     // staging: batches of CB coefficient and XB moment loads from clamped
@@ -602,7 +605,7 @@ __global__ __launch_bounds__(128) void radial_scan_q_kernel(const double *__rest
     // n_r <= 512 with two patches)
     constexpr int CB = 16, XB = 8;
     const double *__restrict__ cl = coefS + (long)l * 4 * nR;
-    const double *__restrict__ xp = X + (long)q * M + (long)p * nR;
+    const double *__restrict__ xp = X + (long)q * M + (long)pa * nR;
     const int nt = blockDim.x;
     for (int c0 = 0, x0 = 0; c0 < 4 * nR || x0 <= nR; c0 += CB * nt, x0 += XB * 64) {
       double tc[CB], tx[XB];
@@ -617,7 +620,7 @@ __global__ __launch_bounds__(128) void radial_scan_q_kernel(const double *__rest
 #pragma unroll
       for (int u = 0; u < XB; ++u) {
         const int e = x0 + u * 64 + lane;
-        if (e <= nR) sx[e] = keep_if(e < nR, tx[u]);
+        if (active && e <= nR) sx[e] = keep_if(e < nR, tx[u]);
       }
     }
   }
@@ -678,13 +681,36 @@ __global__ __launch_bounds__(128) void radial_scan_q_kernel(const double *__rest
     const double a = c2[n], b = c3[n] * sx[n + 1];
     if (i < len) {
       O = a * O + b;
-      so[n] = negG * (Iv[i] + O);
+      if (active) so[n] = negG * (Iv[i] + O);
     }
   }
   __syncthreads();
   const int mc = q - l * l;
-  double *__restrict__ ut = Ut + ((long)mc * (L + 1) + l) * M + (long)p * nR;
-  for (int e = lane; e < nR; e += 64) ut[e] = so[e];
+  double *__restrict__ ut = Ut + ((long)mc * (L + 1) + l) * M + (long)pa * nR;
+  if (active)
+    for (int e = lane; e < nR; e += 64) ut[e] = so[e];
+}
+
+template <int CMAX>
+__global__ __launch_bounds__(128) void radial_scan_q_kernel(const double *__restrict__ X, const double *__restrict__ coefS,
+                                                            const int *__restrict__ qdeg, int nR, int L, int chunk,
+                                                            double negG, double *__restrict__ Ut) {
+  extern __shared__ double smem[];
+  radial_scan_q_body<CMAX>(X, coefS, qdeg, nR, L, chunk, negG, Ut, blockIdx.x, blockDim.x / 64, smem);
+}
+
+// The same over the columns of several plans (batched separable solves):
+// blocks of two waves walk work items (plan, column q).
+template <int CMAX>
+__global__ __launch_bounds__(128) void radial_scan_q_grouped(const ScanQArgs *__restrict__ args,
+                                                             const int2 *__restrict__ items, int n_items) {
+  extern __shared__ double smem[];
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const int2 it = items[w];
+    const ScanQArgs a = args[it.x];
+    __syncthreads();  // the previous item's LDS reads are done
+    radial_scan_q_body<CMAX>(a.X, a.coefS, a.qdeg, a.nR, a.L, a.chunk, a.negG, a.Ut, it.y, a.P, smem);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1052,6 +1078,27 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
   if (chunk <= 15) return go(radial_scan_q_kernel<15>);
   if (chunk <= 31) return go(radial_scan_q_kernel<31>);
   if (chunk <= 63) return go(radial_scan_q_kernel<63>);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_radial_scan_q_grouped(const ScanQArgs *args, const int2 *items, int n_items, int n_blocks,
+                                        int max_nR, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const size_t lds = radial_scan_q_lds(max_nR, 2);
+  if (lds > kScanQMaxLds) return hipErrorInvalidValue;
+  const int chunk = ((max_nR + 63) / 64) | 1;
+  auto go = [&](auto kern) {
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(128), lds, s, args, items, n_items);
+    return hipGetLastError();
+  };
+  if (chunk <= 7) return go(radial_scan_q_grouped<7>);
+  if (chunk <= 15) return go(radial_scan_q_grouped<15>);
+  if (chunk <= 31) return go(radial_scan_q_grouped<31>);
+  if (chunk <= 63) return go(radial_scan_q_grouped<63>);
   return hipErrorInvalidValue;
 }
 

@@ -499,10 +499,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_batched(GemmF64Arg
 //    the accumulators start from A_own (kGemmAccInit).
 //  PHASE 3, theta synthesis, z = mc: V[mc][j][row] =
 //    sum_{l >= m} P2[mc][j][l] Ut[mc][l][row].
-template <int PHASE, int BM, int BN, int WGM, int WGN, int MODE>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_sep_phase(SepPhaseArgs a) {
+template <int PHASE>
+__device__ __forceinline__ GemmF64Args sep_problem(const SepPhaseArgs &a, int z) {
   const long Mr = (long)a.P * a.nR, MJ = Mr * a.nt;
-  const int z = blockIdx.z;
   GemmF64Args g{};
   if constexpr (PHASE == 1) {
     const int mc = z, m = (mc + 1) >> 1;
@@ -544,8 +543,27 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_sep_phase(SepPhaseArg
   }
   g.k_per_split = (g.K + kBK - 1) / kBK * kBK;
   g.tiles_m = 1;
+  return g;
+}
+
+template <int PHASE, int BM, int BN, int WGM, int WGN, int MODE>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_sep_phase(SepPhaseArgs a) {
+  const GemmF64Args g = sep_problem<PHASE>(a, blockIdx.z);
   if ((int)blockIdx.x * BM >= g.M || (int)blockIdx.y * BN >= g.N) return;  // uniform: past this problem's tiles
   gemm_f64_tile<BM, BN, WGM, WGN, MODE>(g, blockIdx.x, blockIdx.y, 0);
+}
+
+// The same over the problems of several plans (batched separable solves):
+// blocks walk work items (plan, tile row, tile column, problem z).
+template <int PHASE, int BM, int BN, int WGM, int WGN, int MODE>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_f64_sep_grouped(const SepPhaseArgs *__restrict__ args,
+                                                                       const int4 *__restrict__ items, int n_items) {
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const int4 it = items[w];
+    __syncthreads();  // the previous item's LDS reads are done
+    const GemmF64Args g = sep_problem<PHASE>(args[it.x], it.w);
+    gemm_f64_tile<BM, BN, WGM, WGN, MODE>(g, it.y, it.z, 0);
+  }
 }
 
 // Persistent grouped form: blocks walk a list of (problem, tm, tn, split)

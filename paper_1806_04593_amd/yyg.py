@@ -343,9 +343,10 @@ class Batch:
         return ms
 
     def info(self):
-        info = (ctypes.c_int * 6)()
-        _check(lib().yyg_batch_info(self._h, info, 6), "yyg_batch_info")
-        return dict(zip(("fields", "precision", "var_ana", "var_syn", "items_ana", "items_syn"), list(info)))
+        info = (ctypes.c_int * 9)()
+        _check(lib().yyg_batch_info(self._h, info, 9), "yyg_batch_info")
+        return dict(zip(("fields", "precision", "var_ana", "var_syn", "items_ana", "items_syn", "var_theta_ana",
+                         "var_rotation", "var_theta_syn"), list(info)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -137,3 +137,75 @@ def test_batch_rejects_bad_arguments():
     with pytest.raises(yyg.YygError) as ei:
         b.autotune()                   # needs one solve first
     assert ei.value.status == -4
+
+
+def test_separable_batch_against_oracle_replays_and_mixed_grids():
+    """Every plan in the separable form: the batch runs the separable phases
+    as grouped launches over all fields (here with a polar plan among the
+    Yin-Yang ones): against the oracle on first launch, on graph replays,
+    with new pointers and after the batch autotuner; against per-plan
+    separable solves of the same fields."""
+    torch = _torch()
+    from paper_1806_04593_amd import yyg
+    descs = _fields(5)
+    descs.append(W.make_polar_desc("polar_f", np.linspace(0.0, 1.0, 41), 6.0, 12, 1.0, 1099, recipe="small"))
+    rhos = [W.density(d) for d in descs]
+    grids = [yyg.Grid(d, 0) for d in descs]
+    single = []
+    for g, r in zip(grids, rhos):
+        g.set_method("separable")
+        d_r = torch.from_numpy(r).to("cuda")
+        d_p = torch.empty(g.shape, dtype=torch.float64, device="cuda")
+        g.upload_rho(d_r)
+        g.solve(d_p)
+        torch.cuda.synchronize()
+        single.append(d_p.cpu().numpy())
+    samples = [_samples(d, 120, 70 + i) for i, d in enumerate(descs)]
+    refs = []
+    for d, r, s in zip(descs, rhos, samples):
+        if d.get("kind") == "polar":
+            refs.append(O.solve_polar_sampled(d["r_edges"], d["n_theta"], d["n_phi"], d["lmax"], d["G"], r,
+                                              np.stack([np.zeros(len(s), int), s[:, 1], s[:, 2], s[:, 3]], 1)))
+            s[:, 0] = 0
+        else:
+            refs.append(_oracle(d, r, s))
+    b = yyg.Batch(grids, "fp64")
+    info = b.info()
+    assert info["var_theta_ana"] >= 0, info           # the separable batch
+    d_rho = [torch.from_numpy(r).to("cuda") for r in rhos]
+    d_phi = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for g in grids]
+
+    def check(tag):
+        worst = worst_single = 0.0
+        for p, s, ref, one in zip(d_phi, samples, refs, single):
+            got = p.cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(got[s[:, 0], s[:, 1], s[:, 2], s[:, 3]] - ref) / np.abs(ref))))
+            worst_single = max(worst_single, float(np.max(np.abs(got - one) / np.abs(one))))
+        _say(f"separable batch {tag}: max rel err {worst:.3e} vs oracle, {worst_single:.3e} vs single ({b.info()})")
+        assert worst <= TOL["fp64"], (tag, worst)
+        assert worst_single <= 1e-13, (tag, worst_single)
+
+    b.solve(d_rho, d_phi)
+    torch.cuda.synchronize()
+    check("first launch")
+    for rep in range(2):
+        for p in d_phi:
+            p.zero_()
+        _ = (torch.arange(4096, device="cuda", dtype=torch.float64) * rep).sum().item()
+        torch.cuda.synchronize()
+        b.solve(d_rho, d_phi)
+        torch.cuda.synchronize()
+        check(f"replay {rep}")
+    d_phi = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for g in grids]
+    b.solve(d_rho, d_phi)
+    torch.cuda.synchronize()
+    check("new pointers")
+    b.autotune()
+    for p in d_phi:
+        p.zero_()
+    b.solve(d_rho, d_phi)
+    torch.cuda.synchronize()
+    check("after autotune")
+    ms = b.profile()
+    assert ms[0] > 0 and ms[1] > 0 and ms[2] > 0
+    b.close()

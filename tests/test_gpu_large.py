@@ -166,20 +166,27 @@ def _batch64():
     return descs, rhos
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp16x2"])
+@pytest.mark.parametrize("precision", ["fp64", "fp16x2", "fp64-separable"])
 def test_batch64_full_sizes(precision):
-    """All 64 fields in one batched solve; 8 fields (the largest and the
-    smallest among them) checked against the oracle at 300 samples each."""
+    """All 64 fields in one batched solve (dense FP64, dense FP16x2, and the
+    separable form's grouped phases); 8 fields (the largest and the smallest
+    among them) checked against the oracle at 300 samples each."""
     torch = _torch()
     yyg = _yyg()
     descs, rhos = _batch64()
     grids = [yyg.Grid(d, 0) for d in descs]
+    sep = precision == "fp64-separable"
+    if sep:
+        precision = "fp64"
+        for g in grids:
+            g.set_method("separable")
     if precision != "fp64":
         for g in grids:
             g.prepare(precision)
     d_rho = [torch.from_numpy(r).to("cuda") for r in rhos]
     d_phi = [torch.zeros(g.shape, dtype=torch.float64, device="cuda") for g in grids]
     b = yyg.Batch(grids, precision)
+    assert (b.info()["var_theta_ana"] >= 0) == sep
     stream = torch.cuda.Stream()
     b.solve(d_rho, d_phi, stream=stream)
     b.solve(d_rho, d_phi, stream=stream)   # a graph replay
