@@ -27,6 +27,7 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp16x2": 2500.0}   # den
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "fp16x2": 3}   # MFMA products per algorithmic multiply-add
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "fp16x2": "f16x2"}
 ALL_PRECISIONS = ("fp64", "fp32", "bf16x3", "fp16x2")
+SEP_LP = ("fp32", "bf16x3")   # reduced precisions of the separable form's phi transforms
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1806_04593_amd", "csrc", f) for f in ("yyg_kernels.hip", "yyg_kernels_lp.hip")]
 METRIC = "grid cells/sec per full Phi solve, FP64 vs split-precision, at stated max rel. error"
 
@@ -345,6 +346,25 @@ def bench_single(a):
         }
         log(f"[bench] fp64 separable: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, "
             f"kernels {avg[4:]} scan {avg[1]}")
+        # the same form with its two phi transforms in FP32 / BF16 x 3
+        for prec in ([] if a.only else SEP_LP):
+            t0 = time.perf_counter()
+            if not a.no_autotune:
+                g.autotune(prec)
+            tune_s = time.perf_counter() - t0
+            ms = timed_steps(g, d_phi, prec, a)
+            kms, kcnt = phase_pass(g, d_phi, prec, a)
+            avg = [float(kms[i] / max(1, kcnt[i])) for i in range(8)]
+            err = None if a.no_check else sampled_error(front, d_phi.cpu().numpy())
+            results[f"{prec}_separable"] = {
+                "cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
+                "method": "separable", "tune_s": round(tune_s, 2),
+                "kernels_ms": {"phi_analysis": avg[4], "theta_analysis_rotation": avg[5], "radial_scan": avg[1],
+                               "theta_synthesis": avg[6], "phi_synthesis": avg[7]},
+                "kernel_names": {"phi_analysis": g.sep_lp_kernel(prec, 0), "phi_synthesis": g.sep_lp_kernel(prec, 4)},
+            }
+            log(f"[bench] {prec} separable: {ms:.4f} ms/step, {cells / (ms * 1e-3):.3e} cells/s, err {err}, "
+                f"kernels {avg[4:]} scan {avg[1]}")
         g.set_method("dense")
 
     # dense form: every precision of the two angular contractions

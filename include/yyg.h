@@ -124,7 +124,8 @@ int yyg_grid_kind(const yyg_grid *g, int *kind, int *patches);
  * two.  Allocates; call before timing or capturing solves. */
 int yyg_prepare(yyg_grid *g, int precision);
 
-/* Solution method of yyg_solve (FP64 only for the separable form).
+/* Solution method of yyg_solve (the separable form in FP64, FP32 or
+ * BF16 x 3; see yyg_solve).
  *  YYG_METHOD_DENSE      the two angular contractions as dense MFMA
  *                        contractions over all angular cells (Eqs. 26-27 and
  *                        5, 28-29 written as matrix products): 2Q + 4Q flops
@@ -164,7 +165,13 @@ int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stre
  * and outer radial sums of Eqs. (19)-(20) at the interfaces, and the
  * synthesis of Eq. (5) with its normalisation (Eqs. 8-9), both patches'
  * moments contributing at every point (Eqs. 28-29).  Output layout as rho.
- * Asynchronous on `stream` when
+ * Precisions: the dense method any that yyg_prepare enabled (FP64 always
+ * is); the separable method FP64, and FP32 or BF16 x 3 for its two phi
+ * transforms (operands converted inside the kernels, FP32 accumulation over
+ * 16-wide stages flushed to FP64; the theta transforms, the rotation and the
+ * radial sums stay FP64; no yyg_prepare needed), YYG_ERR_UNSUPPORTED for
+ * FP16 x 2 (its exponent range would need a per-row scaling the separable
+ * phi transforms do not apply).  Asynchronous on `stream` when
  * phi_is_device != 0 (no host synchronisation, no allocation); with a host
  * `phi` the call copies back and synchronises the stream.  `precision` is a
  * yyg_precision that yyg_prepare has enabled (FP64 always is).  Returns
@@ -258,7 +265,8 @@ int yyg_get_timing(yyg_grid *g, double *ms, long *counts, int n_slots);
  * every candidate on the plan's own shapes (HIP events on `stream`; blocks
  * until done).  Dense method: the tile shape and split-K factor of both
  * angular contractions of `precision`.  Separable method (FP64): the tile
- * variant of each of its five phases, each timed inside whole solves.  Allocates scratch memory for the
+ * variant of each of its five phases, each timed inside whole solves; FP32
+ * or BF16 x 3: the tile shape of the reduced-precision phi transforms.  Allocates scratch memory for the
  * duration of the call and may grow the plan's partial-moment buffer.  With
  * the environment variable YYG_TUNE_CACHE naming a file, earlier choices
  * for the same (precision, shape) are read from it and new ones appended.
@@ -311,6 +319,19 @@ int yyg_sep_info(const yyg_grid *g, int *variants, int n);
  * name[0..n) (truncated if longer); the empty string for phase 2 on a polar
  * grid.  For matching profiles to a plan.  Needs the separable form built. */
 int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n);
+
+/* The kernel that runs phi transform `phase` (0 analysis, 4 synthesis) of
+ * the separable form in `precision` (YYG_FP32 or YYG_BF16X3), named as
+ * profilers print it, NUL-terminated into name[0..n).  Needs the separable
+ * form built. */
+int yyg_sep_lp_kernel(const yyg_grid *g, int precision, int phase, char *name, size_t n);
+
+/* Set the tile of reduced-precision phi transform `phase` (0 or 4) of the
+ * separable form for `precision` (YYG_FP32 or YYG_BF16X3) by hand: tile in
+ * [0, 6) (64 x 80, 128 x 48, 64 x 64, 64 x 32, 32 x 32, 128 x 80).  For tests
+ * and expert tuning; yyg_autotune chooses them.  Needs the separable form
+ * built. */
+int yyg_sep_lp_config(yyg_grid *g, int precision, int phase, int tile);
 
 /* Launch one phase (0-4, as for yyg_sep_config) of the separable solve on
  * `stream`, asynchronously, reading what the earlier phases of the last

@@ -138,6 +138,9 @@ struct yyg_grid {
     // defaults (before autotuning): 32 x 32 tiles, 64 x 32 for the theta
     // synthesis
     int var[5] = {10, 10, 10, 9, 10};
+    // reduced-precision phi transforms (FP32, BF16 x 3): tile of the phi
+    // analysis and of the phi synthesis (yyg::sep_lp_tile_count() shapes)
+    int lpt[2][2] = {{0, 1}, {0, 1}};
   } sep;
 
   bool timing = false;
@@ -635,12 +638,21 @@ int sep_build(yyg_grid *g) {
 // and patch), radial scan into the azimuthal-column-major coefficients,
 // theta synthesis (one problem per azimuthal column), phi synthesis (a
 // strided batch over the colatitudes).
-hipError_t sep_solve(yyg_grid *g, hipStream_t s) {
+// A phi phase (0 or 4) in `precision`: the FP64 variant of the plan, or the
+// plan's reduced-precision tile for FP32 / BF16 x 3.
+hipError_t sep_launch_phi(yyg_grid *g, int r, int precision, hipStream_t s) {
+  auto &S = g->sep;
+  if (precision == YYG_FP64) return sep_launch_phase(g, r, s);
+  const yyg::GemmF64Args &phi = r == 0 ? (S.fold ? S.phi_ana_f : S.phi_ana) : (S.fold ? S.phi_syn_f : S.phi_syn);
+  return yyg::launch_sep_lp_phase(precision, S.lpt[precision - 1][r == 0 ? 0 : 1], r, S.fold, phi, s);
+}
+
+hipError_t sep_solve(yyg_grid *g, hipStream_t s, int precision = YYG_FP64) {
   auto &S = g->sep;
   hipError_t e = hipSuccess;
   g->ahat_cols = true;
   int t = timing_begin(g, 4, s);
-  e = sep_launch_phase(g, 0, s);
+  e = sep_launch_phi(g, 0, precision, s);
   timing_end(g, t, s);
   // the scan's input: the moments, or with two patches their rotated sum
   const double *scan_in = g->n_patch == 2 ? S.At : g->d_Ahat;
@@ -662,7 +674,7 @@ hipError_t sep_solve(yyg_grid *g, hipStream_t s) {
   }
   if (e == hipSuccess) {
     t = timing_begin(g, 7, s);
-    e = sep_launch_phase(g, 4, s);
+    e = sep_launch_phi(g, 4, precision, s);
     timing_end(g, t, s);
   }
   return e;
@@ -1390,7 +1402,11 @@ int yyg_upload_rho(yyg_grid *g, const double *rho, int rho_is_device, void *stre
 int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *stream) {
   if (!g || !phi) return YYG_ERR_INVALID_ARG;
   if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
-  if (precision != YYG_FP64 && !g->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
+  const bool sep_form = g->method == YYG_METHOD_SEPARABLE;
+  // the separable form converts its operands in the kernels (nothing to
+  // prepare); FP16's exponent range would need row scaling it does not do
+  if (sep_form && precision == YYG_FP16X2) return YYG_ERR_UNSUPPORTED;
+  if (!sep_form && precision != YYG_FP64 && !g->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
   if (!g->rho) return YYG_ERR_NOT_READY;
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
@@ -1408,16 +1424,12 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
   const bool lp = precision != YYG_FP64;
   const bool scaled = precision == YYG_FP16X2;
   if (g->method == YYG_METHOD_SEPARABLE) {
-    if (lp) {
-      if (tmp) (void)hipFree(tmp);
-      return YYG_ERR_UNSUPPORTED;
-    }
     int st = sep_set_pointers(g, g->rho, out, s);
     if (st != YYG_OK) {
       if (tmp) (void)hipFree(tmp);
       return st;
     }
-    e = sep_solve(g, s);
+    e = sep_solve(g, s, precision);
     if (!phi_is_device) {
       if (e == hipSuccess)
         e = hipMemcpyAsync(phi, out, (size_t)M * g->nang * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1636,10 +1648,50 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   if (!g) return YYG_ERR_INVALID_ARG;
   if (precision < 0 || precision > YYG_FP16X2) return YYG_ERR_INVALID_ARG;
   const bool lp = precision != YYG_FP64;
-  if (lp && !g->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
+  const bool sep_form = g->method == YYG_METHOD_SEPARABLE;
+  if (sep_form && precision == YYG_FP16X2) return YYG_ERR_UNSUPPORTED;
+  if (lp && !sep_form && !g->lp[precision - 1].ready) return YYG_ERR_NOT_READY;
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   hipStream_t s = as_stream(stream);
+  if (lp && sep_form) {
+    // the reduced-precision phi transforms of the separable form: each
+    // tile shape timed inside whole solves, phi analysis then synthesis
+    if (!g->sep.ready) return YYG_ERR_NOT_READY;
+    const long Mt = (long)g->n_patch * g->n_r;
+    double *phi_t = nullptr, *rho_t = nullptr;
+    int st = dmalloc(&phi_t, (size_t)Mt * g->nang);
+    if (st == YYG_OK && !g->rho) {
+      st = dmalloc(&rho_t, (size_t)Mt * g->nang);
+      if (st == YYG_OK) (void)hipMemsetAsync(rho_t, 0, (size_t)Mt * g->nang * sizeof(double), s);
+    }
+    if (st == YYG_OK) st = sep_set_pointers(g, g->rho ? g->rho : rho_t, phi_t, s);
+    const bool timing = g->timing;
+    g->timing = false;
+    auto solve_ms = [&]() { return time_launch([&] { return sep_solve(g, s, precision); }, s, 5); };
+    for (int r = 0; r < 2 && st == YYG_OK; ++r) {
+      int &cur = g->sep.lpt[precision - 1][r];
+      int best = cur;
+      double bt = solve_ms() - 1e-4;
+      const int t0 = cur;
+      for (int t = 0; t < yyg::sep_lp_tile_count(); ++t) {
+        if (t == t0) continue;
+        cur = t;
+        const double tm = solve_ms();
+        if (tm < bt) {
+          bt = tm;
+          best = t;
+        }
+      }
+      cur = best;
+    }
+    g->timing = timing;
+    (void)hipStreamSynchronize(s);
+    if (phi_t) (void)hipFree(phi_t);
+    if (rho_t) (void)hipFree(rho_t);
+    sep_set_pointers(g, nullptr, nullptr, s);
+    return st;
+  }
   const int Q = g->Q;
   const long M = (long)g->n_patch * g->n_r;
   int *cur_va = lp ? &g->lp[precision - 1].var_ana : &g->var_ana;
@@ -1658,7 +1710,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
   int best_va = *cur_va, best_sp = *cur_sp, best_vs = *cur_vs;
   // a plan in the separable form tunes that form's phases only (FP64): the
   // dense contractions keep their configuration
-  const bool sep_only = !lp && g->method == YYG_METHOD_SEPARABLE;
+  const bool sep_only = !lp && sep_form;
   bool have_a = sep_only, have_s = sep_only;
   if (!sep_only && cache.count(ka)) {
     best_va = cache[ka].first;
@@ -1923,6 +1975,25 @@ int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
   const int r = v >= x0 ? yyg::x4_kernel_name(v - x0, phase, g->sep.fold, name, n)
                         : yyg::sep_kernel_name(phase, v, g->sep.fold, name, n);
   return r == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
+}
+
+int yyg_sep_lp_config(yyg_grid *g, int precision, int phase, int tile) {
+  if (!g || (phase != 0 && phase != 4)) return YYG_ERR_INVALID_ARG;
+  if (precision != YYG_FP32 && precision != YYG_BF16X3) return YYG_ERR_INVALID_ARG;
+  if (tile < 0 || tile >= yyg::sep_lp_tile_count()) return YYG_ERR_INVALID_ARG;
+  if (!g->sep.ready) return YYG_ERR_NOT_READY;
+  g->sep.lpt[precision - 1][phase == 0 ? 0 : 1] = tile;
+  return YYG_OK;
+}
+
+int yyg_sep_lp_kernel(const yyg_grid *g, int precision, int phase, char *name, size_t n) {
+  if (!g || !name || n < 1 || (phase != 0 && phase != 4)) return YYG_ERR_INVALID_ARG;
+  if (precision != YYG_FP32 && precision != YYG_BF16X3) return YYG_ERR_INVALID_ARG;
+  if (!g->sep.ready) return YYG_ERR_NOT_READY;
+  return yyg::sep_lp_kernel_name(precision, g->sep.lpt[precision - 1][phase == 0 ? 0 : 1], phase, g->sep.fold, name,
+                                 n) == 0
+             ? YYG_OK
+             : YYG_ERR_INVALID_ARG;
 }
 
 int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out) {

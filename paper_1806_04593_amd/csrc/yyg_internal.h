@@ -63,6 +63,12 @@ struct GemmF64Args {
 //               column-major C + j c_split_stride
 //  kGemmNFast   strided batch: a problem's tiles are numbered N-fastest (the
 //               blocks that share an A tile run together and share L2)
+//  kGemmLpF32   the operands rounded to FP32 on their way into LDS, FP32
+//               MFMA (16x16x4) with FP32 accumulation over each 16-wide stage,
+//               flushed into FP64 accumulators after every stage
+//  kGemmLpBF3   the same with each operand split into three BF16 parts
+//               (x = x0 + x1 + x2, each the rounding of the remainder) and the
+//               six part products of order < 3 on the 16x16x16 BF16 MFMA
 //  kGemmX4      v_mfma_f64_4x4x4f64 instead of the 16x16x4 form: measured on
 //               MI355X it runs at ~92% of the FP64 matrix peak where the
 //               16x16x4 form stops at ~62%, for four times the operand
@@ -80,7 +86,9 @@ enum {
   kGemmAccInit = 1024,
   kGemmX4 = 2048,
   kGemmFoldAB = 4096,
-  kGemmNFast = 8192
+  kGemmNFast = 8192,
+  kGemmLpF32 = 16384,
+  kGemmLpBF3 = 32768
 };
 // role offset of the kGemmDeep forms of the batched roles
 constexpr int kRoleDeep = 16;
@@ -266,6 +274,14 @@ constexpr size_t kScanQMaxLds = 160 * 1024;
 size_t radial_scan_q_lds(int nR, int patches);
 hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int *qdeg, int nR, int L, double negG,
                                 int patches, double *Ut, hipStream_t s);
+
+// The separable form's phi transforms in a reduced precision (prec 1 = FP32,
+// 2 = BF16 x 3; the operands are FP64 in memory and converted in the tile):
+// sep_lp_tile_count() tile shapes; phase 0 / 4 as launch_gemm_f64_batched
+// roles 2 / 3 (fold) or 0 / 1.
+int sep_lp_tile_count();
+hipError_t launch_sep_lp_phase(int prec, int tile, int phase, bool fold, const GemmF64Args &phi, hipStream_t s);
+int sep_lp_kernel_name(int prec, int tile, int phase, bool fold, char *buf, size_t n);
 
 // Batched separable solves: one plan's column scan (as launch_radial_scan_q)
 // per entry; chunk = ((nR + 63) / 64) | 1, P patches.

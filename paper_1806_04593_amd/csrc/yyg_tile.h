@@ -64,7 +64,11 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr bool FOLDC = (MODE & kGemmFoldC) != 0;
   constexpr bool DT = (MODE & kGemmDT) != 0;
   constexpr bool X4 = (MODE & kGemmX4) != 0;
+  constexpr bool LPF32 = (MODE & kGemmLpF32) != 0;
+  constexpr bool LPBF3 = (MODE & kGemmLpBF3) != 0;
+  constexpr bool LP = LPF32 || LPBF3;
   static_assert(!ACCINIT || GEN, "the initial accumulator is addressed like C");
+  static_assert(!LP || (!X4 && !FOLDAB && !ACCINIT && !(LPF32 && LPBF3)), "reduced precision: the 16x16 phi forms");
   static_assert(!DT || !FOLDC, "the folded synthesis stores rows");
   static_assert(!FOLDA || (BATCH && CT && !AT && !GEN), "folded analysis: batched, row-major A, C column-major");
   static_assert(!FOLDC || (BATCH && AT && !CT && !GEN), "folded synthesis: batched, A k-major");
@@ -97,9 +101,45 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr bool RUN_B = !BT && (BN * kBK) % NT == 0 && kBK % ((BN * kBK) / NT) == 0;
   constexpr int EA = RUN_A ? (BM * kBK) / NT : (BM * kBK + NT - 1) / NT;
   constexpr int EB = RUN_B ? (BN * kBK) / NT : (BN * kBK + NT - 1) / NT;
-  __shared__ double As[2][BM * kLDK];
+  __shared__ double As[LP ? 1 : 2][LP ? 1 : BM * kLDK];
   __shared__ double Ao[FOLDAB ? 2 : 1][FOLDAB ? BM * kLDK : 1];  // FOLDAB: the odd half of A
-  __shared__ double Bs[2][BN * kLDK];
+  __shared__ double Bs[LP ? 1 : 2][LP ? 1 : BN * kLDK];
+  // reduced precisions: the stages as FP32 values, or as three BF16 planes
+  // (bit patterns) with rows of kLDH
+  constexpr int kLDH = kBK + 4;
+  __shared__ float AsF[LPF32 ? 2 : 1][LPF32 ? BM * kLDK : 1];
+  __shared__ float BsF[LPF32 ? 2 : 1][LPF32 ? BN * kLDK : 1];
+  __shared__ __attribute__((aligned(16))) short AsH[LPBF3 ? 2 : 1][LPBF3 ? 3 : 1][LPBF3 ? BM * kLDH : 1];
+  __shared__ __attribute__((aligned(16))) short BsH[LPBF3 ? 2 : 1][LPBF3 ? 3 : 1][LPBF3 ? BN * kLDH : 1];
+  // store one stage element (row, column within the stage) of A / B
+  auto bf16_bits = [](double x) -> short {
+    // round to nearest even of the FP32 rounding of x (|x| within FP32's
+    // range; the remainders of a split are exact in FP64)
+    const float f = (float)x;
+    unsigned u = __builtin_bit_cast(unsigned, f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+  };
+  auto bf16_val = [](short h) -> double {
+    return (double)__builtin_bit_cast(float, (unsigned)(unsigned short)h << 16);
+  };
+  auto put = [&](auto &F64, auto &F32, auto &H, int buf, int row, int col, double v) {
+    if constexpr (LPF32) {
+      F32[buf][row * kLDK + col] = (float)v;
+    } else if constexpr (LPBF3) {
+      const short h0 = bf16_bits(v);
+      const double r1 = v - bf16_val(h0);
+      const short h1 = bf16_bits(r1);
+      const short h2 = bf16_bits(r1 - bf16_val(h1));
+      H[buf][0][row * kLDH + col] = h0;
+      H[buf][1][row * kLDH + col] = h1;
+      H[buf][2][row * kLDH + col] = h2;
+    } else {
+      F64[buf][row * kLDK + col] = v;
+    }
+  };
+  auto putA = [&](int buf, int row, int col, double v) { put(As, AsF, AsH, buf, row, col, v); };
+  auto putB = [&](int buf, int row, int col, double v) { put(Bs, BsF, BsH, buf, row, col, v); };
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = tm * BM, n0 = tn * BN;
@@ -258,14 +298,14 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const bool ok = va && k0 + acol + i < kend;
-        As[buf][arow * kLDK + acol + i] = ok ? aval(ra, i) : 0.0;
+        putA(buf, arow, acol + i, ok ? aval(ra, i) : 0.0);
         if constexpr (FOLDAB) Ao[FOLDAB ? buf : 0][arow * kLDK + acol + i] = ok ? aval_o(ra, i) : 0.0;
       }
     } else if constexpr (AT) {
 #pragma unroll
       for (int i = 0; i < EA; ++i) {
         const int e = tid + i * NT, kk = k0 + e / BM, gm = m0 + e % BM;
-        if (e < BM * kBK) As[buf][(e % BM) * kLDK + e / BM] = (gm < M && kk < kend) ? ra[i] : 0.0;
+        if (e < BM * kBK) putA(buf, e % BM, e / BM, (gm < M && kk < kend) ? ra[i] : 0.0);
       }
     } else {
 #pragma unroll
@@ -273,25 +313,25 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
         if (e < BM * kBK) {
           const bool ok = m0 + row < M && kk < kend;
-          As[buf][row * kLDK + e % kBK] = ok ? aval(ra, i) : 0.0;
+          putA(buf, row, e % kBK, ok ? aval(ra, i) : 0.0);
           if constexpr (FOLDAB) Ao[FOLDAB ? buf : 0][row * kLDK + e % kBK] = ok ? aval_o(ra, i) : 0.0;
         }
       }
     }
     if constexpr (RUN_B) {
 #pragma unroll
-      for (int i = 0; i < EB; ++i) Bs[buf][brow * kLDK + bcol + i] = (vb && k0 + bcol + i < kend) ? rb[i] : 0.0;
+      for (int i = 0; i < EB; ++i) putB(buf, brow, bcol + i, (vb && k0 + bcol + i < kend) ? rb[i] : 0.0);
     } else if constexpr (BT) {
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
         const int e = tid + i * NT, kk = k0 + e / BN, gn = n0 + e % BN;
-        if (e < BN * kBK) Bs[buf][(e % BN) * kLDK + e / BN] = (gn < N && kk < kend) ? rb[i] : 0.0;
+        if (e < BN * kBK) putB(buf, e % BN, e / BN, (gn < N && kk < kend) ? rb[i] : 0.0);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < EB; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
-        if (e < BN * kBK) Bs[buf][row * kLDK + e % kBK] = (n0 + row < N && kk < kend) ? rb[i] : 0.0;
+        if (e < BN * kBK) putB(buf, row, e % kBK, (n0 + row < N && kk < kend) ? rb[i] : 0.0);
       }
     }
   };
@@ -382,9 +422,77 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
           }
     }
   };
+  // reduced precisions: FP32-accumulating 16x16 MFMAs over the stage, then
+  // the stage's sums added to the FP64 accumulators (D layout of these
+  // MFMAs: lane l, element r -> row 4 (l/16) + r, col l % 16; DT swaps)
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  typedef short s16x4 __attribute__((ext_vector_type(4)));
+  auto compute_lp = [&](int buf, bool second) {
+    f32x4 lacc[TIa][TJa];
+#pragma unroll
+    for (int i = 0; i < TIa; ++i)
+#pragma unroll
+      for (int j = 0; j < TJa; ++j) lacc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (LPF32) {
+      float af[TIa][4], bf[TJa][4];
+#pragma unroll
+      for (int i = 0; i < TIa; ++i)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) af[i][s4] = AsF[buf][(wm * (BM / WGM) + i * 16 + frow) * kLDK + fk + s4];
+#pragma unroll
+      for (int j = 0; j < TJa; ++j)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) bf[j][s4] = BsF[buf][(wn * (BN / WGN) + j * 16 + frow) * kLDK + fk + s4];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int i = 0; i < TIa; ++i)
+#pragma unroll
+          for (int j = 0; j < TJa; ++j)
+            lacc[i][j] = DT ? __builtin_amdgcn_mfma_f32_16x16x4f32(bf[j][s4], af[i][s4], lacc[i][j], 0, 0, 0)
+                            : __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s4], bf[j][s4], lacc[i][j], 0, 0, 0);
+    } else if constexpr (LPBF3) {
+      // each lane's four consecutive k of its row are one 16x16x16 operand
+      s16x4 ah[TIa][3], bh[TJa][3];
+#pragma unroll
+      for (int i = 0; i < TIa; ++i)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          ah[i][p] = *reinterpret_cast<const s16x4 *>(&AsH[buf][p][(wm * (BM / WGM) + i * 16 + frow) * kLDH + fk]);
+#pragma unroll
+      for (int j = 0; j < TJa; ++j)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          bh[j][p] = *reinterpret_cast<const s16x4 *>(&BsH[buf][p][(wn * (BN / WGN) + j * 16 + frow) * kLDH + fk]);
+#pragma unroll
+      for (int i = 0; i < TIa; ++i)
+#pragma unroll
+        for (int j = 0; j < TJa; ++j)
+          // part pairs (pa, pb) of order pa + pb < 3, smallest terms first
+#pragma unroll
+          for (int ord = 2; ord >= 0; --ord)
+#pragma unroll
+            for (int pa = 0; pa <= ord; ++pa)
+              lacc[i][j] = DT ? __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh[j][ord - pa], ah[i][pa], lacc[i][j], 0, 0, 0)
+                              : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i][pa], bh[j][ord - pa], lacc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < TIa; ++i)
+#pragma unroll
+      for (int j = 0; j < TJa; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (FOLDC && second)
+            acc2[FOLDC ? i : 0][FOLDC ? j : 0][r] += (double)lacc[i][j][r];
+          else
+            acc[i][j][r] += (double)lacc[i][j][r];
+        }
+  };
   auto compute = [&](int buf, bool second) {
     if constexpr (X4)
       compute4(buf, second);
+    else if constexpr (LP)
+      compute_lp(buf, second);
     else
       compute16(buf, second);
   };
@@ -457,8 +565,10 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
     for (int j = 0; j < TJa; ++j) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * (BM / WGM) + i * 16 + (DT ? ocol : orow + 4 * r);
-        const int col = n0 + wn * (BN / WGN) + j * 16 + (DT ? orow + 4 * r : ocol);
+        // FP64 MFMA: row l/16 + 4r; FP32-accumulating (LP): row 4 (l/16) + r
+        const int dr = LP ? 4 * orow + r : orow + 4 * r;
+        const int row = m0 + wm * (BM / WGM) + i * 16 + (DT ? ocol : dr);
+        const int col = n0 + wn * (BN / WGN) + j * 16 + (DT ? dr : ocol);
         emit(row, col, acc[i][j][r], FOLDC ? acc2[FOLDC ? i : 0][FOLDC ? j : 0][r] : 0.0);
       }
     }

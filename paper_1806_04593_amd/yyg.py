@@ -29,7 +29,7 @@ EXPORTS = [
     "yyg_batch_create", "yyg_batch_solve", "yyg_batch_destroy", "yyg_status_string",
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
     "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind", "yyg_sep_config", "yyg_sep_info",
-    "yyg_sep_kernel", "yyg_sep_phase", "yyg_solve_noalloc",
+    "yyg_sep_kernel", "yyg_sep_phase", "yyg_solve_noalloc", "yyg_sep_lp_kernel", "yyg_sep_lp_config",
 ]
 
 
@@ -92,6 +92,8 @@ def lib():
         L.yyg_sep_kernel.argtypes = [vp, i, ctypes.c_char_p, ctypes.c_size_t]
         L.yyg_sep_phase.argtypes = [vp, i, vp, vp]
         L.yyg_solve_noalloc.argtypes = [vp, vp, vp, vp]
+        L.yyg_sep_lp_kernel.argtypes = [vp, i, i, ctypes.c_char_p, ctypes.c_size_t]
+        L.yyg_sep_lp_config.argtypes = [vp, i, i, i]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -265,6 +267,12 @@ class Grid:
     def sep_kernel(self, phase):
         buf = ctypes.create_string_buffer(256)
         _check(lib().yyg_sep_kernel(self._h, int(phase), buf, 256), "yyg_sep_kernel")
+        return buf.value.decode()
+
+    def sep_lp_kernel(self, precision, phase):
+        buf = ctypes.create_string_buffer(256)
+        _check(lib().yyg_sep_lp_kernel(self._h, PRECISIONS.get(precision, precision), int(phase), buf, 256),
+               "yyg_sep_lp_kernel")
         return buf.value.decode()
 
     def sep_phase(self, phase, phi, stream=None):

@@ -206,3 +206,19 @@ def test_batch64_full_sizes(precision):
         worst = max(worst, err)
     b.close()
     assert worst <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_binary_separable_reduced_precision(precision):
+    """The separable form with its phi transforms in FP32 / BF16 x 3,
+    autotuned as the benchmark runs it, at the binary workload's samples."""
+    desc, rho, s, ref, *_ = _binary()
+    g, _ = _binary_grid()
+    g.set_method("separable")
+    g.autotune(precision)
+    d_phi = _solve(g, precision)
+    err = _max_rel(_at(d_phi, s), ref)
+    _say(f"binary separable {precision} ({g.sep_lp_kernel(precision, 0)} / {g.sep_lp_kernel(precision, 4)}): "
+         f"max rel err {err:.3e}")
+    assert err <= TOL[precision]
+    g.set_method("dense")

@@ -99,3 +99,70 @@ def test_workload_errors(name):
         _say(f"{name} {precision}: max rel err {errs[precision]:.3e} ({g.plan_info(precision)})")
     for precision, err in errs.items():
         assert err <= TOL[precision], (precision, err)
+
+
+# ---------------------------------------------------------------------------
+# the separable form's phi transforms in FP32 and BF16 x 3 (theta transforms,
+# rotation and radial sums in FP64)
+# ---------------------------------------------------------------------------
+
+N_SEP_LP_TILES = 6
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_separable_reduced_precision_every_tile(precision):
+    """Every reduced-precision tile of both phi transforms on a ragged grid
+    (n_r 37, 9 deg, lmax 11) and the small workload, full grid against the
+    oracle; autotuned tiles on sn_core sampled."""
+    torch = _torch()
+    desc = W.make_desc("edge", np.geomspace(1.0, 50.0, 38), 9.0, 11, 0.9, 0)
+    rng = np.random.default_rng(31)
+    rho = rng.uniform(0.1, 1.0, (2, 37, desc["n_theta"], desc["n_phi"]))
+    ref = O.solve(*_oracle_args(desc), rho)
+    g = _grid(desc)
+    g.set_method("separable")
+    for phase in (0, 4):
+        for t in range(N_SEP_LP_TILES):
+            _set_lp_tile(g, precision, phase, t)
+            phi = _solve(g, rho, precision)
+            err = float(np.max(np.abs(phi - ref) / np.abs(ref)))
+            _say(f"separable {precision} phase {phase} tile {t} ({g.sep_lp_kernel(precision, phase)}): {err:.3e}")
+            assert err <= TOL[precision], (phase, t, err)
+    for name in ("small", "sn_core"):
+        desc = W.describe(name)
+        rho = W.density(desc)
+        g = _grid(desc)
+        g.set_method("separable")
+        d_rho = torch.from_numpy(rho).to("cuda")
+        g.upload_rho(d_rho)
+        g.autotune(precision)
+        phi = _solve(g, rho, precision)
+        if name == "small":
+            ref = O.solve(*_oracle_args(desc), rho)
+            err = float(np.max(np.abs(phi - ref) / np.abs(ref)))
+        else:
+            s = np.stack([rng.integers(0, 2, 800), rng.integers(0, 400, 800), rng.integers(0, desc["n_theta"], 800),
+                          rng.integers(0, desc["n_phi"], 800)], 1)
+            ref = O.solve_sampled(*_oracle_args(desc), rho, s)
+            got = phi[s[:, 0], s[:, 1], s[:, 2], s[:, 3]]
+            err = float(np.max(np.abs(got - ref) / np.abs(ref)))
+        _say(f"separable {precision} {name}: {err:.3e}")
+        assert err <= TOL[precision], (name, err)
+
+
+def _set_lp_tile(g, precision, phase, t):
+    """Reduced-precision tile t of phi phase `phase` (yyg_sep_lp_config)."""
+    from paper_1806_04593_amd import yyg
+    assert yyg.lib().yyg_sep_lp_config(g.handle, yyg.PRECISIONS[precision], int(phase), int(t)) == 0
+
+
+def test_separable_fp16x2_refused():
+    from paper_1806_04593_amd import yyg
+    _torch()
+    desc = W.describe("small")
+    g = _grid(desc)
+    g.set_method("separable")
+    rho = W.density(desc)
+    with pytest.raises(yyg.YygError) as ei:
+        _solve(g, rho, "fp16x2")
+    assert ei.value.status == -5
