@@ -28,7 +28,10 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "fp16x2": 3}   # MFMA products pe
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "fp16x2": "f16x2"}
 ALL_PRECISIONS = ("fp64", "fp32", "bf16x3", "fp16x2")
 SEP_LP = ("fp32", "bf16x3")   # reduced precisions of the separable form's phi transforms
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1806_04593_amd", "csrc", f) for f in ("yyg_kernels.hip", "yyg_kernels_lp.hip")]
+# every source a timed kernel is compiled from: counter figures taken on other sources are not used
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1806_04593_amd", "csrc", f)
+               for f in ("yyg_tile.h", "yyg_kernels.hip", "yyg_kernels_x4.hip", "yyg_kernels_sep_lp.hip",
+                         "yyg_kernels_lp.hip", "yyg_batch_sep.hip")]
 METRIC = "grid cells/sec per full Phi solve, FP64 vs split-precision, at stated max rel. error"
 
 

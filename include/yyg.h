@@ -38,6 +38,14 @@
  *   `stream` is a hipStream_t (NULL = legacy default stream).  The library
  *   never frees caller memory.
  * - A grid handle is not thread-safe; distinct handles are independent.
+ * - Device memory cap: when the environment variable YYG_MAX_DEVICE_BYTES
+ *   holds a decimal byte count (> 0), an allocation that would take the
+ *   device memory the library holds in this process (every plan and batch
+ *   together; see yyg_device_bytes) past it fails with
+ *   YYG_ERR_OUT_OF_MEMORY before the HIP runtime is asked, and the call
+ *   that needed it releases what it had allocated.  Read at every
+ *   allocation; unset, 0 or not a plain number: no cap.  Pinned host
+ *   memory and the allocation-free solve's scratch array are not counted.
  */
 #ifndef YYG_H
 #define YYG_H
@@ -55,7 +63,8 @@ typedef enum {
   YYG_ERR_DEVICE = -3,        /* a HIP runtime call or kernel launch failed       */
   YYG_ERR_NOT_READY = -4,     /* solve before upload, or precision not prepared  */
   YYG_ERR_UNSUPPORTED = -5,   /* valid request this build does not implement     */
-  YYG_ERR_NONFINITE = -6      /* reserved for input checks                       */
+  YYG_ERR_NONFINITE = -6      /* the density holds a NaN or an infinity (the check
+                                 of yyg_set_check_finite, off by default)          */
 } yyg_status;
 
 /* Arithmetic of the two angular contractions (analysis and synthesis).  The
@@ -199,6 +208,21 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
  * P' = 2 on a Yin-Yang grid, 1 on the polar grid), each part rounded up to
  * 256 bytes: e.g. 48 MB at n_r 400, 2 deg, lmax 25. */
 int yyg_solve_noalloc(yyg_grid *g, const double *rho, double *phi, void *stream);
+
+/* Opt-in input check (engineering safeguard, not part of the method):
+ * with on != 0, yyg_solve, yyg_solve_noalloc and yyg_batch_solve (for each
+ * field whose plan has it on) first scan the density for NaN and infinite
+ * values on the solve's stream and return YYG_ERR_NONFINITE without
+ * touching phi if they find one.  The check reads the density once more
+ * (8 bytes per cell) and waits for its one-int result, so such a solve
+ * synchronises the stream.  Turning it on allocates a 4-byte device flag
+ * (YYG_ERR_OUT_OF_MEMORY / YYG_ERR_DEVICE on failure); off (the default)
+ * costs nothing. */
+int yyg_set_check_finite(yyg_grid *g, int on);
+
+/* Bytes of device memory the library holds in this process (plans, their
+ * work buffers and batches; the figure YYG_MAX_DEVICE_BYTES caps). */
+int yyg_device_bytes(size_t *held);
 
 /* Debug/test export after a synchronised solve: the angular moments
  * A[p][i][q] of Eqs. (26)-(27) (A_C in cos columns, A_S in sin columns) for

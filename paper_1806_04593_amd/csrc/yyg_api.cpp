@@ -10,7 +10,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <new>
 #include <vector>
 
@@ -27,6 +29,55 @@ struct TimedLaunch {
 };
 
 long round_up(long v, long m) { return (v + m - 1) / m * m; }
+
+// Device memory the library holds, process-wide, against an optional cap:
+// the environment variable YYG_MAX_DEVICE_BYTES (a decimal byte count; unset,
+// empty, 0 or not a plain number: no cap), read at every allocation.  An
+// allocation that would take the total past the cap fails like a failed
+// hipMalloc, before the runtime is asked.
+std::mutex g_mem_mu;
+std::unordered_map<void *, size_t> g_mem_sizes;
+size_t g_mem_held = 0;
+
+size_t mem_cap() {
+  const char *e = std::getenv("YYG_MAX_DEVICE_BYTES");
+  if (!e || !*e) return 0;
+  char *end = nullptr;
+  const unsigned long long v = std::strtoull(e, &end, 10);
+  return (end && *end == '\0' && e[0] != '-') ? (size_t)v : 0;
+}
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+  std::lock_guard<std::mutex> lock(g_mem_mu);
+  const size_t cap = mem_cap();
+  if (cap && (bytes > cap || g_mem_held > cap - bytes)) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  if (*p) {
+    g_mem_sizes[*p] = bytes;
+    g_mem_held += bytes;
+  }
+  return hipSuccess;
+}
+
+hipError_t dev_free(void *p) {
+  if (!p) return hipSuccess;
+  {
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    auto it = g_mem_sizes.find(p);
+    if (it != g_mem_sizes.end()) {
+      g_mem_held -= it->second;
+      g_mem_sizes.erase(it);
+    }
+  }
+  return hipFree(p);
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -66,6 +117,9 @@ struct yyg_grid {
   bool ahat_cols = false;    // d_Ahat holds the column-major layout
   double *d_U = nullptr;     // synthesis operand [P n_r][ldy]
   double *d_rho_owned = nullptr;
+  // opt-in check of the density for NaN / infinity before each solve
+  bool check_finite = false;
+  int *d_flag = nullptr;
   const double *rho = nullptr;
 
   // reduced-precision tables, index prec - 1 (FP32, BF16x3, FP16x2)
@@ -149,45 +203,43 @@ struct yyg_grid {
 
 namespace {
 
-int validate(const yyg_grid_desc *d) {
-  if (!d || !d->r_edges) return YYG_ERR_INVALID_ARG;
-  if (d->kind != YYG_GRID_YINYANG && d->kind != YYG_GRID_POLAR) return YYG_ERR_INVALID_ARG;
-  if (d->kind == YYG_GRID_POLAR && (d->delta_theta != 0.0 || d->delta_phi != 0.0)) return YYG_ERR_INVALID_ARG;
-  if (d->n_r < 1 || d->n_theta < 1 || d->n_phi < 1) return YYG_ERR_INVALID_ARG;
-  if (d->lmax < 0 || d->lmax > YYG_LMAX_CAP) return YYG_ERR_INVALID_ARG;
-  const double q = 0.78539816339744830962;
-  if (!(d->delta_theta >= 0.0 && d->delta_theta < q) || !(d->delta_phi >= 0.0 && d->delta_phi < q))
-    return YYG_ERR_INVALID_ARG;
-  if (!std::isfinite(d->G)) return YYG_ERR_INVALID_ARG;
-  if (!(d->r_edges[0] >= 0.0) || !std::isfinite(d->r_edges[0])) return YYG_ERR_INVALID_ARG;
-  for (int i = 0; i < d->n_r; ++i)
-    if (!(d->r_edges[i + 1] > d->r_edges[i]) || !std::isfinite(d->r_edges[i + 1])) return YYG_ERR_INVALID_ARG;
-  if ((long)d->n_theta * d->n_phi > (1L << 26)) return YYG_ERR_INVALID_ARG;
-  return YYG_OK;
-}
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Release the separable form's device buffers (after a failed build too,
+// so that a retry starts from nothing).
+void sep_release(yyg_grid *g) {
+  auto &S = g->sep;
+  double **b[] = {&S.Wcs, &S.trig, &S.T2, &S.P2, &S.Drot, &S.X2, &S.V,   &S.Ut,
+                  &S.coefS, &S.At, &S.WF, &S.TF, &S.WFD, &S.TFD, &S.BK, &S.WFAB};
+  for (double **x : b) {
+    if (*x) (void)dev_free(*x);
+    *x = nullptr;
+  }
+}
+
+// Release the operand planes of one reduced precision of the dense form.
+template <class LpPlan>
+void lp_release(LpPlan &l) {
+  void **b[] = {reinterpret_cast<void **>(&l.Bt), reinterpret_cast<void **>(&l.eBt), reinterpret_cast<void **>(&l.Y),
+                reinterpret_cast<void **>(&l.eY), reinterpret_cast<void **>(&l.Ar), reinterpret_cast<void **>(&l.Ur)};
+  for (void **x : b) {
+    if (*x) (void)dev_free(*x);
+    *x = nullptr;
+  }
+}
 
 void free_grid(yyg_grid *g) {
   if (!g) return;
   double *bufs[] = {g->d_Bt, g->d_Y, g->d_coef, g->d_part, g->d_Ahat, g->d_U, g->d_rho_owned};
+  (void)dev_free(g->d_flag);
   for (double *b : bufs)
-    if (b) (void)hipFree(b);
-  if (g->d_qdeg) (void)hipFree(g->d_qdeg);
-  for (auto &l : g->lp) {
-    void *b[] = {l.Bt, l.eBt, l.Y, l.eY, l.Ar, l.Ur};
-    for (void *x : b)
-      if (x) (void)hipFree(x);
-  }
-  if (g->d_eA) (void)hipFree(g->d_eA);
-  if (g->d_eU) (void)hipFree(g->d_eU);
-  {
-    void *b[] = {g->sep.Wcs, g->sep.trig, g->sep.T2,    g->sep.P2, g->sep.Drot, g->sep.X2,
-                 g->sep.V,   g->sep.Ut,   g->sep.coefS, g->sep.At, g->sep.WF, g->sep.TF,
-                 g->sep.WFD, g->sep.TFD, g->sep.BK, g->sep.WFAB};
-    for (void *x : b)
-      if (x) (void)hipFree(x);
-  }
+    if (b) (void)dev_free(b);
+  if (g->d_qdeg) (void)dev_free(g->d_qdeg);
+  for (auto &l : g->lp) lp_release(l);
+  if (g->d_eA) (void)dev_free(g->d_eA);
+  if (g->d_eU) (void)dev_free(g->d_eU);
+  sep_release(g);
   for (auto &t : g->launches) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -197,7 +249,7 @@ void free_grid(yyg_grid *g) {
 
 template <class T>
 int dmalloc(T **p, size_t count) {
-  if (hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)) != hipSuccess) {
+  if (dev_malloc(reinterpret_cast<void **>(p), count * sizeof(T)) != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
     return YYG_ERR_OUT_OF_MEMORY;
@@ -561,7 +613,10 @@ int sep_build(yyg_grid *g) {
   if (st == YYG_OK && S.fold) st = dmalloc(&S.TFD, TFD.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.BK, BK.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.WFAB, WFAB.size());
-  if (st != YYG_OK) return st;
+  if (st != YYG_OK) {
+    sep_release(g);
+    return st;
+  }
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
     if (e == hipSuccess && r != hipSuccess) e = r;
@@ -582,6 +637,7 @@ int sep_build(yyg_grid *g) {
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    sep_release(g);
     return YYG_ERR_DEVICE;
   }
   auto kround = [](long k) { return (int)((k + 15) / 16 * 16); };
@@ -640,6 +696,23 @@ int sep_build(yyg_grid *g) {
 // strided batch over the colatitudes).
 // A phi phase (0 or 4) in `precision`: the FP64 variant of the plan, or the
 // plan's reduced-precision tile for FP32 / BF16 x 3.
+// The opt-in input check: YYG_ERR_NONFINITE if rho holds a NaN or an
+// infinity, YYG_OK if not or if the check is off.  Waits for the check on
+// stream s; allocates nothing (the flag is the plan's).
+int check_rho(yyg_grid *g, const double *rho, hipStream_t s) {
+  if (!g->check_finite) return YYG_OK;
+  const long n = (long)g->n_patch * g->n_r * g->nang;
+  int h = 0;
+  hipError_t e = yyg::launch_check_finite(rho, n, g->d_flag, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, g->d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return YYG_ERR_DEVICE;
+  }
+  return h ? YYG_ERR_NONFINITE : YYG_OK;
+}
+
 hipError_t sep_launch_phi(yyg_grid *g, int r, int precision, hipStream_t s) {
   auto &S = g->sep;
   if (precision == YYG_FP64) return sep_launch_phase(g, r, s);
@@ -742,19 +815,19 @@ void batch_free(yyg_batch *b) {
     if (b->h_split[r]) (void)hipHostFree(b->h_split[r]);
     void *d[] = {b->d_f64[r], b->d_lp[r], b->d_split[r], b->d_items[r], b->d_split_items[r]};
     for (void *x : d)
-      if (x) (void)hipFree(x);
+      if (x) (void)dev_free(x);
   }
-  if (b->d_scan) (void)hipFree(b->d_scan);
-  if (b->d_scan_items) (void)hipFree(b->d_scan_items);
+  if (b->d_scan) (void)dev_free(b->d_scan);
+  if (b->d_scan_items) (void)dev_free(b->d_scan_items);
   for (int r = 0; r < 2; ++r) {
     if (b->h_phi[r]) (void)hipHostFree(b->h_phi[r]);
-    if (b->d_phi[r]) (void)hipFree(b->d_phi[r]);
+    if (b->d_phi[r]) (void)dev_free(b->d_phi[r]);
   }
   for (int r = 0; r < 5; ++r)
-    if (b->d_sitems[r]) (void)hipFree(b->d_sitems[r]);
-  if (b->d_sargs) (void)hipFree(b->d_sargs);
-  if (b->d_qscan) (void)hipFree(b->d_qscan);
-  if (b->d_qitems) (void)hipFree(b->d_qitems);
+    if (b->d_sitems[r]) (void)dev_free(b->d_sitems[r]);
+  if (b->d_sargs) (void)dev_free(b->d_sargs);
+  if (b->d_qscan) (void)dev_free(b->d_qscan);
+  if (b->d_qitems) (void)dev_free(b->d_qitems);
   if (b->done) (void)hipEventDestroy(b->done);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
@@ -762,10 +835,10 @@ void batch_free(yyg_batch *b) {
 
 template <class T>
 int upload(T **dst, const std::vector<T> &src) {
-  if (*dst) (void)hipFree(*dst);
+  if (*dst) (void)dev_free(*dst);
   *dst = nullptr;
   if (src.empty()) return YYG_OK;
-  if (hipMalloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T)) != hipSuccess) {
+  if (dev_malloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T)) != hipSuccess) {
     *dst = nullptr;
     (void)hipGetLastError();
     return YYG_ERR_OUT_OF_MEMORY;
@@ -901,14 +974,14 @@ int batch_build(yyg_batch *b) {
     if (lp) {
       if (hipHostMalloc(reinterpret_cast<void **>(&b->h_lp[r]), n * sizeof(yyg::GemmLpArgs), 0) != hipSuccess ||
           hipHostMalloc(reinterpret_cast<void **>(&b->h_split[r]), n * sizeof(yyg::SplitArgs), 0) != hipSuccess ||
-          hipMalloc(reinterpret_cast<void **>(&b->d_lp[r]), n * sizeof(yyg::GemmLpArgs)) != hipSuccess ||
-          hipMalloc(reinterpret_cast<void **>(&b->d_split[r]), n * sizeof(yyg::SplitArgs)) != hipSuccess) {
+          dev_malloc(reinterpret_cast<void **>(&b->d_lp[r]), n * sizeof(yyg::GemmLpArgs)) != hipSuccess ||
+          dev_malloc(reinterpret_cast<void **>(&b->d_split[r]), n * sizeof(yyg::SplitArgs)) != hipSuccess) {
         (void)hipGetLastError();
         return YYG_ERR_OUT_OF_MEMORY;
       }
     } else {
       if (hipHostMalloc(reinterpret_cast<void **>(&b->h_f64[r]), n * sizeof(yyg::GemmF64Args), 0) != hipSuccess ||
-          hipMalloc(reinterpret_cast<void **>(&b->d_f64[r]), n * sizeof(yyg::GemmF64Args)) != hipSuccess) {
+          dev_malloc(reinterpret_cast<void **>(&b->d_f64[r]), n * sizeof(yyg::GemmF64Args)) != hipSuccess) {
         (void)hipGetLastError();
         return YYG_ERR_OUT_OF_MEMORY;
       }
@@ -1028,7 +1101,7 @@ int sep_batch_build(yyg_batch *b) {
   for (int f = 0; f < n; ++f) b->sep_fold = b->sep_fold && b->grids[f]->sep.fold;
   for (int r = 0; r < 2; ++r)
     if (hipHostMalloc(reinterpret_cast<void **>(&b->h_phi[r]), n * sizeof(yyg::GemmF64Args), 0) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&b->d_phi[r]), n * sizeof(yyg::GemmF64Args)) != hipSuccess) {
+        dev_malloc(reinterpret_cast<void **>(&b->d_phi[r]), n * sizeof(yyg::GemmF64Args)) != hipSuccess) {
       (void)hipGetLastError();
       return YYG_ERR_OUT_OF_MEMORY;
     }
@@ -1095,71 +1168,10 @@ hipError_t sep_batch_enqueue(yyg_batch *b, hipStream_t s, hipEvent_t *ev) {
 
 extern "C" {
 
-const char *yyg_status_string(int status) {
-  switch (status) {
-    case YYG_OK: return "ok";
-    case YYG_ERR_INVALID_ARG: return "invalid argument";
-    case YYG_ERR_OUT_OF_MEMORY: return "out of memory";
-    case YYG_ERR_DEVICE: return "HIP device error";
-    case YYG_ERR_NOT_READY: return "not ready (no density uploaded or precision not prepared)";
-    case YYG_ERR_UNSUPPORTED: return "unsupported";
-    case YYG_ERR_NONFINITE: return "non-finite input";
-    default: return "unknown status";
-  }
-}
-
-int yyg_host_table(const yyg_grid_desc *d, int which, double *out, size_t n) {
-  int st = validate(d);
-  if (st != YYG_OK) return st;
-  if (!out) return YYG_ERR_INVALID_ARG;
-  const int L = d->lmax, Q = (L + 1) * (L + 1);
-  const size_t nang = (size_t)d->n_theta * d->n_phi;
-  yyg::PatchGeom g = d->kind == YYG_GRID_POLAR ? yyg::make_polar_patch(d->n_theta, d->n_phi)
-                                               : yyg::make_patch(d->n_theta, d->n_phi, d->delta_theta, d->delta_phi);
-  try {
-    switch (which) {
-      case YYG_TABLE_WEIGHTS:
-        if (n != nang) return YYG_ERR_INVALID_ARG;
-        yyg::overlap_weights(g, out);
-        return YYG_OK;
-      case YYG_TABLE_THETA: {
-        if (n != (size_t)d->n_theta * Q) return YYG_ERR_INVALID_ARG;
-        yyg::theta_table_normalised(g, L, out);
-        auto s = yyg::norm_sqrt(L);
-        auto cols = yyg::column_table(L);
-        for (int j = 0; j < d->n_theta; ++j)
-          for (int q = 0; q < Q; ++q) out[(size_t)j * Q + q] /= s[cols[q].l * (L + 1) + cols[q].m];
-        return YYG_OK;
-      }
-      case YYG_TABLE_PHI:
-        if (n != (size_t)d->n_phi * Q) return YYG_ERR_INVALID_ARG;
-        yyg::phi_table(g, L, out);
-        return YYG_OK;
-      case YYG_TABLE_RADIAL:
-        if (n != (size_t)4 * d->n_r * (L + 1)) return YYG_ERR_INVALID_ARG;
-        yyg::radial_coefficients(d->n_r, d->r_edges, L, out);
-        return YYG_OK;
-      case YYG_TABLE_CROSS:
-        if (n != 3 * nang) return YYG_ERR_INVALID_ARG;
-        if (g.polar) return YYG_ERR_UNSUPPORTED;
-        yyg::cross_points(g, out);
-        return YYG_OK;
-      case YYG_TABLE_ROTATION:
-        if (n != (size_t)yyg::rotation_blocks_size(L)) return YYG_ERR_INVALID_ARG;
-        yyg::rotation_blocks(L, out);
-        return YYG_OK;
-      default:
-        return YYG_ERR_INVALID_ARG;
-    }
-  } catch (const std::bad_alloc &) {
-    return YYG_ERR_OUT_OF_MEMORY;
-  }
-}
-
 int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
   if (!out) return YYG_ERR_INVALID_ARG;
   *out = nullptr;
-  int st = validate(d);
+  int st = yyg::validate_desc(d);
   if (st != YYG_OK) return st;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
@@ -1234,7 +1246,7 @@ int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
   auto cleanup_tmp = [&] {
     double *t[] = {d_w, d_Tt, d_CS, d_P, d_Tr};
     for (double *b : t)
-      if (b) (void)hipFree(b);
+      if (b) (void)dev_free(b);
   };
   st = YYG_OK;
   if (st == YYG_OK) st = dmalloc(&g->d_Bt, (size_t)Q * g->ldb);
@@ -1333,7 +1345,7 @@ int yyg_prepare(yyg_grid *g, int precision) {
   int st = YYG_OK;
   auto bmalloc = [&](void **ptr, size_t bytes) {
     if (st != YYG_OK) return;
-    if (hipMalloc(ptr, bytes) != hipSuccess) {
+    if (dev_malloc(ptr, bytes) != hipSuccess) {
       *ptr = nullptr;
       (void)hipGetLastError();
       st = YYG_ERR_OUT_OF_MEMORY;
@@ -1347,7 +1359,10 @@ int yyg_prepare(yyg_grid *g, int precision) {
   bmalloc(&L.Ur, (size_t)M * L.ldu * parts * eb);
   if (!g->d_eA) bmalloc(reinterpret_cast<void **>(&g->d_eA), (size_t)M * sizeof(int));
   if (!g->d_eU) bmalloc(reinterpret_cast<void **>(&g->d_eU), (size_t)M * sizeof(int));
-  if (st != YYG_OK) return st;
+  if (st != YYG_OK) {
+    lp_release(L);
+    return st;
+  }
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
     if (e == hipSuccess && r != hipSuccess) e = r;
@@ -1359,6 +1374,7 @@ int yyg_prepare(yyg_grid *g, int precision) {
   chk(hipDeviceSynchronize());
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    lp_release(L);
     return YYG_ERR_DEVICE;
   }
   int bm, bn;
@@ -1368,8 +1384,11 @@ int yyg_prepare(yyg_grid *g, int precision) {
   L.nsplit = yyg::choose_split(((M + bm - 1) / bm) * ((Q + bn - 1) / bn), g->nang);
   if (L.nsplit > g->part_cap) {
     double *np = nullptr;
-    if (dmalloc(&np, (size_t)L.nsplit * M * Q) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
-    (void)hipFree(g->d_part);
+    if (dmalloc(&np, (size_t)L.nsplit * M * Q) != YYG_OK) {
+      lp_release(L);
+      return YYG_ERR_OUT_OF_MEMORY;
+    }
+    (void)dev_free(g->d_part);
     g->d_part = np;
     g->part_gen += 1;
     g->part_cap = L.nsplit;
@@ -1411,6 +1430,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
   DeviceGuard dg(g->device);
   if (!dg.ok) return YYG_ERR_DEVICE;
   hipStream_t s = as_stream(stream);
+  if (int st = check_rho(g, g->rho, s); st != YYG_OK) return st;
   const int Q = g->Q, n_r = g->n_r;
   const long M = (long)g->n_patch * n_r;
   double *out = phi;
@@ -1426,7 +1446,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
   if (g->method == YYG_METHOD_SEPARABLE) {
     int st = sep_set_pointers(g, g->rho, out, s);
     if (st != YYG_OK) {
-      if (tmp) (void)hipFree(tmp);
+      if (tmp) (void)dev_free(tmp);
       return st;
     }
     e = sep_solve(g, s, precision);
@@ -1434,7 +1454,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
       if (e == hipSuccess)
         e = hipMemcpyAsync(phi, out, (size_t)M * g->nang * sizeof(double), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
-      (void)hipFree(tmp);
+      (void)dev_free(tmp);
       g->sep.phi_syn.C = nullptr;  // the temporary is gone
       g->sep.phi_syn_d.C = nullptr;
       g->sep.phi_syn_f.C = nullptr;
@@ -1504,7 +1524,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
     if (e == hipSuccess)
       e = hipMemcpyAsync(phi, out, (size_t)M * g->nang * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(tmp);
+    (void)dev_free(tmp);
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1525,6 +1545,7 @@ int yyg_solve_noalloc(yyg_grid *g, const double *rho, double *phi, void *stream)
     return YYG_ERR_DEVICE;
   }
   if (sep_work_doubles(g) * sizeof(double) > bytes) return YYG_ERR_UNSUPPORTED;
+  if (int st = check_rho(g, rho, as_stream(stream)); st != YYG_OK) return st;
   // carve the work buffers out of the scratch array; every one of them is
   // written in full by its phase before any later phase reads it, so none
   // needs clearing
@@ -1553,6 +1574,24 @@ int yyg_solve_noalloc(yyg_grid *g, const double *rho, double *phi, void *stream)
     (void)hipGetLastError();
     return YYG_ERR_DEVICE;
   }
+  return YYG_OK;
+}
+
+int yyg_set_check_finite(yyg_grid *g, int on) {
+  if (!g) return YYG_ERR_INVALID_ARG;
+  if (on && !g->d_flag) {
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return YYG_ERR_DEVICE;
+    if (int st = dmalloc(&g->d_flag, 1); st != YYG_OK) return st;
+  }
+  g->check_finite = on != 0;
+  return YYG_OK;
+}
+
+int yyg_device_bytes(size_t *held) {
+  if (!held) return YYG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mem_mu);
+  *held = g_mem_held;
   return YYG_OK;
 }
 
@@ -1687,8 +1726,8 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     }
     g->timing = timing;
     (void)hipStreamSynchronize(s);
-    if (phi_t) (void)hipFree(phi_t);
-    if (rho_t) (void)hipFree(rho_t);
+    if (phi_t) (void)dev_free(phi_t);
+    if (rho_t) (void)dev_free(rho_t);
     sep_set_pointers(g, nullptr, nullptr, s);
     return st;
   }
@@ -1730,9 +1769,9 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     if (st == YYG_OK) st = dmalloc(&tmp_part, (size_t)smax * M * Q);
     if (st == YYG_OK && tmp_in) (void)hipMemsetAsync(tmp_in, 0, (size_t)M * g->nang * sizeof(double), s);
     if (st != YYG_OK) {
-      if (tmp_in) (void)hipFree(tmp_in);
-      if (tmp_out) (void)hipFree(tmp_out);
-      if (tmp_part) (void)hipFree(tmp_part);
+      if (tmp_in) (void)dev_free(tmp_in);
+      if (tmp_out) (void)dev_free(tmp_out);
+      if (tmp_part) (void)dev_free(tmp_part);
       return st;
     }
   }
@@ -1798,14 +1837,14 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
       }
     }
   }
-  if (tmp_in) (void)hipFree(tmp_in);
-  if (tmp_out) (void)hipFree(tmp_out);
-  if (tmp_part) (void)hipFree(tmp_part);
+  if (tmp_in) (void)dev_free(tmp_in);
+  if (tmp_out) (void)dev_free(tmp_out);
+  if (tmp_part) (void)dev_free(tmp_part);
   if (best_sp > g->part_cap) {
     double *np = nullptr;
     if (dmalloc(&np, (size_t)best_sp * M * Q) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
     (void)hipDeviceSynchronize();
-    (void)hipFree(g->d_part);
+    (void)dev_free(g->d_part);
     g->d_part = np;
     g->part_gen += 1;
     g->part_cap = best_sp;
@@ -1851,8 +1890,8 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     }
     g->timing = timing;
     (void)hipStreamSynchronize(s);
-    if (phi_t) (void)hipFree(phi_t);
-    if (rho_t) (void)hipFree(rho_t);
+    if (phi_t) (void)dev_free(phi_t);
+    if (rho_t) (void)dev_free(rho_t);
     g->sep.phi_ana.A = nullptr;  // the next solve writes its own pointers
     g->sep.phi_syn.C = nullptr;
     g->sep.phi_ana_d.X = nullptr;
@@ -1889,7 +1928,7 @@ int yyg_plan_config(yyg_grid *g, int precision, int var_ana, int split_ana, int 
     double *np = nullptr;
     if (dmalloc(&np, (size_t)split_ana * M * g->Q) != YYG_OK) return YYG_ERR_OUT_OF_MEMORY;
     (void)hipDeviceSynchronize();
-    (void)hipFree(g->d_part);
+    (void)dev_free(g->d_part);
     g->d_part = np;
     g->part_gen += 1;
     g->part_cap = split_ana;
@@ -2118,6 +2157,8 @@ int yyg_batch_solve(yyg_batch *b, const double *const *d_rho, double *const *d_p
   // a graph cannot be recorded on the legacy default stream: use the
   // batch's own blocking stream, which that stream orders against
   hipStream_t s = stream ? as_stream(stream) : b->stream;
+  for (int f = 0; f < n; ++f)
+    if (int st = check_rho(b->grids[f], d_rho[f], s); st != YYG_OK) return st;
   for (int f = 0; f < n; ++f) b->grids[f]->ahat_cols = b->sep;  // the moments' layout the batch leaves
   bool changed = false;
   for (int f = 0; f < n; ++f)

@@ -321,4 +321,7 @@ int choose_split(long tiles, long K);
 constexpr size_t kScratchBytes = 64UL << 20;
 hipError_t scratch_region(int device, double **ptr, size_t *bytes);
 
+// *flag (device int) = 1 if x[0..n) holds a NaN or an infinity, else 0
+hipError_t launch_check_finite(const double *x, long n, int *flag, hipStream_t s);
+
 }  // namespace yyg

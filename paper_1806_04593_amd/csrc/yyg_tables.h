@@ -4,7 +4,13 @@
 #include <cstddef>
 #include <vector>
 
+#include "yyg.h"
+
 namespace yyg {
+
+// YYG_OK, or YYG_ERR_INVALID_ARG when a field of d is outside its documented
+// range (yyg.h, yyg_grid_desc).
+int validate_desc(const yyg_grid_desc *d);
 
 // Column index of (l, m, cos/sin) in the Q = (L+1)^2 spherical-harmonic
 // columns: q(l,0) = l^2, q(l,m,cos) = l^2 + 2m - 1, q(l,m,sin) = l^2 + 2m.

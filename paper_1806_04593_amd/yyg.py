@@ -19,6 +19,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x2": FP16X2}
 
 TABLE_WEIGHTS, TABLE_THETA, TABLE_PHI, TABLE_RADIAL, TABLE_CROSS, TABLE_ROTATION = 0, 1, 2, 3, 4, 5
 METHODS = {"dense": 0, "separable": 1}
+# yyg_status
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_READY, ERR_UNSUPPORTED, ERR_NONFINITE = 0, -1, -2, -3, -4, -5, -6
 GRID_YINYANG, GRID_POLAR = 0, 1
 KINDS = {"yinyang": GRID_YINYANG, "polar": GRID_POLAR}
 
@@ -30,6 +32,7 @@ EXPORTS = [
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
     "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind", "yyg_sep_config", "yyg_sep_info",
     "yyg_sep_kernel", "yyg_sep_phase", "yyg_solve_noalloc", "yyg_sep_lp_kernel", "yyg_sep_lp_config",
+    "yyg_set_check_finite", "yyg_device_bytes",
 ]
 
 
@@ -94,6 +97,8 @@ def lib():
         L.yyg_solve_noalloc.argtypes = [vp, vp, vp, vp]
         L.yyg_sep_lp_kernel.argtypes = [vp, i, i, ctypes.c_char_p, ctypes.c_size_t]
         L.yyg_sep_lp_config.argtypes = [vp, i, i, i]
+        L.yyg_set_check_finite.argtypes = [vp, i]
+        L.yyg_device_bytes.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -104,6 +109,13 @@ def lib():
                 getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
+
+
+def device_bytes():
+    """Device memory the library holds in this process (yyg_device_bytes)."""
+    n = ctypes.c_size_t(0)
+    _check(lib().yyg_device_bytes(ctypes.byref(n)), "yyg_device_bytes")
+    return int(n.value)
 
 
 def _check(status, where):
@@ -245,6 +257,11 @@ class Grid:
         _check(lib().yyg_solve_noalloc(self._h, ctypes.c_void_p(rp), ctypes.c_void_p(pp), _stream_handle(stream)),
                "yyg_solve_noalloc")
         return phi
+
+    def set_check_finite(self, on=True):
+        """yyg_set_check_finite: scan the density for NaN / infinity before
+        every solve (YygError with status YYG_ERR_NONFINITE if found)."""
+        _check(lib().yyg_set_check_finite(self._h, 1 if on else 0), "yyg_set_check_finite")
 
     def autotune(self, precision="fp64", stream=None):
         _check(lib().yyg_autotune(self._h, PRECISIONS.get(precision, precision), _stream_handle(stream)),

@@ -94,3 +94,13 @@ def test_batch_solve_refuses_bad_tensors(i):
         b.solve([good0, bad], [good0, bad])
     with pytest.raises(ValueError):
         b.solve([good0], [good0, bad])        # wrong count
+
+
+def test_safety_entry_points_without_a_device():
+    """The host-side halves of the safety entry points: the device-memory
+    figure is readable without a GPU (nothing held), and the input check
+    refuses a null plan."""
+    L = yyg.lib()
+    assert yyg.device_bytes() >= 0
+    assert L.yyg_device_bytes(None) == yyg.ERR_INVALID_ARG
+    assert L.yyg_set_check_finite(None, 1) == yyg.ERR_INVALID_ARG
