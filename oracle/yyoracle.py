@@ -28,6 +28,10 @@ listed in the design notes of the repository):
   evaluated here in the algebraically identical ratio forms
   R_in,i / r_n^(l+1) and r_n^l R_out,i, using expm1/log to avoid cancellation.
 
+Range: the unnormalised P_l^m of Eq. (A3) and the factorial ratios of
+Eq. (8) leave FP64's range together near lmax 90 (their product overflows
+in the synthesis); the oracle is used up to lmax 80.
+
 Array conventions: rho and phi are [2][n_R][n_theta][n_phi] (patch 0 = Yin,
 patch 1 = Yang, each in its own local coordinates); moment and radial arrays
 are indexed [patch, shell or interface, l, m].  The full-sphere spherical

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libyyg.so")
 
 SOURCES = ["yyg_kernels.hip", "yyg_kernels_x4.hip", "yyg_batch_sep.hip", "yyg_kernels_sep_lp.hip", "yyg_kernels_lp.hip",
-           "yyg_noalloc.hip", "yyg_checks.hip", "yyg_tables.cpp", "yyg_host.cpp", "yyg_api.cpp"]
+           "yyg_phi_stream.hip", "yyg_noalloc.hip", "yyg_checks.hip", "yyg_tables.cpp", "yyg_host.cpp", "yyg_api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

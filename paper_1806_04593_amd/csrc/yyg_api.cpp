@@ -117,6 +117,7 @@ struct yyg_grid {
   bool ahat_cols = false;    // d_Ahat holds the column-major layout
   double *d_U = nullptr;     // synthesis operand [P n_r][ldy]
   double *d_rho_owned = nullptr;
+  int cus = 256;  // compute units of the device (persistent grids)
   // opt-in check of the density for NaN / infinity before each solve
   bool check_finite = false;
   int *d_flag = nullptr;
@@ -168,6 +169,7 @@ struct yyg_grid {
     double *WF = nullptr;    // folded analysis basis [n_t][2][L+1][ldkh]: even (cos) / odd (sin) halves
     double *TF = nullptr;    // folded synthesis basis [h][ldtf]: cos m at m, sin m at ks + m - 1
     yyg::GemmF64Args phi_ana_f{}, phi_syn_f{};
+    yyg::PhiStreamArgs phi_syn_s{};  // streaming folded synthesis
     // folded analysis, both halves per block: basis rows cos m at slot m
     // (m <= L), sin m at slot ks + m - 1, [n_t][ks + L][ldkh], exact weights
     double *WFAB = nullptr;
@@ -365,16 +367,32 @@ int sep_x4_base(int r) {
   return r == 0 ? v + phi : r == 4 ? v + phi + yyg::phi_lean_variant_count() : v;
 }
 
-int sep_variant_count(int r) { return sep_x4_base(r) + yyg::x4_variant_count(r); }
+// The phi synthesis then takes the streaming kernels
+// (yyg::phi_stream_variant_count(), folded grids only) after those.
+int sep_stream_base() { return sep_x4_base(4) + yyg::x4_variant_count(4); }
+
+int sep_variant_count(int r) {
+  return sep_x4_base(r) + yyg::x4_variant_count(r) + (r == 4 ? yyg::phi_stream_variant_count() : 0);
+}
 
 bool sep_fold_variant(int r, int v) {
+  if (r == 4 && v >= sep_stream_base()) return true;
   if (v >= sep_x4_base(r)) return yyg::x4_fold_only(r, v - sep_x4_base(r)) != 0;
   return (r == 0 || r == 4) && v >= 2 * yyg::gemm_f64_variant_count() + yyg::phi_direct_variant_count();
+}
+
+// Whether variant v of phase r can run on this plan's grid and degree.
+bool sep_variant_available(const yyg_grid *g, int r, int v) {
+  if (r < 0 || r > 4 || v < 0 || v >= sep_variant_count(r)) return false;
+  if (sep_fold_variant(r, v) && !g->sep.fold) return false;
+  return !(r == 4 && v >= sep_stream_base() && !yyg::phi_stream_supports(v - sep_stream_base(), g->L));
 }
 
 int sep_set_variant(yyg_grid *g, int r, int v) {
   if (r < 0 || r > 4 || v < 0 || v >= sep_variant_count(r)) return YYG_ERR_INVALID_ARG;
   if (sep_fold_variant(r, v) && !g->sep.fold) return YYG_ERR_UNSUPPORTED;
+  if (r == 4 && v >= sep_stream_base() && !yyg::phi_stream_supports(v - sep_stream_base(), g->L))
+    return YYG_ERR_UNSUPPORTED;
   g->sep.var[r] = v;
   return YYG_OK;
 }
@@ -383,6 +401,8 @@ hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
   const int nv = yyg::gemm_f64_variant_count(), nd = yyg::phi_direct_variant_count();
   const int nf = yyg::phi_fold_variant_count();
+  if (r == 4 && S.var[r] >= sep_stream_base())
+    return yyg::launch_phi_syn_stream(S.var[r] - sep_stream_base(), S.phi_syn_s, g->cus, s);
   if (S.var[r] >= sep_x4_base(r)) {
     if (r == 2 && g->n_patch != 2) return hipSuccess;
     const yyg::GemmF64Args &phi = r == 0 ? (S.fold ? S.phi_ana_f : S.phi_ana) : (S.fold ? S.phi_syn_f : S.phi_syn);
@@ -421,6 +441,7 @@ void sep_bind_work(yyg_grid *g, const SepWork &w) {
   S.phi_ana.C = S.phi_ana_f.C = S.phi_ana_ab.C = w.X2;
   S.phi_ana_d.C = S.phi_ana_fd.C = w.X2;
   S.phi_syn.A = S.phi_syn_f.A = w.V;
+  S.phi_syn_s.V = w.V;
   S.phi_syn_d.X = S.phi_syn_fd.X = w.V;
   S.phi_syn_l.V = w.V;
   S.args.X2 = w.X2;
@@ -449,6 +470,7 @@ int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
   g->sep.phi_ana_f.A = rho;
   g->sep.phi_ana_ab.A = rho;
   g->sep.phi_syn_f.C = phi;
+  g->sep.phi_syn_s.phi = phi;
   g->sep.phi_ana_fd.X = rho;
   g->sep.phi_syn_fd.C = phi;
   g->sep.phi_syn_l.C = phi;
@@ -673,6 +695,8 @@ int sep_build(yyg_grid *g) {
   S.phi_syn_f.k_split = (int)S.ks;
   S.phi_syn_f.fold_k = np;
   S.phi_syn_f.fold_mc = nmc;
+  S.phi_syn_s = yyg::PhiStreamArgs{S.V, S.TF, nullptr, MJ, (long)nt * np, (int)M, nt, np, (int)S.h, L, nmc,
+                                   (int)S.ldtf, (int)S.ks};
   S.phi_ana_d = yyg::PhiDirectArgs{nullptr, S.Wcs, S.X2, (int)M, nt, nmc, np, S.ldk, (long)nmc * S.ldk};
   S.phi_syn_d = yyg::PhiDirectArgs{S.V, S.trig, nullptr, (int)M, nt, np, nmc, S.ldm, 0};
   S.phi_ana_fd = yyg::PhiDirectArgs{nullptr, S.WFD, S.X2, (int)M, nt, (int)S.nba, (int)S.h, S.h, S.nba * S.h,
@@ -1242,6 +1266,11 @@ int yyg_grid_create(const yyg_grid_desc *d, int device, yyg_grid **out) {
     free_grid(g);
     return YYG_ERR_DEVICE;
   }
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+      g->cus = cus;
+  }
   double *d_w = nullptr, *d_Tt = nullptr, *d_CS = nullptr, *d_P = nullptr, *d_Tr = nullptr;
   auto cleanup_tmp = [&] {
     double *t[] = {d_w, d_Tt, d_CS, d_P, d_Tr};
@@ -1458,6 +1487,7 @@ int yyg_solve(yyg_grid *g, double *phi, int phi_is_device, int precision, void *
       g->sep.phi_syn.C = nullptr;  // the temporary is gone
       g->sep.phi_syn_d.C = nullptr;
       g->sep.phi_syn_f.C = nullptr;
+      g->sep.phi_syn_s.phi = nullptr;
       g->sep.phi_syn_fd.C = nullptr;
       g->sep.phi_syn_l.C = nullptr;
     }
@@ -1877,7 +1907,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
       double best = t0 - std::max(0.0003, 0.005 * t0);
       int bv = v0;
       for (int v = 0; v < sep_variant_count(r) && st3 == YYG_OK; ++v) {
-        if (v == v0 || (sep_fold_variant(r, v) && !g->sep.fold)) continue;
+        if (v == v0 || !sep_variant_available(g, r, v)) continue;
         st3 = sep_set_variant(g, r, v);
         if (st3 != YYG_OK) break;
         const double t = solve_ms();
@@ -1899,6 +1929,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     g->sep.phi_ana_f.A = nullptr;
     g->sep.phi_ana_ab.A = nullptr;
     g->sep.phi_syn_f.C = nullptr;
+    g->sep.phi_syn_s.phi = nullptr;
     g->sep.phi_ana_fd.X = nullptr;
     g->sep.phi_syn_fd.C = nullptr;
     g->sep.phi_syn_l.C = nullptr;
@@ -1981,6 +2012,11 @@ int yyg_sep_config(yyg_grid *g, int phase, int variant) {
   return sep_set_variant(g, phase, variant);
 }
 
+int yyg_sep_variant_count(int phase) {
+  if (phase < 0 || phase > 4) return YYG_ERR_INVALID_ARG;
+  return sep_variant_count(phase);
+}
+
 int yyg_sep_info(const yyg_grid *g, int *variants, int n) {
   if (!g || !variants || n < 1) return YYG_ERR_INVALID_ARG;
   for (int i = 0; i < n && i < 5; ++i)
@@ -2011,8 +2047,9 @@ int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
     return YYG_OK;
   }
   const int v = g->sep.var[phase], x0 = sep_x4_base(phase);
-  const int r = v >= x0 ? yyg::x4_kernel_name(v - x0, phase, g->sep.fold, name, n)
-                        : yyg::sep_kernel_name(phase, v, g->sep.fold, name, n);
+  const int r = phase == 4 && v >= sep_stream_base() ? yyg::phi_stream_kernel_name(v - sep_stream_base(), name, n)
+                : v >= x0 ? yyg::x4_kernel_name(v - x0, phase, g->sep.fold, name, n)
+                          : yyg::sep_kernel_name(phase, v, g->sep.fold, name, n);
   return r == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
 }
 

@@ -324,4 +324,23 @@ hipError_t scratch_region(int device, double **ptr, size_t *bytes);
 // *flag (device int) = 1 if x[0..n) holds a NaN or an infinity, else 0
 hipError_t launch_check_finite(const double *x, long n, int *flag, hipStream_t s);
 
+// Folded phi synthesis, streaming form (yyg_phi_stream.hip): for every
+// row (patch, shell) and colatitude j, phi[row][j][s] = e + o and
+// phi[row][j][np - 1 - s] = e - o over the folded cells s < h, with e the
+// cosine part (V columns 0, 1, 3, .., 2L - 1 against TF columns 0..L) and o
+// the sine part (V columns 2, 4, .., 2L against TF columns ks..ks + L - 1).
+struct PhiStreamArgs {
+  const double *V;   // [2L + 1][nt][Mr] theta-synthesis output
+  const double *TF;  // [h][ldtf] folded basis
+  double *phi;       // [Mr][nt][np] rows of ldc = nt * np
+  long MJ, ldc;      // nt * Mr; nt * np
+  int Mr, nt, np, h, L, nmc, ldtf, ks;
+};
+int phi_stream_variant_count();
+// whether variant v holds the basis panel of degree L in LDS
+bool phi_stream_supports(int v, int L);
+int phi_stream_kernel_name(int v, char *buf, size_t n);
+// cus: compute units of the device (the persistent grid's size)
+hipError_t launch_phi_syn_stream(int v, const PhiStreamArgs &a, int cus, hipStream_t s);
+
 }  // namespace yyg

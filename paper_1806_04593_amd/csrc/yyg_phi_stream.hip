@@ -1,0 +1,236 @@
+// Folded phi synthesis of the separable form, streaming variant: the block
+// keeps one panel of the folded azimuthal basis in LDS for its whole life
+// and its waves sweep row tiles independently, loading the coefficients of
+// the theta synthesis straight into registers in the 16x16x4 FP64 MFMA
+// operand layout a few steps ahead of their use (no LDS staging, no
+// barrier after the panel fill).
+//
+// For colatitude j and row (patch, shell) the potential at the azimuthal
+// cell s of the folded half and at its mirror n_phi - 1 - s is e + o and
+// e - o, with e = sum_m c_m TF_cos(s, m) over the cosine columns (m = 0..L)
+// and o = sum_m s_m TF_sin(s, m) over the sine columns (m = 1..L): the
+// synthesis of Eqs. (5) and (28)-(29) along one colatitude row, split into
+// its parts even and odd about the central meridian.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+
+#include "yyg_internal.h"
+
+namespace yyg {
+
+typedef double dbl4s __attribute__((ext_vector_type(4)));
+
+// TI row tiles of 16 rows per wave, a basis panel of TJ tiles of 16 folded
+// azimuthal cells per block, NW waves per block, P steps of coefficient
+// loads in flight, LDB the panel's row capacity (at least 8 ceil((L+1)/4)).
+// One step takes four cosine and four sine columns: the wave's accumulators
+// e and o each gain a 16 x 16 x 4 product per basis tile.
+template <int TI, int TJ, int NW, int P, int LDB>
+__global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n_panels, int tiles_j,
+                                                          int tiles_total) {
+  __shared__ double Bs[TJ * 16 * LDB];
+  const int NQ = (a.L + 4) / 4;   // steps: cosine columns m = 4q + g (m <= L), sine m = 4q + g + 1
+  const int KE = 4 * NQ;          // panel row: cosine part [0, KE), sine part [KE, 2 KE)
+  const int ldb = 2 * KE + 2;     // row stride: 16 rows x 2 lanes land on distinct LDS bank pairs
+  // blocks of one XCD (blockIdx % 8, the hardware's round-robin) share one
+  // contiguous run of row tiles; within it, block ib serves panel ib % n_panels
+  const int xcd = blockIdx.x & 7, ib = blockIdx.x >> 3, nbx = (int)(gridDim.x >> 3);
+  const int panel = ib % n_panels, grp = ib / n_panels;
+  const int groups = (nbx - panel + n_panels - 1) / n_panels;
+  const int slot0 = panel * TJ * 16;
+  for (int e = threadIdx.x; e < TJ * 16 * 2 * KE; e += 64 * NW) {
+    const int sl = e / (2 * KE), kk = e - sl * (2 * KE), slot = slot0 + sl;
+    double v = 0.0;
+    if (slot < a.h) {
+      if (kk < KE) {
+        if (kk <= a.L) v = a.TF[(long)slot * a.ldtf + kk];
+      } else if (kk - KE < a.L) {
+        v = a.TF[(long)slot * a.ldtf + a.ks + (kk - KE)];
+      }
+    }
+    Bs[sl * ldb + kk] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, r16 = lane & 15;
+  const int per = tiles_total / 8, rem = tiles_total % 8;
+  const int t_beg = xcd * per + min(xcd, rem), t_end = t_beg + per + (xcd < rem ? 1 : 0);
+  const int stride = groups * NW;
+  int t = t_beg + grp * NW + wave;
+  if (t >= t_end) return;
+  // element offsets stay below 2^31 (checked by the launcher)
+  auto rowbase = [&](int tt, int i) -> int {
+    tt = min(tt, tiles_total - 1);
+    const int jl = tt / tiles_j, rt = tt - jl * tiles_j;
+    return jl * a.Mr + min(rt * 16 * TI + 16 * i + r16, a.Mr - 1);
+  };
+  const int MJ = (int)a.MJ;
+  // azimuthal columns of step q for lane group g (clamped: past L the basis is zero)
+  auto offE = [&](int q) { return min(max(8 * q + 2 * g - 1, 0), a.nmc - 1) * MJ; };
+  auto offO = [&](int q) { return min(8 * q + 2 * g + 2, a.nmc - 1) * MJ; };
+  dbl4s accE[TI][TJ], accO[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      accE[i][j] = dbl4s{0.0, 0.0, 0.0, 0.0};
+      accO[i][j] = dbl4s{0.0, 0.0, 0.0, 0.0};
+    }
+  // the steps of every tile of this wave, padded to whole rings: the
+  // surplus steps read clamped addresses and their sums are never stored
+  const int n_my = (t_end - t + stride - 1) / stride;
+  const int total = (n_my * NQ + P - 1) / P * P;
+  // load cursor (tile tl, step ql), P steps ahead of the compute cursor
+  int tl = t, ql = 0;
+  int rbl[TI];
+#pragma unroll
+  for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+  auto advance_load = [&]() {
+    if (++ql == NQ) {
+      ql = 0;
+      tl += stride;
+#pragma unroll
+      for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+    }
+  };
+  double raE[P][TI], raO[P][TI];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int oe = offE(ql), oo = offO(ql);
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      raE[p][i] = a.V[oe + rbl[i]];
+      raO[p][i] = a.V[oo + rbl[i]];
+    }
+    advance_load();
+  }
+  // basis fragments of the current step, read one step ahead: lane (g, r16)
+  // holds cell 16 j + r16 of the panel at column 4 q + g
+  const double *bp = &Bs[r16 * ldb + g];
+  double bE[TJ], bO[TJ];
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    bE[j] = bp[16 * j * ldb];
+    bO[j] = bp[16 * j * ldb + KE];
+  }
+  int q = 0;
+  for (int base = 0; base < total; base += P) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      double nE[TJ], nO[TJ];
+      const int qn = q + 1 == NQ ? 0 : q + 1;
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        nE[j] = bp[16 * j * ldb + 4 * qn];
+        nO[j] = bp[16 * j * ldb + KE + 4 * qn];
+      }
+      double aE[TI], aO[TI];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        aE[i] = raE[p][i];
+        aO[i] = raO[p][i];
+      }
+      {
+        const int oe = offE(ql), oo = offO(ql);
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+          raE[p][i] = a.V[oe + rbl[i]];
+          raO[p][i] = a.V[oo + rbl[i]];
+        }
+        advance_load();
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          accE[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE[i], bE[j], accE[i][j], 0, 0, 0);
+          accO[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO[i], bO[j], accO[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        bE[j] = nE[j];
+        bO[j] = nO[j];
+      }
+      if (++q == NQ) {
+        // tile t done: D layout of the 16x16x4 FP64 MFMA, lane l, element r
+        // -> row l / 16 + 4 r, cell l % 16 of the basis tile
+        const int jl = t / tiles_j, rt = t - jl * tiles_j;
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = rt * 16 * TI + 16 * i + g + 4 * r, slot = slot0 + 16 * j + r16;
+              if (t < t_end && row < a.Mr && slot < a.h) {
+                double *o = a.phi + (long)row * a.ldc + (long)jl * a.np;
+                const double e = accE[i][j][r], od = accO[i][j][r];
+                o[slot] = e + od;
+                const int cm = a.np - 1 - slot;
+                if (cm != slot) o[cm] = e - od;
+              }
+              accE[i][j][r] = 0.0;
+              accO[i][j][r] = 0.0;
+            }
+        q = 0;
+        t += stride;
+      }
+    }
+  }
+}
+
+namespace {
+
+struct StreamVariant {
+  int ti, tj, nw, p, ldb, bpc;
+  void (*kernel)(PhiStreamArgs, int, int, int);
+  const char *name;
+};
+
+#define YYG_STREAM(TI, TJ, NW, P, LDB, BPC)                                                             \
+  {                                                                                                     \
+    TI, TJ, NW, P, LDB, BPC, phi_syn_stream<TI, TJ, NW, P, LDB>,                                        \
+        "yyg::phi_syn_stream<" #TI ", " #TJ ", " #NW ", " #P ", " #LDB ">"                              \
+  }
+
+// a variant serves the degrees whose panel rows (8 ceil((L+1)/4) + 2
+// doubles) fit its LDB: L <= 67 at 138, L <= 131 at 266
+const StreamVariant kStream[] = {
+    YYG_STREAM(1, 6, 8, 4, 138, 1), YYG_STREAM(1, 4, 8, 8, 138, 1), YYG_STREAM(1, 3, 4, 8, 138, 3),
+    YYG_STREAM(1, 6, 8, 8, 138, 1), YYG_STREAM(1, 3, 8, 4, 266, 1),
+};
+
+}  // namespace
+
+int phi_stream_variant_count() { return (int)(sizeof(kStream) / sizeof(kStream[0])); }
+
+bool phi_stream_supports(int v, int L) {
+  return v >= 0 && v < phi_stream_variant_count() && L >= 0 && 8 * ((L + 4) / 4) + 2 <= kStream[v].ldb;
+}
+
+int phi_stream_kernel_name(int v, char *buf, size_t n) {
+  if (v < 0 || v >= phi_stream_variant_count()) return -1;
+  return snprintf(buf, n, "%s", kStream[v].name) < 0 ? -1 : 0;
+}
+
+hipError_t launch_phi_syn_stream(int v, const PhiStreamArgs &a, int cus, hipStream_t s) {
+  if (!phi_stream_supports(v, a.L)) return hipErrorInvalidValue;
+  if (a.Mr <= 0 || a.nt <= 0 || a.h <= 0) return hipSuccess;
+  const StreamVariant &k = kStream[v];
+  // element offsets of the coefficients are 32-bit in the kernel
+  if ((long)a.nmc * a.MJ >= INT_MAX) return hipErrorInvalidValue;
+  const int rows = 16 * k.ti;
+  const long tj = (a.Mr + rows - 1) / rows, tt = tj * a.nt;
+  if (tt >= INT_MAX / 2) return hipErrorInvalidValue;
+  const int n_panels = (a.h + 16 * k.tj - 1) / (16 * k.tj);
+  // a whole number of blocks per XCD, at least one per panel on each
+  int per_xcd = std::max(n_panels, k.bpc * std::max(cus, 8) / 8);
+  const dim3 grid(8 * per_xcd), block(64 * k.nw);
+  hipLaunchKernelGGL(k.kernel, grid, block, 0, s, a, n_panels, (int)tj, (int)tt);
+  return hipGetLastError();
+}
+
+}  // namespace yyg

@@ -32,7 +32,7 @@ EXPORTS = [
     "yyg_autotune", "yyg_plan_info", "yyg_plan_config", "yyg_batch_autotune", "yyg_batch_info",
     "yyg_batch_profile", "yyg_set_method", "yyg_grid_kind", "yyg_sep_config", "yyg_sep_info",
     "yyg_sep_kernel", "yyg_sep_phase", "yyg_solve_noalloc", "yyg_sep_lp_kernel", "yyg_sep_lp_config",
-    "yyg_set_check_finite", "yyg_device_bytes",
+    "yyg_set_check_finite", "yyg_device_bytes", "yyg_sep_variant_count",
 ]
 
 
@@ -99,6 +99,7 @@ def lib():
         L.yyg_sep_lp_config.argtypes = [vp, i, i, i]
         L.yyg_set_check_finite.argtypes = [vp, i]
         L.yyg_device_bytes.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+        L.yyg_sep_variant_count.argtypes = [i]
         L.yyg_autotune.argtypes = [vp, i, vp]
         L.yyg_plan_info.argtypes = [vp, i, ctypes.POINTER(i), i]
         L.yyg_plan_config.argtypes = [vp, i, i, i, i]
@@ -275,6 +276,12 @@ class Grid:
 
     def sep_config(self, phase, variant):
         _check(lib().yyg_sep_config(self._h, int(phase), int(variant)), "yyg_sep_config")
+
+    def sep_variant_count(self, phase):
+        """yyg_sep_variant_count: the length of phase `phase`'s variant range."""
+        n = lib().yyg_sep_variant_count(int(phase))
+        _check(min(n, 0), "yyg_sep_variant_count")
+        return n
 
     def sep_info(self):
         v = (ctypes.c_int * 5)()

@@ -222,3 +222,22 @@ def test_binary_separable_reduced_precision(precision):
          f"max rel err {err:.3e}")
     assert err <= TOL[precision]
     g.set_method("dense")
+
+
+N_STREAM_BINARY = 4   # streaming phi-synthesis variants that hold lmax 64
+
+
+def test_binary_separable_stream_variants():
+    """Each streaming phi-synthesis variant at the binary workload (the
+    other phases as the autotuner left them), at the oracle's samples."""
+    desc, rho, s, ref, *_ = _binary()
+    g, _ = _binary_grid()
+    g.set_method("separable")
+    n = g.sep_variant_count(4)
+    for v in range(n - 5, n - 5 + N_STREAM_BINARY):
+        g.sep_config(4, v)
+        d_phi = _solve(g)
+        err = _max_rel(_at(d_phi, s), ref)
+        _say(f"binary separable, phi synthesis {g.sep_kernel(4)}: max rel err {err:.3e}")
+        assert err <= TOL["fp64"]
+    g.set_method("dense")

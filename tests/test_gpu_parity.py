@@ -123,6 +123,8 @@ N_PHI_FOLD = 8
 N_PHI_LEAN = 4   # phi synthesis only
 N_X4 = 12        # tiles on the 4x4x4 FP64 MFMA, every phase (last in each phase's range)
 N_BOTH = {0: 8, 4: 6}   # then the folded phi transforms with both halves per block
+N_STREAM = 5     # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
+N_STREAM_SMALL_L = 4   # of which the first four hold panels up to lmax 67, the last up to 131
 
 
 def _n_x4(phase):
@@ -398,12 +400,37 @@ def test_separable_every_phase_variant(phase):
     # every tile with one and with three stages of loads in flight; the phi
     # phases also every LDS-basis variant, unfolded and folded; every phase
     # the 4x4x4-MFMA tiles
-    for v in range(_x4_base(phase) + _n_x4(phase)):
+    for v in range(_x4_base(phase) + _n_x4(phase) + (N_STREAM if phase == 4 else 0)):
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
         err = _max_rel(phi, ref)
         assert err <= TOL_FP64, (phase, v, err)
+
+
+def test_phi_stream_variants_at_high_degree():
+    """The streaming phi synthesis at lmax 80 (21 steps of four cosine and
+    four sine columns): the variants whose LDS panel holds only lmax <= 67
+    are refused with YYG_ERR_UNSUPPORTED, the wide-panel variant matches
+    the oracle on a ragged grid (n_r 5, 5 deg).  (The oracle's unnormalised
+    associated Legendre values leave FP64's range near lmax 90.)"""
+    yyg = _yyg()
+    desc = W.make_desc("edge", np.geomspace(1.0, 9.0, 6), 5.0, 80, 0.9, 0)
+    rng = np.random.default_rng(31)
+    rho = rng.uniform(0.1, 1.0, (2, 5, desc["n_theta"], desc["n_phi"]))
+    ref = O.solve(*_oracle_args(desc), rho)
+    g = yyg.Grid(desc, 0)
+    g.set_method("separable")
+    base = _x4_base(4) + _n_x4(4)
+    for v in range(base, base + N_STREAM_SMALL_L):
+        with pytest.raises(yyg.YygError) as ei:
+            g.sep_config(4, v)
+        assert ei.value.status == yyg.ERR_UNSUPPORTED
+    g.sep_config(4, base + N_STREAM - 1)
+    _say(f"phi stream at lmax 80: {g.sep_kernel(4)}")
+    _, phi = _gpu_solve(desc, rho, grid=g)
+    err = _max_rel(phi, ref)
+    assert err <= TOL_FP64, err
 
 
 def test_separable_phase_alone():
