@@ -589,7 +589,17 @@ template <int ROLE, int BM, int BN, int WGM, int WGN, int MODE>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_nt_f64_batched(GemmF64Args g, int per_problem,
                                                                       int tiles_total) {
   const int t = xcd_tile(blockIdx.x, tiles_total);
-  const int z = t / per_problem, tile = t - z * per_problem;
+  int z, tile;
+  if constexpr ((MODE & kGemmFoldA) != 0) {
+    // the even and odd halves (z = 2 j, 2 j + 1) of one row tile back to
+    // back on one XCD: the second reads the same density rows from its L2
+    const int u = t >> 1, zj = u / per_problem;
+    tile = u - zj * per_problem;
+    z = 2 * zj + (t & 1);
+  } else {
+    z = t / per_problem;
+    tile = t - z * per_problem;
+  }
   if constexpr ((MODE & kGemmNFast) != 0) {
     const int tiles_n = per_problem / g.tiles_m;
     gemm_f64_tile<BM, BN, WGM, WGN, MODE | kGemmBatch>(g, tile / tiles_n, tile % tiles_n, z);
