@@ -28,32 +28,14 @@ typedef double dbl4s __attribute__((ext_vector_type(4)));
 // loads in flight, LDB the panel's row capacity (at least 8 ceil((L+1)/4)).
 // One step takes four cosine and four sine columns: the wave's accumulators
 // e and o each gain a 16 x 16 x 4 product per basis tile.
-template <int TI, int TJ, int NW, int P, int LDB>
-__global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n_panels, int tiles_j,
-                                                          int tiles_total) {
-  __shared__ double Bs[TJ * 16 * LDB];
-  const int NQ = (a.L + 4) / 4;   // steps: cosine columns m = 4q + g (m <= L), sine m = 4q + g + 1
-  const int KE = 4 * NQ;          // panel row: cosine part [0, KE), sine part [KE, 2 KE)
-  const int ldb = 2 * KE + 2;     // row stride: 16 rows x 2 lanes land on distinct LDS bank pairs
-  // blocks of one XCD (blockIdx % 8, the hardware's round-robin) share one
-  // contiguous run of row tiles; within it, block ib serves panel ib % n_panels
-  const int xcd = blockIdx.x & 7, ib = blockIdx.x >> 3, nbx = (int)(gridDim.x >> 3);
-  const int panel = ib % n_panels, grp = ib / n_panels;
-  const int groups = (nbx - panel + n_panels - 1) / n_panels;
-  const int slot0 = panel * TJ * 16;
-  for (int e = threadIdx.x; e < TJ * 16 * 2 * KE; e += 64 * NW) {
-    const int sl = e / (2 * KE), kk = e - sl * (2 * KE), slot = slot0 + sl;
-    double v = 0.0;
-    if (slot < a.h) {
-      if (kk < KE) {
-        if (kk <= a.L) v = a.TF[(long)slot * a.ldtf + kk];
-      } else if (kk - KE < a.L) {
-        v = a.TF[(long)slot * a.ldtf + a.ks + (kk - KE)];
-      }
-    }
-    Bs[sl * ldb + kk] = v;
-  }
-  __syncthreads();
+// The wave's sweep for a panel of TJR basis tiles (TJR <= TJ: the last panel
+// of a row may hold fewer), once its panel is in LDS.
+template <int TI, int TJR, int NW, int P>
+__device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, const double *Bs, int ldb, int NQ,
+                                                     int KE, int slot0, int groups, int grp, int xcd,
+                                                     int tiles_j, int tiles_total) {
+  constexpr int TJ = TJR;
+  const int NQO = (a.L + 3) / 4;   // sine steps that hold a column (the last step may hold none)
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, r16 = lane & 15;
   const int per = tiles_total / 8, rem = tiles_total % 8;
@@ -145,10 +127,14 @@ __global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) {
-          accE[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE[i], bE[j], accE[i][j], 0, 0, 0);
-          accO[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO[i], bO[j], accO[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < TJ; ++j) accE[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE[i], bE[j], accE[i][j], 0, 0, 0);
+      if (q < NQO) {  // uniform: a sine step past L adds nothing
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+            accO[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO[i], bO[j], accO[i][j], 0, 0, 0);
+      }
 #pragma unroll
       for (int j = 0; j < TJ; ++j) {
         bE[j] = nE[j];
@@ -180,6 +166,41 @@ __global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n
       }
     }
   }
+}
+
+template <int TI, int TJ, int NW, int P, int LDB>
+__global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n_panels, int tiles_j,
+                                                          int tiles_total) {
+  __shared__ double Bs[TJ * 16 * LDB];
+  const int NQ = (a.L + 4) / 4;   // steps: cosine columns m = 4q + g (m <= L), sine m = 4q + g + 1
+  const int KE = 4 * NQ;          // panel row: cosine part [0, KE), sine part [KE, 2 KE)
+  const int ldb = 2 * KE + 2;     // row stride: 16 rows x 2 lanes land on distinct LDS bank pairs
+  // blocks of one XCD (blockIdx % 8, the hardware's round-robin) share one
+  // contiguous run of row tiles; within it, block ib serves panel ib % n_panels
+  const int xcd = blockIdx.x & 7, ib = blockIdx.x >> 3, nbx = (int)(gridDim.x >> 3);
+  const int panel = ib % n_panels, grp = ib / n_panels;
+  const int groups = (nbx - panel + n_panels - 1) / n_panels;
+  const int slot0 = panel * TJ * 16;
+  for (int e = threadIdx.x; e < TJ * 16 * 2 * KE; e += 64 * NW) {
+    const int sl = e / (2 * KE), kk = e - sl * (2 * KE), slot = slot0 + sl;
+    double v = 0.0;
+    if (slot < a.h) {
+      if (kk < KE) {
+        if (kk <= a.L) v = a.TF[(long)slot * a.ldtf + kk];
+      } else if (kk - KE < a.L) {
+        v = a.TF[(long)slot * a.ldtf + a.ks + (kk - KE)];
+      }
+    }
+    Bs[sl * ldb + kk] = v;
+  }
+  __syncthreads();
+  // the last panel of a row runs with the tiles it holds when that is one
+  // fewer (the other cases keep the full panel; its surplus tiles are zero)
+  if (TJ > 1 && a.h - slot0 <= 16 * (TJ - 1))
+    phi_syn_stream_sweep<TI, (TJ > 1 ? TJ - 1 : 1), NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j,
+                                                           tiles_total);
+  else
+    phi_syn_stream_sweep<TI, TJ, NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j, tiles_total);
 }
 
 namespace {
