@@ -363,9 +363,13 @@ int yyg_sep_lp_kernel(const yyg_grid *g, int precision, int phase, char *name, s
 
 /* Set the tile of reduced-precision phi transform `phase` (0 or 4) of the
  * separable form for `precision` (YYG_FP32 or YYG_BF16X3) by hand: tile in
- * [0, 6) (64 x 80, 128 x 48, 64 x 64, 64 x 32, 32 x 32, 128 x 80).  For tests
- * and expert tuning; yyg_autotune chooses them.  Needs the separable form
- * built. */
+ * [0, 6) (64 x 80, 128 x 48, 64 x 64, 64 x 32, 32 x 32, 128 x 80); the FP32
+ * phi synthesis of a mirror-symmetric grid also takes [6, 11), the
+ * streaming kernel of yyg_sep_config's phi synthesis with an FP32 basis
+ * panel and FP32 products added to FP64 sums every 16 columns (the first 4
+ * for lmax <= 67, the last for lmax <= 131; YYG_ERR_UNSUPPORTED beyond and
+ * on other grids).  For tests and expert tuning; yyg_autotune chooses them.
+ * Needs the separable form built. */
 int yyg_sep_lp_config(yyg_grid *g, int precision, int phase, int tile);
 
 /* Launch one phase (0-4, as for yyg_sep_config) of the separable solve on

@@ -737,9 +737,24 @@ int check_rho(yyg_grid *g, const double *rho, hipStream_t s) {
   return h ? YYG_ERR_NONFINITE : YYG_OK;
 }
 
+// Choices of a reduced-precision phi transform (side 0 analysis, 1
+// synthesis): the tile shapes, and for the FP32 synthesis of a folded grid
+// also the FP32 streaming kernels after them.
+int sep_lp_choices(const yyg_grid *g, int precision, int side) {
+  return yyg::sep_lp_tile_count() +
+         (precision == YYG_FP32 && side == 1 && g->sep.fold ? yyg::phi_stream32_variant_count() : 0);
+}
+
+bool sep_lp_available(const yyg_grid *g, int precision, int side, int t) {
+  if (t < 0 || t >= sep_lp_choices(g, precision, side)) return false;
+  return t < yyg::sep_lp_tile_count() || yyg::phi_stream32_supports(t - yyg::sep_lp_tile_count(), g->L);
+}
+
 hipError_t sep_launch_phi(yyg_grid *g, int r, int precision, hipStream_t s) {
   auto &S = g->sep;
   if (precision == YYG_FP64) return sep_launch_phase(g, r, s);
+  if (r == 4 && precision == YYG_FP32 && S.lpt[0][1] >= yyg::sep_lp_tile_count())
+    return yyg::launch_phi_syn_stream32(S.lpt[0][1] - yyg::sep_lp_tile_count(), S.phi_syn_s, g->cus, s);
   const yyg::GemmF64Args &phi = r == 0 ? (S.fold ? S.phi_ana_f : S.phi_ana) : (S.fold ? S.phi_syn_f : S.phi_syn);
   return yyg::launch_sep_lp_phase(precision, S.lpt[precision - 1][r == 0 ? 0 : 1], r, S.fold, phi, s);
 }
@@ -1743,8 +1758,8 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
       int best = cur;
       double bt = solve_ms() - 1e-4;
       const int t0 = cur;
-      for (int t = 0; t < yyg::sep_lp_tile_count(); ++t) {
-        if (t == t0) continue;
+      for (int t = 0; t < sep_lp_choices(g, precision, r); ++t) {
+        if (t == t0 || !sep_lp_available(g, precision, r, t)) continue;
         cur = t;
         const double tm = solve_ms();
         if (tm < bt) {
@@ -2056,9 +2071,11 @@ int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
 int yyg_sep_lp_config(yyg_grid *g, int precision, int phase, int tile) {
   if (!g || (phase != 0 && phase != 4)) return YYG_ERR_INVALID_ARG;
   if (precision != YYG_FP32 && precision != YYG_BF16X3) return YYG_ERR_INVALID_ARG;
-  if (tile < 0 || tile >= yyg::sep_lp_tile_count()) return YYG_ERR_INVALID_ARG;
   if (!g->sep.ready) return YYG_ERR_NOT_READY;
-  g->sep.lpt[precision - 1][phase == 0 ? 0 : 1] = tile;
+  const int side = phase == 0 ? 0 : 1;
+  if (tile < 0 || tile >= yyg::sep_lp_tile_count() + yyg::phi_stream32_variant_count()) return YYG_ERR_INVALID_ARG;
+  if (!sep_lp_available(g, precision, side, tile)) return YYG_ERR_UNSUPPORTED;
+  g->sep.lpt[precision - 1][side] = tile;
   return YYG_OK;
 }
 
@@ -2066,10 +2083,10 @@ int yyg_sep_lp_kernel(const yyg_grid *g, int precision, int phase, char *name, s
   if (!g || !name || n < 1 || (phase != 0 && phase != 4)) return YYG_ERR_INVALID_ARG;
   if (precision != YYG_FP32 && precision != YYG_BF16X3) return YYG_ERR_INVALID_ARG;
   if (!g->sep.ready) return YYG_ERR_NOT_READY;
-  return yyg::sep_lp_kernel_name(precision, g->sep.lpt[precision - 1][phase == 0 ? 0 : 1], phase, g->sep.fold, name,
-                                 n) == 0
-             ? YYG_OK
-             : YYG_ERR_INVALID_ARG;
+  const int t = g->sep.lpt[precision - 1][phase == 0 ? 0 : 1];
+  const int r = t >= yyg::sep_lp_tile_count() ? yyg::phi_stream32_kernel_name(t - yyg::sep_lp_tile_count(), name, n)
+                                              : yyg::sep_lp_kernel_name(precision, t, phase, g->sep.fold, name, n);
+  return r == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
 }
 
 int yyg_batch_create(yyg_grid *const *grids, int n, int precision, yyg_batch **out) {

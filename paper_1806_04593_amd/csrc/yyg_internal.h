@@ -342,5 +342,11 @@ bool phi_stream_supports(int v, int L);
 int phi_stream_kernel_name(int v, char *buf, size_t n);
 // cus: compute units of the device (the persistent grid's size)
 hipError_t launch_phi_syn_stream(int v, const PhiStreamArgs &a, int cus, hipStream_t s);
+// the same with FP32 basis panels and FP32 MFMAs flushed to FP64 every 16
+// columns (the separable form's FP32 precision)
+int phi_stream32_variant_count();
+bool phi_stream32_supports(int v, int L);
+int phi_stream32_kernel_name(int v, char *buf, size_t n);
+hipError_t launch_phi_syn_stream32(int v, const PhiStreamArgs &a, int cus, hipStream_t s);
 
 }  // namespace yyg

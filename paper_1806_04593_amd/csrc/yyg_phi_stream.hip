@@ -203,6 +203,190 @@ __global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n
     phi_syn_stream_sweep<TI, TJ, NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j, tiles_total);
 }
 
+// FP32 form (the separable solve's FP32 precision): the basis panel in LDS
+// as FP32, the coefficients converted to FP32 as they enter the MFMA, FP32
+// 16x16x4 products accumulated over FL steps (FL 4: 16 cosine and 16 sine
+// columns, as the reduced-precision tiles flush every 16-wide stage) and then
+// added to FP64 accumulators.  D layout of the FP32 MFMA: lane l, element r
+// -> row 4 (l / 16) + r, cell l % 16.
+template <int TI, int TJR, int NW, int P>
+__device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, const float *Bs, int ldb, int NQ,
+                                                       int KE, int slot0, int groups, int grp, int xcd,
+                                                       int tiles_j, int tiles_total) {
+  constexpr int TJ = TJR, FL = 4;
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const int NQO = (a.L + 3) / 4;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, r16 = lane & 15;
+  const int per = tiles_total / 8, rem = tiles_total % 8;
+  const int t_beg = xcd * per + min(xcd, rem), t_end = t_beg + per + (xcd < rem ? 1 : 0);
+  const int stride = groups * NW;
+  int t = t_beg + grp * NW + wave;
+  if (t >= t_end) return;
+  auto rowbase = [&](int tt, int i) -> int {
+    tt = min(tt, tiles_total - 1);
+    const int jl = tt / tiles_j, rt = tt - jl * tiles_j;
+    return jl * a.Mr + min(rt * 16 * TI + 16 * i + r16, a.Mr - 1);
+  };
+  const int MJ = (int)a.MJ;
+  auto offE = [&](int q) { return min(max(8 * q + 2 * g - 1, 0), a.nmc - 1) * MJ; };
+  auto offO = [&](int q) { return min(8 * q + 2 * g + 2, a.nmc - 1) * MJ; };
+  dbl4s accE[TI][TJ], accO[TI][TJ];
+  f32x4 fE[TI][TJ], fO[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      accE[i][j] = dbl4s{0.0, 0.0, 0.0, 0.0};
+      accO[i][j] = dbl4s{0.0, 0.0, 0.0, 0.0};
+      fE[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      fO[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          accE[i][j][r] += (double)fE[i][j][r];
+          accO[i][j][r] += (double)fO[i][j][r];
+          fE[i][j][r] = 0.f;
+          fO[i][j][r] = 0.f;
+        }
+  };
+  const int n_my = (t_end - t + stride - 1) / stride;
+  const int total = (n_my * NQ + P - 1) / P * P;
+  int tl = t, ql = 0;
+  int rbl[TI];
+#pragma unroll
+  for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+  auto advance_load = [&]() {
+    if (++ql == NQ) {
+      ql = 0;
+      tl += stride;
+#pragma unroll
+      for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+    }
+  };
+  double raE[P][TI], raO[P][TI];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int oe = offE(ql), oo = offO(ql);
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      raE[p][i] = a.V[oe + rbl[i]];
+      raO[p][i] = a.V[oo + rbl[i]];
+    }
+    advance_load();
+  }
+  const float *bp = &Bs[r16 * ldb + g];
+  float bE[TJ], bO[TJ];
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    bE[j] = bp[16 * j * ldb];
+    bO[j] = bp[16 * j * ldb + KE];
+  }
+  int q = 0;
+  for (int base = 0; base < total; base += P) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      float nE[TJ], nO[TJ];
+      const int qn = q + 1 == NQ ? 0 : q + 1;
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        nE[j] = bp[16 * j * ldb + 4 * qn];
+        nO[j] = bp[16 * j * ldb + KE + 4 * qn];
+      }
+      float aE[TI], aO[TI];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        aE[i] = (float)raE[p][i];
+        aO[i] = (float)raO[p][i];
+      }
+      {
+        const int oe = offE(ql), oo = offO(ql);
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+          raE[p][i] = a.V[oe + rbl[i]];
+          raO[p][i] = a.V[oo + rbl[i]];
+        }
+        advance_load();
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) fE[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(aE[i], bE[j], fE[i][j], 0, 0, 0);
+      if (q < NQO) {
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) fO[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(aO[i], bO[j], fO[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        bE[j] = nE[j];
+        bO[j] = nO[j];
+      }
+      ++q;
+      if (q % FL == 0 || q == NQ) flush();  // uniform
+      if (q == NQ) {
+        const int jl = t / tiles_j, rt = t - jl * tiles_j;
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = rt * 16 * TI + 16 * i + 4 * g + r, slot = slot0 + 16 * j + r16;
+              if (t < t_end && row < a.Mr && slot < a.h) {
+                double *o = a.phi + (long)row * a.ldc + (long)jl * a.np;
+                const double e = accE[i][j][r], od = accO[i][j][r];
+                o[slot] = e + od;
+                const int cm = a.np - 1 - slot;
+                if (cm != slot) o[cm] = e - od;
+              }
+              accE[i][j][r] = 0.0;
+              accO[i][j][r] = 0.0;
+            }
+        q = 0;
+        t += stride;
+      }
+    }
+  }
+}
+
+template <int TI, int TJ, int NW, int P, int LDB>
+__global__ __launch_bounds__(64 * NW) void phi_syn_stream32(PhiStreamArgs a, int n_panels, int tiles_j,
+                                                            int tiles_total) {
+  __shared__ float Bs[TJ * 16 * LDB];
+  const int NQ = (a.L + 4) / 4;
+  const int KE = 4 * NQ;
+  const int ldb = 2 * KE + 2;     // 32 lanes of a 4-byte read on distinct banks
+  const int xcd = blockIdx.x & 7, ib = blockIdx.x >> 3, nbx = (int)(gridDim.x >> 3);
+  const int panel = ib % n_panels, grp = ib / n_panels;
+  const int groups = (nbx - panel + n_panels - 1) / n_panels;
+  const int slot0 = panel * TJ * 16;
+  for (int e = threadIdx.x; e < TJ * 16 * 2 * KE; e += 64 * NW) {
+    const int sl = e / (2 * KE), kk = e - sl * (2 * KE), slot = slot0 + sl;
+    double v = 0.0;
+    if (slot < a.h) {
+      if (kk < KE) {
+        if (kk <= a.L) v = a.TF[(long)slot * a.ldtf + kk];
+      } else if (kk - KE < a.L) {
+        v = a.TF[(long)slot * a.ldtf + a.ks + (kk - KE)];
+      }
+    }
+    Bs[sl * ldb + kk] = (float)v;
+  }
+  __syncthreads();
+  if (TJ > 1 && a.h - slot0 <= 16 * (TJ - 1))
+    phi_syn_stream32_sweep<TI, (TJ > 1 ? TJ - 1 : 1), NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j,
+                                                             tiles_total);
+  else
+    phi_syn_stream32_sweep<TI, TJ, NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j, tiles_total);
+}
+
 namespace {
 
 struct StreamVariant {
@@ -224,7 +408,30 @@ const StreamVariant kStream[] = {
     YYG_STREAM(1, 6, 8, 8, 138, 1), YYG_STREAM(1, 3, 8, 4, 266, 1),
 };
 
+#define YYG_STREAM32(TI, TJ, NW, P, LDB, BPC)                                                           \
+  {                                                                                                     \
+    TI, TJ, NW, P, LDB, BPC, phi_syn_stream32<TI, TJ, NW, P, LDB>,                                      \
+        "yyg::phi_syn_stream32<" #TI ", " #TJ ", " #NW ", " #P ", " #LDB ">"                            \
+  }
+
+// FP32 panels: LDB floats per row (L <= 67 at 138, L <= 131 at 266)
+const StreamVariant kStream32[] = {
+    YYG_STREAM32(1, 6, 8, 4, 138, 1), YYG_STREAM32(1, 4, 4, 8, 138, 2), YYG_STREAM32(1, 5, 8, 4, 138, 1),
+    YYG_STREAM32(1, 3, 4, 4, 138, 2), YYG_STREAM32(1, 6, 8, 4, 266, 1),
+};
+
 }  // namespace
+
+int phi_stream32_variant_count() { return (int)(sizeof(kStream32) / sizeof(kStream32[0])); }
+
+bool phi_stream32_supports(int v, int L) {
+  return v >= 0 && v < phi_stream32_variant_count() && L >= 0 && 8 * ((L + 4) / 4) + 2 <= kStream32[v].ldb;
+}
+
+int phi_stream32_kernel_name(int v, char *buf, size_t n) {
+  if (v < 0 || v >= phi_stream32_variant_count()) return -1;
+  return snprintf(buf, n, "%s", kStream32[v].name) < 0 ? -1 : 0;
+}
 
 int phi_stream_variant_count() { return (int)(sizeof(kStream) / sizeof(kStream[0])); }
 
@@ -237,10 +444,10 @@ int phi_stream_kernel_name(int v, char *buf, size_t n) {
   return snprintf(buf, n, "%s", kStream[v].name) < 0 ? -1 : 0;
 }
 
-hipError_t launch_phi_syn_stream(int v, const PhiStreamArgs &a, int cus, hipStream_t s) {
-  if (!phi_stream_supports(v, a.L)) return hipErrorInvalidValue;
+namespace {
+
+hipError_t launch_stream(const StreamVariant &k, const PhiStreamArgs &a, int cus, hipStream_t s) {
   if (a.Mr <= 0 || a.nt <= 0 || a.h <= 0) return hipSuccess;
-  const StreamVariant &k = kStream[v];
   // element offsets of the coefficients are 32-bit in the kernel
   if ((long)a.nmc * a.MJ >= INT_MAX) return hipErrorInvalidValue;
   const int rows = 16 * k.ti;
@@ -252,6 +459,18 @@ hipError_t launch_phi_syn_stream(int v, const PhiStreamArgs &a, int cus, hipStre
   const dim3 grid(8 * per_xcd), block(64 * k.nw);
   hipLaunchKernelGGL(k.kernel, grid, block, 0, s, a, n_panels, (int)tj, (int)tt);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_phi_syn_stream(int v, const PhiStreamArgs &a, int cus, hipStream_t s) {
+  if (!phi_stream_supports(v, a.L)) return hipErrorInvalidValue;
+  return launch_stream(kStream[v], a, cus, s);
+}
+
+hipError_t launch_phi_syn_stream32(int v, const PhiStreamArgs &a, int cus, hipStream_t s) {
+  if (!phi_stream32_supports(v, a.L)) return hipErrorInvalidValue;
+  return launch_stream(kStream32[v], a, cus, s);
 }
 
 }  // namespace yyg

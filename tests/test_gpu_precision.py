@@ -107,6 +107,7 @@ def test_workload_errors(name):
 # ---------------------------------------------------------------------------
 
 N_SEP_LP_TILES = 6
+N_STREAM32 = 5   # FP32 phi synthesis: the FP32 streaming kernels after the tiles
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
@@ -122,7 +123,8 @@ def test_separable_reduced_precision_every_tile(precision):
     g = _grid(desc)
     g.set_method("separable")
     for phase in (0, 4):
-        for t in range(N_SEP_LP_TILES):
+        n = N_SEP_LP_TILES + (N_STREAM32 if precision == "fp32" and phase == 4 else 0)
+        for t in range(n):
             _set_lp_tile(g, precision, phase, t)
             phi = _solve(g, rho, precision)
             err = float(np.max(np.abs(phi - ref) / np.abs(ref)))
@@ -148,6 +150,21 @@ def test_separable_reduced_precision_every_tile(precision):
             err = float(np.max(np.abs(got - ref) / np.abs(ref)))
         _say(f"separable {precision} {name}: {err:.3e}")
         assert err <= TOL[precision], (name, err)
+
+
+def test_separable_stream32_only_for_the_fp32_synthesis():
+    """The FP32 streaming kernels are choices of the FP32 phi synthesis only:
+    the analysis and BF16 x 3 refuse them."""
+    from paper_1806_04593_amd import yyg
+    desc = W.make_desc("edge", np.geomspace(1.0, 50.0, 38), 9.0, 11, 0.9, 0)
+    g = _grid(desc)
+    g.set_method("separable")
+    L = yyg.lib()
+    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 4, N_SEP_LP_TILES) == 0
+    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 0, N_SEP_LP_TILES) == yyg.ERR_UNSUPPORTED
+    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["bf16x3"], 4, N_SEP_LP_TILES) == yyg.ERR_UNSUPPORTED
+    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 4,
+                               N_SEP_LP_TILES + N_STREAM32) == yyg.ERR_INVALID_ARG
 
 
 def _set_lp_tile(g, precision, phase, t):
