@@ -329,11 +329,11 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * one block covers both halves of its rows (the analysis reading each
  * density value once, the synthesis its tiles ordered along the cells;
  * mirror-symmetric grids only, else YYG_ERR_UNSUPPORTED).  Last, the phi
- * synthesis takes 5 folded streaming kernels: each block keeps one panel of
+ * synthesis takes 7 folded streaming kernels: each block keeps one panel of
  * the folded basis in LDS for its whole life and its waves sweep row tiles
  * on their own, loading the coefficients straight into 16x16x4 FP64 MFMA
  * operands several steps ahead (persistent grid of one to three blocks per
- * compute unit); the first 4 hold lmax <= 67, the last lmax <= 131
+ * compute unit); the first 6 hold lmax <= 67, the last lmax <= 131
  * (YYG_ERR_UNSUPPORTED beyond, and on grids that are not mirror-symmetric).
  * yyg_sep_variant_count gives the length of each phase's range.
  * Needs the separable form built (yyg_set_method); synchronises the

@@ -89,25 +89,37 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
     }
     advance_load();
   }
-  // basis fragments of the current step, read one step ahead: lane (g, r16)
-  // holds cell 16 j + r16 of the panel at column 4 q + g
+  // basis fragments of the current step, read one step ahead (up to 6
+  // tiles; wider panels read them at the step, for registers): lane
+  // (g, r16) holds cell 16 j + r16 of the panel at column 4 q + g
+  constexpr bool BPF = TJ <= 6;
   const double *bp = &Bs[r16 * ldb + g];
   double bE[TJ], bO[TJ];
+  if constexpr (BPF) {
 #pragma unroll
-  for (int j = 0; j < TJ; ++j) {
-    bE[j] = bp[16 * j * ldb];
-    bO[j] = bp[16 * j * ldb + KE];
+    for (int j = 0; j < TJ; ++j) {
+      bE[j] = bp[16 * j * ldb];
+      bO[j] = bp[16 * j * ldb + KE];
+    }
   }
   int q = 0;
   for (int base = 0; base < total; base += P) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      double nE[TJ], nO[TJ];
-      const int qn = q + 1 == NQ ? 0 : q + 1;
+      double nE[BPF ? TJ : 1], nO[BPF ? TJ : 1];
+      if constexpr (BPF) {
+        const int qn = q + 1 == NQ ? 0 : q + 1;
 #pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-        nE[j] = bp[16 * j * ldb + 4 * qn];
-        nO[j] = bp[16 * j * ldb + KE + 4 * qn];
+        for (int j = 0; j < TJ; ++j) {
+          nE[j] = bp[16 * j * ldb + 4 * qn];
+          nO[j] = bp[16 * j * ldb + KE + 4 * qn];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          bE[j] = bp[16 * j * ldb + 4 * q];
+          bO[j] = bp[16 * j * ldb + KE + 4 * q];
+        }
       }
       double aE[TI], aO[TI];
 #pragma unroll
@@ -135,10 +147,12 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
           for (int j = 0; j < TJ; ++j)
             accO[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO[i], bO[j], accO[i][j], 0, 0, 0);
       }
+      if constexpr (BPF) {
 #pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-        bE[j] = nE[j];
-        bO[j] = nO[j];
+        for (int j = 0; j < TJ; ++j) {
+          bE[j] = nE[j];
+          bO[j] = nO[j];
+        }
       }
       if (++q == NQ) {
         // tile t done: D layout of the 16x16x4 FP64 MFMA, lane l, element r
@@ -405,7 +419,8 @@ struct StreamVariant {
 // doubles) fit its LDB: L <= 67 at 138, L <= 131 at 266
 const StreamVariant kStream[] = {
     YYG_STREAM(1, 6, 8, 4, 138, 1), YYG_STREAM(1, 4, 8, 8, 138, 1), YYG_STREAM(1, 3, 4, 8, 138, 3),
-    YYG_STREAM(1, 6, 8, 8, 138, 1), YYG_STREAM(1, 3, 8, 4, 266, 1),
+    YYG_STREAM(1, 6, 8, 8, 138, 1), YYG_STREAM(1, 9, 8, 4, 138, 1), YYG_STREAM(1, 9, 8, 2, 138, 1),
+    YYG_STREAM(1, 3, 8, 4, 266, 1),
 };
 
 #define YYG_STREAM32(TI, TJ, NW, P, LDB, BPC)                                                           \

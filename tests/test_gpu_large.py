@@ -224,7 +224,8 @@ def test_binary_separable_reduced_precision(precision):
     g.set_method("dense")
 
 
-N_STREAM_BINARY = 4   # streaming phi-synthesis variants that hold lmax 64
+N_STREAM = 7          # streaming phi-synthesis variants, last in the phase's range
+N_STREAM_BINARY = 6   # of which the first six hold lmax 64
 
 
 def test_binary_separable_stream_variants():
@@ -234,7 +235,7 @@ def test_binary_separable_stream_variants():
     g, _ = _binary_grid()
     g.set_method("separable")
     n = g.sep_variant_count(4)
-    for v in range(n - 5, n - 5 + N_STREAM_BINARY):
+    for v in range(n - N_STREAM, n - N_STREAM + N_STREAM_BINARY):
         g.sep_config(4, v)
         d_phi = _solve(g)
         err = _max_rel(_at(d_phi, s), ref)

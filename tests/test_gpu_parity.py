@@ -123,8 +123,8 @@ N_PHI_FOLD = 8
 N_PHI_LEAN = 4   # phi synthesis only
 N_X4 = 12        # tiles on the 4x4x4 FP64 MFMA, every phase (last in each phase's range)
 N_BOTH = {0: 8, 4: 6}   # then the folded phi transforms with both halves per block
-N_STREAM = 5     # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
-N_STREAM_SMALL_L = 4   # of which the first four hold panels up to lmax 67, the last up to 131
+N_STREAM = 7     # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
+N_STREAM_SMALL_L = 6   # of which the first six hold panels up to lmax 67, the last up to 131
 
 
 def _n_x4(phase):
