@@ -335,6 +335,10 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * operands several steps ahead (persistent grid of one to three blocks per
  * compute unit); the first 6 hold lmax <= 67, the last lmax <= 131
  * (YYG_ERR_UNSUPPORTED beyond, and on grids that are not mirror-symmetric).
+ * The phi analysis likewise ends with 6 streaming kernels (the
+ * colatitude-independent folded C/S basis in LDS, the overlap weights
+ * applied to the density pairs as they load; folded point counts
+ * h <= 272 for the first 5, h <= 416 for the last).
  * yyg_sep_variant_count gives the length of each phase's range.
  * Needs the separable form built (yyg_set_method); synchronises the
  * device.  For tests and expert tuning; yyg_autotune chooses all of them. */

@@ -170,6 +170,9 @@ struct yyg_grid {
     double *TF = nullptr;    // folded synthesis basis [h][ldtf]: cos m at m, sin m at ks + m - 1
     yyg::GemmF64Args phi_ana_f{}, phi_syn_f{};
     yyg::PhiStreamArgs phi_syn_s{};  // streaming folded synthesis
+    yyg::PhiAnaStreamArgs phi_ana_s{};  // streaming folded analysis
+    double *CSF = nullptr;  // its colatitude-independent folded basis [16 (nte + nto)][ldcs]
+    double *Wt = nullptr;   // its folded overlap weights [n_t][ldcs]
     // folded analysis, both halves per block: basis rows cos m at slot m
     // (m <= L), sin m at slot ks + m - 1, [n_t][ks + L][ldkh], exact weights
     double *WFAB = nullptr;
@@ -212,8 +215,8 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 // so that a retry starts from nothing).
 void sep_release(yyg_grid *g) {
   auto &S = g->sep;
-  double **b[] = {&S.Wcs, &S.trig, &S.T2, &S.P2, &S.Drot, &S.X2, &S.V,   &S.Ut,
-                  &S.coefS, &S.At, &S.WF, &S.TF, &S.WFD, &S.TFD, &S.BK, &S.WFAB};
+  double **b[] = {&S.Wcs, &S.trig, &S.T2, &S.P2, &S.Drot, &S.X2, &S.V,   &S.Ut,  &S.coefS,
+                  &S.At,  &S.WF,   &S.TF, &S.WFD, &S.TFD,  &S.BK, &S.WFAB, &S.CSF, &S.Wt};
   for (double **x : b) {
     if (*x) (void)dev_free(*x);
     *x = nullptr;
@@ -367,16 +370,19 @@ int sep_x4_base(int r) {
   return r == 0 ? v + phi : r == 4 ? v + phi + yyg::phi_lean_variant_count() : v;
 }
 
-// The phi synthesis then takes the streaming kernels
-// (yyg::phi_stream_variant_count(), folded grids only) after those.
-int sep_stream_base() { return sep_x4_base(4) + yyg::x4_variant_count(4); }
+// The phi transforms then take the streaming kernels after those (folded
+// grids only): yyg::phi_ana_stream_variant_count() for the analysis,
+// yyg::phi_stream_variant_count() for the synthesis.
+int sep_stream_base(int r) { return sep_x4_base(r) + yyg::x4_variant_count(r); }
 
-int sep_variant_count(int r) {
-  return sep_x4_base(r) + yyg::x4_variant_count(r) + (r == 4 ? yyg::phi_stream_variant_count() : 0);
+int sep_stream_count(int r) {
+  return r == 0 ? yyg::phi_ana_stream_variant_count() : r == 4 ? yyg::phi_stream_variant_count() : 0;
 }
 
+int sep_variant_count(int r) { return sep_stream_base(r) + sep_stream_count(r); }
+
 bool sep_fold_variant(int r, int v) {
-  if (r == 4 && v >= sep_stream_base()) return true;
+  if ((r == 0 || r == 4) && v >= sep_stream_base(r)) return true;
   if (v >= sep_x4_base(r)) return yyg::x4_fold_only(r, v - sep_x4_base(r)) != 0;
   return (r == 0 || r == 4) && v >= 2 * yyg::gemm_f64_variant_count() + yyg::phi_direct_variant_count();
 }
@@ -385,14 +391,15 @@ bool sep_fold_variant(int r, int v) {
 bool sep_variant_available(const yyg_grid *g, int r, int v) {
   if (r < 0 || r > 4 || v < 0 || v >= sep_variant_count(r)) return false;
   if (sep_fold_variant(r, v) && !g->sep.fold) return false;
-  return !(r == 4 && v >= sep_stream_base() && !yyg::phi_stream_supports(v - sep_stream_base(), g->L));
+  if (r == 4 && v >= sep_stream_base(4)) return yyg::phi_stream_supports(v - sep_stream_base(4), g->L);
+  if (r == 0 && v >= sep_stream_base(0))
+    return yyg::phi_ana_stream_supports(v - sep_stream_base(0), (int)g->sep.h, g->n_p);
+  return true;
 }
 
 int sep_set_variant(yyg_grid *g, int r, int v) {
   if (r < 0 || r > 4 || v < 0 || v >= sep_variant_count(r)) return YYG_ERR_INVALID_ARG;
-  if (sep_fold_variant(r, v) && !g->sep.fold) return YYG_ERR_UNSUPPORTED;
-  if (r == 4 && v >= sep_stream_base() && !yyg::phi_stream_supports(v - sep_stream_base(), g->L))
-    return YYG_ERR_UNSUPPORTED;
+  if (!sep_variant_available(g, r, v)) return YYG_ERR_UNSUPPORTED;
   g->sep.var[r] = v;
   return YYG_OK;
 }
@@ -401,8 +408,10 @@ hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   auto &S = g->sep;
   const int nv = yyg::gemm_f64_variant_count(), nd = yyg::phi_direct_variant_count();
   const int nf = yyg::phi_fold_variant_count();
-  if (r == 4 && S.var[r] >= sep_stream_base())
-    return yyg::launch_phi_syn_stream(S.var[r] - sep_stream_base(), S.phi_syn_s, g->cus, s);
+  if (r == 4 && S.var[r] >= sep_stream_base(4))
+    return yyg::launch_phi_syn_stream(S.var[r] - sep_stream_base(4), S.phi_syn_s, g->cus, s);
+  if (r == 0 && S.var[r] >= sep_stream_base(0))
+    return yyg::launch_phi_ana_stream(S.var[r] - sep_stream_base(0), S.phi_ana_s, g->cus, s);
   if (S.var[r] >= sep_x4_base(r)) {
     if (r == 2 && g->n_patch != 2) return hipSuccess;
     const yyg::GemmF64Args &phi = r == 0 ? (S.fold ? S.phi_ana_f : S.phi_ana) : (S.fold ? S.phi_syn_f : S.phi_syn);
@@ -442,6 +451,7 @@ void sep_bind_work(yyg_grid *g, const SepWork &w) {
   S.phi_ana_d.C = S.phi_ana_fd.C = w.X2;
   S.phi_syn.A = S.phi_syn_f.A = w.V;
   S.phi_syn_s.V = w.V;
+  S.phi_ana_s.X2 = w.X2;
   S.phi_syn_d.X = S.phi_syn_fd.X = w.V;
   S.phi_syn_l.V = w.V;
   S.args.X2 = w.X2;
@@ -468,6 +478,7 @@ int sep_set_pointers(yyg_grid *g, const double *rho, double *phi, hipStream_t) {
   g->sep.phi_ana_d.X = rho;
   g->sep.phi_syn_d.C = phi;
   g->sep.phi_ana_f.A = rho;
+  g->sep.phi_ana_s.rho = rho;
   g->sep.phi_ana_ab.A = rho;
   g->sep.phi_syn_f.C = phi;
   g->sep.phi_syn_s.phi = phi;
@@ -486,7 +497,8 @@ int sep_build(yyg_grid *g) {
   S.ldm = round_up(nmc, 16);
   S.ldl = round_up(L + 1, 16);
   if (yyg::radial_scan_q_lds(g->n_r, g->n_patch) > yyg::kScanQMaxLds) return YYG_ERR_UNSUPPORTED;
-  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD, BK, WFAB;
+  std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD, BK, WFAB, CSF, WTF;
+  int nte = 0, nto = 0, ldcs = 0;
   try {
     coef.resize((size_t)4 * g->n_r * (L + 1));
     yyg::radial_coefficients(g->n_r, g->r_edges.data(), L, coef.data());
@@ -559,6 +571,23 @@ int sep_build(yyg_grid *g) {
           TF[(size_t)k * S.ldtf + m] = trig[(size_t)k * S.ldm + (m ? 2 * m - 1 : 0)];
           if (m > 0) TF[(size_t)k * S.ldtf + S.ks + m - 1] = trig[(size_t)k * S.ldm + 2 * m];
         }
+      // the streaming analysis: the folded C / S rows without the weights
+      // (cos outputs m = 0..L in tiles of 16, then sin outputs m = 1..L) and
+      // the weights per colatitude, the middle cell's half in the weight
+      nte = (L + 16) / 16;
+      nto = (L + 15) / 16;
+      ldcs = (int)round_up(h, 16);
+      CSF.assign((size_t)16 * (nte + nto) * ldcs, 0.0);
+      WTF.assign((size_t)nt * ldcs, 0.0);
+      for (int k = 0; k < h; ++k) {
+        for (int m = 0; m <= L; ++m) {
+          CSF[(size_t)m * ldcs + k] = CSt[(size_t)(m ? 2 * m - 1 : 0) * S.ldk + k];
+          if (m > 0) CSF[((size_t)16 * nte + m - 1) * ldcs + k] = CSt[(size_t)(2 * m) * S.ldk + k];
+        }
+        for (int j = 0; j < nt; ++j)
+          WTF[(size_t)j * ldcs + k] =
+              (k == mid ? 0.5 : 1.0) * 0.5 * (g->w_host[(size_t)j * np + k] + g->w_host[(size_t)j * np + np - 1 - k]);
+      }
       // both halves in one basis for kGemmFoldAB: slot s < ks the cos half,
       // ks <= s < ks + L the sin half
       WFAB.assign((size_t)nt * (S.ks + L) * S.ldkh, 0.0);
@@ -635,6 +664,8 @@ int sep_build(yyg_grid *g) {
   if (st == YYG_OK && S.fold) st = dmalloc(&S.TFD, TFD.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.BK, BK.size());
   if (st == YYG_OK && S.fold) st = dmalloc(&S.WFAB, WFAB.size());
+  if (st == YYG_OK && S.fold) st = dmalloc(&S.CSF, CSF.size());
+  if (st == YYG_OK && S.fold) st = dmalloc(&S.Wt, WTF.size());
   if (st != YYG_OK) {
     sep_release(g);
     return st;
@@ -656,6 +687,8 @@ int sep_build(yyg_grid *g) {
     chk(hipMemcpy(S.TFD, TFD.data(), TFD.size() * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemcpy(S.BK, BK.data(), BK.size() * sizeof(double), hipMemcpyHostToDevice));
     chk(hipMemcpy(S.WFAB, WFAB.data(), WFAB.size() * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(S.CSF, CSF.data(), CSF.size() * sizeof(double), hipMemcpyHostToDevice));
+    chk(hipMemcpy(S.Wt, WTF.data(), WTF.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -697,6 +730,8 @@ int sep_build(yyg_grid *g) {
   S.phi_syn_f.fold_mc = nmc;
   S.phi_syn_s = yyg::PhiStreamArgs{S.V, S.TF, nullptr, MJ, (long)nt * np, (int)M, nt, np, (int)S.h, L, nmc,
                                    (int)S.ldtf, (int)S.ks};
+  S.phi_ana_s = yyg::PhiAnaStreamArgs{nullptr, S.CSF, S.Wt, S.X2, MJ, (long)nt * np, (int)M, nt, np, (int)S.h, L,
+                                      nmc, ldcs, nte, nto};
   S.phi_ana_d = yyg::PhiDirectArgs{nullptr, S.Wcs, S.X2, (int)M, nt, nmc, np, S.ldk, (long)nmc * S.ldk};
   S.phi_syn_d = yyg::PhiDirectArgs{S.V, S.trig, nullptr, (int)M, nt, np, nmc, S.ldm, 0};
   S.phi_ana_fd = yyg::PhiDirectArgs{nullptr, S.WFD, S.X2, (int)M, nt, (int)S.nba, (int)S.h, S.h, S.nba * S.h,
@@ -1942,6 +1977,7 @@ int yyg_autotune(yyg_grid *g, int precision, void *stream) {
     g->sep.phi_ana_d.X = nullptr;
     g->sep.phi_syn_d.C = nullptr;
     g->sep.phi_ana_f.A = nullptr;
+    g->sep.phi_ana_s.rho = nullptr;
     g->sep.phi_ana_ab.A = nullptr;
     g->sep.phi_syn_f.C = nullptr;
     g->sep.phi_syn_s.phi = nullptr;
@@ -2062,7 +2098,9 @@ int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
     return YYG_OK;
   }
   const int v = g->sep.var[phase], x0 = sep_x4_base(phase);
-  const int r = phase == 4 && v >= sep_stream_base() ? yyg::phi_stream_kernel_name(v - sep_stream_base(), name, n)
+  const int r = phase == 4 && v >= sep_stream_base(4) ? yyg::phi_stream_kernel_name(v - sep_stream_base(4), name, n)
+                : phase == 0 && v >= sep_stream_base(0)
+                    ? yyg::phi_ana_stream_kernel_name(v - sep_stream_base(0), name, n)
                 : v >= x0 ? yyg::x4_kernel_name(v - x0, phase, g->sep.fold, name, n)
                           : yyg::sep_kernel_name(phase, v, g->sep.fold, name, n);
   return r == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;

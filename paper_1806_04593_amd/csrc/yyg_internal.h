@@ -349,4 +349,24 @@ bool phi_stream32_supports(int v, int L);
 int phi_stream32_kernel_name(int v, char *buf, size_t n);
 hipError_t launch_phi_syn_stream32(int v, const PhiStreamArgs &a, int cus, hipStream_t s);
 
+// Folded phi analysis, streaming form (yyg_phi_stream.hip): for every row
+// (patch, shell) and colatitude j, X2[mc][j][row] = sum_{k < h} a_k CSF[c][k]
+// with a_k = w[j][k] (rho[row][j][k] + rho[row][j][np - 1 - k]) for the
+// cosine outputs c < 16 nte (m = c, column mc = max(2m - 1, 0)) and
+// a_k = w[j][k] (rho_k - rho_mirror) for the sine outputs (m = c - 16 nte + 1,
+// column 2m), m <= L.
+struct PhiAnaStreamArgs {
+  const double *rho;   // [Mr][nt][np]
+  const double *CSF;   // [16 (nte + nto)][ldcs] folded basis, zero past h and past L
+  const double *Wt;    // [nt][ldcs] folded overlap weights (middle cell halved), zero past h
+  double *X2;          // [2L + 1][nt][Mr]
+  long MJ, ldr;        // nt * Mr; nt * np
+  int Mr, nt, np, h, L, nmc, ldcs, nte, nto;
+};
+int phi_ana_stream_variant_count();
+// whether variant v holds the basis panel of h folded points in LDS
+bool phi_ana_stream_supports(int v, int h, int np);
+int phi_ana_stream_kernel_name(int v, char *buf, size_t n);
+hipError_t launch_phi_ana_stream(int v, const PhiAnaStreamArgs &a, int cus, hipStream_t s);
+
 }  // namespace yyg

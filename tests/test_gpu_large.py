@@ -259,3 +259,23 @@ def test_binary_separable_fp32_stream_variants():
         _say(f"binary separable fp32, phi synthesis {g.sep_lp_kernel('fp32', 4)}: max rel err {err:.3e}")
         assert err <= TOL["fp32"] and err <= 1e-6
     g.set_method("dense")
+
+
+N_ANA_STREAM = 6   # streaming phi-analysis variants, last in the phase's range (all hold h = 271)
+
+
+def test_binary_separable_analysis_stream_variants():
+    """Each streaming phi-analysis variant at the binary workload's samples
+    (weights applied to the density pairs as they load), and the moments
+    they lead to within the FP64 rounding bound."""
+    desc, rho, s, ref, AC, AS = _binary()
+    g, _ = _binary_grid()
+    g.set_method("separable")
+    n = g.sep_variant_count(0)
+    for v in range(n - N_ANA_STREAM, n):
+        g.sep_config(0, v)
+        d_phi = _solve(g)
+        err = _max_rel(_at(d_phi, s), ref)
+        _say(f"binary separable, phi analysis {g.sep_kernel(0)}: max rel err {err:.3e}")
+        assert err <= TOL["fp64"]
+    g.set_method("dense")

@@ -125,6 +125,7 @@ N_X4 = 12        # tiles on the 4x4x4 FP64 MFMA, every phase (last in each phase
 N_BOTH = {0: 8, 4: 6}   # then the folded phi transforms with both halves per block
 N_STREAM = 7     # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
 N_STREAM_SMALL_L = 6   # of which the first six hold panels up to lmax 67, the last up to 131
+N_ANA_STREAM = 6   # phi analysis: then the streaming kernels (colatitude-independent basis in LDS)
 
 
 def _n_x4(phase):
@@ -400,7 +401,9 @@ def test_separable_every_phase_variant(phase):
     # every tile with one and with three stages of loads in flight; the phi
     # phases also every LDS-basis variant, unfolded and folded; every phase
     # the 4x4x4-MFMA tiles
-    for v in range(_x4_base(phase) + _n_x4(phase) + (N_STREAM if phase == 4 else 0)):
+    n_stream = N_STREAM if phase == 4 else N_ANA_STREAM if phase == 0 else 0
+    assert g.sep_variant_count(phase) == _x4_base(phase) + _n_x4(phase) + n_stream
+    for v in range(_x4_base(phase) + _n_x4(phase) + n_stream):
         g.sep_config(phase, v)
         _say(f"separable phase {phase} variant {v}: {g.sep_info()}")
         _, phi = _gpu_solve(desc, rho, grid=g)
