@@ -496,7 +496,7 @@ int sep_build(yyg_grid *g) {
   S.ldk = round_up(np, 16);
   S.ldm = round_up(nmc, 16);
   S.ldl = round_up(L + 1, 16);
-  if (yyg::radial_scan_q_lds(g->n_r, g->n_patch) > yyg::kScanQMaxLds) return YYG_ERR_UNSUPPORTED;
+  if (!yyg::radial_scan_q_supports(g->n_r, g->n_patch)) return YYG_ERR_UNSUPPORTED;
   std::vector<double> CSt, Wcs, trig, T, P, T2, P2, D, coef, coefS, WF, TF, WFD, TFD, BK, WFAB, CSF, WTF;
   int nte = 0, nto = 0, ldcs = 0;
   try {

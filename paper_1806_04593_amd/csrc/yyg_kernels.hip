@@ -1058,6 +1058,12 @@ hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, 
 
 size_t radial_scan_q_lds(int nR, int patches) { return (4UL * nR + (size_t)patches * (2UL * nR + 1)) * sizeof(double); }
 
+// the column and its coefficients fit in LDS and a lane's chunk in the
+// largest instance (63 shells)
+bool radial_scan_q_supports(int nR, int patches) {
+  return nR >= 1 && radial_scan_q_lds(nR, patches) <= kScanQMaxLds && (((nR + 63) / 64) | 1) <= 63;
+}
+
 hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int *qdeg, int nR, int L, double negG,
                                 int patches, double *Ut, hipStream_t s) {
   if (nR <= 0) return hipSuccess;
