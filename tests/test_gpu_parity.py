@@ -411,6 +411,29 @@ def test_separable_every_phase_variant(phase):
         assert err <= TOL_FP64, (phase, v, err)
 
 
+def test_phi_stream_variants_odd_row_length():
+    """The streaming phi transforms on a grid with an odd number of cells
+    per row (7 deg: 41, so the middle cell has no mirror and the last pair
+    of folded cells is cut), every variant of both, against the oracle."""
+    yyg = _yyg()
+    desc = W.make_desc("odd", np.geomspace(1.0, 20.0, 12), 7.0, 9, 0.9, 0)
+    assert desc["n_phi"] % 2 == 1
+    rng = np.random.default_rng(41)
+    rho = rng.uniform(0.1, 1.0, (2, 11, desc["n_theta"], desc["n_phi"]))
+    ref = O.solve(*_oracle_args(desc), rho)
+    g = yyg.Grid(desc, 0)
+    g.set_method("separable")
+    for phase, n in ((4, N_STREAM), (0, N_ANA_STREAM)):
+        total = g.sep_variant_count(phase)
+        for v in range(total - n, total):
+            g.sep_config(phase, v)
+            _, phi = _gpu_solve(desc, rho, grid=g)
+            err = _max_rel(phi, ref)
+            _say(f"odd n_phi {desc['n_phi']}: {g.sep_kernel(phase)} {err:.2e}")
+            assert err <= TOL_FP64, (phase, v, err)
+        g.sep_config(phase, 10)
+
+
 def test_phi_stream_variants_at_high_degree():
     """The streaming phi synthesis at lmax 80 (21 steps of four cosine and
     four sine columns): the variants whose LDS panel holds only lmax <= 67
