@@ -367,12 +367,15 @@ int yyg_sep_lp_kernel(const yyg_grid *g, int precision, int phase, char *name, s
 
 /* Set the tile of reduced-precision phi transform `phase` (0 or 4) of the
  * separable form for `precision` (YYG_FP32 or YYG_BF16X3) by hand: tile in
- * [0, 6) (64 x 80, 128 x 48, 64 x 64, 64 x 32, 32 x 32, 128 x 80); the FP32
- * phi synthesis of a mirror-symmetric grid also takes [6, 11), the
+ * [0, 6) (64 x 80, 128 x 48, 64 x 64, 64 x 32, 32 x 32, 128 x 80).  In FP32
+ * on a mirror-symmetric grid the phi synthesis also takes [6, 11), the
  * streaming kernel of yyg_sep_config's phi synthesis with an FP32 basis
  * panel and FP32 products added to FP64 sums every 16 columns (the first 4
- * for lmax <= 67, the last for lmax <= 131; YYG_ERR_UNSUPPORTED beyond and
- * on other grids).  For tests and expert tuning; yyg_autotune chooses them.
+ * for lmax <= 67, the last for lmax <= 131), and the phi analysis [6, 10),
+ * the streaming analysis with an FP32 basis panel (a degree up to 64 in one
+ * panel of 9 tiles for the first two, so that each density row is read
+ * once; FP64 sums every 16 points; h <= 272) — YYG_ERR_UNSUPPORTED beyond
+ * these limits and on other grids.  For tests and expert tuning; yyg_autotune chooses them.
  * Needs the separable form built. */
 int yyg_sep_lp_config(yyg_grid *g, int precision, int phase, int tile);
 

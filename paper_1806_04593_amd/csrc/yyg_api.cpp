@@ -773,16 +773,19 @@ int check_rho(yyg_grid *g, const double *rho, hipStream_t s) {
 }
 
 // Choices of a reduced-precision phi transform (side 0 analysis, 1
-// synthesis): the tile shapes, and for the FP32 synthesis of a folded grid
-// also the FP32 streaming kernels after them.
+// synthesis): the tile shapes, and in FP32 on a folded grid also the FP32
+// streaming kernels after them.
 int sep_lp_choices(const yyg_grid *g, int precision, int side) {
+  if (precision != YYG_FP32 || !g->sep.fold) return yyg::sep_lp_tile_count();
   return yyg::sep_lp_tile_count() +
-         (precision == YYG_FP32 && side == 1 && g->sep.fold ? yyg::phi_stream32_variant_count() : 0);
+         (side == 1 ? yyg::phi_stream32_variant_count() : yyg::phi_ana_stream32_variant_count());
 }
 
 bool sep_lp_available(const yyg_grid *g, int precision, int side, int t) {
   if (t < 0 || t >= sep_lp_choices(g, precision, side)) return false;
-  return t < yyg::sep_lp_tile_count() || yyg::phi_stream32_supports(t - yyg::sep_lp_tile_count(), g->L);
+  const int u = t - yyg::sep_lp_tile_count();
+  if (u < 0) return true;
+  return side == 1 ? yyg::phi_stream32_supports(u, g->L) : yyg::phi_ana_stream32_supports(u, (int)g->sep.h, g->n_p);
 }
 
 hipError_t sep_launch_phi(yyg_grid *g, int r, int precision, hipStream_t s) {
@@ -790,6 +793,8 @@ hipError_t sep_launch_phi(yyg_grid *g, int r, int precision, hipStream_t s) {
   if (precision == YYG_FP64) return sep_launch_phase(g, r, s);
   if (r == 4 && precision == YYG_FP32 && S.lpt[0][1] >= yyg::sep_lp_tile_count())
     return yyg::launch_phi_syn_stream32(S.lpt[0][1] - yyg::sep_lp_tile_count(), S.phi_syn_s, g->cus, s);
+  if (r == 0 && precision == YYG_FP32 && S.lpt[0][0] >= yyg::sep_lp_tile_count())
+    return yyg::launch_phi_ana_stream32(S.lpt[0][0] - yyg::sep_lp_tile_count(), S.phi_ana_s, g->cus, s);
   const yyg::GemmF64Args &phi = r == 0 ? (S.fold ? S.phi_ana_f : S.phi_ana) : (S.fold ? S.phi_syn_f : S.phi_syn);
   return yyg::launch_sep_lp_phase(precision, S.lpt[precision - 1][r == 0 ? 0 : 1], r, S.fold, phi, s);
 }
@@ -2111,7 +2116,9 @@ int yyg_sep_lp_config(yyg_grid *g, int precision, int phase, int tile) {
   if (precision != YYG_FP32 && precision != YYG_BF16X3) return YYG_ERR_INVALID_ARG;
   if (!g->sep.ready) return YYG_ERR_NOT_READY;
   const int side = phase == 0 ? 0 : 1;
-  if (tile < 0 || tile >= yyg::sep_lp_tile_count() + yyg::phi_stream32_variant_count()) return YYG_ERR_INVALID_ARG;
+  if (tile < 0 || tile >= yyg::sep_lp_tile_count() +
+                              std::max(yyg::phi_stream32_variant_count(), yyg::phi_ana_stream32_variant_count()))
+    return YYG_ERR_INVALID_ARG;
   if (!sep_lp_available(g, precision, side, tile)) return YYG_ERR_UNSUPPORTED;
   g->sep.lpt[precision - 1][side] = tile;
   return YYG_OK;
@@ -2121,9 +2128,10 @@ int yyg_sep_lp_kernel(const yyg_grid *g, int precision, int phase, char *name, s
   if (!g || !name || n < 1 || (phase != 0 && phase != 4)) return YYG_ERR_INVALID_ARG;
   if (precision != YYG_FP32 && precision != YYG_BF16X3) return YYG_ERR_INVALID_ARG;
   if (!g->sep.ready) return YYG_ERR_NOT_READY;
-  const int t = g->sep.lpt[precision - 1][phase == 0 ? 0 : 1];
-  const int r = t >= yyg::sep_lp_tile_count() ? yyg::phi_stream32_kernel_name(t - yyg::sep_lp_tile_count(), name, n)
-                                              : yyg::sep_lp_kernel_name(precision, t, phase, g->sep.fold, name, n);
+  const int t = g->sep.lpt[precision - 1][phase == 0 ? 0 : 1], u = t - yyg::sep_lp_tile_count();
+  const int r = u < 0        ? yyg::sep_lp_kernel_name(precision, t, phase, g->sep.fold, name, n)
+                : phase == 4 ? yyg::phi_stream32_kernel_name(u, name, n)
+                             : yyg::phi_ana_stream32_kernel_name(u, name, n);
   return r == 0 ? YYG_OK : YYG_ERR_INVALID_ARG;
 }
 

@@ -370,5 +370,11 @@ int phi_ana_stream_variant_count();
 bool phi_ana_stream_supports(int v, int h, int np);
 int phi_ana_stream_kernel_name(int v, char *buf, size_t n);
 hipError_t launch_phi_ana_stream(int v, const PhiAnaStreamArgs &a, int cus, hipStream_t s);
+// the same with an FP32 basis panel and FP32 MFMAs added to FP64 sums every
+// 16 points (the separable form's FP32 precision)
+int phi_ana_stream32_variant_count();
+bool phi_ana_stream32_supports(int v, int h, int np);
+int phi_ana_stream32_kernel_name(int v, char *buf, size_t n);
+hipError_t launch_phi_ana_stream32(int v, const PhiAnaStreamArgs &a, int cus, hipStream_t s);
 
 }  // namespace yyg

@@ -567,6 +567,158 @@ __global__ __launch_bounds__(64 * NW) void phi_ana_stream(PhiAnaStreamArgs a, in
     phi_ana_stream_sweep<TI, TJ, NW, P>(a, Bs, ldb, NS, tile0, groups, grp, xcd, tiles_j, tiles_total);
 }
 
+// FP32 form of the streaming analysis (the separable solve's FP32
+// precision): the basis panel in LDS as FP32 (all 16 (nte + nto) outputs of
+// a degree up to 64 fit in one panel, so each density row is read once),
+// the weighted density pairs converted to FP32 as they enter the MFMA, the
+// FP32 16x16x4 products of one 16-wide stage added to FP64 sums.  D layout
+// of the FP32 MFMA: lane l, element r -> output 4 (l / 16) + r, row l % 16.
+template <int TI, int TJR, int NW, int P>
+__device__ __forceinline__ void phi_ana_stream32_sweep(const PhiAnaStreamArgs &a, const float *Bs, int ldb, int NS,
+                                                       int tile0, int groups, int grp, int xcd, int tiles_j,
+                                                       int tiles_total) {
+  constexpr int TJ = TJR;
+  typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, r16 = lane & 15;
+  const int per = tiles_total / 8, rem = tiles_total % 8;
+  const int t_beg = xcd * per + min(xcd, rem), t_end = t_beg + per + (xcd < rem ? 1 : 0);
+  const int stride = groups * NW;
+  int t = t_beg + grp * NW + wave;
+  if (t >= t_end) return;
+  auto rowbase = [&](int tt, int i) -> int {
+    tt = min(tt, tiles_total - 1);
+    const int jl = tt / tiles_j, rt = tt - jl * tiles_j;
+    return min(rt * 16 * TI + 16 * i + r16, a.Mr - 1) * (int)a.ldr + jl * a.np;
+  };
+  auto wbase = [&](int tt) -> int { return (min(tt, tiles_total - 1) / tiles_j) * a.ldcs; };
+  bool isE[TJ];
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) isE[j] = tile0 + j < a.nte;
+  dbl4s acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4s{0.0, 0.0, 0.0, 0.0};
+  const int n_my = (t_end - t + stride - 1) / stride;
+  const int total = (n_my * NS + P - 1) / P * P;
+  int tl = t, sl = 0;
+  int rbl[TI], wbl = wbase(tl);
+#pragma unroll
+  for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+  auto advance_load = [&]() {
+    if (++sl == NS) {
+      sl = 0;
+      tl += stride;
+#pragma unroll
+      for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+      wbl = wbase(tl);
+    }
+  };
+  double rf[P][TI][4], rb[P][TI][4], rw[P][4];
+  auto load = [&](int p) {
+    const int k = 16 * sl + 4 * g;
+    const int kf = min(k, a.np - 4), kb = max(a.np - 4 - k, 0);
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      const dbl2u f0 = *reinterpret_cast<const dbl2u *>(a.rho + rbl[i] + kf);
+      const dbl2u f1 = *reinterpret_cast<const dbl2u *>(a.rho + rbl[i] + kf + 2);
+      const dbl2u b0 = *reinterpret_cast<const dbl2u *>(a.rho + rbl[i] + kb);
+      const dbl2u b1 = *reinterpret_cast<const dbl2u *>(a.rho + rbl[i] + kb + 2);
+      rf[p][i][0] = f0.x;
+      rf[p][i][1] = f0.y;
+      rf[p][i][2] = f1.x;
+      rf[p][i][3] = f1.y;
+      rb[p][i][3] = b0.x;
+      rb[p][i][2] = b0.y;
+      rb[p][i][1] = b1.x;
+      rb[p][i][0] = b1.y;
+    }
+    const dbl2u w0 = *reinterpret_cast<const dbl2u *>(a.Wt + wbl + k);
+    const dbl2u w1 = *reinterpret_cast<const dbl2u *>(a.Wt + wbl + k + 2);
+    rw[p][0] = w0.x;
+    rw[p][1] = w0.y;
+    rw[p][2] = w1.x;
+    rw[p][3] = w1.y;
+  };
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    load(p);
+    advance_load();
+  }
+  const float *bp = &Bs[r16 * ldb + 4 * g];
+  int st = 0;
+  for (int base = 0; base < total; base += P) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      float ae[TI][4], ao[TI][4];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          ae[i][s4] = (float)(rw[p][s4] * (rf[p][i][s4] + rb[p][i][s4]));
+          ao[i][s4] = (float)(rw[p][s4] * (rf[p][i][s4] - rb[p][i][s4]));
+        }
+      load(p);
+      advance_load();
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        const f32x4 bf = *reinterpret_cast<const f32x4 *>(bp + 16 * j * ldb + 16 * st);
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+          f32x4 f = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+            f = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[s4], isE[j] ? ae[i][s4] : ao[i][s4], f, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[r];
+        }
+      }
+      if (++st == NS) {
+        const int jl = t / tiles_j, rt = t - jl * tiles_j;
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = rt * 16 * TI + 16 * i + r16, o = 4 * g + r;
+              const int m = isE[j] ? 16 * (tile0 + j) + o : 16 * (tile0 + j - a.nte) + o + 1;
+              const int mc = isE[j] ? max(2 * m - 1, 0) : 2 * m;
+              if (t < t_end && row < a.Mr && m <= a.L && tile0 + j < a.nte + a.nto)
+                a.X2[(long)mc * a.MJ + (long)jl * a.Mr + row] = acc[i][j][r];
+              acc[i][j][r] = 0.0;
+            }
+        st = 0;
+        t += stride;
+      }
+    }
+  }
+}
+
+template <int TI, int TJ, int NW, int P, int LDB>
+__global__ __launch_bounds__(64 * NW) void phi_ana_stream32(PhiAnaStreamArgs a, int n_panels, int tiles_j,
+                                                            int tiles_total) {
+  __shared__ float Bs[TJ * 16 * LDB];
+  const int NS = (a.h + 15) / 16;
+  const int ldb = 16 * NS + 4;      // floats: the 16-byte reads of 8 lanes hit distinct banks
+  const int xcd = blockIdx.x & 7, ib = blockIdx.x >> 3, nbx = (int)(gridDim.x >> 3);
+  const int panel = ib % n_panels, grp = ib / n_panels;
+  const int groups = (nbx - panel + n_panels - 1) / n_panels;
+  const int tile0 = panel * TJ, ntiles = a.nte + a.nto;
+  for (int e = threadIdx.x; e < TJ * 16 * 16 * NS; e += 64 * NW) {
+    const int sl = e / (16 * NS), kk = e - sl * (16 * NS), c = 16 * tile0 + sl;
+    Bs[sl * ldb + kk] = (c < 16 * ntiles && kk < a.ldcs) ? (float)a.CSF[(long)c * a.ldcs + kk] : 0.f;
+  }
+  __syncthreads();
+  if (TJ > 1 && ntiles - tile0 <= TJ - 1)
+    phi_ana_stream32_sweep<TI, (TJ > 1 ? TJ - 1 : 1), NW, P>(a, Bs, ldb, NS, tile0, groups, grp, xcd, tiles_j,
+                                                             tiles_total);
+  else
+    phi_ana_stream32_sweep<TI, TJ, NW, P>(a, Bs, ldb, NS, tile0, groups, grp, xcd, tiles_j, tiles_total);
+}
+
 namespace {
 
 struct StreamVariant {
@@ -619,7 +771,30 @@ const AnaVariant kAna[] = {
     YYG_ANA_STREAM(2, 2, 8, 2, 276, 1), YYG_ANA_STREAM(2, 3, 4, 2, 276, 1), YYG_ANA_STREAM(1, 2, 4, 4, 420, 1),
 };
 
+#define YYG_ANA_STREAM32(TI, TJ, NW, P, LDB, BPC)                                                       \
+  {                                                                                                     \
+    TI, TJ, NW, P, LDB, BPC, phi_ana_stream32<TI, TJ, NW, P, LDB>,                                      \
+        "yyg::phi_ana_stream32<" #TI ", " #TJ ", " #NW ", " #P ", " #LDB ">"                            \
+  }
+
+// FP32 panels: 9 tiles (lmax <= 64 in one panel) x 276 floats (h <= 272)
+const AnaVariant kAna32[] = {
+    YYG_ANA_STREAM32(1, 9, 8, 1, 276, 1), YYG_ANA_STREAM32(1, 9, 8, 2, 276, 1), YYG_ANA_STREAM32(1, 5, 8, 2, 276, 1),
+    YYG_ANA_STREAM32(1, 5, 8, 1, 276, 1),
+};
+
 }  // namespace
+
+int phi_ana_stream32_variant_count() { return (int)(sizeof(kAna32) / sizeof(kAna32[0])); }
+
+bool phi_ana_stream32_supports(int v, int h, int np) {
+  return v >= 0 && v < phi_ana_stream32_variant_count() && np >= 8 && 16 * ((h + 15) / 16) + 4 <= kAna32[v].ldb;
+}
+
+int phi_ana_stream32_kernel_name(int v, char *buf, size_t n) {
+  if (v < 0 || v >= phi_ana_stream32_variant_count()) return -1;
+  return snprintf(buf, n, "%s", kAna32[v].name) < 0 ? -1 : 0;
+}
 
 int phi_ana_stream_variant_count() { return (int)(sizeof(kAna) / sizeof(kAna[0])); }
 
@@ -632,10 +807,10 @@ int phi_ana_stream_kernel_name(int v, char *buf, size_t n) {
   return snprintf(buf, n, "%s", kAna[v].name) < 0 ? -1 : 0;
 }
 
-hipError_t launch_phi_ana_stream(int v, const PhiAnaStreamArgs &a, int cus, hipStream_t s) {
-  if (!phi_ana_stream_supports(v, a.h, a.np)) return hipErrorInvalidValue;
+namespace {
+
+hipError_t launch_ana(const AnaVariant &k, const PhiAnaStreamArgs &a, int cus, hipStream_t s) {
   if (a.Mr <= 0 || a.nt <= 0 || a.h <= 0) return hipSuccess;
-  const AnaVariant &k = kAna[v];
   // 32-bit element offsets of the density in the kernel
   if ((long)a.Mr * a.ldr >= INT_MAX || (long)a.nt * a.ldcs >= INT_MAX) return hipErrorInvalidValue;
   const int rows = 16 * k.ti;
@@ -646,6 +821,18 @@ hipError_t launch_phi_ana_stream(int v, const PhiAnaStreamArgs &a, int cus, hipS
   const dim3 grid(8 * per_xcd), block(64 * k.nw);
   hipLaunchKernelGGL(k.kernel, grid, block, 0, s, a, n_panels, (int)tj, (int)tt);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_phi_ana_stream(int v, const PhiAnaStreamArgs &a, int cus, hipStream_t s) {
+  if (!phi_ana_stream_supports(v, a.h, a.np)) return hipErrorInvalidValue;
+  return launch_ana(kAna[v], a, cus, s);
+}
+
+hipError_t launch_phi_ana_stream32(int v, const PhiAnaStreamArgs &a, int cus, hipStream_t s) {
+  if (!phi_ana_stream32_supports(v, a.h, a.np)) return hipErrorInvalidValue;
+  return launch_ana(kAna32[v], a, cus, s);
 }
 
 int phi_stream32_variant_count() { return (int)(sizeof(kStream32) / sizeof(kStream32[0])); }

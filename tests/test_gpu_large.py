@@ -279,3 +279,19 @@ def test_binary_separable_analysis_stream_variants():
         _say(f"binary separable, phi analysis {g.sep_kernel(0)}: max rel err {err:.3e}")
         assert err <= TOL["fp64"]
     g.set_method("dense")
+
+
+def test_binary_separable_fp32_analysis_stream_variants():
+    """Each FP32 streaming phi-analysis kernel at the binary workload's
+    samples (the FP32 synthesis as the autotuner left it)."""
+    from paper_1806_04593_amd import yyg
+    desc, rho, s, ref, *_ = _binary()
+    g, _ = _binary_grid()
+    g.set_method("separable")
+    for t in range(6, 10):
+        assert yyg.lib().yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 0, t) == 0
+        d_phi = _solve(g, "fp32")
+        err = _max_rel(_at(d_phi, s), ref)
+        _say(f"binary separable fp32, phi analysis {g.sep_lp_kernel('fp32', 0)}: max rel err {err:.3e}")
+        assert err <= 1e-6
+    g.set_method("dense")

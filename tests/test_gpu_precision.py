@@ -108,6 +108,7 @@ def test_workload_errors(name):
 
 N_SEP_LP_TILES = 6
 N_STREAM32 = 5   # FP32 phi synthesis: the FP32 streaming kernels after the tiles
+N_ANA_STREAM32 = 4   # FP32 phi analysis: the FP32 streaming kernels after the tiles
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
@@ -123,7 +124,7 @@ def test_separable_reduced_precision_every_tile(precision):
     g = _grid(desc)
     g.set_method("separable")
     for phase in (0, 4):
-        n = N_SEP_LP_TILES + (N_STREAM32 if precision == "fp32" and phase == 4 else 0)
+        n = N_SEP_LP_TILES + ((N_STREAM32 if phase == 4 else N_ANA_STREAM32) if precision == "fp32" else 0)
         for t in range(n):
             _set_lp_tile(g, precision, phase, t)
             phi = _solve(g, rho, precision)
@@ -153,16 +154,19 @@ def test_separable_reduced_precision_every_tile(precision):
 
 
 def test_separable_stream32_only_for_the_fp32_synthesis():
-    """The FP32 streaming kernels are choices of the FP32 phi synthesis only:
-    the analysis and BF16 x 3 refuse them."""
+    """The FP32 streaming kernels are choices of the FP32 phi transforms
+    only: BF16 x 3 refuses them, and each transform has its own count."""
     from paper_1806_04593_amd import yyg
     desc = W.make_desc("edge", np.geomspace(1.0, 50.0, 38), 9.0, 11, 0.9, 0)
     g = _grid(desc)
     g.set_method("separable")
     L = yyg.lib()
     assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 4, N_SEP_LP_TILES) == 0
-    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 0, N_SEP_LP_TILES) == yyg.ERR_UNSUPPORTED
+    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 0, N_SEP_LP_TILES) == 0
+    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 0,
+                               N_SEP_LP_TILES + N_ANA_STREAM32) == yyg.ERR_UNSUPPORTED
     assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["bf16x3"], 4, N_SEP_LP_TILES) == yyg.ERR_UNSUPPORTED
+    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["bf16x3"], 0, N_SEP_LP_TILES) == yyg.ERR_UNSUPPORTED
     assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 4,
                                N_SEP_LP_TILES + N_STREAM32) == yyg.ERR_INVALID_ARG
 
