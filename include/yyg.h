@@ -329,12 +329,14 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * one block covers both halves of its rows (the analysis reading each
  * density value once, the synthesis its tiles ordered along the cells;
  * mirror-symmetric grids only, else YYG_ERR_UNSUPPORTED).  Last, the phi
- * synthesis takes 7 folded streaming kernels: each block keeps one panel of
+ * synthesis takes 10 folded streaming kernels: each block keeps one panel of
  * the folded basis in LDS for its whole life and its waves sweep row tiles
  * on their own, loading the coefficients straight into 16x16x4 FP64 MFMA
  * operands several steps ahead (persistent grid of one to three blocks per
- * compute unit); the first 6 hold lmax <= 67, the last lmax <= 131
- * (YYG_ERR_UNSUPPORTED beyond, and on grids that are not mirror-symmetric).
+ * compute unit; the last 3 number the row tiles colatitude row fastest, so
+ * that a block's waves write neighbouring rows of the same planes); the
+ * seventh holds lmax <= 131, the others lmax <= 67 (YYG_ERR_UNSUPPORTED
+ * beyond, and on grids that are not mirror-symmetric).
  * The phi analysis likewise ends with 6 streaming kernels (the
  * colatitude-independent folded C/S basis in LDS, the overlap weights
  * applied to the density pairs as they load; folded point counts
@@ -368,13 +370,14 @@ int yyg_sep_lp_kernel(const yyg_grid *g, int precision, int phase, char *name, s
 /* Set the tile of reduced-precision phi transform `phase` (0 or 4) of the
  * separable form for `precision` (YYG_FP32 or YYG_BF16X3) by hand: tile in
  * [0, 6) (64 x 80, 128 x 48, 64 x 64, 64 x 32, 32 x 32, 128 x 80).  In FP32
- * on a mirror-symmetric grid the phi synthesis also takes [6, 11), the
+ * on a mirror-symmetric grid the phi synthesis also takes [6, 13), the
  * streaming kernel of yyg_sep_config's phi synthesis with an FP32 basis
- * panel and FP32 products added to FP64 sums every 16 columns (the first 4
- * for lmax <= 67, the last for lmax <= 131), and the phi analysis [6, 10),
+ * panel and FP32 products added to FP64 sums every 16 columns (tiles 10 and
+ * 12 for lmax <= 131, the others for lmax <= 67; the last two number the
+ * row tiles colatitude row fastest), and the phi analysis [6, 13),
  * the streaming analysis with an FP32 basis panel (a degree up to 64 in one
- * panel of 9 tiles for the first two, so that each density row is read
- * once; FP64 sums every 16 points; h <= 272) — YYG_ERR_UNSUPPORTED beyond
+ * panel of 9 tiles for all but the second and third, so that each density
+ * row is read once; FP64 sums every 16 points; h <= 272) — YYG_ERR_UNSUPPORTED beyond
  * these limits and on other grids.  For tests and expert tuning; yyg_autotune chooses them.
  * Needs the separable form built. */
 int yyg_sep_lp_config(yyg_grid *g, int precision, int phase, int tile);

@@ -30,7 +30,22 @@ typedef double dbl4s __attribute__((ext_vector_type(4)));
 // e and o each gain a 16 x 16 x 4 product per basis tile.
 // The wave's sweep for a panel of TJR basis tiles (TJR <= TJ: the last panel
 // of a row may hold fewer), once its panel is in LDS.
-template <int TI, int TJR, int NW, int P>
+// Row tile tt -> (colatitude row jl, tile rt of 16 TI (patch, shell) rows):
+// CF false numbers the (patch, shell) tiles fastest, CF true the colatitude
+// rows, so that the waves of a block then write neighbouring rows of the
+// same planes (whose shared cache lines meet in L2 before they are evicted).
+template <bool CF>
+__device__ __forceinline__ void tile_split(int tt, int tiles_j, int nt, int &jl, int &rt) {
+  if (CF) {
+    rt = tt / nt;
+    jl = tt - rt * nt;
+  } else {
+    jl = tt / tiles_j;
+    rt = tt - jl * tiles_j;
+  }
+}
+
+template <int TI, int TJR, int NW, int P, bool CF>
 __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, const double *Bs, int ldb, int NQ,
                                                      int KE, int slot0, int groups, int grp, int xcd,
                                                      int tiles_j, int tiles_total) {
@@ -46,7 +61,8 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
   // element offsets stay below 2^31 (checked by the launcher)
   auto rowbase = [&](int tt, int i) -> int {
     tt = min(tt, tiles_total - 1);
-    const int jl = tt / tiles_j, rt = tt - jl * tiles_j;
+    int jl, rt;
+    tile_split<CF>(tt, tiles_j, a.nt, jl, rt);
     return jl * a.Mr + min(rt * 16 * TI + 16 * i + r16, a.Mr - 1);
   };
   const int MJ = (int)a.MJ;
@@ -157,7 +173,8 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
       if (++q == NQ) {
         // tile t done: D layout of the 16x16x4 FP64 MFMA, lane l, element r
         // -> row l / 16 + 4 r, cell l % 16 of the basis tile
-        const int jl = t / tiles_j, rt = t - jl * tiles_j;
+        int jl, rt;
+        tile_split<CF>(t, tiles_j, a.nt, jl, rt);
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -182,9 +199,9 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
   }
 }
 
-template <int TI, int TJ, int NW, int P, int LDB>
-__global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n_panels, int tiles_j,
-                                                          int tiles_total) {
+template <int TI, int TJ, int NW, int P, int LDB, bool CF>
+__device__ __forceinline__ void phi_syn_stream_body(const PhiStreamArgs &a, int n_panels, int tiles_j,
+                                                    int tiles_total) {
   __shared__ double Bs[TJ * 16 * LDB];
   const int NQ = (a.L + 4) / 4;   // steps: cosine columns m = 4q + g (m <= L), sine m = 4q + g + 1
   const int KE = 4 * NQ;          // panel row: cosine part [0, KE), sine part [KE, 2 KE)
@@ -211,10 +228,23 @@ __global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n
   // the last panel of a row runs with the tiles it holds when that is one
   // fewer (the other cases keep the full panel; its surplus tiles are zero)
   if (TJ > 1 && a.h - slot0 <= 16 * (TJ - 1))
-    phi_syn_stream_sweep<TI, (TJ > 1 ? TJ - 1 : 1), NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j,
-                                                           tiles_total);
+    phi_syn_stream_sweep<TI, (TJ > 1 ? TJ - 1 : 1), NW, P, CF>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd,
+                                                               tiles_j, tiles_total);
   else
-    phi_syn_stream_sweep<TI, TJ, NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j, tiles_total);
+    phi_syn_stream_sweep<TI, TJ, NW, P, CF>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j, tiles_total);
+}
+
+template <int TI, int TJ, int NW, int P, int LDB>
+__global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n_panels, int tiles_j,
+                                                          int tiles_total) {
+  phi_syn_stream_body<TI, TJ, NW, P, LDB, false>(a, n_panels, tiles_j, tiles_total);
+}
+
+// the same with the row tiles numbered colatitude row fastest
+template <int TI, int TJ, int NW, int P, int LDB>
+__global__ __launch_bounds__(64 * NW) void phi_syn_stream_cf(PhiStreamArgs a, int n_panels, int tiles_j,
+                                                             int tiles_total) {
+  phi_syn_stream_body<TI, TJ, NW, P, LDB, true>(a, n_panels, tiles_j, tiles_total);
 }
 
 // FP32 form (the separable solve's FP32 precision): the basis panel in LDS
@@ -223,7 +253,7 @@ __global__ __launch_bounds__(64 * NW) void phi_syn_stream(PhiStreamArgs a, int n
 // columns, as the reduced-precision tiles flush every 16-wide stage) and then
 // added to FP64 accumulators.  D layout of the FP32 MFMA: lane l, element r
 // -> row 4 (l / 16) + r, cell l % 16.
-template <int TI, int TJR, int NW, int P>
+template <int TI, int TJR, int NW, int P, bool CF>
 __device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, const float *Bs, int ldb, int NQ,
                                                        int KE, int slot0, int groups, int grp, int xcd,
                                                        int tiles_j, int tiles_total) {
@@ -239,7 +269,8 @@ __device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, c
   if (t >= t_end) return;
   auto rowbase = [&](int tt, int i) -> int {
     tt = min(tt, tiles_total - 1);
-    const int jl = tt / tiles_j, rt = tt - jl * tiles_j;
+    int jl, rt;
+    tile_split<CF>(tt, tiles_j, a.nt, jl, rt);
     return jl * a.Mr + min(rt * 16 * TI + 16 * i + r16, a.Mr - 1);
   };
   const int MJ = (int)a.MJ;
@@ -345,7 +376,8 @@ __device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, c
       ++q;
       if (q % FL == 0 || q == NQ) flush();  // uniform
       if (q == NQ) {
-        const int jl = t / tiles_j, rt = t - jl * tiles_j;
+        int jl, rt;
+        tile_split<CF>(t, tiles_j, a.nt, jl, rt);
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -370,9 +402,9 @@ __device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, c
   }
 }
 
-template <int TI, int TJ, int NW, int P, int LDB>
-__global__ __launch_bounds__(64 * NW) void phi_syn_stream32(PhiStreamArgs a, int n_panels, int tiles_j,
-                                                            int tiles_total) {
+template <int TI, int TJ, int NW, int P, int LDB, bool CF>
+__device__ __forceinline__ void phi_syn_stream32_body(const PhiStreamArgs &a, int n_panels, int tiles_j,
+                                                      int tiles_total) {
   __shared__ float Bs[TJ * 16 * LDB];
   const int NQ = (a.L + 4) / 4;
   const int KE = 4 * NQ;
@@ -395,10 +427,23 @@ __global__ __launch_bounds__(64 * NW) void phi_syn_stream32(PhiStreamArgs a, int
   }
   __syncthreads();
   if (TJ > 1 && a.h - slot0 <= 16 * (TJ - 1))
-    phi_syn_stream32_sweep<TI, (TJ > 1 ? TJ - 1 : 1), NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j,
-                                                             tiles_total);
+    phi_syn_stream32_sweep<TI, (TJ > 1 ? TJ - 1 : 1), NW, P, CF>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd,
+                                                                 tiles_j, tiles_total);
   else
-    phi_syn_stream32_sweep<TI, TJ, NW, P>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j, tiles_total);
+    phi_syn_stream32_sweep<TI, TJ, NW, P, CF>(a, Bs, ldb, NQ, KE, slot0, groups, grp, xcd, tiles_j, tiles_total);
+}
+
+template <int TI, int TJ, int NW, int P, int LDB>
+__global__ __launch_bounds__(64 * NW) void phi_syn_stream32(PhiStreamArgs a, int n_panels, int tiles_j,
+                                                            int tiles_total) {
+  phi_syn_stream32_body<TI, TJ, NW, P, LDB, false>(a, n_panels, tiles_j, tiles_total);
+}
+
+// the same with the row tiles numbered colatitude row fastest
+template <int TI, int TJ, int NW, int P, int LDB>
+__global__ __launch_bounds__(64 * NW) void phi_syn_stream32_cf(PhiStreamArgs a, int n_panels, int tiles_j,
+                                                               int tiles_total) {
+  phi_syn_stream32_body<TI, TJ, NW, P, LDB, true>(a, n_panels, tiles_j, tiles_total);
 }
 
 // Folded phi analysis (Eqs. 14-15 and 21-22 along one colatitude row, the
@@ -607,14 +652,15 @@ __device__ __forceinline__ void phi_ana_stream32_sweep(const PhiAnaStreamArgs &a
   int rbl[TI], wbl = wbase(tl);
 #pragma unroll
   for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+  // without a branch: arithmetic on the ring's values is then not moved
+  // past the loads that refill the ring (which would need other registers)
   auto advance_load = [&]() {
-    if (++sl == NS) {
-      sl = 0;
-      tl += stride;
+    const bool next = ++sl == NS;
+    sl = next ? 0 : sl;
+    tl += next ? stride : 0;
 #pragma unroll
-      for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
-      wbl = wbase(tl);
-    }
+    for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+    wbl = wbase(tl);
   };
   double rf[P][TI][4], rb[P][TI][4], rw[P][4];
   auto load = [&](int p) {
@@ -642,10 +688,13 @@ __device__ __forceinline__ void phi_ana_stream32_sweep(const PhiAnaStreamArgs &a
     rw[p][2] = w1.x;
     rw[p][3] = w1.y;
   };
+  // slots filled in order (the waits in the loop count on slot p's loads
+  // being older than slot p + 1's)
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     load(p);
     advance_load();
+    __builtin_amdgcn_sched_barrier(0);
   }
   const float *bp = &Bs[r16 * ldb + 4 * g];
   int st = 0;
@@ -660,20 +709,40 @@ __device__ __forceinline__ void phi_ana_stream32_sweep(const PhiAnaStreamArgs &a
           ae[i][s4] = (float)(rw[p][s4] * (rf[p][i][s4] + rb[p][i][s4]));
           ao[i][s4] = (float)(rw[p][s4] * (rf[p][i][s4] - rb[p][i][s4]));
         }
+      // the slot's loads after its values are used, into the same
+      // registers: a load hoisted above them would need other registers and
+      // a copy (after a wait for every load in flight) at the loop's end
+      __builtin_amdgcn_sched_barrier(0);
       load(p);
       advance_load();
+      // tiles in groups of G: the group's basis fragments first, then its
+      // TI x G independent product chains interleaved step by step (the
+      // matrix pipe does not wait on one chain), then its FP32 sums added
+      // to the FP64 ones; a small group keeps registers for the ring
+      constexpr int G = TJ < 3 ? TJ : 3;
 #pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-        const f32x4 bf = *reinterpret_cast<const f32x4 *>(bp + 16 * j * ldb + 16 * st);
+      for (int j0 = 0; j0 < TJ; j0 += G) {
+        f32x4 bf[G], f[TI][G];
 #pragma unroll
-        for (int i = 0; i < TI; ++i) {
-          f32x4 f = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int u = 0; u < G; ++u)
+          if (j0 + u < TJ) bf[u] = *reinterpret_cast<const f32x4 *>(bp + 16 * (j0 + u) * ldb + 16 * st);
 #pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4)
-            f = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[s4], isE[j] ? ae[i][s4] : ao[i][s4], f, 0, 0, 0);
+        for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)f[r];
-        }
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+              if (j0 + u < TJ)
+                f[i][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    bf[u][s4], isE[j0 + u] ? ae[i][s4] : ao[i][s4], s4 == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : f[i][u],
+                    0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int u = 0; u < G; ++u)
+            if (j0 + u < TJ)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[i][j0 + u][r] += (double)f[i][u][r];
       }
       if (++st == NS) {
         const int jl = t / tiles_j, rt = t - jl * tiles_j;
@@ -733,12 +802,19 @@ struct StreamVariant {
         "yyg::phi_syn_stream<" #TI ", " #TJ ", " #NW ", " #P ", " #LDB ">"                              \
   }
 
+#define YYG_STREAM_CF(TI, TJ, NW, P, LDB, BPC)                                                          \
+  {                                                                                                     \
+    TI, TJ, NW, P, LDB, BPC, phi_syn_stream_cf<TI, TJ, NW, P, LDB>,                                     \
+        "yyg::phi_syn_stream_cf<" #TI ", " #TJ ", " #NW ", " #P ", " #LDB ">"                           \
+  }
+
 // a variant serves the degrees whose panel rows (8 ceil((L+1)/4) + 2
 // doubles) fit its LDB: L <= 67 at 138, L <= 131 at 266
 const StreamVariant kStream[] = {
     YYG_STREAM(1, 6, 8, 4, 138, 1), YYG_STREAM(1, 4, 8, 8, 138, 1), YYG_STREAM(1, 3, 4, 8, 138, 3),
     YYG_STREAM(1, 6, 8, 8, 138, 1), YYG_STREAM(1, 9, 8, 4, 138, 1), YYG_STREAM(1, 9, 8, 2, 138, 1),
-    YYG_STREAM(1, 3, 8, 4, 266, 1),
+    YYG_STREAM(1, 3, 8, 4, 266, 1), YYG_STREAM_CF(1, 9, 8, 4, 138, 1), YYG_STREAM_CF(1, 6, 8, 4, 138, 1),
+    YYG_STREAM_CF(1, 9, 8, 2, 138, 1),
 };
 
 #define YYG_STREAM32(TI, TJ, NW, P, LDB, BPC)                                                           \
@@ -747,10 +823,17 @@ const StreamVariant kStream[] = {
         "yyg::phi_syn_stream32<" #TI ", " #TJ ", " #NW ", " #P ", " #LDB ">"                            \
   }
 
+#define YYG_STREAM32_CF(TI, TJ, NW, P, LDB, BPC)                                                        \
+  {                                                                                                     \
+    TI, TJ, NW, P, LDB, BPC, phi_syn_stream32_cf<TI, TJ, NW, P, LDB>,                                   \
+        "yyg::phi_syn_stream32_cf<" #TI ", " #TJ ", " #NW ", " #P ", " #LDB ">"                         \
+  }
+
 // FP32 panels: LDB floats per row (L <= 67 at 138, L <= 131 at 266)
 const StreamVariant kStream32[] = {
     YYG_STREAM32(1, 6, 8, 4, 138, 1), YYG_STREAM32(1, 4, 4, 8, 138, 2), YYG_STREAM32(1, 5, 8, 4, 138, 1),
-    YYG_STREAM32(1, 3, 4, 4, 138, 2), YYG_STREAM32(1, 6, 8, 4, 266, 1),
+    YYG_STREAM32(1, 3, 4, 4, 138, 2), YYG_STREAM32(1, 6, 8, 4, 266, 1), YYG_STREAM32_CF(1, 6, 8, 4, 138, 1),
+    YYG_STREAM32_CF(1, 6, 8, 4, 266, 1),
 };
 
 struct AnaVariant {
@@ -779,8 +862,9 @@ const AnaVariant kAna[] = {
 
 // FP32 panels: 9 tiles (lmax <= 64 in one panel) x 276 floats (h <= 272)
 const AnaVariant kAna32[] = {
-    YYG_ANA_STREAM32(1, 9, 8, 1, 276, 1), YYG_ANA_STREAM32(1, 9, 8, 2, 276, 1), YYG_ANA_STREAM32(1, 5, 8, 2, 276, 1),
-    YYG_ANA_STREAM32(1, 5, 8, 1, 276, 1),
+    YYG_ANA_STREAM32(1, 9, 8, 1, 276, 1), YYG_ANA_STREAM32(1, 5, 8, 2, 276, 1), YYG_ANA_STREAM32(1, 5, 8, 1, 276, 1),
+    YYG_ANA_STREAM32(1, 9, 4, 4, 276, 1), YYG_ANA_STREAM32(1, 9, 4, 3, 276, 1), YYG_ANA_STREAM32(1, 9, 4, 2, 276, 1),
+    YYG_ANA_STREAM32(1, 9, 8, 2, 276, 1),
 };
 
 }  // namespace

@@ -26,6 +26,9 @@ def main():
     ap.add_argument("--sep-variants", default=None,
                     help="comma-separated variants of the five separable phases (as yyg_sep_config), "
                          "instead of the autotuner's choice, to profile the kernels a bench run chose")
+    ap.add_argument("--sep-lp-tiles", default=None,
+                    help="analysis,synthesis tiles of the reduced-precision phi transforms (as yyg_sep_lp_config) "
+                         "for --precision fp32 / bf16x3 with the separable method")
     ap.add_argument("--dense-config", default=None,
                     help="var_ana,split_ana,var_syn of the dense plan (as yyg_plan_config) instead of the "
                          "autotuner's choice")
@@ -59,6 +62,11 @@ def main():
         g.set_config(va, sp, vs, a.precision)
     else:
         g.autotune(a.precision)
+    if a.sep_lp_tiles and a.method == "separable" and a.precision in yyg.PRECISIONS and a.precision != "fp64":
+        for phase, t in zip((0, 4), (int(x) for x in a.sep_lp_tiles.split(","))):
+            st = yyg.lib().yyg_sep_lp_config(g.handle, yyg.PRECISIONS[a.precision], phase, t)
+            if st != 0:
+                raise SystemExit(f"yyg_sep_lp_config({a.precision}, {phase}, {t}) returned {st}")
     d_rho = torch.from_numpy(rho).to("cuda:0")
     d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
     g.upload_rho(d_rho)
@@ -67,6 +75,8 @@ def main():
         g.solve(d_phi, a.precision)
     torch.cuda.synchronize()
     launch = ([g.sep_kernel(p) for p in range(5)] if a.method == "separable" else g.plan_info(a.precision))
+    if a.method == "separable" and a.precision != "fp64":
+        launch += [g.sep_lp_kernel(a.precision, 0), g.sep_lp_kernel(a.precision, 4)]
     print(f"[prof] {a.solves} solves of {a.workload} ({a.precision}, {a.method}) in {time.perf_counter() - t0:.3f} s; "
           f"launch {launch}", flush=True)
     sys.stdout.flush()

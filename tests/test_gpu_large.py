@@ -224,8 +224,7 @@ def test_binary_separable_reduced_precision(precision):
     g.set_method("dense")
 
 
-N_STREAM = 7          # streaming phi-synthesis variants, last in the phase's range
-N_STREAM_BINARY = 6   # of which the first six hold lmax 64
+N_STREAM = 10         # streaming phi-synthesis variants, last in the phase's range (all hold lmax 64)
 
 
 def test_binary_separable_stream_variants():
@@ -235,13 +234,16 @@ def test_binary_separable_stream_variants():
     g, _ = _binary_grid()
     g.set_method("separable")
     n = g.sep_variant_count(4)
-    for v in range(n - N_STREAM, n - N_STREAM + N_STREAM_BINARY):
+    for v in range(n - N_STREAM, n):
         g.sep_config(4, v)
         d_phi = _solve(g)
         err = _max_rel(_at(d_phi, s), ref)
         _say(f"binary separable, phi synthesis {g.sep_kernel(4)}: max rel err {err:.3e}")
         assert err <= TOL["fp64"]
     g.set_method("dense")
+
+
+N_STREAM32_L64 = 7   # FP32 streaming phi-synthesis kernels (tiles 6 onwards), all holding lmax 64
 
 
 def test_binary_separable_fp32_stream_variants():
@@ -252,7 +254,7 @@ def test_binary_separable_fp32_stream_variants():
     desc, rho, s, ref, *_ = _binary()
     g, _ = _binary_grid()
     g.set_method("separable")
-    for t in range(6, 10):
+    for t in range(6, 6 + N_STREAM32_L64):
         assert yyg.lib().yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 4, t) == 0
         d_phi = _solve(g, "fp32")
         err = _max_rel(_at(d_phi, s), ref)
@@ -281,6 +283,9 @@ def test_binary_separable_analysis_stream_variants():
     g.set_method("dense")
 
 
+N_ANA_STREAM32 = 7   # FP32 streaming phi-analysis kernels (tiles 6 onwards of the FP32 analysis)
+
+
 def test_binary_separable_fp32_analysis_stream_variants():
     """Each FP32 streaming phi-analysis kernel at the binary workload's
     samples (the FP32 synthesis as the autotuner left it)."""
@@ -288,7 +293,7 @@ def test_binary_separable_fp32_analysis_stream_variants():
     desc, rho, s, ref, *_ = _binary()
     g, _ = _binary_grid()
     g.set_method("separable")
-    for t in range(6, 10):
+    for t in range(6, 6 + N_ANA_STREAM32):
         assert yyg.lib().yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 0, t) == 0
         d_phi = _solve(g, "fp32")
         err = _max_rel(_at(d_phi, s), ref)

@@ -123,8 +123,8 @@ N_PHI_FOLD = 8
 N_PHI_LEAN = 4   # phi synthesis only
 N_X4 = 12        # tiles on the 4x4x4 FP64 MFMA, every phase (last in each phase's range)
 N_BOTH = {0: 8, 4: 6}   # then the folded phi transforms with both halves per block
-N_STREAM = 7     # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
-N_STREAM_SMALL_L = 6   # of which the first six hold panels up to lmax 67, the last up to 131
+N_STREAM = 10    # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
+N_STREAM_WIDE = (6,)   # of which these hold panels up to lmax 131, the others up to 67
 N_ANA_STREAM = 6   # phi analysis: then the streaming kernels (colatitude-independent basis in LDS)
 
 
@@ -448,15 +448,18 @@ def test_phi_stream_variants_at_high_degree():
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
     base = _x4_base(4) + _n_x4(4)
-    for v in range(base, base + N_STREAM_SMALL_L):
+    for u in range(N_STREAM):
+        if u in N_STREAM_WIDE:
+            continue
         with pytest.raises(yyg.YygError) as ei:
-            g.sep_config(4, v)
+            g.sep_config(4, base + u)
         assert ei.value.status == yyg.ERR_UNSUPPORTED
-    g.sep_config(4, base + N_STREAM - 1)
-    _say(f"phi stream at lmax 80: {g.sep_kernel(4)}")
-    _, phi = _gpu_solve(desc, rho, grid=g)
-    err = _max_rel(phi, ref)
-    assert err <= TOL_FP64, err
+    for u in N_STREAM_WIDE:
+        g.sep_config(4, base + u)
+        _say(f"phi stream at lmax 80: {g.sep_kernel(4)}")
+        _, phi = _gpu_solve(desc, rho, grid=g)
+        err = _max_rel(phi, ref)
+        assert err <= TOL_FP64, err
 
 
 def test_separable_phase_alone():

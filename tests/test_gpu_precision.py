@@ -107,8 +107,8 @@ def test_workload_errors(name):
 # ---------------------------------------------------------------------------
 
 N_SEP_LP_TILES = 6
-N_STREAM32 = 5   # FP32 phi synthesis: the FP32 streaming kernels after the tiles
-N_ANA_STREAM32 = 4   # FP32 phi analysis: the FP32 streaming kernels after the tiles
+N_STREAM32 = 7   # FP32 phi synthesis: the FP32 streaming kernels after the tiles
+N_ANA_STREAM32 = 7   # FP32 phi analysis: the FP32 streaming kernels after the tiles
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
@@ -163,12 +163,16 @@ def test_separable_stream32_only_for_the_fp32_synthesis():
     L = yyg.lib()
     assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 4, N_SEP_LP_TILES) == 0
     assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 0, N_SEP_LP_TILES) == 0
-    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 0,
-                               N_SEP_LP_TILES + N_ANA_STREAM32) == yyg.ERR_UNSUPPORTED
     assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["bf16x3"], 4, N_SEP_LP_TILES) == yyg.ERR_UNSUPPORTED
     assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["bf16x3"], 0, N_SEP_LP_TILES) == yyg.ERR_UNSUPPORTED
-    assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], 4,
-                               N_SEP_LP_TILES + N_STREAM32) == yyg.ERR_INVALID_ARG
+    # past a transform's own kernels: refused, and past every tile index a
+    # precision has, an invalid argument
+    n_max = N_SEP_LP_TILES + max(N_STREAM32, N_ANA_STREAM32)
+    for phase, n in ((4, N_STREAM32), (0, N_ANA_STREAM32)):
+        assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, N_SEP_LP_TILES + n - 1) == 0
+        for t in range(N_SEP_LP_TILES + n, n_max):
+            assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, t) == yyg.ERR_UNSUPPORTED
+        assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, n_max) == yyg.ERR_INVALID_ARG
 
 
 def _set_lp_tile(g, precision, phase, t):
