@@ -337,10 +337,10 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * that a block's waves write neighbouring rows of the same planes); the
  * seventh holds lmax <= 131, the others lmax <= 67 (YYG_ERR_UNSUPPORTED
  * beyond, and on grids that are not mirror-symmetric).
- * The phi analysis likewise ends with 6 streaming kernels (the
+ * The phi analysis likewise ends with 8 streaming kernels (the
  * colatitude-independent folded C/S basis in LDS, the overlap weights
  * applied to the density pairs as they load; folded point counts
- * h <= 272 for the first 5, h <= 416 for the last).
+ * h <= 416 for the sixth, h <= 272 for the others).
  * yyg_sep_variant_count gives the length of each phase's range.
  * Needs the separable form built (yyg_set_method); synchronises the
  * device.  For tests and expert tuning; yyg_autotune chooses all of them. */

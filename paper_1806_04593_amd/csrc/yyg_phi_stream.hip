@@ -490,14 +490,15 @@ __device__ __forceinline__ void phi_ana_stream_sweep(const PhiAnaStreamArgs &a, 
   int rbl[TI], wbl = wbase(tl);
 #pragma unroll
   for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+  // without a branch: arithmetic on the ring's values is then not moved
+  // past the loads that refill the ring (which would need other registers)
   auto advance_load = [&]() {
-    if (++sl == NS) {
-      sl = 0;
-      tl += stride;
+    const bool next = ++sl == NS;
+    sl = next ? 0 : sl;
+    tl += next ? stride : 0;
 #pragma unroll
-      for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
-      wbl = wbase(tl);
-    }
+    for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+    wbl = wbase(tl);
   };
   // stage registers: front and mirror runs of each row tile, the weights
   double rf[P][TI][4], rb[P][TI][4], rw[P][4];
@@ -527,10 +528,13 @@ __device__ __forceinline__ void phi_ana_stream_sweep(const PhiAnaStreamArgs &a, 
     rw[p][2] = w1.x;
     rw[p][3] = w1.y;
   };
+  // slots filled in order (the waits in the loop count on slot p's loads
+  // being older than slot p + 1's)
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     load(p);
     advance_load();
+    __builtin_amdgcn_sched_barrier(0);
   }
   // lane (g, r16) reads output r16 of each tile at points 16 s + 4 g .. + 3
   const double *bp = &Bs[r16 * ldb + 4 * g];
@@ -556,6 +560,8 @@ __device__ __forceinline__ void phi_ana_stream_sweep(const PhiAnaStreamArgs &a, 
           ae[i][s4] = rw[p][s4] * (rf[p][i][s4] + rb[p][i][s4]);
           ao[i][s4] = rw[p][s4] * (rf[p][i][s4] - rb[p][i][s4]);
         }
+      // the slot's loads after its values are used, into the same registers
+      __builtin_amdgcn_sched_barrier(0);
       load(p);
       advance_load();
 #pragma unroll
@@ -852,6 +858,7 @@ struct AnaVariant {
 const AnaVariant kAna[] = {
     YYG_ANA_STREAM(2, 3, 8, 2, 276, 1), YYG_ANA_STREAM(1, 3, 8, 2, 276, 1), YYG_ANA_STREAM(1, 3, 8, 4, 276, 1),
     YYG_ANA_STREAM(2, 2, 8, 2, 276, 1), YYG_ANA_STREAM(2, 3, 4, 2, 276, 1), YYG_ANA_STREAM(1, 2, 4, 4, 420, 1),
+    YYG_ANA_STREAM(1, 3, 8, 6, 276, 1), YYG_ANA_STREAM(2, 2, 8, 3, 276, 1),
 };
 
 #define YYG_ANA_STREAM32(TI, TJ, NW, P, LDB, BPC)                                                       \

@@ -263,7 +263,7 @@ def test_binary_separable_fp32_stream_variants():
     g.set_method("dense")
 
 
-N_ANA_STREAM = 6   # streaming phi-analysis variants, last in the phase's range (all hold h = 271)
+N_ANA_STREAM = 8   # streaming phi-analysis variants, last in the phase's range (all hold h = 271)
 
 
 def test_binary_separable_analysis_stream_variants():

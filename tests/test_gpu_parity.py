@@ -125,7 +125,7 @@ N_X4 = 12        # tiles on the 4x4x4 FP64 MFMA, every phase (last in each phase
 N_BOTH = {0: 8, 4: 6}   # then the folded phi transforms with both halves per block
 N_STREAM = 10    # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
 N_STREAM_WIDE = (6,)   # of which these hold panels up to lmax 131, the others up to 67
-N_ANA_STREAM = 6   # phi analysis: then the streaming kernels (colatitude-independent basis in LDS)
+N_ANA_STREAM = 8   # phi analysis: then the streaming kernels (colatitude-independent basis in LDS)
 
 
 def _n_x4(phase):
