@@ -337,10 +337,17 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * that a block's waves write neighbouring rows of the same planes); the
  * seventh holds lmax <= 131, the others lmax <= 67 (YYG_ERR_UNSUPPORTED
  * beyond, and on grids that are not mirror-symmetric).
- * The phi analysis likewise ends with 8 streaming kernels (the
+ * The phi analysis likewise takes 8 streaming kernels (the
  * colatitude-independent folded C/S basis in LDS, the overlap weights
  * applied to the density pairs as they load; folded point counts
- * h <= 416 for the sixth, h <= 272 for the others).
+ * h <= 416 for the sixth, h <= 272 for the others), and last 8 folded
+ * tiles (64 x 64 with 4 x 1 and 2 x 2 waves, 64 x 32, 128 x 64, the two
+ * 64 x 64 with three stages of loads in flight, 128 x 64 with 2 x 2 waves,
+ * 64 x 64 with 4 x 2 waves) that sum the last output column on
+ * the vector units when it falls just past their MFMA tiles (lmax a
+ * multiple of the tile width: cos lmax, the 65th column of the even half
+ * at lmax 64, then costs no MFMA tile of its own; mirror-symmetric grids
+ * only).
  * yyg_sep_variant_count gives the length of each phase's range.
  * Needs the separable form built (yyg_set_method); synchronises the
  * device.  For tests and expert tuning; yyg_autotune chooses all of them. */

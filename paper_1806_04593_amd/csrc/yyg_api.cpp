@@ -379,7 +379,11 @@ int sep_stream_count(int r) {
   return r == 0 ? yyg::phi_ana_stream_variant_count() : r == 4 ? yyg::phi_stream_variant_count() : 0;
 }
 
-int sep_variant_count(int r) { return sep_stream_base(r) + sep_stream_count(r); }
+// The phi analysis last takes yyg::fold_xcol_variant_count() folded tiles
+// whose last output column is summed on the vector units (folded grids only).
+int sep_xcol_base(int r) { return sep_stream_base(r) + sep_stream_count(r); }
+
+int sep_variant_count(int r) { return sep_xcol_base(r) + (r == 0 ? yyg::fold_xcol_variant_count() : 0); }
 
 bool sep_fold_variant(int r, int v) {
   if ((r == 0 || r == 4) && v >= sep_stream_base(r)) return true;
@@ -392,6 +396,7 @@ bool sep_variant_available(const yyg_grid *g, int r, int v) {
   if (r < 0 || r > 4 || v < 0 || v >= sep_variant_count(r)) return false;
   if (sep_fold_variant(r, v) && !g->sep.fold) return false;
   if (r == 4 && v >= sep_stream_base(4)) return yyg::phi_stream_supports(v - sep_stream_base(4), g->L);
+  if (r == 0 && v >= sep_xcol_base(0)) return true;
   if (r == 0 && v >= sep_stream_base(0))
     return yyg::phi_ana_stream_supports(v - sep_stream_base(0), (int)g->sep.h, g->n_p);
   return true;
@@ -410,6 +415,7 @@ hipError_t sep_launch_phase(yyg_grid *g, int r, hipStream_t s) {
   const int nf = yyg::phi_fold_variant_count();
   if (r == 4 && S.var[r] >= sep_stream_base(4))
     return yyg::launch_phi_syn_stream(S.var[r] - sep_stream_base(4), S.phi_syn_s, g->cus, s);
+  if (r == 0 && S.var[r] >= sep_xcol_base(0)) return yyg::launch_fold_xcol(S.var[r] - sep_xcol_base(0), S.phi_ana_f, s);
   if (r == 0 && S.var[r] >= sep_stream_base(0))
     return yyg::launch_phi_ana_stream(S.var[r] - sep_stream_base(0), S.phi_ana_s, g->cus, s);
   if (S.var[r] >= sep_x4_base(r)) {
@@ -2104,6 +2110,7 @@ int yyg_sep_kernel(const yyg_grid *g, int phase, char *name, size_t n) {
   }
   const int v = g->sep.var[phase], x0 = sep_x4_base(phase);
   const int r = phase == 4 && v >= sep_stream_base(4) ? yyg::phi_stream_kernel_name(v - sep_stream_base(4), name, n)
+                : phase == 0 && v >= sep_xcol_base(0) ? yyg::fold_xcol_kernel_name(v - sep_xcol_base(0), name, n)
                 : phase == 0 && v >= sep_stream_base(0)
                     ? yyg::phi_ana_stream_kernel_name(v - sep_stream_base(0), name, n)
                 : v >= x0 ? yyg::x4_kernel_name(v - x0, phase, g->sep.fold, name, n)

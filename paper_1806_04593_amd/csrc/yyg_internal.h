@@ -88,7 +88,11 @@ enum {
   kGemmFoldAB = 4096,
   kGemmNFast = 8192,
   kGemmLpF32 = 16384,
-  kGemmLpBF3 = 32768
+  kGemmLpBF3 = 32768,
+  // FOLDA: the column n0 + BN, when it is the last (N - 1), summed on the
+  // vector units from the stage already in LDS, so that an N of one past a
+  // multiple of BN needs no further MFMA tile
+  kGemmXCol = 65536
 };
 // role offset of the kGemmDeep forms of the batched roles
 constexpr int kRoleDeep = 16;
@@ -170,6 +174,11 @@ hipError_t launch_gemm_f64_sep(int variant, int phase, bool deep, const SepPhase
 // role 2 = role 0 with kGemmFoldA, role 3 = role 1 with kGemmFoldC; roles
 // + kRoleDeep: the same with kGemmDeep.
 hipError_t launch_gemm_f64_batched(int variant, int role, const GemmF64Args &g, hipStream_t s);
+// folded phi analysis tiles with the last output column summed on the vector
+// units (kGemmXCol); g as for role 2 of launch_gemm_f64_batched
+int fold_xcol_variant_count();
+hipError_t launch_fold_xcol(int v, const GemmF64Args &g, hipStream_t s);
+int fold_xcol_kernel_name(int v, char *buf, size_t n);
 
 // FP64 NT GEMM C = A . B^T in one of several tile shapes ("variants");
 // role 0 = analysis, 1 = synthesis (separate kernel symbols).

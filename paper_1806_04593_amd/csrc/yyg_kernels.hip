@@ -1108,6 +1108,59 @@ hipError_t launch_radial_scan_q_grouped(const ScanQArgs *args, const int2 *items
   return hipErrorInvalidValue;
 }
 
+namespace {
+
+// Folded phi analysis with the last output column on the vector units
+// (kGemmXCol): N - 1 columns in MFMA tiles of BN, the column N - 1 beside
+// them when N - 1 is a multiple of BN (L + 1 = 65 outputs per half in
+// 64-wide tiles, where an MFMA tile for the one column would double the work).
+template <int BM, int BN, int WGM, int WGN, bool DEEP>
+hipError_t launch_fold_xcol_t(const GemmF64Args &a, hipStream_t s) {
+  GemmF64Args g = a;
+  g.tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = std::max(1, (g.N - 1 + BN - 1) / BN);
+  const long per = (long)g.tiles_m * tiles_n, total = per * g.batch;
+  if (total > INT_MAX || g.batch % 2) return hipErrorInvalidValue;
+  constexpr int MODE = kGemmCTrans | kGemmDT | kGemmFoldA | kGemmXCol | (DEEP ? kGemmDeep : 0);
+  hipLaunchKernelGGL((gemm_nt_f64_batched<0, BM, BN, WGM, WGN, MODE>), dim3((unsigned)total), dim3(64 * WGM * WGN), 0,
+                     s, g, (int)per, (int)total);
+  return hipGetLastError();
+}
+
+struct XColVariant {
+  int bm, bn, wm, wn, deep;
+  hipError_t (*fn)(const GemmF64Args &, hipStream_t);
+};
+
+#define YYG_XCOL(BM, BN, WM, WN, D) \
+  { BM, BN, WM, WN, D, launch_fold_xcol_t<BM, BN, WM, WN, D> }
+
+const XColVariant kXCol[] = {
+    YYG_XCOL(64, 64, 4, 1, false), YYG_XCOL(64, 64, 2, 2, false), YYG_XCOL(64, 32, 4, 1, false),
+    YYG_XCOL(128, 64, 4, 1, false), YYG_XCOL(64, 64, 4, 1, true), YYG_XCOL(64, 64, 2, 2, true),
+    YYG_XCOL(128, 64, 2, 2, false), YYG_XCOL(64, 64, 4, 2, false),
+};
+
+#undef YYG_XCOL
+
+}  // namespace
+
+int fold_xcol_variant_count() { return (int)(sizeof(kXCol) / sizeof(kXCol[0])); }
+
+hipError_t launch_fold_xcol(int v, const GemmF64Args &g, hipStream_t s) {
+  if (v < 0 || v >= fold_xcol_variant_count()) return hipErrorInvalidValue;
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  return kXCol[v].fn(g, s);
+}
+
+int fold_xcol_kernel_name(int v, char *buf, size_t n) {
+  if (v < 0 || v >= fold_xcol_variant_count()) return -1;
+  const XColVariant &x = kXCol[v];
+  const int mode = kGemmCTrans | kGemmDT | kGemmFoldA | kGemmXCol | (x.deep ? kGemmDeep : 0);
+  return snprintf(buf, n, "yyg::gemm_nt_f64_batched<0, %d, %d, %d, %d, %d>", x.bm, x.bn, x.wm, x.wn, mode) < 0 ? -1
+                                                                                                               : 0;
+}
+
 int sep_kernel_name(int phase, int v, bool fold, char *buf, size_t n) {
   const int nv = gemm_f64_variant_count(), nd = phi_direct_variant_count(), nf = phi_fold_variant_count();
   const int nl = phase == 4 ? phi_lean_variant_count() : 0;

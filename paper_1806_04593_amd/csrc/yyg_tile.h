@@ -67,6 +67,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   constexpr bool LPF32 = (MODE & kGemmLpF32) != 0;
   constexpr bool LPBF3 = (MODE & kGemmLpBF3) != 0;
   constexpr bool LP = LPF32 || LPBF3;
+  constexpr bool XCOL = (MODE & kGemmXCol) != 0;
   static_assert(!ACCINIT || GEN, "the initial accumulator is addressed like C");
   static_assert(!LP || (!X4 && !FOLDAB && !ACCINIT && !(LPF32 && LPBF3)), "reduced precision: the 16x16 phi forms");
   static_assert(!DT || !FOLDC, "the folded synthesis stores rows");
@@ -87,6 +88,8 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   const long lda = g.lda, ldb = g.ldb, ldc = g.ldc;
   constexpr int NT = 64 * WGM * WGN;
   constexpr int TI = BM / WGM / 16, TJ = BN / WGN / 16;
+  static_assert(!XCOL || (FOLDA && !X4 && !LP && NT % BM == 0 && kBK % (NT / BM) == 0),
+                "extra column: folded analysis FP64 16x16 tiles, whole threads per row");
   static_assert(TI >= 1 && TJ >= 1 && TI * 16 * WGM == BM && TJ * 16 * WGN == BN, "tile/wave mismatch");
   // X4 (v_mfma_f64_4x4x4f64): the wave tile as R4 four-wide by S16
   // sixteen-wide products; the four-wide side is M (N with DT).
@@ -149,6 +152,17 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   C += (long)zj * g.c_split_stride;
 
   const int wm = wave % WGM, wn = wave / WGM;
+
+  // XCOL: output column nx = n0 + BN (active when it is N - 1, uniform over
+  // the block): XTPR threads per row of the tile each sum XSPT of a stage's
+  // 16 contraction points, from A's stage in LDS and the column's basis
+  // values staged beside it
+  constexpr int XTPR = XCOL ? NT / BM : 1, XSPT = kBK / XTPR;
+  __shared__ double Bx[XCOL ? 2 : 1][XCOL ? kBK : 1];
+  const int nx = n0 + BN;
+  const bool xon = XCOL && nx == N - 1;
+  const int xr = tid / XTPR, xq = tid % XTPR;
+  double xacc = 0.0;
 
   // FOLDC: acc sums the stages below k_split (the even part), acc2 the rest
   // (acc4 / acc4b in the X4 form: one value per lane and product)
@@ -214,7 +228,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   // FOLDA keeps the raw front and mirror values (ra[i], ra[EA + i]) until
   // the stash: folding them at load time would wait for the loads there
   constexpr int EAR = FLD ? 2 * EA : EA;
-  double ra[PF][EAR], rb[PF][EB];
+  double ra[PF][EAR], rb[PF][EB], rx[PF];
   // run mapping: this thread's row and first column
   const int arow = RUN_A ? tid / (kBK / EA) : 0, acol = RUN_A ? (tid % (kBK / EA)) * EA : 0;
   const int brow = RUN_B ? tid / (kBK / EB) : 0, bcol = RUN_B ? (tid % (kBK / EB)) * EB : 0;
@@ -332,6 +346,27 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
       for (int i = 0; i < EB; ++i) {
         const int e = tid + i * NT, row = e / kBK, kk = k0 + e % kBK;
         if (e < BN * kBK) putB(buf, row, e % kBK, (n0 + row < N && kk < kend) ? rb[i] : 0.0);
+      }
+    }
+  };
+
+  // XCOL: every thread loads (a clamped, valid address); the first kBK
+  // store the stage's basis values of column nx
+  auto xload = [&](double &x, int k0) {
+    if constexpr (XCOL) x = B[(long)min(nx, N - 1) * ldb + min(k0 + (tid & (kBK - 1)), K - 1)];
+  };
+  auto xstash = [&](double x, int buf, int k0) {
+    if constexpr (XCOL) {
+      if (tid < kBK) Bx[XCOL ? buf : 0][tid] = (xon && k0 + tid < kend) ? x : 0.0;
+    }
+  };
+  auto xcompute = [&](int buf) {
+    if constexpr (XCOL) {
+      if (xon) {  // uniform
+        const double *ap = &As[buf][xr * kLDK + xq * XSPT];
+        const double *bx = &Bx[XCOL ? buf : 0][xq * XSPT];
+#pragma unroll
+        for (int s = 0; s < XSPT; ++s) xacc = __builtin_fma(ap[s], bx[s], xacc);
       }
     }
   };
@@ -500,8 +535,14 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   const int nk = (kend - kbeg + kBK - 1) / kBK;
 #pragma unroll
   for (int p = 0; p < PF; ++p)
-    if (p < nk) load(ra[p], rb[p], kbeg + p * kBK);
-  if (nk > 0) stash(ra[0], rb[0], 0, kbeg);
+    if (p < nk) {
+      load(ra[p], rb[p], kbeg + p * kBK);
+      xload(rx[p], kbeg + p * kBK);
+    }
+  if (nk > 0) {
+    stash(ra[0], rb[0], 0, kbeg);
+    xstash(rx[0], 0, kbeg);
+  }
   __syncthreads();
 
   // Stage `it` sits in LDS buffer it & 1 and register slot it % PF; the
@@ -513,9 +554,16 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
       const int it = base + sl;
       if (it < nk) {  // uniform across the block
         const int buf = it & 1;
-        if (it + PF < nk) load(ra[sl], rb[sl], kbeg + (it + PF) * kBK);
+        if (it + PF < nk) {
+          load(ra[sl], rb[sl], kbeg + (it + PF) * kBK);
+          xload(rx[sl], kbeg + (it + PF) * kBK);
+        }
         compute(buf, FOLDC && kbeg + it * kBK >= g.k_split);
-        if (it + 1 < nk) stash(ra[(sl + 1) % PF], rb[(sl + 1) % PF], buf ^ 1, kbeg + (it + 1) * kBK);
+        xcompute(buf);
+        if (it + 1 < nk) {
+          stash(ra[(sl + 1) % PF], rb[(sl + 1) % PF], buf ^ 1, kbeg + (it + 1) * kBK);
+          xstash(rx[(sl + 1) % PF], buf ^ 1, kbeg + (it + 1) * kBK);
+        }
         __syncthreads();
       }
     }
@@ -548,6 +596,13 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
       }
     }
   };
+  if constexpr (XCOL) {
+    if (xon) {  // uniform: the row's partial sums meet in its first thread
+#pragma unroll
+      for (int o = 1; o < XTPR; o <<= 1) xacc += __shfl_xor(xacc, o);
+      if (xq == 0) emit(m0 + xr, nx, xacc, 0.0);
+    }
+  }
   if constexpr (X4) {
 #pragma unroll
     for (int r = 0; r < R4; ++r)

@@ -263,7 +263,8 @@ def test_binary_separable_fp32_stream_variants():
     g.set_method("dense")
 
 
-N_ANA_STREAM = 8   # streaming phi-analysis variants, last in the phase's range (all hold h = 271)
+N_ANA_STREAM = 8   # streaming phi-analysis variants (all hold h = 271), before the N_XCOL last ones
+N_XCOL = 8         # folded analysis tiles with the last output column on the vector units, last in the range
 
 
 def test_binary_separable_analysis_stream_variants():
@@ -273,8 +274,25 @@ def test_binary_separable_analysis_stream_variants():
     desc, rho, s, ref, AC, AS = _binary()
     g, _ = _binary_grid()
     g.set_method("separable")
-    n = g.sep_variant_count(0)
+    n = g.sep_variant_count(0) - N_XCOL
     for v in range(n - N_ANA_STREAM, n):
+        g.sep_config(0, v)
+        d_phi = _solve(g)
+        err = _max_rel(_at(d_phi, s), ref)
+        _say(f"binary separable, phi analysis {g.sep_kernel(0)}: max rel err {err:.3e}")
+        assert err <= TOL["fp64"]
+    g.set_method("dense")
+
+
+def test_binary_separable_analysis_extra_column_tiles():
+    """Each folded phi-analysis tile whose last output column (cos 64, the
+    65th of the even half) is summed on the vector units, at the binary
+    workload's samples."""
+    desc, rho, s, ref, AC, AS = _binary()
+    g, _ = _binary_grid()
+    g.set_method("separable")
+    n = g.sep_variant_count(0)
+    for v in range(n - N_XCOL, n):
         g.sep_config(0, v)
         d_phi = _solve(g)
         err = _max_rel(_at(d_phi, s), ref)

@@ -126,6 +126,7 @@ N_BOTH = {0: 8, 4: 6}   # then the folded phi transforms with both halves per bl
 N_STREAM = 10    # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
 N_STREAM_WIDE = (6,)   # of which these hold panels up to lmax 131, the others up to 67
 N_ANA_STREAM = 8   # phi analysis: then the streaming kernels (colatitude-independent basis in LDS)
+N_XCOL = 8         # and last the folded tiles with their last output column on the vector units
 
 
 def _n_x4(phase):
@@ -401,7 +402,7 @@ def test_separable_every_phase_variant(phase):
     # every tile with one and with three stages of loads in flight; the phi
     # phases also every LDS-basis variant, unfolded and folded; every phase
     # the 4x4x4-MFMA tiles
-    n_stream = N_STREAM if phase == 4 else N_ANA_STREAM if phase == 0 else 0
+    n_stream = N_STREAM if phase == 4 else N_ANA_STREAM + N_XCOL if phase == 0 else 0
     assert g.sep_variant_count(phase) == _x4_base(phase) + _n_x4(phase) + n_stream
     for v in range(_x4_base(phase) + _n_x4(phase) + n_stream):
         g.sep_config(phase, v)
@@ -423,7 +424,7 @@ def test_phi_stream_variants_odd_row_length():
     ref = O.solve(*_oracle_args(desc), rho)
     g = yyg.Grid(desc, 0)
     g.set_method("separable")
-    for phase, n in ((4, N_STREAM), (0, N_ANA_STREAM)):
+    for phase, n in ((4, N_STREAM), (0, N_ANA_STREAM + N_XCOL)):
         total = g.sep_variant_count(phase)
         for v in range(total - n, total):
             g.sep_config(phase, v)
@@ -432,6 +433,32 @@ def test_phi_stream_variants_odd_row_length():
             _say(f"odd n_phi {desc['n_phi']}: {g.sep_kernel(phase)} {err:.2e}")
             assert err <= TOL_FP64, (phase, v, err)
         g.sep_config(phase, 10)
+
+
+@pytest.mark.parametrize("case", [
+    dict(name="lmax64", res=5.0, lmax=64, nr=5),
+    dict(name="lmax32_odd", res=7.0, lmax=32, nr=6),
+])
+def test_phi_analysis_extra_column_tiles(case):
+    """The folded phi-analysis tiles whose last output column is summed on
+    the vector units, at degrees where that column is active (lmax 64: L + 1
+    = 65 columns in 64-wide tiles, and in 32-wide ones on their second
+    tile; lmax 32 on a grid with an odd number of cells per row, 41),
+    every variant against the oracle."""
+    yyg = _yyg()
+    desc = W.make_desc("edge", np.geomspace(1.0, 9.0, case["nr"] + 1), case["res"], case["lmax"], 0.9, 0)
+    rng = np.random.default_rng(53)
+    rho = rng.uniform(0.1, 1.0, (2, case["nr"], desc["n_theta"], desc["n_phi"]))
+    ref = O.solve(*_oracle_args(desc), rho)
+    g = yyg.Grid(desc, 0)
+    g.set_method("separable")
+    total = g.sep_variant_count(0)
+    for v in range(total - N_XCOL, total):
+        g.sep_config(0, v)
+        _, phi = _gpu_solve(desc, rho, grid=g)
+        err = _max_rel(phi, ref)
+        _say(f"{case['name']} n_phi {desc['n_phi']}: {g.sep_kernel(0)} {err:.2e}")
+        assert err <= TOL_FP64, (v, err)
 
 
 def test_phi_stream_variants_at_high_degree():
