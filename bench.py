@@ -30,8 +30,8 @@ ALL_PRECISIONS = ("fp64", "fp32", "bf16x3", "fp16x2")
 SEP_LP = ("fp32", "bf16x3")   # reduced precisions of the separable form's phi transforms
 # every source a timed kernel is compiled from: counter figures taken on other sources are not used
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1806_04593_amd", "csrc", f)
-               for f in ("yyg_tile.h", "yyg_kernels.hip", "yyg_kernels_x4.hip", "yyg_kernels_sep_lp.hip",
-                         "yyg_kernels_lp.hip", "yyg_batch_sep.hip")]
+               for f in ("yyg_internal.h", "yyg_tile.h", "yyg_kernels.hip", "yyg_kernels_x4.hip",
+                         "yyg_kernels_sep_lp.hip", "yyg_kernels_lp.hip", "yyg_batch_sep.hip", "yyg_phi_stream.hip")]
 METRIC = "grid cells/sec per full Phi solve, FP64 vs split-precision, at stated max rel. error"
 
 
@@ -266,7 +266,8 @@ def phi_roofline(head, desc, M, nang):
     ms_k = head["phase_alone_ms"][name]
     kname = head["kernel_names"][name]
     args = kname[kname.find("<") + 1:].rstrip(">").split(", ")
-    folded = (kname.startswith("yyg::phi_syn_lean_kernel<")
+    # the streaming kernels run on mirror-symmetric grids only, always folded
+    folded = (kname.startswith(("yyg::phi_syn_lean_kernel<", "yyg::phi_syn_stream", "yyg::phi_ana_stream"))
               or (kname.startswith("yyg::phi_direct_kernel<") and args[-1] == "true")
               or (kname.startswith("yyg::gemm_nt_f64_batched<") and int(args[-1]) & (128 | 256 | 4096)))
     if folded:
