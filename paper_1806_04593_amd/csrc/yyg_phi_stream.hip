@@ -86,17 +86,19 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
   int rbl[TI];
 #pragma unroll
   for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+  // without a branch: the loads that refill a ring slot then stay after
+  // the reads of its values (a load hoisted above them would need other
+  // registers and a copy, after a wait for every load in flight, at the
+  // end of each ring)
   auto advance_load = [&]() {
-    if (++ql == NQ) {
-      ql = 0;
-      tl += stride;
+    const bool next = ++ql == NQ;
+    ql = next ? 0 : ql;
+    tl += next ? stride : 0;
 #pragma unroll
-      for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
-    }
+    for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
   };
   double raE[P][TI], raO[P][TI];
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
+  auto refill = [&](int p) {
     const int oe = offE(ql), oo = offO(ql);
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
@@ -104,6 +106,13 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
       raO[p][i] = a.V[oo + rbl[i]];
     }
     advance_load();
+  };
+  // slots filled in order (the waits in the loop count on slot p's loads
+  // being older than slot p + 1's)
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    refill(p);
+    __builtin_amdgcn_sched_barrier(0);
   }
   // basis fragments of the current step, read one step ahead (up to 6
   // tiles; wider panels read them at the step, for registers): lane
@@ -137,32 +146,22 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
           bO[j] = bp[16 * j * ldb + KE + 4 * q];
         }
       }
-      double aE[TI], aO[TI];
-#pragma unroll
-      for (int i = 0; i < TI; ++i) {
-        aE[i] = raE[p][i];
-        aO[i] = raO[p][i];
-      }
-      {
-        const int oe = offE(ql), oo = offO(ql);
-#pragma unroll
-        for (int i = 0; i < TI; ++i) {
-          raE[p][i] = a.V[oe + rbl[i]];
-          raO[p][i] = a.V[oo + rbl[i]];
-        }
-        advance_load();
-      }
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) accE[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aE[i], bE[j], accE[i][j], 0, 0, 0);
+        for (int j = 0; j < TJ; ++j)
+          accE[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(raE[p][i], bE[j], accE[i][j], 0, 0, 0);
       if (q < NQO) {  // uniform: a sine step past L adds nothing
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
           for (int j = 0; j < TJ; ++j)
-            accO[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aO[i], bO[j], accO[i][j], 0, 0, 0);
+            accO[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(raO[p][i], bO[j], accO[i][j], 0, 0, 0);
       }
+      // the slot's refill P steps ahead, after its values have gone into
+      // this step's products: into the same registers, no copy
+      __builtin_amdgcn_sched_barrier(0);
+      refill(p);
       if constexpr (BPF) {
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
@@ -306,17 +305,19 @@ __device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, c
   int rbl[TI];
 #pragma unroll
   for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
+  // without a branch: the loads that refill a ring slot then stay after
+  // the reads of its values (a load hoisted above them would need other
+  // registers and a copy, after a wait for every load in flight, at the
+  // end of each ring)
   auto advance_load = [&]() {
-    if (++ql == NQ) {
-      ql = 0;
-      tl += stride;
+    const bool next = ++ql == NQ;
+    ql = next ? 0 : ql;
+    tl += next ? stride : 0;
 #pragma unroll
-      for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
-    }
+    for (int i = 0; i < TI; ++i) rbl[i] = rowbase(tl, i);
   };
   double raE[P][TI], raO[P][TI];
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
+  auto refill = [&](int p) {
     const int oe = offE(ql), oo = offO(ql);
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
@@ -324,6 +325,13 @@ __device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, c
       raO[p][i] = a.V[oo + rbl[i]];
     }
     advance_load();
+  };
+  // slots filled in order (the waits in the loop count on slot p's loads
+  // being older than slot p + 1's)
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    refill(p);
+    __builtin_amdgcn_sched_barrier(0);
   }
   const float *bp = &Bs[r16 * ldb + g];
   float bE[TJ], bO[TJ];
@@ -349,15 +357,10 @@ __device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, c
         aE[i] = (float)raE[p][i];
         aO[i] = (float)raO[p][i];
       }
-      {
-        const int oe = offE(ql), oo = offO(ql);
-#pragma unroll
-        for (int i = 0; i < TI; ++i) {
-          raE[p][i] = a.V[oe + rbl[i]];
-          raO[p][i] = a.V[oo + rbl[i]];
-        }
-        advance_load();
-      }
+      // the slot's refill after its values are converted, into the same
+      // registers
+      __builtin_amdgcn_sched_barrier(0);
+      refill(p);
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -820,7 +823,8 @@ const StreamVariant kStream[] = {
     YYG_STREAM(1, 6, 8, 4, 138, 1), YYG_STREAM(1, 4, 8, 8, 138, 1), YYG_STREAM(1, 3, 4, 8, 138, 3),
     YYG_STREAM(1, 6, 8, 8, 138, 1), YYG_STREAM(1, 9, 8, 4, 138, 1), YYG_STREAM(1, 9, 8, 2, 138, 1),
     YYG_STREAM(1, 3, 8, 4, 266, 1), YYG_STREAM_CF(1, 9, 8, 4, 138, 1), YYG_STREAM_CF(1, 6, 8, 4, 138, 1),
-    YYG_STREAM_CF(1, 9, 8, 2, 138, 1),
+    YYG_STREAM_CF(1, 9, 8, 2, 138, 1), YYG_STREAM(1, 9, 8, 8, 138, 1), YYG_STREAM(1, 6, 8, 12, 138, 1),
+    YYG_STREAM_CF(1, 6, 8, 8, 138, 1), YYG_STREAM_CF(1, 9, 8, 8, 138, 1),
 };
 
 #define YYG_STREAM32(TI, TJ, NW, P, LDB, BPC)                                                           \
