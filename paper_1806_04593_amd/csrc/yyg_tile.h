@@ -548,7 +548,26 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmF64Args &g, int tm, int 
   // Stage `it` sits in LDS buffer it & 1 and register slot it % PF; the
   // loop is unrolled by PF so that every slot index is a constant.  With
   // PF = 1 the stage loaded this iteration is the one stored after it.
-  for (int base = 0; base < nk; base += PF) {
+  // Steady state first, where every step refills its slot: no condition
+  // around the loads, so that each slot is refilled in its own registers
+  // and the stash waits for its own stage only (not for the later stages
+  // in flight); then the last stages with their conditions.
+  int base0 = 0;
+  for (; base0 + 2 * PF - 1 < nk; base0 += PF) {
+#pragma unroll
+    for (int sl = 0; sl < PF; ++sl) {
+      const int it = base0 + sl, buf = it & 1;
+      __builtin_amdgcn_sched_barrier(0);
+      load(ra[sl], rb[sl], kbeg + (it + PF) * kBK);
+      xload(rx[sl], kbeg + (it + PF) * kBK);
+      compute(buf, FOLDC && kbeg + it * kBK >= g.k_split);
+      xcompute(buf);
+      stash(ra[(sl + 1) % PF], rb[(sl + 1) % PF], buf ^ 1, kbeg + (it + 1) * kBK);
+      xstash(rx[(sl + 1) % PF], buf ^ 1, kbeg + (it + 1) * kBK);
+      __syncthreads();
+    }
+  }
+  for (int base = base0; base < nk; base += PF) {
 #pragma unroll
     for (int sl = 0; sl < PF; ++sl) {
       const int it = base + sl;
