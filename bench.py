@@ -250,6 +250,16 @@ def phase_alone_ms(g, d_phi, phase, a):
 DENSE_TUNE_MAX_CELLS = 5e7
 
 
+def phi_folded(kname):
+    """Whether a phi-transform kernel works on the rows folded about the
+    central meridian (half the multiply-adds of the unfolded count)."""
+    args = kname[kname.find("<") + 1:].rstrip(">").split(", ")
+    # the streaming kernels run on mirror-symmetric grids only, always folded
+    return bool(kname.startswith(("yyg::phi_syn_lean_kernel<", "yyg::phi_syn_stream", "yyg::phi_ana_stream"))
+                or (kname.startswith("yyg::phi_direct_kernel<") and args[-1] == "true")
+                or (kname.startswith("yyg::gemm_nt_f64_batched<") and int(args[-1]) & (128 | 256 | 4096)))
+
+
 def phi_roofline(head, desc, M, nang):
     """Roofline of the dominant single-launch kernel of the separable solve,
     the longer phi transform."""
@@ -265,12 +275,7 @@ def phi_roofline(head, desc, M, nang):
     # per-phase events inside solves add a launch gap to each)
     ms_k = head["phase_alone_ms"][name]
     kname = head["kernel_names"][name]
-    args = kname[kname.find("<") + 1:].rstrip(">").split(", ")
-    # the streaming kernels run on mirror-symmetric grids only, always folded
-    folded = (kname.startswith(("yyg::phi_syn_lean_kernel<", "yyg::phi_syn_stream", "yyg::phi_ana_stream"))
-              or (kname.startswith("yyg::phi_direct_kernel<") and args[-1] == "true")
-              or (kname.startswith("yyg::gemm_nt_f64_batched<") and int(args[-1]) & (128 | 256 | 4096)))
-    if folded:
+    if phi_folded(kname):
         flops_k /= 2.0   # folded about the central meridian: half the multiply-adds
     tf = flops_k / (ms_k * 1e-3) / 1e12
     gbs = bytes_k / (ms_k * 1e-3) / 1e9
@@ -347,12 +352,16 @@ def bench_single(a):
         err = None if a.no_check else sampled_error(front, d_phi.cpu().numpy())
         L2 = 2 * desc["lmax"] + 1
         phi_flops = 2.0 * M * nang * L2           # each phi transform (unfolded count)
+        # algorithmic TFLOP/s of each phi transform in the solve (halved
+        # count for the folded kernels)
+        names = {p: g.sep_kernel(q) for p, q in (("phi_analysis", 0), ("phi_synthesis", 4))}
+        alg = {p: phi_flops / (2.0 if phi_folded(n) else 1.0) for p, n in names.items()}
         results["fp64_separable"] = {
             "cells_per_s": cells / (ms * 1e-3), "ms_per_step": ms, "max_rel_err_vs_oracle": err,
             "kernels_ms": {"phi_analysis": avg[4], "theta_analysis_rotation": avg[5], "radial_scan": avg[1],
                            "theta_synthesis": avg[6], "phi_synthesis": avg[7]},
-            "phi_synthesis_tflops": phi_flops / (avg[7] * 1e-3) / 1e12,
-            "phi_analysis_tflops": phi_flops / (avg[4] * 1e-3) / 1e12,
+            "phi_synthesis_tflops": alg["phi_synthesis"] / (avg[7] * 1e-3) / 1e12,
+            "phi_analysis_tflops": alg["phi_analysis"] / (avg[4] * 1e-3) / 1e12,
             "phase_alone_ms": alone, "variants": g.sep_info(), "tune_s": round(tune_s, 2),
             "kernel_names": {n: g.sep_kernel(p) for p, n in enumerate(
                 ("phi_analysis", "theta_analysis", "rotation", "theta_synthesis", "phi_synthesis"))},
