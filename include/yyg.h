@@ -154,9 +154,10 @@ int yyg_prepare(yyg_grid *g, int precision);
  *                        transform folds into even and odd halves of
  *                        ceil(n_phi/2) points.  Equal to the dense result up
  *                        to rounding; about 2(2L+1) + 4Q/n_phi flops per
- *                        cell.  Needs 8(4 n_r + P(2 n_r + 1)) bytes of LDS
- *                        for its radial scan (P patches): YYG_ERR_UNSUPPORTED
- *                        beyond 160 KiB (n_r > 2559 on a Yin-Yang grid).
+ *                        cell.  Needs 8(4 n_r + P(n_r + 1)) bytes of LDS
+ *                        for its radial scan (P patches) and at most 63
+ *                        shells per lane: YYG_ERR_UNSUPPORTED beyond
+ *                        (n_r > 3413 on a Yin-Yang grid, 4032 polar).
  * Switching to the separable form builds its tables (allocates). */
 enum { YYG_METHOD_DENSE = 0, YYG_METHOD_SEPARABLE = 1 };
 int yyg_set_method(yyg_grid *g, int method);

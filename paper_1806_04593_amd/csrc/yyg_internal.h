@@ -281,7 +281,7 @@ hipError_t launch_split_rows(int prec, const double *X, long ldx, int rows, int 
 // (hipErrorInvalidValue beyond).
 constexpr size_t kScanQMaxLds = 160 * 1024;
 size_t radial_scan_q_lds(int nR, int patches);
-// n_r the column scan takes (n_r <= 2559 with two patches, 3412 with one)
+// n_r the column scan takes (n_r <= 3413 with two patches, 4032 with one)
 bool radial_scan_q_supports(int nR, int patches);
 hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int *qdeg, int nR, int L, double negG,
                                 int patches, double *Ut, hipStream_t s);

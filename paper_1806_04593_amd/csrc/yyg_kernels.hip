@@ -580,8 +580,9 @@ __global__ __launch_bounds__(256) void phi_syn_lean_kernel(PhiLeanArgs a) {
 // in LDS; lane i owns the radial chunk [i c, i c + c) (c odd, so that the
 // chunk-strided LDS reads spread over the banks); the chunk summaries
 // (product of multipliers, local value) combine across the wave with
-// shuffles, and the potential coefficients -G U_n^(q) go back through LDS to
-// Ut[mc][l][p nR + n] (q = l^2 + mc), rows contiguous.
+// shuffles, and the potential coefficients -G U_n^(q) go back through the
+// column's LDS (once every lane has read it) to Ut[mc][l][p nR + n]
+// (q = l^2 + mc), rows contiguous.
 // CMAX bounds the chunk length: the chunk loops unroll with every LDS read
 // at a clamped index, so that the reads issue ahead of the recurrences.
 // Column q of one plan's scan; waves p >= P (a one-patch plan in a block
@@ -596,9 +597,8 @@ __device__ __forceinline__ void radial_scan_q_body(const double *__restrict__ X,
   const bool active = p < P;
   const int pa = active ? p : 0;                     // an inactive wave addresses patch 0 and stores nothing
   const long M = (long)P * nR;
-  double *sc = smem;                                 // [4][nR]: c0, c1, c2, c3 over n
-  double *sx = smem + 4L * nR + (long)pa * (2 * nR + 1);  // [nR + 1]: the moments, zero at nR
-  double *so = sx + nR + 1;                          // [nR]: output staging
+  double *sc = smem;                                  // [4][nR]: c0, c1, c2, c3 over n
+  double *sx = smem + 4L * nR + (long)pa * (nR + 1);  // [nR + 1]: the moments, zero at nR; then the outputs
   {
     // staging: batches of CB coefficient and XB moment loads from clamped
     // addresses, all in flight before the first LDS store (one batch covers
@@ -681,14 +681,18 @@ __device__ __forceinline__ void radial_scan_q_body(const double *__restrict__ X,
     const double a = c2[n], b = c3[n] * sx[n + 1];
     if (i < len) {
       O = a * O + b;
-      if (active) so[n] = negG * (Iv[i] + O);
+      Iv[i] = negG * (Iv[i] + O);  // the output of shell n
     }
   }
+  __syncthreads();  // every lane has read the column: its space takes the outputs
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i)
+    if (active && i < len) sx[n0 + i] = Iv[i];
   __syncthreads();
   const int mc = q - l * l;
   double *__restrict__ ut = Ut + ((long)mc * (L + 1) + l) * M + (long)pa * nR;
   if (active)
-    for (int e = lane; e < nR; e += 64) ut[e] = so[e];
+    for (int e = lane; e < nR; e += 64) ut[e] = sx[e];
 }
 
 template <int CMAX>
@@ -1056,7 +1060,7 @@ hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, 
 }
 
 
-size_t radial_scan_q_lds(int nR, int patches) { return (4UL * nR + (size_t)patches * (2UL * nR + 1)) * sizeof(double); }
+size_t radial_scan_q_lds(int nR, int patches) { return (4UL * nR + (size_t)patches * (nR + 1UL)) * sizeof(double); }
 
 // the column and its coefficients fit in LDS and a lane's chunk in the
 // largest instance (63 shells)
@@ -1080,8 +1084,14 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
     hipLaunchKernelGGL(kern, dim3(Q), dim3(64 * patches), lds, s, X, coefS, qdeg, nR, L, chunk, negG, Ut);
     return hipGetLastError();
   };
+  // the unrolled chunk loops run CMAX steps: an instance close to the chunk
+  // (n_r 550: 9, n_r 1000: 17) keeps the dependent recurrences short
   if (chunk <= 7) return go(radial_scan_q_kernel<7>);
+  if (chunk <= 9) return go(radial_scan_q_kernel<9>);
+  if (chunk <= 11) return go(radial_scan_q_kernel<11>);
   if (chunk <= 15) return go(radial_scan_q_kernel<15>);
+  if (chunk <= 17) return go(radial_scan_q_kernel<17>);
+  if (chunk <= 23) return go(radial_scan_q_kernel<23>);
   if (chunk <= 31) return go(radial_scan_q_kernel<31>);
   if (chunk <= 63) return go(radial_scan_q_kernel<63>);
   return hipErrorInvalidValue;

@@ -223,12 +223,20 @@ def test_determinism_and_patch_swap():
 
 
 def test_separable_shell_limit():
-    """The separable form's radial scan keeps a column in LDS: more shells
-    than fit are refused with YYG_ERR_UNSUPPORTED, and the dense form of
-    the same plan still solves."""
+    """The separable form's radial scan keeps a column in LDS: 3413 shells
+    fill its 160 KiB with two patches and solve against the oracle; one
+    more is refused with YYG_ERR_UNSUPPORTED, and the dense form of that
+    plan still solves."""
     yyg = _yyg()
     _torch()
-    desc = W.make_desc("deep", np.linspace(0.0, 1.0, 2601), 30.0, 2, 1.0, 0)
+    desc = W.make_desc("deep", np.linspace(0.0, 1.0, 3414), 30.0, 2, 1.0, 0)
+    g = yyg.Grid(desc, 0)
+    g.set_method("separable")
+    rng = np.random.default_rng(7)
+    rho = rng.uniform(0.5, 1.0, g.shape)
+    _, phi = _gpu_solve(desc, rho, grid=g)
+    assert _max_rel(phi, O.solve(*_oracle_args(desc), rho)) <= TOL_FP64
+    desc = W.make_desc("deep", np.linspace(0.0, 1.0, 3415), 30.0, 2, 1.0, 0)
     g = yyg.Grid(desc, 0)
     with pytest.raises(yyg.YygError) as ei:
         g.set_method("separable")
@@ -238,13 +246,15 @@ def test_separable_shell_limit():
     assert _max_rel(phi, O.solve(*_oracle_args(desc), rho)) <= TOL_FP64
 
 
-@pytest.mark.parametrize("n_r", [449, 1000, 1100, 2000, 2600])
+@pytest.mark.parametrize("n_r", [449, 1000, 1100, 2000, 2600, 3500])
 def test_radial_scan_forms_against_oracle(n_r):
     """Every radial-scan instance on a tiny angular grid (30 deg, lmax 4),
     log-spaced shells over four decades, full grid against the oracle:
     dense scans in registers (n_r <= 1024) and in the loop form beyond;
-    the separable column scans with 15, 31 and 63-value chunks per lane
-    (n_r 449, 1000 / 1100, 2000); 2600 shells only in the dense form."""
+    the separable column scans with 9, 17, 23, 63 and 63-value chunks per
+    lane (n_r 449, 1000, 1100, 2000, 2600: the instance nearest above the
+    chunk); 3500 shells, past what the column scan's LDS holds with two
+    patches (3413), only in the dense form."""
     yyg = _yyg()
     _torch()
     desc = W.make_desc("scan", np.geomspace(1.0, 1e4, n_r + 1), 30.0, 4, 1.0, 0)
@@ -256,7 +266,7 @@ def test_radial_scan_forms_against_oracle(n_r):
     err = _max_rel(dense, ref)
     _say(f"scan n_r={n_r}: dense max rel err {err:.3e}")
     assert err <= TOL_FP64
-    if n_r <= 2559:
+    if n_r <= 3413:
         g.set_method("separable")
         _, sep = _gpu_solve(desc, rho, grid=g)
         err = _max_rel(sep, ref)
