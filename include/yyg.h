@@ -378,11 +378,11 @@ int yyg_sep_lp_kernel(const yyg_grid *g, int precision, int phase, char *name, s
 /* Set the tile of reduced-precision phi transform `phase` (0 or 4) of the
  * separable form for `precision` (YYG_FP32 or YYG_BF16X3) by hand: tile in
  * [0, 6) (64 x 80, 128 x 48, 64 x 64, 64 x 32, 32 x 32, 128 x 80).  In FP32
- * on a mirror-symmetric grid the phi synthesis also takes [6, 13), the
+ * on a mirror-symmetric grid the phi synthesis also takes [6, 15), the
  * streaming kernel of yyg_sep_config's phi synthesis with an FP32 basis
  * panel and FP32 products added to FP64 sums every 16 columns (tiles 10 and
- * 12 for lmax <= 131, the others for lmax <= 67; the last two number the
- * row tiles colatitude row fastest), and the phi analysis [6, 13),
+ * 12 for lmax <= 131, the others for lmax <= 67; tiles 11, 12 and 14 number
+ * the row tiles colatitude row fastest), and the phi analysis [6, 13),
  * the streaming analysis with an FP32 basis panel (a degree up to 64 in one
  * panel of 9 tiles for all but the second and third, so that each density
  * row is read once; FP64 sums every 16 points; h <= 272) — YYG_ERR_UNSUPPORTED beyond

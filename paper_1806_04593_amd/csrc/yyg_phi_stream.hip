@@ -843,7 +843,7 @@ const StreamVariant kStream[] = {
 const StreamVariant kStream32[] = {
     YYG_STREAM32(1, 6, 8, 4, 138, 1), YYG_STREAM32(1, 4, 4, 8, 138, 2), YYG_STREAM32(1, 5, 8, 4, 138, 1),
     YYG_STREAM32(1, 3, 4, 4, 138, 2), YYG_STREAM32(1, 6, 8, 4, 266, 1), YYG_STREAM32_CF(1, 6, 8, 4, 138, 1),
-    YYG_STREAM32_CF(1, 6, 8, 4, 266, 1),
+    YYG_STREAM32_CF(1, 6, 8, 4, 266, 1), YYG_STREAM32(1, 6, 8, 8, 138, 1), YYG_STREAM32_CF(1, 6, 8, 8, 138, 1),
 };
 
 struct AnaVariant {

@@ -243,7 +243,7 @@ def test_binary_separable_stream_variants():
     g.set_method("dense")
 
 
-N_STREAM32_L64 = 7   # FP32 streaming phi-synthesis kernels (tiles 6 onwards), all holding lmax 64
+N_STREAM32_L64 = 9   # FP32 streaming phi-synthesis kernels (tiles 6 onwards), all holding lmax 64
 
 
 def test_binary_separable_fp32_stream_variants():

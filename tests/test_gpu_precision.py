@@ -107,7 +107,7 @@ def test_workload_errors(name):
 # ---------------------------------------------------------------------------
 
 N_SEP_LP_TILES = 6
-N_STREAM32 = 7   # FP32 phi synthesis: the FP32 streaming kernels after the tiles
+N_STREAM32 = 9   # FP32 phi synthesis: the FP32 streaming kernels after the tiles
 N_ANA_STREAM32 = 7   # FP32 phi analysis: the FP32 streaming kernels after the tiles
 
 
