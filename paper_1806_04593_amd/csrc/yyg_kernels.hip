@@ -586,19 +586,25 @@ __global__ __launch_bounds__(256) void phi_syn_lean_kernel(PhiLeanArgs a) {
 // CMAX bounds the chunk length: the chunk loops unroll with every LDS read
 // at a clamped index, so that the reads issue ahead of the recurrences.
 // Column q of one plan's scan; waves p >= P (a one-patch plan in a block
-// sized for two) take part in the barriers only.
-template <int CMAX>
+// sized for two) take part in the barriers only.  NCOL = 2: the block's
+// waves 0..P-1 scan column q, waves P..2P-1 column q2 of the same degree
+// (its recurrence coefficients staged once for both; q2 < 0: those waves
+// take part in the barriers only).
+template <int CMAX, int NCOL = 1>
 __device__ __forceinline__ void radial_scan_q_body(const double *__restrict__ X, const double *__restrict__ coefS,
                                                    const int *__restrict__ qdeg, int nR, int L, int chunk,
                                                    double negG, double *__restrict__ Ut, int q, int P,
-                                                   double *smem) {
+                                                   double *smem, int q2 = -1) {
   const int l = qdeg[q];
-  const int tid = threadIdx.x, lane = tid & 63, p = tid >> 6;
-  const bool active = p < P;
-  const int pa = active ? p : 0;                     // an inactive wave addresses patch 0 and stores nothing
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int col = NCOL > 1 ? w / P : 0, p = NCOL > 1 ? w - col * P : w;
+  const bool active = p < P && (col == 0 || q2 >= 0);
+  const int pa = p < P ? p : 0;                       // an inactive wave addresses patch 0 and stores nothing
+  if (col == 1 && q2 >= 0) q = q2;
   const long M = (long)P * nR;
   double *sc = smem;                                  // [4][nR]: c0, c1, c2, c3 over n
-  double *sx = smem + 4L * nR + (long)pa * (nR + 1);  // [nR + 1]: the moments, zero at nR; then the outputs
+  // [nR + 1]: the moments, zero at nR; then the outputs
+  double *sx = smem + 4L * nR + (long)(col * P + pa) * (nR + 1);
   {
     // staging: batches of CB coefficient and XB moment loads from clamped
     // addresses, all in flight before the first LDS store (one batch covers
@@ -701,6 +707,24 @@ __global__ __launch_bounds__(128) void radial_scan_q_kernel(const double *__rest
                                                             double negG, double *__restrict__ Ut) {
   extern __shared__ double smem[];
   radial_scan_q_body<CMAX>(X, coefS, qdeg, nR, L, chunk, negG, Ut, blockIdx.x, blockDim.x / 64, smem);
+}
+
+// Two columns of one degree per block (P waves each): block b of degree l
+// (l (l + 1) / 2 <= b < (l + 1) (l + 2) / 2) takes columns l^2 + 2 j and
+// l^2 + 2 j + 1, j = b - l (l + 1) / 2, the second absent for j = l (the
+// degree's 2l + 1 columns are odd in number).
+template <int CMAX>
+__global__ __launch_bounds__(256) void radial_scan_q2_kernel(const double *__restrict__ X,
+                                                             const double *__restrict__ coefS,
+                                                             const int *__restrict__ qdeg, int nR, int L, int chunk,
+                                                             double negG, double *__restrict__ Ut, int P) {
+  extern __shared__ double smem[];
+  const int b = blockIdx.x;
+  int l = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while (l * (l + 1) / 2 > b) --l;            // exact for any rounding of the square root
+  while ((l + 1) * (l + 2) / 2 <= b) ++l;
+  const int j = b - l * (l + 1) / 2, q = l * l + 2 * j;
+  radial_scan_q_body<CMAX, 2>(X, coefS, qdeg, nR, L, chunk, negG, Ut, q, P, smem, j < l ? q + 1 : -1);
 }
 
 // The same over the columns of several plans (batched separable solves):
@@ -1062,6 +1086,11 @@ hipError_t launch_expand_self_basis(const double *P, const double *Tr, int n_t, 
 
 size_t radial_scan_q_lds(int nR, int patches) { return (4UL * nR + (size_t)patches * (nR + 1UL)) * sizeof(double); }
 
+// the paired form: the coefficients once, two columns of every patch
+static size_t radial_scan_q2_lds(int nR, int patches) {
+  return (4UL * nR + 2UL * patches * (nR + 1UL)) * sizeof(double);
+}
+
 // the column and its coefficients fit in LDS and a lane's chunk in the
 // largest instance (63 shells)
 bool radial_scan_q_supports(int nR, int patches) {
@@ -1084,8 +1113,33 @@ hipError_t launch_radial_scan_q(const double *X, const double *coefS, const int 
     hipLaunchKernelGGL(kern, dim3(Q), dim3(64 * patches), lds, s, X, coefS, qdeg, nR, L, chunk, negG, Ut);
     return hipGetLastError();
   };
-  // the unrolled chunk loops run CMAX steps: an instance close to the chunk
-  // (n_r 550: 9, n_r 1000: 17) keeps the dependent recurrences short
+  // two columns per block where they fit in LDS (the coefficients staged
+  // once for both) ...; the unrolled chunk loops run CMAX steps: an instance
+  // close to the chunk (n_r 550: 9, n_r 1000: 17) keeps the dependent
+  // recurrences short
+  // (with enough columns: Q / 2 blocks must still fill the device; at
+  // lmax 25, 351 paired blocks ran slower than 676 single ones)
+  const size_t lds2 = radial_scan_q2_lds(nR, patches);
+  if (lds2 <= kScanQMaxLds && Q >= 1024) {
+    const int blocks = (L + 1) * (L + 2) / 2;
+    auto go2 = [&](auto kern) {
+      if (lds2 > 64 * 1024 &&
+          hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds2) != hipSuccess)
+        return hipGetLastError();
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(128 * patches), lds2, s, X, coefS, qdeg, nR, L, chunk, negG, Ut,
+                         patches);
+      return hipGetLastError();
+    };
+    if (chunk <= 7) return go2(radial_scan_q2_kernel<7>);
+    if (chunk <= 9) return go2(radial_scan_q2_kernel<9>);
+    if (chunk <= 11) return go2(radial_scan_q2_kernel<11>);
+    if (chunk <= 15) return go2(radial_scan_q2_kernel<15>);
+    if (chunk <= 17) return go2(radial_scan_q2_kernel<17>);
+    if (chunk <= 23) return go2(radial_scan_q2_kernel<23>);
+    if (chunk <= 31) return go2(radial_scan_q2_kernel<31>);
+    return go2(radial_scan_q2_kernel<63>);
+  }
   if (chunk <= 7) return go(radial_scan_q_kernel<7>);
   if (chunk <= 9) return go(radial_scan_q_kernel<9>);
   if (chunk <= 11) return go(radial_scan_q_kernel<11>);

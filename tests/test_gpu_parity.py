@@ -222,6 +222,27 @@ def test_determinism_and_patch_swap():
     del torch
 
 
+@pytest.mark.parametrize("n_r, lmax", [(1000, 40), (2559, 31)])
+def test_paired_radial_scan_against_oracle(n_r, lmax):
+    """The column scan with two columns of one degree per block (lmax >= 31:
+    at least 1024 columns) against the oracle on a coarse angular grid:
+    n_r 1000 (17-shell chunks) and 2559 (the most shells the paired form's
+    LDS holds with two patches: 160 KiB; one more takes one column per
+    block, as every grid of the other scan tests does)."""
+    yyg = _yyg()
+    _torch()
+    desc = W.make_desc("scan", np.geomspace(1.0, 1e4, n_r + 1), 30.0, lmax, 1.0, 0)
+    rng = np.random.default_rng(n_r + lmax)
+    rho = rng.uniform(0.1, 1.0, (2, n_r, desc["n_theta"], desc["n_phi"]))
+    ref = O.solve(*_oracle_args(desc), rho)
+    g = yyg.Grid(desc, 0)
+    g.set_method("separable")
+    _, sep = _gpu_solve(desc, rho, grid=g)
+    err = _max_rel(sep, ref)
+    _say(f"paired scan n_r={n_r} lmax={lmax}: separable max rel err {err:.3e}")
+    assert err <= TOL_FP64
+
+
 def test_separable_shell_limit():
     """The separable form's radial scan keeps a column in LDS: 3413 shells
     fill its 160 KiB with two patches and solve against the oracle; one
