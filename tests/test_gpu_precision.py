@@ -175,6 +175,28 @@ def test_separable_stream32_only_for_the_fp32_synthesis():
         assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, n_max) == yyg.ERR_INVALID_ARG
 
 
+def test_separable_fp32_streams_odd_row_length():
+    """The FP32 streaming phi kernels on a grid with an odd number of cells
+    per row (7 deg: 41; the middle cell has no mirror), every analysis and
+    synthesis variant, full grid against the oracle."""
+    _torch()
+    desc = W.make_desc("odd", np.geomspace(1.0, 20.0, 12), 7.0, 9, 0.9, 0)
+    assert desc["n_phi"] % 2 == 1
+    rng = np.random.default_rng(43)
+    rho = rng.uniform(0.1, 1.0, (2, 11, desc["n_theta"], desc["n_phi"]))
+    ref = O.solve(*_oracle_args(desc), rho)
+    g = _grid(desc)
+    g.set_method("separable")
+    for phase, n in ((0, N_ANA_STREAM32), (4, N_STREAM32)):
+        for t in range(N_SEP_LP_TILES, N_SEP_LP_TILES + n):
+            _set_lp_tile(g, "fp32", phase, t)
+            phi = _solve(g, rho, "fp32")
+            err = float(np.max(np.abs(phi - ref) / np.abs(ref)))
+            _say(f"odd n_phi {desc['n_phi']}: fp32 phase {phase} {g.sep_lp_kernel('fp32', phase)} {err:.2e}")
+            assert err <= 1e-6, (phase, t, err)
+        _set_lp_tile(g, "fp32", phase, 0)
+
+
 def _set_lp_tile(g, precision, phase, t):
     """Reduced-precision tile t of phi phase `phase` (yyg_sep_lp_config)."""
     from paper_1806_04593_amd import yyg
