@@ -127,6 +127,8 @@ N_STREAM = 14    # phi synthesis: then the streaming kernels (basis panel in LDS
 N_STREAM_WIDE = (6,)   # of which these hold panels up to lmax 131, the others up to 67
 N_ANA_STREAM = 8   # phi analysis: then the streaming kernels (colatitude-independent basis in LDS)
 N_XCOL = 8         # and last the folded tiles with their last output column on the vector units
+N_SEP_LP_TILES = 6   # FP32 phi transforms: tiles first, then the FP32 streaming kernels
+N_LP_STREAM = {0: 7, 4: 9}
 
 
 def _n_x4(phase):
@@ -350,12 +352,48 @@ def test_separable_ragged_shapes(case):
         _say(f"separable ragged, folded phi variant {f}: {g.sep_info()}")
         _, phi_f = _gpu_solve(desc, rho, grid=g)
         assert _max_rel(phi_f, ref) <= TOL_FP64, f
+    # the streaming phi kernels and the extra-column analysis tiles on the
+    # same shapes (every one that holds the degree)
+    yyg = _yyg()
+    n0, n4 = g.sep_variant_count(0), g.sep_variant_count(4)
+    ran = 0
+    for phase, lo, hi in ((0, n0 - N_XCOL - N_ANA_STREAM, n0), (4, n4 - N_STREAM, n4)):
+        for v in range(lo, hi):
+            try:
+                g.sep_config(phase, v)
+            except yyg.YygError as e:
+                assert e.status == yyg.ERR_UNSUPPORTED, (phase, v)
+                continue
+            _, phi_s = _gpu_solve(desc, rho, grid=g)
+            err = _max_rel(phi_s, ref)
+            _say(f"separable ragged, {g.sep_kernel(phase)}: {err:.2e}")
+            assert err <= TOL_FP64, (phase, v, g.sep_kernel(phase), err)
+            ran += 1
+        g.sep_config(phase, 10)
+    assert ran >= N_XCOL + N_ANA_STREAM
     # the separable form keeps its moments column-major; the export is the
     # same [patch][shell][q] array as after a dense solve
     th, ph = O.patch_edges(desc["n_theta"], desc["n_phi"], desc["delta_theta"], desc["delta_phi"])
     w = O.overlap_weights(th, ph, desc["delta_theta"], desc["delta_phi"])
     AC, AS = O.moments(rho, w, O.theta_integrals(th, desc["lmax"]), *O.phi_integrals(ph, desc["lmax"]))
     assert np.all(np.abs(g.moments() - _moments_to_q(AC, AS)) <= _moment_bound(desc, rho))
+    # last, the FP32 streaming kernels of the separable FP32 solve (the
+    # moments it leaves carry FP32 rounding)
+    torch = _torch()
+    for phase, n in N_LP_STREAM.items():
+        for t in range(N_SEP_LP_TILES, N_SEP_LP_TILES + n):
+            st = yyg.lib().yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, t)
+            if st == yyg.ERR_UNSUPPORTED:
+                continue
+            assert st == 0, (phase, t, st)
+            d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda")
+            g.upload_rho(torch.from_numpy(rho).to("cuda"))
+            g.solve(d_phi, "fp32")
+            torch.cuda.synchronize()
+            err = _max_rel(d_phi.cpu().numpy(), ref)
+            _say(f"separable ragged, fp32 {g.sep_lp_kernel('fp32', phase)}: {err:.2e}")
+            assert err <= 1e-5, (phase, t, g.sep_lp_kernel("fp32", phase), err)
+        assert yyg.lib().yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, 0) == 0
 
 
 @pytest.mark.parametrize("name", ["sn_core", "spheroid"])
