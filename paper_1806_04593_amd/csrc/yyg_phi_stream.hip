@@ -45,6 +45,67 @@ __device__ __forceinline__ void tile_split(int tt, int tiles_j, int nt, int &jl,
   }
 }
 
+// Lane groups (16 lanes) 2 and 3 of a trade places with groups 0 and 1 of
+// b, both 32-bit halves of the doubles (v_permlane32_swap).
+__device__ __forceinline__ void swap_half_waves(double &a, double &b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
+  b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+
+// Stores a finished row tile (rows row0 + [0, 16 TI) of colatitude row jl,
+// folded cells slot0 + [0, 16 TJ)): e + o at each cell and e - o at its
+// mirror, then clears the sums.  Lane group g, element r of a product holds
+// row F32 ? 4 g + r : g + 4 r (the FP32 and FP64 16x16x4 D layouts), cell
+// r16.  Tiles go in pairs (j, j + 1): after swapping half-waves between
+// their values, lane group g holds tile j + g / 2 of two rows, so that one
+// store instruction writes two rows x 32 consecutive cells rather than four
+// rows x 16 (fewer cache lines, since the rows are not 128-byte aligned).
+// `live` is uniform; every lane takes part in the swaps.
+template <int TI, int TJ, bool F32>
+__device__ __forceinline__ void store_row_tile(const PhiStreamArgs &a, dbl4s (&accE)[TI][TJ],
+                                               dbl4s (&accO)[TI][TJ], int row0, int jl, int slot0, int g,
+                                               int r16, bool live) {
+  auto rowof = [](int sg, int r) { return F32 ? 4 * sg + r : sg + 4 * r; };
+  double *const base = a.phi + (long)jl * a.np;
+  auto put = [&](int row, int slot, double sum, double dif) {
+    if (live && row < a.Mr && slot < a.h) {
+      double *o = base + (long)row * a.ldc;
+      o[slot] = sum;
+      const int cm = a.np - 1 - slot;
+      if (cm != slot) o[cm] = dif;
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+#pragma unroll
+    for (int j = 0; j + 1 < TJ; j += 2)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double s0 = accE[i][j][r] + accO[i][j][r], d0 = accE[i][j][r] - accO[i][j][r];
+        double s1 = accE[i][j + 1][r] + accO[i][j + 1][r], d1 = accE[i][j + 1][r] - accO[i][j + 1][r];
+        swap_half_waves(s0, s1);
+        swap_half_waves(d0, d1);
+        const int slot = slot0 + 16 * (j + (g >> 1)) + r16;
+        put(row0 + 16 * i + rowof(g & 1, r), slot, s0, d0);
+        put(row0 + 16 * i + rowof(2 + (g & 1), r), slot, s1, d1);
+      }
+    if constexpr ((TJ & 1) != 0)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        put(row0 + 16 * i + rowof(g, r), slot0 + 16 * (TJ - 1) + r16, accE[i][TJ - 1][r] + accO[i][TJ - 1][r],
+            accE[i][TJ - 1][r] - accO[i][TJ - 1][r]);
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      accE[i][j] = dbl4s{0.0, 0.0, 0.0, 0.0};
+      accO[i][j] = dbl4s{0.0, 0.0, 0.0, 0.0};
+    }
+  }
+}
+
 template <int TI, int TJR, int NW, int P, bool CF>
 __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, const double *Bs, int ldb, int NQ,
                                                      int KE, int slot0, int groups, int grp, int xcd,
@@ -170,27 +231,10 @@ __device__ __forceinline__ void phi_syn_stream_sweep(const PhiStreamArgs &a, con
         }
       }
       if (++q == NQ) {
-        // tile t done: D layout of the 16x16x4 FP64 MFMA, lane l, element r
-        // -> row l / 16 + 4 r, cell l % 16 of the basis tile
+        // tile t done
         int jl, rt;
         tile_split<CF>(t, tiles_j, a.nt, jl, rt);
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-          for (int j = 0; j < TJ; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = rt * 16 * TI + 16 * i + g + 4 * r, slot = slot0 + 16 * j + r16;
-              if (t < t_end && row < a.Mr && slot < a.h) {
-                double *o = a.phi + (long)row * a.ldc + (long)jl * a.np;
-                const double e = accE[i][j][r], od = accO[i][j][r];
-                o[slot] = e + od;
-                const int cm = a.np - 1 - slot;
-                if (cm != slot) o[cm] = e - od;
-              }
-              accE[i][j][r] = 0.0;
-              accO[i][j][r] = 0.0;
-            }
+        store_row_tile<TI, TJ, false>(a, accE, accO, rt * 16 * TI, jl, slot0, g, r16, t < t_end);
         q = 0;
         t += stride;
       }
@@ -381,23 +425,7 @@ __device__ __forceinline__ void phi_syn_stream32_sweep(const PhiStreamArgs &a, c
       if (q == NQ) {
         int jl, rt;
         tile_split<CF>(t, tiles_j, a.nt, jl, rt);
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-          for (int j = 0; j < TJ; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = rt * 16 * TI + 16 * i + 4 * g + r, slot = slot0 + 16 * j + r16;
-              if (t < t_end && row < a.Mr && slot < a.h) {
-                double *o = a.phi + (long)row * a.ldc + (long)jl * a.np;
-                const double e = accE[i][j][r], od = accO[i][j][r];
-                o[slot] = e + od;
-                const int cm = a.np - 1 - slot;
-                if (cm != slot) o[cm] = e - od;
-              }
-              accE[i][j][r] = 0.0;
-              accO[i][j][r] = 0.0;
-            }
+        store_row_tile<TI, TJ, true>(a, accE, accO, rt * 16 * TI, jl, slot0, g, r16, t < t_end);
         q = 0;
         t += stride;
       }
