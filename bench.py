@@ -63,11 +63,12 @@ def measured_traffic(workload, key, kernel, name=None, tile=None):
         rec = data.get(f"{workload}/{key}")
         if not rec or rec.get("kernel_sha") != kernel_sha():
             return None
-        if name is not None and name in rec.get("by_name", {}):
-            # every variant the autotuner launched in an unpinned counter run
-            return float(rec["by_name"][name]["bytes_per_launch"])
-        k = rec["kernels"][kernel]
+        k = rec["kernels"].get(kernel, {})
         if name is not None and k.get("name") != name:
+            # not the pinned run's variant: every variant the autotuner
+            # launched in an unpinned counter run
+            if name in rec.get("by_name", {}):
+                return float(rec["by_name"][name]["bytes_per_launch"])
             return None
         if tile is not None:
             args = [int(x) for x in k["name"][k["name"].index("<") + 1:].rstrip(">").split(",")]
