@@ -95,6 +95,52 @@ def test_polar_ragged_shapes(method, case):
     assert _max_rel(phi, _oracle(desc, rho)) <= TOL["fp64"]
 
 
+N_STREAM, N_ANA_STREAM, N_XCOL = 14, 8, 8   # last variants of the phi synthesis / analysis ranges
+N_SEP_LP_TILES, N_LP_STREAM = 6, {0: 7, 4: 9}   # FP32 phi transforms: tiles, then streaming kernels
+
+
+def test_polar_streaming_phi_kernels():
+    """The streaming phi kernels on a polar grid (one patch of full rows, 51
+    cells: the middle cell has no mirror; n_r 130, lmax 13): every FP64
+    streaming synthesis and analysis variant and every extra-column analysis
+    tile, then every FP32 streaming kernel of the separable FP32 solve,
+    full grid against the oracle's polar solve."""
+    torch = _torch()
+    from paper_1806_04593_amd import yyg
+    desc = W.make_polar_desc("edge", np.linspace(0.0, 2.0, 131), 10.0, 13, 0.7, 0)
+    desc.update(n_theta=25, n_phi=51)
+    rng = np.random.default_rng(23)
+    rho = rng.uniform(0.1, 1.0, (1, 130, 25, 51))
+    ref = _oracle(desc, rho)
+    g = yyg.Grid(desc, 0)
+    g.set_method("separable")
+    d_rho = torch.from_numpy(rho).to("cuda")
+    d_phi = torch.empty(g.shape, dtype=torch.float64, device="cuda")
+
+    def run(precision):
+        g.upload_rho(d_rho)
+        g.solve(d_phi, precision)
+        torch.cuda.synchronize()
+        return _max_rel(d_phi.cpu().numpy(), ref)
+
+    for phase, n in ((4, N_STREAM), (0, N_ANA_STREAM + N_XCOL)):
+        total = g.sep_variant_count(phase)
+        for v in range(total - n, total):
+            g.sep_config(phase, v)   # all hold lmax 13 and 26 folded points
+            err = run("fp64")
+            _say(f"polar {g.sep_kernel(phase)}: {err:.2e}")
+            assert err <= TOL["fp64"], (phase, v, err)
+        g.sep_config(phase, 10)
+    L = yyg.lib()
+    for phase, n in N_LP_STREAM.items():
+        for t in range(N_SEP_LP_TILES, N_SEP_LP_TILES + n):
+            assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, t) == 0, (phase, t)
+            err = run("fp32")
+            _say(f"polar fp32 {g.sep_lp_kernel('fp32', phase)}: {err:.2e}")
+            assert err <= 1e-6, (phase, t, err)
+        assert L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, 0) == 0
+
+
 @pytest.mark.parametrize("method", ["dense", "separable"])
 def test_polar_spherical_symmetry_exact(method):
     """Spherically symmetric density at lmax 25: the shell theorem holds to

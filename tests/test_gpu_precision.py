@@ -197,6 +197,36 @@ def test_separable_fp32_streams_odd_row_length():
         _set_lp_tile(g, "fp32", phase, 0)
 
 
+def test_separable_fp32_streams_at_high_degree():
+    """The FP32 streaming phi kernels at lmax 80 on a ragged grid (n_r 5,
+    5 deg): the synthesis kernels whose LDS panel holds only lmax <= 67 are
+    refused with YYG_ERR_UNSUPPORTED; the two wide-panel ones (the fifth and
+    seventh) and every analysis kernel (bounded by the row length, not the
+    degree) match the oracle."""
+    from paper_1806_04593_amd import yyg
+    _torch()
+    desc = W.make_desc("edge", np.geomspace(1.0, 9.0, 6), 5.0, 80, 0.9, 0)
+    rng = np.random.default_rng(37)
+    rho = rng.uniform(0.1, 1.0, (2, 5, desc["n_theta"], desc["n_phi"]))
+    ref = O.solve(*_oracle_args(desc), rho)
+    g = _grid(desc)
+    g.set_method("separable")
+    L = yyg.lib()
+    wide = (4, 6)
+    for phase, n in ((4, N_STREAM32), (0, N_ANA_STREAM32)):
+        for v in range(n):
+            st = L.yyg_sep_lp_config(g.handle, yyg.PRECISIONS["fp32"], phase, N_SEP_LP_TILES + v)
+            if phase == 4 and v not in wide:
+                assert st == yyg.ERR_UNSUPPORTED, (phase, v, st)
+                continue
+            assert st == 0, (phase, v, st)
+            phi = _solve(g, rho, "fp32")
+            err = float(np.max(np.abs(phi - ref) / np.abs(ref)))
+            _say(f"lmax 80: fp32 phase {phase} {g.sep_lp_kernel('fp32', phase)} {err:.2e}")
+            assert err <= TOL["fp32"], (phase, v, err)
+        _set_lp_tile(g, "fp32", phase, 0)
+
+
 def _set_lp_tile(g, precision, phase, t):
     """Reduced-precision tile t of phi phase `phase` (yyg_sep_lp_config)."""
     from paper_1806_04593_amd import yyg
