@@ -59,6 +59,32 @@ def test_noalloc_matches_solve_twice_then_smaller():
         g.close()
 
 
+def test_noalloc_streaming_phi_kernels():
+    """The allocation-free solve with the streaming phi synthesis and analysis
+    and an extra-column analysis tile selected (their own argument blocks,
+    pointed at the scratch regions) equals yyg_solve with the same kernels,
+    bit for bit."""
+    torch = _torch()
+    stream = torch.cuda.current_stream()
+    desc, rho, g, d_rho, _ = _case("sn_core")
+    n0, n4 = g.sep_variant_count(0), g.sep_variant_count(4)
+    # first streaming analysis + first streaming synthesis; last extra-column
+    # tile + last streaming synthesis (8 streaming analysis kernels and 8
+    # extra-column tiles end the analysis range, 14 streaming kernels the
+    # synthesis range)
+    for v0, v4 in ((n0 - 16, n4 - 14), (n0 - 1, n4 - 1)):
+        g.sep_config(0, v0)
+        g.sep_config(4, v4)
+        ref = torch.empty(g.shape, dtype=torch.float64, device="cuda")
+        g.upload_rho(d_rho)
+        g.solve(ref)
+        out = torch.full(g.shape, float("nan"), dtype=torch.float64, device="cuda")
+        assert _noalloc(g, d_rho, out, stream) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (g.sep_kernel(0), g.sep_kernel(4))
+    g.close()
+
+
 def test_noalloc_refusals():
     torch = _torch()
     from paper_1806_04593_amd import yyg
