@@ -574,20 +574,25 @@ def test_separable_phase_alone():
         g.sep_phase(4, d_phi)
     assert ei.value.status == -4          # YYG_ERR_NOT_READY: dense method
     g.set_method("separable")
-    g.solve(d_phi)
-    torch.cuda.synchronize()
-    ref = d_phi.clone()
-    for phase in range(5):
-        d_phi.fill_(0.0)
-        for _ in range(2):
-            g.sep_phase(phase, d_phi)
-        if phase < 4:
-            g.sep_phase(4, d_phi)
+    # the default tiles, then the streaming phi synthesis and analysis
+    for streaming in (False, True):
+        if streaming:
+            g.sep_config(0, g.sep_variant_count(0) - N_XCOL - N_ANA_STREAM)
+            g.sep_config(4, g.sep_variant_count(4) - N_STREAM)
+        g.solve(d_phi)
         torch.cuda.synchronize()
-        assert torch.equal(d_phi, ref), phase
+        ref = d_phi.clone()
+        for phase in range(5):
+            d_phi.fill_(0.0)
+            for _ in range(2):
+                g.sep_phase(phase, d_phi)
+            if phase < 4:
+                g.sep_phase(4, d_phi)
+            torch.cuda.synchronize()
+            assert torch.equal(d_phi, ref), (streaming, phase)
 
 
-@pytest.mark.parametrize("method", ["dense", "separable"])
+@pytest.mark.parametrize("method", ["dense", "separable", "separable_streaming"])
 def test_solve_captures_in_a_graph(method):
     """A solve on device buffers is asynchronous and allocation-free, so it
     records into a HIP graph: replays (with eager work and synchronisations
@@ -597,8 +602,12 @@ def test_solve_captures_in_a_graph(method):
     desc = W.describe("small")
     rho = W.density(desc)
     g = yyg.Grid(desc, 0)
-    if method == "separable":
+    if method != "dense":
         g.set_method("separable")
+    if method == "separable_streaming":
+        # the streaming phi synthesis and analysis (persistent grids)
+        g.sep_config(0, g.sep_variant_count(0) - N_XCOL - N_ANA_STREAM)
+        g.sep_config(4, g.sep_variant_count(4) - N_STREAM)
     d_rho = torch.from_numpy(rho).to("cuda")
     d_phi = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
     g.upload_rho(d_rho)
