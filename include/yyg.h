@@ -330,13 +330,15 @@ int yyg_plan_info(const yyg_grid *g, int precision, int *info, int n);
  * one block covers both halves of its rows (the analysis reading each
  * density value once, the synthesis its tiles ordered along the cells;
  * mirror-symmetric grids only, else YYG_ERR_UNSUPPORTED).  Last, the phi
- * synthesis takes 14 folded streaming kernels: each block keeps one panel of
+ * synthesis takes 16 folded streaming kernels: each block keeps one panel of
  * the folded basis in LDS for its whole life and its waves sweep row tiles
  * on their own, loading the coefficients straight into 16x16x4 FP64 MFMA
  * operands several steps ahead (persistent grid of one to three blocks per
- * compute unit; the eighth to tenth and the last two number the row tiles
- * colatitude row fastest, so that a block's waves write neighbouring rows
- * of the same planes); the seventh holds lmax <= 131, the others lmax <= 67
+ * compute unit; the eighth to tenth, the thirteenth, fourteenth and
+ * fifteenth number the row tiles colatitude row fastest, so that a block's
+ * waves write neighbouring rows of the same planes; the last two give each
+ * wave two row tiles of 16 rows, which share every basis fragment read from
+ * LDS); the seventh holds lmax <= 131, the others lmax <= 67
  * (YYG_ERR_UNSUPPORTED beyond, and on grids that are not mirror-symmetric).
  * The phi analysis likewise takes 8 streaming kernels (the
  * colatitude-independent folded C/S basis in LDS, the overlap weights

@@ -853,6 +853,7 @@ const StreamVariant kStream[] = {
     YYG_STREAM(1, 3, 8, 4, 266, 1), YYG_STREAM_CF(1, 9, 8, 4, 138, 1), YYG_STREAM_CF(1, 6, 8, 4, 138, 1),
     YYG_STREAM_CF(1, 9, 8, 2, 138, 1), YYG_STREAM(1, 9, 8, 8, 138, 1), YYG_STREAM(1, 6, 8, 12, 138, 1),
     YYG_STREAM_CF(1, 6, 8, 8, 138, 1), YYG_STREAM_CF(1, 9, 8, 8, 138, 1),
+    YYG_STREAM_CF(2, 6, 4, 4, 138, 1), YYG_STREAM(2, 6, 4, 4, 138, 1),
 };
 
 #define YYG_STREAM32(TI, TJ, NW, P, LDB, BPC)                                                           \

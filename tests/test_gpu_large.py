@@ -224,7 +224,7 @@ def test_binary_separable_reduced_precision(precision):
     g.set_method("dense")
 
 
-N_STREAM = 14         # streaming phi-synthesis variants, last in the phase's range (all hold lmax 64)
+N_STREAM = 16         # streaming phi-synthesis variants, last in the phase's range (all hold lmax 64)
 
 
 def test_binary_separable_stream_variants():

@@ -123,7 +123,7 @@ N_PHI_FOLD = 8
 N_PHI_LEAN = 4   # phi synthesis only
 N_X4 = 12        # tiles on the 4x4x4 FP64 MFMA, every phase (last in each phase's range)
 N_BOTH = {0: 8, 4: 6}   # then the folded phi transforms with both halves per block
-N_STREAM = 14    # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
+N_STREAM = 16    # phi synthesis: then the streaming kernels (basis panel in LDS, coefficients to registers)
 N_STREAM_WIDE = (6,)   # of which these hold panels up to lmax 131, the others up to 67
 N_ANA_STREAM = 8   # phi analysis: then the streaming kernels (colatitude-independent basis in LDS)
 N_XCOL = 8         # and last the folded tiles with their last output column on the vector units

@@ -95,7 +95,7 @@ def test_polar_ragged_shapes(method, case):
     assert _max_rel(phi, _oracle(desc, rho)) <= TOL["fp64"]
 
 
-N_STREAM, N_ANA_STREAM, N_XCOL = 14, 8, 8   # last variants of the phi synthesis / analysis ranges
+N_STREAM, N_ANA_STREAM, N_XCOL = 16, 8, 8   # last variants of the phi synthesis / analysis ranges
 N_SEP_LP_TILES, N_LP_STREAM = 6, {0: 7, 4: 9}   # FP32 phi transforms: tiles, then streaming kernels
 
 

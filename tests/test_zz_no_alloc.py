@@ -70,9 +70,9 @@ def test_noalloc_streaming_phi_kernels():
     n0, n4 = g.sep_variant_count(0), g.sep_variant_count(4)
     # first streaming analysis + first streaming synthesis; last extra-column
     # tile + last streaming synthesis (8 streaming analysis kernels and 8
-    # extra-column tiles end the analysis range, 14 streaming kernels the
+    # extra-column tiles end the analysis range, 16 streaming kernels the
     # synthesis range)
-    for v0, v4 in ((n0 - 16, n4 - 14), (n0 - 1, n4 - 1)):
+    for v0, v4 in ((n0 - 16, n4 - 16), (n0 - 1, n4 - 1)):
         g.sep_config(0, v0)
         g.sep_config(4, v4)
         ref = torch.empty(g.shape, dtype=torch.float64, device="cuda")
